@@ -1,0 +1,518 @@
+/*
+ * gridpull_oracle.c -- plain, slow FP64 reference of the GridPull pull step.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the checker for the HIP library:
+ * only the tests, the smoke check and the benchmark's CPU-baseline leg load
+ * it.  It shares no code, header, table or helper with the HIP path.
+ *
+ * Everything is double precision, single threaded, in the order the paper
+ * states the method (Chen, Liu, Han: "GridPull: Towards Scalability in
+ * Learning Implicit Representations from 3D Point Clouds", ICCV 2023):
+ *
+ *   Sec. 3 "Overview" / Eq. 1       field D on the (R+1)^3 grid vertices,
+ *                                   f(q) = trilinear interpolation of D
+ *   Sec. 3 "Signed Distance Inference", Eq. 3
+ *                                   interpolation as the 8-term polynomial
+ *                                   a0 + a1 x + ... + a7 xyz through the
+ *                                   8 cell corners (same function as Eq. 1)
+ *   same paragraph                  pull p = q - f(q) grad f / |grad f|
+ *   Eq. 4                           L_Pull = |p - NN(q)|
+ *   same section, band paragraph    pulling only in cells within M1 of the
+ *                                   cells holding points
+ *   Eq. 5 and the M2 paragraph      TV term per vertex, six axis neighbours,
+ *                                   on the M2 band
+ *   Eq. 6                           L_Surface = |f(s)|
+ *   Eq. 7                           L_grad = 1 - cos(grad f(q), grad f(NN(q)))
+ *   Eq. 8 (second "objective")      L = L_Pull + a L_TV + b L_Surface + c L_grad
+ *   Sec. 4 "Details"                Adam, lr decay x0.3 every 400 iterations
+ *
+ * Readings where the paper is silent (all listed in the design notes):
+ *   - cells/vertices: R counts cells, vertices are R+1 per axis;
+ *   - cell location: u = (q - lo) * inv_h in double, c = floor(u) clamped to
+ *     R-1, valid iff 0 <= u <= R on every axis (a point on hi lands in the last
+ *     cell with t = 1);
+ *   - band: Chebyshev dilation of the point cells by M, clipped to the grid;
+ *   - L_Surface uses s = NN(q) per query; every query-side term is a mean
+ *     over the valid queries (cell inside the M1 band);
+ *   - TV: tau_i = sqrt(sum over the six neighbours j that are also M2-band
+ *     vertices of (D_i - D_j)^2); L_TV = mean of tau over the M2-band vertices;
+ *   - |grad f| < eps_n: the normalised gradient is 0 (no derivative) and the
+ *     gradient-consistency term is 1 (no derivative); e = r/|r| is 0 at r = 0;
+ *     the derivative of |f_s| is sign(f_s), 0 at 0;
+ *   - nearest neighbour: smallest d2 = ((dx*dx + dy*dy) + dz*dz) with
+ *     dx = (double)q_x - (double)s_x, no fused multiply-add, ties to the
+ *     lowest point index.
+ *
+ * Linear ids are x-major: cell (cx*Ry + cy)*Rz + cz, vertex
+ * (i*(Ry+1) + j)*(Rz+1) + k.
+ *
+ * Flags: cell_flags bit 1 = contains a point, bit 2 = M1 band, bit 4 = M2 band;
+ *        vert_flags bit 1 = corner of an M1- or M2-band cell (optimised),
+ *        bit 2 = corner of an M2-band cell (TV set).
+ *
+ * Build: gcc -O2 -ffp-contract=off -fno-fast-math -shared -fPIC -lm
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* ------------------------------------------------------------------------- */
+/* Grid geometry (Sec. 3, "Discrete Grids")                                   */
+/* ------------------------------------------------------------------------- */
+
+typedef struct {
+    int64_t R[3];      /* cells per axis */
+    int64_t V[3];      /* vertices per axis = R + 1 */
+    double lo[3];
+    double h[3];       /* cell size (hi - lo) / R */
+    double inv_h[3];   /* R / (hi - lo) */
+} grid_t;
+
+static void grid_init(grid_t* g, const int32_t* R, const double* lo, const double* hi)
+{
+    for (int a = 0; a < 3; ++a) {
+        g->R[a] = R[a];
+        g->V[a] = (int64_t)R[a] + 1;
+        g->lo[a] = lo[a];
+        g->h[a] = (hi[a] - lo[a]) / (double)R[a];
+        g->inv_h[a] = (double)R[a] / (hi[a] - lo[a]);
+    }
+}
+
+static int64_t cell_id(const grid_t* g, const int64_t c[3])
+{
+    return (c[0] * g->R[1] + c[1]) * g->R[2] + c[2];
+}
+
+static int64_t vertex_id(const grid_t* g, int64_t i, int64_t j, int64_t k)
+{
+    return (i * g->V[1] + j) * g->V[2] + k;
+}
+
+/* Locate a position in the grid: cell c and local coordinate t in [0,1].
+ * Returns 1 if 0 <= u_a <= R_a on every axis, else 0 (c, t then undefined). */
+static int locate(const grid_t* g, const double x[3], int64_t c[3], double t[3])
+{
+    for (int a = 0; a < 3; ++a) {
+        double u = (x[a] - g->lo[a]) * g->inv_h[a];
+        if (!(u >= 0.0) || !(u <= (double)g->R[a])) return 0;
+        double fl = floor(u);
+        int64_t ci = (int64_t)fl;
+        if (ci > g->R[a] - 1) ci = g->R[a] - 1;
+        c[a] = ci;
+        t[a] = u - (double)ci;
+    }
+    return 1;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Bands (Sec. 3: M1 band for pulling, M2 band for TV)                        */
+/* ------------------------------------------------------------------------- */
+
+static void dilate(const grid_t* g, const uint8_t* cell_flags_in, uint8_t bit_in,
+                   uint8_t* cell_flags, uint8_t bit_out, int64_t M)
+{
+    for (int64_t cx = 0; cx < g->R[0]; ++cx)
+    for (int64_t cy = 0; cy < g->R[1]; ++cy)
+    for (int64_t cz = 0; cz < g->R[2]; ++cz) {
+        int64_t b[3] = {cx, cy, cz};
+        if (!(cell_flags_in[cell_id(g, b)] & bit_in)) continue;
+        for (int64_t x = cx - M; x <= cx + M; ++x) {
+            if (x < 0 || x >= g->R[0]) continue;
+            for (int64_t y = cy - M; y <= cy + M; ++y) {
+                if (y < 0 || y >= g->R[1]) continue;
+                for (int64_t z = cz - M; z <= cz + M; ++z) {
+                    if (z < 0 || z >= g->R[2]) continue;
+                    int64_t c[3] = {x, y, z};
+                    cell_flags[cell_id(g, c)] |= bit_out;
+                }
+            }
+        }
+    }
+}
+
+static void mark_corners(const grid_t* g, const uint8_t* cell_flags, uint8_t cell_bits,
+                         uint8_t* vert_flags, uint8_t vbit)
+{
+    for (int64_t cx = 0; cx < g->R[0]; ++cx)
+    for (int64_t cy = 0; cy < g->R[1]; ++cy)
+    for (int64_t cz = 0; cz < g->R[2]; ++cz) {
+        int64_t c[3] = {cx, cy, cz};
+        if (!(cell_flags[cell_id(g, c)] & cell_bits)) continue;
+        for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b)
+        for (int d = 0; d < 2; ++d)
+            vert_flags[vertex_id(g, cx + a, cy + b, cz + d)] |= vbit;
+    }
+}
+
+/* Base cells, M1/M2 bands and the optimised / TV vertex sets.
+ * cell_flags [R_x R_y R_z] and vert_flags [(R+1)^3] are written in full.
+ * Returns -1 on success, else the index of the first point outside [lo, hi]. */
+int64_t og_build_band(const int32_t* R, const double* lo, const double* hi,
+                      const float* px, const float* py, const float* pz, int64_t n_points,
+                      int32_t m1, int32_t m2, uint8_t* cell_flags, uint8_t* vert_flags)
+{
+    grid_t g;
+    grid_init(&g, R, lo, hi);
+    int64_t nc = g.R[0] * g.R[1] * g.R[2];
+    int64_t nv = g.V[0] * g.V[1] * g.V[2];
+    memset(cell_flags, 0, (size_t)nc);
+    memset(vert_flags, 0, (size_t)nv);
+    for (int64_t j = 0; j < n_points; ++j) {
+        double x[3] = {px[j], py[j], pz[j]};
+        int64_t c[3];
+        double t[3];
+        if (!locate(&g, x, c, t)) return j;
+        cell_flags[cell_id(&g, c)] |= 1;
+    }
+    dilate(&g, cell_flags, 1, cell_flags, 2, m1);
+    dilate(&g, cell_flags, 1, cell_flags, 4, m2);
+    mark_corners(&g, cell_flags, 2 | 4, vert_flags, 1);
+    mark_corners(&g, cell_flags, 4, vert_flags, 2);
+    return -1;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Nearest surface point NN(q) (Eq. 4), brute force over all points          */
+/* ------------------------------------------------------------------------- */
+
+static double dist2(const float* q, float sx, float sy, float sz)
+{
+    double dx = (double)q[0] - (double)sx;
+    double dy = (double)q[1] - (double)sy;
+    double dz = (double)q[2] - (double)sz;
+    double xx = dx * dx;
+    double yy = dy * dy;
+    double zz = dz * dz;
+    double s = xx + yy;
+    return s + zz;
+}
+
+void og_nn_bruteforce(const float* qx, const float* qy, const float* qz, int64_t n_queries,
+                      const float* px, const float* py, const float* pz, int64_t n_points,
+                      int32_t* nn)
+{
+    for (int64_t k = 0; k < n_queries; ++k) {
+        float q[3] = {qx[k], qy[k], qz[k]};
+        double best = INFINITY;
+        int64_t arg = -1;
+        for (int64_t j = 0; j < n_points; ++j) {
+            double d = dist2(q, px[j], py[j], pz[j]);
+            if (d < best) { best = d; arg = j; }   /* strict: ties keep the lowest j */
+        }
+        nn[k] = (int32_t)arg;
+    }
+}
+
+/* ------------------------------------------------------------------------- */
+/* Trilinear interpolation and its gradient (Eq. 1 / Eq. 3)                   */
+/* ------------------------------------------------------------------------- */
+
+typedef struct {
+    int64_t vid[8];     /* corner (a,b,c) at index 4a + 2b + c */
+    double w[8];        /* W_a(t_x) W_b(t_y) W_c(t_z), W_0 = 1 - t, W_1 = t */
+    double dw[8][3];    /* derivative of w with respect to q_x, q_y, q_z */
+    double f;           /* f(q) */
+    double g[3];        /* grad f(q) */
+    double n;           /* |grad f(q)| */
+} interp_t;
+
+static void interpolate(const grid_t* g, const double* D, const int64_t c[3], const double t[3],
+                        interp_t* it)
+{
+    double W[3][2] = {{1.0 - t[0], t[0]}, {1.0 - t[1], t[1]}, {1.0 - t[2], t[2]}};
+    double dW[2] = {-1.0, 1.0};
+    it->f = 0.0;
+    it->g[0] = it->g[1] = it->g[2] = 0.0;
+    for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b)
+    for (int d = 0; d < 2; ++d) {
+        int k = 4 * a + 2 * b + d;
+        it->vid[k] = vertex_id(g, c[0] + a, c[1] + b, c[2] + d);
+        it->w[k] = W[0][a] * W[1][b] * W[2][d];
+        it->dw[k][0] = dW[a] * g->inv_h[0] * W[1][b] * W[2][d];
+        it->dw[k][1] = W[0][a] * dW[b] * g->inv_h[1] * W[2][d];
+        it->dw[k][2] = W[0][a] * W[1][b] * dW[d] * g->inv_h[2];
+        double Dv = D[it->vid[k]];
+        it->f += it->w[k] * Dv;
+        for (int e = 0; e < 3; ++e) it->g[e] += it->dw[k][e] * Dv;
+    }
+    it->n = sqrt(it->g[0] * it->g[0] + it->g[1] * it->g[1] + it->g[2] * it->g[2]);
+}
+
+/* Field value and gradient at an arbitrary position (for the closed-form
+ * checks).  Returns 0 if the position is outside the grid. */
+int og_eval(const int32_t* R, const double* lo, const double* hi, const double* D,
+            double x, double y, double z, double* f_out, double* g_out)
+{
+    grid_t g;
+    grid_init(&g, R, lo, hi);
+    double p[3] = {x, y, z};
+    int64_t c[3];
+    double t[3];
+    if (!locate(&g, p, c, t)) return 0;
+    interp_t it;
+    interpolate(&g, D, c, t, &it);
+    *f_out = it.f;
+    for (int a = 0; a < 3; ++a) g_out[a] = it.g[a];
+    return 1;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Loss (Eq. 4-8) and its exact gradient with respect to D                    */
+/* ------------------------------------------------------------------------- */
+
+static void scatter(double* G, const interp_t* it, double scale, double dl_df, const double dl_dg[3])
+{
+    for (int k = 0; k < 8; ++k) {
+        double v = it->w[k] * dl_df;
+        for (int a = 0; a < 3; ++a) v += it->dw[k][a] * dl_dg[a];
+        G[it->vid[k]] += scale * v;
+    }
+}
+
+/*
+ * terms_out[5] = { total, L_Pull, L_TV, L_Surface, L_grad }:
+ *   L_Pull, L_Surface, L_grad are means over the valid queries (a query is
+ *   valid when it lies in the grid and its cell is in the M1 band), L_TV is the
+ *   mean of tau over the M2-band vertices, total = L_Pull + alpha L_TV +
+ *   beta L_Surface + gamma L_grad.
+ * grad_out (nullable, [(R+1)^3]) receives d total / d D (zeroed first).
+ * per_query (nullable, [n_queries][4]) receives l_pull, l_surf, l_grad and a
+ *   validity flag per query.
+ * tau_out (nullable, [(R+1)^3]) receives tau at the M2-band vertices.
+ * Returns the number of valid queries, or -1 if a nearest point lies outside
+ * the grid.
+ */
+int64_t og_loss_grad(const int32_t* R, const double* lo, const double* hi,
+                     const uint8_t* cell_flags, const uint8_t* vert_flags, const double* D,
+                     const float* qx, const float* qy, const float* qz, const int32_t* nn,
+                     int64_t n_queries,
+                     const float* px, const float* py, const float* pz,
+                     double alpha, double beta, double gamma, double eps_n,
+                     double* terms_out, double* grad_out, double* per_query, double* tau_out)
+{
+    grid_t g;
+    grid_init(&g, R, lo, hi);
+    int64_t nv = g.V[0] * g.V[1] * g.V[2];
+    if (grad_out) memset(grad_out, 0, (size_t)nv * sizeof(double));
+
+    /* Pass 1: count the valid queries, so that the gradient of each mean can
+     * be scattered directly. */
+    int64_t n_valid = 0;
+    for (int64_t k = 0; k < n_queries; ++k) {
+        double q[3] = {qx[k], qy[k], qz[k]};
+        int64_t c[3];
+        double t[3];
+        if (locate(&g, q, c, t) && (cell_flags[cell_id(&g, c)] & 2)) ++n_valid;
+    }
+    double inv_q = n_valid > 0 ? 1.0 / (double)n_valid : 0.0;
+
+    double sum_pull = 0.0, sum_surf = 0.0, sum_grad = 0.0;
+    for (int64_t k = 0; k < n_queries; ++k) {
+        double q[3] = {qx[k], qy[k], qz[k]};
+        int64_t c[3];
+        double t[3];
+        if (per_query) { per_query[4 * k] = per_query[4 * k + 1] = per_query[4 * k + 2] = 0.0;
+                         per_query[4 * k + 3] = 0.0; }
+        if (!locate(&g, q, c, t) || !(cell_flags[cell_id(&g, c)] & 2)) continue;
+
+        /* f and grad f at the query (Eq. 1, Eq. 3). */
+        interp_t iq;
+        interpolate(&g, D, c, t, &iq);
+        double gh[3] = {0.0, 0.0, 0.0};
+        int q_ok = iq.n >= eps_n;
+        if (q_ok) for (int a = 0; a < 3; ++a) gh[a] = iq.g[a] / iq.n;
+
+        /* The nearest surface point s = NN(q) and f, grad f there. */
+        int64_t j = nn[k];
+        double s[3] = {px[j], py[j], pz[j]};
+        int64_t cs[3];
+        double ts[3];
+        if (!locate(&g, s, cs, ts)) return -1;
+        interp_t is;
+        interpolate(&g, D, cs, ts, &is);
+        double ghs[3] = {0.0, 0.0, 0.0};
+        int s_ok = is.n >= eps_n;
+        if (s_ok) for (int a = 0; a < 3; ++a) ghs[a] = is.g[a] / is.n;
+
+        /* Pull (Sec. 3): p = q - f(q) * grad f / |grad f|; residual p - s (Eq. 4). */
+        double r[3];
+        for (int a = 0; a < 3; ++a) {
+            double p = q[a] - iq.f * gh[a];
+            r[a] = p - s[a];
+        }
+        double l_pull = sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
+        double e[3] = {0.0, 0.0, 0.0};
+        if (l_pull > 0.0) for (int a = 0; a < 3; ++a) e[a] = r[a] / l_pull;
+
+        /* Surface term (Eq. 6). */
+        double l_surf = fabs(is.f);
+        double sgn = is.f > 0.0 ? 1.0 : (is.f < 0.0 ? -1.0 : 0.0);
+
+        /* Gradient consistency (Eq. 7). */
+        double cosv = 0.0, l_grad = 1.0;
+        int grad_ok = q_ok && s_ok;
+        if (grad_ok) {
+            cosv = gh[0] * ghs[0] + gh[1] * ghs[1] + gh[2] * ghs[2];
+            l_grad = 1.0 - cosv;
+        }
+
+        sum_pull += l_pull;
+        sum_surf += l_surf;
+        sum_grad += l_grad;
+        if (per_query) { per_query[4 * k] = l_pull; per_query[4 * k + 1] = l_surf;
+                         per_query[4 * k + 2] = l_grad; per_query[4 * k + 3] = 1.0; }
+
+        if (!grad_out) continue;
+
+        /* Adjoint at the query: l = l_pull + gamma l_grad as a function of f, grad f. */
+        double dl_df = -(gh[0] * e[0] + gh[1] * e[1] + gh[2] * e[2]);
+        double dl_dg[3] = {0.0, 0.0, 0.0};
+        if (q_ok) {
+            /* d l_pull / d gh = -f e; through gh = g / |g|: (I - gh gh^T) / |g| */
+            double u[3] = {-iq.f * e[0], -iq.f * e[1], -iq.f * e[2]};
+            double ug = u[0] * gh[0] + u[1] * gh[1] + u[2] * gh[2];
+            for (int a = 0; a < 3; ++a) dl_dg[a] = (u[a] - ug * gh[a]) / iq.n;
+        }
+        double dls_dg[3] = {0.0, 0.0, 0.0};
+        if (grad_ok) {
+            for (int a = 0; a < 3; ++a) {
+                dl_dg[a] += gamma * (-(ghs[a] - cosv * gh[a]) / iq.n);
+                dls_dg[a] = gamma * (-(gh[a] - cosv * ghs[a]) / is.n);
+            }
+        }
+        scatter(grad_out, &iq, inv_q, dl_df, dl_dg);
+        /* Adjoint at the surface point: beta |f_s| + gamma l_grad. */
+        scatter(grad_out, &is, inv_q, beta * sgn, dls_dg);
+    }
+
+    /* TV term (Eq. 5) over the M2-band vertices. */
+    int64_t n_tv = 0;
+    for (int64_t v = 0; v < nv; ++v) if (vert_flags[v] & 2) ++n_tv;
+    double* tau = (double*)calloc((size_t)nv, sizeof(double));
+    double sum_tv = 0.0;
+    const int off[6][3] = {{1, 0, 0}, {-1, 0, 0}, {0, 1, 0}, {0, -1, 0}, {0, 0, 1}, {0, 0, -1}};
+    for (int64_t i = 0; i < g.V[0]; ++i)
+    for (int64_t jj = 0; jj < g.V[1]; ++jj)
+    for (int64_t kk = 0; kk < g.V[2]; ++kk) {
+        int64_t v = vertex_id(&g, i, jj, kk);
+        if (!(vert_flags[v] & 2)) continue;
+        double s2 = 0.0;
+        for (int o = 0; o < 6; ++o) {
+            int64_t a = i + off[o][0], b = jj + off[o][1], cc = kk + off[o][2];
+            if (a < 0 || b < 0 || cc < 0 || a >= g.V[0] || b >= g.V[1] || cc >= g.V[2]) continue;
+            int64_t u = vertex_id(&g, a, b, cc);
+            if (!(vert_flags[u] & 2)) continue;
+            double d = D[v] - D[u];
+            s2 += d * d;
+        }
+        tau[v] = sqrt(s2);
+        sum_tv += tau[v];
+    }
+    double l_tv = n_tv > 0 ? sum_tv / (double)n_tv : 0.0;
+    if (grad_out && n_tv > 0) {
+        double sc = alpha / (double)n_tv;
+        for (int64_t i = 0; i < g.V[0]; ++i)
+        for (int64_t jj = 0; jj < g.V[1]; ++jj)
+        for (int64_t kk = 0; kk < g.V[2]; ++kk) {
+            int64_t v = vertex_id(&g, i, jj, kk);
+            if (!(vert_flags[v] & 2)) continue;
+            double acc = 0.0;
+            for (int o = 0; o < 6; ++o) {
+                int64_t a = i + off[o][0], b = jj + off[o][1], cc = kk + off[o][2];
+                if (a < 0 || b < 0 || cc < 0 || a >= g.V[0] || b >= g.V[1] || cc >= g.V[2]) continue;
+                int64_t u = vertex_id(&g, a, b, cc);
+                if (!(vert_flags[u] & 2)) continue;
+                double d = D[v] - D[u];
+                /* d tau_v / d D_v and d tau_u / d D_v; a zero tau has d = 0 here. */
+                if (tau[v] > 0.0) acc += d / tau[v];
+                if (tau[u] > 0.0) acc += d / tau[u];
+            }
+            grad_out[v] += sc * acc;
+        }
+    }
+    if (tau_out) memcpy(tau_out, tau, (size_t)nv * sizeof(double));
+    free(tau);
+
+    double l_pull = sum_pull * inv_q, l_surf = sum_surf * inv_q, l_grad = sum_grad * inv_q;
+    terms_out[1] = l_pull;
+    terms_out[2] = l_tv;
+    terms_out[3] = l_surf;
+    terms_out[4] = l_grad;
+    terms_out[0] = l_pull + alpha * l_tv + beta * l_surf + gamma * l_grad;
+    return n_valid;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Adam (Sec. 4 "Details": Adam, lr0, x decay every decay_every iterations;   */
+/* Kingma and Ba, ICLR 2015)                                                  */
+/* ------------------------------------------------------------------------- */
+
+void og_adam(int64_t n, double* D, const double* G, double* m, double* v, const uint8_t* vert_flags,
+             int32_t t, double lr0, double decay, int32_t decay_every,
+             double beta1, double beta2, double eps)
+{
+    double lr = lr0 * pow(decay, (double)((t - 1) / decay_every));
+    double bc1 = 1.0 - pow(beta1, (double)t);
+    double bc2 = 1.0 - pow(beta2, (double)t);
+    for (int64_t i = 0; i < n; ++i) {
+        if (!(vert_flags[i] & 1)) continue;
+        m[i] = beta1 * m[i] + (1.0 - beta1) * G[i];
+        v[i] = beta2 * v[i] + (1.0 - beta2) * G[i] * G[i];
+        double mh = m[i] / bc1;
+        double vh = v[i] / bc2;
+        D[i] = D[i] - lr * mh / (sqrt(vh) + eps);
+    }
+}
+
+/* ------------------------------------------------------------------------- */
+/* Query offsets: Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11) and the   */
+/* Box-Muller transform.  Query k of a batch draws one Philox block with      */
+/* counter (k mod 2^32, k >> 32, iteration, stream) and key (seed mod 2^32,    */
+/* seed >> 32); the four words become uniforms U = ((x >> 8) + 1/2) 2^-24 and   */
+/* the offsets are z0, z1 = sqrt(-2 ln U0) (cos, sin)(2 pi U1) and             */
+/* z2 = sqrt(-2 ln U2) cos(2 pi U3).                                           */
+/* ------------------------------------------------------------------------- */
+
+void og_philox4x32_10(const uint32_t* ctr_in, const uint32_t* key_in, uint32_t* out)
+{
+    uint32_t c[4] = {ctr_in[0], ctr_in[1], ctr_in[2], ctr_in[3]};
+    uint32_t k[2] = {key_in[0], key_in[1]};
+    for (int round = 0; round < 10; ++round) {
+        uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)c[0];
+        uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)c[2];
+        uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+        uint32_t n0 = hi1 ^ c[1] ^ k[0];
+        uint32_t n1 = lo1;
+        uint32_t n2 = hi0 ^ c[3] ^ k[1];
+        uint32_t n3 = lo0;
+        c[0] = n0; c[1] = n1; c[2] = n2; c[3] = n3;
+        k[0] += 0x9E3779B9u;
+        k[1] += 0xBB67AE85u;
+    }
+    out[0] = c[0]; out[1] = c[1]; out[2] = c[2]; out[3] = c[3];
+}
+
+void og_query_offsets(uint64_t seed, uint32_t iteration, uint32_t stream, int64_t k0, int64_t n,
+                      double* z_out /* [n][3] */)
+{
+    const double two_pi = 6.283185307179586476925286766559;
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    for (int64_t i = 0; i < n; ++i) {
+        uint64_t k = (uint64_t)(k0 + i);
+        uint32_t ctr[4] = {(uint32_t)k, (uint32_t)(k >> 32), iteration, stream};
+        uint32_t x[4];
+        og_philox4x32_10(ctr, key, x);
+        double U[4];
+        for (int a = 0; a < 4; ++a) U[a] = ((double)(x[a] >> 8) + 0.5) * (1.0 / 16777216.0);
+        double r0 = sqrt(-2.0 * log(U[0]));
+        double r1 = sqrt(-2.0 * log(U[2]));
+        z_out[3 * i + 0] = r0 * cos(two_pi * U[1]);
+        z_out[3 * i + 1] = r0 * sin(two_pi * U[1]);
+        z_out[3 * i + 2] = r1 * cos(two_pi * U[3]);
+    }
+}
