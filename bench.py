@@ -1,0 +1,248 @@
+#!/usr/bin/env python
+"""Throughput of the GridPull optimisation iteration on one MI355X.
+
+One step = one full iteration of the hot path over one batch of synthetic
+queries: sample queries around the points, nearest surface point of every
+query, forward (pull, surface, gradient-consistency and TV terms), backward
+(hand-written adjoint scattered into the grid), Adam step.  The band and the
+point buckets are built once before timing (their build time is reported as
+setup_ms).
+
+value = queries pulled per second over the whole timed iteration, measured
+on the eager launch sequence with HIP events around every kernel (from which
+the roofline of the dominant kernel is computed); the same iteration replayed
+as a captured hipGraph is reported next to it.  cpu_baseline times the FP64
+oracle (one thread) on a bounded sample of the same workload and scales it to
+the same unit.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "pulled queries/sec (fwd+bwd) & % HBM peak; batched vs per-shape at 1e-5 rel err"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_bytes(name, Q, J, V, V2, n_slots, per_point_sigma):
+    """Algorithmic bytes per launch of each kernel (the model in the design notes)."""
+    mqj = min(Q, J)
+    return {
+        "k_sample": 12 * Q + 16 * mqj + (4 * mqj if per_point_sigma else 0),
+        "k_nn": 16 * Q + 16 * J,
+        "k_forward_query": 16 * Q + 12 * mqj + 4 * V,
+        "k_backward_query": 16 * Q + 12 * mqj + 12 * V,
+        "k_tv_forward": 8 * V2,
+        "k_tv_backward": 16 * V2,
+        "k_adam": 28 * V + 4 * n_slots,
+    }.get(name)
+
+
+def build_problem(config: int):
+    import numpy as np
+
+    from paper_2308_13175_amd import synth
+    from paper_2308_13175_amd.problem import AdamConfig, Problem, spec_from_synth
+
+    t0 = time.perf_counter()
+    wl = synth.WORKLOADS[config]()
+    log("inputs: %s, %d points, %d queries/step (%.1f s)" % (wl.name, wl.n_points, wl.n_queries,
+                                                              time.perf_counter() - t0))
+    hmin = min(min(s.domain.h) for s in wl.shapes)
+    adam = AdamConfig(lr0=wl.lr0_cells * hmin, eps=1e-8 * (5e4 / max(wl.n_queries, 1)))
+    specs = [spec_from_synth(s) for s in wl.shapes]
+    import torch
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    prob = Problem(specs, m1=wl.m1, m2=wl.m2, adam=adam)
+    torch.cuda.synchronize()
+    setup_ms = (time.perf_counter() - t0) * 1e3
+    if config == 1:
+        s = wl.shapes[0]
+        prob.set_dense_field([synth.sphere_sdf_field(s.domain, 0.5, noise=0.01, seed=0)])
+    else:
+        prob.init_sphere()
+    return wl, prob, setup_ms
+
+
+def cpu_baseline(wl, budget_s: float = 16.0):
+    """The FP64 oracle on one host thread, on a bounded sample of the workload."""
+    import numpy as np
+
+    import oracle
+    from paper_2308_13175_amd import synth
+
+    s = wl.shapes[0]
+    dom = s.domain
+    pts = s.points
+    Q = s.n_queries
+    J = len(pts)
+    q_all = synth.host_queries(pts, min(Q, 2_000_000), s.sigma, seed=99)
+    cf, vf = oracle.build_band(dom.dims, dom.lo, dom.hi, pts, wl.m1, wl.m2)
+    pos = None
+    D = np.zeros(dom.n_vertices)
+    ctr = [0.5 * (dom.lo[a] + dom.hi[a]) for a in range(3)]
+    # small-sphere initial field (only its cost matters here)
+    vx, vy, vz = dom.vdims
+    xs = dom.lo[0] + np.arange(vx) * dom.h[0] - ctr[0]
+    ys = dom.lo[1] + np.arange(vy) * dom.h[1] - ctr[1]
+    zs = dom.lo[2] + np.arange(vz) * dom.h[2] - ctr[2]
+    D = (np.sqrt(xs[:, None, None] ** 2 + ys[None, :, None] ** 2 + zs[None, None, :] ** 2)
+         - 2 * min(dom.h)).reshape(-1)
+    # nearest neighbours: brute force on a query sample, scaled linearly
+    n_nn = 64
+    t0 = time.perf_counter()
+    oracle.nn_bruteforce(q_all[:n_nn], pts)
+    t = time.perf_counter() - t0
+    n_nn = int(max(64, min(len(q_all), n_nn * (0.5 * budget_s) / max(t, 1e-6))))
+    t0 = time.perf_counter()
+    nn_s = oracle.nn_bruteforce(q_all[:n_nn], pts)
+    t_nn_q = (time.perf_counter() - t0) / n_nn
+    # per-query loss/gradient work: the fixed part (TV, gradient clear) measured with no queries
+    empty = np.zeros((0, 3), np.float32)
+    t0 = time.perf_counter()
+    oracle.loss_grad(dom.dims, dom.lo, dom.hi, cf, vf, D, empty, np.zeros(0, np.int32), pts)
+    t_fixed = time.perf_counter() - t0
+    nq = min(len(q_all), 200_000)
+    nn_l = oracle.nn_exact(q_all[:nq], pts)
+    t0 = time.perf_counter()
+    oracle.loss_grad(dom.dims, dom.lo, dom.hi, cf, vf, D, q_all[:nq], nn_l, pts)
+    t_q = max(time.perf_counter() - t0 - t_fixed, 0.0) / nq
+    G = np.zeros(dom.n_vertices)
+    m = np.zeros(dom.n_vertices)
+    v = np.zeros(dom.n_vertices)
+    t0 = time.perf_counter()
+    oracle.adam(D, G, m, v, vf, 1, 0.01)
+    t_adam = time.perf_counter() - t0
+    t_iter = Q * (t_nn_q + t_q) + t_fixed + t_adam
+    Qtot = wl.n_queries
+    return {
+        "value": Qtot / (t_iter * Qtot / Q) if Q else 0.0,
+        "unit": "queries/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": ("FP64 oracle, 1 thread, shape 0 of %s: brute-force NN on %d queries + loss/gradient on %d "
+                   "queries, scaled linearly to %d queries per iteration, plus the band-wide TV/gradient clear "
+                   "and Adam over the full grid, measured once (NN %.3g s/query, loss %.3g s/query, fixed %.3g s, "
+                   "Adam %.3g s)" % (wl.name, n_nn, nq, Q, t_nn_q, t_q, t_fixed, t_adam)),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--config", type=int, default=2, choices=[1, 2, 3, 4, 5],
+                    help="workload: 1 sphere-10k, 2 torus-200k (default), 3 union24-2M, 4 batched64, 5 room-20M")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-graph", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path (--gpus %d requested)" % args.gpus,
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2308_13175_amd import gridpull as gp
+    from paper_2308_13175_amd.problem import GraphedIteration
+
+    torch.cuda.set_device(0)
+    wl, prob, setup_ms = build_problem(args.config)
+    Q, J = prob.n_queries, prob.n_points
+    n_tv = None
+    log("band: %d slots, %d optimised vertices, setup %.1f ms" % (prob.n_slots, prob.n_active, setup_ms))
+
+    for _ in range(args.warmup):
+        prob.iteration(None)
+    torch.cuda.synchronize()
+    gp.gp_timing_enable(prob.ctx, True)
+    gp.gp_timing_report(prob.ctx)          # start a clean period
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        prob.iteration(None)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    kern = gp.gp_timing_report(prob.ctx)
+    gp.gp_timing_enable(prob.ctx, False)
+    prob.sync()
+    loss = prob.loss.cpu().numpy()
+    n_valid = int(prob.n_valid.sum())
+    log("loss after %d iterations: %s, valid %d" % (args.warmup + args.steps, loss[0].tolist(), n_valid))
+
+    graph = None
+    if not args.no_graph:
+        graph = GraphedIteration(prob)
+        for _ in range(args.warmup):
+            graph.replay()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            graph.replay()
+        torch.cuda.synchronize()
+        g_elapsed = time.perf_counter() - t0
+        prob.sync()
+
+    # TV vertex count for the byte model
+    _, flags = prob.layout()
+    V2 = int(((flags & 2) > 0).sum())
+    V = prob.n_active
+    per_point_sigma = prob.sigma is not None
+    avg = {k: (n, ms / max(n, 1)) for k, (n, ms) in kern.items()}
+    dom_k = max((k for k in avg if kernel_bytes(k, Q, J, V, V2, prob.n_slots, per_point_sigma) is not None),
+                key=lambda k: kern[k][1])
+    by = kernel_bytes(dom_k, Q, J, V, V2, prob.n_slots, per_point_sigma)
+    ach = by / (avg[dom_k][1] * 1e-3) / 1e9
+    fb_ms = sum(avg[k][1] for k in ("k_forward_query", "k_tv_forward", "k_finalize", "k_backward_query",
+                                     "k_tv_backward") if k in avg)
+    fb_bytes = 16 * Q + 12 * min(Q, J) + 12 * V
+    ms_step = elapsed * 1e3 / args.steps
+    out = {
+        "metric": METRIC,
+        "value": Q * args.steps / elapsed,
+        "unit": "queries/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": wl.name, "shapes": len(wl.shapes), "points": J, "queries_per_step": Q,
+                   "grid": [list(s.domain.dims) for s in wl.shapes][:4], "m1": wl.m1, "m2": wl.m2,
+                   "slots": prob.n_slots, "optimised_vertices": V, "tv_vertices": V2,
+                   "step": "sample+nn+forward+backward+adam"},
+        "roofline": {"bound": "hbm", "kernel": dom_k, "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": ach / HBM_PEAK_GBS, "traffic": None, "bytes_per_launch": by,
+                     "avg_launch_ms": avg[dom_k][1]},
+        "fwd_bwd": {"queries_per_s": Q / (fb_ms * 1e-3), "ms": fb_ms,
+                    "algorithmic_GBps": fb_bytes / (fb_ms * 1e-3) / 1e9},
+        "kernels_avg_ms": {k: round(v[1], 5) for k, v in sorted(avg.items())},
+        "setup_ms": setup_ms,
+    }
+    if graph is not None:
+        out["graph"] = {"queries_per_s": Q * args.steps / g_elapsed, "ms_per_step": g_elapsed * 1e3 / args.steps}
+    if not args.no_cpu_baseline:
+        t0 = time.perf_counter()
+        out["cpu_baseline"] = cpu_baseline(wl)
+        log("cpu baseline took %.1f s" % (time.perf_counter() - t0))
+    prob.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

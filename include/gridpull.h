@@ -1,0 +1,264 @@
+/*
+ * gridpull.h -- C ABI of the MI355X (gfx950) GridPull pull-step library.
+ *
+ * GridPull (Chen, Liu, Han, ICCV 2023) fits a signed distance field D stored
+ * on the vertices of a uniform grid to a point cloud S, with no neural
+ * network.  One optimisation iteration samples queries q near the points,
+ * interpolates D trilinearly (Sec. 3, Eq. 1 / Eq. 3), pulls each query along
+ * the normalised field gradient, p = q - f(q) grad f(q) / |grad f(q)|, and
+ * minimises (Eq. 8)
+ *
+ *     L = L_Pull + alpha L_TV + beta L_Surface + gamma L_grad
+ *
+ * with L_Pull = |p - NN(q)| (Eq. 4), the per-vertex total variation L_TV over
+ * six axis neighbours (Eq. 5), L_Surface = |f(s)| at the surface point
+ * s = NN(q) (Eq. 6) and L_grad = 1 - cos(grad f(q), grad f(s)) (Eq. 7).
+ * Pulling is restricted to the cells within M1 cells of a cell holding a
+ * point, TV to the cells within M2 (Sec. 3, band paragraphs); only the
+ * vertices of those cells are optimised.  The optimiser is Adam with the
+ * learning rate multiplied by a decay factor every fixed number of
+ * iterations (Sec. 4, "Details").
+ *
+ * Conventions (every entry point):
+ *  - A grid has R_x x R_y x R_z cells and (R+1) vertices per axis over the
+ *    box [lo, hi]; h_a = (hi_a - lo_a) / R_a.  Vertex (i,j,k) sits at
+ *    lo + (i,j,k) h.  Linear ids are x-major: vertex (i*(R_y+1)+j)*(R_z+1)+k,
+ *    cell (cx*R_y+cy)*R_z+cz.
+ *  - Cell location is done in double: u_a = ((double)x_a - lo_a) * inv_h_a with
+ *    inv_h_a = R_a / (hi_a - lo_a); the cell is floor(u) clamped to R-1 (a
+ *    point on hi lies in the last cell); a position is inside iff
+ *    0 <= u_a <= R_a on every axis.  A query is valid iff it is inside and its
+ *    cell is in the M1 band; invalid queries carry no loss and no gradient.
+ *  - Coordinates are structure-of-arrays float32 (x[], y[], z[]).
+ *  - Pointers documented "device" are device memory owned by the caller; the
+ *    library never frees them.  Pointers documented "host" are host memory.
+ *  - The context owns its internal structures (brick directory, masks, point
+ *    buckets, scratch) and frees them in gp_destroy.
+ *  - Work is enqueued on the context's stream and is asynchronous unless the
+ *    entry point says it synchronises.  Device-detected failures (a
+ *    non-finite loss) raise a device flag that the next synchronising call
+ *    (gp_sync, gp_build_band) reports.
+ *  - No exceptions cross the ABI.  Every call returns a gp_status;
+ *    gp_last_error gives a message for the last failure.  A context is not
+ *    thread safe.
+ *  - Several shapes can share one context ("batched"): each has its own grid
+ *    and slices of the point and query arrays, and each kernel launch covers
+ *    all shapes.  A single shape is n_shapes = 1.
+ *
+ * Field layout ("slots"): values of the optimised vertices are stored in
+ * bricks of 8x8x8 vertices; the brick holding vertex (i,j,k) is
+ * (i>>3, j>>3, k>>3) and the vertex's slot is brick*512 + ((i&7)*8+(j&7))*8+(k&7).
+ * Only bricks that hold an optimised vertex exist.  Slots of different
+ * shapes are disjoint, in shape order.  The field, its gradient and the Adam
+ * moments are caller-owned float32 device arrays of n_slots entries in this
+ * layout; gp_export_layout maps slots to vertex ids.
+ */
+#ifndef GRIDPULL_H
+#define GRIDPULL_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct gp_ctx_s* gp_ctx;
+
+typedef enum {
+    GP_OK = 0,
+    GP_ERR_ARG = 1,       /* null pointer, bad size or dimension, unsupported option */
+    GP_ERR_DOMAIN = 2,    /* a point lies outside its shape's [lo, hi]              */
+    GP_ERR_CAPACITY = 3,  /* a size exceeds what the library can index             */
+    GP_ERR_OOM = 4,       /* device allocation failed                               */
+    GP_ERR_DEVICE = 5,    /* a HIP runtime call failed                              */
+    GP_ERR_STATE = 6,     /* call out of order (e.g. before gp_build_band)          */
+    GP_ERR_NUMERIC = 7    /* a loss came out non-finite                             */
+} gp_status;
+
+/* One shape of a batch (host memory).  Sec. 3: grid G of R^3 cells over the
+ * space occupied by the point cloud; here R may differ per axis. */
+typedef struct {
+    int32_t dims[3];              /* cells per axis, each >= 1                      */
+    double lo[3], hi[3];          /* domain box, hi > lo on every axis              */
+    int64_t point_off, point_cnt; /* this shape's points: [point_off, +point_cnt)   */
+    int64_t query_off, query_cnt; /* this shape's queries: [query_off, +query_cnt)  */
+} gp_shape;
+
+/* Balance weights of Eq. 8 (the paper uses alpha = beta = 1, gamma = 0.005). */
+typedef struct {
+    float alpha, beta, gamma;
+} gp_weights;
+
+/* Create a context on HIP device `device`, enqueueing on `hip_stream`
+ * (a hipStream_t; NULL = the null stream).  *out receives the context. */
+gp_status gp_create(gp_ctx* out, int device, void* hip_stream);
+
+/* Free the context and everything it owns.  NULL is ignored. */
+void gp_destroy(gp_ctx ctx);
+
+/* Message of the last failure on this context ("" if none).  The string is
+ * owned by the context and valid until the next call on it. */
+const char* gp_last_error(gp_ctx ctx);
+
+/* Change the stream later calls enqueue on. */
+gp_status gp_set_stream(gp_ctx ctx, void* hip_stream);
+
+/* Wait for the context's stream, then report any device-side flag
+ * (GP_ERR_NUMERIC for a non-finite loss since the last gp_sync). */
+gp_status gp_sync(gp_ctx ctx);
+
+/*
+ * Build the bands and indices of every shape (Sec. 3: uniform grid for query
+ * localisation, the M1 band for pulling, the M2 band for TV; the spatial
+ * index over the points that replaces the paper's KD-tree).
+ *   base cells  = cells holding at least one point (location rule above);
+ *   M1 band     = cells within Chebyshev distance m1 of a base cell (clipped);
+ *   M2 band     = same with m2;
+ *   optimised vertices = corners of M1- or M2-band cells;
+ *   TV vertices = corners of M2-band cells.
+ * shapes:   host [n_shapes]; point and query slices must lie inside the arrays
+ *           later passed and must not overlap between shapes.
+ * px,py,pz: device float32 points of all shapes; the context keeps a sorted
+ *           copy, so the arrays may be freed afterwards.
+ * m1, m2:   band half-widths in cells, 0 <= m <= 64.
+ * brick:    brick edge in vertices; only 8 is supported (else GP_ERR_ARG).
+ * n_slots_out, n_active_vertices_out: host; the field length and the number
+ *           of optimised vertices over all shapes.
+ * Synchronises.  May be called again to rebuild (previous state is dropped).
+ * Errors: GP_ERR_ARG (null pointers, n_shapes < 1, dims < 1, hi <= lo,
+ * m out of range), GP_ERR_DOMAIN (a point outside its shape's box),
+ * GP_ERR_CAPACITY (more than 2^31 slots or points), GP_ERR_OOM.
+ */
+gp_status gp_build_band(gp_ctx ctx, const gp_shape* shapes, int32_t n_shapes,
+                        const float* px, const float* py, const float* pz,
+                        int32_t m1, int32_t m2, int32_t brick,
+                        int64_t* n_slots_out, int64_t* n_active_vertices_out);
+
+/*
+ * Nearest surface point of every query (NN(q) of Eq. 4), within the query's
+ * own shape: nn_out[k] = argmin_j d2(q_k, s_j) with
+ * d2 = ((dx*dx + dy*dy) + dz*dz), dx = (double)q_x - (double)s_x in double
+ * without fused multiply-add; ties go to the lowest point index.  The index
+ * is relative to the shape's point_off.  Defined for every query, also those
+ * outside the band or the domain.
+ * qx,qy,qz: device float32 [n_queries]; n_queries must equal the end of the
+ *           last shape's query slice.  nn_out: device int32 [n_queries].
+ * Errors: GP_ERR_STATE before gp_build_band, GP_ERR_ARG.
+ */
+gp_status gp_nn_query(gp_ctx ctx, const float* qx, const float* qy, const float* qz,
+                      int64_t n_queries, int32_t* nn_out);
+
+/*
+ * Draw one iteration's queries (Sec. 3: Gaussian around randomly chosen
+ * surface points, resampled every iteration).  For shape s with J points and
+ * Q queries, query k uses source point P[(floor(k*J/Q) + o) mod J] where P is
+ * the library's spatially sorted point order and o is a per-iteration random
+ * offset, so every point is used floor(Q/J) or ceil(Q/J) times; the offset is
+ * sigma_j * z with z from Philox4x32-10 (counter (k mod 2^32, k >> 32,
+ * iteration, s), key (seed mod 2^32, seed >> 32)) and the Box-Muller
+ * transform of U = ((x >> 8) + 1/2) 2^-24: z0, z1 = sqrt(-2 ln U0)
+ * (cos, sin)(2 pi U1), z2 = sqrt(-2 ln U2) cos(2 pi U3).
+ * sigma:  device float32 per point (indexed like the points) or NULL to use
+ *         sigma_const for every point.
+ * qx,qy,qz: device float32 outputs [total queries].
+ * src_out: device int32 [total queries] or NULL; receives the source point
+ *         index (relative to point_off).
+ * iteration < 0 uses the context's device-resident iteration counter plus
+ * one (the t of the next gp_step), for replayed graphs.
+ */
+gp_status gp_sample_queries(gp_ctx ctx, uint64_t seed, int32_t iteration,
+                            const float* sigma, float sigma_const,
+                            float* qx, float* qy, float* qz, int32_t* src_out);
+
+/*
+ * Forward pass of Eq. 8 for every shape.
+ * qx,qy,qz,nn: device [n_queries] (nn as returned by gp_nn_query).
+ * field:    device float32 [n_slots].
+ * loss_out: device double [n_shapes][5] = {L, L_Pull, L_TV, L_Surface, L_grad}
+ *           where L_Pull, L_Surface and L_grad are means over the shape's
+ *           valid queries (0 if none) and L_TV is the mean of
+ *           tau_i = sqrt(sum over the six neighbours j that are TV vertices of
+ *           (D_i - D_j)^2) over the TV vertices; L = L_Pull + alpha L_TV +
+ *           beta L_Surface + gamma L_grad.
+ * n_valid_out: device int64 [n_shapes], the valid-query counts.
+ * A normalised gradient with |grad f| < 1e-12 is taken as 0 (then
+ * L_grad = 1 for that query).  The context keeps the valid counts and the
+ * per-vertex tau for the next gp_pull_backward.
+ */
+gp_status gp_pull_forward(gp_ctx ctx, const float* qx, const float* qy, const float* qz,
+                          const int32_t* nn, int64_t n_queries, const float* field,
+                          gp_weights w, double* loss_out, int64_t* n_valid_out);
+
+/*
+ * Backward pass: grad[slot] += sum_s dloss[s] * dL_s / dD[slot] for every
+ * optimised vertex, with the L of gp_pull_forward, through trilinear
+ * interpolation, the analytic gradient and its normalisation (derivative 0
+ * where |grad f| < 1e-12 and where the residual p - s is 0; d|f_s| = sign f_s).
+ * Must follow a gp_pull_forward on the same queries and field (it reuses
+ * that call's valid counts and tau); else GP_ERR_STATE.
+ * dloss: device double [n_shapes] upstream scale (1 for plain optimisation).
+ * grad:  device float32 [n_slots], accumulated into.
+ */
+gp_status gp_pull_backward(gp_ctx ctx, const float* qx, const float* qy, const float* qz,
+                           const int32_t* nn, int64_t n_queries, const float* field,
+                           gp_weights w, const double* dloss, float* grad);
+
+/*
+ * One Adam step (Kingma and Ba, 2015) on the optimised vertices at iteration
+ * t, learning rate lr0 * decay^floor((t-1)/decay_every) (Sec. 4: decay 0.3
+ * every 400 iterations); then grad is set to 0 on every slot.  Slots that are
+ * not optimised vertices keep their field value.
+ * t >= 1: that iteration.  t = 0: the context's device-resident iteration
+ *   counter plus one (so a captured graph of a whole iteration replays the
+ *   schedule correctly).  Either way the counter is left at the step's t;
+ *   gp_build_band resets it to 0.
+ * field, grad, m, v: device float32 [n_slots] (m, v start at 0).
+ * Errors: GP_ERR_ARG for t < 0, decay_every < 1, beta outside [0, 1), eps < 0.
+ */
+gp_status gp_step(gp_ctx ctx, float* field, float* grad, float* m, float* v, int32_t t,
+                  float lr0, float decay, int32_t decay_every,
+                  float beta1, float beta2, float eps);
+
+/* ---- per-kernel timing ---------------------------------------------------- */
+
+/* enable != 0: bracket every kernel this context launches with HIP events on
+ * its stream (not allowed while the stream is being captured into a graph). */
+gp_status gp_timing_enable(gp_ctx ctx, int enable);
+
+/* Synchronise, then write one line "kernel_name launches total_ms" per kernel
+ * launched since the last report into buf (host, NUL-terminated, truncated to
+ * buf_size), and start a new period.  GP_ERR_CAPACITY if buf is too small. */
+gp_status gp_timing_report(gp_ctx ctx, char* buf, int64_t buf_size);
+
+/* ---- layout helpers (not on the per-iteration path) ------------------- */
+
+/* host [n_shapes + 1]: slot_begin[s] is the first slot of shape s,
+ * slot_begin[n_shapes] = n_slots. */
+gp_status gp_shape_slots(gp_ctx ctx, int64_t* slot_begin);
+
+/* vertex_id_of_slot: device int64 [n_slots], the vertex id within the slot's
+ * shape, -1 for slots past the grid's last vertex.  slot_flags: device
+ * uint8 [n_slots] or NULL; bit 1 = optimised vertex, 2 = TV vertex,
+ * 4 = the cell whose lowest corner is this vertex is in the M1 band,
+ * 8 = ... in the M2 band, 16 = ... holds a point. */
+gp_status gp_export_layout(gp_ctx ctx, int64_t* vertex_id_of_slot, uint8_t* slot_flags);
+
+/* field[slot] = dense[dense_off(s) + vertex id] for every slot (0 where the
+ * slot has no vertex), where dense is the concatenation, in shape order, of
+ * each shape's (R+1)^3 vertex values in x-major order.  Device arrays. */
+gp_status gp_gather_vertices(gp_ctx ctx, const float* dense, float* field);
+
+/* dense[dense_off(s) + vertex id] = field[slot] for every optimised vertex;
+ * other entries are left as they are.  Device arrays. */
+gp_status gp_scatter_vertices(gp_ctx ctx, const float* field, float* dense);
+
+/* Geometric initialisation (Sec. 3): field = |x_v - centre_s| - radius_s at
+ * every slot with a vertex.  centre: host double [n_shapes][3];
+ * radius: host double [n_shapes]. */
+gp_status gp_init_sphere(gp_ctx ctx, const double* centre, const double* radius, float* field);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GRIDPULL_H */

@@ -187,3 +187,41 @@ def query_offsets(seed: int, iteration: int, stream: int, k0: int, n: int) -> np
     z = np.zeros((n, 3))
     lib.og_query_offsets(int(seed), int(iteration), int(stream), int(k0), int(n), _p(z))
     return z
+
+
+def nn_exact(queries: np.ndarray, points: np.ndarray, k: int = 16, workers: int = -1) -> np.ndarray:
+    """The same NN(q) as nn_bruteforce, for inputs too large for brute force.
+
+    A k-d tree (scipy, a library primitive) proposes the k nearest candidates;
+    they are re-ranked with the exact double distance and lowest-index tie rule
+    of og_nn_bruteforce.  Queries whose k-th candidate is not clearly farther
+    than the best (a possible tie or near tie beyond k) are re-run by brute
+    force, so the result does not depend on the tree's own rounding.
+    """
+    from scipy.spatial import cKDTree
+
+    q = np.asarray(queries, np.float32)
+    p = np.asarray(points, np.float32)
+    J = len(p)
+    if J == 0:
+        return np.full(len(q), -1, np.int32)
+    k = min(k, J)
+    tree = cKDTree(p.astype(np.float64))
+    d, idx = tree.query(q.astype(np.float64), k=k, workers=workers)
+    if k == 1:
+        d = d[:, None]
+        idx = idx[:, None]
+    qd = q.astype(np.float64)
+    pd = p.astype(np.float64)
+    dx = qd[:, None, 0] - pd[idx, 0]
+    dy = qd[:, None, 1] - pd[idx, 1]
+    dz = qd[:, None, 2] - pd[idx, 2]
+    d2 = (dx * dx + dy * dy) + dz * dz
+    best = d2.min(axis=1)
+    cand = np.where(d2 == best[:, None], idx, np.iinfo(np.int64).max)
+    out = cand.min(axis=1).astype(np.int32)
+    unsafe = (d[:, -1] <= np.sqrt(best) * (1 + 1e-7) + 1e-12) & (k < J)
+    if np.any(unsafe):
+        sel = np.nonzero(unsafe)[0]
+        out[sel] = nn_bruteforce(q[sel], p)
+    return out

@@ -1,0 +1,526 @@
+// Band and index construction (once per shape).
+//
+// Sec. 3 of the paper: a uniform grid localises queries; pulling is done only
+// in the cells within M1 of a cell that holds a point, TV only within M2; the
+// vertices of those cells are the optimised parameters.  Here the band is
+// built on the device with dense per-shape scratch flags (one byte per cell
+// and per vertex), separable Chebyshev dilation, then compacted into 8^3
+// vertex bricks addressed through a dense brick directory.  The point cloud is
+// bucketed by cell (a counting layout over the same brick slots) for the
+// nearest-neighbour search that stands in for the paper's KD-tree.
+#include <hipcub/hipcub.hpp>
+
+#include <algorithm>
+#include <memory>
+
+#include "gp_internal.h"
+
+namespace gp {
+namespace {
+
+constexpr int kThreads = 256;
+
+inline unsigned blocks_for(int64_t n, int threads = kThreads)
+{
+    int64_t b = (n + threads - 1) / threads;
+    if (b < 1) b = 1;
+    if (b > (int64_t)1 << 30) b = (int64_t)1 << 30;
+    return (unsigned)b;
+}
+
+#define GRID_STRIDE(i, n) \
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < (n); i += (int64_t)gridDim.x * blockDim.x)
+
+// bit 1 of cell flags: the cell holds a point.  Records the lowest index of a
+// point outside [lo, hi].
+__global__ void k_locate_points(const float* __restrict__ px, const float* __restrict__ py,
+                                const float* __restrict__ pz, ShapeDesc s, uint8_t* __restrict__ cells,
+                                unsigned long long* __restrict__ bad)
+{
+    GRID_STRIDE(j, s.point_cnt)
+    {
+        int64_t g = s.point_off + j;
+        Loc L = locate(s, px[g], py[g], pz[g]);
+        if (!L.inside) {
+            atomicMin(bad, (unsigned long long)j);
+            continue;
+        }
+        int64_t cid = ((int64_t)L.c[0] * s.R[1] + L.c[1]) * s.R[2] + L.c[2];
+        cells[cid] = 1;
+    }
+}
+
+// One axis of the separable Chebyshev dilation.  Source bits (src1 for the
+// M1 band, src2 for the M2 band) are ORed over |d| <= m along `axis` into
+// bits 2 and 4; bit 1 (point cells) is copied.
+__global__ void k_dilate(const uint8_t* __restrict__ in, uint8_t* __restrict__ out, int32_t R0, int32_t R1,
+                         int32_t R2, int axis, int32_t m1, int32_t m2, uint8_t src1, uint8_t src2)
+{
+    int64_t n = (int64_t)R0 * R1 * R2;
+    GRID_STRIDE(i, n)
+    {
+        int32_t cz = (int32_t)(i % R2);
+        int32_t cy = (int32_t)((i / R2) % R1);
+        int32_t cx = (int32_t)(i / ((int64_t)R2 * R1));
+        int32_t c = axis == 0 ? cx : (axis == 1 ? cy : cz);
+        int32_t Ra = axis == 0 ? R0 : (axis == 1 ? R1 : R2);
+        int64_t stride = axis == 0 ? (int64_t)R1 * R2 : (axis == 1 ? (int64_t)R2 : 1);
+        int32_t m = m1 > m2 ? m1 : m2;
+        int32_t lo = c - m < 0 ? 0 : c - m;
+        int32_t hi = c + m > Ra - 1 ? Ra - 1 : c + m;
+        uint8_t o = in[i] & 1;
+        for (int32_t d = lo; d <= hi; ++d) {
+            uint8_t v = in[i + (int64_t)(d - c) * stride];
+            int32_t ad = d > c ? d - c : c - d;
+            if (ad <= m1 && (v & src1)) o |= 2;
+            if (ad <= m2 && (v & src2)) o |= 4;
+        }
+        out[i] = o;
+    }
+}
+
+// Vertex flags: bit 1 = corner of an M1- or M2-band cell, bit 2 = corner of
+// an M2-band cell.
+__global__ void k_vertex_flags(const uint8_t* __restrict__ cells, uint8_t* __restrict__ verts, int32_t R0,
+                               int32_t R1, int32_t R2)
+{
+    const int64_t V1 = R1 + 1, V2 = R2 + 1;
+    int64_t n = (int64_t)(R0 + 1) * V1 * V2;
+    GRID_STRIDE(i, n)
+    {
+        int32_t k = (int32_t)(i % V2);
+        int32_t j = (int32_t)((i / V2) % V1);
+        int32_t ii = (int32_t)(i / (V2 * V1));
+        uint8_t o = 0;
+        for (int a = 0; a < 2; ++a) {
+            int32_t cx = ii - a;
+            if (cx < 0 || cx >= R0) continue;
+            for (int b = 0; b < 2; ++b) {
+                int32_t cy = j - b;
+                if (cy < 0 || cy >= R1) continue;
+                for (int d = 0; d < 2; ++d) {
+                    int32_t cz = k - d;
+                    if (cz < 0 || cz >= R2) continue;
+                    uint8_t f = cells[((int64_t)cx * R1 + cy) * R2 + cz];
+                    if (f & 6) o |= 1;
+                    if (f & 4) o |= 2;
+                }
+            }
+        }
+        verts[i] = o;
+    }
+}
+
+// A brick exists iff it holds an optimised vertex.
+__global__ void k_brick_active(const uint8_t* __restrict__ verts, ShapeDesc s, int32_t* __restrict__ active)
+{
+    const int64_t nbt = (int64_t)s.nb[0] * s.nb[1] * s.nb[2];
+    const int32_t V0 = s.R[0] + 1, V1 = s.R[1] + 1, V2 = s.R[2] + 1;
+    GRID_STRIDE(b, nbt)
+    {
+        int32_t bz = (int32_t)(b % s.nb[2]);
+        int32_t by = (int32_t)((b / s.nb[2]) % s.nb[1]);
+        int32_t bx = (int32_t)(b / ((int64_t)s.nb[2] * s.nb[1]));
+        int32_t any = 0;
+        for (int32_t lx = 0; lx < kBrick && !any; ++lx) {
+            int32_t i = bx * kBrick + lx;
+            if (i >= V0) break;
+            for (int32_t ly = 0; ly < kBrick && !any; ++ly) {
+                int32_t j = by * kBrick + ly;
+                if (j >= V1) break;
+                const uint8_t* row = verts + ((int64_t)i * V1 + j) * V2;
+                for (int32_t lz = 0; lz < kBrick; ++lz) {
+                    int32_t k = bz * kBrick + lz;
+                    if (k >= V2) break;
+                    if (row[k] & 1) { any = 1; break; }
+                }
+            }
+        }
+        active[b] = any;
+    }
+}
+
+__global__ void k_fill_dir(const int32_t* __restrict__ active, const int32_t* __restrict__ index, ShapeDesc s,
+                           int32_t shape, int64_t brick_base, int32_t* __restrict__ dir,
+                           BrickInfo* __restrict__ bricks)
+{
+    const int64_t nbt = (int64_t)s.nb[0] * s.nb[1] * s.nb[2];
+    GRID_STRIDE(b, nbt)
+    {
+        if (!active[b]) {
+            dir[b] = -1;
+            continue;
+        }
+        int64_t gb = brick_base + index[b];
+        dir[b] = (int32_t)gb;
+        BrickInfo bi;
+        bi.shape = shape;
+        bi.bz = (int32_t)(b % s.nb[2]);
+        bi.by = (int32_t)((b / s.nb[2]) % s.nb[1]);
+        bi.bx = (int32_t)(b / ((int64_t)s.nb[2] * s.nb[1]));
+        bricks[index[b]] = bi;
+    }
+}
+
+// Per (brick, 32-bit word): pack the vertex and cell flags of 32 slots.
+__global__ void k_fill_masks(const BrickInfo* __restrict__ bricks, int64_t n_bricks, ShapeDesc s,
+                             const uint8_t* __restrict__ cells, const uint8_t* __restrict__ verts,
+                             uint32_t* __restrict__ m_base, uint32_t* __restrict__ m_a1,
+                             uint32_t* __restrict__ m_a2, uint32_t* __restrict__ m_v,
+                             uint32_t* __restrict__ m_v2)
+{
+    const int32_t V1 = s.R[1] + 1, V2 = s.R[2] + 1;
+    GRID_STRIDE(w, n_bricks * kMaskWords)
+    {
+        int64_t b = w / kMaskWords;
+        int32_t word = (int32_t)(w % kMaskWords);
+        BrickInfo bi = bricks[b];
+        uint32_t fb = 0, f1 = 0, f2 = 0, fv = 0, fv2 = 0;
+        for (int bit = 0; bit < 32; ++bit) {
+            int32_t local = word * 32 + bit;
+            int32_t i = bi.bx * kBrick + (local >> 6);
+            int32_t j = bi.by * kBrick + ((local >> 3) & 7);
+            int32_t k = bi.bz * kBrick + (local & 7);
+            if (i > s.R[0] || j > s.R[1] || k > s.R[2]) continue;
+            uint8_t vf = verts[((int64_t)i * V1 + j) * V2 + k];
+            if (vf & 1) fv |= 1u << bit;
+            if (vf & 2) fv2 |= 1u << bit;
+            if (i < s.R[0] && j < s.R[1] && k < s.R[2]) {
+                uint8_t cf = cells[((int64_t)i * s.R[1] + j) * s.R[2] + k];
+                if (cf & 1) fb |= 1u << bit;
+                if (cf & 2) f1 |= 1u << bit;
+                if (cf & 4) f2 |= 1u << bit;
+            }
+        }
+        m_base[w] = fb;
+        m_a1[w] = f1;
+        m_a2[w] = f2;
+        m_v[w] = fv;
+        m_v2[w] = fv2;
+    }
+}
+
+// Count TV vertices and optimised vertices per shape.
+__global__ void k_count_masks(const BrickInfo* __restrict__ bricks, int64_t n_bricks,
+                              const uint32_t* __restrict__ m_v, const uint32_t* __restrict__ m_v2,
+                              unsigned long long* __restrict__ n_v, unsigned long long* __restrict__ n_v2)
+{
+    GRID_STRIDE(w, n_bricks * kMaskWords)
+    {
+        int32_t s = bricks[w / kMaskWords].shape;
+        uint32_t a = m_v[w], b = m_v2[w];
+        if (a) atomicAdd(&n_v[s], (unsigned long long)__popc(a));
+        if (b) atomicAdd(&n_v2[s], (unsigned long long)__popc(b));
+    }
+}
+
+// Point bucket keys: the slot of the point's cell (the slot of its lowest corner).
+__global__ void k_point_keys(const float* __restrict__ px, const float* __restrict__ py,
+                             const float* __restrict__ pz, Band B, int32_t shape,
+                             uint32_t* __restrict__ keys, int32_t* __restrict__ vals,
+                             unsigned* __restrict__ counts)
+{
+    const ShapeDesc& s = B.shapes[shape];
+    GRID_STRIDE(j, s.point_cnt)
+    {
+        int64_t g = s.point_off + j;
+        Loc L = locate(s, px[g], py[g], pz[g]);
+        int32_t br = brick_of(B, s, L.c[0] >> 3, L.c[1] >> 3, L.c[2] >> 3);
+        uint32_t slot = (uint32_t)br * kBrickVol + (uint32_t)local_index(L.c[0], L.c[1], L.c[2]);
+        keys[s.sorted_off + j] = slot;
+        vals[s.sorted_off + j] = (int32_t)g;
+        atomicAdd(&counts[slot], 1u);
+    }
+}
+
+__global__ void k_gather_sorted(const float* __restrict__ px, const float* __restrict__ py,
+                                const float* __restrict__ pz, const uint32_t* __restrict__ keys,
+                                const int32_t* __restrict__ vals, Band B, int64_t n,
+                                float* __restrict__ spx, float* __restrict__ spy, float* __restrict__ spz,
+                                int32_t* __restrict__ sid)
+{
+    GRID_STRIDE(i, n)
+    {
+        int32_t g = vals[i];
+        int32_t shape = B.bricks[keys[i] / kBrickVol].shape;
+        spx[i] = px[g];
+        spy[i] = py[g];
+        spz[i] = pz[g];
+        sid[i] = (int32_t)(g - B.shapes[shape].point_off);
+    }
+}
+
+struct ShapeBricks {
+    DevBuf<int32_t> dir;
+    DevBuf<BrickInfo> bricks;
+    DevBuf<uint32_t> m_base, m_a1, m_a2, m_v, m_v2;
+    int64_t n_dir = 0;
+    int64_t n_bricks = 0;
+};
+
+}  // namespace
+}  // namespace gp
+
+using namespace gp;
+
+gp_status gp_build_band_impl(gp_ctx ctx, const gp_shape* shapes, int32_t n_shapes, const float* px,
+                             const float* py, const float* pz, int32_t m1, int32_t m2)
+{
+    hipStream_t st = ctx->stream;
+    ctx->built = false;
+    ctx->have_forward = false;
+
+    // ---- host-side descriptors ------------------------------------------
+    std::vector<ShapeDesc> hs(n_shapes);
+    int64_t dir_total = 0, dense_total = 0, sorted_total = 0, tiles_total = 0;
+    int64_t n_points = 0, n_queries = 0;
+    for (int32_t s = 0; s < n_shapes; ++s) {
+        const gp_shape& in = shapes[s];
+        ShapeDesc& d = hs[s];
+        for (int a = 0; a < 3; ++a) {
+            d.lo[a] = in.lo[a];
+            d.inv_h[a] = (double)in.dims[a] / (in.hi[a] - in.lo[a]);
+            d.inv_hf[a] = (float)d.inv_h[a];
+            d.h[a] = (float)((in.hi[a] - in.lo[a]) / (double)in.dims[a]);
+            d.R[a] = in.dims[a];
+            d.nb[a] = (in.dims[a] + 1 + kBrick - 1) / kBrick;
+        }
+        d.dir_off = dir_total;
+        dir_total += (int64_t)d.nb[0] * d.nb[1] * d.nb[2];
+        d.dense_off = dense_total;
+        dense_total += (int64_t)(d.R[0] + 1) * (d.R[1] + 1) * (d.R[2] + 1);
+        d.point_off = in.point_off;
+        d.point_cnt = in.point_cnt;
+        d.query_off = in.query_off;
+        d.query_cnt = in.query_cnt;
+        d.sorted_off = sorted_total;
+        sorted_total += in.point_cnt;
+        d.tile_begin = tiles_total;
+        tiles_total += (in.query_cnt + kQueryTile - 1) / kQueryTile;
+        d.tile_end = tiles_total;
+        n_points = std::max(n_points, in.point_off + in.point_cnt);
+        n_queries = std::max(n_queries, in.query_off + in.query_cnt);
+        d.n_tv = 0;
+        d.brick_begin = d.brick_end = 0;
+    }
+    if (sorted_total >= ((int64_t)1 << 31) || n_points >= ((int64_t)1 << 31))
+        return gp_fail(ctx, GP_ERR_CAPACITY, "more than 2^31 points");
+
+    DevBuf<ShapeDesc> d_shape1;
+    GP_HIP(ctx, d_shape1.alloc(1));
+    DevBuf<unsigned long long> d_bad;
+    GP_HIP(ctx, d_bad.alloc(1));
+
+    std::vector<std::unique_ptr<ShapeBricks>> parts;
+    int64_t brick_base = 0;
+    void* cub_tmp = nullptr;
+    size_t cub_bytes = 0;
+    DevBuf<uint8_t> cub_buf;
+
+    for (int32_t s = 0; s < n_shapes; ++s) {
+        ShapeDesc& d = hs[s];
+        const int64_t nc = (int64_t)d.R[0] * d.R[1] * d.R[2];
+        const int64_t nv = (int64_t)(d.R[0] + 1) * (d.R[1] + 1) * (d.R[2] + 1);
+        const int64_t nbt = (int64_t)d.nb[0] * d.nb[1] * d.nb[2];
+        DevBuf<uint8_t> c0, c1, vf;
+        DevBuf<int32_t> active, index;
+        if (c0.alloc(nc) != hipSuccess || c1.alloc(nc) != hipSuccess || vf.alloc(nv) != hipSuccess ||
+            active.alloc(nbt) != hipSuccess || index.alloc(nbt) != hipSuccess)
+            return gp_fail(ctx, GP_ERR_OOM, "out of device memory for the band scratch of shape " +
+                                                std::to_string(s));
+        GP_HIP(ctx, hipMemsetAsync(c0.p, 0, nc, st));
+        unsigned long long init = ~0ull;
+        GP_HIP(ctx, hipMemcpyAsync(d_bad.p, &init, sizeof(init), hipMemcpyHostToDevice, st));
+        if (d.point_cnt > 0)
+            k_locate_points<<<blocks_for(d.point_cnt), kThreads, 0, st>>>(px, py, pz, d, c0.p, d_bad.p);
+        unsigned long long bad = 0;
+        GP_HIP(ctx, hipMemcpyAsync(&bad, d_bad.p, sizeof(bad), hipMemcpyDeviceToHost, st));
+        GP_HIP(ctx, hipStreamSynchronize(st));
+        if (bad != ~0ull)
+            return gp_fail(ctx, GP_ERR_DOMAIN, "shape " + std::to_string(s) + ": point " + std::to_string(bad) +
+                                                   " lies outside the domain");
+        // separable Chebyshev dilation x -> y -> z
+        k_dilate<<<blocks_for(nc), kThreads, 0, st>>>(c0.p, c1.p, d.R[0], d.R[1], d.R[2], 0, m1, m2, 1, 1);
+        k_dilate<<<blocks_for(nc), kThreads, 0, st>>>(c1.p, c0.p, d.R[0], d.R[1], d.R[2], 1, m1, m2, 2, 4);
+        k_dilate<<<blocks_for(nc), kThreads, 0, st>>>(c0.p, c1.p, d.R[0], d.R[1], d.R[2], 2, m1, m2, 2, 4);
+        k_vertex_flags<<<blocks_for(nv), kThreads, 0, st>>>(c1.p, vf.p, d.R[0], d.R[1], d.R[2]);
+        k_brick_active<<<blocks_for(nbt), kThreads, 0, st>>>(vf.p, d, active.p);
+        size_t need = 0;
+        GP_HIP(ctx, hipcub::DeviceScan::ExclusiveSum(nullptr, need, active.p, index.p, (int)nbt, st));
+        if (need > cub_bytes) {
+            GP_HIP(ctx, cub_buf.alloc(need));
+            cub_tmp = cub_buf.p;
+            cub_bytes = need;
+        }
+        GP_HIP(ctx, hipcub::DeviceScan::ExclusiveSum(cub_tmp, need, active.p, index.p, (int)nbt, st));
+        int32_t last_idx = 0, last_act = 0;
+        GP_HIP(ctx, hipMemcpyAsync(&last_idx, index.p + nbt - 1, 4, hipMemcpyDeviceToHost, st));
+        GP_HIP(ctx, hipMemcpyAsync(&last_act, active.p + nbt - 1, 4, hipMemcpyDeviceToHost, st));
+        GP_HIP(ctx, hipStreamSynchronize(st));
+        const int64_t nb_s = (int64_t)last_idx + last_act;
+        if ((brick_base + nb_s) * kBrickVol >= ((int64_t)1 << 31))
+            return gp_fail(ctx, GP_ERR_CAPACITY, "more than 2^31 field slots");
+
+        auto part = std::make_unique<ShapeBricks>();
+        part->n_dir = nbt;
+        part->n_bricks = nb_s;
+        if (part->dir.alloc(nbt) != hipSuccess || part->bricks.alloc(nb_s) != hipSuccess ||
+            part->m_base.alloc(nb_s * kMaskWords) != hipSuccess || part->m_a1.alloc(nb_s * kMaskWords) != hipSuccess ||
+            part->m_a2.alloc(nb_s * kMaskWords) != hipSuccess || part->m_v.alloc(nb_s * kMaskWords) != hipSuccess ||
+            part->m_v2.alloc(nb_s * kMaskWords) != hipSuccess)
+            return gp_fail(ctx, GP_ERR_OOM, "out of device memory for the bricks of shape " + std::to_string(s));
+        k_fill_dir<<<blocks_for(nbt), kThreads, 0, st>>>(active.p, index.p, d, s, brick_base, part->dir.p,
+                                                          part->bricks.p);
+        if (nb_s > 0)
+            k_fill_masks<<<blocks_for(nb_s * kMaskWords), kThreads, 0, st>>>(
+                part->bricks.p, nb_s, d, c1.p, vf.p, part->m_base.p, part->m_a1.p, part->m_a2.p, part->m_v.p,
+                part->m_v2.p);
+        GP_HIP(ctx, hipGetLastError());
+        d.brick_begin = brick_base;
+        d.brick_end = brick_base + nb_s;
+        brick_base += nb_s;
+        GP_HIP(ctx, hipStreamSynchronize(st));   // scratch buffers are freed at scope end
+        parts.push_back(std::move(part));
+    }
+
+    // ---- assemble the global arrays --------------------------------------
+    const int64_t n_bricks = brick_base;
+    const int64_t n_slots = n_bricks * kBrickVol;
+    ctx->n_shapes = n_shapes;
+    ctx->n_bricks = n_bricks;
+    ctx->n_slots = n_slots;
+    ctx->n_dir = dir_total;
+    ctx->n_points = n_points;
+    ctx->n_queries = n_queries;
+    ctx->n_tiles = tiles_total;
+    ctx->m1 = m1;
+    ctx->m2 = m2;
+    if (ctx->dir.alloc(dir_total) != hipSuccess || ctx->bricks.alloc(n_bricks) != hipSuccess ||
+        ctx->m_base.alloc(n_bricks * kMaskWords) != hipSuccess ||
+        ctx->m_a1.alloc(n_bricks * kMaskWords) != hipSuccess ||
+        ctx->m_a2.alloc(n_bricks * kMaskWords) != hipSuccess ||
+        ctx->m_v.alloc(n_bricks * kMaskWords) != hipSuccess ||
+        ctx->m_v2.alloc(n_bricks * kMaskWords) != hipSuccess || ctx->shapes.alloc(n_shapes) != hipSuccess)
+        return gp_fail(ctx, GP_ERR_OOM, "out of device memory for the band");
+    for (int32_t s = 0; s < n_shapes; ++s) {
+        ShapeBricks& p = *parts[s];
+        const ShapeDesc& d = hs[s];
+        GP_HIP(ctx, hipMemcpyAsync(ctx->dir.p + d.dir_off, p.dir.p, p.n_dir * 4, hipMemcpyDeviceToDevice, st));
+        if (p.n_bricks == 0) continue;
+        const size_t mb = (size_t)p.n_bricks * kMaskWords * 4;
+        const int64_t mo = d.brick_begin * kMaskWords;
+        GP_HIP(ctx, hipMemcpyAsync(ctx->bricks.p + d.brick_begin, p.bricks.p, p.n_bricks * sizeof(BrickInfo),
+                                   hipMemcpyDeviceToDevice, st));
+        GP_HIP(ctx, hipMemcpyAsync(ctx->m_base.p + mo, p.m_base.p, mb, hipMemcpyDeviceToDevice, st));
+        GP_HIP(ctx, hipMemcpyAsync(ctx->m_a1.p + mo, p.m_a1.p, mb, hipMemcpyDeviceToDevice, st));
+        GP_HIP(ctx, hipMemcpyAsync(ctx->m_a2.p + mo, p.m_a2.p, mb, hipMemcpyDeviceToDevice, st));
+        GP_HIP(ctx, hipMemcpyAsync(ctx->m_v.p + mo, p.m_v.p, mb, hipMemcpyDeviceToDevice, st));
+        GP_HIP(ctx, hipMemcpyAsync(ctx->m_v2.p + mo, p.m_v2.p, mb, hipMemcpyDeviceToDevice, st));
+    }
+
+    // per-shape vertex counts
+    DevBuf<unsigned long long> cnt;
+    GP_HIP(ctx, cnt.alloc(2 * (size_t)n_shapes));
+    GP_HIP(ctx, hipMemsetAsync(cnt.p, 0, 2 * sizeof(unsigned long long) * n_shapes, st));
+    if (n_bricks > 0)
+        k_count_masks<<<blocks_for(n_bricks * kMaskWords), kThreads, 0, st>>>(ctx->bricks.p, n_bricks, ctx->m_v.p,
+                                                                             ctx->m_v2.p, cnt.p, cnt.p + n_shapes);
+    std::vector<unsigned long long> hcnt(2 * (size_t)n_shapes);
+    GP_HIP(ctx, hipMemcpyAsync(hcnt.data(), cnt.p, hcnt.size() * 8, hipMemcpyDeviceToHost, st));
+    GP_HIP(ctx, hipStreamSynchronize(st));
+    int64_t n_active = 0;
+    for (int32_t s = 0; s < n_shapes; ++s) {
+        hs[s].n_tv = (int64_t)hcnt[n_shapes + s];
+        n_active += (int64_t)hcnt[s];
+    }
+    ctx->n_active = n_active;
+    GP_HIP(ctx, hipMemcpyAsync(ctx->shapes.p, hs.data(), n_shapes * sizeof(ShapeDesc), hipMemcpyHostToDevice, st));
+
+    // ---- query tiles -------------------------------------------------------
+    std::vector<int64_t> ts(tiles_total > 0 ? tiles_total : 1);
+    std::vector<int32_t> tsh(tiles_total > 0 ? tiles_total : 1);
+    for (int32_t s = 0; s < n_shapes; ++s)
+        for (int64_t t = hs[s].tile_begin; t < hs[s].tile_end; ++t) {
+            ts[t] = hs[s].query_off + (t - hs[s].tile_begin) * kQueryTile;
+            tsh[t] = s;
+        }
+    GP_HIP(ctx, ctx->tile_start.alloc(ts.size()));
+    GP_HIP(ctx, ctx->tile_shape.alloc(tsh.size()));
+    GP_HIP(ctx, hipMemcpyAsync(ctx->tile_start.p, ts.data(), ts.size() * 8, hipMemcpyHostToDevice, st));
+    GP_HIP(ctx, hipMemcpyAsync(ctx->tile_shape.p, tsh.data(), tsh.size() * 4, hipMemcpyHostToDevice, st));
+
+    // ---- point buckets (sorted by cell slot) ------------------------------
+    const int64_t np = sorted_total;
+    {
+        DevBuf<uint32_t> k_in, k_out;
+        DevBuf<int32_t> v_in;
+        DevBuf<unsigned> counts;
+        if (k_in.alloc(np) != hipSuccess || k_out.alloc(np) != hipSuccess || v_in.alloc(np) != hipSuccess ||
+            counts.alloc(n_slots + 1) != hipSuccess || ctx->cell_start.alloc(n_slots + 1) != hipSuccess ||
+            ctx->spx.alloc(np) != hipSuccess || ctx->spy.alloc(np) != hipSuccess || ctx->spz.alloc(np) != hipSuccess ||
+            ctx->sid.alloc(np) != hipSuccess || ctx->ox.alloc(np) != hipSuccess || ctx->oy.alloc(np) != hipSuccess ||
+            ctx->oz.alloc(np) != hipSuccess)
+            return gp_fail(ctx, GP_ERR_OOM, "out of device memory for the point buckets");
+        GP_HIP(ctx, hipMemsetAsync(counts.p, 0, (n_slots + 1) * sizeof(unsigned), st));
+        for (int32_t s = 0; s < n_shapes; ++s) {
+            if (hs[s].point_cnt == 0) continue;
+            const size_t nb = (size_t)hs[s].point_cnt * sizeof(float);
+            GP_HIP(ctx, hipMemcpyAsync(ctx->ox.p + hs[s].sorted_off, px + hs[s].point_off, nb, hipMemcpyDeviceToDevice, st));
+            GP_HIP(ctx, hipMemcpyAsync(ctx->oy.p + hs[s].sorted_off, py + hs[s].point_off, nb, hipMemcpyDeviceToDevice, st));
+            GP_HIP(ctx, hipMemcpyAsync(ctx->oz.p + hs[s].sorted_off, pz + hs[s].point_off, nb, hipMemcpyDeviceToDevice, st));
+        }
+        Band B = ctx->band();
+        for (int32_t s = 0; s < n_shapes; ++s)
+            if (hs[s].point_cnt > 0)
+                k_point_keys<<<blocks_for(hs[s].point_cnt), kThreads, 0, st>>>(px, py, pz, B, s, k_in.p, v_in.p,
+                                                                               counts.p);
+        GP_HIP(ctx, hipGetLastError());
+        // cell_start = exclusive prefix sum of the per-slot counts
+        size_t need = 0;
+        GP_HIP(ctx, hipcub::DeviceScan::ExclusiveSum(nullptr, need, counts.p, (unsigned*)ctx->cell_start.p,
+                                                     (int)(n_slots + 1), st));
+        int end_bit = 1;
+        while (((int64_t)1 << end_bit) < n_slots + 1 && end_bit < 32) ++end_bit;
+        size_t need2 = 0;
+        DevBuf<int32_t> v_out;
+        GP_HIP(ctx, v_out.alloc(np));
+        if (np > 0)
+            GP_HIP(ctx, hipcub::DeviceRadixSort::SortPairs(nullptr, need2, k_in.p, k_out.p, v_in.p, v_out.p, (int)np,
+                                                          0, end_bit, st));
+        need = std::max(need, need2);
+        if (need > cub_bytes) {
+            GP_HIP(ctx, cub_buf.alloc(need));
+            cub_tmp = cub_buf.p;
+            cub_bytes = need;
+        }
+        GP_HIP(ctx, hipcub::DeviceScan::ExclusiveSum(cub_tmp, need, counts.p, (unsigned*)ctx->cell_start.p,
+                                                     (int)(n_slots + 1), st));
+        if (np > 0) {
+            GP_HIP(ctx, hipcub::DeviceRadixSort::SortPairs(cub_tmp, need, k_in.p, k_out.p, v_in.p, v_out.p, (int)np, 0,
+                                                          end_bit, st));
+            k_gather_sorted<<<blocks_for(np), kThreads, 0, st>>>(px, py, pz, k_out.p, v_out.p, B, np, ctx->spx.p,
+                                                                 ctx->spy.p, ctx->spz.p, ctx->sid.p);
+        }
+        GP_HIP(ctx, hipGetLastError());
+        GP_HIP(ctx, hipStreamSynchronize(st));
+    }
+
+    // ---- scratch ----------------------------------------------------------
+    if (ctx->q_part.alloc((size_t)std::max<int64_t>(tiles_total, 1) * 4) != hipSuccess ||
+        ctx->tv_part.alloc((size_t)std::max<int64_t>(n_bricks, 1)) != hipSuccess ||
+        ctx->tau.alloc((size_t)std::max<int64_t>(n_slots, 1)) != hipSuccess ||
+        ctx->inv_qv.alloc(n_shapes) != hipSuccess || ctx->flag.alloc(1) != hipSuccess ||
+        ctx->iter.alloc(1) != hipSuccess || ctx->step_c.alloc(2) != hipSuccess)
+        return gp_fail(ctx, GP_ERR_OOM, "out of device memory for the iteration scratch");
+    GP_HIP(ctx, hipMemsetAsync(ctx->flag.p, 0, 4, st));
+    GP_HIP(ctx, hipMemsetAsync(ctx->iter.p, 0, 4, st));
+    GP_HIP(ctx, hipMemsetAsync(ctx->tau.p, 0, std::max<int64_t>(n_slots, 1) * 4, st));
+
+    ctx->h_shapes = hs;
+    ctx->h_slot_begin.resize(n_shapes + 1);
+    for (int32_t s = 0; s < n_shapes; ++s) ctx->h_slot_begin[s] = hs[s].brick_begin * kBrickVol;
+    ctx->h_slot_begin[n_shapes] = n_slots;
+    GP_HIP(ctx, hipStreamSynchronize(st));
+    ctx->built = true;
+    return GP_OK;
+}

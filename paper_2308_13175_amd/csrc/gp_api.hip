@@ -1,0 +1,320 @@
+// The C ABI: argument validation, status codes, stream handling.  The
+// numerical work lives in band.hip, nn.hip, sample.hip, pull.hip and step.hip.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "gp_internal.h"
+
+hipEvent_t gp_timer_begin(gp_ctx ctx)
+{
+    if (!ctx || !ctx->timing) return nullptr;
+    hipEvent_t e = nullptr;
+    if (!ctx->event_pool.empty()) {
+        e = ctx->event_pool.back();
+        ctx->event_pool.pop_back();
+    } else if (hipEventCreate(&e) != hipSuccess) {
+        return nullptr;
+    }
+    if (hipEventRecord(e, ctx->stream) != hipSuccess) {
+        ctx->event_pool.push_back(e);
+        return nullptr;
+    }
+    return e;
+}
+
+void gp_timer_end(gp_ctx ctx, const char* name, hipEvent_t begin)
+{
+    if (!ctx || !begin) return;
+    hipEvent_t e = nullptr;
+    if (!ctx->event_pool.empty()) {
+        e = ctx->event_pool.back();
+        ctx->event_pool.pop_back();
+    } else if (hipEventCreate(&e) != hipSuccess) {
+        ctx->event_pool.push_back(begin);
+        return;
+    }
+    (void)hipEventRecord(e, ctx->stream);
+    ctx->timed.push_back({name, begin, e});
+}
+
+gp_status gp_fail(gp_ctx ctx, gp_status st, const std::string& msg)
+{
+    if (ctx) ctx->err = msg;
+    return st;
+}
+
+gp_status gp_hip_fail(gp_ctx ctx, hipError_t e, const char* what)
+{
+    std::string m = std::string(what) + ": " + hipGetErrorString(e);
+    if (e == hipErrorOutOfMemory) return gp_fail(ctx, GP_ERR_OOM, m);
+    return gp_fail(ctx, GP_ERR_DEVICE, m);
+}
+
+namespace {
+
+gp_status ready(gp_ctx ctx)
+{
+    if (!ctx) return GP_ERR_ARG;
+    ctx->err.clear();
+    if (!ctx->built) return gp_fail(ctx, GP_ERR_STATE, "gp_build_band has not completed on this context");
+    if (hipSetDevice(ctx->device) != hipSuccess) return gp_fail(ctx, GP_ERR_DEVICE, "hipSetDevice failed");
+    return GP_OK;
+}
+
+gp_status check_queries(gp_ctx ctx, const void* a, const void* b, const void* c, int64_t n)
+{
+    if (n != ctx->n_queries)
+        return gp_fail(ctx, GP_ERR_ARG, "n_queries (" + std::to_string(n) + ") must equal the end of the last query "
+                                        "slice (" + std::to_string(ctx->n_queries) + ")");
+    if (n > 0 && (!a || !b || !c)) return gp_fail(ctx, GP_ERR_ARG, "null query array");
+    return GP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+gp_status gp_create(gp_ctx* out, int device, void* hip_stream)
+{
+    if (!out) return GP_ERR_ARG;
+    *out = nullptr;
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) return GP_ERR_ARG;
+    if (hipSetDevice(device) != hipSuccess) return GP_ERR_DEVICE;
+    gp_ctx c = new (std::nothrow) gp_ctx_s();
+    if (!c) return GP_ERR_OOM;
+    c->device = device;
+    c->stream = (hipStream_t)hip_stream;
+    *out = c;
+    return GP_OK;
+}
+
+void gp_destroy(gp_ctx ctx)
+{
+    if (!ctx) return;
+    (void)hipSetDevice(ctx->device);
+    (void)hipStreamSynchronize(ctx->stream);
+    for (auto& r : ctx->timed) {
+        (void)hipEventDestroy(r.a);
+        (void)hipEventDestroy(r.b);
+    }
+    for (auto e : ctx->event_pool) (void)hipEventDestroy(e);
+    delete ctx;
+}
+
+const char* gp_last_error(gp_ctx ctx)
+{
+    return ctx ? ctx->err.c_str() : "null context";
+}
+
+gp_status gp_set_stream(gp_ctx ctx, void* hip_stream)
+{
+    if (!ctx) return GP_ERR_ARG;
+    ctx->stream = (hipStream_t)hip_stream;
+    return GP_OK;
+}
+
+gp_status gp_sync(gp_ctx ctx)
+{
+    if (!ctx) return GP_ERR_ARG;
+    ctx->err.clear();
+    (void)hipSetDevice(ctx->device);
+    GP_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    if (!ctx->built) return GP_OK;
+    int32_t f = 0;
+    GP_HIP(ctx, hipMemcpy(&f, ctx->flag.p, 4, hipMemcpyDeviceToHost));
+    if (f) {
+        int32_t z = 0;
+        GP_HIP(ctx, hipMemcpy(ctx->flag.p, &z, 4, hipMemcpyHostToDevice));
+        if (f & 2) return gp_fail(ctx, GP_ERR_ARG, "a nearest-point index was outside its shape's points");
+        return gp_fail(ctx, GP_ERR_NUMERIC, "a loss was not finite");
+    }
+    return GP_OK;
+}
+
+gp_status gp_build_band(gp_ctx ctx, const gp_shape* shapes, int32_t n_shapes, const float* px, const float* py,
+                        const float* pz, int32_t m1, int32_t m2, int32_t brick, int64_t* n_slots_out,
+                        int64_t* n_active_vertices_out)
+{
+    if (!ctx) return GP_ERR_ARG;
+    ctx->err.clear();
+    if (!shapes || n_shapes < 1) return gp_fail(ctx, GP_ERR_ARG, "need at least one shape");
+    if (m1 < 0 || m2 < 0 || m1 > 64 || m2 > 64) return gp_fail(ctx, GP_ERR_ARG, "m1 and m2 must lie in [0, 64]");
+    if (brick != 8) return gp_fail(ctx, GP_ERR_ARG, "only 8^3 bricks are supported");
+    bool any_points = false;
+    for (int32_t s = 0; s < n_shapes; ++s) {
+        const gp_shape& d = shapes[s];
+        for (int a = 0; a < 3; ++a) {
+            if (d.dims[a] < 1 || d.dims[a] > (1 << 20))
+                return gp_fail(ctx, GP_ERR_ARG, "shape " + std::to_string(s) + ": dims must lie in [1, 2^20]");
+            if (!(d.hi[a] > d.lo[a]) || !std::isfinite(d.lo[a]) || !std::isfinite(d.hi[a]))
+                return gp_fail(ctx, GP_ERR_ARG, "shape " + std::to_string(s) + ": need finite lo < hi");
+        }
+        if (d.point_off < 0 || d.point_cnt < 0 || d.query_off < 0 || d.query_cnt < 0)
+            return gp_fail(ctx, GP_ERR_ARG, "shape " + std::to_string(s) + ": negative slice");
+        any_points = any_points || d.point_cnt > 0;
+        // slices of different shapes must not overlap
+        for (int32_t t = 0; t < s; ++t) {
+            const gp_shape& e = shapes[t];
+            if (d.point_cnt > 0 && e.point_cnt > 0 && d.point_off < e.point_off + e.point_cnt &&
+                e.point_off < d.point_off + d.point_cnt)
+                return gp_fail(ctx, GP_ERR_ARG, "point slices of shapes overlap");
+            if (d.query_cnt > 0 && e.query_cnt > 0 && d.query_off < e.query_off + e.query_cnt &&
+                e.query_off < d.query_off + d.query_cnt)
+                return gp_fail(ctx, GP_ERR_ARG, "query slices of shapes overlap");
+        }
+    }
+    if (any_points && (!px || !py || !pz)) return gp_fail(ctx, GP_ERR_ARG, "null point array");
+    if (hipSetDevice(ctx->device) != hipSuccess) return gp_fail(ctx, GP_ERR_DEVICE, "hipSetDevice failed");
+    gp_status st = gp_build_band_impl(ctx, shapes, n_shapes, px, py, pz, m1, m2);
+    if (st != GP_OK) {
+        (void)hipStreamSynchronize(ctx->stream);
+        return st;
+    }
+    if (n_slots_out) *n_slots_out = ctx->n_slots;
+    if (n_active_vertices_out) *n_active_vertices_out = ctx->n_active;
+    return GP_OK;
+}
+
+gp_status gp_nn_query(gp_ctx ctx, const float* qx, const float* qy, const float* qz, int64_t n_queries,
+                      int32_t* nn_out)
+{
+    gp_status st = ready(ctx);
+    if (st != GP_OK) return st;
+    if ((st = check_queries(ctx, qx, qy, qz, n_queries)) != GP_OK) return st;
+    if (n_queries > 0 && !nn_out) return gp_fail(ctx, GP_ERR_ARG, "null nn_out");
+    return gp_nn_impl(ctx, qx, qy, qz, nn_out);
+}
+
+gp_status gp_sample_queries(gp_ctx ctx, uint64_t seed, int32_t iteration, const float* sigma, float sigma_const,
+                            float* qx, float* qy, float* qz, int32_t* src_out)
+{
+    gp_status st = ready(ctx);
+    if (st != GP_OK) return st;
+    if (ctx->n_queries > 0 && (!qx || !qy || !qz)) return gp_fail(ctx, GP_ERR_ARG, "null query array");
+    if (!sigma && !(sigma_const >= 0.f)) return gp_fail(ctx, GP_ERR_ARG, "sigma_const must be >= 0");
+    return gp_sample_impl(ctx, seed, iteration, sigma, sigma_const, qx, qy, qz, src_out);
+}
+
+gp_status gp_pull_forward(gp_ctx ctx, const float* qx, const float* qy, const float* qz, const int32_t* nn,
+                          int64_t n_queries, const float* field, gp_weights w, double* loss_out,
+                          int64_t* n_valid_out)
+{
+    gp_status st = ready(ctx);
+    if (st != GP_OK) return st;
+    if ((st = check_queries(ctx, qx, qy, qz, n_queries)) != GP_OK) return st;
+    if ((n_queries > 0 && !nn) || !field || !loss_out || !n_valid_out)
+        return gp_fail(ctx, GP_ERR_ARG, "null argument");
+    return gp_forward_impl(ctx, qx, qy, qz, nn, field, w, loss_out, n_valid_out);
+}
+
+gp_status gp_pull_backward(gp_ctx ctx, const float* qx, const float* qy, const float* qz, const int32_t* nn,
+                           int64_t n_queries, const float* field, gp_weights w, const double* dloss, float* grad)
+{
+    gp_status st = ready(ctx);
+    if (st != GP_OK) return st;
+    if (!ctx->have_forward)
+        return gp_fail(ctx, GP_ERR_STATE, "gp_pull_backward needs a preceding gp_pull_forward");
+    if ((st = check_queries(ctx, qx, qy, qz, n_queries)) != GP_OK) return st;
+    if ((n_queries > 0 && !nn) || !field || !dloss || !grad) return gp_fail(ctx, GP_ERR_ARG, "null argument");
+    return gp_backward_impl(ctx, qx, qy, qz, nn, field, w, dloss, grad);
+}
+
+gp_status gp_step(gp_ctx ctx, float* field, float* grad, float* m, float* v, int32_t t, float lr0, float decay,
+                  int32_t decay_every, float beta1, float beta2, float eps)
+{
+    gp_status st = ready(ctx);
+    if (st != GP_OK) return st;
+    if (!field || !grad || !m || !v) return gp_fail(ctx, GP_ERR_ARG, "null argument");
+    if (t < 0 || decay_every < 1) return gp_fail(ctx, GP_ERR_ARG, "need t >= 0 and decay_every >= 1");
+    if (!(beta1 >= 0.f && beta1 < 1.f) || !(beta2 >= 0.f && beta2 < 1.f) || !(eps >= 0.f))
+        return gp_fail(ctx, GP_ERR_ARG, "need 0 <= beta < 1 and eps >= 0");
+    if ((st = gp_step_consts_impl(ctx, t, lr0, decay, decay_every, beta1, beta2)) != GP_OK) return st;
+    return gp_step_impl(ctx, field, grad, m, v, beta1, beta2, eps);
+}
+
+gp_status gp_timing_enable(gp_ctx ctx, int enable)
+{
+    if (!ctx) return GP_ERR_ARG;
+    ctx->timing = enable != 0;
+    return GP_OK;
+}
+
+gp_status gp_timing_report(gp_ctx ctx, char* buf, int64_t buf_size)
+{
+    if (!ctx || !buf || buf_size < 1) return GP_ERR_ARG;
+    ctx->err.clear();
+    (void)hipSetDevice(ctx->device);
+    GP_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    std::vector<std::pair<std::string, std::pair<int64_t, double>>> agg;
+    for (auto& r : ctx->timed) {
+        float ms = 0.f;
+        GP_HIP(ctx, hipEventElapsedTime(&ms, r.a, r.b));
+        size_t i = 0;
+        while (i < agg.size() && agg[i].first != r.name) ++i;
+        if (i == agg.size()) agg.push_back({r.name, {0, 0.0}});
+        agg[i].second.first += 1;
+        agg[i].second.second += ms;
+        ctx->event_pool.push_back(r.a);
+        ctx->event_pool.push_back(r.b);
+    }
+    ctx->timed.clear();
+    std::string out;
+    for (auto& a : agg) {
+        char line[256];
+        snprintf(line, sizeof(line), "%s %lld %.6f\n", a.first.c_str(), (long long)a.second.first, a.second.second);
+        out += line;
+    }
+    if ((int64_t)out.size() + 1 > buf_size) {
+        buf[0] = 0;
+        return gp_fail(ctx, GP_ERR_CAPACITY, "timing report does not fit the buffer");
+    }
+    memcpy(buf, out.c_str(), out.size() + 1);
+    return GP_OK;
+}
+
+gp_status gp_shape_slots(gp_ctx ctx, int64_t* slot_begin)
+{
+    gp_status st = ready(ctx);
+    if (st != GP_OK) return st;
+    if (!slot_begin) return gp_fail(ctx, GP_ERR_ARG, "null slot_begin");
+    for (size_t i = 0; i < ctx->h_slot_begin.size(); ++i) slot_begin[i] = ctx->h_slot_begin[i];
+    return GP_OK;
+}
+
+gp_status gp_export_layout(gp_ctx ctx, int64_t* vertex_id_of_slot, uint8_t* slot_flags)
+{
+    gp_status st = ready(ctx);
+    if (st != GP_OK) return st;
+    if (!vertex_id_of_slot && !slot_flags) return gp_fail(ctx, GP_ERR_ARG, "nothing to export");
+    return gp_layout_impl(ctx, vertex_id_of_slot, slot_flags);
+}
+
+gp_status gp_gather_vertices(gp_ctx ctx, const float* dense, float* field)
+{
+    gp_status st = ready(ctx);
+    if (st != GP_OK) return st;
+    if (!dense || !field) return gp_fail(ctx, GP_ERR_ARG, "null argument");
+    return gp_gather_impl(ctx, dense, field, true);
+}
+
+gp_status gp_scatter_vertices(gp_ctx ctx, const float* field, float* dense)
+{
+    gp_status st = ready(ctx);
+    if (st != GP_OK) return st;
+    if (!dense || !field) return gp_fail(ctx, GP_ERR_ARG, "null argument");
+    return gp_gather_impl(ctx, dense, const_cast<float*>(field), false);
+}
+
+gp_status gp_init_sphere(gp_ctx ctx, const double* centre, const double* radius, float* field)
+{
+    gp_status st = ready(ctx);
+    if (st != GP_OK) return st;
+    if (!centre || !radius || !field) return gp_fail(ctx, GP_ERR_ARG, "null argument");
+    return gp_init_sphere_impl(ctx, centre, radius, field);
+}
+
+}  // extern "C"

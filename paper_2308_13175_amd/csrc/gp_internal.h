@@ -1,0 +1,318 @@
+// Internal definitions of the gfx950 GridPull library: device-side shape
+// descriptors, the brick-sparse field layout and the helpers every kernel
+// shares (cell location, brick lookup, trilinear value and gradient).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "gridpull.h"
+
+namespace gp {
+
+constexpr int kBrick = 8;                 // vertices per brick edge
+constexpr int kBrickVol = 512;            // vertices per brick
+constexpr int kMaskWords = kBrickVol / 32;
+constexpr int kQueryBlock = 256;          // threads per block of the query kernels
+constexpr int kQueriesPerThread = 4;
+constexpr int kQueryTile = kQueryBlock * kQueriesPerThread;
+constexpr float kEpsNorm = 1e-12f;        // |grad f| below this: no normalised gradient
+
+// Per-shape constants as the kernels see them.
+struct ShapeDesc {
+    double lo[3];
+    double inv_h[3];       // R_a / (hi_a - lo_a)
+    float inv_hf[3];       // the same in float (gradient factors)
+    float h[3];
+    int32_t R[3];          // cells per axis
+    int32_t nb[3];         // bricks per axis = ceil((R+1)/8)
+    int64_t dir_off;       // first directory entry of this shape
+    int64_t brick_begin;   // global brick range [brick_begin, brick_end)
+    int64_t brick_end;
+    int64_t point_off;
+    int64_t point_cnt;
+    int64_t query_off;
+    int64_t query_cnt;
+    int64_t tile_begin;    // query tiles [tile_begin, tile_end)
+    int64_t tile_end;
+    int64_t dense_off;     // offset of the shape's (R+1)^3 dense vertex array
+    int64_t sorted_off;    // first entry of the shape's points in the sorted copy
+    int64_t n_tv;          // number of TV vertices
+};
+
+// Brick metadata: owning shape and brick coordinates.
+struct BrickInfo {
+    int32_t shape;
+    int32_t bx, by, bz;
+};
+
+// Read-only view of the band structures.
+struct Band {
+    const ShapeDesc* shapes;
+    const int32_t* dir;          // brick directory, -1 = no brick
+    const BrickInfo* bricks;
+    const uint32_t* m_a1;        // [n_bricks][16] cell (lowest corner) in the M1 band
+    const uint32_t* m_v;         // [n_bricks][16] optimised vertex
+    const uint32_t* m_v2;        // [n_bricks][16] TV vertex
+    const int64_t* tile_start;   // [n_tiles] first query of each tile
+    const int32_t* tile_shape;   // [n_tiles]
+};
+
+struct Loc {
+    int32_t c[3];
+    float t[3];
+    bool inside;
+};
+
+// Cell location in double, shared by every kernel: u = (x - lo) * inv_h,
+// c = floor(u) clamped to R-1; inside iff 0 <= u <= R.
+__device__ inline Loc locate(const ShapeDesc& s, float x, float y, float z)
+{
+#pragma clang fp contract(off)
+    Loc L;
+    const float p[3] = {x, y, z};
+    bool in = true;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        double u = ((double)p[a] - s.lo[a]) * s.inv_h[a];
+        in = in && (u >= 0.0) && (u <= (double)s.R[a]);
+        double fl = floor(u);
+        // clamp also for positions outside (their result is not used for values)
+        fl = fmin(fmax(fl, 0.0), (double)(s.R[a] - 1));
+        int32_t ci = (int32_t)fl;
+        L.c[a] = ci;
+        L.t[a] = (float)(u - (double)ci);
+    }
+    L.inside = in;
+    return L;
+}
+
+__device__ inline int32_t brick_of(const Band& B, const ShapeDesc& s, int32_t bx, int32_t by, int32_t bz)
+{
+    return B.dir[s.dir_off + ((int64_t)bx * s.nb[1] + by) * s.nb[2] + bz];
+}
+
+__device__ inline int32_t local_index(int32_t i, int32_t j, int32_t k)
+{
+    return ((i & 7) * 8 + (j & 7)) * 8 + (k & 7);
+}
+
+__device__ inline bool mask_bit(const uint32_t* m, int32_t brick, int32_t local)
+{
+    return (m[(int64_t)brick * kMaskWords + (local >> 5)] >> (local & 31)) & 1u;
+}
+
+// Slots of the eight corners of cell c, corner (a,b,c) at index 4a+2b+c.
+// Every corner of an M1-band cell exists, so no -1 is returned for them.
+__device__ inline void corner_slots(const Band& B, const ShapeDesc& s, const int32_t c[3], int32_t slot[8])
+{
+    int32_t bx[2] = {c[0] >> 3, (c[0] + 1) >> 3};
+    int32_t by[2] = {c[1] >> 3, (c[1] + 1) >> 3};
+    int32_t bz[2] = {c[2] >> 3, (c[2] + 1) >> 3};
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int d = 0; d < 2; ++d) {
+                int32_t br = brick_of(B, s, bx[a], by[b], bz[d]);
+                slot[4 * a + 2 * b + d] = br * kBrickVol + local_index(c[0] + a, c[1] + b, c[2] + d);
+            }
+}
+
+// Trilinear value and gradient from the eight corner values (Eq. 1 / Eq. 3).
+struct Interp {
+    float f;
+    float g[3];
+};
+
+__device__ inline Interp trilinear(const float D[8], const float t[3], const float inv_h[3])
+{
+    // interpolate along z, then y, then x; keep the partial differences
+    float e[4], dz[4];
+#pragma unroll
+    for (int ab = 0; ab < 4; ++ab) {
+        dz[ab] = D[2 * ab + 1] - D[2 * ab];
+        e[ab] = fmaf(t[2], dz[ab], D[2 * ab]);
+    }
+    float fa[2], fya[2], fza[2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+        fya[a] = e[2 * a + 1] - e[2 * a];
+        fa[a] = fmaf(t[1], fya[a], e[2 * a]);
+        fza[a] = fmaf(t[1], dz[2 * a + 1] - dz[2 * a], dz[2 * a]);
+    }
+    Interp r;
+    float fx = fa[1] - fa[0];
+    r.f = fmaf(t[0], fx, fa[0]);
+    r.g[0] = fx * inv_h[0];
+    r.g[1] = fmaf(t[0], fya[1] - fya[0], fya[0]) * inv_h[1];
+    r.g[2] = fmaf(t[0], fza[1] - fza[0], fza[0]) * inv_h[2];
+    return r;
+}
+
+// Adjoint of trilinear(): contribution to each corner value given
+// dl/df and dl/dgrad f.
+__device__ inline void trilinear_adjoint(const float t[3], const float inv_h[3], float df,
+                                         const float dg[3], float out[8])
+{
+    const float gx = dg[0] * inv_h[0], gy = dg[1] * inv_h[1], gz = dg[2] * inv_h[2];
+    const float wx[2] = {1.f - t[0], t[0]}, wy[2] = {1.f - t[1], t[1]}, wz[2] = {1.f - t[2], t[2]};
+    const float sg[2] = {-1.f, 1.f};
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int d = 0; d < 2; ++d) {
+                float wyz = wy[b] * wz[d];
+                float v = wyz * fmaf(wx[a], df, sg[a] * gx);
+                v = fmaf(wx[a] * wz[d] * sg[b], gy, v);
+                v = fmaf(wx[a] * wy[b] * sg[d], gz, v);
+                out[4 * a + 2 * b + d] = v;
+            }
+}
+
+}  // namespace gp
+
+// ---------------------------------------------------------------------------
+// Host-side context
+// ---------------------------------------------------------------------------
+
+template <class T>
+struct DevBuf {
+    T* p = nullptr;
+    size_t n = 0;
+    DevBuf() = default;
+    DevBuf(const DevBuf&) = delete;
+    DevBuf& operator=(const DevBuf&) = delete;
+    ~DevBuf() { release(); }
+    void release()
+    {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        n = 0;
+    }
+    hipError_t alloc(size_t count)
+    {
+        release();
+        if (count == 0) count = 1;
+        hipError_t e = hipMalloc(&p, count * sizeof(T));
+        if (e == hipSuccess) n = count;
+        else p = nullptr;
+        return e;
+    }
+};
+
+struct gp_ctx_s {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    std::string err;
+
+    // band state
+    bool built = false;
+    int32_t n_shapes = 0;
+    int32_t m1 = 0, m2 = 0;
+    int64_t n_bricks = 0;
+    int64_t n_slots = 0;
+    int64_t n_active = 0;
+    int64_t n_points = 0;       // end of the last point slice
+    int64_t n_queries = 0;      // end of the last query slice
+    int64_t n_tiles = 0;
+    int64_t n_dir = 0;
+    std::vector<gp::ShapeDesc> h_shapes;
+    std::vector<int64_t> h_slot_begin;
+
+    DevBuf<gp::ShapeDesc> shapes;
+    DevBuf<int32_t> dir;
+    DevBuf<gp::BrickInfo> bricks;
+    DevBuf<uint32_t> m_a1, m_a2, m_base, m_v, m_v2;
+    DevBuf<int64_t> tile_start;
+    DevBuf<int32_t> tile_shape;
+
+    // nearest-neighbour buckets: points sorted by cell slot
+    DevBuf<int32_t> cell_start;   // [n_slots + 1]
+    DevBuf<float> spx, spy, spz;  // sorted coordinates
+    DevBuf<int32_t> sid;          // original index within the shape
+    DevBuf<float> ox, oy, oz;     // points in their original order, at sorted_off + index
+
+    // per-iteration scratch
+    DevBuf<double> q_part;        // [n_tiles][4] sum pull, surf, grad, count
+    DevBuf<double> tv_part;       // [n_bricks] sum tau
+    DevBuf<float> tau;            // [n_slots]
+    DevBuf<double> inv_qv;        // [n_shapes] 1 / valid count (0 if none)
+    DevBuf<int32_t> flag;         // device error flag
+    DevBuf<int32_t> iter;         // device-resident iteration counter (last Adam t)
+    DevBuf<float> step_c;         // [2] lr_t / (1 - beta1^t), 1 / sqrt(1 - beta2^t)
+    bool have_forward = false;
+
+    // optional per-kernel timing with events on the context's stream
+    struct TimedLaunch {
+        const char* name;
+        hipEvent_t a, b;
+    };
+    bool timing = false;
+    std::vector<TimedLaunch> timed;
+    std::vector<hipEvent_t> event_pool;
+
+    gp::Band band() const
+    {
+        gp::Band b;
+        b.shapes = shapes.p;
+        b.dir = dir.p;
+        b.bricks = bricks.p;
+        b.m_a1 = m_a1.p;
+        b.m_v = m_v.p;
+        b.m_v2 = m_v2.p;
+        b.tile_start = tile_start.p;
+        b.tile_shape = tile_shape.p;
+        return b;
+    }
+};
+
+// Brackets one kernel launch with events when timing is enabled.
+hipEvent_t gp_timer_begin(gp_ctx ctx);
+void gp_timer_end(gp_ctx ctx, const char* name, hipEvent_t begin);
+
+struct GpTimed {
+    gp_ctx c;
+    const char* name;
+    hipEvent_t a;
+    GpTimed(gp_ctx c_, const char* n) : c(c_), name(n), a(gp_timer_begin(c_)) {}
+    ~GpTimed() { gp_timer_end(c, name, a); }
+};
+#define GP_TIMED(ctx, name) GpTimed gp_timed_scope_(ctx, name)
+
+// status helpers (defined in gp_api.hip)
+gp_status gp_fail(gp_ctx ctx, gp_status st, const std::string& msg);
+gp_status gp_hip_fail(gp_ctx ctx, hipError_t e, const char* what);
+
+#define GP_HIP(ctx, call)                                              \
+    do {                                                               \
+        hipError_t e_ = (call);                                        \
+        if (e_ != hipSuccess) return gp_hip_fail((ctx), e_, #call);    \
+    } while (0)
+
+// kernel launch wrappers implemented in the other translation units
+gp_status gp_build_band_impl(gp_ctx ctx, const gp_shape* shapes, int32_t n_shapes,
+                             const float* px, const float* py, const float* pz,
+                             int32_t m1, int32_t m2);
+gp_status gp_nn_impl(gp_ctx ctx, const float* qx, const float* qy, const float* qz, int32_t* nn);
+gp_status gp_sample_impl(gp_ctx ctx, uint64_t seed, int32_t iteration, const float* sigma,
+                         float sigma_const, float* qx, float* qy, float* qz, int32_t* src);
+gp_status gp_step_consts_impl(gp_ctx ctx, int32_t t, float lr0, float decay, int32_t decay_every, float beta1,
+                              float beta2);
+gp_status gp_forward_impl(gp_ctx ctx, const float* qx, const float* qy, const float* qz,
+                          const int32_t* nn, const float* field, gp_weights w,
+                          double* loss_out, int64_t* n_valid_out);
+gp_status gp_backward_impl(gp_ctx ctx, const float* qx, const float* qy, const float* qz,
+                           const int32_t* nn, const float* field, gp_weights w,
+                           const double* dloss, float* grad);
+gp_status gp_step_impl(gp_ctx ctx, float* field, float* grad, float* m, float* v, float beta1, float beta2,
+                       float eps);
+gp_status gp_layout_impl(gp_ctx ctx, int64_t* vid, uint8_t* flags);
+gp_status gp_gather_impl(gp_ctx ctx, const float* dense, float* field, bool to_field);
+gp_status gp_init_sphere_impl(gp_ctx ctx, const double* centre, const double* radius, float* field);

@@ -1,0 +1,351 @@
+// Forward and backward of the GridPull loss (Eq. 4-8).
+//
+// Query side, one thread per query of a 1024-query tile:
+//   locate q (double), check the M1 band, gather the 8 corners of its cell,
+//   f(q) and grad f(q) by trilinear interpolation (Eq. 1 / Eq. 3), the pull
+//   p = q - f grad f / |grad f|, the residual p - s to the query's nearest
+//   point s = NN(q) (Eq. 4), and at s: f(s) (Eq. 6) and grad f(s) for the
+//   cosine term (Eq. 7).  The forward writes per-tile sums (double); the
+//   backward recomputes the same quantities and scatters the adjoint into
+//   the 8 corners at q and the 8 corners at s with float atomics.
+// Vertex side, one block per brick: tau_i over the six axis neighbours that
+//   are TV vertices (Eq. 5) in the forward; in the backward the gradient is
+//   gathered per vertex (each vertex writes only its own slot).
+#include "gp_internal.h"
+
+namespace gp {
+namespace {
+
+struct Side {
+    int32_t slot[8];
+    float t[3];
+    Interp it;
+    float n;       // |grad f|
+    float gh[3];   // normalised gradient (0 if n < eps)
+    bool ok;       // n >= eps
+};
+
+__device__ inline void eval_side(const Band& B, const ShapeDesc& s, const float* __restrict__ D, const Loc& L,
+                                 Side& out)
+{
+    corner_slots(B, s, L.c, out.slot);
+    float v[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) v[i] = D[out.slot[i]];
+    out.t[0] = L.t[0];
+    out.t[1] = L.t[1];
+    out.t[2] = L.t[2];
+    out.it = trilinear(v, out.t, s.inv_hf);
+    const float* g = out.it.g;
+    out.n = sqrtf(fmaf(g[0], g[0], fmaf(g[1], g[1], g[2] * g[2])));
+    out.ok = out.n >= kEpsNorm;
+    const float inv = out.ok ? 1.f / out.n : 0.f;
+    out.gh[0] = g[0] * inv;
+    out.gh[1] = g[1] * inv;
+    out.gh[2] = g[2] * inv;
+}
+
+// Everything one valid query contributes.  Returns false for an invalid query.
+struct QueryState {
+    Side q, s;
+    float r[3];      // residual p - s
+    float lp;        // |p - s|
+};
+
+__device__ inline bool eval_query(const Band& B, const ShapeDesc& s, const float* __restrict__ D, float x, float y,
+                                  float z, int32_t nn, const float* __restrict__ px, const float* __restrict__ py,
+                                  const float* __restrict__ pz, int32_t* bad_nn, QueryState& st)
+{
+    Loc L = locate(s, x, y, z);
+    if (!L.inside) return false;
+    const int32_t br = brick_of(B, s, L.c[0] >> 3, L.c[1] >> 3, L.c[2] >> 3);
+    if (br < 0 || !mask_bit(B.m_a1, br, local_index(L.c[0], L.c[1], L.c[2]))) return false;
+    if (nn < 0 || nn >= s.point_cnt) {
+        atomicOr(bad_nn, 2);   // reported as an argument error by the next gp_sync
+        return false;
+    }
+    eval_side(B, s, D, L, st.q);
+    const int64_t g = s.sorted_off + nn;
+    const float sx = px[g], sy = py[g], sz = pz[g];
+    Loc Ls = locate(s, sx, sy, sz);
+    eval_side(B, s, D, Ls, st.s);
+    const float f = st.q.it.f;
+    st.r[0] = (x - sx) - f * st.q.gh[0];
+    st.r[1] = (y - sy) - f * st.q.gh[1];
+    st.r[2] = (z - sz) - f * st.q.gh[2];
+    st.lp = sqrtf(fmaf(st.r[0], st.r[0], fmaf(st.r[1], st.r[1], st.r[2] * st.r[2])));
+    return true;
+}
+
+template <int N>
+__device__ inline void block_sum(double (&v)[N], double* lds /* [4 waves][N] */)
+{
+#pragma unroll
+    for (int i = 0; i < N; ++i)
+        for (int o = 32; o > 0; o >>= 1) v[i] += __shfl_xor(v[i], o, 64);
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (lane == 0)
+        for (int i = 0; i < N; ++i) lds[wave * N + i] = v[i];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const int nw = blockDim.x >> 6;
+        for (int i = 0; i < N; ++i) {
+            double a = 0.0;
+            for (int w = 0; w < nw; ++w) a += lds[w * N + i];
+            v[i] = a;
+        }
+    }
+}
+
+__global__ __launch_bounds__(kQueryBlock) void k_forward_query(Band B, const float* __restrict__ qx,
+                                                               const float* __restrict__ qy,
+                                                               const float* __restrict__ qz,
+                                                               const int32_t* __restrict__ nn,
+                                                               const float* __restrict__ px,
+                                                               const float* __restrict__ py,
+                                                               const float* __restrict__ pz,
+                                                               const float* __restrict__ D,
+                                                               double* __restrict__ q_part, int32_t* flag)
+{
+    __shared__ double lds[4 * 4];
+    const int64_t tile = blockIdx.x;
+    const int32_t shape = B.tile_shape[tile];
+    const ShapeDesc& s = B.shapes[shape];
+    const int64_t q0 = B.tile_start[tile];
+    const int64_t qe = min(q0 + (int64_t)kQueryTile, s.query_off + s.query_cnt);
+    float sp = 0.f, ss = 0.f, sg = 0.f;
+    int cnt = 0;
+    for (int64_t k = q0 + threadIdx.x; k < qe; k += blockDim.x) {
+        QueryState st;
+        if (!eval_query(B, s, D, qx[k], qy[k], qz[k], nn[k], px, py, pz, flag, st)) continue;
+        const float lg = (st.q.ok && st.s.ok)
+                             ? 1.f - fmaf(st.q.gh[0], st.s.gh[0], fmaf(st.q.gh[1], st.s.gh[1], st.q.gh[2] * st.s.gh[2]))
+                             : 1.f;
+        sp += st.lp;
+        ss += fabsf(st.s.it.f);
+        sg += lg;
+        ++cnt;
+    }
+    double v[4] = {(double)sp, (double)ss, (double)sg, (double)cnt};
+    block_sum<4>(v, lds);
+    if (threadIdx.x == 0)
+        for (int i = 0; i < 4; ++i) q_part[tile * 4 + i] = v[i];
+}
+
+__global__ __launch_bounds__(kQueryBlock) void k_backward_query(Band B, const float* __restrict__ qx,
+                                                                const float* __restrict__ qy,
+                                                                const float* __restrict__ qz,
+                                                                const int32_t* __restrict__ nn,
+                                                                const float* __restrict__ px,
+                                                                const float* __restrict__ py,
+                                                                const float* __restrict__ pz,
+                                                                const float* __restrict__ D, gp_weights w,
+                                                                const double* __restrict__ dloss,
+                                                                const double* __restrict__ inv_qv,
+                                                                float* __restrict__ G, int32_t* flag)
+{
+    const int64_t tile = blockIdx.x;
+    const int32_t shape = B.tile_shape[tile];
+    const ShapeDesc& s = B.shapes[shape];
+    const int64_t q0 = B.tile_start[tile];
+    const int64_t qe = min(q0 + (int64_t)kQueryTile, s.query_off + s.query_cnt);
+    const float scale = (float)(dloss[shape] * inv_qv[shape]);
+    for (int64_t k = q0 + threadIdx.x; k < qe; k += blockDim.x) {
+        QueryState st;
+        if (!eval_query(B, s, D, qx[k], qy[k], qz[k], nn[k], px, py, pz, flag, st)) continue;
+        const float f = st.q.it.f;
+        const float inv_lp = st.lp > 0.f ? 1.f / st.lp : 0.f;
+        const float e[3] = {st.r[0] * inv_lp, st.r[1] * inv_lp, st.r[2] * inv_lp};
+        const float* gh = st.q.gh;
+        const float* ghs = st.s.gh;
+        // pull term: d/df = -gh.e ; d/dgh = -f e, projected through gh = g/|g|
+        const float df = -fmaf(gh[0], e[0], fmaf(gh[1], e[1], gh[2] * e[2]));
+        float dg[3] = {0.f, 0.f, 0.f}, dgs[3] = {0.f, 0.f, 0.f};
+        if (st.q.ok) {
+            const float inv_n = 1.f / st.q.n;
+            const float u[3] = {-f * e[0], -f * e[1], -f * e[2]};
+            const float ug = fmaf(u[0], gh[0], fmaf(u[1], gh[1], u[2] * gh[2]));
+#pragma unroll
+            for (int a = 0; a < 3; ++a) dg[a] = (u[a] - ug * gh[a]) * inv_n;
+        }
+        // gradient-consistency term through both normalised gradients
+        if (st.q.ok && st.s.ok) {
+            const float c = fmaf(gh[0], ghs[0], fmaf(gh[1], ghs[1], gh[2] * ghs[2]));
+            const float kq = w.gamma / st.q.n, ks = w.gamma / st.s.n;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                dg[a] -= kq * (ghs[a] - c * gh[a]);
+                dgs[a] = -ks * (gh[a] - c * ghs[a]);
+            }
+        }
+        const float fs = st.s.it.f;
+        const float dfs = w.beta * (fs > 0.f ? 1.f : (fs < 0.f ? -1.f : 0.f));
+        float cq[8], cs[8];
+        trilinear_adjoint(st.q.t, s.inv_hf, df, dg, cq);
+        trilinear_adjoint(st.s.t, s.inv_hf, dfs, dgs, cs);
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            atomicAdd(&G[st.q.slot[i]], scale * cq[i]);
+            atomicAdd(&G[st.s.slot[i]], scale * cs[i]);
+        }
+    }
+}
+
+// Slot of vertex (i,j,k) of shape s, or -1 outside the grid or the bricks.
+__device__ inline int32_t vertex_slot(const Band& B, const ShapeDesc& s, int32_t own, const BrickInfo& bi, int32_t i,
+                                      int32_t j, int32_t k)
+{
+    if (i < 0 || j < 0 || k < 0 || i > s.R[0] || j > s.R[1] || k > s.R[2]) return -1;
+    const int32_t bx = i >> 3, by = j >> 3, bz = k >> 3;
+    const int32_t br = (bx == bi.bx && by == bi.by && bz == bi.bz) ? own : brick_of(B, s, bx, by, bz);
+    if (br < 0) return -1;
+    return br * kBrickVol + local_index(i, j, k);
+}
+
+__device__ inline bool is_tv(const Band& B, int32_t slot)
+{
+    return slot >= 0 && mask_bit(B.m_v2, slot / kBrickVol, slot % kBrickVol);
+}
+
+__global__ __launch_bounds__(256) void k_tv_forward(Band B, const float* __restrict__ D, float* __restrict__ tau,
+                                                    double* __restrict__ tv_part)
+{
+    __shared__ double lds[4];
+    const int32_t brick = blockIdx.x;
+    const BrickInfo bi = B.bricks[brick];
+    const ShapeDesc& s = B.shapes[bi.shape];
+    float acc = 0.f;
+    for (int local = threadIdx.x; local < kBrickVol; local += blockDim.x) {
+        const int32_t slot = brick * kBrickVol + local;
+        if (!mask_bit(B.m_v2, brick, local)) continue;
+        const int32_t i = bi.bx * kBrick + (local >> 6), j = bi.by * kBrick + ((local >> 3) & 7),
+                      k = bi.bz * kBrick + (local & 7);
+        const float dv = D[slot];
+        const int32_t nb[6] = {vertex_slot(B, s, brick, bi, i + 1, j, k), vertex_slot(B, s, brick, bi, i - 1, j, k),
+                               vertex_slot(B, s, brick, bi, i, j + 1, k), vertex_slot(B, s, brick, bi, i, j - 1, k),
+                               vertex_slot(B, s, brick, bi, i, j, k + 1), vertex_slot(B, s, brick, bi, i, j, k - 1)};
+        float s2 = 0.f;
+#pragma unroll
+        for (int o = 0; o < 6; ++o) {
+            if (!is_tv(B, nb[o])) continue;
+            const float d = dv - D[nb[o]];
+            s2 = fmaf(d, d, s2);
+        }
+        const float t = sqrtf(s2);
+        tau[slot] = t;
+        acc += t;
+    }
+    double v[1] = {(double)acc};
+    block_sum<1>(v, lds);
+    if (threadIdx.x == 0) tv_part[brick] = v[0];
+}
+
+__global__ __launch_bounds__(256) void k_tv_backward(Band B, const float* __restrict__ D,
+                                                     const float* __restrict__ tau, gp_weights w,
+                                                     const double* __restrict__ dloss, float* __restrict__ G)
+{
+    const int32_t brick = blockIdx.x;
+    const BrickInfo bi = B.bricks[brick];
+    const ShapeDesc& s = B.shapes[bi.shape];
+    if (s.n_tv <= 0) return;
+    const float scale = (float)((double)w.alpha * dloss[bi.shape] / (double)s.n_tv);
+    for (int local = threadIdx.x; local < kBrickVol; local += blockDim.x) {
+        const int32_t slot = brick * kBrickVol + local;
+        if (!mask_bit(B.m_v2, brick, local)) continue;
+        const int32_t i = bi.bx * kBrick + (local >> 6), j = bi.by * kBrick + ((local >> 3) & 7),
+                      k = bi.bz * kBrick + (local & 7);
+        const float dv = D[slot];
+        const float tv = tau[slot];
+        const float inv_tv = tv > 0.f ? 1.f / tv : 0.f;
+        const int32_t nb[6] = {vertex_slot(B, s, brick, bi, i + 1, j, k), vertex_slot(B, s, brick, bi, i - 1, j, k),
+                               vertex_slot(B, s, brick, bi, i, j + 1, k), vertex_slot(B, s, brick, bi, i, j - 1, k),
+                               vertex_slot(B, s, brick, bi, i, j, k + 1), vertex_slot(B, s, brick, bi, i, j, k - 1)};
+        float acc = 0.f;
+#pragma unroll
+        for (int o = 0; o < 6; ++o) {
+            if (!is_tv(B, nb[o])) continue;
+            const float d = dv - D[nb[o]];
+            const float tj = tau[nb[o]];
+            const float inv_tj = tj > 0.f ? 1.f / tj : 0.f;
+            acc = fmaf(d, inv_tv + inv_tj, acc);
+        }
+        G[slot] += scale * acc;
+    }
+}
+
+// One block per shape: deterministic sums of the tile and brick partials.
+__global__ __launch_bounds__(256) void k_finalize(Band B, const double* __restrict__ q_part,
+                                                  const double* __restrict__ tv_part, gp_weights w,
+                                                  double* __restrict__ loss_out, int64_t* __restrict__ n_valid_out,
+                                                  double* __restrict__ inv_qv, int32_t* __restrict__ flag)
+{
+    __shared__ double lds[4 * 5];
+    const int32_t shape = blockIdx.x;
+    const ShapeDesc& s = B.shapes[shape];
+    double v[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int64_t t = s.tile_begin + threadIdx.x; t < s.tile_end; t += blockDim.x)
+        for (int i = 0; i < 4; ++i) v[i] += q_part[t * 4 + i];
+    for (int64_t b = s.brick_begin + threadIdx.x; b < s.brick_end; b += blockDim.x) v[4] += tv_part[b];
+    block_sum<5>(v, lds);
+    if (threadIdx.x == 0) {
+        const double nq = v[3];
+        const double iq = nq > 0.0 ? 1.0 / nq : 0.0;
+        const double pull = v[0] * iq, surf = v[1] * iq, grad = v[2] * iq;
+        const double tv = s.n_tv > 0 ? v[4] / (double)s.n_tv : 0.0;
+        const double total = pull + (double)w.alpha * tv + (double)w.beta * surf + (double)w.gamma * grad;
+        loss_out[shape * 5 + 0] = total;
+        loss_out[shape * 5 + 1] = pull;
+        loss_out[shape * 5 + 2] = tv;
+        loss_out[shape * 5 + 3] = surf;
+        loss_out[shape * 5 + 4] = grad;
+        n_valid_out[shape] = (int64_t)nq;
+        inv_qv[shape] = iq;
+        if (!isfinite(total)) atomicOr(flag, 1);
+    }
+}
+
+}  // namespace
+}  // namespace gp
+
+using namespace gp;
+
+gp_status gp_forward_impl(gp_ctx ctx, const float* qx, const float* qy, const float* qz, const int32_t* nn,
+                          const float* field, gp_weights w, double* loss_out, int64_t* n_valid_out)
+{
+    hipStream_t st = ctx->stream;
+    Band B = ctx->band();
+    if (ctx->n_tiles > 0) {
+        GP_TIMED(ctx, "k_forward_query");
+        k_forward_query<<<(unsigned)ctx->n_tiles, kQueryBlock, 0, st>>>(B, qx, qy, qz, nn, ctx->ox.p, ctx->oy.p,
+                                                                        ctx->oz.p, field, ctx->q_part.p, ctx->flag.p);
+    }
+    if (ctx->n_bricks > 0) {
+        GP_TIMED(ctx, "k_tv_forward");
+        k_tv_forward<<<(unsigned)ctx->n_bricks, 256, 0, st>>>(B, field, ctx->tau.p, ctx->tv_part.p);
+    }
+    GP_TIMED(ctx, "k_finalize");
+    k_finalize<<<(unsigned)ctx->n_shapes, 256, 0, st>>>(B, ctx->q_part.p, ctx->tv_part.p, w, loss_out, n_valid_out,
+                                                        ctx->inv_qv.p, ctx->flag.p);
+    GP_HIP(ctx, hipGetLastError());
+    ctx->have_forward = true;
+    return GP_OK;
+}
+
+gp_status gp_backward_impl(gp_ctx ctx, const float* qx, const float* qy, const float* qz, const int32_t* nn,
+                           const float* field, gp_weights w, const double* dloss, float* grad)
+{
+    hipStream_t st = ctx->stream;
+    Band B = ctx->band();
+    if (ctx->n_tiles > 0) {
+        GP_TIMED(ctx, "k_backward_query");
+        k_backward_query<<<(unsigned)ctx->n_tiles, kQueryBlock, 0, st>>>(B, qx, qy, qz, nn, ctx->ox.p, ctx->oy.p,
+                                                                         ctx->oz.p, field, w, dloss, ctx->inv_qv.p,
+                                                                         grad, ctx->flag.p);
+    }
+    if (ctx->n_bricks > 0) {
+        GP_TIMED(ctx, "k_tv_backward");
+        k_tv_backward<<<(unsigned)ctx->n_bricks, 256, 0, st>>>(B, field, ctx->tau.p, w, dloss, grad);
+    }
+    GP_HIP(ctx, hipGetLastError());
+    return GP_OK;
+}

@@ -1,0 +1,185 @@
+// Adam step over the field slots (Sec. 4 "Details": Adam with a stepwise
+// decayed learning rate; only band variables are optimised, Sec. 3) and the
+// layout helpers that convert between the brick slots and dense vertex ids.
+#include "gp_internal.h"
+
+namespace gp {
+namespace {
+
+constexpr int kThreads = 256;
+
+inline unsigned blocks_for(int64_t n)
+{
+    int64_t b = (n + kThreads - 1) / kThreads;
+    if (b < 1) b = 1;
+    if (b > (int64_t)1 << 30) b = (int64_t)1 << 30;
+    return (unsigned)b;
+}
+
+#define GRID_STRIDE(i, n) \
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < (n); i += (int64_t)gridDim.x * blockDim.x)
+
+// Step constants on the device, so that a captured graph of a whole
+// iteration advances the schedule on every replay.  t_arg >= 1 sets the
+// iteration; t_arg == 0 advances the stored counter by one.
+__global__ void k_step_consts(int32_t* __restrict__ iter, float* __restrict__ c, int32_t t_arg, float lr0,
+                              float decay, int32_t decay_every, float beta1, float beta2)
+{
+    const int32_t t = t_arg > 0 ? t_arg : *iter + 1;
+    *iter = t;
+    const double lr = (double)lr0 * pow((double)decay, (double)((t - 1) / decay_every));
+    const double bc1 = 1.0 - pow((double)beta1, (double)t);
+    const double bc2 = 1.0 - pow((double)beta2, (double)t);
+    c[0] = (float)(lr / bc1);
+    c[1] = (float)(1.0 / sqrt(bc2));
+}
+
+// One thread per slot; c[0] = lr_t / (1 - beta1^t), c[1] = 1 / sqrt(1 - beta2^t).
+__global__ void k_adam(const uint32_t* __restrict__ m_v, int64_t n_slots, float* __restrict__ D,
+                       float* __restrict__ G, float* __restrict__ M, float* __restrict__ V,
+                       const float* __restrict__ c, float beta1, float beta2, float eps)
+{
+    const float lr_over_bc1 = c[0], inv_sqrt_bc2 = c[1];
+    GRID_STRIDE(i, n_slots)
+    {
+        const uint32_t word = m_v[i >> 5];
+        const float g = G[i];
+        if ((word >> (i & 31)) & 1u) {
+            const float m = fmaf(beta1, M[i], (1.f - beta1) * g);
+            const float v = fmaf(beta2, V[i], (1.f - beta2) * g * g);
+            M[i] = m;
+            V[i] = v;
+            D[i] -= lr_over_bc1 * m / fmaf(sqrtf(v), inv_sqrt_bc2, eps);
+        }
+        G[i] = 0.f;
+    }
+}
+
+__device__ inline int64_t slot_vertex(const Band& B, int64_t slot, int32_t& shape, int32_t ijk[3])
+{
+    const BrickInfo bi = B.bricks[slot / kBrickVol];
+    const int32_t local = (int32_t)(slot % kBrickVol);
+    const ShapeDesc& s = B.shapes[bi.shape];
+    shape = bi.shape;
+    ijk[0] = bi.bx * kBrick + (local >> 6);
+    ijk[1] = bi.by * kBrick + ((local >> 3) & 7);
+    ijk[2] = bi.bz * kBrick + (local & 7);
+    if (ijk[0] > s.R[0] || ijk[1] > s.R[1] || ijk[2] > s.R[2]) return -1;
+    return ((int64_t)ijk[0] * (s.R[1] + 1) + ijk[1]) * (s.R[2] + 1) + ijk[2];
+}
+
+__global__ void k_layout(Band B, const uint32_t* __restrict__ m_base, const uint32_t* __restrict__ m_a2,
+                         int64_t n_slots, int64_t* __restrict__ vid, uint8_t* __restrict__ flags)
+{
+    GRID_STRIDE(i, n_slots)
+    {
+        int32_t shape, ijk[3];
+        const int64_t v = slot_vertex(B, i, shape, ijk);
+        if (vid) vid[i] = v;
+        if (flags) {
+            const int64_t w = i >> 5;
+            const uint32_t bit = 1u << (i & 31);
+            uint8_t f = 0;
+            if (B.m_v[w] & bit) f |= 1;
+            if (B.m_v2[w] & bit) f |= 2;
+            if (B.m_a1[w] & bit) f |= 4;
+            if (m_a2[w] & bit) f |= 8;
+            if (m_base[w] & bit) f |= 16;
+            flags[i] = f;
+        }
+    }
+}
+
+__global__ void k_gather(Band B, int64_t n_slots, const float* __restrict__ dense, float* __restrict__ field,
+                         int to_field)
+{
+    GRID_STRIDE(i, n_slots)
+    {
+        int32_t shape, ijk[3];
+        const int64_t v = slot_vertex(B, i, shape, ijk);
+        const int64_t off = B.shapes[shape].dense_off;
+        if (to_field) {
+            field[i] = v >= 0 ? dense[off + v] : 0.f;
+        } else if (v >= 0 && ((B.m_v[i >> 5] >> (i & 31)) & 1u)) {
+            const_cast<float*>(dense)[off + v] = field[i];
+        }
+    }
+}
+
+__global__ void k_init_sphere(Band B, int64_t n_slots, const double* __restrict__ centre,
+                              const double* __restrict__ radius, float* __restrict__ field)
+{
+    GRID_STRIDE(i, n_slots)
+    {
+        int32_t shape, ijk[3];
+        const int64_t v = slot_vertex(B, i, shape, ijk);
+        if (v < 0) {
+            field[i] = 0.f;
+            continue;
+        }
+        const ShapeDesc& s = B.shapes[shape];
+        double r2 = 0.0;
+        for (int a = 0; a < 3; ++a) {
+            const double x = s.lo[a] + (double)ijk[a] / s.inv_h[a] - centre[3 * shape + a];
+            r2 += x * x;
+        }
+        field[i] = (float)(sqrt(r2) - radius[shape]);
+    }
+}
+
+}  // namespace
+}  // namespace gp
+
+using namespace gp;
+
+gp_status gp_step_consts_impl(gp_ctx ctx, int32_t t, float lr0, float decay, int32_t decay_every, float beta1,
+                              float beta2)
+{
+    GP_TIMED(ctx, "k_step_consts");
+    k_step_consts<<<1, 1, 0, ctx->stream>>>(ctx->iter.p, ctx->step_c.p, t, lr0, decay, decay_every, beta1, beta2);
+    GP_HIP(ctx, hipGetLastError());
+    return GP_OK;
+}
+
+gp_status gp_step_impl(gp_ctx ctx, float* field, float* grad, float* m, float* v, float beta1, float beta2, float eps)
+{
+    if (ctx->n_slots == 0) return GP_OK;
+    GP_TIMED(ctx, "k_adam");
+    k_adam<<<blocks_for(ctx->n_slots), kThreads, 0, ctx->stream>>>(ctx->m_v.p, ctx->n_slots, field, grad, m, v,
+                                                                   ctx->step_c.p, beta1, beta2, eps);
+    GP_HIP(ctx, hipGetLastError());
+    return GP_OK;
+}
+
+gp_status gp_layout_impl(gp_ctx ctx, int64_t* vid, uint8_t* flags)
+{
+    if (ctx->n_slots == 0) return GP_OK;
+    k_layout<<<blocks_for(ctx->n_slots), kThreads, 0, ctx->stream>>>(ctx->band(), ctx->m_base.p, ctx->m_a2.p,
+                                                                     ctx->n_slots, vid, flags);
+    GP_HIP(ctx, hipGetLastError());
+    return GP_OK;
+}
+
+gp_status gp_gather_impl(gp_ctx ctx, const float* dense, float* field, bool to_field)
+{
+    if (ctx->n_slots == 0) return GP_OK;
+    k_gather<<<blocks_for(ctx->n_slots), kThreads, 0, ctx->stream>>>(ctx->band(), ctx->n_slots, dense, field,
+                                                                     to_field ? 1 : 0);
+    GP_HIP(ctx, hipGetLastError());
+    return GP_OK;
+}
+
+gp_status gp_init_sphere_impl(gp_ctx ctx, const double* centre, const double* radius, float* field)
+{
+    if (ctx->n_slots == 0) return GP_OK;
+    const int32_t n = ctx->n_shapes;
+    DevBuf<double> d;
+    GP_HIP(ctx, d.alloc(4 * (size_t)n));
+    GP_HIP(ctx, hipMemcpyAsync(d.p, centre, 3 * sizeof(double) * n, hipMemcpyHostToDevice, ctx->stream));
+    GP_HIP(ctx, hipMemcpyAsync(d.p + 3 * n, radius, sizeof(double) * n, hipMemcpyHostToDevice, ctx->stream));
+    k_init_sphere<<<blocks_for(ctx->n_slots), kThreads, 0, ctx->stream>>>(ctx->band(), ctx->n_slots, d.p, d.p + 3 * n,
+                                                                          field);
+    GP_HIP(ctx, hipGetLastError());
+    GP_HIP(ctx, hipStreamSynchronize(ctx->stream));   // the scratch is freed on return
+    return GP_OK;
+}

@@ -1,0 +1,217 @@
+"""HIP path vs the FP64 oracle, element by element, on seeded inputs.
+
+Bar: bit-exact for band sets, valid-query counts and nearest-neighbour
+indices; per-step loss terms within 1e-5 relative; gradients within 1e-5 of
+the largest oracle gradient entry (norm-relative).
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2308_13175_amd import synth
+from helpers import (assert_grad_close, assert_terms_close, compare_band, log, loss_terms, make_problem, spec)
+
+pytestmark = pytest.mark.gpu
+
+
+def _sphere_case(res=64, J=10_000, Q=50_000, sigma=0.02, m1=3, m2=3, seed=0):
+    dom = synth.cube_domain(res)
+    pts = synth.sphere_points(J, 0.5, seed=seed)
+    q = synth.host_queries(pts, Q, sigma, seed=seed + 100)
+    D = synth.sphere_sdf_field(dom, 0.5, noise=0.01, seed=seed)
+    return dom, pts, q, D
+
+
+def _run_gpu(dom, pts, q, D, m1=3, m2=3, weights=(1.0, 1.0, 0.005)):
+    prob = make_problem([spec(pts, dom, len(q), 0.0)], m1=m1, m2=m2, weights=weights)
+    prob.set_dense_field([D])
+    prob.set_queries(q)
+    prob.nearest()
+    prob.forward()
+    prob.grad.zero_()
+    prob.backward()
+    prob.sync()
+    return prob
+
+
+def _oracle(dom, pts, q, D, m1=3, m2=3, weights=(1.0, 1.0, 0.005)):
+    cf, vf = oracle.build_band(dom.dims, dom.lo, dom.hi, pts, m1, m2)
+    nn = oracle.nn_bruteforce(q, pts)
+    ref = oracle.loss_grad(dom.dims, dom.lo, dom.hi, cf, vf, D.astype(np.float64), q, nn, pts, *weights)
+    return cf, vf, nn, ref
+
+
+@pytest.mark.parametrize("m1,m2", [(3, 3), (1, 4), (4, 2)])
+def test_sphere_64_parity(m1, m2):
+    log("case: sphere 64^3 J=10k Q=50k m1=%d m2=%d" % (m1, m2))
+    dom, pts, q, D = _sphere_case()
+    prob = _run_gpu(dom, pts, q, D, m1, m2)
+    cf, vf, nn, ref = _oracle(dom, pts, q, D, m1, m2)
+    compare_band(prob, 0, dom, cf, vf)
+    assert prob.n_active == int((vf & 1).sum())
+    assert np.array_equal(prob.nn[: len(q)].cpu().numpy(), nn)
+    got, nv = loss_terms(prob)
+    assert int(nv[0]) == ref["n_valid"]
+    assert_terms_close(got[0], ref)
+    assert_grad_close(prob.dense_grad()[0], ref["dD"])
+    prob.close()
+
+
+def test_anisotropic_grid_and_edge_cases():
+    """Anisotropic cells, a point on hi, queries outside the domain, duplicate points."""
+    log("case: anisotropic 24x17x31 with edge cases")
+    # bounds exactly representable in float32, so points placed on lo/hi are inside
+    dom = synth.Domain((24, 17, 31), (-1.125, -0.625, -0.875), (0.875, 0.8125, 1.0625))
+    rng = np.random.default_rng(5)
+    pts = (synth.sphere_points(3000, 0.45, seed=3) + np.float32(0.05)).astype(np.float32)
+    pts[0] = np.array(dom.hi, dtype=np.float32)          # exactly on hi
+    pts[1] = np.array(dom.lo, dtype=np.float32)          # exactly on lo
+    pts[2] = pts[3]                                      # duplicate: NN ties
+    q = synth.host_queries(pts, 9000, 0.05, seed=7)
+    q[:20] = np.float32(3.0)                             # outside the domain
+    q[20:40] = pts[3:23]                                 # exactly on points
+    q[40] = pts[2]
+    D = rng.normal(size=dom.n_vertices).astype(np.float32) * 0.2
+    prob = _run_gpu(dom, pts, q, D, 2, 3)
+    cf, vf, nn, ref = _oracle(dom, pts, q, D, 2, 3)
+    compare_band(prob, 0, dom, cf, vf)
+    got_nn = prob.nn[: len(q)].cpu().numpy()
+    assert np.array_equal(got_nn, nn)
+    assert got_nn[40] == 2
+    got, nv = loss_terms(prob)
+    assert int(nv[0]) == ref["n_valid"]
+    assert_terms_close(got[0], ref)
+    assert_grad_close(prob.dense_grad()[0], ref["dD"])
+    prob.close()
+
+
+def test_dense_band_when_m_covers_the_grid():
+    log("case: M >= R (every cell optimised)")
+    dom = synth.cube_domain(12)
+    pts = synth.sphere_points(500, 0.5, seed=9)
+    q = synth.host_queries(pts, 3000, 0.2, seed=10)
+    D = synth.sphere_sdf_field(dom, 0.5, noise=0.05, seed=1)
+    prob = _run_gpu(dom, pts, q, D, 12, 12)
+    cf, vf, nn, ref = _oracle(dom, pts, q, D, 12, 12)
+    assert np.all(cf & 2) and np.all(vf & 1)
+    compare_band(prob, 0, dom, cf, vf)
+    got, nv = loss_terms(prob)
+    assert int(nv[0]) == ref["n_valid"]
+    assert_terms_close(got[0], ref)
+    assert_grad_close(prob.dense_grad()[0], ref["dD"])
+    prob.close()
+
+
+def test_constant_field_takes_the_zero_gradient_path():
+    log("case: constant field")
+    dom = synth.cube_domain(16)
+    pts = synth.sphere_points(400, 0.5, seed=11)
+    q = synth.host_queries(pts, 2000, 0.05, seed=12)
+    D = np.full(dom.n_vertices, 0.25, np.float32)
+    prob = _run_gpu(dom, pts, q, D)
+    cf, vf, nn, ref = _oracle(dom, pts, q, D)
+    got, nv = loss_terms(prob)
+    assert got[0][4] == 1.0 and ref["grad"] == 1.0
+    assert_terms_close(got[0], ref)
+    g = prob.dense_grad()[0]
+    assert np.all(np.isfinite(g))
+    assert_grad_close(g, ref["dD"])
+    prob.close()
+
+
+@pytest.mark.parametrize("weights", [(1.0, 0.0, 0.0), (0.0, 1.0, 0.0), (0.0, 0.0, 1.0), (2.0, 0.5, 0.3)])
+def test_each_term_separately(weights):
+    log("case: weights", weights)
+    dom, pts, q, D = _sphere_case(res=32, J=3000, Q=12_000, sigma=0.04, seed=4)
+    prob = _run_gpu(dom, pts, q, D, 3, 3, weights)
+    _, _, _, ref = _oracle(dom, pts, q, D, 3, 3, weights)
+    got, _ = loss_terms(prob)
+    assert_terms_close(got[0], ref)
+    assert_grad_close(prob.dense_grad()[0], ref["dD"])
+    prob.close()
+
+
+def test_adam_step_parity():
+    import torch
+
+    log("case: Adam steps")
+    dom, pts, q, D = _sphere_case(res=32, J=2000, Q=4000, sigma=0.04, seed=6)
+    prob = make_problem([spec(pts, dom, len(q), 0.0)])
+    prob.set_dense_field([D])
+    cf, vf = oracle.build_band(dom.dims, dom.lo, dom.hi, pts, 3, 3)
+    rng = np.random.default_rng(0)
+    Dd = D.astype(np.float64)
+    m = np.zeros(dom.n_vertices)
+    v = np.zeros(dom.n_vertices)
+    for t in (1, 2, 3):
+        G = (rng.normal(size=dom.n_vertices) * 10.0 ** rng.uniform(-6, -2, dom.n_vertices)).astype(np.float32)
+        dense_g = torch.from_numpy(G).cuda()
+        from paper_2308_13175_amd import gridpull as gp
+        gp.gp_gather_vertices(prob.ctx, dense_g, prob.grad)
+        prob.step(t, lr0=0.01)
+        oracle.adam(Dd, G.astype(np.float64), m, v, vf, t, lr0=0.01)
+        got = prob.dense_field()[0]
+        act = (vf & 1) > 0
+        assert np.max(np.abs(got[act] - Dd[act])) <= 1e-5 * 0.01 * t + 1e-7
+        # the gradient buffer is cleared by the step
+        assert float(prob.grad.abs().max()) == 0.0
+    # vertices outside the band never move (their slots are not exported)
+    prob.close()
+
+
+def test_sampler_offsets_and_stratification():
+    import torch
+
+    log("case: sampler")
+    dom = synth.cube_domain(32)
+    pts = synth.sphere_points(3000, 0.5, seed=13)
+    sig = np.linspace(0.01, 0.05, len(pts)).astype(np.float32)
+    Q = 7001                                     # not a multiple of J
+    prob = make_problem([spec(pts, dom, Q, sig)])
+    for it in (1, 2):
+        prob.sample(seed=12345, iteration=it)
+        prob.sync()
+        q = prob.queries().astype(np.float64)
+        src = prob.src[:Q].cpu().numpy()
+        counts = np.bincount(src, minlength=len(pts))
+        assert counts.min() >= Q // len(pts) and counts.max() <= -(-Q // len(pts))
+        z = oracle.query_offsets(12345, it, 0, 0, Q)
+        expect = pts[src].astype(np.float64) + sig[src][:, None].astype(np.float64) * z
+        err = np.abs(q - expect)
+        tol = sig[src][:, None] * (1e-5 * (1 + np.abs(z))) + 1e-6
+        assert np.all(err <= tol), float(np.max(err / tol))
+    prob.close()
+
+
+def test_batched_equals_single_shape():
+    log("case: batched vs single")
+    shapes = []
+    rng = np.random.default_rng(21)
+    for i, res in enumerate((16, 32, 24)):
+        dom = synth.Domain((res, res + 3, res - 2), (-1.0, -1.0, -1.0), (1.0, 1.1, 0.95))
+        pts = synth.sphere_points(800 * (i + 1), 0.3 + 0.1 * i, seed=30 + i)
+        q = synth.host_queries(pts, 3000 * (i + 1), 0.05, seed=40 + i)
+        D = synth.sphere_sdf_field(dom, 0.3 + 0.1 * i, noise=0.02, seed=i)
+        shapes.append((dom, pts, q, D))
+    batch = make_problem([spec(p, d, len(q), 0.0) for d, p, q, D in shapes])
+    batch.set_dense_field([D for d, p, q, D in shapes])
+    batch.set_queries(np.concatenate([q for d, p, q, D in shapes]))
+    batch.nearest()
+    batch.forward()
+    batch.backward()
+    bl, bn = loss_terms(batch)
+    bg = batch.dense_grad()
+    for i, (dom, pts, q, D) in enumerate(shapes):
+        single = _run_gpu(dom, pts, q, D)
+        sl, sn = loss_terms(single)
+        assert bn[i] == sn[0]
+        assert np.max(np.abs(bl[i] - sl[0]) / np.maximum(np.abs(sl[0]), 1e-30)) <= 1e-5
+        sg = single.dense_grad()[0]
+        assert np.max(np.abs(bg[i] - sg)) <= 1e-5 * np.abs(sg).max()
+        _, _, _, ref = _oracle(dom, pts, q, D)
+        assert_terms_close(bl[i], ref)
+        assert_grad_close(bg[i], ref["dD"])
+        single.close()
+    batch.close()
