@@ -19,7 +19,7 @@ constexpr int kMaskWords = kBrickVol / 32;
 constexpr int kQueryBlock = 256;          // threads per block of the query kernels
 constexpr int kQueriesPerThread = 4;
 constexpr int kQueryTile = kQueryBlock * kQueriesPerThread;
-constexpr float kEpsNorm = 1e-12f;        // |grad f| below this: no normalised gradient
+constexpr double kEpsNorm = 1e-12;        // |grad f| below this: no normalised gradient
 
 // Per-shape constants as the kernels see them.
 struct ShapeDesc {
@@ -54,6 +54,7 @@ struct Band {
     const ShapeDesc* shapes;
     const int32_t* dir;          // brick directory, -1 = no brick
     const BrickInfo* bricks;
+    const uint32_t* m_base;      // [n_bricks][16] cell (lowest corner) holds a point
     const uint32_t* m_a1;        // [n_bricks][16] cell (lowest corner) in the M1 band
     const uint32_t* m_v;         // [n_bricks][16] optimised vertex
     const uint32_t* m_v2;        // [n_bricks][16] TV vertex
@@ -63,7 +64,7 @@ struct Band {
 
 struct Loc {
     int32_t c[3];
-    float t[3];
+    double t[3];     // exact local coordinate in [0, 1]
     bool inside;
 };
 
@@ -84,7 +85,7 @@ __device__ inline Loc locate(const ShapeDesc& s, float x, float y, float z)
         fl = fmin(fmax(fl, 0.0), (double)(s.R[a] - 1));
         int32_t ci = (int32_t)fl;
         L.c[a] = ci;
-        L.t[a] = (float)(u - (double)ci);
+        L.t[a] = u - (double)ci;
     }
     L.inside = in;
     return L;
@@ -123,34 +124,60 @@ __device__ inline void corner_slots(const Band& B, const ShapeDesc& s, const int
             }
 }
 
-// Trilinear value and gradient from the eight corner values (Eq. 1 / Eq. 3).
+// Block-wide minimum of v[0..2] and maximum of v[3..5] (blockDim = 256).
+// Every thread receives the result.  scratch: shared int [4 * 6].
+__device__ inline void block_minmax6(int32_t v[6], int32_t* scratch)
+{
+#pragma unroll
+    for (int i = 0; i < 6; ++i)
+        for (int o = 32; o > 0; o >>= 1) {
+            int32_t w = __shfl_xor(v[i], o, 64);
+            v[i] = i < 3 ? min(v[i], w) : max(v[i], w);
+        }
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (lane == 0)
+        for (int i = 0; i < 6; ++i) scratch[wave * 6 + i] = v[i];
+    __syncthreads();
+    const int nw = blockDim.x >> 6;
+    for (int i = 0; i < 6; ++i) {
+        int32_t r = scratch[i];
+        for (int w = 1; w < nw; ++w) r = i < 3 ? min(r, scratch[w * 6 + i]) : max(r, scratch[w * 6 + i]);
+        v[i] = r;
+    }
+    __syncthreads();
+}
+
+// Trilinear value and gradient from the eight corner values (Eq. 1 / Eq. 3),
+// in double from the float corner values and the exact double local
+// coordinate: the gradient is a sum of corner differences that can cancel,
+// and its error would be amplified by the normalisation 1/|grad f|.
 struct Interp {
-    float f;
-    float g[3];
+    double f;
+    double g[3];
 };
 
-__device__ inline Interp trilinear(const float D[8], const float t[3], const float inv_h[3])
+__device__ inline Interp trilinear(const float D[8], const double t[3], const double inv_h[3])
 {
     // interpolate along z, then y, then x; keep the partial differences
-    float e[4], dz[4];
+    double e[4], dz[4];
 #pragma unroll
     for (int ab = 0; ab < 4; ++ab) {
-        dz[ab] = D[2 * ab + 1] - D[2 * ab];
-        e[ab] = fmaf(t[2], dz[ab], D[2 * ab]);
+        dz[ab] = (double)D[2 * ab + 1] - (double)D[2 * ab];
+        e[ab] = fma(t[2], dz[ab], (double)D[2 * ab]);
     }
-    float fa[2], fya[2], fza[2];
+    double fa[2], fya[2], fza[2];
 #pragma unroll
     for (int a = 0; a < 2; ++a) {
         fya[a] = e[2 * a + 1] - e[2 * a];
-        fa[a] = fmaf(t[1], fya[a], e[2 * a]);
-        fza[a] = fmaf(t[1], dz[2 * a + 1] - dz[2 * a], dz[2 * a]);
+        fa[a] = fma(t[1], fya[a], e[2 * a]);
+        fza[a] = fma(t[1], dz[2 * a + 1] - dz[2 * a], dz[2 * a]);
     }
     Interp r;
-    float fx = fa[1] - fa[0];
-    r.f = fmaf(t[0], fx, fa[0]);
+    const double fx = fa[1] - fa[0];
+    r.f = fma(t[0], fx, fa[0]);
     r.g[0] = fx * inv_h[0];
-    r.g[1] = fmaf(t[0], fya[1] - fya[0], fya[0]) * inv_h[1];
-    r.g[2] = fmaf(t[0], fza[1] - fza[0], fza[0]) * inv_h[2];
+    r.g[1] = fma(t[0], fya[1] - fya[0], fya[0]) * inv_h[1];
+    r.g[2] = fma(t[0], fza[1] - fza[0], fza[0]) * inv_h[2];
     return r;
 }
 
@@ -264,6 +291,7 @@ struct gp_ctx_s {
         b.shapes = shapes.p;
         b.dir = dir.p;
         b.bricks = bricks.p;
+        b.m_base = m_base.p;
         b.m_a1 = m_a1.p;
         b.m_v = m_v.p;
         b.m_v2 = m_v2.p;

@@ -16,40 +16,54 @@
 namespace gp {
 namespace {
 
+// One side (the query q or its surface point s): the cell, the slots of its
+// corners and the field there.  Value, gradient and normalised gradient are
+// kept in double: the pull residual and the adjoint below subtract nearly
+// equal quantities both far from the surface (|f| >> |q - s|) and near
+// convergence (p close to s).
 struct Side {
+    int32_t c[3];      // cell
     int32_t slot[8];
-    float t[3];
-    Interp it;
-    float n;       // |grad f|
-    float gh[3];   // normalised gradient (0 if n < eps)
-    bool ok;       // n >= eps
+    float t[3];        // local coordinate (for the adjoint weights)
+    double f;          // f
+    double g[3];       // grad f
+    double n;          // |grad f|
+    double gh[3];      // grad f / |grad f| (0 if |grad f| < eps)
+    bool ok;           // |grad f| >= eps
 };
 
 __device__ inline void eval_side(const Band& B, const ShapeDesc& s, const float* __restrict__ D, const Loc& L,
                                  Side& out)
 {
+    out.c[0] = L.c[0];
+    out.c[1] = L.c[1];
+    out.c[2] = L.c[2];
     corner_slots(B, s, L.c, out.slot);
     float v[8];
 #pragma unroll
     for (int i = 0; i < 8; ++i) v[i] = D[out.slot[i]];
-    out.t[0] = L.t[0];
-    out.t[1] = L.t[1];
-    out.t[2] = L.t[2];
-    out.it = trilinear(v, out.t, s.inv_hf);
-    const float* g = out.it.g;
-    out.n = sqrtf(fmaf(g[0], g[0], fmaf(g[1], g[1], g[2] * g[2])));
+    out.t[0] = (float)L.t[0];
+    out.t[1] = (float)L.t[1];
+    out.t[2] = (float)L.t[2];
+    const Interp it = trilinear(v, L.t, s.inv_h);
+    out.f = it.f;
+    out.g[0] = it.g[0];
+    out.g[1] = it.g[1];
+    out.g[2] = it.g[2];
+    out.n = sqrt(fma(it.g[0], it.g[0], fma(it.g[1], it.g[1], it.g[2] * it.g[2])));
     out.ok = out.n >= kEpsNorm;
-    const float inv = out.ok ? 1.f / out.n : 0.f;
-    out.gh[0] = g[0] * inv;
-    out.gh[1] = g[1] * inv;
-    out.gh[2] = g[2] * inv;
+    const double inv = out.ok ? 1.0 / out.n : 0.0;
+    out.gh[0] = it.g[0] * inv;
+    out.gh[1] = it.g[1] * inv;
+    out.gh[2] = it.g[2] * inv;
 }
 
 // Everything one valid query contributes.  Returns false for an invalid query.
 struct QueryState {
     Side q, s;
-    float r[3];      // residual p - s
-    float lp;        // |p - s|
+    double d[3];     // q - s (exact)
+    double r[3];     // residual p - s = (q - s) - f gh
+    double lp;       // |p - s|
 };
 
 __device__ inline bool eval_query(const Band& B, const ShapeDesc& s, const float* __restrict__ D, float x, float y,
@@ -69,11 +83,13 @@ __device__ inline bool eval_query(const Band& B, const ShapeDesc& s, const float
     const float sx = px[g], sy = py[g], sz = pz[g];
     Loc Ls = locate(s, sx, sy, sz);
     eval_side(B, s, D, Ls, st.s);
-    const float f = st.q.it.f;
-    st.r[0] = (x - sx) - f * st.q.gh[0];
-    st.r[1] = (y - sy) - f * st.q.gh[1];
-    st.r[2] = (z - sz) - f * st.q.gh[2];
-    st.lp = sqrtf(fmaf(st.r[0], st.r[0], fmaf(st.r[1], st.r[1], st.r[2] * st.r[2])));
+    st.d[0] = (double)x - (double)sx;
+    st.d[1] = (double)y - (double)sy;
+    st.d[2] = (double)z - (double)sz;
+    const double f = st.q.f;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) st.r[a] = fma(-f, st.q.gh[a], st.d[a]);
+    st.lp = sqrt(fma(st.r[0], st.r[0], fma(st.r[1], st.r[1], st.r[2] * st.r[2])));
     return true;
 }
 
@@ -113,23 +129,47 @@ __global__ __launch_bounds__(kQueryBlock) void k_forward_query(Band B, const flo
     const ShapeDesc& s = B.shapes[shape];
     const int64_t q0 = B.tile_start[tile];
     const int64_t qe = min(q0 + (int64_t)kQueryTile, s.query_off + s.query_cnt);
-    float sp = 0.f, ss = 0.f, sg = 0.f;
+    double sp = 0.0, ss = 0.0, sg = 0.0;
     int cnt = 0;
     for (int64_t k = q0 + threadIdx.x; k < qe; k += blockDim.x) {
         QueryState st;
         if (!eval_query(B, s, D, qx[k], qy[k], qz[k], nn[k], px, py, pz, flag, st)) continue;
-        const float lg = (st.q.ok && st.s.ok)
-                             ? 1.f - fmaf(st.q.gh[0], st.s.gh[0], fmaf(st.q.gh[1], st.s.gh[1], st.q.gh[2] * st.s.gh[2]))
-                             : 1.f;
+        const double lg = (st.q.ok && st.s.ok)
+                              ? 1.0 - fma(st.q.gh[0], st.s.gh[0], fma(st.q.gh[1], st.s.gh[1], st.q.gh[2] * st.s.gh[2]))
+                              : 1.0;
         sp += st.lp;
-        ss += fabsf(st.s.it.f);
+        ss += fabs(st.s.f);
         sg += lg;
         ++cnt;
     }
-    double v[4] = {(double)sp, (double)ss, (double)sg, (double)cnt};
+    double v[4] = {sp, ss, sg, (double)cnt};
     block_sum<4>(v, lds);
     if (threadIdx.x == 0)
         for (int i = 0; i < 4; ++i) q_part[tile * 4 + i] = v[i];
+}
+
+constexpr int kAccExpand = 2;        // vertices added around the tile's cell box for the s-side corners
+constexpr int kAccMax = 8192;        // LDS accumulators per block
+
+// Vertex box of a tile: accumulate there in LDS, flush once per vertex.
+struct AccBox {
+    int32_t lo[3], dim[3];
+    bool ok;
+};
+
+__device__ inline void scatter_side(const Side& sd, const float cv[8], const AccBox& A, float* __restrict__ acc,
+                                    float* __restrict__ G, float scale)
+{
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        const int32_t x = sd.c[0] + (i >> 2) - A.lo[0], y = sd.c[1] + ((i >> 1) & 1) - A.lo[1],
+                      z = sd.c[2] + (i & 1) - A.lo[2];
+        if (A.ok && (uint32_t)x < (uint32_t)A.dim[0] && (uint32_t)y < (uint32_t)A.dim[1] &&
+            (uint32_t)z < (uint32_t)A.dim[2])
+            atomicAdd(&acc[(x * A.dim[1] + y) * A.dim[2] + z], cv[i]);
+        else
+            atomicAdd(&G[sd.slot[i]], scale * cv[i]);
+    }
 }
 
 __global__ __launch_bounds__(kQueryBlock) void k_backward_query(Band B, const float* __restrict__ qx,
@@ -144,49 +184,87 @@ __global__ __launch_bounds__(kQueryBlock) void k_backward_query(Band B, const fl
                                                                 const double* __restrict__ inv_qv,
                                                                 float* __restrict__ G, int32_t* flag)
 {
+    __shared__ float s_acc[kAccMax];
+    __shared__ int32_t s_red[4 * 6];
     const int64_t tile = blockIdx.x;
     const int32_t shape = B.tile_shape[tile];
     const ShapeDesc& s = B.shapes[shape];
     const int64_t q0 = B.tile_start[tile];
     const int64_t qe = min(q0 + (int64_t)kQueryTile, s.query_off + s.query_cnt);
     const float scale = (float)(dloss[shape] * inv_qv[shape]);
+
+    // vertex box around the cells of the tile's queries
+    int32_t box[6] = {0x7fffffff, 0x7fffffff, 0x7fffffff, -1, -1, -1};
+    for (int64_t k = q0 + threadIdx.x; k < qe; k += blockDim.x) {
+        const Loc L = locate(s, qx[k], qy[k], qz[k]);
+        if (!L.inside) continue;
+        for (int a = 0; a < 3; ++a) {
+            box[a] = min(box[a], L.c[a]);
+            box[3 + a] = max(box[3 + a], L.c[a]);
+        }
+    }
+    block_minmax6(box, s_red);
+    AccBox A;
+    int64_t nv = 1;
+    for (int a = 0; a < 3; ++a) {
+        A.lo[a] = max(box[a] - kAccExpand, 0);
+        A.dim[a] = max(min(box[3 + a] + 1 + kAccExpand, s.R[a]) - A.lo[a] + 1, 0);
+        nv *= A.dim[a];
+    }
+    A.ok = box[3] >= 0 && nv <= kAccMax;
+    if (A.ok) {
+        for (int32_t i = threadIdx.x; i < (int32_t)nv; i += blockDim.x) s_acc[i] = 0.f;
+        __syncthreads();
+    }
+
     for (int64_t k = q0 + threadIdx.x; k < qe; k += blockDim.x) {
         QueryState st;
         if (!eval_query(B, s, D, qx[k], qy[k], qz[k], nn[k], px, py, pz, flag, st)) continue;
-        const float f = st.q.it.f;
-        const float inv_lp = st.lp > 0.f ? 1.f / st.lp : 0.f;
-        const float e[3] = {st.r[0] * inv_lp, st.r[1] * inv_lp, st.r[2] * inv_lp};
-        const float* gh = st.q.gh;
-        const float* ghs = st.s.gh;
-        // pull term: d/df = -gh.e ; d/dgh = -f e, projected through gh = g/|g|
-        const float df = -fmaf(gh[0], e[0], fmaf(gh[1], e[1], gh[2] * e[2]));
-        float dg[3] = {0.f, 0.f, 0.f}, dgs[3] = {0.f, 0.f, 0.f};
+        // pull term, d l / d f = -gh.e with e = r/|r|; d l / d grad f is the
+        // projection of -f e orthogonal to gh over |grad f|, which equals
+        // -f/(|grad f| |r|) (I - gh gh^T)(q - s) because r = (q - s) - f gh
+        const double inv_lp = st.lp > 0.0 ? 1.0 / st.lp : 0.0;
+        const double* gh = st.q.gh;
+        const double* ghs = st.s.gh;
+        const double df = -(gh[0] * st.r[0] + gh[1] * st.r[1] + gh[2] * st.r[2]) * inv_lp;
+        double dg[3] = {0.0, 0.0, 0.0}, dgs[3] = {0.0, 0.0, 0.0};
         if (st.q.ok) {
-            const float inv_n = 1.f / st.q.n;
-            const float u[3] = {-f * e[0], -f * e[1], -f * e[2]};
-            const float ug = fmaf(u[0], gh[0], fmaf(u[1], gh[1], u[2] * gh[2]));
+            const double k = -st.q.f * inv_lp / st.q.n;
+            const double dd = gh[0] * st.d[0] + gh[1] * st.d[1] + gh[2] * st.d[2];
 #pragma unroll
-            for (int a = 0; a < 3; ++a) dg[a] = (u[a] - ug * gh[a]) * inv_n;
+            for (int a = 0; a < 3; ++a) dg[a] = k * fma(-dd, gh[a], st.d[a]);
         }
         // gradient-consistency term through both normalised gradients
         if (st.q.ok && st.s.ok) {
-            const float c = fmaf(gh[0], ghs[0], fmaf(gh[1], ghs[1], gh[2] * ghs[2]));
-            const float kq = w.gamma / st.q.n, ks = w.gamma / st.s.n;
+            const double c = gh[0] * ghs[0] + gh[1] * ghs[1] + gh[2] * ghs[2];
+            const double kq = (double)w.gamma / st.q.n, ks = (double)w.gamma / st.s.n;
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
-                dg[a] -= kq * (ghs[a] - c * gh[a]);
-                dgs[a] = -ks * (gh[a] - c * ghs[a]);
+                dg[a] -= kq * fma(-c, gh[a], ghs[a]);
+                dgs[a] = -ks * fma(-c, ghs[a], gh[a]);
             }
         }
-        const float fs = st.s.it.f;
-        const float dfs = w.beta * (fs > 0.f ? 1.f : (fs < 0.f ? -1.f : 0.f));
+        const double fs = st.s.f;
+        const float dfs = w.beta * (fs > 0.0 ? 1.f : (fs < 0.0 ? -1.f : 0.f));
+        const float dgf[3] = {(float)dg[0], (float)dg[1], (float)dg[2]};
+        const float dgsf[3] = {(float)dgs[0], (float)dgs[1], (float)dgs[2]};
         float cq[8], cs[8];
-        trilinear_adjoint(st.q.t, s.inv_hf, df, dg, cq);
-        trilinear_adjoint(st.s.t, s.inv_hf, dfs, dgs, cs);
-#pragma unroll
-        for (int i = 0; i < 8; ++i) {
-            atomicAdd(&G[st.q.slot[i]], scale * cq[i]);
-            atomicAdd(&G[st.s.slot[i]], scale * cs[i]);
+        trilinear_adjoint(st.q.t, s.inv_hf, (float)df, dgf, cq);
+        trilinear_adjoint(st.s.t, s.inv_hf, dfs, dgsf, cs);
+        scatter_side(st.q, cq, A, s_acc, G, scale);
+        scatter_side(st.s, cs, A, s_acc, G, scale);
+    }
+
+    // flush: one global atomic per vertex of the box that received anything
+    if (A.ok) {
+        __syncthreads();
+        for (int32_t li = threadIdx.x; li < (int32_t)nv; li += blockDim.x) {
+            const float v = s_acc[li];
+            if (v == 0.f) continue;
+            const int32_t z = A.lo[2] + li % A.dim[2], y = A.lo[1] + (li / A.dim[2]) % A.dim[1],
+                          x = A.lo[0] + li / (A.dim[2] * A.dim[1]);
+            const int32_t br = brick_of(B, s, x >> 3, y >> 3, z >> 3);
+            atomicAdd(&G[br * kBrickVol + local_index(x, y, z)], scale * v);
         }
     }
 }

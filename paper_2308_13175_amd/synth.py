@@ -105,6 +105,20 @@ class Primitive:
         p = 1.6075
         return 4 * math.pi * (((a * b) ** p + (a * c) ** p + (b * c) ** p) / 3) ** (1 / p)
 
+    def bounds(self):
+        c = np.asarray(self.centre, dtype=np.float64)
+        if self.kind == "torus":
+            R, r = self.size[0], self.size[1]
+            e = np.array([R + r, R + r, r])
+        else:
+            e = np.asarray(self.size, dtype=np.float64)
+        return c - e, c + e
+
+    def overlaps(self, other: "Primitive") -> bool:
+        a0, a1 = self.bounds()
+        b0, b1 = other.bounds()
+        return bool(np.all(a0 < b1) and np.all(b0 < a1))
+
     def inside(self, x: np.ndarray) -> np.ndarray:
         """Strictly inside (points on the surface are outside)."""
         d = x - np.asarray(self.centre)
@@ -181,7 +195,7 @@ def union_surface_points(prims: Sequence[Primitive], n: int, rng,
             x = p.sample(rng, int(k))
             keep = np.ones(len(x), dtype=bool)
             for j, o in enumerate(prims):
-                if j != i:
+                if j != i and p.overlaps(o):
                     keep &= ~o.inside(x)
             for o in extra_inside:
                 keep &= ~o.inside(x)
@@ -237,15 +251,31 @@ def room_points(n: int = 20_000_000, n_furniture: int = 200, noise: float = 0.00
                               (float(hx), float(hy), float(hz))))
     areas = np.array([room.area()] + [p.area() for p in furn])
     probs = areas / areas.sum()
+    bl = np.array([p.bounds()[0] for p in furn])
+    bh = np.array([p.bounds()[1] for p in furn])
+    overlap = np.all((bl[:, None, :] < bh[None, :, :]) & (bl[None, :, :] < bh[:, None, :]), axis=2)
+    np.fill_diagonal(overlap, False)
     chunks = []
     got = 0
     while got < n:
         want = int((n - got) * 1.2) + 1024
         counts = rng.multinomial(want, probs)
         x = room.sample(rng, int(counts[0]))
+        # room points strictly inside a piece of furniture are hidden: test each
+        # piece only against the points in its footprint (x-sorted slices)
         keep = np.ones(len(x), dtype=bool)
-        for o in furn:
-            keep &= ~o.inside(x)
+        order = np.argsort(x[:, 0], kind="stable")
+        xs = x[order, 0]
+        for i, o in enumerate(furn):
+            a, b = np.searchsorted(xs, bl[i, 0], "right"), np.searchsorted(xs, bh[i, 0], "left")
+            if b <= a:
+                continue
+            cand = order[a:b]
+            y = x[cand]
+            sel = (y[:, 1] > bl[i, 1]) & (y[:, 1] < bh[i, 1]) & (y[:, 2] < bh[i, 2])
+            if np.any(sel):
+                c2 = cand[sel]
+                keep[c2[o.inside(x[c2])]] = False
         chunks.append(x[keep])
         got += int(keep.sum())
         for i, p in enumerate(furn):
@@ -254,9 +284,8 @@ def room_points(n: int = 20_000_000, n_furniture: int = 200, noise: float = 0.00
                 continue
             y = p.sample(rng, k)
             keep = (y[:, 2] >= 0.0)
-            for j, o in enumerate(furn):
-                if j != i:
-                    keep &= ~o.inside(y)
+            for j in np.nonzero(overlap[i])[0]:
+                keep &= ~furn[j].inside(y)
             chunks.append(y[keep])
             got += int(keep.sum())
     pts = np.concatenate(chunks)

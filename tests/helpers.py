@@ -24,35 +24,39 @@ def spec(points, dom, n_queries, sigma):
     return ShapeSpec(points, dom.dims, dom.lo, dom.hi, n_queries, sigma)
 
 
-def slot_flags_by_vertex(prob, shape_index, dom):
-    """Per vertex id of one shape: the slot flags the library exported (or -1 if no slot)."""
+def _cell_of_vertex(dom, vid):
+    V = np.asarray(dom.vdims, dtype=np.int64)
+    R = np.asarray(dom.dims, dtype=np.int64)
+    i = vid // (V[1] * V[2])
+    j = (vid // V[2]) % V[1]
+    k = vid % V[2]
+    ok = (i < R[0]) & (j < R[1]) & (k < R[2])
+    return ok, (i * R[1] + j) * R[2] + k
+
+
+def compare_band(prob, shape_index, dom, cf, vf):
+    """Bit-exact comparison of the exported band with the oracle's dense flags.
+
+    Compares sorted id sets: optimised and TV vertices, point cells, M1 and M2
+    cells (a cell is reported on the slot of its lowest corner).
+    """
     vid, flags = prob.layout()
     b, e = prob.slot_begin[shape_index], prob.slot_begin[shape_index + 1]
     vid, flags = vid[b:e], flags[b:e]
     have = vid >= 0
-    out = np.full(dom.n_vertices, -1, dtype=np.int16)
-    assert len(np.unique(vid[have])) == int(have.sum()), "a vertex appears in two slots"
-    out[vid[have]] = flags[have]
-    return out
-
-
-def compare_band(prob, shape_index, dom, cf, vf):
-    """Bit-exact comparison of the exported band with the oracle's dense flags."""
-    got = slot_flags_by_vertex(prob, shape_index, dom)
-    V = np.asarray(dom.vdims)
-    R = np.asarray(dom.dims)
-    # vertex sets: optimised (1) and TV (2)
-    in_slot = got >= 0
-    g = np.where(in_slot, got, 0).astype(np.uint8)
-    assert np.array_equal((g & 1) > 0, (vf & 1) > 0), "optimised vertex set differs"
-    assert np.array_equal((g & 2) > 0, (vf & 2) > 0), "TV vertex set differs"
-    # cell sets: bits 4 (M1), 8 (M2), 16 (point cells) on the cell's lowest corner
-    ijk = np.stack(np.meshgrid(np.arange(R[0]), np.arange(R[1]), np.arange(R[2]), indexing="ij"), -1).reshape(-1, 3)
-    lower = (ijk[:, 0] * V[1] + ijk[:, 1]) * V[2] + ijk[:, 2]
-    gc = np.where(got[lower] >= 0, got[lower], 0).astype(np.uint8)
-    assert np.array_equal((gc & 16) > 0, (cf & 1) > 0), "point-cell set differs"
-    assert np.array_equal((gc & 4) > 0, (cf & 2) > 0), "M1 band differs"
-    assert np.array_equal((gc & 8) > 0, (cf & 4) > 0), "M2 band differs"
+    vid, flags = vid[have], flags[have]
+    assert len(np.unique(vid)) == len(vid), "a vertex appears in two slots"
+    for bit, obit, what in ((1, 1, "optimised vertex"), (2, 2, "TV vertex")):
+        got = np.sort(vid[(flags & bit) > 0])
+        ref = np.nonzero(vf & obit)[0]
+        assert np.array_equal(got, ref), "%s set differs (%d vs %d)" % (what, len(got), len(ref))
+    for bit, obit, what in ((16, 1, "point cell"), (4, 2, "M1 cell"), (8, 4, "M2 cell")):
+        sel = (flags & bit) > 0
+        ok, cid = _cell_of_vertex(dom, vid[sel])
+        assert np.all(ok), "%s flag on a vertex with no cell" % what
+        got = np.sort(cid)
+        ref = np.nonzero(cf & obit)[0]
+        assert np.array_equal(got, ref), "%s set differs (%d vs %d)" % (what, len(got), len(ref))
 
 
 def loss_terms(prob):
@@ -70,4 +74,5 @@ def assert_terms_close(got, ref, rtol=1e-5):
 def assert_grad_close(got, ref, rtol=1e-5):
     gmax = np.abs(ref).max()
     err = np.abs(got - ref).max()
+    log("  gradient: max err %.3e / max |g| %.3e = %.2e" % (err, gmax, err / gmax))
     assert err <= rtol * gmax, "gradient: max err %.3e vs max |g| %.3e (rel %.2e)" % (err, gmax, err / gmax)
