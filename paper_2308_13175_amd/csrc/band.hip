@@ -235,18 +235,13 @@ __global__ void k_point_keys(const float* __restrict__ px, const float* __restri
 
 __global__ void k_gather_sorted(const float* __restrict__ px, const float* __restrict__ py,
                                 const float* __restrict__ pz, const uint32_t* __restrict__ keys,
-                                const int32_t* __restrict__ vals, Band B, int64_t n,
-                                float* __restrict__ spx, float* __restrict__ spy, float* __restrict__ spz,
-                                int32_t* __restrict__ sid)
+                                const int32_t* __restrict__ vals, Band B, int64_t n, float4* __restrict__ spts)
 {
     GRID_STRIDE(i, n)
     {
         int32_t g = vals[i];
         int32_t shape = B.bricks[keys[i] / kBrickVol].shape;
-        spx[i] = px[g];
-        spy[i] = py[g];
-        spz[i] = pz[g];
-        sid[i] = (int32_t)(g - B.shapes[shape].point_off);
+        spts[i] = make_float4(px[g], py[g], pz[g], __int_as_float((int32_t)(g - B.shapes[shape].point_off)));
     }
 }
 
@@ -457,8 +452,7 @@ gp_status gp_build_band_impl(gp_ctx ctx, const gp_shape* shapes, int32_t n_shape
         DevBuf<unsigned> counts;
         if (k_in.alloc(np) != hipSuccess || k_out.alloc(np) != hipSuccess || v_in.alloc(np) != hipSuccess ||
             counts.alloc(n_slots + 1) != hipSuccess || ctx->cell_start.alloc(n_slots + 1) != hipSuccess ||
-            ctx->spx.alloc(np) != hipSuccess || ctx->spy.alloc(np) != hipSuccess || ctx->spz.alloc(np) != hipSuccess ||
-            ctx->sid.alloc(np) != hipSuccess || ctx->ox.alloc(np) != hipSuccess || ctx->oy.alloc(np) != hipSuccess ||
+            ctx->spts.alloc(np) != hipSuccess || ctx->ox.alloc(np) != hipSuccess || ctx->oy.alloc(np) != hipSuccess ||
             ctx->oz.alloc(np) != hipSuccess)
             return gp_fail(ctx, GP_ERR_OOM, "out of device memory for the point buckets");
         GP_HIP(ctx, hipMemsetAsync(counts.p, 0, (n_slots + 1) * sizeof(unsigned), st));
@@ -498,8 +492,7 @@ gp_status gp_build_band_impl(gp_ctx ctx, const gp_shape* shapes, int32_t n_shape
         if (np > 0) {
             GP_HIP(ctx, hipcub::DeviceRadixSort::SortPairs(cub_tmp, need, k_in.p, k_out.p, v_in.p, v_out.p, (int)np, 0,
                                                           end_bit, st));
-            k_gather_sorted<<<blocks_for(np), kThreads, 0, st>>>(px, py, pz, k_out.p, v_out.p, B, np, ctx->spx.p,
-                                                                 ctx->spy.p, ctx->spz.p, ctx->sid.p);
+            k_gather_sorted<<<blocks_for(np), kThreads, 0, st>>>(px, py, pz, k_out.p, v_out.p, B, np, ctx->spts.p);
         }
         GP_HIP(ctx, hipGetLastError());
         GP_HIP(ctx, hipStreamSynchronize(st));

@@ -262,8 +262,7 @@ struct gp_ctx_s {
 
     // nearest-neighbour buckets: points sorted by cell slot
     DevBuf<int32_t> cell_start;   // [n_slots + 1]
-    DevBuf<float> spx, spy, spz;  // sorted coordinates
-    DevBuf<int32_t> sid;          // original index within the shape
+    DevBuf<float4> spts;          // sorted points: x, y, z, original index within the shape (bits)
     DevBuf<float> ox, oy, oz;     // points in their original order, at sorted_off + index
 
     // per-iteration scratch

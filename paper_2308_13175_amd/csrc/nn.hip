@@ -1,28 +1,37 @@
 // Nearest surface point NN(q) of every query (Eq. 4).
 //
-// The paper organises the points in a KD-tree.  On the GPU the points are
-// instead bucketed by grid cell (sorted by the slot of their cell, built once
-// in band.hip), and each query searches cells ring by ring around its own
-// cell.  A cell is opened only if its box can hold a point at least as close
-// as the best so far, and the search stops once every unopened cell is
-// provably farther.  Distances are compared exactly in double without fused
-// multiply-add, ties going to the lowest point index, so the result equals a
-// brute-force search bit for bit.
+// The paper organises the points in a KD-tree.  Here the points are bucketed
+// by grid cell (sorted by the slot of their cell, built once in band.hip); a
+// cell's points are contiguous, and so are the points of a run of cells along
+// z inside one brick.
 //
-// A block handles a tile of 1024 queries that the sampler drew from
-// neighbouring points.  Before searching, the block stages the bounding box
-// of its queries' cells (grown by one cell) in LDS: a per-cell offset table
-// and the points of those cells, copied cooperatively.  Ring searches then read
-// cells inside the box from LDS and only cells outside it from global memory,
-// so the result does not depend on the staging.
+// A block takes a tile of 1024 queries, sorts them by the Morton code of their
+// cell and cuts the sorted list into groups of at most 64 queries whose cells
+// span at most 8 cells per axis (one group per wave at a time).  The wave then scans that box grown by one cell, then the
+// shell of the box grown by two, three, ... cells, all lanes in lockstep.  A
+// shell is cut into z-runs of cells inside one brick (each run's points are
+// contiguous); runs that cannot hold a point closer than the current best of
+// any unresolved lane are skipped, the rest are gathered 64 at a time (one
+// per lane), their point ranges fetched in one round trip, and the
+// concatenated points streamed in chunks of 64: every lane loads one point
+// and readlane hands each point to all lanes.  Each lane keeps its smallest
+// and second-smallest float distance: when the second exceeds the first by
+// more than the float error bound, the float argmin is the exact argmin; when
+// in addition the best distance is below the query's gap to the scanned box,
+// no unscanned point can be as close and the query is resolved.  Near ties
+// (and queries still open after the last shell) run an exact ring search:
+// distances in double without fused multiply-add, ties to the lowest point
+// index, so every result equals a brute-force search bit for bit.
+#include <hipcub/hipcub.hpp>
+
 #include "gp_internal.h"
 
 namespace gp {
 namespace {
 
-constexpr int kNnExpand = 1;           // cells added on every side of the tile's query box
-constexpr int kNnMaxCells = 4096;      // staged cells
-constexpr int kNnMaxPoints = 4096;     // staged points
+constexpr int kNnShells = 8;      // box growth steps scanned in lockstep before the fallback
+constexpr int kNnGroupCap = 8;     // a group's query cells span at most this many cells per axis
+constexpr int kNnMaxGroups = kQueryTile;   // groups per tile (worst case one query each)
 
 struct Best {
     double d2;
@@ -61,52 +70,18 @@ __device__ inline float cell_gap(float du, int32_t d, float margin)
 
 struct Global {
     const int32_t* cell_start;
-    const float* spx;
-    const float* spy;
-    const float* spz;
-    const int32_t* sid;
+    const float4* pts;    // x, y, z, original index (bits)
 };
 
-struct Staged {
-    int32_t lo[3], dim[3];
-    bool ok;
-    const uint16_t* off;   // [ncell + 1] first staged point of each cell
-    const float4* pts;     // x, y, z, id (bit pattern)
-};
-
-// Global range of the points of cell (x, y, z): false if the cell holds none.
-__device__ inline bool cell_range(const Band& B, const ShapeDesc& s, const Global& G, int32_t x, int32_t y, int32_t z,
-                                  int32_t& b, int32_t& e)
+// Global range of the points of cells (x, y, za..zb) (one brick): empty if none.
+__device__ inline void run_range(const Band& B, const ShapeDesc& s, const Global& G, int32_t x, int32_t y,
+                                 int32_t za, int32_t zb, int32_t& b, int32_t& e)
 {
-    const int32_t br = brick_of(B, s, x >> 3, y >> 3, z >> 3);
-    if (br < 0) return false;
-    const int32_t local = local_index(x, y, z);
-    if (!mask_bit(B.m_base, br, local)) return false;
-    const int32_t slot = br * kBrickVol + local;
-    b = G.cell_start[slot];
-    e = G.cell_start[slot + 1];
-    return e > b;
-}
-
-__device__ inline void visit_cell(const Band& B, const ShapeDesc& s, const Global& G, const Staged& S, int32_t x,
-                                  int32_t y, int32_t z, float qx, float qy, float qz, Best& best)
-{
-    if (S.ok) {
-        const int32_t lx = x - S.lo[0], ly = y - S.lo[1], lz = z - S.lo[2];
-        if ((uint32_t)lx < (uint32_t)S.dim[0] && (uint32_t)ly < (uint32_t)S.dim[1] &&
-            (uint32_t)lz < (uint32_t)S.dim[2]) {
-            const int32_t li = (lx * S.dim[1] + ly) * S.dim[2] + lz;
-            const int32_t b = S.off[li], e = S.off[li + 1];
-            for (int32_t i = b; i < e; ++i) {
-                const float4 p = S.pts[i];
-                consider(exact_d2(qx, qy, qz, p.x, p.y, p.z), __float_as_int(p.w), best);
-            }
-            return;
-        }
-    }
-    int32_t b, e;
-    if (!cell_range(B, s, G, x, y, z, b, e)) return;
-    for (int32_t i = b; i < e; ++i) consider(exact_d2(qx, qy, qz, G.spx[i], G.spy[i], G.spz[i]), G.sid[i], best);
+    b = e = 0;
+    const int32_t br = brick_of(B, s, x >> 3, y >> 3, za >> 3);
+    if (br < 0) return;
+    b = G.cell_start[br * kBrickVol + local_index(x, y, za)];
+    e = G.cell_start[br * kBrickVol + local_index(x, y, zb) + 1];
 }
 
 // Query's clamped cell and its local coordinate within that cell.
@@ -122,8 +97,10 @@ __device__ inline void query_cell(const ShapeDesc& s, float x, float y, float z,
     }
 }
 
-__device__ inline int32_t search(const Band& B, const ShapeDesc& s, const Global& G, const Staged& S, float x,
-                                 float y, float z)
+// Exact ring search: cells in rings of growing Chebyshev radius around the
+// query's cell, each opened only if its box can hold a point at least as close
+// as the best so far; stops once every unopened cell is provably farther.
+__device__ inline int32_t search(const Band& B, const ShapeDesc& s, const Global& G, float x, float y, float z)
 {
     if (s.point_cnt <= 0) return -1;
     int32_t c0[3];
@@ -158,7 +135,12 @@ __device__ inline int32_t search(const Band& B, const ShapeDesc& s, const Global
                     const float gz = cell_gap(du[2], cz - c0[2], margin[2]);
                     const float lb = fmaf(gz * gz, h2[2], lbxy) * (1.f - 1e-6f);
                     if ((double)lb > best.d2) continue;
-                    visit_cell(B, s, G, S, cx, cy, cz, x, y, z, best);
+                    int32_t b, e;
+                    run_range(B, s, G, cx, cy, cz, cz, b, e);
+                    for (int32_t i = b; i < e; ++i) {
+                        const float4 p = G.pts[i];
+                        consider(exact_d2(x, y, z, p.x, p.y, p.z), __float_as_int(p.w), best);
+                    }
                 }
             }
         }
@@ -184,109 +166,310 @@ __device__ inline int32_t search(const Band& B, const ShapeDesc& s, const Global
     return best.id;
 }
 
-// Exclusive prefix sum of one int per thread over the block (blockDim = 256).
-__device__ inline int32_t block_exclusive_scan(int32_t v, int32_t* scratch /* [4] */, int32_t& total)
+// Wave-wide minimum of v[0..2] and maximum of v[3..5].
+__device__ inline void wave_minmax6(int32_t v[6])
 {
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int i = 0; i < 6; ++i)
+        for (int o = 32; o > 0; o >>= 1) {
+            int32_t w = __shfl_xor(v[i], o, 64);
+            v[i] = i < 3 ? min(v[i], w) : max(v[i], w);
+        }
+}
+
+__device__ inline uint32_t spread3(uint32_t v)
+{
+    v &= 0x3ffu;
+    v = (v | (v << 16)) & 0x030000ffu;
+    v = (v | (v << 8)) & 0x0300f00fu;
+    v = (v | (v << 4)) & 0x030c30c3u;
+    v = (v | (v << 2)) & 0x09249249u;
+    return v;
+}
+
+__device__ inline float lane_float(float v, int32_t lane)
+{
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
+}
+
+// Per-lane scan state.
+struct Scan {
+    float x, y, z;
+    int32_t c0[3];
+    float du[3];
+    float best1, best2;
+    int32_t id1;
+    bool open;   // live and not yet resolved
+};
+
+// Runs of cells gathered for one wave: run i lives in the registers of lane
+// i % 64 until the batch of 64 is scanned.
+struct Runs {
+    int32_t x, y, z0, z1;   // this lane's run
+    int32_t n;              // runs in the batch (wave-uniform)
+};
+
+__device__ inline int32_t wave_exclusive_sum(int32_t v, int32_t& total)
+{
+    const int lane = threadIdx.x & 63;
     int32_t incl = v;
     for (int o = 1; o < 64; o <<= 1) {
-        int32_t w = __shfl_up(incl, o, 64);
+        const int32_t w = __shfl_up(incl, o, 64);
         if (lane >= o) incl += w;
     }
-    if (lane == 63) scratch[wave] = incl;
-    __syncthreads();
-    int32_t base = 0;
-    total = 0;
-    const int nw = blockDim.x >> 6;
-    for (int w = 0; w < nw; ++w) {
-        if (w < wave) base += scratch[w];
-        total += scratch[w];
-    }
-    __syncthreads();
-    return base + incl - v;
+    total = __shfl(incl, 63, 64);
+    return incl - v;
 }
+
+// Evaluate the staged chunk buf[0..cnt) (an LDS broadcast per point) for every lane.
+__device__ inline void eval_chunk(const float4* __restrict__ buf, int32_t cnt, Scan& q)
+{
+    float b1 = q.best1, b2 = q.best2;
+    int32_t id = q.id1;
+#pragma unroll 4
+    for (int32_t t = 0; t < cnt; ++t) {
+        const float4 p = buf[t];
+        const float dx = q.x - p.x, dy = q.y - p.y, dz = q.z - p.z;
+        const float d2f = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+        const bool lt = d2f < b1;
+        b2 = lt ? b1 : fminf(b2, d2f);
+        id = lt ? __float_as_int(p.w) : id;
+        b1 = lt ? d2f : b1;
+    }
+    q.best1 = b1;
+    q.best2 = b2;
+    q.id1 = id;
+}
+
+// Scan the points of the gathered runs for every lane, then empty the batch.
+// buf: this wave's LDS staging area of 64 points.
+__device__ inline void flush_runs(const Band& B, const ShapeDesc& s, const Global& G, Runs& R, Scan& q,
+                                  float4* __restrict__ buf)
+{
+    const int lane = threadIdx.x & 63;
+    int32_t pb = 0, pe = 0;
+    if (lane < R.n) run_range(B, s, G, R.x, R.y, R.z0, R.z1, pb, pe);
+    int32_t total;
+    const int32_t off = wave_exclusive_sum(pe - pb, total);
+    total = __builtin_amdgcn_readfirstlane(total);
+    // stream position p -> the last run whose offset is <= p
+    auto point_at = [&](int32_t p) -> float4 {
+        int32_t j = 0;
+        for (int step = 32; step > 0; step >>= 1) {
+            const int32_t c = j + step;
+            const int32_t o = __shfl(off, c < R.n ? c : R.n - 1, 64);
+            if (c < R.n && o <= p) j = c;
+        }
+        const int32_t idx = __shfl(pb, j, 64) + (p - __shfl(off, j, 64));
+        const float4 v = G.pts[p < total ? idx : 0];   // a scan only happens for a shape with points
+        return p < total ? v : make_float4(0.f, 0.f, 0.f, 0.f);
+    };
+    float4 nxt = point_at(lane);
+    for (int32_t c = 0; c < total; c += 64) {
+        buf[lane] = nxt;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        nxt = point_at(c + 64 + lane);    // the next chunk's loads fly during the evaluation
+        eval_chunk(buf, min(64, total - c), q);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+    }
+    R.n = 0;
+}
+
+__device__ inline void add_run(const Band& B, const ShapeDesc& s, const Global& G, Runs& R, Scan& q, int32_t x,
+                               int32_t y, int32_t z0, int32_t z1, float4* __restrict__ buf)
+{
+    if ((threadIdx.x & 63) == (R.n & 63)) {
+        R.x = x;
+        R.y = y;
+        R.z0 = z0;
+        R.z1 = z1;
+    }
+    if (++R.n == 64) flush_runs(B, s, G, R, q, buf);
+}
+
+// Cut the z range [za, zb] of row (x, y) into runs inside one brick and gather
+// those some open lane may need.
+__device__ inline void add_row(const Band& B, const ShapeDesc& s, const Global& G, Runs& R, Scan& q, int32_t x,
+                               int32_t y, int32_t za, int32_t zb, float lbxy, float h2z, float4* __restrict__ buf)
+{
+    for (int32_t z0 = za; z0 <= zb;) {
+        const int32_t z1 = min(zb, z0 | 7);
+        const float gz = fmaxf(fmaxf((float)(z0 - q.c0[2]) - q.du[2], q.du[2] - (float)(z1 + 1 - q.c0[2])) - 1e-3f, 0.f);
+        const bool need = q.open && fmaf(gz * gz, h2z, lbxy) * (1.f - 1e-5f) <= q.best1;
+        if (__any(need)) add_run(B, s, G, R, q, x, y, z0, z1, buf);
+        z0 = z1 + 1;
+    }
+}
+
+using BlockSort = hipcub::BlockRadixSort<uint32_t, kQueryBlock, kQueriesPerThread, int32_t>;
 
 __global__ __launch_bounds__(kQueryBlock) void k_nn(Band B, Global G, const float* __restrict__ qx,
                                                     const float* __restrict__ qy, const float* __restrict__ qz,
                                                     int32_t* __restrict__ nn)
 {
-    __shared__ uint16_t s_off[kNnMaxCells + 1];
-    __shared__ float4 s_pts[kNnMaxPoints];
+    __shared__ typename BlockSort::TempStorage sort_tmp;
+    __shared__ int16_t s_order[kQueryTile];
     __shared__ int32_t s_red[4 * 6];
-    __shared__ int32_t s_flag;
+    __shared__ float4 s_buf[kQueryBlock];
+    __shared__ int16_t s_group[kNnMaxGroups + 1];
+    __shared__ int32_t s_ngroups;
 
     const int64_t tile = blockIdx.x;
     const int32_t shape = B.tile_shape[tile];
     const ShapeDesc& s = B.shapes[shape];
     const int64_t q0 = B.tile_start[tile];
-    const int64_t qe = min(q0 + (int64_t)kQueryTile, s.query_off + s.query_cnt);
+    float4* wbuf = s_buf + (threadIdx.x & ~63);
+    const int32_t nq = (int32_t)min((int64_t)kQueryTile, s.query_off + s.query_cnt - q0);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 
-    // ---- bounding box of the tile's query cells ---------------------------
+    // ---- sort the tile's queries by the Morton code of their cell ----------
+    uint32_t key[kQueriesPerThread];
+    int32_t val[kQueriesPerThread];
+    int32_t cells[kQueriesPerThread][3];
     int32_t box[6] = {0x7fffffff, 0x7fffffff, 0x7fffffff, -1, -1, -1};
-    for (int64_t k = q0 + threadIdx.x; k < qe; k += blockDim.x) {
-        int32_t c0[3];
+#pragma unroll
+    for (int j = 0; j < kQueriesPerThread; ++j) {
+        const int32_t li = threadIdx.x * kQueriesPerThread + j;
+        val[j] = li;
         float du[3];
-        query_cell(s, qx[k], qy[k], qz[k], c0, du);
-        for (int a = 0; a < 3; ++a) {
-            box[a] = min(box[a], c0[a]);
-            box[3 + a] = max(box[3 + a], c0[a]);
+        cells[j][0] = cells[j][1] = cells[j][2] = 0;
+        if (li < nq) {
+            query_cell(s, qx[q0 + li], qy[q0 + li], qz[q0 + li], cells[j], du);
+            for (int a = 0; a < 3; ++a) {
+                box[a] = min(box[a], cells[j][a]);
+                box[3 + a] = max(box[3 + a], cells[j][a]);
+            }
         }
     }
     block_minmax6(box, s_red);
-    Staged S;
-    int64_t ncell = 1;
-    for (int a = 0; a < 3; ++a) {
-        S.lo[a] = max(box[a] - kNnExpand, 0);
-        S.dim[a] = min(box[3 + a] + kNnExpand, s.R[a] - 1) - S.lo[a] + 1;
-        ncell *= S.dim[a];
+#pragma unroll
+    for (int j = 0; j < kQueriesPerThread; ++j) {
+        const int32_t li = threadIdx.x * kQueriesPerThread + j;
+        key[j] = 0xffffffffu;
+        if (li < nq)
+            key[j] = spread3((uint32_t)min(cells[j][0] - box[0], 1023)) |
+                     (spread3((uint32_t)min(cells[j][1] - box[1], 1023)) << 1) |
+                     (spread3((uint32_t)min(cells[j][2] - box[2], 1023)) << 2);
     }
-    S.off = s_off;
-    S.pts = s_pts;
-    S.ok = s.point_cnt > 0 && ncell <= kNnMaxCells;
+    BlockSort(sort_tmp).Sort(key, val);
+#pragma unroll
+    for (int j = 0; j < kQueriesPerThread; ++j) s_order[threadIdx.x * kQueriesPerThread + j] = (int16_t)val[j];
+    __syncthreads();
+    // greedy groups along the sorted order: at most 64 queries, cell span <= kNnGroupCap per axis
+    if (threadIdx.x == 0) {
+        int32_t ng = 0, cnt = 0;
+        int32_t glo[3] = {0, 0, 0}, ghi[3] = {0, 0, 0};
+        for (int32_t pos = 0; pos < nq; ++pos) {
+            const int32_t li = s_order[pos];
+            int32_t c[3];
+            float du[3];
+            query_cell(s, qx[q0 + li], qy[q0 + li], qz[q0 + li], c, du);
+            bool fits = cnt > 0 && cnt < 64;
+            for (int a = 0; a < 3 && fits; ++a)
+                fits = max(ghi[a], c[a]) - min(glo[a], c[a]) < kNnGroupCap;
+            if (!fits) {
+                s_group[ng++] = (int16_t)pos;
+                cnt = 0;
+                for (int a = 0; a < 3; ++a) glo[a] = ghi[a] = c[a];
+            }
+            for (int a = 0; a < 3; ++a) {
+                glo[a] = min(glo[a], c[a]);
+                ghi[a] = max(ghi[a], c[a]);
+            }
+            ++cnt;
+        }
+        s_group[ng] = (int16_t)nq;
+        s_ngroups = ng;
+    }
+    __syncthreads();
+    const int32_t ngroups = s_ngroups;
 
-    // ---- stage the box: counts, prefix sum, copy ---------------------------
-    if (S.ok) {
-        const int32_t nc = (int32_t)ncell;
-        const int32_t chunk = (nc + blockDim.x - 1) / blockDim.x;
-        const int32_t c_begin = min((int32_t)threadIdx.x * chunk, nc), c_end = min(c_begin + chunk, nc);
-        if (threadIdx.x == 0) s_flag = 0;
-        __syncthreads();
-        int32_t mine = 0;
-        for (int32_t i = c_begin; i < c_end; ++i) {
-            const int32_t lz = i % S.dim[2], ly = (i / S.dim[2]) % S.dim[1], lx = i / (S.dim[2] * S.dim[1]);
-            int32_t b = 0, e = 0;
-            cell_range(B, s, G, S.lo[0] + lx, S.lo[1] + ly, S.lo[2] + lz, b, e);
-            const int32_t c = e - b;
-            if (c > kNnMaxPoints) s_flag = 1;
-            s_off[i] = (uint16_t)min(c, kNnMaxPoints);
-            mine += c;
-        }
-        int32_t total = 0;
-        int32_t base = block_exclusive_scan(mine, s_red, total);
-        if (total > kNnMaxPoints) s_flag = 1;
-        for (int32_t i = c_begin; i < c_end; ++i) {
-            const int32_t c = s_off[i];
-            s_off[i] = (uint16_t)min(base, kNnMaxPoints);
-            base += c;
-        }
-        if (threadIdx.x == blockDim.x - 1) s_off[nc] = (uint16_t)min(total, kNnMaxPoints);
-        __syncthreads();
-        S.ok = s_flag == 0;
-        if (S.ok) {
-            for (int32_t i = threadIdx.x; i < nc; i += blockDim.x) {
-                const int32_t lz = i % S.dim[2], ly = (i / S.dim[2]) % S.dim[1], lx = i / (S.dim[2] * S.dim[1]);
-                int32_t b = 0, e = 0;
-                if (!cell_range(B, s, G, S.lo[0] + lx, S.lo[1] + ly, S.lo[2] + lz, b, e)) continue;
-                int32_t d = s_off[i];
-                for (int32_t j = b; j < e; ++j, ++d)
-                    s_pts[d] = make_float4(G.spx[j], G.spy[j], G.spz[j], __int_as_float(G.sid[j]));
+    const float h2[3] = {s.h[0] * s.h[0], s.h[1] * s.h[1], s.h[2] * s.h[2]};
+    // wave w takes groups w, w + 4, ...
+    for (int32_t gi = wave; gi < ngroups; gi += kQueryBlock / 64) {
+        const int32_t pos = s_group[gi] + lane;
+        const bool live = pos < s_group[gi + 1];
+        const int32_t li = live ? s_order[pos] : 0;
+        const int64_t k = q0 + li;
+        Scan q;
+        q.x = live ? qx[k] : 0.f;
+        q.y = live ? qy[k] : 0.f;
+        q.z = live ? qz[k] : 0.f;
+        query_cell(s, q.x, q.y, q.z, q.c0, q.du);
+        q.best1 = q.best2 = __builtin_inff();
+        q.id1 = -1;
+        q.open = live && s.point_cnt > 0;
+        int32_t wb[6] = {0x7fffffff, 0x7fffffff, 0x7fffffff, -1, -1, -1};
+        if (live)
+            for (int a = 0; a < 3; ++a) {
+                wb[a] = q.c0[a];
+                wb[3 + a] = q.c0[a];
+            }
+        wave_minmax6(wb);
+        int32_t plo[3] = {0, 0, 0}, phi[3] = {-1, -1, -1};   // box scanned so far (empty)
+        Runs R;
+        R.n = 0;
+        R.x = R.y = R.z0 = R.z1 = 0;
+        for (int e = 1; e <= kNnShells && __any(q.open); ++e) {
+            int32_t lo[3], hi[3];
+            for (int a = 0; a < 3; ++a) {
+                lo[a] = max(wb[a] - e, 0);
+                hi[a] = min(wb[3 + a] + e, s.R[a] - 1);
+            }
+            // rows an open lane can still need: all of the box until it has a
+            // candidate, then only those within its best distance of its cell
+            // (every other row is provably farther, so the box gap stays valid)
+            int32_t reach[6] = {0x7fffffff, 0x7fffffff, 0x7fffffff, -1, -1, -1};
+            if (q.open) {
+                const bool have = q.best1 < __builtin_inff();
+                const float r = sqrtf(q.best1);
+                for (int a = 0; a < 2; ++a) {
+                    const int32_t m = have ? (int32_t)ceilf(r / s.h[a]) + 1 : 0;
+                    reach[a] = have ? q.c0[a] - m : lo[a];
+                    reach[3 + a] = have ? q.c0[a] + m : hi[a];
+                }
+            }
+            wave_minmax6(reach);
+            const int32_t x_lo = max(lo[0], reach[0]), x_hi = min(hi[0], reach[3]);
+            const int32_t y_lo = max(lo[1], reach[1]), y_hi = min(hi[1], reach[4]);
+            for (int32_t xx = x_lo; xx <= x_hi; ++xx) {
+                const float gx = cell_gap(q.du[0], xx - q.c0[0], 1e-3f);
+                for (int32_t yy = y_lo; yy <= y_hi; ++yy) {
+                    const float gy = cell_gap(q.du[1], yy - q.c0[1], 1e-3f);
+                    const float lbxy = fmaf(gx * gx, h2[0], gy * gy * h2[1]);
+                    const bool need = q.open && lbxy * (1.f - 1e-5f) <= q.best1;
+                    if (!__any(need)) continue;
+                    const bool inner = xx >= plo[0] && xx <= phi[0] && yy >= plo[1] && yy <= phi[1];
+                    if (!inner) {
+                        add_row(B, s, G, R, q, xx, yy, lo[2], hi[2], lbxy, h2[2], wbuf);
+                    } else {
+                        if (lo[2] < plo[2]) add_row(B, s, G, R, q, xx, yy, lo[2], plo[2] - 1, lbxy, h2[2], wbuf);
+                        if (hi[2] > phi[2]) add_row(B, s, G, R, q, xx, yy, phi[2] + 1, hi[2], lbxy, h2[2], wbuf);
+                    }
+                }
+            }
+            if (R.n > 0) flush_runs(B, s, G, R, q, wbuf);
+            // resolved: a unique float minimum that no unscanned point can match
+            if (q.open && q.id1 >= 0 && q.best2 > q.best1 * (1.f + 1e-6f)) {
+                float gap = __builtin_inff();
+                for (int a = 0; a < 3; ++a) {
+                    if (lo[a] > 0) gap = fminf(gap, fmaxf((float)(q.c0[a] - lo[a]) + q.du[a] - 1e-3f, 0.f) * s.h[a]);
+                    if (hi[a] < s.R[a] - 1)
+                        gap = fminf(gap, fmaxf((float)(hi[a] + 1 - q.c0[a]) - q.du[a] - 1e-3f, 0.f) * s.h[a]);
+                }
+                if (q.best1 * (1.f + 1e-6f) < gap * gap * (1.f - 1e-5f)) q.open = false;
+            }
+            for (int a = 0; a < 3; ++a) {
+                plo[a] = lo[a];
+                phi[a] = hi[a];
             }
         }
-        __syncthreads();
+        if (!live) continue;
+        nn[k] = (s.point_cnt > 0 && !q.open) ? q.id1 : search(B, s, G, q.x, q.y, q.z);
     }
-
-    // ---- exact ring search per query -----------------------------------------
-    for (int64_t k = q0 + threadIdx.x; k < qe; k += blockDim.x) nn[k] = search(B, s, G, S, qx[k], qy[k], qz[k]);
 }
 
 }  // namespace
@@ -297,7 +480,7 @@ using namespace gp;
 gp_status gp_nn_impl(gp_ctx ctx, const float* qx, const float* qy, const float* qz, int32_t* nn)
 {
     if (ctx->n_tiles == 0) return GP_OK;
-    Global G{ctx->cell_start.p, ctx->spx.p, ctx->spy.p, ctx->spz.p, ctx->sid.p};
+    Global G{ctx->cell_start.p, ctx->spts.p};
     GP_TIMED(ctx, "k_nn");
     k_nn<<<(unsigned)ctx->n_tiles, kQueryBlock, 0, ctx->stream>>>(ctx->band(), G, qx, qy, qz, nn);
     GP_HIP(ctx, hipGetLastError());

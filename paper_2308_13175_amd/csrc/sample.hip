@@ -40,10 +40,7 @@ __device__ inline float unit_open(uint32_t x)
     return ((float)(x >> 8) + 0.5f) * 5.9604644775390625e-8f;
 }
 
-__global__ __launch_bounds__(kQueryBlock) void k_sample(Band B, const float* __restrict__ spx,
-                                                        const float* __restrict__ spy,
-                                                        const float* __restrict__ spz,
-                                                        const int32_t* __restrict__ sid,
+__global__ __launch_bounds__(kQueryBlock) void k_sample(Band B, const float4* __restrict__ spts,
                                                         const float* __restrict__ sigma, float sigma_const,
                                                         uint32_t key0, uint32_t key1, int32_t iteration_arg,
                                                         const int32_t* __restrict__ iter_counter,
@@ -72,7 +69,8 @@ __global__ __launch_bounds__(kQueryBlock) void k_sample(Band B, const float* __r
         int64_t j = (kk * J) / Q + rot;
         if (j >= J) j -= J;
         const int64_t p = s.sorted_off + j;
-        const int32_t orig = sid[p];
+        const float4 sp = spts[p];
+        const int32_t orig = __float_as_int(sp.w);
         const float sg = sigma ? sigma[s.point_off + orig] : sigma_const;
         const U4 r = philox4x32_10((uint32_t)kk, (uint32_t)((uint64_t)kk >> 32), iteration, (uint32_t)shape, key0, key1);
         const float u0 = unit_open(r.x[0]), u1 = unit_open(r.x[1]);
@@ -82,9 +80,9 @@ __global__ __launch_bounds__(kQueryBlock) void k_sample(Band B, const float* __r
         float s1, c1, s3, c3;
         sincospif(2.f * u1, &s1, &c1);
         sincospif(2.f * u3, &s3, &c3);
-        qx[k] = fmaf(sg, r0 * c1, spx[p]);
-        qy[k] = fmaf(sg, r0 * s1, spy[p]);
-        qz[k] = fmaf(sg, r1 * c3, spz[p]);
+        qx[k] = fmaf(sg, r0 * c1, sp.x);
+        qy[k] = fmaf(sg, r0 * s1, sp.y);
+        qz[k] = fmaf(sg, r1 * c3, sp.z);
         if (src) src[k] = orig;
     }
 }
@@ -100,7 +98,7 @@ gp_status gp_sample_impl(gp_ctx ctx, uint64_t seed, int32_t iteration, const flo
     if (ctx->n_tiles == 0) return GP_OK;
     GP_TIMED(ctx, "k_sample");
     k_sample<<<(unsigned)ctx->n_tiles, kQueryBlock, 0, ctx->stream>>>(
-        ctx->band(), ctx->spx.p, ctx->spy.p, ctx->spz.p, ctx->sid.p, sigma, sigma_const, (uint32_t)seed,
+        ctx->band(), ctx->spts.p, sigma, sigma_const, (uint32_t)seed,
         (uint32_t)(seed >> 32), iteration, ctx->iter.p, qx, qy, qz, src);
     GP_HIP(ctx, hipGetLastError());
     return GP_OK;

@@ -162,7 +162,7 @@ def test_autograd_wrapper_matches_backward():
     direct = torch.zeros_like(prob.field)
     prob.backward(field.detach(), direct, torch.full((1,), 2.5, dtype=torch.float64, device="cuda"))
     assert float((field.grad - direct).abs().max()) <= 1e-6 * float(direct.abs().max())
-    assert abs(float(loss[0]) - float(prob.loss[0, 0])) <= 1e-12 * abs(float(loss[0]))
+    assert abs(float(loss[0].detach()) - float(prob.loss[0, 0])) <= 1e-12 * abs(float(loss[0].detach()))
     prob.close()
 
 
@@ -174,9 +174,12 @@ def test_graph_replay_equals_eager_iterations():
     from paper_2308_13175_amd.problem import GraphedIteration
 
     log("case: graph replay")
+    from paper_2308_13175_amd.problem import AdamConfig
+
     dom = synth.cube_domain(48)
     pts = synth.sphere_points(5000, 0.5, seed=2)
-    mk = lambda: make_problem([spec(pts, dom, 20000, 0.03)])
+    lr0 = 0.1 * dom.h[0]
+    mk = lambda: make_problem([spec(pts, dom, 20000, 0.03)], adam=AdamConfig(lr0=lr0))
     a, b = mk(), mk()
     for p in (a, b):
         p.init_sphere(radii=[0.3])
@@ -187,10 +190,12 @@ def test_graph_replay_equals_eager_iterations():
         g.replay()
         torch.cuda.synchronize()
         junk = torch.randn(1000, device="cuda").sum()      # unrelated eager work between replays
+        # same iteration number on both sides: identical queries
+        assert np.array_equal(a.qx.cpu().numpy(), b.qx.cpu().numpy()), it
         la, lb = a.loss.cpu().numpy(), b.loss.cpu().numpy()
         assert np.max(np.abs(la - lb) / np.maximum(np.abs(la), 1e-30)) <= 1e-5, (it, la, lb)
+        # fields agree up to the float atomics' summation order, seen through Adam
         fa, fb = a.field.cpu().numpy(), b.field.cpu().numpy()
-        assert np.max(np.abs(fa - fb)) <= 1e-5, it
-        assert np.array_equal(a.qx.cpu().numpy(), b.qx.cpu().numpy())
+        assert np.max(np.abs(fa - fb)) <= 1e-3 * lr0, (it, np.max(np.abs(fa - fb)))
     a.close()
     b.close()
