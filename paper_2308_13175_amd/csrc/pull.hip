@@ -148,25 +148,66 @@ __global__ __launch_bounds__(kQueryBlock) void k_forward_query(Band B, const flo
         for (int i = 0; i < 4; ++i) q_part[tile * 4 + i] = v[i];
 }
 
-constexpr int kAccExpand = 2;        // vertices added around the tile's cell box for the s-side corners
-constexpr int kAccMax = 8192;        // LDS accumulators per block
+constexpr int kCacheBricks = 32;   // LDS brick accumulators per block (32 x 2 KB)
+constexpr int kCacheTable = 64;    // open-addressing table: global brick -> LDS brick
 
-// Vertex box of a tile: accumulate there in LDS, flush once per vertex.
-struct AccBox {
-    int32_t lo[3], dim[3];
-    bool ok;
-};
-
-__device__ inline void scatter_side(const Side& sd, const float cv[8], const AccBox& A, float* __restrict__ acc,
-                                    float* __restrict__ G, float scale)
+// The bricks a tile's contributions land in are few (the queries of a tile
+// come from neighbouring points): they are accumulated in LDS copies of those
+// bricks and flushed once, brick by brick, so that the lanes of a wave add to
+// consecutive addresses (combined per cache line by the memory side).
+__device__ inline int32_t table_home(int32_t br)
 {
+    return (int32_t)(((uint32_t)br * 2654435761u) >> 26);
+}
+
+__device__ inline void cache_insert(int32_t* keys, int32_t br)
+{
+    int32_t h = table_home(br);
+    for (int p = 0; p < kCacheTable; ++p) {
+        const int32_t old = atomicCAS(&keys[h], -1, br);
+        if (old == -1 || old == br) return;
+        h = (h + 1) & (kCacheTable - 1);
+    }
+}
+
+__device__ inline int32_t cache_find(const int32_t* keys, const int32_t* idx, int32_t br)
+{
+    int32_t h = table_home(br);
+    for (int p = 0; p < kCacheTable; ++p) {
+        const int32_t k = keys[h];
+        if (k == br) return idx[h];
+        if (k == -1) return -1;
+        h = (h + 1) & (kCacheTable - 1);
+    }
+    return -1;
+}
+
+// Bricks holding the corners of cell c.
+__device__ inline void insert_cell_bricks(const Band& B, const ShapeDesc& s, const int32_t c[3], int32_t* keys)
+{
+    const int32_t bx0 = c[0] >> 3, by0 = c[1] >> 3, bz0 = c[2] >> 3;
+    const int32_t bx1 = (c[0] + 1) >> 3, by1 = (c[1] + 1) >> 3, bz1 = (c[2] + 1) >> 3;
+    for (int32_t bx = bx0; bx <= bx1; ++bx)
+        for (int32_t by = by0; by <= by1; ++by)
+            for (int32_t bz = bz0; bz <= bz1; ++bz) {
+                const int32_t br = brick_of(B, s, bx, by, bz);
+                if (br >= 0) cache_insert(keys, br);
+            }
+}
+
+__device__ inline void scatter_side(const Side& sd, const float cv[8], const int32_t* keys, const int32_t* idx,
+                                    float* __restrict__ acc, float* __restrict__ G, float scale)
+{
+    int32_t last_br = -1, last_li = -1;
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
-        const int32_t x = sd.c[0] + (i >> 2) - A.lo[0], y = sd.c[1] + ((i >> 1) & 1) - A.lo[1],
-                      z = sd.c[2] + (i & 1) - A.lo[2];
-        if (A.ok && (uint32_t)x < (uint32_t)A.dim[0] && (uint32_t)y < (uint32_t)A.dim[1] &&
-            (uint32_t)z < (uint32_t)A.dim[2])
-            atomicAdd(&acc[(x * A.dim[1] + y) * A.dim[2] + z], cv[i]);
+        const int32_t br = sd.slot[i] >> 9, local = sd.slot[i] & (kBrickVol - 1);
+        if (br != last_br) {
+            last_br = br;
+            last_li = cache_find(keys, idx, br);
+        }
+        if (last_li >= 0)
+            atomicAdd(&acc[last_li * kBrickVol + local], cv[i]);
         else
             atomicAdd(&G[sd.slot[i]], scale * cv[i]);
     }
@@ -184,8 +225,9 @@ __global__ __launch_bounds__(kQueryBlock) void k_backward_query(Band B, const fl
                                                                 const double* __restrict__ inv_qv,
                                                                 float* __restrict__ G, int32_t* flag)
 {
-    __shared__ float s_acc[kAccMax];
-    __shared__ int32_t s_red[4 * 6];
+    __shared__ float s_acc[kCacheBricks * kBrickVol];
+    __shared__ int32_t s_keys[kCacheTable], s_idx[kCacheTable], s_brick[kCacheBricks];
+    __shared__ int32_t s_used;
     const int64_t tile = blockIdx.x;
     const int32_t shape = B.tile_shape[tile];
     const ShapeDesc& s = B.shapes[shape];
@@ -193,29 +235,36 @@ __global__ __launch_bounds__(kQueryBlock) void k_backward_query(Band B, const fl
     const int64_t qe = min(q0 + (int64_t)kQueryTile, s.query_off + s.query_cnt);
     const float scale = (float)(dloss[shape] * inv_qv[shape]);
 
-    // vertex box around the cells of the tile's queries
-    int32_t box[6] = {0x7fffffff, 0x7fffffff, 0x7fffffff, -1, -1, -1};
+    // pass 1: the bricks the tile's valid queries and their surface points touch
+    if (threadIdx.x < kCacheTable) s_keys[threadIdx.x] = -1;
+    __syncthreads();
     for (int64_t k = q0 + threadIdx.x; k < qe; k += blockDim.x) {
         const Loc L = locate(s, qx[k], qy[k], qz[k]);
         if (!L.inside) continue;
-        for (int a = 0; a < 3; ++a) {
-            box[a] = min(box[a], L.c[a]);
-            box[3 + a] = max(box[3 + a], L.c[a]);
-        }
+        const int32_t br = brick_of(B, s, L.c[0] >> 3, L.c[1] >> 3, L.c[2] >> 3);
+        if (br < 0 || !mask_bit(B.m_a1, br, local_index(L.c[0], L.c[1], L.c[2]))) continue;
+        insert_cell_bricks(B, s, L.c, s_keys);
+        const int32_t j = nn[k];
+        if (j < 0 || j >= s.point_cnt) continue;
+        const int64_t g = s.sorted_off + j;
+        const Loc Ls = locate(s, px[g], py[g], pz[g]);
+        insert_cell_bricks(B, s, Ls.c, s_keys);
     }
-    block_minmax6(box, s_red);
-    AccBox A;
-    int64_t nv = 1;
-    for (int a = 0; a < 3; ++a) {
-        A.lo[a] = max(box[a] - kAccExpand, 0);
-        A.dim[a] = max(min(box[3 + a] + 1 + kAccExpand, s.R[a]) - A.lo[a] + 1, 0);
-        nv *= A.dim[a];
+    __syncthreads();
+    // LDS brick numbers in table order (the first wave holds the 64 entries)
+    if (threadIdx.x < kCacheTable) {
+        const bool used = s_keys[threadIdx.x] != -1;
+        const uint64_t m = __ballot(used);
+        const int32_t before = __popcll(m & ((1ull << threadIdx.x) - 1ull));
+        const int32_t li = used && before < kCacheBricks ? before : -1;
+        s_idx[threadIdx.x] = li;
+        if (li >= 0) s_brick[li] = s_keys[threadIdx.x];
+        if (threadIdx.x == 0) s_used = min(__popcll(m), kCacheBricks);
     }
-    A.ok = box[3] >= 0 && nv <= kAccMax;
-    if (A.ok) {
-        for (int32_t i = threadIdx.x; i < (int32_t)nv; i += blockDim.x) s_acc[i] = 0.f;
-        __syncthreads();
-    }
+    __syncthreads();
+    const int32_t used = s_used;
+    for (int32_t i = threadIdx.x; i < used * kBrickVol; i += blockDim.x) s_acc[i] = 0.f;
+    __syncthreads();
 
     for (int64_t k = q0 + threadIdx.x; k < qe; k += blockDim.x) {
         QueryState st;
@@ -251,21 +300,15 @@ __global__ __launch_bounds__(kQueryBlock) void k_backward_query(Band B, const fl
         float cq[8], cs[8];
         trilinear_adjoint(st.q.t, s.inv_hf, (float)df, dgf, cq);
         trilinear_adjoint(st.s.t, s.inv_hf, dfs, dgsf, cs);
-        scatter_side(st.q, cq, A, s_acc, G, scale);
-        scatter_side(st.s, cs, A, s_acc, G, scale);
+        scatter_side(st.q, cq, s_keys, s_idx, s_acc, G, scale);
+        scatter_side(st.s, cs, s_keys, s_idx, s_acc, G, scale);
     }
 
-    // flush: one global atomic per vertex of the box that received anything
-    if (A.ok) {
-        __syncthreads();
-        for (int32_t li = threadIdx.x; li < (int32_t)nv; li += blockDim.x) {
-            const float v = s_acc[li];
-            if (v == 0.f) continue;
-            const int32_t z = A.lo[2] + li % A.dim[2], y = A.lo[1] + (li / A.dim[2]) % A.dim[1],
-                          x = A.lo[0] + li / (A.dim[2] * A.dim[1]);
-            const int32_t br = brick_of(B, s, x >> 3, y >> 3, z >> 3);
-            atomicAdd(&G[br * kBrickVol + local_index(x, y, z)], scale * v);
-        }
+    // flush: the cached bricks in slot order, one atomic per vertex that received anything
+    __syncthreads();
+    for (int32_t i = threadIdx.x; i < used * kBrickVol; i += blockDim.x) {
+        const float v = s_acc[i];
+        if (v != 0.f) atomicAdd(&G[s_brick[i >> 9] * kBrickVol + (i & (kBrickVol - 1))], scale * v);
     }
 }
 
