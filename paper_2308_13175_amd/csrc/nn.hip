@@ -5,23 +5,26 @@
 // cell's points are contiguous, and so are the points of a run of cells along
 // z inside one brick.
 //
-// A block takes a tile of 1024 queries, sorts them by the Morton code of their
-// cell and cuts the sorted list into groups of at most 64 queries whose cells
-// span at most 8 cells per axis (one group per wave at a time).  The wave then scans that box grown by one cell, then the
-// shell of the box grown by two, three, ... cells, all lanes in lockstep.  A
-// shell is cut into z-runs of cells inside one brick (each run's points are
-// contiguous); runs that cannot hold a point closer than the current best of
-// any unresolved lane are skipped, the rest are gathered 64 at a time (one
-// per lane), their point ranges fetched in one round trip, and the
-// concatenated points streamed in chunks of 64: every lane loads one point
-// and readlane hands each point to all lanes.  Each lane keeps its smallest
-// and second-smallest float distance: when the second exceeds the first by
-// more than the float error bound, the float argmin is the exact argmin; when
-// in addition the best distance is below the query's gap to the scanned box,
-// no unscanned point can be as close and the query is resolved.  Near ties
-// (and queries still open after the last shell) run an exact ring search:
-// distances in double without fused multiply-add, ties to the lowest point
-// index, so every result equals a brute-force search bit for bit.
+// A block takes a tile of 1024 queries and sorts them by the Morton code of
+// their cell; each wave cuts its quarter of the sorted list into groups of at
+// most 64 queries whose cells span at most 8 cells per axis and scans the
+// groups one at a time, all lanes in lockstep: first the group's box grown by
+// one cell, then the shell of the box grown by two, three, ... cells.  Of a
+// shell only the cells inside the union of the open lanes' reach are taken
+// (a lane's reach is the whole box until it has a candidate, then the cells
+// meeting the bounding box of the ball of its best distance).  The shell's
+// rows (x, y) are laid out one per lane and cut into z-runs inside one brick
+// (each run's points are contiguous), staged in LDS 64 at a time; their point
+// ranges are fetched in one round trip and the concatenated points streamed
+// in chunks of 64 through LDS, each point broadcast to every lane.  Each lane
+// keeps its smallest and second-smallest float distance: when the second
+// exceeds the first by more than the float error bound, the float argmin is
+// the exact argmin; when in addition the best distance is below the query's
+// gap to the scanned box, no unscanned point can be as close and the query
+// is resolved.  Near ties (and queries still open after the last shell) run
+// an exact ring search: distances in double without fused multiply-add, ties
+// to the lowest point index, so every result equals a brute-force search bit
+// for bit.
 #include <hipcub/hipcub.hpp>
 
 #include "gp_internal.h"
@@ -31,7 +34,6 @@ namespace {
 
 constexpr int kNnShells = 8;      // box growth steps scanned in lockstep before the fallback
 constexpr int kNnGroupCap = 8;     // a group's query cells span at most this many cells per axis
-constexpr int kNnMaxGroups = kQueryTile;   // groups per tile (worst case one query each)
 
 struct Best {
     double d2;
@@ -187,11 +189,6 @@ __device__ inline uint32_t spread3(uint32_t v)
     return v;
 }
 
-__device__ inline float lane_float(float v, int32_t lane)
-{
-    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
-}
-
 // Per-lane scan state.
 struct Scan {
     float x, y, z;
@@ -202,12 +199,13 @@ struct Scan {
     bool open;   // live and not yet resolved
 };
 
-// Runs of cells gathered for one wave: run i lives in the registers of lane
-// i % 64 until the batch of 64 is scanned.
-struct Runs {
-    int32_t x, y, z0, z1;   // this lane's run
-    int32_t n;              // runs in the batch (wave-uniform)
-};
+// Orders the LDS accesses of the lanes of one wave.
+__device__ inline void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 
 __device__ inline int32_t wave_exclusive_sum(int32_t v, int32_t& total)
 {
@@ -219,6 +217,12 @@ __device__ inline int32_t wave_exclusive_sum(int32_t v, int32_t& total)
     }
     total = __shfl(incl, 63, 64);
     return incl - v;
+}
+
+// Rank of this lane among the lanes set in m.
+__device__ inline int32_t lane_rank(uint64_t m)
+{
+    return (int32_t)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
 }
 
 // Evaluate the staged chunk buf[0..cnt) (an LDS broadcast per point) for every lane.
@@ -241,14 +245,21 @@ __device__ inline void eval_chunk(const float4* __restrict__ buf, int32_t cnt, S
     q.id1 = id;
 }
 
-// Scan the points of the gathered runs for every lane, then empty the batch.
+constexpr int kRunCap = 128;   // runs staged per wave (a batch of 64 plus one append round)
+
+// Scan the points of the first min(n, 64) staged runs (x, y, z0, z1) for
+// every lane, drop those runs from the stage and return how many are left.
 // buf: this wave's LDS staging area of 64 points.
-__device__ inline void flush_runs(const Band& B, const ShapeDesc& s, const Global& G, Runs& R, Scan& q,
-                                  float4* __restrict__ buf)
+__device__ inline int32_t flush_runs(const Band& B, const ShapeDesc& s, const Global& G, int4* __restrict__ runs,
+                                     int32_t n, Scan& q, float4* __restrict__ buf)
 {
     const int lane = threadIdx.x & 63;
+    const int32_t cnt = min(n, 64);
     int32_t pb = 0, pe = 0;
-    if (lane < R.n) run_range(B, s, G, R.x, R.y, R.z0, R.z1, pb, pe);
+    if (lane < cnt) {
+        const int4 r = runs[lane];
+        run_range(B, s, G, r.x, r.y, r.z, r.w, pb, pe);
+    }
     int32_t total;
     const int32_t off = wave_exclusive_sum(pe - pb, total);
     total = __builtin_amdgcn_readfirstlane(total);
@@ -257,54 +268,66 @@ __device__ inline void flush_runs(const Band& B, const ShapeDesc& s, const Globa
         int32_t j = 0;
         for (int step = 32; step > 0; step >>= 1) {
             const int32_t c = j + step;
-            const int32_t o = __shfl(off, c < R.n ? c : R.n - 1, 64);
-            if (c < R.n && o <= p) j = c;
+            const int32_t o = __shfl(off, c < cnt ? c : cnt - 1, 64);
+            if (c < cnt && o <= p) j = c;
         }
         const int32_t idx = __shfl(pb, j, 64) + (p - __shfl(off, j, 64));
         const float4 v = G.pts[p < total ? idx : 0];   // a scan only happens for a shape with points
         return p < total ? v : make_float4(0.f, 0.f, 0.f, 0.f);
     };
-    float4 nxt = point_at(lane);
+    float4 nxt = total > 0 ? point_at(lane) : make_float4(0.f, 0.f, 0.f, 0.f);
     for (int32_t c = 0; c < total; c += 64) {
         buf[lane] = nxt;
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        wave_sync();
         nxt = point_at(c + 64 + lane);    // the next chunk's loads fly during the evaluation
         eval_chunk(buf, min(64, total - c), q);
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
+        wave_sync();
     }
-    R.n = 0;
+    const int32_t rest = n - cnt;
+    int4 keep = make_int4(0, 0, 0, 0);
+    if (lane < rest) keep = runs[64 + lane];
+    wave_sync();
+    if (lane < rest) runs[lane] = keep;
+    wave_sync();
+    return rest;
 }
 
-__device__ inline void add_run(const Band& B, const ShapeDesc& s, const Global& G, Runs& R, Scan& q, int32_t x,
-                               int32_t y, int32_t z0, int32_t z1, float4* __restrict__ buf)
+// Stage the brick-aligned pieces of this lane's z range [za, zb] on row
+// (x, y) (an empty range adds nothing), flushing whenever 64 are staged.
+__device__ inline void stage_range(const Band& B, const ShapeDesc& s, const Global& G, int4* __restrict__ runs,
+                                   int32_t& n, Scan& q, float4* __restrict__ buf, int32_t x, int32_t y, int32_t za,
+                                   int32_t zb)
 {
-    if ((threadIdx.x & 63) == (R.n & 63)) {
-        R.x = x;
-        R.y = y;
-        R.z0 = z0;
-        R.z1 = z1;
-    }
-    if (++R.n == 64) flush_runs(B, s, G, R, q, buf);
-}
-
-// Cut the z range [za, zb] of row (x, y) into runs inside one brick and gather
-// those some open lane may need.
-__device__ inline void add_row(const Band& B, const ShapeDesc& s, const Global& G, Runs& R, Scan& q, int32_t x,
-                               int32_t y, int32_t za, int32_t zb, float lbxy, float h2z, float4* __restrict__ buf)
-{
-    for (int32_t z0 = za; z0 <= zb;) {
+    int32_t z0 = za;
+    for (;;) {
+        const bool has = z0 <= zb;
+        const uint64_t m = __ballot(has);
+        if (m == 0) break;
         const int32_t z1 = min(zb, z0 | 7);
-        const float gz = fmaxf(fmaxf((float)(z0 - q.c0[2]) - q.du[2], q.du[2] - (float)(z1 + 1 - q.c0[2])) - 1e-3f, 0.f);
-        const bool need = q.open && fmaf(gz * gz, h2z, lbxy) * (1.f - 1e-5f) <= q.best1;
-        if (__any(need)) add_run(B, s, G, R, q, x, y, z0, z1, buf);
-        z0 = z1 + 1;
+        if (has) runs[n + lane_rank(m)] = make_int4(x, y, z0, z1);
+        n += __popcll(m);
+        z0 = has ? z1 + 1 : z0;
+        if (n >= 64) {
+            wave_sync();
+            n = flush_runs(B, s, G, runs, n, q, buf);
+        }
     }
 }
 
 using BlockSort = hipcub::BlockRadixSort<uint32_t, kQueryBlock, kQueriesPerThread, int32_t>;
+
+__device__ inline uint32_t compact3(uint32_t v)
+{
+    v &= 0x09249249u;
+    v = (v | (v >> 2)) & 0x030c30c3u;
+    v = (v | (v >> 4)) & 0x0300f00fu;
+    v = (v | (v >> 8)) & 0x030000ffu;
+    v = (v | (v >> 16)) & 0x000003ffu;
+    return v;
+}
+
+constexpr int kWaves = kQueryBlock / 64;
+constexpr int kWaveSpan = kQueryTile / kWaves;   // sorted positions grouped and scanned by one wave
 
 __global__ __launch_bounds__(kQueryBlock) void k_nn(Band B, Global G, const float* __restrict__ qx,
                                                     const float* __restrict__ qy, const float* __restrict__ qz,
@@ -312,18 +335,21 @@ __global__ __launch_bounds__(kQueryBlock) void k_nn(Band B, Global G, const floa
 {
     __shared__ typename BlockSort::TempStorage sort_tmp;
     __shared__ int16_t s_order[kQueryTile];
-    __shared__ int32_t s_red[4 * 6];
+    __shared__ uint32_t s_cell[kQueryTile];          // sorted position -> packed cell (10 bits per axis)
+    __shared__ int32_t s_red[kWaves * 6];
     __shared__ float4 s_buf[kQueryBlock];
-    __shared__ int16_t s_group[kNnMaxGroups + 1];
-    __shared__ int32_t s_ngroups;
+    __shared__ int4 s_runs[kWaves][kRunCap];
+    __shared__ int16_t s_group[kWaves][kWaveSpan + 1];
+    __shared__ int32_t s_ngroups[kWaves];
 
     const int64_t tile = blockIdx.x;
     const int32_t shape = B.tile_shape[tile];
     const ShapeDesc& s = B.shapes[shape];
     const int64_t q0 = B.tile_start[tile];
-    float4* wbuf = s_buf + (threadIdx.x & ~63);
-    const int32_t nq = (int32_t)min((int64_t)kQueryTile, s.query_off + s.query_cnt - q0);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    float4* wbuf = s_buf + wave * 64;
+    int4* runs = s_runs[wave];
+    const int32_t nq = (int32_t)min((int64_t)kQueryTile, s.query_off + s.query_cnt - q0);
 
     // ---- sort the tile's queries by the Morton code of their cell ----------
     uint32_t key[kQueriesPerThread];
@@ -356,42 +382,47 @@ __global__ __launch_bounds__(kQueryBlock) void k_nn(Band B, Global G, const floa
     }
     BlockSort(sort_tmp).Sort(key, val);
 #pragma unroll
-    for (int j = 0; j < kQueriesPerThread; ++j) s_order[threadIdx.x * kQueriesPerThread + j] = (int16_t)val[j];
+    for (int j = 0; j < kQueriesPerThread; ++j) {
+        const int32_t pos = threadIdx.x * kQueriesPerThread + j;
+        s_order[pos] = (int16_t)val[j];
+        s_cell[pos] = compact3(key[j]) | (compact3(key[j] >> 1) << 10) | (compact3(key[j] >> 2) << 20);
+    }
     __syncthreads();
-    // greedy groups along the sorted order: at most 64 queries, cell span <= kNnGroupCap per axis
-    if (threadIdx.x == 0) {
+
+    // ---- greedy groups along this wave's part of the sorted order: at most
+    // 64 queries whose cells span at most kNnGroupCap cells per axis ---------
+    const int32_t wb0 = min(wave * kWaveSpan, nq), we0 = min(wb0 + kWaveSpan, nq);
+    if (lane == 0) {
         int32_t ng = 0, cnt = 0;
         int32_t glo[3] = {0, 0, 0}, ghi[3] = {0, 0, 0};
-        for (int32_t pos = 0; pos < nq; ++pos) {
-            const int32_t li = s_order[pos];
-            int32_t c[3];
-            float du[3];
-            query_cell(s, qx[q0 + li], qy[q0 + li], qz[q0 + li], c, du);
+        for (int32_t pos = wb0; pos < we0; ++pos) {
+            const uint32_t pc = s_cell[pos];
+            const int32_t c[3] = {(int32_t)(pc & 1023u), (int32_t)((pc >> 10) & 1023u), (int32_t)(pc >> 20)};
             bool fits = cnt > 0 && cnt < 64;
-            for (int a = 0; a < 3 && fits; ++a)
-                fits = max(ghi[a], c[a]) - min(glo[a], c[a]) < kNnGroupCap;
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+                fits = fits && max(ghi[a], c[a]) - min(glo[a], c[a]) < kNnGroupCap;
             if (!fits) {
-                s_group[ng++] = (int16_t)pos;
+                s_group[wave][ng++] = (int16_t)pos;
                 cnt = 0;
-                for (int a = 0; a < 3; ++a) glo[a] = ghi[a] = c[a];
             }
+#pragma unroll
             for (int a = 0; a < 3; ++a) {
-                glo[a] = min(glo[a], c[a]);
-                ghi[a] = max(ghi[a], c[a]);
+                glo[a] = fits ? min(glo[a], c[a]) : c[a];
+                ghi[a] = fits ? max(ghi[a], c[a]) : c[a];
             }
             ++cnt;
         }
-        s_group[ng] = (int16_t)nq;
-        s_ngroups = ng;
+        s_group[wave][ng] = (int16_t)we0;
+        s_ngroups[wave] = ng;
     }
-    __syncthreads();
-    const int32_t ngroups = s_ngroups;
+    wave_sync();
+    const int32_t ngroups = s_ngroups[wave];
 
-    const float h2[3] = {s.h[0] * s.h[0], s.h[1] * s.h[1], s.h[2] * s.h[2]};
-    // wave w takes groups w, w + 4, ...
-    for (int32_t gi = wave; gi < ngroups; gi += kQueryBlock / 64) {
-        const int32_t pos = s_group[gi] + lane;
-        const bool live = pos < s_group[gi + 1];
+    const float inv_h[3] = {1.f / s.h[0], 1.f / s.h[1], 1.f / s.h[2]};
+    for (int32_t gi = 0; gi < ngroups; ++gi) {
+        const int32_t pos = s_group[wave][gi] + lane;
+        const bool live = pos < s_group[wave][gi + 1];
         const int32_t li = live ? s_order[pos] : 0;
         const int64_t k = q0 + li;
         Scan q;
@@ -410,48 +441,62 @@ __global__ __launch_bounds__(kQueryBlock) void k_nn(Band B, Global G, const floa
             }
         wave_minmax6(wb);
         int32_t plo[3] = {0, 0, 0}, phi[3] = {-1, -1, -1};   // box scanned so far (empty)
-        Runs R;
-        R.n = 0;
-        R.x = R.y = R.z0 = R.z1 = 0;
+        int32_t n = 0;                                        // runs staged
         for (int e = 1; e <= kNnShells && __any(q.open); ++e) {
             int32_t lo[3], hi[3];
             for (int a = 0; a < 3; ++a) {
                 lo[a] = max(wb[a] - e, 0);
                 hi[a] = min(wb[3 + a] + e, s.R[a] - 1);
             }
-            // rows an open lane can still need: all of the box until it has a
-            // candidate, then only those within its best distance of its cell
-            // (every other row is provably farther, so the box gap stays valid)
+            // cells an open lane can still need: all of the box until it has
+            // a candidate, then the cells meeting the bounding box of the ball
+            // of its best distance (every other cell is provably farther, so
+            // the box gap stays valid for every lane)
             int32_t reach[6] = {0x7fffffff, 0x7fffffff, 0x7fffffff, -1, -1, -1};
             if (q.open) {
                 const bool have = q.best1 < __builtin_inff();
                 const float r = sqrtf(q.best1);
-                for (int a = 0; a < 2; ++a) {
-                    const int32_t m = have ? (int32_t)ceilf(r / s.h[a]) + 1 : 0;
-                    reach[a] = have ? q.c0[a] - m : lo[a];
-                    reach[3 + a] = have ? q.c0[a] + m : hi[a];
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    const float ra = r * inv_h[a] * (1.f + 1e-5f) + 1e-3f;
+                    reach[a] = have ? q.c0[a] + (int32_t)floorf(q.du[a] - ra) : lo[a];
+                    reach[3 + a] = have ? q.c0[a] + (int32_t)floorf(q.du[a] + ra) : hi[a];
                 }
             }
             wave_minmax6(reach);
-            const int32_t x_lo = max(lo[0], reach[0]), x_hi = min(hi[0], reach[3]);
-            const int32_t y_lo = max(lo[1], reach[1]), y_hi = min(hi[1], reach[4]);
-            for (int32_t xx = x_lo; xx <= x_hi; ++xx) {
-                const float gx = cell_gap(q.du[0], xx - q.c0[0], 1e-3f);
-                for (int32_t yy = y_lo; yy <= y_hi; ++yy) {
-                    const float gy = cell_gap(q.du[1], yy - q.c0[1], 1e-3f);
-                    const float lbxy = fmaf(gx * gx, h2[0], gy * gy * h2[1]);
-                    const bool need = q.open && lbxy * (1.f - 1e-5f) <= q.best1;
-                    if (!__any(need)) continue;
-                    const bool inner = xx >= plo[0] && xx <= phi[0] && yy >= plo[1] && yy <= phi[1];
-                    if (!inner) {
-                        add_row(B, s, G, R, q, xx, yy, lo[2], hi[2], lbxy, h2[2], wbuf);
-                    } else {
-                        if (lo[2] < plo[2]) add_row(B, s, G, R, q, xx, yy, lo[2], plo[2] - 1, lbxy, h2[2], wbuf);
-                        if (hi[2] > phi[2]) add_row(B, s, G, R, q, xx, yy, phi[2] + 1, hi[2], lbxy, h2[2], wbuf);
+            int32_t elo[3], ehi[3];
+            bool empty = false;
+            for (int a = 0; a < 3; ++a) {
+                elo[a] = max(lo[a], reach[a]);
+                ehi[a] = min(hi[a], reach[3 + a]);
+                empty = empty || elo[a] > ehi[a];
+            }
+            if (!empty) {
+                // rows (x, y) of the needed box, one per lane; rows inside the
+                // previous box only need the z cells outside it
+                const int32_t ny = ehi[1] - elo[1] + 1;
+                const int32_t nrows = (ehi[0] - elo[0] + 1) * ny;
+                for (int32_t base = 0; base < nrows; base += 64) {
+                    const int32_t r = base + lane;
+                    const bool row = r < nrows;
+                    const int32_t x = elo[0] + (row ? r / ny : 0);
+                    const int32_t y = elo[1] + (row ? r % ny : 0);
+                    const bool inner = x >= plo[0] && x <= phi[0] && y >= plo[1] && y <= phi[1];
+                    int32_t za = elo[2], zb = ehi[2], zc = 0, zd = -1;
+                    if (!row) zb = -1;
+                    if (row && inner) {
+                        zb = min(ehi[2], plo[2] - 1);
+                        zc = max(elo[2], phi[2] + 1);
+                        zd = ehi[2];
                     }
+                    stage_range(B, s, G, runs, n, q, wbuf, x, y, za, zb);
+                    stage_range(B, s, G, runs, n, q, wbuf, x, y, zc, zd);
                 }
             }
-            if (R.n > 0) flush_runs(B, s, G, R, q, wbuf);
+            if (n > 0) {
+                wave_sync();
+                n = flush_runs(B, s, G, runs, n, q, wbuf);
+            }
             // resolved: a unique float minimum that no unscanned point can match
             if (q.open && q.id1 >= 0 && q.best2 > q.best1 * (1.f + 1e-6f)) {
                 float gap = __builtin_inff();
