@@ -7,23 +7,30 @@
 //
 // A block takes a tile of 1024 queries and sorts them by the Morton code of
 // their cell; each wave cuts its quarter of the sorted list into groups of at
-// most 64 queries whose cells span at most 8 cells per axis and scans the
-// groups one at a time, all lanes in lockstep: first the group's box grown by
-// one cell, then the shell of the box grown by two, three, ... cells.  Of a
-// shell only the cells inside the union of the open lanes' reach are taken
-// (a lane's reach is the whole box until it has a candidate, then the cells
-// meeting the bounding box of the ball of its best distance).  The shell's
-// rows (x, y) are laid out one per lane and cut into z-runs inside one brick
-// (each run's points are contiguous), staged in LDS 64 at a time; their point
-// ranges are fetched in one round trip and the concatenated points streamed
-// in chunks of 64 through LDS, each point broadcast to every lane.  Each lane
-// keeps its smallest and second-smallest float distance: when the second
-// exceeds the first by more than the float error bound, the float argmin is
-// the exact argmin; when in addition the best distance is below the query's
-// gap to the scanned box, no unscanned point can be as close and the query
-// is resolved.  Near ties (and queries still open after the last shell) run
-// an exact ring search: distances in double without fused multiply-add, ties
-// to the lowest point index, so every result equals a brute-force search bit
+// most 64 queries whose cells span at most 8 cells per axis and serves the
+// groups one at a time in two passes.
+//
+// Lockstep pass (lane = query): the box of the group's cells grown by one
+// cell.  Its rows (x, y) are laid out one per lane and cut into z-runs inside
+// one brick (each run's points are contiguous), staged in LDS 64 at a time;
+// their point ranges are fetched in one round trip and the concatenated
+// points streamed in chunks of 64 through LDS, each point broadcast to every
+// lane.  Each lane keeps its smallest and second-smallest float distance: when
+// the second exceeds the first by more than the float error bound, the float
+// argmin is the exact argmin; when in addition the best distance is below the
+// query's gap to the box, no other point can be as close and the query is
+// resolved.
+//
+// Point-parallel pass (lane = point) for the few queries left open: up to 8
+// at a time, the cells meeting the bounding box of the ball of each one's
+// candidate distance, outside the box already scanned, are streamed once;
+// every lane tests its point against each of the queries, and the per-lane
+// minima are reduced over the wave.  Afterwards no unseen point can beat the
+// candidate, so a unique float minimum is the answer.
+//
+// Near ties (and queries with no candidate, or a very large ball) run an
+// exact ring search: distances in double without fused multiply-add, ties to
+// the lowest point index, so every result equals a brute-force search bit
 // for bit.
 #include <hipcub/hipcub.hpp>
 
@@ -32,7 +39,8 @@
 namespace gp {
 namespace {
 
-constexpr int kNnShells = 8;      // box growth steps scanned in lockstep before the fallback
+constexpr int kNnFirstShell = 1;  // growth of the group's box scanned in lockstep
+constexpr int kNnMaxGrow = 8;     // growth beyond which a group with no point in its box goes to the ring search
 constexpr int kNnGroupCap = 8;     // a group's query cells span at most this many cells per axis
 
 struct Best {
@@ -245,13 +253,105 @@ __device__ inline void eval_chunk(const float4* __restrict__ buf, int32_t cnt, S
     q.id1 = id;
 }
 
-constexpr int kRunCap = 128;   // runs staged per wave (a batch of 64 plus one append round)
+// Smallest and second-smallest value (and the argmin, ties to the lower id)
+// of (b1, b2, id) triples: merge the partner's triple into this one.
+__device__ inline void merge_min2(float& b1, float& b2, int32_t& id, float ob1, float ob2, int32_t oid)
+{
+    b2 = fminf(fminf(b2, ob2), fmaxf(b1, ob1));
+    id = (ob1 < b1 || (ob1 == b1 && oid < id)) ? oid : id;
+    b1 = fminf(b1, ob1);
+}
 
-// Scan the points of the first min(n, 64) staged runs (x, y, z0, z1) for
-// every lane, drop those runs from the stage and return how many are left.
-// buf: this wave's LDS staging area of 64 points.
+template <int Ctrl>
+__device__ inline int32_t dpp(int32_t v)
+{
+    return __builtin_amdgcn_update_dpp(v, v, Ctrl, 0xf, 0xf, false);
+}
+
+template <int Ctrl>
+__device__ inline void dpp_merge(float& b1, float& b2, int32_t& id)
+{
+    const float ob1 = __int_as_float(dpp<Ctrl>(__float_as_int(b1)));
+    const float ob2 = __int_as_float(dpp<Ctrl>(__float_as_int(b2)));
+    const int32_t oid = dpp<Ctrl>(id);
+    merge_min2(b1, b2, id, ob1, ob2, oid);
+}
+
+// Wave-wide merge of every lane's triple; the result is returned in all lanes.
+// Within each row of 16 lanes: swap neighbours, pairs, then mirror the half
+// row and the row (DPP); the four rows are then combined from their lane 0.
+__device__ inline void wave_min2(float& b1, float& b2, int32_t& id)
+{
+    dpp_merge<0xB1>(b1, b2, id);    // quad_perm [1, 0, 3, 2]
+    dpp_merge<0x4E>(b1, b2, id);    // quad_perm [2, 3, 0, 1]
+    dpp_merge<0x141>(b1, b2, id);   // row_half_mirror
+    dpp_merge<0x140>(b1, b2, id);   // row_mirror
+    float r1 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(b1), 0));
+    float r2 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(b2), 0));
+    int32_t ri = __builtin_amdgcn_readlane(id, 0);
+#pragma unroll
+    for (int row = 1; row < 4; ++row)
+        merge_min2(r1, r2, ri, __int_as_float(__builtin_amdgcn_readlane(__float_as_int(b1), 16 * row)),
+                   __int_as_float(__builtin_amdgcn_readlane(__float_as_int(b2), 16 * row)),
+                   __builtin_amdgcn_readlane(id, 16 * row));
+    b1 = r1;
+    b2 = r2;
+    id = ri;
+}
+
+constexpr int kRunCap = 128;   // runs staged per wave (a batch of 64 plus one append round)
+constexpr int kTail = 8;       // open queries served together by the point-parallel pass
+constexpr int kTailSpan = 24;  // larger balls (cells per axis) go to the ring search
+
+// Lockstep evaluation: lane = query, each staged point broadcast from LDS.
+struct Lockstep {
+    Scan* q;
+    float4* buf;   // this wave's 64-point staging area
+    __device__ void stage(const float4& p) const
+    {
+        buf[threadIdx.x & 63] = p;
+        wave_sync();
+    }
+    __device__ void eval(const float4&, int32_t cnt) const
+    {
+        eval_chunk(buf, cnt, *q);
+        wave_sync();
+    }
+};
+
+// Point-parallel evaluation: lane = point, each of up to kTail queries (slot
+// k at tq[k]) keeps per-lane smallest / second-smallest distance and argmin,
+// reduced over the wave afterwards.
+struct Tail {
+    const float4* tq;
+    int32_t ns;
+    float b1[kTail], b2[kTail];
+    int32_t id[kTail];
+    __device__ void stage(const float4&) const {}
+    __device__ void eval(const float4& p, int32_t cnt)
+    {
+        const bool ok = (int32_t)(threadIdx.x & 63) < cnt;
+#pragma unroll
+        for (int k = 0; k < kTail; ++k) {
+            if (k < ns) {
+                const float4 t = tq[k];
+                const float dx = t.x - p.x, dy = t.y - p.y, dz = t.z - p.z;
+                float d = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+                d = ok ? d : __builtin_inff();
+                const bool lt = d < b1[k];
+                b2[k] = fminf(b2[k], fmaxf(b1[k], d));
+                id[k] = lt ? __float_as_int(p.w) : id[k];
+                b1[k] = fminf(b1[k], d);
+            }
+        }
+    }
+};
+
+// Scan the points of the first min(n, 64) staged runs (x, y, z0, z1) with
+// the evaluator, drop those runs from the stage and return how many are left.
+template <class Ev>
 __device__ inline int32_t flush_runs(const Band& B, const ShapeDesc& s, const Global& G, int4* __restrict__ runs,
-                                     int32_t n, Scan& q, float4* __restrict__ buf)
+                                     int32_t n, Ev& ev)
 {
     const int lane = threadIdx.x & 63;
     const int32_t cnt = min(n, 64);
@@ -277,11 +377,10 @@ __device__ inline int32_t flush_runs(const Band& B, const ShapeDesc& s, const Gl
     };
     float4 nxt = total > 0 ? point_at(lane) : make_float4(0.f, 0.f, 0.f, 0.f);
     for (int32_t c = 0; c < total; c += 64) {
-        buf[lane] = nxt;
-        wave_sync();
+        const float4 cur = nxt;
+        ev.stage(cur);
         nxt = point_at(c + 64 + lane);    // the next chunk's loads fly during the evaluation
-        eval_chunk(buf, min(64, total - c), q);
-        wave_sync();
+        ev.eval(cur, min(64, total - c));
     }
     const int32_t rest = n - cnt;
     int4 keep = make_int4(0, 0, 0, 0);
@@ -294,9 +393,9 @@ __device__ inline int32_t flush_runs(const Band& B, const ShapeDesc& s, const Gl
 
 // Stage the brick-aligned pieces of this lane's z range [za, zb] on row
 // (x, y) (an empty range adds nothing), flushing whenever 64 are staged.
+template <class Ev>
 __device__ inline void stage_range(const Band& B, const ShapeDesc& s, const Global& G, int4* __restrict__ runs,
-                                   int32_t& n, Scan& q, float4* __restrict__ buf, int32_t x, int32_t y, int32_t za,
-                                   int32_t zb)
+                                   int32_t& n, Ev& ev, int32_t x, int32_t y, int32_t za, int32_t zb)
 {
     int32_t z0 = za;
     for (;;) {
@@ -309,8 +408,40 @@ __device__ inline void stage_range(const Band& B, const ShapeDesc& s, const Glob
         z0 = has ? z1 + 1 : z0;
         if (n >= 64) {
             wave_sync();
-            n = flush_runs(B, s, G, runs, n, q, buf);
+            n = flush_runs(B, s, G, runs, n, ev);
         }
+    }
+}
+
+// Stage every cell of box [lo, hi] outside box [olo, ohi] (which may be
+// empty), rows (x, y) one per lane, and scan them all.
+template <class Ev>
+__device__ inline void scan_box(const Band& B, const ShapeDesc& s, const Global& G, int4* __restrict__ runs, Ev& ev,
+                                const int32_t lo[3], const int32_t hi[3], const int32_t olo[3], const int32_t ohi[3])
+{
+    const int lane = threadIdx.x & 63;
+    if (lo[0] > hi[0] || lo[1] > hi[1] || lo[2] > hi[2]) return;
+    int32_t n = 0;
+    const int32_t ny = hi[1] - lo[1] + 1;
+    const int32_t nrows = (hi[0] - lo[0] + 1) * ny;
+    for (int32_t base = 0; base < nrows; base += 64) {
+        const int32_t r = base + lane;
+        const bool row = r < nrows;
+        const int32_t x = lo[0] + (row ? r / ny : 0);
+        const int32_t y = lo[1] + (row ? r % ny : 0);
+        const bool inner = x >= olo[0] && x <= ohi[0] && y >= olo[1] && y <= ohi[1];
+        int32_t za = lo[2], zb = row ? hi[2] : -1, zc = 0, zd = -1;
+        if (row && inner) {
+            zb = min(hi[2], olo[2] - 1);
+            zc = max(lo[2], ohi[2] + 1);
+            zd = hi[2];
+        }
+        stage_range(B, s, G, runs, n, ev, x, y, za, zb);
+        stage_range(B, s, G, runs, n, ev, x, y, zc, zd);
+    }
+    if (n > 0) {
+        wave_sync();
+        flush_runs(B, s, G, runs, n, ev);
     }
 }
 
@@ -329,7 +460,7 @@ __device__ inline uint32_t compact3(uint32_t v)
 constexpr int kWaves = kQueryBlock / 64;
 constexpr int kWaveSpan = kQueryTile / kWaves;   // sorted positions grouped and scanned by one wave
 
-__global__ __launch_bounds__(kQueryBlock) void k_nn(Band B, Global G, const float* __restrict__ qx,
+__global__ __launch_bounds__(kQueryBlock, 4) void k_nn(Band B, Global G, const float* __restrict__ qx,
                                                     const float* __restrict__ qy, const float* __restrict__ qz,
                                                     int32_t* __restrict__ nn)
 {
@@ -341,6 +472,7 @@ __global__ __launch_bounds__(kQueryBlock) void k_nn(Band B, Global G, const floa
     __shared__ int4 s_runs[kWaves][kRunCap];
     __shared__ int16_t s_group[kWaves][kWaveSpan + 1];
     __shared__ int32_t s_ngroups[kWaves];
+    __shared__ float4 s_tq[kWaves][kTail];
 
     const int64_t tile = blockIdx.x;
     const int32_t shape = B.tile_shape[tile];
@@ -391,35 +523,56 @@ __global__ __launch_bounds__(kQueryBlock) void k_nn(Band B, Global G, const floa
 
     // ---- greedy groups along this wave's part of the sorted order: at most
     // 64 queries whose cells span at most kNnGroupCap cells per axis ---------
-    const int32_t wb0 = min(wave * kWaveSpan, nq), we0 = min(wb0 + kWaveSpan, nq);
-    if (lane == 0) {
+    // (lane l holds positions 4l .. 4l+3 of the wave's part; the walk reads
+    // them with readlane, so its state lives in scalar registers)
+    const int32_t wb0 = __builtin_amdgcn_readfirstlane(min(wave * kWaveSpan, nq));
+    const int32_t we0 = __builtin_amdgcn_readfirstlane(min(wb0 + kWaveSpan, nq));
+    static_assert(kWaveSpan == 64 * 4, "four sorted positions per lane");
+    uint32_t pcell[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int32_t pos = wb0 + 4 * lane + j;
+        pcell[j] = pos < we0 ? s_cell[pos] : 0u;
+    }
+    {
         int32_t ng = 0, cnt = 0;
         int32_t glo[3] = {0, 0, 0}, ghi[3] = {0, 0, 0};
-        for (int32_t pos = wb0; pos < we0; ++pos) {
-            const uint32_t pc = s_cell[pos];
-            const int32_t c[3] = {(int32_t)(pc & 1023u), (int32_t)((pc >> 10) & 1023u), (int32_t)(pc >> 20)};
-            bool fits = cnt > 0 && cnt < 64;
+        const int32_t npos = we0 - wb0;
+        for (int32_t l = 0; 4 * l < npos; ++l) {
 #pragma unroll
-            for (int a = 0; a < 3; ++a)
-                fits = fits && max(ghi[a], c[a]) - min(glo[a], c[a]) < kNnGroupCap;
-            if (!fits) {
-                s_group[wave][ng++] = (int16_t)pos;
-                cnt = 0;
-            }
+            for (int j = 0; j < 4; ++j) {
+                const int32_t pos = wb0 + 4 * l + j;
+                if (pos < we0) {
+                    const uint32_t pc = __builtin_amdgcn_readlane(pcell[j], l);
+                    const int32_t c[3] = {(int32_t)(pc & 1023u), (int32_t)((pc >> 10) & 1023u), (int32_t)(pc >> 20)};
+                    bool fits = cnt > 0 && cnt < 64;
 #pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                glo[a] = fits ? min(glo[a], c[a]) : c[a];
-                ghi[a] = fits ? max(ghi[a], c[a]) : c[a];
+                    for (int a = 0; a < 3; ++a)
+                        fits = fits && max(ghi[a], c[a]) - min(glo[a], c[a]) < kNnGroupCap;
+                    if (!fits) {
+                        if (lane == 0) s_group[wave][ng] = (int16_t)pos;
+                        ++ng;
+                        cnt = 0;
+                    }
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) {
+                        glo[a] = fits ? min(glo[a], c[a]) : c[a];
+                        ghi[a] = fits ? max(ghi[a], c[a]) : c[a];
+                    }
+                    ++cnt;
+                }
             }
-            ++cnt;
         }
-        s_group[wave][ng] = (int16_t)we0;
-        s_ngroups[wave] = ng;
+        if (lane == 0) {
+            s_group[wave][ng] = (int16_t)we0;
+            s_ngroups[wave] = ng;
+        }
     }
     wave_sync();
     const int32_t ngroups = s_ngroups[wave];
 
     const float inv_h[3] = {1.f / s.h[0], 1.f / s.h[1], 1.f / s.h[2]};
+    float4* tq = s_tq[wave];
     for (int32_t gi = 0; gi < ngroups; ++gi) {
         const int32_t pos = s_group[wave][gi] + lane;
         const bool live = pos < s_group[wave][gi + 1];
@@ -440,64 +593,27 @@ __global__ __launch_bounds__(kQueryBlock) void k_nn(Band B, Global G, const floa
                 wb[3 + a] = q.c0[a];
             }
         wave_minmax6(wb);
-        int32_t plo[3] = {0, 0, 0}, phi[3] = {-1, -1, -1};   // box scanned so far (empty)
-        int32_t n = 0;                                        // runs staged
-        for (int e = 1; e <= kNnShells && __any(q.open); ++e) {
+        if (__any(q.open)) {
+            // ---- lockstep pass over the group's box grown by kNnFirstShell
+            // cells, grown further one cell at a time while it holds no point
             int32_t lo[3], hi[3];
-            for (int a = 0; a < 3; ++a) {
-                lo[a] = max(wb[a] - e, 0);
-                hi[a] = min(wb[3 + a] + e, s.R[a] - 1);
-            }
-            // cells an open lane can still need: all of the box until it has
-            // a candidate, then the cells meeting the bounding box of the ball
-            // of its best distance (every other cell is provably farther, so
-            // the box gap stays valid for every lane)
-            int32_t reach[6] = {0x7fffffff, 0x7fffffff, 0x7fffffff, -1, -1, -1};
-            if (q.open) {
-                const bool have = q.best1 < __builtin_inff();
-                const float r = sqrtf(q.best1);
-#pragma unroll
-                for (int a = 0; a < 3; ++a) {
-                    const float ra = r * inv_h[a] * (1.f + 1e-5f) + 1e-3f;
-                    reach[a] = have ? q.c0[a] + (int32_t)floorf(q.du[a] - ra) : lo[a];
-                    reach[3 + a] = have ? q.c0[a] + (int32_t)floorf(q.du[a] + ra) : hi[a];
-                }
-            }
-            wave_minmax6(reach);
-            int32_t elo[3], ehi[3];
-            bool empty = false;
-            for (int a = 0; a < 3; ++a) {
-                elo[a] = max(lo[a], reach[a]);
-                ehi[a] = min(hi[a], reach[3 + a]);
-                empty = empty || elo[a] > ehi[a];
-            }
-            if (!empty) {
-                // rows (x, y) of the needed box, one per lane; rows inside the
-                // previous box only need the z cells outside it
-                const int32_t ny = ehi[1] - elo[1] + 1;
-                const int32_t nrows = (ehi[0] - elo[0] + 1) * ny;
-                for (int32_t base = 0; base < nrows; base += 64) {
-                    const int32_t r = base + lane;
-                    const bool row = r < nrows;
-                    const int32_t x = elo[0] + (row ? r / ny : 0);
-                    const int32_t y = elo[1] + (row ? r % ny : 0);
-                    const bool inner = x >= plo[0] && x <= phi[0] && y >= plo[1] && y <= phi[1];
-                    int32_t za = elo[2], zb = ehi[2], zc = 0, zd = -1;
-                    if (!row) zb = -1;
-                    if (row && inner) {
-                        zb = min(ehi[2], plo[2] - 1);
-                        zc = max(elo[2], phi[2] + 1);
-                        zd = ehi[2];
+            {
+                int32_t olo[3] = {0, 0, 0}, ohi[3] = {-1, -1, -1};
+                for (int e = kNnFirstShell;; ++e) {
+                    for (int a = 0; a < 3; ++a) {
+                        lo[a] = max(wb[a] - e, 0);
+                        hi[a] = min(wb[3 + a] + e, s.R[a] - 1);
                     }
-                    stage_range(B, s, G, runs, n, q, wbuf, x, y, za, zb);
-                    stage_range(B, s, G, runs, n, q, wbuf, x, y, zc, zd);
+                    Lockstep ev{&q, wbuf};
+                    scan_box(B, s, G, runs, ev, lo, hi, olo, ohi);
+                    if (__any(q.id1 >= 0) || e >= kNnMaxGrow) break;
+                    for (int a = 0; a < 3; ++a) {
+                        olo[a] = lo[a];
+                        ohi[a] = hi[a];
+                    }
                 }
             }
-            if (n > 0) {
-                wave_sync();
-                n = flush_runs(B, s, G, runs, n, q, wbuf);
-            }
-            // resolved: a unique float minimum that no unscanned point can match
+            // resolved: a unique float minimum that no point outside the box can match
             if (q.open && q.id1 >= 0 && q.best2 > q.best1 * (1.f + 1e-6f)) {
                 float gap = __builtin_inff();
                 for (int a = 0; a < 3; ++a) {
@@ -507,10 +623,65 @@ __global__ __launch_bounds__(kQueryBlock) void k_nn(Band B, Global G, const floa
                 }
                 if (q.best1 * (1.f + 1e-6f) < gap * gap * (1.f - 1e-5f)) q.open = false;
             }
-            for (int a = 0; a < 3; ++a) {
-                plo[a] = lo[a];
-                phi[a] = hi[a];
+
+            // ---- point-parallel pass for the open lanes that have a candidate:
+            // the cells meeting the bounding box of the ball of the candidate
+            // distance, outside the box already scanned, kTail lanes at a time.
+            // Afterwards every point that can beat the candidate has been seen.
+            int32_t ball[6] = {0x7fffffff, 0x7fffffff, 0x7fffffff, -1, -1, -1};
+            bool tail = q.open && q.id1 >= 0;
+            if (tail) {
+                const float r = sqrtf(q.best1);
+    #pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    const float ra = r * inv_h[a] * (1.f + 1e-5f) + 1e-3f;
+                    ball[a] = max(q.c0[a] + (int32_t)floorf(q.du[a] - ra), 0);
+                    ball[3 + a] = min(q.c0[a] + (int32_t)floorf(q.du[a] + ra), s.R[a] - 1);
+                    tail = tail && ball[3 + a] - ball[a] < kTailSpan;
+                }
             }
+            uint64_t pend = __ballot(tail);
+            while (pend != 0) {
+                uint64_t batch = 0;
+                for (int t = 0; t < kTail && pend != 0; ++t) {
+                    batch |= pend & (~pend + 1);
+                    pend &= pend - 1;
+                }
+                const bool inb = (batch >> lane) & 1;
+                if (inb) tq[lane_rank(batch)] = make_float4(q.x, q.y, q.z, 0.f);
+                int32_t reg[6];
+                for (int a = 0; a < 6; ++a) reg[a] = inb ? ball[a] : (a < 3 ? 0x7fffffff : -1);
+                wave_minmax6(reg);
+                wave_sync();
+                Tail ev;
+                ev.tq = tq;
+                ev.ns = __popcll(batch);
+    #pragma unroll
+                for (int t = 0; t < kTail; ++t) {
+                    ev.b1[t] = ev.b2[t] = __builtin_inff();
+                    ev.id[t] = -1;
+                }
+                scan_box(B, s, G, runs, ev, reg, reg + 3, lo, hi);
+                // reduce every slot over the wave and merge it into its lane
+                uint64_t own = batch;
+#pragma unroll
+                for (int t = 0; t < kTail; ++t) {
+                    if (t < ev.ns) {
+                        float b1 = ev.b1[t], b2 = ev.b2[t];
+                        int32_t id = ev.id[t];
+                        wave_min2(b1, b2, id);
+                        const int32_t owner = __builtin_ctzll(own);
+                        own &= own - 1;
+                        if (lane == owner) {
+                            q.best2 = fminf(fminf(q.best2, b2), fmaxf(q.best1, b1));
+                            q.id1 = b1 < q.best1 ? id : q.id1;
+                            q.best1 = fminf(q.best1, b1);
+                        }
+                    }
+                }
+                wave_sync();
+            }
+            if (tail && q.best2 > q.best1 * (1.f + 1e-6f)) q.open = false;
         }
         if (!live) continue;
         nn[k] = (s.point_cnt > 0 && !q.open) ? q.id1 : search(B, s, G, q.x, q.y, q.z);
