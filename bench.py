@@ -27,6 +27,13 @@ if ROOT not in sys.path:
 
 METRIC = "pulled queries/sec (fwd+bwd) & % HBM peak; batched vs per-shape at 1e-5 rel err"
 HBM_PEAK_GBS = 8000.0
+FP32_PEAK_TFLOPS = 157.3        # MI355X vector FP32 (published)
+NN_FLOPS_PER_PAIR = 8           # dx, dy, dz; three squares; two adds
+WORKLOAD_KEYS = {1: "sphere10k", 2: "torus200k", 3: "union24", 4: "batched64", 5: "room20m"}
+PROFILES = os.path.join(ROOT, "profiles")
+KERNEL_SOURCES = {"k_nn": "nn.hip", "k_forward_query": "pull.hip", "k_backward_query": "pull.hip",
+                  "k_tv_forward": "pull.hip", "k_tv_backward": "pull.hip", "k_adam": "step.hip",
+                  "k_sample": "sample.hip"}
 
 
 def log(*a):
@@ -45,6 +52,98 @@ def kernel_bytes(name, Q, J, V, V2, n_slots, per_point_sigma):
         "k_tv_backward": 16 * V2,
         "k_adam": 28 * V + 4 * n_slots,
     }.get(name)
+
+
+def nn_required_pairs(points, dom, queries, n_sample=10000, seed=0, max_reach=12):
+    """Mean number of (query, point) pairs an exact cell-bucket search must test.
+
+    For a query at exact nearest distance d, every point in a grid cell whose
+    box comes within d of the query can be the nearest point (or tie with it),
+    so any exact search over the cell buckets has to test it.  Counted on a
+    random sample of the queries with a host k-d tree for d.
+    """
+    import numpy as np
+    from scipy.spatial import cKDTree
+
+    R = np.asarray(dom.dims, np.int64)
+    lo = np.asarray(dom.lo, np.float64)
+    hi = np.asarray(dom.hi, np.float64)
+    h = (hi - lo) / R
+    inv_h = R / (hi - lo)
+    P = np.asarray(points, np.float64)
+    pc = np.clip(np.floor((P - lo) * inv_h), 0, R - 1).astype(np.int64)
+    ids, counts = np.unique((pc[:, 0] * R[1] + pc[:, 1]) * R[2] + pc[:, 2], return_counts=True)
+    rng = np.random.default_rng(seed)
+    sel = rng.choice(len(queries), min(n_sample, len(queries)), replace=False)
+    Q = np.asarray(queries, np.float64)[sel]
+    d, _ = cKDTree(P).query(Q)
+    qc = np.clip(np.floor((Q - lo) * inv_h), 0, R - 1).astype(np.int64)
+    reach = np.minimum(np.ceil(d[:, None] * inv_h[None, :] + 1).astype(np.int64).max(1), max_reach)
+    total = np.zeros(len(Q))
+    for M in np.unique(reach):
+        m = reach == M
+        q, c0, d2 = Q[m], qc[m], d[m] ** 2
+        for ox in range(-M, M + 1):
+            for oy in range(-M, M + 1):
+                for oz in range(-M, M + 1):
+                    c = c0 + np.array([ox, oy, oz])
+                    ok = np.all((c >= 0) & (c < R), axis=1)
+                    blo = lo + c * h
+                    g = np.maximum(np.maximum(blo - q, q - (blo + h)), 0.0)
+                    ok &= (g * g).sum(1) <= d2
+                    cid = (c[ok, 0] * R[1] + c[ok, 1]) * R[2] + c[ok, 2]
+                    k = np.minimum(np.searchsorted(ids, cid), len(ids) - 1)
+                    hit = ids[k] == cid
+                    t = np.zeros(len(cid))
+                    t[hit] = counts[k[hit]]
+                    total[np.nonzero(m)[0][ok]] += t
+    return float(total.mean()), len(Q)
+
+
+def _source_sha(kernel):
+    import hashlib
+
+    src = KERNEL_SOURCES.get(kernel)
+    if src is None:
+        return None
+    with open(os.path.join(ROOT, "paper_2308_13175_amd", "csrc", src), "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def measured_traffic(kernel, config):
+    """HBM bytes per launch from the committed counter summary, or None.
+
+    The summary records the sha256 of the kernel's source file when the
+    counters were taken; a kernel changed since then gets None.
+    """
+    path = os.path.join(PROFILES, "%s_%s_traffic.txt" % (kernel, WORKLOAD_KEYS.get(config, "")))
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    with open(path) as f:
+        for line in f:
+            if ":" in line and not line.startswith("#"):
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+    if kv.get("source_sha256") != _source_sha(kernel):
+        return None
+    try:
+        return float(kv["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def copy_calibration(mib=256, reps=3):
+    """A plain device copy of known size, for scaling the HBM counters."""
+    import torch
+
+    a = torch.empty(mib << 18, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    a.fill_(1.0)
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    log("copy calibration: %d x %d MiB device copy" % (reps, mib))
 
 
 def build_problem(config: int):
@@ -147,6 +246,8 @@ def main():
                     help="workload: 1 sphere-10k, 2 torus-200k (default), 3 union24-2M, 4 batched64, 5 room-20M")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain 256 MiB device copy (scale for the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path (--gpus %d requested)" % args.gpus,
@@ -203,12 +304,38 @@ def main():
     avg = {k: (n, ms / max(n, 1)) for k, (n, ms) in kern.items()}
     dom_k = max((k for k in avg if kernel_bytes(k, Q, J, V, V2, prob.n_slots, per_point_sigma) is not None),
                 key=lambda k: kern[k][1])
-    by = kernel_bytes(dom_k, Q, J, V, V2, prob.n_slots, per_point_sigma)
-    ach = by / (avg[dom_k][1] * 1e-3) / 1e9
     fb_ms = sum(avg[k][1] for k in ("k_forward_query", "k_tv_forward", "k_finalize", "k_backward_query",
                                      "k_tv_backward") if k in avg)
     fb_bytes = 16 * Q + 12 * min(Q, J) + 12 * V
     ms_step = elapsed * 1e3 / args.steps
+    if dom_k == "k_nn":
+        # ALU bound: distance tests an exact cell-bucket search must make
+        qs = prob.queries()
+        pairs, n_s = [], 0
+        off = 0
+        for sh in wl.shapes:
+            pr, n = nn_required_pairs(sh.points, sh.domain, qs[off:off + sh.n_queries],
+                                      n_sample=max(200, int(10000 * sh.n_queries / max(Q, 1))))
+            pairs.append(pr * sh.n_queries)
+            off += sh.n_queries
+        per_launch = NN_FLOPS_PER_PAIR * sum(pairs)
+        ach = per_launch / (avg[dom_k][1] * 1e-3) / 1e12
+        roof = {"bound": "alu", "kernel": dom_k, "achieved": ach, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": ach / FP32_PEAK_TFLOPS, "traffic": measured_traffic(dom_k, args.config),
+                "flops_per_launch": per_launch, "required_pairs_per_query": sum(pairs) / max(Q, 1),
+                "avg_launch_ms": avg[dom_k][1]}
+    else:
+        by = kernel_bytes(dom_k, Q, J, V, V2, prob.n_slots, per_point_sigma)
+        ach = by / (avg[dom_k][1] * 1e-3) / 1e9
+        roof = {"bound": "hbm", "kernel": dom_k, "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": ach / HBM_PEAK_GBS, "traffic": measured_traffic(dom_k, args.config),
+                "bytes_per_launch": by, "avg_launch_ms": avg[dom_k][1]}
+    kernels_hbm = {}
+    for k in avg:
+        by = kernel_bytes(k, Q, J, V, V2, prob.n_slots, per_point_sigma)
+        if by is not None:
+            kernels_hbm[k] = {"bytes": by, "GBps": by / (avg[k][1] * 1e-3) / 1e9,
+                              "frac": by / (avg[k][1] * 1e-3) / 1e9 / HBM_PEAK_GBS}
     out = {
         "metric": METRIC,
         "value": Q * args.steps / elapsed,
@@ -226,12 +353,12 @@ def main():
                    "grid": [list(s.domain.dims) for s in wl.shapes][:4], "m1": wl.m1, "m2": wl.m2,
                    "slots": prob.n_slots, "optimised_vertices": V, "tv_vertices": V2,
                    "step": "sample+nn+forward+backward+adam"},
-        "roofline": {"bound": "hbm", "kernel": dom_k, "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": ach / HBM_PEAK_GBS, "traffic": None, "bytes_per_launch": by,
-                     "avg_launch_ms": avg[dom_k][1]},
+        "roofline": roof,
         "fwd_bwd": {"queries_per_s": Q / (fb_ms * 1e-3), "ms": fb_ms,
-                    "algorithmic_GBps": fb_bytes / (fb_ms * 1e-3) / 1e9},
+                    "algorithmic_GBps": fb_bytes / (fb_ms * 1e-3) / 1e9,
+                    "hbm_frac": fb_bytes / (fb_ms * 1e-3) / 1e9 / HBM_PEAK_GBS},
         "kernels_avg_ms": {k: round(v[1], 5) for k, v in sorted(avg.items())},
+        "kernels_hbm": kernels_hbm,
         "setup_ms": setup_ms,
     }
     if graph is not None:
@@ -241,6 +368,8 @@ def main():
         out["cpu_baseline"] = cpu_baseline(wl)
         log("cpu baseline took %.1f s" % (time.perf_counter() - t0))
     prob.close()
+    if args.copy_calibration:
+        copy_calibration()
     print(json.dumps(out), flush=True)
 
 
