@@ -146,6 +146,93 @@ def copy_calibration(mib=256, reps=3):
     log("copy calibration: %d x %d MiB device copy" % (reps, mib))
 
 
+def batched_vs_per_shape(wl, prob, steps, warmup):
+    """Config 4: one batched launch sequence against one context per shape.
+
+    Times the same iteration (eager and as captured graphs) both ways, then
+    puts both in the same state (geometric initial field, the batched
+    queries) and compares nearest neighbours, loss terms and gradients.
+    """
+    import numpy as np
+    import torch
+
+    from paper_2308_13175_amd import gridpull as gp
+    from paper_2308_13175_amd.problem import GraphedIteration, Problem, spec_from_synth
+
+    singles = [Problem([spec_from_synth(sh)], m1=wl.m1, m2=wl.m2, adam=prob.adam) for sh in wl.shapes]
+    for p in singles:
+        p.init_sphere()
+    torch.cuda.synchronize()
+
+    def run_eager(n):
+        for _ in range(n):
+            for p in singles:
+                p.iteration(None)
+
+    run_eager(warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    run_eager(steps)
+    torch.cuda.synchronize()
+    eager_s = (time.perf_counter() - t0) / steps
+    graphs = [GraphedIteration(p) for p in singles]
+    for _ in range(warmup):
+        for g in graphs:
+            g.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        for g in graphs:
+            g.replay()
+    torch.cuda.synchronize()
+    graph_s = (time.perf_counter() - t0) / steps
+    del graphs
+
+    # same state both ways: initial field, the batched problem's queries
+    prob.init_sphere()
+    for p in singles:
+        p.init_sphere()
+    prob.sample(7, 1)
+    prob.nearest()
+    prob.grad.zero_()
+    prob.forward()
+    prob.backward()
+    off = 0
+    sizes = [int(np.prod(np.asarray(sp.dims, np.int64) + 1)) for sp in prob.specs]
+    dense_b = torch.zeros(sum(sizes), dtype=torch.float32, device=prob.device)
+    gp.gp_scatter_vertices(prob.ctx, prob.grad, dense_b)
+    loss_b = prob.loss.cpu().numpy()
+    nn_equal = True
+    worst_loss, worst_grad = 0.0, 0.0
+    doff = 0
+    for i, p in enumerate(singles):
+        n = p.n_queries
+        p.qx[:n].copy_(prob.qx[off:off + n])
+        p.qy[:n].copy_(prob.qy[off:off + n])
+        p.qz[:n].copy_(prob.qz[off:off + n])
+        p.nearest()
+        p.grad.zero_()
+        p.forward()
+        p.backward()
+        nn_equal = nn_equal and bool(torch.equal(p.nn[:n], prob.nn[off:off + n]))
+        l1 = p.loss.cpu().numpy()[0]
+        l0 = loss_b[i]
+        worst_loss = max(worst_loss, float(np.max(np.abs(l1 - l0) / np.maximum(np.abs(l0), 1e-300))))
+        dense_s = torch.zeros(sizes[i], dtype=torch.float32, device=prob.device)
+        gp.gp_scatter_vertices(p.ctx, p.grad, dense_s)
+        ref = dense_b[doff:doff + sizes[i]]
+        gmax = float(ref.abs().max())
+        if gmax > 0:
+            worst_grad = max(worst_grad, float((dense_s - ref).abs().max()) / gmax)
+        off += n
+        doff += sizes[i]
+        p.close()
+    return {"per_shape_queries_per_s": prob.n_queries / eager_s, "per_shape_ms_per_step": eager_s * 1e3,
+            "per_shape_graph_queries_per_s": prob.n_queries / graph_s, "per_shape_graph_ms_per_step": graph_s * 1e3,
+            "nn_identical": nn_equal, "max_rel_err_loss_terms": worst_loss,
+            "max_rel_err_grad": worst_grad, "shapes": len(singles)}
+
+
 def build_problem(config: int):
     import numpy as np
 
@@ -363,6 +450,13 @@ def main():
     }
     if graph is not None:
         out["graph"] = {"queries_per_s": Q * args.steps / g_elapsed, "ms_per_step": g_elapsed * 1e3 / args.steps}
+    if args.config == 4:
+        cmp = batched_vs_per_shape(wl, prob, max(3, args.steps // 5), 2)
+        cmp["batched_queries_per_s"] = out["value"]
+        if graph is not None:
+            cmp["batched_graph_queries_per_s"] = out["graph"]["queries_per_s"]
+        cmp["speedup_eager"] = out["value"] / cmp["per_shape_queries_per_s"]
+        out["batched_vs_per_shape"] = cmp
     if not args.no_cpu_baseline:
         t0 = time.perf_counter()
         out["cpu_baseline"] = cpu_baseline(wl)
