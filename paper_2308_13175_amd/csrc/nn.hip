@@ -41,7 +41,7 @@ namespace {
 
 constexpr int kNnFirstShell = 1;  // growth of the group's box scanned in lockstep
 constexpr int kNnMaxGrow = 8;     // growth beyond which a group with no point in its box goes to the ring search
-constexpr int kNnGroupCap = 8;     // a group's query cells span at most this many cells per axis
+constexpr int kNnGroupCap = 8;     // a group's query cells span fewer than this many cells per axis
 
 struct Best {
     double d2;
@@ -522,46 +522,36 @@ __global__ __launch_bounds__(kQueryBlock, 4) void k_nn(Band B, Global G, const f
     __syncthreads();
 
     // ---- greedy groups along this wave's part of the sorted order: at most
-    // 64 queries whose cells span at most kNnGroupCap cells per axis ---------
-    // (lane l holds positions 4l .. 4l+3 of the wave's part; the walk reads
-    // them with readlane, so its state lives in scalar registers)
+    // 64 queries whose cells span fewer than kNnGroupCap cells per axis.  From
+    // each group's first position the next 64 cells are loaded one per lane;
+    // prefix minima and maxima over the lanes give the span of every prefix,
+    // and the group ends before the first lane whose prefix does not fit.
     const int32_t wb0 = __builtin_amdgcn_readfirstlane(min(wave * kWaveSpan, nq));
     const int32_t we0 = __builtin_amdgcn_readfirstlane(min(wb0 + kWaveSpan, nq));
-    static_assert(kWaveSpan == 64 * 4, "four sorted positions per lane");
-    uint32_t pcell[4];
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        const int32_t pos = wb0 + 4 * lane + j;
-        pcell[j] = pos < we0 ? s_cell[pos] : 0u;
-    }
     {
-        int32_t ng = 0, cnt = 0;
-        int32_t glo[3] = {0, 0, 0}, ghi[3] = {0, 0, 0};
-        const int32_t npos = we0 - wb0;
-        for (int32_t l = 0; 4 * l < npos; ++l) {
+        int32_t ng = 0;
+        for (int32_t g = wb0; g < we0; ++ng) {
+            const int32_t pos = g + lane;
+            const bool in = pos < we0;
+            const uint32_t pc = in ? s_cell[pos] : 0u;
+            int32_t lo[3] = {(int32_t)(pc & 1023u), (int32_t)((pc >> 10) & 1023u), (int32_t)(pc >> 20)};
+            int32_t hi[3] = {lo[0], lo[1], lo[2]};
+            for (int o = 1; o < 64; o <<= 1) {
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const int32_t pos = wb0 + 4 * l + j;
-                if (pos < we0) {
-                    const uint32_t pc = __builtin_amdgcn_readlane(pcell[j], l);
-                    const int32_t c[3] = {(int32_t)(pc & 1023u), (int32_t)((pc >> 10) & 1023u), (int32_t)(pc >> 20)};
-                    bool fits = cnt > 0 && cnt < 64;
-#pragma unroll
-                    for (int a = 0; a < 3; ++a)
-                        fits = fits && max(ghi[a], c[a]) - min(glo[a], c[a]) < kNnGroupCap;
-                    if (!fits) {
-                        if (lane == 0) s_group[wave][ng] = (int16_t)pos;
-                        ++ng;
-                        cnt = 0;
+                for (int a = 0; a < 3; ++a) {
+                    const int32_t l = __shfl_up(lo[a], o, 64), h = __shfl_up(hi[a], o, 64);
+                    if (lane >= o) {
+                        lo[a] = min(lo[a], l);
+                        hi[a] = max(hi[a], h);
                     }
-#pragma unroll
-                    for (int a = 0; a < 3; ++a) {
-                        glo[a] = fits ? min(glo[a], c[a]) : c[a];
-                        ghi[a] = fits ? max(ghi[a], c[a]) : c[a];
-                    }
-                    ++cnt;
                 }
             }
+            const bool fits = in && hi[0] - lo[0] < kNnGroupCap && hi[1] - lo[1] < kNnGroupCap &&
+                              hi[2] - lo[2] < kNnGroupCap;
+            const uint64_t bad = __ballot(!fits);
+            const int32_t len = bad ? max((int32_t)__builtin_ctzll(bad), 1) : 64;
+            if (lane == 0) s_group[wave][ng] = (int16_t)g;
+            g += len;
         }
         if (lane == 0) {
             s_group[wave][ng] = (int16_t)we0;
