@@ -204,6 +204,20 @@ gp_status gp_pull_backward(gp_ctx ctx, const float* qx, const float* qy, const f
                            gp_weights w, const double* dloss, float* grad);
 
 /*
+ * Forward and backward in one pass over the queries (Eq. 4-8 and their
+ * derivative): the same loss_out / n_valid_out as gp_pull_forward and the same
+ * accumulation grad[slot] += sum_s dloss[s] * dL_s / dD[slot] as
+ * gp_pull_backward, with each query evaluated once.  dloss must be known
+ * before the call (the training iteration passes 1).  Leaves the context
+ * state of a gp_pull_forward, so a gp_pull_backward may follow.
+ * Arguments and errors as for gp_pull_forward and gp_pull_backward.
+ */
+gp_status gp_pull_forward_backward(gp_ctx ctx, const float* qx, const float* qy, const float* qz,
+                                   const int32_t* nn, int64_t n_queries, const float* field,
+                                   gp_weights w, const double* dloss, double* loss_out,
+                                   int64_t* n_valid_out, float* grad);
+
+/*
  * One Adam step (Kingma and Ba, 2015) on the optimised vertices at iteration
  * t, learning rate lr0 * decay^floor((t-1)/decay_every) (Sec. 4: decay 0.3
  * every 400 iterations); then grad is set to 0 on every slot.  Slots that are

@@ -223,6 +223,18 @@ gp_status gp_pull_backward(gp_ctx ctx, const float* qx, const float* qy, const f
     return gp_backward_impl(ctx, qx, qy, qz, nn, field, w, dloss, grad);
 }
 
+gp_status gp_pull_forward_backward(gp_ctx ctx, const float* qx, const float* qy, const float* qz,
+                                   const int32_t* nn, int64_t n_queries, const float* field, gp_weights w,
+                                   const double* dloss, double* loss_out, int64_t* n_valid_out, float* grad)
+{
+    gp_status st = ready(ctx);
+    if (st != GP_OK) return st;
+    if ((st = check_queries(ctx, qx, qy, qz, n_queries)) != GP_OK) return st;
+    if ((n_queries > 0 && !nn) || !field || !dloss || !loss_out || !n_valid_out || !grad)
+        return gp_fail(ctx, GP_ERR_ARG, "null argument");
+    return gp_forward_backward_impl(ctx, qx, qy, qz, nn, field, w, dloss, loss_out, n_valid_out, grad);
+}
+
 gp_status gp_step(gp_ctx ctx, float* field, float* grad, float* m, float* v, int32_t t, float lr0, float decay,
                   int32_t decay_every, float beta1, float beta2, float eps)
 {

@@ -273,6 +273,7 @@ struct gp_ctx_s {
     DevBuf<int32_t> flag;         // device error flag
     DevBuf<int32_t> iter;         // device-resident iteration counter (last Adam t)
     DevBuf<float> step_c;         // [2] lr_t / (1 - beta1^t), 1 / sqrt(1 - beta2^t)
+    DevBuf<float> g_raw;          // [n_slots] unscaled query contributions of a fused pass (kept zero between passes)
     DevBuf<uint32_t> nn_tune;     // [n_shapes][3] extra box growth, queries searched, queries left to the ball pass
     bool have_forward = false;
 
@@ -339,6 +340,9 @@ gp_status gp_forward_impl(gp_ctx ctx, const float* qx, const float* qy, const fl
 gp_status gp_backward_impl(gp_ctx ctx, const float* qx, const float* qy, const float* qz,
                            const int32_t* nn, const float* field, gp_weights w,
                            const double* dloss, float* grad);
+gp_status gp_forward_backward_impl(gp_ctx ctx, const float* qx, const float* qy, const float* qz,
+                                   const int32_t* nn, const float* field, gp_weights w, const double* dloss,
+                                   double* loss_out, int64_t* n_valid_out, float* grad);
 gp_status gp_step_impl(gp_ctx ctx, float* field, float* grad, float* m, float* v, float beta1, float beta2,
                        float eps);
 gp_status gp_layout_impl(gp_ctx ctx, int64_t* vid, uint8_t* flags);

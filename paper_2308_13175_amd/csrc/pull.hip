@@ -182,26 +182,60 @@ __device__ inline int32_t cache_find(const int32_t* keys, const int32_t* idx, in
     return -1;
 }
 
-// Bricks holding the corners of cell c.
-__device__ inline void insert_cell_bricks(const Band& B, const ShapeDesc& s, const int32_t c[3], int32_t* keys)
+// Adjoint of one valid query (Eq. 4, 6, 7 differentiated): the contributions
+// to the 8 corners of q's cell and the 8 corners of s's cell.
+__device__ inline void query_adjoint(const ShapeDesc& s, const QueryState& st, gp_weights w, float cq[8], float cs[8])
 {
-    const int32_t bx0 = c[0] >> 3, by0 = c[1] >> 3, bz0 = c[2] >> 3;
-    const int32_t bx1 = (c[0] + 1) >> 3, by1 = (c[1] + 1) >> 3, bz1 = (c[2] + 1) >> 3;
-    for (int32_t bx = bx0; bx <= bx1; ++bx)
-        for (int32_t by = by0; by <= by1; ++by)
-            for (int32_t bz = bz0; bz <= bz1; ++bz) {
-                const int32_t br = brick_of(B, s, bx, by, bz);
-                if (br >= 0) cache_insert(keys, br);
-            }
+    // pull term, d l / d f = -gh.e with e = r/|r|; d l / d grad f is the
+    // projection of -f e orthogonal to gh over |grad f|, which equals
+    // -f/(|grad f| |r|) (I - gh gh^T)(q - s) because r = (q - s) - f gh
+    const double inv_lp = st.lp > 0.0 ? 1.0 / st.lp : 0.0;
+    const double* gh = st.q.gh;
+    const double* ghs = st.s.gh;
+    const double df = -(gh[0] * st.r[0] + gh[1] * st.r[1] + gh[2] * st.r[2]) * inv_lp;
+    double dg[3] = {0.0, 0.0, 0.0}, dgs[3] = {0.0, 0.0, 0.0};
+    if (st.q.ok) {
+        const double k = -st.q.f * inv_lp / st.q.n;
+        const double dd = gh[0] * st.d[0] + gh[1] * st.d[1] + gh[2] * st.d[2];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) dg[a] = k * fma(-dd, gh[a], st.d[a]);
+    }
+    // gradient-consistency term through both normalised gradients
+    if (st.q.ok && st.s.ok) {
+        const double c = gh[0] * ghs[0] + gh[1] * ghs[1] + gh[2] * ghs[2];
+        const double kq = (double)w.gamma / st.q.n, ks = (double)w.gamma / st.s.n;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            dg[a] -= kq * fma(-c, gh[a], ghs[a]);
+            dgs[a] = -ks * fma(-c, ghs[a], gh[a]);
+        }
+    }
+    const double fs = st.s.f;
+    const float dfs = w.beta * (fs > 0.0 ? 1.f : (fs < 0.0 ? -1.f : 0.f));
+    const float dgf[3] = {(float)dg[0], (float)dg[1], (float)dg[2]};
+    const float dgsf[3] = {(float)dgs[0], (float)dgs[1], (float)dgs[2]};
+    trilinear_adjoint(st.q.t, s.inv_hf, (float)df, dgf, cq);
+    trilinear_adjoint(st.s.t, s.inv_hf, dfs, dgsf, cs);
 }
 
-__device__ inline void scatter_side(const Side& sd, const float cv[8], const int32_t* keys, const int32_t* idx,
-                                    float* __restrict__ acc, float* __restrict__ G, float scale)
+__device__ inline void insert_slot_bricks(const int32_t slot[8], int32_t* keys)
+{
+    int32_t last = -1;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        const int32_t br = slot[i] >> 9;
+        if (br != last) cache_insert(keys, br);
+        last = br;
+    }
+}
+
+__device__ inline void scatter_slots(const int32_t slot[8], const float cv[8], const int32_t* keys,
+                                     const int32_t* idx, float* __restrict__ acc, float* __restrict__ G, float scale)
 {
     int32_t last_br = -1, last_li = -1;
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
-        const int32_t br = sd.slot[i] >> 9, local = sd.slot[i] & (kBrickVol - 1);
+        const int32_t br = slot[i] >> 9, local = slot[i] & (kBrickVol - 1);
         if (br != last_br) {
             last_br = br;
             last_li = cache_find(keys, idx, br);
@@ -209,46 +243,73 @@ __device__ inline void scatter_side(const Side& sd, const float cv[8], const int
         if (last_li >= 0)
             atomicAdd(&acc[last_li * kBrickVol + local], cv[i]);
         else
-            atomicAdd(&G[sd.slot[i]], scale * cv[i]);
+            atomicAdd(&G[slot[i]], scale * cv[i]);
     }
 }
 
-__global__ __launch_bounds__(kQueryBlock) void k_backward_query(Band B, const float* __restrict__ qx,
-                                                                const float* __restrict__ qy,
-                                                                const float* __restrict__ qz,
-                                                                const int32_t* __restrict__ nn,
-                                                                const float* __restrict__ px,
-                                                                const float* __restrict__ py,
-                                                                const float* __restrict__ pz,
-                                                                const float* __restrict__ D, gp_weights w,
-                                                                const double* __restrict__ dloss,
-                                                                const double* __restrict__ inv_qv,
-                                                                float* __restrict__ G, int32_t* flag)
+// One thread per query of a tile: evaluate, take the adjoint, keep the 16
+// corner contributions in registers while the block registers the bricks
+// they fall in, then accumulate them in LDS copies of those bricks (at most
+// kCacheBricks, the rest straight to memory) and add the bricks to G once, in
+// slot order.  kLoss: also the tile's loss partials, and the contributions
+// go out unscaled (the per-shape scale 1/valid count is applied when they are
+// folded into the gradient); otherwise they are scaled by dloss / valid count.
+template <bool kLoss>
+__global__ __launch_bounds__(kQueryTile) void k_query_grad(Band B, const float* __restrict__ qx,
+                                                           const float* __restrict__ qy,
+                                                           const float* __restrict__ qz,
+                                                           const int32_t* __restrict__ nn,
+                                                           const float* __restrict__ px,
+                                                           const float* __restrict__ py,
+                                                           const float* __restrict__ pz,
+                                                           const float* __restrict__ D, gp_weights w,
+                                                           const double* __restrict__ dloss,
+                                                           const double* __restrict__ inv_qv,
+                                                           float* __restrict__ G, double* __restrict__ q_part,
+                                                           int32_t* flag)
 {
     __shared__ float s_acc[kCacheBricks * kBrickVol];
     __shared__ int32_t s_keys[kCacheTable], s_idx[kCacheTable], s_brick[kCacheBricks];
     __shared__ int32_t s_used;
+    __shared__ double s_red[kQueryTile / 64 * 4];
     const int64_t tile = blockIdx.x;
     const int32_t shape = B.tile_shape[tile];
     const ShapeDesc& s = B.shapes[shape];
     const int64_t q0 = B.tile_start[tile];
     const int64_t qe = min(q0 + (int64_t)kQueryTile, s.query_off + s.query_cnt);
-    const float scale = (float)(dloss[shape] * inv_qv[shape]);
+    const float scale = kLoss ? 1.f : (float)(dloss[shape] * inv_qv[shape]);
 
-    // pass 1: the bricks the tile's valid queries and their surface points touch
     if (threadIdx.x < kCacheTable) s_keys[threadIdx.x] = -1;
+    for (int32_t i = threadIdx.x; i < kCacheBricks * kBrickVol / 4; i += blockDim.x)
+        reinterpret_cast<float4*>(s_acc)[i] = make_float4(0.f, 0.f, 0.f, 0.f);
     __syncthreads();
-    for (int64_t k = q0 + threadIdx.x; k < qe; k += blockDim.x) {
-        const Loc L = locate(s, qx[k], qy[k], qz[k]);
-        if (!L.inside) continue;
-        const int32_t br = brick_of(B, s, L.c[0] >> 3, L.c[1] >> 3, L.c[2] >> 3);
-        if (br < 0 || !mask_bit(B.m_a1, br, local_index(L.c[0], L.c[1], L.c[2]))) continue;
-        insert_cell_bricks(B, s, L.c, s_keys);
-        const int32_t j = nn[k];
-        if (j < 0 || j >= s.point_cnt) continue;
-        const int64_t g = s.sorted_off + j;
-        const Loc Ls = locate(s, px[g], py[g], pz[g]);
-        insert_cell_bricks(B, s, Ls.c, s_keys);
+
+    const int64_t k = q0 + threadIdx.x;
+    float cq[8], cs[8];
+    int32_t sq[8], ss[8];
+    bool valid = false;
+    double part[4] = {0.0, 0.0, 0.0, 0.0};
+    if (k < qe) {
+        QueryState st;
+        valid = eval_query(B, s, D, qx[k], qy[k], qz[k], nn[k], px, py, pz, flag, st);
+        if (valid) {
+            if (kLoss) {
+                part[0] = st.lp;
+                part[1] = fabs(st.s.f);
+                part[2] = (st.q.ok && st.s.ok) ? 1.0 - fma(st.q.gh[0], st.s.gh[0],
+                                                           fma(st.q.gh[1], st.s.gh[1], st.q.gh[2] * st.s.gh[2]))
+                                               : 1.0;
+                part[3] = 1.0;
+            }
+            query_adjoint(s, st, w, cq, cs);
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                sq[i] = st.q.slot[i];
+                ss[i] = st.s.slot[i];
+            }
+            insert_slot_bricks(sq, s_keys);
+            insert_slot_bricks(ss, s_keys);
+        }
     }
     __syncthreads();
     // LDS brick numbers in table order (the first wave holds the 64 entries)
@@ -262,53 +323,31 @@ __global__ __launch_bounds__(kQueryBlock) void k_backward_query(Band B, const fl
         if (threadIdx.x == 0) s_used = min(__popcll(m), kCacheBricks);
     }
     __syncthreads();
-    const int32_t used = s_used;
-    for (int32_t i = threadIdx.x; i < used * kBrickVol; i += blockDim.x) s_acc[i] = 0.f;
-    __syncthreads();
-
-    for (int64_t k = q0 + threadIdx.x; k < qe; k += blockDim.x) {
-        QueryState st;
-        if (!eval_query(B, s, D, qx[k], qy[k], qz[k], nn[k], px, py, pz, flag, st)) continue;
-        // pull term, d l / d f = -gh.e with e = r/|r|; d l / d grad f is the
-        // projection of -f e orthogonal to gh over |grad f|, which equals
-        // -f/(|grad f| |r|) (I - gh gh^T)(q - s) because r = (q - s) - f gh
-        const double inv_lp = st.lp > 0.0 ? 1.0 / st.lp : 0.0;
-        const double* gh = st.q.gh;
-        const double* ghs = st.s.gh;
-        const double df = -(gh[0] * st.r[0] + gh[1] * st.r[1] + gh[2] * st.r[2]) * inv_lp;
-        double dg[3] = {0.0, 0.0, 0.0}, dgs[3] = {0.0, 0.0, 0.0};
-        if (st.q.ok) {
-            const double k = -st.q.f * inv_lp / st.q.n;
-            const double dd = gh[0] * st.d[0] + gh[1] * st.d[1] + gh[2] * st.d[2];
-#pragma unroll
-            for (int a = 0; a < 3; ++a) dg[a] = k * fma(-dd, gh[a], st.d[a]);
-        }
-        // gradient-consistency term through both normalised gradients
-        if (st.q.ok && st.s.ok) {
-            const double c = gh[0] * ghs[0] + gh[1] * ghs[1] + gh[2] * ghs[2];
-            const double kq = (double)w.gamma / st.q.n, ks = (double)w.gamma / st.s.n;
-#pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                dg[a] -= kq * fma(-c, gh[a], ghs[a]);
-                dgs[a] = -ks * fma(-c, ghs[a], gh[a]);
-            }
-        }
-        const double fs = st.s.f;
-        const float dfs = w.beta * (fs > 0.0 ? 1.f : (fs < 0.0 ? -1.f : 0.f));
-        const float dgf[3] = {(float)dg[0], (float)dg[1], (float)dg[2]};
-        const float dgsf[3] = {(float)dgs[0], (float)dgs[1], (float)dgs[2]};
-        float cq[8], cs[8];
-        trilinear_adjoint(st.q.t, s.inv_hf, (float)df, dgf, cq);
-        trilinear_adjoint(st.s.t, s.inv_hf, dfs, dgsf, cs);
-        scatter_side(st.q, cq, s_keys, s_idx, s_acc, G, scale);
-        scatter_side(st.s, cs, s_keys, s_idx, s_acc, G, scale);
+    if (valid) {
+        scatter_slots(sq, cq, s_keys, s_idx, s_acc, G, scale);
+        scatter_slots(ss, cs, s_keys, s_idx, s_acc, G, scale);
     }
-
-    // flush: the cached bricks in slot order, one atomic per vertex that received anything
     __syncthreads();
+    // flush: the cached bricks in slot order, one atomic per vertex that received anything
+    const int32_t used = s_used;
     for (int32_t i = threadIdx.x; i < used * kBrickVol; i += blockDim.x) {
         const float v = s_acc[i];
         if (v != 0.f) atomicAdd(&G[s_brick[i >> 9] * kBrickVol + (i & (kBrickVol - 1))], scale * v);
+    }
+    if (kLoss) {
+        // tile partials in a fixed order: lanes, then waves
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            for (int o = 32; o > 0; o >>= 1) part[i] += __shfl_xor(part[i], o, 64);
+        const int wave = threadIdx.x >> 6;
+        if ((threadIdx.x & 63) == 0)
+            for (int i = 0; i < 4; ++i) s_red[wave * 4 + i] = part[i];
+        __syncthreads();
+        if (threadIdx.x < 4) {
+            double a = 0.0;
+            for (int wv = 0; wv < kQueryTile / 64; ++wv) a += s_red[wv * 4 + threadIdx.x];
+            q_part[tile * 4 + threadIdx.x] = a;
+        }
     }
 }
 
@@ -361,36 +400,55 @@ __global__ __launch_bounds__(256) void k_tv_forward(Band B, const float* __restr
     if (threadIdx.x == 0) tv_part[brick] = v[0];
 }
 
+// Gather form of the TV gradient (each vertex writes its own slot).  With
+// raw != nullptr the query contributions accumulated unscaled in raw are
+// added too, times dloss / valid count of the shape, and raw is cleared.
 __global__ __launch_bounds__(256) void k_tv_backward(Band B, const float* __restrict__ D,
                                                      const float* __restrict__ tau, gp_weights w,
-                                                     const double* __restrict__ dloss, float* __restrict__ G)
+                                                     const double* __restrict__ dloss,
+                                                     const double* __restrict__ inv_qv, float* __restrict__ raw,
+                                                     float* __restrict__ G)
 {
     const int32_t brick = blockIdx.x;
     const BrickInfo bi = B.bricks[brick];
     const ShapeDesc& s = B.shapes[bi.shape];
-    if (s.n_tv <= 0) return;
-    const float scale = (float)((double)w.alpha * dloss[bi.shape] / (double)s.n_tv);
+    const bool tv_on = s.n_tv > 0;
+    const float scale = tv_on ? (float)((double)w.alpha * dloss[bi.shape] / (double)s.n_tv) : 0.f;
+    const float rscale = raw ? (float)(dloss[bi.shape] * inv_qv[bi.shape]) : 0.f;
     for (int local = threadIdx.x; local < kBrickVol; local += blockDim.x) {
         const int32_t slot = brick * kBrickVol + local;
-        if (!mask_bit(B.m_v2, brick, local)) continue;
-        const int32_t i = bi.bx * kBrick + (local >> 6), j = bi.by * kBrick + ((local >> 3) & 7),
-                      k = bi.bz * kBrick + (local & 7);
-        const float dv = D[slot];
-        const float tv = tau[slot];
-        const float inv_tv = tv > 0.f ? 1.f / tv : 0.f;
-        const int32_t nb[6] = {vertex_slot(B, s, brick, bi, i + 1, j, k), vertex_slot(B, s, brick, bi, i - 1, j, k),
-                               vertex_slot(B, s, brick, bi, i, j + 1, k), vertex_slot(B, s, brick, bi, i, j - 1, k),
-                               vertex_slot(B, s, brick, bi, i, j, k + 1), vertex_slot(B, s, brick, bi, i, j, k - 1)};
-        float acc = 0.f;
-#pragma unroll
-        for (int o = 0; o < 6; ++o) {
-            if (!is_tv(B, nb[o])) continue;
-            const float d = dv - D[nb[o]];
-            const float tj = tau[nb[o]];
-            const float inv_tj = tj > 0.f ? 1.f / tj : 0.f;
-            acc = fmaf(d, inv_tv + inv_tj, acc);
+        float add = 0.f;
+        bool touch = false;
+        if (raw) {
+            const float r = raw[slot];
+            if (r != 0.f) {
+                add = rscale * r;
+                raw[slot] = 0.f;
+                touch = true;
+            }
         }
-        G[slot] += scale * acc;
+        if (tv_on && mask_bit(B.m_v2, brick, local)) {
+            const int32_t i = bi.bx * kBrick + (local >> 6), j = bi.by * kBrick + ((local >> 3) & 7),
+                          k = bi.bz * kBrick + (local & 7);
+            const float dv = D[slot];
+            const float tv = tau[slot];
+            const float inv_tv = tv > 0.f ? 1.f / tv : 0.f;
+            const int32_t nb[6] = {vertex_slot(B, s, brick, bi, i + 1, j, k), vertex_slot(B, s, brick, bi, i - 1, j, k),
+                                   vertex_slot(B, s, brick, bi, i, j + 1, k), vertex_slot(B, s, brick, bi, i, j - 1, k),
+                                   vertex_slot(B, s, brick, bi, i, j, k + 1), vertex_slot(B, s, brick, bi, i, j, k - 1)};
+            float acc = 0.f;
+#pragma unroll
+            for (int o = 0; o < 6; ++o) {
+                if (!is_tv(B, nb[o])) continue;
+                const float d = dv - D[nb[o]];
+                const float tj = tau[nb[o]];
+                const float inv_tj = tj > 0.f ? 1.f / tj : 0.f;
+                acc = fmaf(d, inv_tv + inv_tj, acc);
+            }
+            add = fmaf(scale, acc, add);
+            touch = true;
+        }
+        if (touch) G[slot] += add;
     }
 }
 
@@ -459,14 +517,46 @@ gp_status gp_backward_impl(gp_ctx ctx, const float* qx, const float* qy, const f
     Band B = ctx->band();
     if (ctx->n_tiles > 0) {
         GP_TIMED(ctx, "k_backward_query");
-        k_backward_query<<<(unsigned)ctx->n_tiles, kQueryBlock, 0, st>>>(B, qx, qy, qz, nn, ctx->ox.p, ctx->oy.p,
-                                                                         ctx->oz.p, field, w, dloss, ctx->inv_qv.p,
-                                                                         grad, ctx->flag.p);
+        k_query_grad<false><<<(unsigned)ctx->n_tiles, kQueryTile, 0, st>>>(
+            B, qx, qy, qz, nn, ctx->ox.p, ctx->oy.p, ctx->oz.p, field, w, dloss, ctx->inv_qv.p, grad, nullptr,
+            ctx->flag.p);
     }
     if (ctx->n_bricks > 0) {
         GP_TIMED(ctx, "k_tv_backward");
-        k_tv_backward<<<(unsigned)ctx->n_bricks, 256, 0, st>>>(B, field, ctx->tau.p, w, dloss, grad);
+        k_tv_backward<<<(unsigned)ctx->n_bricks, 256, 0, st>>>(B, field, ctx->tau.p, w, dloss, ctx->inv_qv.p,
+                                                               nullptr, grad);
     }
     GP_HIP(ctx, hipGetLastError());
+    return GP_OK;
+}
+
+gp_status gp_forward_backward_impl(gp_ctx ctx, const float* qx, const float* qy, const float* qz,
+                                   const int32_t* nn, const float* field, gp_weights w, const double* dloss,
+                                   double* loss_out, int64_t* n_valid_out, float* grad)
+{
+    hipStream_t st = ctx->stream;
+    Band B = ctx->band();
+    if (ctx->n_tiles > 0) {
+        GP_TIMED(ctx, "k_query_grad");
+        k_query_grad<true><<<(unsigned)ctx->n_tiles, kQueryTile, 0, st>>>(
+            B, qx, qy, qz, nn, ctx->ox.p, ctx->oy.p, ctx->oz.p, field, w, dloss, ctx->inv_qv.p, ctx->g_raw.p,
+            ctx->q_part.p, ctx->flag.p);
+    }
+    if (ctx->n_bricks > 0) {
+        GP_TIMED(ctx, "k_tv_forward");
+        k_tv_forward<<<(unsigned)ctx->n_bricks, 256, 0, st>>>(B, field, ctx->tau.p, ctx->tv_part.p);
+    }
+    {
+        GP_TIMED(ctx, "k_finalize");
+        k_finalize<<<(unsigned)ctx->n_shapes, 256, 0, st>>>(B, ctx->q_part.p, ctx->tv_part.p, w, loss_out,
+                                                            n_valid_out, ctx->inv_qv.p, ctx->flag.p);
+    }
+    if (ctx->n_bricks > 0) {
+        GP_TIMED(ctx, "k_tv_backward");
+        k_tv_backward<<<(unsigned)ctx->n_bricks, 256, 0, st>>>(B, field, ctx->tau.p, w, dloss, ctx->inv_qv.p,
+                                                               ctx->g_raw.p, grad);
+    }
+    GP_HIP(ctx, hipGetLastError());
+    ctx->have_forward = true;
     return GP_OK;
 }

@@ -197,6 +197,17 @@ class Problem:
                             self.qz[: self.n_queries], self.nn, f, self.weights, d, g)
         return g
 
+    def forward_backward(self, field: Optional[torch.Tensor] = None, grad: Optional[torch.Tensor] = None,
+                         dloss: Optional[torch.Tensor] = None):
+        """Loss and gradient in one pass over the queries (same results as forward + backward)."""
+        f = self.field if field is None else field
+        g = self.grad if grad is None else grad
+        d = self.dloss if dloss is None else dloss
+        gp.gp_pull_forward_backward(self.ctx, self.qx[: self.n_queries], self.qy[: self.n_queries],
+                                    self.qz[: self.n_queries], self.nn, f, self.weights, d, self.loss,
+                                    self.n_valid, g)
+        return self.loss
+
     def step(self, t: Optional[int] = None, lr0: Optional[float] = None):
         """Adam step at iteration t; t=None uses the context's device-resident counter."""
         a = self.adam
@@ -211,8 +222,7 @@ class Problem:
         """
         self.sample(seed, -1 if t is None else int(t))
         self.nearest()
-        self.forward()
-        self.backward()
+        self.forward_backward()
         self.step(t)
 
     def sync(self):

@@ -215,3 +215,36 @@ def test_batched_equals_single_shape():
         assert_grad_close(bg[i], ref["dD"])
         single.close()
     batch.close()
+
+
+@pytest.mark.parametrize("m1,m2", [(3, 3), (1, 4), (4, 2)])
+def test_fused_forward_backward(m1, m2):
+    """gp_pull_forward_backward = gp_pull_forward + gp_pull_backward = the
+    oracle (M1 < M2 puts band vertices outside the TV set, M1 > M2 the other
+    way round); a second fused call on a cleared gradient gives the same result
+    (its unscaled accumulator starts from zero again)."""
+    import torch
+
+    log("case: fused forward+backward, sphere 64^3 m1=%d m2=%d" % (m1, m2))
+    dom, pts, q, D = _sphere_case()
+    prob = _run_gpu(dom, pts, q, D, m1, m2)
+    sep_loss, _ = loss_terms(prob)
+    sep_grad = prob.dense_grad()[0]
+    cf, vf, nn, ref = _oracle(dom, pts, q, D, m1, m2)
+    for rep in range(2):
+        prob.grad.zero_()
+        prob.forward_backward()
+        prob.sync()
+        got, nv = loss_terms(prob)
+        assert int(nv[0]) == ref["n_valid"]
+        assert_terms_close(got[0], ref)
+        np.testing.assert_allclose(got[0], sep_loss[0], rtol=1e-12, atol=0)
+        g = prob.dense_grad()[0]
+        assert_grad_close(g, ref["dD"])
+        assert np.abs(g - sep_grad).max() <= 1e-6 * np.abs(sep_grad).max(), rep
+    # a scaled upstream gradient scales the query and TV parts alike
+    prob.grad.zero_()
+    prob.forward_backward(dloss=torch.full((1,), 2.5, dtype=torch.float64, device=prob.device))
+    g = prob.dense_grad()[0]
+    assert np.abs(g - 2.5 * sep_grad).max() <= 1e-6 * 2.5 * np.abs(sep_grad).max()
+    prob.close()
