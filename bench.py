@@ -32,6 +32,7 @@ NN_FLOPS_PER_PAIR = 8           # dx, dy, dz; three squares; two adds
 WORKLOAD_KEYS = {1: "sphere10k", 2: "torus200k", 3: "union24", 4: "batched64", 5: "room20m"}
 PROFILES = os.path.join(ROOT, "profiles")
 KERNEL_SOURCES = {"k_nn": "nn.hip", "k_forward_query": "pull.hip", "k_backward_query": "pull.hip",
+                  "k_query_grad": "pull.hip",
                   "k_tv_forward": "pull.hip", "k_tv_backward": "pull.hip", "k_adam": "step.hip",
                   "k_sample": "sample.hip"}
 
@@ -48,6 +49,7 @@ def kernel_bytes(name, Q, J, V, V2, n_slots, per_point_sigma):
         "k_nn": 16 * Q + 16 * J,
         "k_forward_query": 16 * Q + 12 * mqj + 4 * V,
         "k_backward_query": 16 * Q + 12 * mqj + 12 * V,
+        "k_query_grad": 16 * Q + 12 * mqj + 12 * V,
         "k_tv_forward": 8 * V2,
         "k_tv_backward": 16 * V2,
         "k_adam": 28 * V + 4 * n_slots,
@@ -391,8 +393,8 @@ def main():
     avg = {k: (n, ms / max(n, 1)) for k, (n, ms) in kern.items()}
     dom_k = max((k for k in avg if kernel_bytes(k, Q, J, V, V2, prob.n_slots, per_point_sigma) is not None),
                 key=lambda k: kern[k][1])
-    fb_ms = sum(avg[k][1] for k in ("k_forward_query", "k_tv_forward", "k_finalize", "k_backward_query",
-                                     "k_tv_backward") if k in avg)
+    fb_ms = sum(avg[k][1] for k in ("k_forward_query", "k_query_grad", "k_tv_forward", "k_finalize",
+                                     "k_backward_query", "k_tv_backward") if k in avg)
     fb_bytes = 16 * Q + 12 * min(Q, J) + 12 * V
     ms_step = elapsed * 1e3 / args.steps
     if dom_k == "k_nn":

@@ -499,7 +499,7 @@ gp_status gp_build_band_impl(gp_ctx ctx, const gp_shape* shapes, int32_t n_shape
     }
 
     // ---- scratch ----------------------------------------------------------
-    if (ctx->q_part.alloc((size_t)std::max<int64_t>(tiles_total, 1) * 4) != hipSuccess ||
+    if (ctx->q_part.alloc((size_t)std::max<int64_t>(tiles_total, 1) * 4 * 4) != hipSuccess ||   // up to 4 parts per tile
         ctx->tv_part.alloc((size_t)std::max<int64_t>(n_bricks, 1)) != hipSuccess ||
         ctx->tau.alloc((size_t)std::max<int64_t>(n_slots, 1)) != hipSuccess ||
         ctx->inv_qv.alloc(n_shapes) != hipSuccess || ctx->flag.alloc(1) != hipSuccess ||

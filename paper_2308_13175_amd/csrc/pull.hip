@@ -70,18 +70,24 @@ __device__ inline bool eval_query(const Band& B, const ShapeDesc& s, const float
                                   float z, int32_t nn, const float* __restrict__ px, const float* __restrict__ py,
                                   const float* __restrict__ pz, int32_t* bad_nn, QueryState& st)
 {
-    Loc L = locate(s, x, y, z);
-    if (!L.inside) return false;
-    const int32_t br = brick_of(B, s, L.c[0] >> 3, L.c[1] >> 3, L.c[2] >> 3);
+    // the loads of both sides are issued before any of them is tested
+    const Loc L = locate(s, x, y, z);
+    const bool nn_ok = nn >= 0 && nn < s.point_cnt;
+    const int64_t g = s.sorted_off + (nn_ok ? nn : 0);
+    float sx = 0.f, sy = 0.f, sz = 0.f;
+    if (s.point_cnt > 0) {
+        sx = px[g];
+        sy = py[g];
+        sz = pz[g];
+    }
+    const int32_t br = L.inside ? brick_of(B, s, L.c[0] >> 3, L.c[1] >> 3, L.c[2] >> 3) : -1;
     if (br < 0 || !mask_bit(B.m_a1, br, local_index(L.c[0], L.c[1], L.c[2]))) return false;
-    if (nn < 0 || nn >= s.point_cnt) {
+    if (!nn_ok) {
         atomicOr(bad_nn, 2);   // reported as an argument error by the next gp_sync
         return false;
     }
+    const Loc Ls = locate(s, sx, sy, sz);
     eval_side(B, s, D, L, st.q);
-    const int64_t g = s.sorted_off + nn;
-    const float sx = px[g], sy = py[g], sz = pz[g];
-    Loc Ls = locate(s, sx, sy, sz);
     eval_side(B, s, D, Ls, st.s);
     st.d[0] = (double)x - (double)sx;
     st.d[1] = (double)y - (double)sy;
@@ -148,34 +154,69 @@ __global__ __launch_bounds__(kQueryBlock) void k_forward_query(Band B, const flo
         for (int i = 0; i < 4; ++i) q_part[tile * 4 + i] = v[i];
 }
 
-constexpr int kCacheBricks = 32;   // LDS brick accumulators per block (32 x 2 KB)
-constexpr int kCacheTable = 64;    // open-addressing table: global brick -> LDS brick
+constexpr int kGradParts = 4;                          // blocks per query tile in the gradient pass
+constexpr int kGradBlock = kQueryTile / kGradParts;    // one query per thread
+// The contributions of a block land in few places (its queries come from
+// neighbouring points).  They are accumulated in LDS copies of the 4^3-vertex
+// octants of the bricks they touch ("cells" of the cache, keyed by brick * 8 +
+// octant) and flushed once, octant by octant, so that the lanes of a wave add
+// to nearby addresses.  The accumulators hold fixed point with 32 fraction
+// bits in 64-bit integers: integer LDS atomics run at full rate where float
+// ones do not, and the sums inside a block become exact.  A contribution of
+// 2^20 or more in magnitude bypasses them (a float atomic on the gradient),
+// so no sum can leave the range of the fixed point; so do the contributions
+// of octants beyond the cache's capacity.
+constexpr int kOctVol = 64;                       // vertices per octant
+constexpr int kCacheOcts = 96;                    // LDS octant accumulators per block (96 x 512 B)
+constexpr int kCacheTable = 256;                  // open-addressing table: octant key -> LDS octant
+constexpr double kFixScale = 4294967296.0;        // 2^32
+constexpr float kFixLimit = 1048576.f;            // 2^20
 
-// The bricks a tile's contributions land in are few (the queries of a tile
-// come from neighbouring points): they are accumulated in LDS copies of those
-// bricks and flushed once, brick by brick, so that the lanes of a wave add to
-// consecutive addresses (combined per cache line by the memory side).
-__device__ inline int32_t table_home(int32_t br)
+// Octant key of a slot, and the slot's place inside its octant.
+__device__ inline int32_t oct_key(int32_t slot)
 {
-    return (int32_t)(((uint32_t)br * 2654435761u) >> 26);
+    const int32_t l = slot & (kBrickVol - 1);
+    return ((slot >> 9) << 3) | ((l >> 6) & 4) | ((l >> 4) & 2) | ((l >> 2) & 1);
 }
 
-__device__ inline void cache_insert(int32_t* keys, int32_t br)
+__device__ inline int32_t oct_index(int32_t slot)
 {
-    int32_t h = table_home(br);
+    const int32_t l = slot & (kBrickVol - 1);
+    return ((l >> 2) & 48) | ((l >> 1) & 12) | (l & 3);
+}
+
+// Slot of place w of octant key.
+__device__ inline int32_t oct_slot(int32_t key, int32_t w)
+{
+    const int32_t o = key & 7;
+    const int32_t i = ((o >> 2) << 2) | (w >> 4), j = (((o >> 1) & 1) << 2) | ((w >> 2) & 3),
+                  k = ((o & 1) << 2) | (w & 3);
+    return (key >> 3) * kBrickVol + ((i * kBrick + j) * kBrick + k);
+}
+
+__device__ inline int32_t table_home(int32_t key)
+{
+    return (int32_t)(((uint32_t)key * 2654435761u) >> 24);
+}
+
+__device__ inline void cache_insert(int32_t* keys, int32_t key)
+{
+    int32_t h = table_home(key);
+#pragma unroll 1
     for (int p = 0; p < kCacheTable; ++p) {
-        const int32_t old = atomicCAS(&keys[h], -1, br);
-        if (old == -1 || old == br) return;
+        const int32_t old = atomicCAS(&keys[h], -1, key);
+        if (old == -1 || old == key) return;
         h = (h + 1) & (kCacheTable - 1);
     }
 }
 
-__device__ inline int32_t cache_find(const int32_t* keys, const int32_t* idx, int32_t br)
+__device__ inline int32_t cache_find(const int32_t* keys, const int32_t* idx, int32_t key)
 {
-    int32_t h = table_home(br);
+    int32_t h = table_home(key);
+#pragma unroll 1
     for (int p = 0; p < kCacheTable; ++p) {
         const int32_t k = keys[h];
-        if (k == br) return idx[h];
+        if (k == key) return idx[h];
         if (k == -1) return -1;
         h = (h + 1) & (kCacheTable - 1);
     }
@@ -218,44 +259,46 @@ __device__ inline void query_adjoint(const ShapeDesc& s, const QueryState& st, g
     trilinear_adjoint(st.s.t, s.inv_hf, dfs, dgsf, cs);
 }
 
-__device__ inline void insert_slot_bricks(const int32_t slot[8], int32_t* keys)
+__device__ inline void insert_slot_octs(const int32_t slot[8], int32_t* keys)
 {
     int32_t last = -1;
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
-        const int32_t br = slot[i] >> 9;
-        if (br != last) cache_insert(keys, br);
-        last = br;
+        const int32_t key = oct_key(slot[i]);
+        if (key != last) cache_insert(keys, key);
+        last = key;
     }
 }
 
 __device__ inline void scatter_slots(const int32_t slot[8], const float cv[8], const int32_t* keys,
-                                     const int32_t* idx, float* __restrict__ acc, float* __restrict__ G, float scale)
+                                     const int32_t* idx, unsigned long long* __restrict__ acc,
+                                     float* __restrict__ G, float scale)
 {
-    int32_t last_br = -1, last_li = -1;
+    int32_t last_key = -1, last_li = -1;
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
-        const int32_t br = slot[i] >> 9, local = slot[i] & (kBrickVol - 1);
-        if (br != last_br) {
-            last_br = br;
-            last_li = cache_find(keys, idx, br);
+        const int32_t key = oct_key(slot[i]);
+        if (key != last_key) {
+            last_key = key;
+            last_li = cache_find(keys, idx, key);
         }
-        if (last_li >= 0)
-            atomicAdd(&acc[last_li * kBrickVol + local], cv[i]);
+        if (last_li >= 0 && fabsf(cv[i]) < kFixLimit)
+            atomicAdd(&acc[last_li * kOctVol + oct_index(slot[i])],
+                      (unsigned long long)__double2ll_rn((double)cv[i] * kFixScale));
         else
             atomicAdd(&G[slot[i]], scale * cv[i]);
     }
 }
 
-// One thread per query of a tile: evaluate, take the adjoint, keep the 16
+// One thread per query of a quarter tile: evaluate, take the adjoint, keep the 16
 // corner contributions in registers while the block registers the bricks
-// they fall in, then accumulate them in LDS copies of those bricks (at most
-// kCacheBricks, the rest straight to memory) and add the bricks to G once, in
-// slot order.  kLoss: also the tile's loss partials, and the contributions
+// they fall in, then accumulate them in LDS copies of those octants (at most
+// kCacheOcts, the rest straight to memory; fixed point) and add the octants to
+// G once.  kLoss: also the tile's loss partials, and the contributions
 // go out unscaled (the per-shape scale 1/valid count is applied when they are
 // folded into the gradient); otherwise they are scaled by dloss / valid count.
 template <bool kLoss>
-__global__ __launch_bounds__(kQueryTile) void k_query_grad(Band B, const float* __restrict__ qx,
+__global__ __launch_bounds__(kGradBlock) void k_query_grad(Band B, const float* __restrict__ qx,
                                                            const float* __restrict__ qy,
                                                            const float* __restrict__ qz,
                                                            const int32_t* __restrict__ nn,
@@ -268,20 +311,22 @@ __global__ __launch_bounds__(kQueryTile) void k_query_grad(Band B, const float* 
                                                            float* __restrict__ G, double* __restrict__ q_part,
                                                            int32_t* flag)
 {
-    __shared__ float s_acc[kCacheBricks * kBrickVol];
-    __shared__ int32_t s_keys[kCacheTable], s_idx[kCacheTable], s_brick[kCacheBricks];
-    __shared__ int32_t s_used;
-    __shared__ double s_red[kQueryTile / 64 * 4];
-    const int64_t tile = blockIdx.x;
+    __shared__ unsigned long long s_acc[kCacheOcts * kOctVol];
+    __shared__ int32_t s_keys[kCacheTable], s_idx[kCacheTable], s_oct[kCacheOcts];
+    __shared__ int32_t s_wcount[kGradBlock / 64];
+    __shared__ double s_red[kGradBlock / 64 * 4];
+    const int64_t tile = blockIdx.x / kGradParts;
+    const int32_t quarter = blockIdx.x % kGradParts;
     const int32_t shape = B.tile_shape[tile];
     const ShapeDesc& s = B.shapes[shape];
-    const int64_t q0 = B.tile_start[tile];
-    const int64_t qe = min(q0 + (int64_t)kQueryTile, s.query_off + s.query_cnt);
+    const int64_t q0 = B.tile_start[tile] + (int64_t)quarter * kGradBlock;
+    const int64_t qe = min(B.tile_start[tile] + (int64_t)kQueryTile, s.query_off + s.query_cnt);
     const float scale = kLoss ? 1.f : (float)(dloss[shape] * inv_qv[shape]);
 
-    if (threadIdx.x < kCacheTable) s_keys[threadIdx.x] = -1;
-    for (int32_t i = threadIdx.x; i < kCacheBricks * kBrickVol / 4; i += blockDim.x)
-        reinterpret_cast<float4*>(s_acc)[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+    static_assert(kCacheTable == kGradBlock, "one table entry per thread");
+    s_keys[threadIdx.x] = -1;
+    for (int32_t i = threadIdx.x; i < kCacheOcts * kOctVol / 2; i += blockDim.x)
+        reinterpret_cast<ulonglong2*>(s_acc)[i] = make_ulonglong2(0ull, 0ull);
     __syncthreads();
 
     const int64_t k = q0 + threadIdx.x;
@@ -307,20 +352,26 @@ __global__ __launch_bounds__(kQueryTile) void k_query_grad(Band B, const float* 
                 sq[i] = st.q.slot[i];
                 ss[i] = st.s.slot[i];
             }
-            insert_slot_bricks(sq, s_keys);
-            insert_slot_bricks(ss, s_keys);
+            insert_slot_octs(sq, s_keys);
+            insert_slot_octs(ss, s_keys);
         }
     }
     __syncthreads();
-    // LDS brick numbers in table order (the first wave holds the 64 entries)
-    if (threadIdx.x < kCacheTable) {
-        const bool used = s_keys[threadIdx.x] != -1;
-        const uint64_t m = __ballot(used);
-        const int32_t before = __popcll(m & ((1ull << threadIdx.x) - 1ull));
-        const int32_t li = used && before < kCacheBricks ? before : -1;
+    // LDS octant numbers in table order (one table entry per thread)
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const bool used_e = s_keys[threadIdx.x] != -1;
+    const uint64_t um = __ballot(used_e);
+    if (lane == 0) s_wcount[wave] = __popcll(um);
+    __syncthreads();
+    int32_t before = __popcll(um & ((1ull << lane) - 1ull)), n_used = 0;
+    for (int wv = 0; wv < kGradBlock / 64; ++wv) {
+        before += wv < wave ? s_wcount[wv] : 0;
+        n_used += s_wcount[wv];
+    }
+    {
+        const int32_t li = used_e && before < kCacheOcts ? before : -1;
         s_idx[threadIdx.x] = li;
-        if (li >= 0) s_brick[li] = s_keys[threadIdx.x];
-        if (threadIdx.x == 0) s_used = min(__popcll(m), kCacheBricks);
+        if (li >= 0) s_oct[li] = s_keys[threadIdx.x];
     }
     __syncthreads();
     if (valid) {
@@ -328,11 +379,12 @@ __global__ __launch_bounds__(kQueryTile) void k_query_grad(Band B, const float* 
         scatter_slots(ss, cs, s_keys, s_idx, s_acc, G, scale);
     }
     __syncthreads();
-    // flush: the cached bricks in slot order, one atomic per vertex that received anything
-    const int32_t used = s_used;
-    for (int32_t i = threadIdx.x; i < used * kBrickVol; i += blockDim.x) {
-        const float v = s_acc[i];
-        if (v != 0.f) atomicAdd(&G[s_brick[i >> 9] * kBrickVol + (i & (kBrickVol - 1))], scale * v);
+    // flush: the cached octants, one atomic per vertex that received anything
+    const int32_t used = min(n_used, kCacheOcts);
+    for (int32_t i = threadIdx.x; i < used * kOctVol; i += blockDim.x) {
+        const long long a = (long long)s_acc[i];
+        if (a != 0) atomicAdd(&G[oct_slot(s_oct[i >> 6], i & (kOctVol - 1))],
+                              (float)((double)a * (1.0 / kFixScale) * (double)scale));
     }
     if (kLoss) {
         // tile partials in a fixed order: lanes, then waves
@@ -345,8 +397,8 @@ __global__ __launch_bounds__(kQueryTile) void k_query_grad(Band B, const float* 
         __syncthreads();
         if (threadIdx.x < 4) {
             double a = 0.0;
-            for (int wv = 0; wv < kQueryTile / 64; ++wv) a += s_red[wv * 4 + threadIdx.x];
-            q_part[tile * 4 + threadIdx.x] = a;
+            for (int wv = 0; wv < kGradBlock / 64; ++wv) a += s_red[wv * 4 + threadIdx.x];
+            q_part[blockIdx.x * 4 + threadIdx.x] = a;
         }
     }
 }
@@ -456,13 +508,15 @@ __global__ __launch_bounds__(256) void k_tv_backward(Band B, const float* __rest
 __global__ __launch_bounds__(256) void k_finalize(Band B, const double* __restrict__ q_part,
                                                   const double* __restrict__ tv_part, gp_weights w,
                                                   double* __restrict__ loss_out, int64_t* __restrict__ n_valid_out,
-                                                  double* __restrict__ inv_qv, int32_t* __restrict__ flag)
+                                                  double* __restrict__ inv_qv, int32_t* __restrict__ flag,
+                                                  int32_t parts)
 {
     __shared__ double lds[4 * 5];
     const int32_t shape = blockIdx.x;
     const ShapeDesc& s = B.shapes[shape];
     double v[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-    for (int64_t t = s.tile_begin + threadIdx.x; t < s.tile_end; t += blockDim.x)
+    // q_part holds `parts` partial sums per tile
+    for (int64_t t = s.tile_begin * parts + threadIdx.x; t < s.tile_end * parts; t += blockDim.x)
         for (int i = 0; i < 4; ++i) v[i] += q_part[t * 4 + i];
     for (int64_t b = s.brick_begin + threadIdx.x; b < s.brick_end; b += blockDim.x) v[4] += tv_part[b];
     block_sum<5>(v, lds);
@@ -504,7 +558,7 @@ gp_status gp_forward_impl(gp_ctx ctx, const float* qx, const float* qy, const fl
     }
     GP_TIMED(ctx, "k_finalize");
     k_finalize<<<(unsigned)ctx->n_shapes, 256, 0, st>>>(B, ctx->q_part.p, ctx->tv_part.p, w, loss_out, n_valid_out,
-                                                        ctx->inv_qv.p, ctx->flag.p);
+                                                        ctx->inv_qv.p, ctx->flag.p, 1);
     GP_HIP(ctx, hipGetLastError());
     ctx->have_forward = true;
     return GP_OK;
@@ -517,7 +571,7 @@ gp_status gp_backward_impl(gp_ctx ctx, const float* qx, const float* qy, const f
     Band B = ctx->band();
     if (ctx->n_tiles > 0) {
         GP_TIMED(ctx, "k_backward_query");
-        k_query_grad<false><<<(unsigned)ctx->n_tiles, kQueryTile, 0, st>>>(
+        k_query_grad<false><<<(unsigned)(ctx->n_tiles * kGradParts), kGradBlock, 0, st>>>(
             B, qx, qy, qz, nn, ctx->ox.p, ctx->oy.p, ctx->oz.p, field, w, dloss, ctx->inv_qv.p, grad, nullptr,
             ctx->flag.p);
     }
@@ -538,7 +592,7 @@ gp_status gp_forward_backward_impl(gp_ctx ctx, const float* qx, const float* qy,
     Band B = ctx->band();
     if (ctx->n_tiles > 0) {
         GP_TIMED(ctx, "k_query_grad");
-        k_query_grad<true><<<(unsigned)ctx->n_tiles, kQueryTile, 0, st>>>(
+        k_query_grad<true><<<(unsigned)(ctx->n_tiles * kGradParts), kGradBlock, 0, st>>>(
             B, qx, qy, qz, nn, ctx->ox.p, ctx->oy.p, ctx->oz.p, field, w, dloss, ctx->inv_qv.p, ctx->g_raw.p,
             ctx->q_part.p, ctx->flag.p);
     }
@@ -549,7 +603,7 @@ gp_status gp_forward_backward_impl(gp_ctx ctx, const float* qx, const float* qy,
     {
         GP_TIMED(ctx, "k_finalize");
         k_finalize<<<(unsigned)ctx->n_shapes, 256, 0, st>>>(B, ctx->q_part.p, ctx->tv_part.p, w, loss_out,
-                                                            n_valid_out, ctx->inv_qv.p, ctx->flag.p);
+                                                            n_valid_out, ctx->inv_qv.p, ctx->flag.p, kGradParts);
     }
     if (ctx->n_bricks > 0) {
         GP_TIMED(ctx, "k_tv_backward");
