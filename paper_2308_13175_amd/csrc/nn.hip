@@ -244,10 +244,11 @@ __device__ inline void eval_chunk(const float4* __restrict__ buf, int32_t cnt, S
         const float4 p = buf[t];
         const float dx = q.x - p.x, dy = q.y - p.y, dz = q.z - p.z;
         const float d2f = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+        // (b1 <= b2: the second smallest of b1, b2, d2f is their median)
         const bool lt = d2f < b1;
-        b2 = lt ? b1 : fminf(b2, d2f);
+        b2 = __builtin_amdgcn_fmed3f(b1, b2, d2f);
         id = lt ? __float_as_int(p.w) : id;
-        b1 = lt ? d2f : b1;
+        b1 = fminf(b1, d2f);
     }
     q.best1 = b1;
     q.best2 = b2;
@@ -340,7 +341,7 @@ struct Tail {
                 float d = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
                 d = ok ? d : __builtin_inff();
                 const bool lt = d < b1[k];
-                b2[k] = fminf(b2[k], fmaxf(b1[k], d));
+                b2[k] = __builtin_amdgcn_fmed3f(b1[k], b2[k], d);
                 id[k] = lt ? __float_as_int(p.w) : id[k];
                 b1[k] = fminf(b1[k], d);
             }

@@ -403,124 +403,195 @@ __global__ __launch_bounds__(kGradBlock) void k_query_grad(Band B, const float* 
     }
 }
 
-// Slot of vertex (i,j,k) of shape s, or -1 outside the grid or the bricks.
-__device__ inline int32_t vertex_slot(const Band& B, const ShapeDesc& s, int32_t own, const BrickInfo& bi, int32_t i,
-                                      int32_t j, int32_t k)
+// ---- TV (Eq. 5): one block per brick, one thread per vertex.  The brick's
+// field values (and in the backward its tau) are staged in LDS with a halo of
+// one vertex across each face, together with a flag for TV vertices (vertices
+// of an absent brick or outside the grid are not TV vertices).
+
+constexpr int kHalo = kBrick + 2;                        // staged vertices per axis
+constexpr int kHaloVol = kHalo * kHalo * kHalo;
+
+__device__ inline int32_t halo_index(int32_t i, int32_t j, int32_t k)   // brick-local, -1..8
 {
-    if (i < 0 || j < 0 || k < 0 || i > s.R[0] || j > s.R[1] || k > s.R[2]) return -1;
-    const int32_t bx = i >> 3, by = j >> 3, bz = k >> 3;
-    const int32_t br = (bx == bi.bx && by == bi.by && bz == bi.bz) ? own : brick_of(B, s, bx, by, bz);
-    if (br < 0) return -1;
-    return br * kBrickVol + local_index(i, j, k);
+    return ((i + 1) * kHalo + (j + 1)) * kHalo + (k + 1);
 }
 
-__device__ inline bool is_tv(const Band& B, int32_t slot)
+// Stage values of one or two slot arrays (a, b may be null) and the TV flags.
+__device__ inline void stage_brick(const Band& B, const ShapeDesc& s, int32_t brick, const BrickInfo& bi,
+                                   const float* __restrict__ a, const float* __restrict__ b, float* sa, float* sb,
+                                   uint8_t* tv)
 {
-    return slot >= 0 && mask_bit(B.m_v2, slot / kBrickVol, slot % kBrickVol);
+    const int t = threadIdx.x;   // 0 .. 511: the brick's own vertex t
+    {
+        const int32_t li = t >> 6, lj = (t >> 3) & 7, lk = t & 7;
+        const int32_t h = halo_index(li, lj, lk);
+        const int32_t slot = brick * kBrickVol + t;
+        sa[h] = a[slot];
+        if (b) sb[h] = b[slot];
+        tv[h] = (uint8_t)mask_bit(B.m_v2, brick, t);
+    }
+    if (t < 6 * 64) {
+        // face f: axis f / 2, side -1 (even f) or +1 (odd f); 64 vertices each
+        const int f = t >> 6, w = t & 63, axis = f >> 1, side = (f & 1) ? 1 : -1;
+        int32_t l[3];
+        l[axis] = side > 0 ? kBrick : -1;
+        l[(axis + 1) % 3] = w >> 3;
+        l[(axis + 2) % 3] = w & 7;
+        const int32_t gi = bi.bx * kBrick + l[0], gj = bi.by * kBrick + l[1], gk = bi.bz * kBrick + l[2];
+        const int32_t h = halo_index(l[0], l[1], l[2]);
+        float va = 0.f, vb = 0.f;
+        uint8_t flag = 0;
+        if (gi >= 0 && gj >= 0 && gk >= 0 && gi <= s.R[0] && gj <= s.R[1] && gk <= s.R[2]) {
+            const int32_t nb = brick_of(B, s, gi >> 3, gj >> 3, gk >> 3);
+            if (nb >= 0) {
+                const int32_t loc = local_index(gi, gj, gk);
+                const int32_t slot = nb * kBrickVol + loc;
+                va = a[slot];
+                if (b) vb = b[slot];
+                flag = (uint8_t)mask_bit(B.m_v2, nb, loc);
+            }
+        }
+        sa[h] = va;
+        if (b) sb[h] = vb;
+        tv[h] = flag;
+    }
 }
 
-__global__ __launch_bounds__(256) void k_tv_forward(Band B, const float* __restrict__ D, float* __restrict__ tau,
-                                                    double* __restrict__ tv_part)
+__global__ __launch_bounds__(kBrickVol) void k_tv_forward(Band B, const float* __restrict__ D, float* __restrict__ tau,
+                                                          double* __restrict__ tv_part)
 {
-    __shared__ double lds[4];
+    __shared__ float s_d[kHaloVol];
+    __shared__ uint8_t s_tv[kHaloVol];
+    __shared__ double lds[kBrickVol / 64];
     const int32_t brick = blockIdx.x;
     const BrickInfo bi = B.bricks[brick];
     const ShapeDesc& s = B.shapes[bi.shape];
-    float acc = 0.f;
-    for (int local = threadIdx.x; local < kBrickVol; local += blockDim.x) {
-        const int32_t slot = brick * kBrickVol + local;
-        if (!mask_bit(B.m_v2, brick, local)) continue;
-        const int32_t i = bi.bx * kBrick + (local >> 6), j = bi.by * kBrick + ((local >> 3) & 7),
-                      k = bi.bz * kBrick + (local & 7);
-        const float dv = D[slot];
-        const int32_t nb[6] = {vertex_slot(B, s, brick, bi, i + 1, j, k), vertex_slot(B, s, brick, bi, i - 1, j, k),
-                               vertex_slot(B, s, brick, bi, i, j + 1, k), vertex_slot(B, s, brick, bi, i, j - 1, k),
-                               vertex_slot(B, s, brick, bi, i, j, k + 1), vertex_slot(B, s, brick, bi, i, j, k - 1)};
+    stage_brick(B, s, brick, bi, D, nullptr, s_d, nullptr, s_tv);
+    __syncthreads();
+    const int t = threadIdx.x;
+    const int32_t li = t >> 6, lj = (t >> 3) & 7, lk = t & 7;
+    const int32_t h = halo_index(li, lj, lk);
+    float tau_v = 0.f;
+    if (s_tv[h]) {
+        const float dv = s_d[h];
+        const int32_t nbh[6] = {h + kHalo * kHalo, h - kHalo * kHalo, h + kHalo, h - kHalo, h + 1, h - 1};
         float s2 = 0.f;
 #pragma unroll
         for (int o = 0; o < 6; ++o) {
-            if (!is_tv(B, nb[o])) continue;
-            const float d = dv - D[nb[o]];
+            if (!s_tv[nbh[o]]) continue;
+            const float d = dv - s_d[nbh[o]];
             s2 = fmaf(d, d, s2);
         }
-        const float t = sqrtf(s2);
-        tau[slot] = t;
-        acc += t;
+        tau_v = sqrtf(s2);
+        tau[brick * kBrickVol + t] = tau_v;
     }
-    double v[1] = {(double)acc};
-    block_sum<1>(v, lds);
-    if (threadIdx.x == 0) tv_part[brick] = v[0];
+    double v = (double)tau_v;
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    if ((t & 63) == 0) lds[t >> 6] = v;
+    __syncthreads();
+    if (t == 0) {
+        double a = 0.0;
+        for (int wv = 0; wv < kBrickVol / 64; ++wv) a += lds[wv];
+        tv_part[brick] = a;
+    }
 }
 
 // Gather form of the TV gradient (each vertex writes its own slot).  With
 // raw != nullptr the query contributions accumulated unscaled in raw are
 // added too, times dloss / valid count of the shape, and raw is cleared.
-__global__ __launch_bounds__(256) void k_tv_backward(Band B, const float* __restrict__ D,
-                                                     const float* __restrict__ tau, gp_weights w,
-                                                     const double* __restrict__ dloss,
-                                                     const double* __restrict__ inv_qv, float* __restrict__ raw,
-                                                     float* __restrict__ G)
+__global__ __launch_bounds__(kBrickVol) void k_tv_backward(Band B, const float* __restrict__ D,
+                                                           const float* __restrict__ tau, gp_weights w,
+                                                           const double* __restrict__ dloss,
+                                                           const double* __restrict__ inv_qv,
+                                                           float* __restrict__ raw, float* __restrict__ G)
 {
+    __shared__ float s_d[kHaloVol], s_t[kHaloVol];
+    __shared__ uint8_t s_tv[kHaloVol];
     const int32_t brick = blockIdx.x;
     const BrickInfo bi = B.bricks[brick];
     const ShapeDesc& s = B.shapes[bi.shape];
     const bool tv_on = s.n_tv > 0;
+    if (tv_on) stage_brick(B, s, brick, bi, D, tau, s_d, s_t, s_tv);
+    __syncthreads();
     const float scale = tv_on ? (float)((double)w.alpha * dloss[bi.shape] / (double)s.n_tv) : 0.f;
     const float rscale = raw ? (float)(dloss[bi.shape] * inv_qv[bi.shape]) : 0.f;
-    for (int local = threadIdx.x; local < kBrickVol; local += blockDim.x) {
-        const int32_t slot = brick * kBrickVol + local;
-        float add = 0.f;
-        bool touch = false;
-        if (raw) {
-            const float r = raw[slot];
-            if (r != 0.f) {
-                add = rscale * r;
-                raw[slot] = 0.f;
-                touch = true;
-            }
-        }
-        if (tv_on && mask_bit(B.m_v2, brick, local)) {
-            const int32_t i = bi.bx * kBrick + (local >> 6), j = bi.by * kBrick + ((local >> 3) & 7),
-                          k = bi.bz * kBrick + (local & 7);
-            const float dv = D[slot];
-            const float tv = tau[slot];
-            const float inv_tv = tv > 0.f ? 1.f / tv : 0.f;
-            const int32_t nb[6] = {vertex_slot(B, s, brick, bi, i + 1, j, k), vertex_slot(B, s, brick, bi, i - 1, j, k),
-                                   vertex_slot(B, s, brick, bi, i, j + 1, k), vertex_slot(B, s, brick, bi, i, j - 1, k),
-                                   vertex_slot(B, s, brick, bi, i, j, k + 1), vertex_slot(B, s, brick, bi, i, j, k - 1)};
-            float acc = 0.f;
-#pragma unroll
-            for (int o = 0; o < 6; ++o) {
-                if (!is_tv(B, nb[o])) continue;
-                const float d = dv - D[nb[o]];
-                const float tj = tau[nb[o]];
-                const float inv_tj = tj > 0.f ? 1.f / tj : 0.f;
-                acc = fmaf(d, inv_tv + inv_tj, acc);
-            }
-            add = fmaf(scale, acc, add);
+    const int t = threadIdx.x;
+    const int32_t slot = brick * kBrickVol + t;
+    float add = 0.f;
+    bool touch = false;
+    if (raw) {
+        const float r = raw[slot];
+        if (r != 0.f) {
+            add = rscale * r;
+            raw[slot] = 0.f;
             touch = true;
         }
-        if (touch) G[slot] += add;
     }
+    const int32_t li = t >> 6, lj = (t >> 3) & 7, lk = t & 7;
+    const int32_t h = halo_index(li, lj, lk);
+    if (tv_on && s_tv[h]) {
+        const float dv = s_d[h];
+        const float tv = s_t[h];
+        const float inv_tv = tv > 0.f ? 1.f / tv : 0.f;
+        const int32_t nbh[6] = {h + kHalo * kHalo, h - kHalo * kHalo, h + kHalo, h - kHalo, h + 1, h - 1};
+        float acc = 0.f;
+#pragma unroll
+        for (int o = 0; o < 6; ++o) {
+            if (!s_tv[nbh[o]]) continue;
+            const float d = dv - s_d[nbh[o]];
+            const float tj = s_t[nbh[o]];
+            const float inv_tj = tj > 0.f ? 1.f / tj : 0.f;
+            acc = fmaf(d, inv_tv + inv_tj, acc);
+        }
+        add = fmaf(scale, acc, add);
+        touch = true;
+    }
+    if (touch) G[slot] += add;
 }
 
 // One block per shape: deterministic sums of the tile and brick partials.
-__global__ __launch_bounds__(256) void k_finalize(Band B, const double* __restrict__ q_part,
-                                                  const double* __restrict__ tv_part, gp_weights w,
-                                                  double* __restrict__ loss_out, int64_t* __restrict__ n_valid_out,
-                                                  double* __restrict__ inv_qv, int32_t* __restrict__ flag,
-                                                  int32_t parts)
+// The tile partials of a shape are contiguous (4 doubles per entry); each
+// thread reads pairs of them with a fixed stride, so it always adds to the
+// same two of the four sums.
+constexpr int kFinalizeBlock = 1024;
+
+__global__ __launch_bounds__(kFinalizeBlock) void k_finalize(Band B, const double* __restrict__ q_part,
+                                                             const double* __restrict__ tv_part, gp_weights w,
+                                                             double* __restrict__ loss_out,
+                                                             int64_t* __restrict__ n_valid_out,
+                                                             double* __restrict__ inv_qv, int32_t* __restrict__ flag,
+                                                             int32_t parts)
 {
-    __shared__ double lds[4 * 5];
+    __shared__ double lds[kFinalizeBlock / 64 * 5];
     const int32_t shape = blockIdx.x;
     const ShapeDesc& s = B.shapes[shape];
     double v[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-    // q_part holds `parts` partial sums per tile
-    for (int64_t t = s.tile_begin * parts + threadIdx.x; t < s.tile_end * parts; t += blockDim.x)
-        for (int i = 0; i < 4; ++i) v[i] += q_part[t * 4 + i];
+    // q_part holds `parts` partial sums per tile, 4 doubles each
+    const double2* qp = reinterpret_cast<const double2*>(q_part);
+    const int64_t pb = s.tile_begin * parts * 2, pe = s.tile_end * parts * 2;
+    const int hi = threadIdx.x & 1;   // (kFinalizeBlock is even: a thread's pairs are all low or all high)
+    double a0 = 0.0, a1 = 0.0;
+    for (int64_t m = pb + threadIdx.x; m < pe; m += blockDim.x) {
+        const double2 d = qp[m];
+        a0 += d.x;
+        a1 += d.y;
+    }
+    v[2 * hi] = a0;
+    v[2 * hi + 1] = a1;
     for (int64_t b = s.brick_begin + threadIdx.x; b < s.brick_end; b += blockDim.x) v[4] += tv_part[b];
-    block_sum<5>(v, lds);
+#pragma unroll
+    for (int i = 0; i < 5; ++i)
+        for (int o = 32; o > 0; o >>= 1) v[i] += __shfl_xor(v[i], o, 64);
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (lane == 0)
+        for (int i = 0; i < 5; ++i) lds[wave * 5 + i] = v[i];
+    __syncthreads();
     if (threadIdx.x == 0) {
+        for (int i = 0; i < 5; ++i) {
+            double a = 0.0;
+            for (int wv = 0; wv < kFinalizeBlock / 64; ++wv) a += lds[wv * 5 + i];
+            v[i] = a;
+        }
         const double nq = v[3];
         const double iq = nq > 0.0 ? 1.0 / nq : 0.0;
         const double pull = v[0] * iq, surf = v[1] * iq, grad = v[2] * iq;
@@ -554,10 +625,10 @@ gp_status gp_forward_impl(gp_ctx ctx, const float* qx, const float* qy, const fl
     }
     if (ctx->n_bricks > 0) {
         GP_TIMED(ctx, "k_tv_forward");
-        k_tv_forward<<<(unsigned)ctx->n_bricks, 256, 0, st>>>(B, field, ctx->tau.p, ctx->tv_part.p);
+        k_tv_forward<<<(unsigned)ctx->n_bricks, kBrickVol, 0, st>>>(B, field, ctx->tau.p, ctx->tv_part.p);
     }
     GP_TIMED(ctx, "k_finalize");
-    k_finalize<<<(unsigned)ctx->n_shapes, 256, 0, st>>>(B, ctx->q_part.p, ctx->tv_part.p, w, loss_out, n_valid_out,
+    k_finalize<<<(unsigned)ctx->n_shapes, kFinalizeBlock, 0, st>>>(B, ctx->q_part.p, ctx->tv_part.p, w, loss_out, n_valid_out,
                                                         ctx->inv_qv.p, ctx->flag.p, 1);
     GP_HIP(ctx, hipGetLastError());
     ctx->have_forward = true;
@@ -577,7 +648,7 @@ gp_status gp_backward_impl(gp_ctx ctx, const float* qx, const float* qy, const f
     }
     if (ctx->n_bricks > 0) {
         GP_TIMED(ctx, "k_tv_backward");
-        k_tv_backward<<<(unsigned)ctx->n_bricks, 256, 0, st>>>(B, field, ctx->tau.p, w, dloss, ctx->inv_qv.p,
+        k_tv_backward<<<(unsigned)ctx->n_bricks, kBrickVol, 0, st>>>(B, field, ctx->tau.p, w, dloss, ctx->inv_qv.p,
                                                                nullptr, grad);
     }
     GP_HIP(ctx, hipGetLastError());
@@ -598,16 +669,16 @@ gp_status gp_forward_backward_impl(gp_ctx ctx, const float* qx, const float* qy,
     }
     if (ctx->n_bricks > 0) {
         GP_TIMED(ctx, "k_tv_forward");
-        k_tv_forward<<<(unsigned)ctx->n_bricks, 256, 0, st>>>(B, field, ctx->tau.p, ctx->tv_part.p);
+        k_tv_forward<<<(unsigned)ctx->n_bricks, kBrickVol, 0, st>>>(B, field, ctx->tau.p, ctx->tv_part.p);
     }
     {
         GP_TIMED(ctx, "k_finalize");
-        k_finalize<<<(unsigned)ctx->n_shapes, 256, 0, st>>>(B, ctx->q_part.p, ctx->tv_part.p, w, loss_out,
+        k_finalize<<<(unsigned)ctx->n_shapes, kFinalizeBlock, 0, st>>>(B, ctx->q_part.p, ctx->tv_part.p, w, loss_out,
                                                             n_valid_out, ctx->inv_qv.p, ctx->flag.p, kGradParts);
     }
     if (ctx->n_bricks > 0) {
         GP_TIMED(ctx, "k_tv_backward");
-        k_tv_backward<<<(unsigned)ctx->n_bricks, 256, 0, st>>>(B, field, ctx->tau.p, w, dloss, ctx->inv_qv.p,
+        k_tv_backward<<<(unsigned)ctx->n_bricks, kBrickVol, 0, st>>>(B, field, ctx->tau.p, w, dloss, ctx->inv_qv.p,
                                                                ctx->g_raw.p, grad);
     }
     GP_HIP(ctx, hipGetLastError());
