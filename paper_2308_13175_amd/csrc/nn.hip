@@ -416,27 +416,55 @@ __device__ inline void stage_range(const Band& B, const ShapeDesc& s, const Glob
 }
 
 // Stage every cell of box [lo, hi] outside box [olo, ohi] (which may be
-// empty), rows (x, y) one per lane, and scan them all.
+// empty), rows (x, y) one per lane, and scan them all.  With balls (x, y, z,
+// r^2; a negative r^2 is an unused place), a column is taken only where it
+// comes within r of one of the nb ball centres, and only the cells meeting
+// the union of those chords.
 template <class Ev>
 __device__ inline void scan_box(const Band& B, const ShapeDesc& s, const Global& G, int4* __restrict__ runs, Ev& ev,
-                                const int32_t lo[3], const int32_t hi[3], const int32_t olo[3], const int32_t ohi[3])
+                                const int32_t lo[3], const int32_t hi[3], const int32_t olo[3], const int32_t ohi[3],
+                                const float4* balls = nullptr, int32_t nb = 0)
 {
     const int lane = threadIdx.x & 63;
     if (lo[0] > hi[0] || lo[1] > hi[1] || lo[2] > hi[2]) return;
     int32_t n = 0;
     const int32_t ny = hi[1] - lo[1] + 1;
     const int32_t nrows = (hi[0] - lo[0] + 1) * ny;
+    const float lo0 = (float)s.lo[0], lo1 = (float)s.lo[1], lo2 = (float)s.lo[2];
+    const float ih2 = (float)s.inv_h[2];
     for (int32_t base = 0; base < nrows; base += 64) {
         const int32_t r = base + lane;
-        const bool row = r < nrows;
+        bool row = r < nrows;
         const int32_t x = lo[0] + (row ? r / ny : 0);
         const int32_t y = lo[1] + (row ? r % ny : 0);
+        int32_t za = lo[2], zb = hi[2];
+        if (balls) {
+            const float xl = fmaf((float)x, s.h[0], lo0), yl = fmaf((float)y, s.h[1], lo1);
+            const float mx = 1e-3f * s.h[0], my = 1e-3f * s.h[1];
+            int32_t zlo = 0x7fffffff, zhi = -1;
+            for (int k = 0; k < nb; ++k) {
+                const float4 t = balls[k];
+                const float gx = fmaxf(fmaxf(xl - t.x, t.x - (xl + s.h[0])) - mx, 0.f);
+                const float gy = fmaxf(fmaxf(yl - t.y, t.y - (yl + s.h[1])) - my, 0.f);
+                const float lxy = fmaf(gx, gx, gy * gy);
+                if (lxy <= t.w) {
+                    const float rz = sqrtf(t.w - lxy) + 1e-3f * s.h[2];
+                    const float ua = fminf(fmaxf((t.z - rz - lo2) * ih2, -1.f), 1e8f);
+                    const float ub = fminf(fmaxf((t.z + rz - lo2) * ih2, -1.f), 1e8f);
+                    zlo = min(zlo, (int32_t)floorf(ua));
+                    zhi = max(zhi, (int32_t)floorf(ub));
+                }
+            }
+            za = max(za, zlo);
+            zb = min(zb, zhi);
+        }
+        if (!row) zb = -1;
         const bool inner = x >= olo[0] && x <= ohi[0] && y >= olo[1] && y <= ohi[1];
-        int32_t za = lo[2], zb = row ? hi[2] : -1, zc = 0, zd = -1;
+        int32_t zc = 0, zd = -1;
         if (row && inner) {
-            zb = min(hi[2], olo[2] - 1);
-            zc = max(lo[2], ohi[2] + 1);
-            zd = hi[2];
+            zc = max(za, ohi[2] + 1);
+            zd = zb;
+            zb = min(zb, olo[2] - 1);
         }
         stage_range(B, s, G, runs, n, ev, x, y, za, zb);
         stage_range(B, s, G, runs, n, ev, x, y, zc, zd);
@@ -644,7 +672,7 @@ __global__ __launch_bounds__(kQueryBlock, 4) void k_nn(Band B, Global G, const f
                     pend &= pend - 1;
                 }
                 const bool inb = (batch >> lane) & 1;
-                if (inb) tq[lane_rank(batch)] = make_float4(q.x, q.y, q.z, 0.f);
+                if (inb) tq[lane_rank(batch)] = make_float4(q.x, q.y, q.z, q.best1 * (1.f + 4e-5f) + 1e-30f);
                 int32_t reg[6];
                 for (int a = 0; a < 6; ++a) reg[a] = inb ? ball[a] : (a < 3 ? 0x7fffffff : -1);
                 wave_minmax6(reg);
@@ -657,7 +685,7 @@ __global__ __launch_bounds__(kQueryBlock, 4) void k_nn(Band B, Global G, const f
                     ev.b1[t] = ev.b2[t] = __builtin_inff();
                     ev.id[t] = -1;
                 }
-                scan_box(B, s, G, runs, ev, reg, reg + 3, lo, hi);
+                scan_box(B, s, G, runs, ev, reg, reg + 3, lo, hi, tq, ev.ns);
                 // reduce every slot over the wave and merge it into its lane
                 uint64_t own = batch;
 #pragma unroll
