@@ -504,12 +504,10 @@ gp_status gp_build_band_impl(gp_ctx ctx, const gp_shape* shapes, int32_t n_shape
         ctx->tau.alloc((size_t)std::max<int64_t>(n_slots, 1)) != hipSuccess ||
         ctx->inv_qv.alloc(n_shapes) != hipSuccess || ctx->flag.alloc(1) != hipSuccess ||
         ctx->iter.alloc(1) != hipSuccess || ctx->step_c.alloc(2) != hipSuccess ||
-        ctx->nn_tune.alloc(3 * (size_t)n_shapes) != hipSuccess ||
         ctx->g_raw.alloc((size_t)std::max<int64_t>(n_slots, 1)) != hipSuccess)
         return gp_fail(ctx, GP_ERR_OOM, "out of device memory for the iteration scratch");
     GP_HIP(ctx, hipMemsetAsync(ctx->flag.p, 0, 4, st));
     GP_HIP(ctx, hipMemsetAsync(ctx->iter.p, 0, 4, st));
-    GP_HIP(ctx, hipMemsetAsync(ctx->nn_tune.p, 0, 12 * (size_t)n_shapes, st));
     GP_HIP(ctx, hipMemsetAsync(ctx->tau.p, 0, std::max<int64_t>(n_slots, 1) * 4, st));
     GP_HIP(ctx, hipMemsetAsync(ctx->g_raw.p, 0, std::max<int64_t>(n_slots, 1) * 4, st));
 

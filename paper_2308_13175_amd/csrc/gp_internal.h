@@ -274,7 +274,6 @@ struct gp_ctx_s {
     DevBuf<int32_t> iter;         // device-resident iteration counter (last Adam t)
     DevBuf<float> step_c;         // [2] lr_t / (1 - beta1^t), 1 / sqrt(1 - beta2^t)
     DevBuf<float> g_raw;          // [n_slots] unscaled query contributions of a fused pass (kept zero between passes)
-    DevBuf<uint32_t> nn_tune;     // [n_shapes][3] extra box growth, queries searched, queries left to the ball pass
     bool have_forward = false;
 
     // optional per-kernel timing with events on the context's stream

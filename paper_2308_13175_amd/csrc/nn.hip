@@ -39,8 +39,7 @@
 namespace gp {
 namespace {
 
-constexpr int kNnFirstShell = 1;  // growth of the group's box scanned in lockstep (per shape one more
-                                   // while many queries need the ball pass, see k_nn_tune)
+constexpr int kNnFirstShell = 1;  // growth of the group's box scanned in lockstep
 constexpr int kNnMaxGrow = 8;     // growth beyond which a group with no point in its box goes to the ring search
 constexpr int kNnGroupCap = 8;     // a group's query cells span fewer than this many cells per axis
 
@@ -492,7 +491,7 @@ constexpr int kWaveSpan = kQueryTile / kWaves;   // sorted positions grouped and
 
 __global__ __launch_bounds__(kQueryBlock, 4) void k_nn(Band B, Global G, const float* __restrict__ qx,
                                                     const float* __restrict__ qy, const float* __restrict__ qz,
-                                                    int32_t* __restrict__ nn, uint32_t* __restrict__ tune)
+                                                    int32_t* __restrict__ nn)
 {
     __shared__ typename BlockSort::TempStorage sort_tmp;
     __shared__ int16_t s_order[kQueryTile];
@@ -593,8 +592,6 @@ __global__ __launch_bounds__(kQueryBlock, 4) void k_nn(Band B, Global G, const f
 
     const float inv_h[3] = {1.f / s.h[0], 1.f / s.h[1], 1.f / s.h[2]};
     float4* tq = s_tq[wave];
-    const int32_t first = kNnFirstShell + (int32_t)tune[3 * shape];
-    uint32_t n_live = 0, n_ball = 0;    // this wave's queries, and those left to the ball pass
     for (int32_t gi = 0; gi < ngroups; ++gi) {
         const int32_t pos = s_group[wave][gi] + lane;
         const bool live = pos < s_group[wave][gi + 1];
@@ -621,7 +618,7 @@ __global__ __launch_bounds__(kQueryBlock, 4) void k_nn(Band B, Global G, const f
             int32_t lo[3], hi[3];
             {
                 int32_t olo[3] = {0, 0, 0}, ohi[3] = {-1, -1, -1};
-                for (int e = first;; ++e) {
+                for (int e = kNnFirstShell;; ++e) {
                     for (int a = 0; a < 3; ++a) {
                         lo[a] = max(wb[a] - e, 0);
                         hi[a] = min(wb[3 + a] + e, s.R[a] - 1);
@@ -663,8 +660,6 @@ __global__ __launch_bounds__(kQueryBlock, 4) void k_nn(Band B, Global G, const f
                 }
             }
             uint64_t pend = __ballot(tail);
-            n_live += __popcll(__ballot(live));
-            n_ball += __popcll(pend);
             while (pend != 0) {
                 uint64_t batch = 0;
                 for (int t = 0; t < kTail && pend != 0; ++t) {
@@ -710,29 +705,6 @@ __global__ __launch_bounds__(kQueryBlock, 4) void k_nn(Band B, Global G, const f
         if (!live) continue;
         nn[k] = (s.point_cnt > 0 && !q.open) ? q.id1 : search(B, s, G, q.x, q.y, q.z);
     }
-    if (lane == 0 && n_live > 0) {
-        atomicAdd(&tune[3 * shape + 1], n_live);
-        atomicAdd(&tune[3 * shape + 2], n_ball);
-    }
-}
-
-// Per shape, after a search: scan one more cell around the groups in the
-// lockstep pass while more than a fifth of the queries still need the ball
-// pass, one less once fewer than one in twenty do.  Only the amount of work
-// depends on it; the results do not.
-__global__ void k_nn_tune(uint32_t* __restrict__ tune, int32_t n_shapes)
-{
-    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n_shapes) return;
-    uint32_t extra = tune[3 * i];
-    const uint32_t live = tune[3 * i + 1], ball = tune[3 * i + 2];
-    if (live > 0) {
-        if (extra == 0 && (uint64_t)ball * 5 > live) extra = 1;
-        else if (extra == 1 && (uint64_t)ball * 20 < live) extra = 0;
-    }
-    tune[3 * i] = extra;
-    tune[3 * i + 1] = 0;
-    tune[3 * i + 2] = 0;
 }
 
 }  // namespace
@@ -744,13 +716,8 @@ gp_status gp_nn_impl(gp_ctx ctx, const float* qx, const float* qy, const float* 
 {
     if (ctx->n_tiles == 0) return GP_OK;
     Global G{ctx->cell_start.p, ctx->spts.p};
-    {
-        GP_TIMED(ctx, "k_nn");
-        k_nn<<<(unsigned)ctx->n_tiles, kQueryBlock, 0, ctx->stream>>>(ctx->band(), G, qx, qy, qz, nn,
-                                                                      ctx->nn_tune.p);
-        GP_HIP(ctx, hipGetLastError());
-    }
-    k_nn_tune<<<(unsigned)((ctx->n_shapes + 63) / 64), 64, 0, ctx->stream>>>(ctx->nn_tune.p, ctx->n_shapes);
+    GP_TIMED(ctx, "k_nn");
+    k_nn<<<(unsigned)ctx->n_tiles, kQueryBlock, 0, ctx->stream>>>(ctx->band(), G, qx, qy, qz, nn);
     GP_HIP(ctx, hipGetLastError());
     return GP_OK;
 }
