@@ -541,7 +541,11 @@ __global__ __launch_bounds__(kQueryBlock, 4) void k_nn(Band B, Global G, const f
                      (spread3((uint32_t)min(cells[j][1] - box[1], 1023)) << 1) |
                      (spread3((uint32_t)min(cells[j][2] - box[2], 1023)) << 2);
     }
-    BlockSort(sort_tmp).Sort(key, val);
+    // only the bits the tile's cell box needs (3 per axis per doubling of its span)
+    int32_t span = 1;
+    for (int a = 0; a < 3; ++a) span = max(span, box[3 + a] - box[a] + 1);
+    const int32_t bits = min(3 * (32 - __builtin_clz((uint32_t)span - 1u | 1u)), 30);
+    BlockSort(sort_tmp).Sort(key, val, 0, bits);
 #pragma unroll
     for (int j = 0; j < kQueriesPerThread; ++j) {
         const int32_t pos = threadIdx.x * kQueriesPerThread + j;

@@ -167,7 +167,7 @@ constexpr int kGradBlock = kQueryTile / kGradParts;    // one query per thread
 // so no sum can leave the range of the fixed point; so do the contributions
 // of octants beyond the cache's capacity.
 constexpr int kOctVol = 64;                       // vertices per octant
-constexpr int kCacheOcts = 96;                    // LDS octant accumulators per block (96 x 512 B)
+constexpr int kCacheOcts = 72;                    // LDS octant accumulators per block (72 x 512 B)
 constexpr int kCacheTable = 256;                  // open-addressing table: octant key -> LDS octant
 constexpr double kFixScale = 4294967296.0;        // 2^32
 constexpr float kFixLimit = 1048576.f;            // 2^20
