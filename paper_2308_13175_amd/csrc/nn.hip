@@ -254,50 +254,39 @@ __device__ inline void eval_chunk(const float4* __restrict__ buf, int32_t cnt, S
     q.id1 = id;
 }
 
-// Smallest and second-smallest value (and the argmin, ties to the lower id)
-// of (b1, b2, id) triples: merge the partner's triple into this one.
-__device__ inline void merge_min2(float& b1, float& b2, int32_t& id, float ob1, float ob2, int32_t oid)
-{
-    b2 = fminf(fminf(b2, ob2), fmaxf(b1, ob1));
-    id = (ob1 < b1 || (ob1 == b1 && oid < id)) ? oid : id;
-    b1 = fminf(b1, ob1);
-}
-
 template <int Ctrl>
-__device__ inline int32_t dpp(int32_t v)
+__device__ inline uint32_t dpp_u(uint32_t v)
 {
-    return __builtin_amdgcn_update_dpp(v, v, Ctrl, 0xf, 0xf, false);
+    return (uint32_t)__builtin_amdgcn_update_dpp((int32_t)v, (int32_t)v, Ctrl, 0xf, 0xf, false);
 }
 
-template <int Ctrl>
-__device__ inline void dpp_merge(float& b1, float& b2, int32_t& id)
+// Wave-wide minimum of non-negative floats (their bits order as integers).
+__device__ inline float wave_min_pos(float v)
 {
-    const float ob1 = __int_as_float(dpp<Ctrl>(__float_as_int(b1)));
-    const float ob2 = __int_as_float(dpp<Ctrl>(__float_as_int(b2)));
-    const int32_t oid = dpp<Ctrl>(id);
-    merge_min2(b1, b2, id, ob1, ob2, oid);
+    uint32_t u = __float_as_uint(v);
+    u = min(u, dpp_u<0xB1>(u));    // quad_perm [1, 0, 3, 2]
+    u = min(u, dpp_u<0x4E>(u));    // quad_perm [2, 3, 0, 1]
+    u = min(u, dpp_u<0x141>(u));   // row_half_mirror
+    u = min(u, dpp_u<0x140>(u));   // row_mirror
+    u = min(min((uint32_t)__builtin_amdgcn_readlane((int32_t)u, 0), (uint32_t)__builtin_amdgcn_readlane((int32_t)u, 16)),
+            min((uint32_t)__builtin_amdgcn_readlane((int32_t)u, 32), (uint32_t)__builtin_amdgcn_readlane((int32_t)u, 48)));
+    return __uint_as_float(u);
 }
 
-// Wave-wide merge of every lane's triple; the result is returned in all lanes.
-// Within each row of 16 lanes: swap neighbours, pairs, then mirror the half
-// row and the row (DPP); the four rows are then combined from their lane 0.
-__device__ inline void wave_min2(float& b1, float& b2, int32_t& id)
+// Smallest and second-smallest distance over the wave and an argmin: the
+// smallest of the lanes' b1; its lane; then the second smallest is the
+// smaller of that lane's b2 and every other lane's b1 (two lanes tying on
+// the smallest give b2 == b1, which never counts as unique).
+__device__ inline void wave_best2(float& b1, float& b2, int32_t& id)
 {
-    dpp_merge<0xB1>(b1, b2, id);    // quad_perm [1, 0, 3, 2]
-    dpp_merge<0x4E>(b1, b2, id);    // quad_perm [2, 3, 0, 1]
-    dpp_merge<0x141>(b1, b2, id);   // row_half_mirror
-    dpp_merge<0x140>(b1, b2, id);   // row_mirror
-    float r1 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(b1), 0));
-    float r2 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(b2), 0));
-    int32_t ri = __builtin_amdgcn_readlane(id, 0);
-#pragma unroll
-    for (int row = 1; row < 4; ++row)
-        merge_min2(r1, r2, ri, __int_as_float(__builtin_amdgcn_readlane(__float_as_int(b1), 16 * row)),
-                   __int_as_float(__builtin_amdgcn_readlane(__float_as_int(b2), 16 * row)),
-                   __builtin_amdgcn_readlane(id, 16 * row));
-    b1 = r1;
-    b2 = r2;
-    id = ri;
+    const float m = wave_min_pos(b1);
+    const uint64_t at = __ballot(b1 == m);
+    const int32_t lead = (int32_t)__builtin_ctzll(at);
+    const int lane = threadIdx.x & 63;
+    const float second = wave_min_pos(lane == lead ? b2 : b1);
+    id = __builtin_amdgcn_readlane(id, lead);
+    b1 = m;
+    b2 = second;
 }
 
 constexpr int kRunCap = 128;   // runs staged per wave (a batch of 64 plus one append round)
@@ -692,7 +681,7 @@ __global__ __launch_bounds__(kQueryBlock, 4) void k_nn(Band B, Global G, const f
                     if (t < ev.ns) {
                         float b1 = ev.b1[t], b2 = ev.b2[t];
                         int32_t id = ev.id[t];
-                        wave_min2(b1, b2, id);
+                        wave_best2(b1, b2, id);
                         const int32_t owner = __builtin_ctzll(own);
                         own &= own - 1;
                         if (lane == owner) {
