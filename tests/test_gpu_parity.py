@@ -248,3 +248,70 @@ def test_fused_forward_backward(m1, m2):
     g = prob.dense_grad()[0]
     assert np.abs(g - 2.5 * sep_grad).max() <= 1e-6 * 2.5 * np.abs(sep_grad).max()
     prob.close()
+
+
+def test_nn_exact_ties_and_distant_queries():
+    """Points on a lattice in shuffled index order, queries at lattice cube
+    centres and edge midpoints (8-way and 4-way exact ties: the lowest index
+    must win), queries on lattice points, and queries many cells away from
+    every point (the box grows to its limit, then the ring search)."""
+    log("case: exact ties and distant queries")
+    dom = synth.Domain((40, 40, 40), (-1.0, -1.0, -1.0), (1.0, 1.0, 1.0))
+    g = np.arange(-4, 5, dtype=np.float32) * np.float32(0.0625)      # lattice step 1/16, exact in float
+    lat = np.stack(np.meshgrid(g, g, g, indexing="ij"), -1).reshape(-1, 3)
+    rng = np.random.default_rng(3)
+    pts = lat[rng.permutation(len(lat))].astype(np.float32)
+    half = np.float32(0.03125)
+    centres = lat[(lat[:, 0] < g[-1]) & (lat[:, 1] < g[-1]) & (lat[:, 2] < g[-1])] + half
+    edges = lat[(lat[:, 0] < g[-1])] + np.array([half, 0, 0], np.float32)
+    far = np.array([[0.9, 0.9, 0.9], [-0.95, 0.9, -0.9], [0.0, 0.95, 0.0], [0.93, -0.97, 0.11]], np.float32)
+    q = np.concatenate([centres, edges, lat[:50], far]).astype(np.float32)
+    q = q[rng.permutation(len(q))]
+    D = synth.sphere_sdf_field(dom, 0.3, noise=0.02, seed=4)
+    prob = _run_gpu(dom, pts, q, D, 3, 3)
+    cf, vf, nn, ref = _oracle(dom, pts, q, D, 3, 3)
+    got_nn = prob.nn[: len(q)].cpu().numpy()
+    bad = np.nonzero(got_nn != nn)[0]
+    assert len(bad) == 0, "%d of %d differ, e.g. query %s: %d vs %d" % (len(bad), len(q), q[bad[0]], got_nn[bad[0]], nn[bad[0]])
+    got, nv = loss_terms(prob)
+    assert int(nv[0]) == ref["n_valid"]
+    assert_terms_close(got[0], ref)
+    assert_grad_close(prob.dense_grad()[0], ref["dD"])
+    prob.close()
+
+
+def test_batch_with_a_shape_without_queries_and_a_one_point_shape():
+    """A batch of three shapes: one with points but no queries, one with a
+    single point, one ordinary; every shape agrees with the oracle."""
+    log("case: batch with an empty query set and a one-point shape")
+    dom0 = synth.cube_domain(16)
+    dom1 = synth.Domain((20, 12, 16), (-0.5, -0.5, -0.5), (1.5, 0.7, 1.1))
+    dom2 = synth.cube_domain(24)
+    p0 = synth.sphere_points(300, 0.4, seed=50)
+    p1 = np.array([[0.25, 0.05, 0.3]], np.float32)
+    p2 = synth.sphere_points(900, 0.5, seed=51)
+    q1 = synth.host_queries(p1, 500, 0.15, seed=52)
+    q2 = synth.host_queries(p2, 4000, 0.05, seed=53)
+    D = [synth.sphere_sdf_field(d, 0.4, noise=0.01, seed=i) for i, d in enumerate((dom0, dom1, dom2))]
+    batch = make_problem([spec(p0, dom0, 0, 0.0), spec(p1, dom1, len(q1), 0.0), spec(p2, dom2, len(q2), 0.0)])
+    batch.set_dense_field(D)
+    batch.set_queries(np.concatenate([q1, q2]))
+    batch.nearest()
+    batch.forward()
+    batch.backward()
+    batch.sync()
+    bl, bn = loss_terms(batch)
+    bg = batch.dense_grad()
+    nn = batch.nn[: len(q1) + len(q2)].cpu().numpy()
+    assert np.all(nn[: len(q1)] == 0)
+    for i, (dom, pts, q) in enumerate(((dom0, p0, np.zeros((0, 3), np.float32)), (dom1, p1, q1), (dom2, p2, q2))):
+        cf, vf, onn, ref = _oracle(dom, pts, q, D[i])
+        if i == 2:
+            assert np.array_equal(nn[len(q1):], onn)
+        assert int(bn[i]) == ref["n_valid"]
+        assert_terms_close(bl[i], ref)
+        if np.abs(ref["dD"]).max() > 0:
+            assert_grad_close(bg[i], ref["dD"])
+        else:
+            assert np.abs(bg[i]).max() == 0.0
+    batch.close()
