@@ -257,6 +257,17 @@ gp_status gp_shape_slots(gp_ctx ctx, int64_t* slot_begin);
  * 8 = ... in the M2 band, 16 = ... holds a point. */
 gp_status gp_export_layout(gp_ctx ctx, int64_t* vertex_id_of_slot, uint8_t* slot_flags);
 
+/* Sorted linear ids, (cx*Ry + cy)*Rz + cz, of the M1-band cells of one shape
+ * (Sec. 3: the cells near the surface where queries are pulled; a query is
+ * valid iff its cell is one of them).  cell_ids: device int64 [capacity];
+ * *n_out (host) receives the number of cells.  When it exceeds capacity
+ * nothing is written and GP_ERR_CAPACITY is returned with *n_out set, so a
+ * call with capacity 0 asks for the size.  Synchronises with the context's
+ * stream; allocates temporary device memory (not for the hot loop).
+ * Errors: GP_ERR_ARG for a shape out of range or a null n_out. */
+gp_status gp_export_active_cells(gp_ctx ctx, int32_t shape, int64_t* cell_ids, int64_t capacity,
+                                 int64_t* n_out);
+
 /* field[slot] = dense[dense_off(s) + vertex id] for every slot (0 where the
  * slot has no vertex), where dense is the concatenation, in shape order, of
  * each shape's (R+1)^3 vertex values in x-major order.  Device arrays. */

@@ -305,6 +305,15 @@ gp_status gp_export_layout(gp_ctx ctx, int64_t* vertex_id_of_slot, uint8_t* slot
     return gp_layout_impl(ctx, vertex_id_of_slot, slot_flags);
 }
 
+gp_status gp_export_active_cells(gp_ctx ctx, int32_t shape, int64_t* cell_ids, int64_t capacity, int64_t* n_out)
+{
+    gp_status st = ready(ctx);
+    if (st != GP_OK) return st;
+    if (!n_out || shape < 0 || shape >= ctx->n_shapes || capacity < 0 || (capacity > 0 && !cell_ids))
+        return gp_fail(ctx, GP_ERR_ARG, "need a shape index in range, n_out, and cell_ids when capacity > 0");
+    return gp_active_cells_impl(ctx, shape, cell_ids, capacity, n_out);
+}
+
 gp_status gp_gather_vertices(gp_ctx ctx, const float* dense, float* field)
 {
     gp_status st = ready(ctx);

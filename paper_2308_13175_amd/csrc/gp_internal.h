@@ -345,5 +345,6 @@ gp_status gp_forward_backward_impl(gp_ctx ctx, const float* qx, const float* qy,
 gp_status gp_step_impl(gp_ctx ctx, float* field, float* grad, float* m, float* v, float beta1, float beta2,
                        float eps);
 gp_status gp_layout_impl(gp_ctx ctx, int64_t* vid, uint8_t* flags);
+gp_status gp_active_cells_impl(gp_ctx ctx, int32_t shape, int64_t* cell_ids, int64_t capacity, int64_t* n_out);
 gp_status gp_gather_impl(gp_ctx ctx, const float* dense, float* field, bool to_field);
 gp_status gp_init_sphere_impl(gp_ctx ctx, const double* centre, const double* radius, float* field);

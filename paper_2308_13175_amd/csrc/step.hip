@@ -1,6 +1,8 @@
 // Adam step over the field slots (Sec. 4 "Details": Adam with a stepwise
 // decayed learning rate; only band variables are optimised, Sec. 3) and the
 // layout helpers that convert between the brick slots and dense vertex ids.
+#include <hipcub/hipcub.hpp>
+
 #include "gp_internal.h"
 
 namespace gp {
@@ -89,6 +91,28 @@ __global__ void k_layout(Band B, const uint32_t* __restrict__ m_base, const uint
         }
     }
 }
+
+// Linear id of the M1-band cell whose lowest corner is each slot of one
+// shape's slot range, or -1.
+__global__ void k_active_cells(Band B, int64_t slot0, int64_t n, int64_t* __restrict__ ids)
+{
+    GRID_STRIDE(i, n)
+    {
+        const int64_t slot = slot0 + i;
+        int32_t shape, ijk[3];
+        int64_t id = -1;
+        if ((B.m_a1[slot >> 5] >> (slot & 31)) & 1u) {
+            slot_vertex(B, slot, shape, ijk);
+            const ShapeDesc& s = B.shapes[shape];
+            id = ((int64_t)ijk[0] * s.R[1] + ijk[1]) * s.R[2] + ijk[2];
+        }
+        ids[i] = id;
+    }
+}
+
+struct NonNegative {
+    __device__ bool operator()(const int64_t& v) const { return v >= 0; }
+};
 
 __global__ void k_gather(Band B, int64_t n_slots, const float* __restrict__ dense, float* __restrict__ field,
                          int to_field)
@@ -181,5 +205,40 @@ gp_status gp_init_sphere_impl(gp_ctx ctx, const double* centre, const double* ra
                                                                           field);
     GP_HIP(ctx, hipGetLastError());
     GP_HIP(ctx, hipStreamSynchronize(ctx->stream));   // the scratch is freed on return
+    return GP_OK;
+}
+
+gp_status gp_active_cells_impl(gp_ctx ctx, int32_t shape, int64_t* cell_ids, int64_t capacity, int64_t* n_out)
+{
+    const int64_t b = ctx->h_slot_begin[shape], e = ctx->h_slot_begin[shape + 1], n = e - b;
+    *n_out = 0;
+    if (n == 0) return GP_OK;
+    hipStream_t st = ctx->stream;
+    DevBuf<int64_t> ids, sel;
+    DevBuf<int64_t> cnt;
+    if (ids.alloc(n) != hipSuccess || sel.alloc(n) != hipSuccess || cnt.alloc(1) != hipSuccess)
+        return gp_fail(ctx, GP_ERR_OOM, "out of device memory for the cell export");
+    k_active_cells<<<blocks_for(n), kThreads, 0, st>>>(ctx->band(), b, n, ids.p);
+    GP_HIP(ctx, hipGetLastError());
+    size_t need = 0;
+    GP_HIP(ctx, hipcub::DeviceSelect::If(nullptr, need, ids.p, sel.p, cnt.p, (int)n, NonNegative(), st));
+    DevBuf<uint8_t> tmp;
+    if (tmp.alloc(need) != hipSuccess) return gp_fail(ctx, GP_ERR_OOM, "out of device memory for the cell export");
+    GP_HIP(ctx, hipcub::DeviceSelect::If(tmp.p, need, ids.p, sel.p, cnt.p, (int)n, NonNegative(), st));
+    int64_t m = 0;
+    GP_HIP(ctx, hipMemcpyAsync(&m, cnt.p, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    GP_HIP(ctx, hipStreamSynchronize(st));
+    *n_out = m;
+    if (m > capacity)
+        return gp_fail(ctx, GP_ERR_CAPACITY, "cell_ids holds " + std::to_string(capacity) + " ids, " +
+                                                 std::to_string(m) + " needed");
+    if (m == 0) return GP_OK;
+    // slot order is brick-major: sort the ids
+    size_t need2 = 0;
+    GP_HIP(ctx, hipcub::DeviceRadixSort::SortKeys(nullptr, need2, sel.p, cell_ids, (int)m, 0, 64, st));
+    DevBuf<uint8_t> tmp2;
+    if (tmp2.alloc(need2) != hipSuccess) return gp_fail(ctx, GP_ERR_OOM, "out of device memory for the cell export");
+    GP_HIP(ctx, hipcub::DeviceRadixSort::SortKeys(tmp2.p, need2, sel.p, cell_ids, (int)m, 0, 64, st));
+    GP_HIP(ctx, hipStreamSynchronize(st));
     return GP_OK;
 }

@@ -18,12 +18,13 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libgridpull.so")
 
 GP_OK = 0
+GP_ERR_CAPACITY = 3
 STATUS = {0: "GP_OK", 1: "GP_ERR_ARG", 2: "GP_ERR_DOMAIN", 3: "GP_ERR_CAPACITY", 4: "GP_ERR_OOM",
           5: "GP_ERR_DEVICE", 6: "GP_ERR_STATE", 7: "GP_ERR_NUMERIC"}
 
 EXPORTS = ("gp_create", "gp_destroy", "gp_last_error", "gp_set_stream", "gp_sync", "gp_build_band",
            "gp_nn_query", "gp_sample_queries", "gp_pull_forward", "gp_pull_backward", "gp_pull_forward_backward", "gp_step",
-           "gp_shape_slots", "gp_export_layout", "gp_gather_vertices", "gp_scatter_vertices",
+           "gp_shape_slots", "gp_export_layout", "gp_export_active_cells", "gp_gather_vertices", "gp_scatter_vertices",
            "gp_init_sphere", "gp_timing_enable", "gp_timing_report")
 
 
@@ -72,6 +73,7 @@ def load_library(path: str = LIB_PATH):
         "gp_step": (st, [P, P, P, P, P, i32, f32, f32, i32, f32, f32, f32]),
         "gp_shape_slots": (st, [P, P]),
         "gp_export_layout": (st, [P, P, P]),
+        "gp_export_active_cells": (st, [P, i32, P, i64, ctypes.POINTER(i64)]),
         "gp_gather_vertices": (st, [P, P, P]),
         "gp_scatter_vertices": (st, [P, P, P]),
         "gp_init_sphere": (st, [P, P, P, P]),
@@ -226,6 +228,20 @@ def gp_export_layout(ctx, vertex_id_of_slot, slot_flags=None) -> None:
     _stream(ctx)
     _check(ctx, load_library().gp_export_layout(ctx, _ptr(vertex_id_of_slot, torch.int64),
                                                 _ptr(slot_flags, torch.uint8)))
+
+
+def gp_export_active_cells(ctx, shape: int, device=None) -> torch.Tensor:
+    """Sorted linear ids of the M1-band cells of one shape (device int64 tensor)."""
+    _stream(ctx)
+    lib = load_library()
+    n = ctypes.c_int64(0)
+    st = lib.gp_export_active_cells(ctx, int(shape), None, 0, ctypes.byref(n))
+    if st not in (GP_OK, GP_ERR_CAPACITY):
+        _check(ctx, st)
+    out = torch.empty(max(n.value, 1), dtype=torch.int64, device=device or "cuda")
+    if n.value > 0:
+        _check(ctx, lib.gp_export_active_cells(ctx, int(shape), _ptr(out, torch.int64), n.value, ctypes.byref(n)))
+    return out[: n.value]
 
 
 def gp_gather_vertices(ctx, dense, field) -> None:

@@ -51,6 +51,9 @@ def test_sphere_64_parity(m1, m2):
     cf, vf, nn, ref = _oracle(dom, pts, q, D, m1, m2)
     compare_band(prob, 0, dom, cf, vf)
     assert prob.n_active == int((vf & 1).sum())
+    from paper_2308_13175_amd import gridpull as gp
+    cells = gp.gp_export_active_cells(prob.ctx, 0).cpu().numpy()
+    assert np.array_equal(cells, np.nonzero(cf & 2)[0])
     assert np.array_equal(prob.nn[: len(q)].cpu().numpy(), nn)
     got, nv = loss_terms(prob)
     assert int(nv[0]) == ref["n_valid"]
