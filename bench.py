@@ -137,6 +137,42 @@ def measured_traffic(kernel, config):
         return None
 
 
+def copy_bandwidth(mib=1024, reps=10):
+    """Measured device-to-device copy rate (read + write bytes per second)."""
+    import torch
+
+    a = torch.empty(mib << 18, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    a.fill_(1.0)
+    b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    gbps = 2.0 * (mib << 20) * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del a, b
+    return gbps
+
+
+def fwd_bwd_median_ms(prob, n=50):
+    """Median duration of one fused forward + backward (query pass, TV, loss) by events."""
+    import torch
+
+    times = []
+    for _ in range(n):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        prob.forward_backward()
+        e1.record()
+        times.append((e0, e1))
+    torch.cuda.synchronize()
+    ms = sorted(a.elapsed_time(b) for a, b in times)
+    prob.grad.zero_()
+    return ms[len(ms) // 2]
+
+
 def copy_calibration(mib=256, reps=3):
     """A plain device copy of known size, for scaling the HBM counters."""
     import torch
@@ -150,7 +186,7 @@ def copy_calibration(mib=256, reps=3):
     log("copy calibration: %d x %d MiB device copy" % (reps, mib))
 
 
-def batched_vs_per_shape(wl, prob, steps, warmup):
+def batched_vs_per_shape(wl, prob, steps, warmup, autotune=True):
     """Config 4: one batched launch sequence against one context per shape.
 
     Times the same iteration (eager and as captured graphs) both ways, then
@@ -174,6 +210,9 @@ def batched_vs_per_shape(wl, prob, steps, warmup):
                 p.iteration(None)
 
     run_eager(warmup)
+    if autotune:
+        for p in singles:
+            p.autotune(reps=1)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     run_eager(steps)
@@ -316,10 +355,21 @@ def cpu_baseline(wl, budget_s: float = 16.0):
     t_adam = time.perf_counter() - t0
     t_iter = Q * (t_nn_q + t_q) + t_fixed + t_adam
     Qtot = wl.n_queries
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
     return {
         "value": Qtot / (t_iter * Qtot / Q) if Q else 0.0,
         "unit": "queries/s",
         "cores": 1,
+        "host_cpu": model,
+        "host_threads": os.cpu_count(),
         "kind": "oracle",
         "sample": ("FP64 oracle, 1 thread, shape 0 of %s: brute-force NN on %d queries + loss/gradient on %d "
                    "queries, scaled linearly to %d queries per iteration, plus the band-wide TV/gradient clear "
@@ -337,6 +387,8 @@ def main():
                     help="workload: 1 sphere-10k, 2 torus-200k (default), 3 union24-2M, 4 batched64, 5 room-20M")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the default NN search shape instead of timing the candidates first")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 256 MiB device copy (scale for the HBM byte counters)")
     args = ap.parse_args()
@@ -358,6 +410,12 @@ def main():
 
     for _ in range(args.warmup):
         prob.iteration(None)
+    tuned_ms = None
+    if not args.no_autotune:
+        _, _, tuned_ms = prob.autotune(reps=3)
+    nn_span, nn_shell = gp.gp_get_nn_params(prob.ctx)
+    log("NN search shape: group span %d, first shell %d%s" % (
+        nn_span, nn_shell, " (autotuned, %.3f ms)" % tuned_ms if tuned_ms is not None else ""))
     torch.cuda.synchronize()
     gp.gp_timing_enable(prob.ctx, True)
     gp.gp_timing_report(prob.ctx)          # start a clean period
@@ -387,6 +445,8 @@ def main():
         g_elapsed = time.perf_counter() - t0
         prob.sync()
 
+    fb_median = fwd_bwd_median_ms(prob)
+    copy_gbps = copy_bandwidth()
     # TV vertex count for the byte model
     _, flags = prob.layout()
     V2 = int(((flags & 2) > 0).sum())
@@ -447,9 +507,13 @@ def main():
                    "slots": prob.n_slots, "optimised_vertices": V, "tv_vertices": V2,
                    "step": "sample+nn+forward+backward+adam"},
         "roofline": roof,
-        "fwd_bwd": {"queries_per_s": Q / (fb_ms * 1e-3), "ms": fb_ms,
+        "nn_search": {"group_span": nn_span, "first_shell": nn_shell, "autotuned": tuned_ms is not None,
+                      "autotune_best_ms": tuned_ms},
+        "fwd_bwd": {"queries_per_s": Q / (fb_ms * 1e-3), "ms": fb_ms, "median_ms": fb_median,
                     "algorithmic_GBps": fb_bytes / (fb_ms * 1e-3) / 1e9,
-                    "hbm_frac": fb_bytes / (fb_ms * 1e-3) / 1e9 / HBM_PEAK_GBS},
+                    "hbm_frac": fb_bytes / (fb_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                    "copy_frac": fb_bytes / (fb_ms * 1e-3) / 1e9 / copy_gbps},
+        "copy_GBps": copy_gbps,
         "kernels_avg_ms": {k: round(v[1], 5) for k, v in sorted(avg.items())},
         "kernels_hbm": kernels_hbm,
         "setup_ms": setup_ms,
@@ -459,7 +523,7 @@ def main():
     if graph is not None:
         out["graph"] = {"queries_per_s": graph_qps, "ms_per_step": g_elapsed * 1e3 / args.steps}
     if args.config == 4:
-        cmp = batched_vs_per_shape(wl, prob, max(3, args.steps // 5), 2)
+        cmp = batched_vs_per_shape(wl, prob, max(3, args.steps // 5), 2, not args.no_autotune)
         cmp["batched_queries_per_s"] = eager_qps
         if graph is not None:
             cmp["batched_graph_queries_per_s"] = graph_qps

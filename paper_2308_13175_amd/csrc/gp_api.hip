@@ -189,6 +189,45 @@ gp_status gp_nn_query(gp_ctx ctx, const float* qx, const float* qy, const float*
     return gp_nn_impl(ctx, qx, qy, qz, nn_out);
 }
 
+gp_status gp_set_nn_params(gp_ctx ctx, int32_t group_span, int32_t first_shell)
+{
+    if (!ctx) return GP_ERR_ARG;
+    if (group_span < 1 || group_span > gp::kNnSpanMax)
+        return gp_fail(ctx, GP_ERR_ARG, "group_span must be in [1, 64]");
+    if (first_shell < 0 || first_shell > gp::kNnShellMax)
+        return gp_fail(ctx, GP_ERR_ARG, "first_shell must be in [0, 4]");
+    ctx->nn_params.span = group_span;
+    ctx->nn_params.shell = first_shell;
+    return GP_OK;
+}
+
+gp_status gp_get_nn_params(gp_ctx ctx, int32_t* group_span, int32_t* first_shell)
+{
+    if (!ctx) return GP_ERR_ARG;
+    if (!group_span || !first_shell) return gp_fail(ctx, GP_ERR_ARG, "null output");
+    *group_span = ctx->nn_params.span;
+    *first_shell = ctx->nn_params.shell;
+    return GP_OK;
+}
+
+gp_status gp_autotune_nn(gp_ctx ctx, const float* qx, const float* qy, const float* qz, int64_t n_queries,
+                         int32_t* nn_out, int32_t reps, int32_t* group_span_out, int32_t* first_shell_out,
+                         float* best_ms_out)
+{
+    gp_status st = ready(ctx);
+    if (st != GP_OK) return st;
+    if ((st = check_queries(ctx, qx, qy, qz, n_queries)) != GP_OK) return st;
+    if (n_queries > 0 && !nn_out) return gp_fail(ctx, GP_ERR_ARG, "null nn_out");
+    if (reps < 1 || reps > 100) return gp_fail(ctx, GP_ERR_ARG, "reps must be in [1, 100]");
+    gp::NnParams best;
+    float ms = -1.f;
+    if ((st = gp_autotune_nn_impl(ctx, qx, qy, qz, nn_out, reps, &best, &ms)) != GP_OK) return st;
+    if (group_span_out) *group_span_out = best.span;
+    if (first_shell_out) *first_shell_out = best.shell;
+    if (best_ms_out) *best_ms_out = ms;
+    return GP_OK;
+}
+
 gp_status gp_sample_queries(gp_ctx ctx, uint64_t seed, int32_t iteration, const float* sigma, float sigma_const,
                             float* qx, float* qy, float* qz, int32_t* src_out)
 {

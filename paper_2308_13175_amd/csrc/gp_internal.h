@@ -62,6 +62,17 @@ struct Band {
     const int32_t* tile_shape;   // [n_tiles]
 };
 
+// Nearest-neighbour search shape: a group of queries is cut where its cells
+// would span `span` or more cells on an axis, and its lockstep box is the
+// group's cell box grown by `shell` cells.  Any values give the same exact
+// result; they only move work between the lockstep and per-query passes.
+struct NnParams {
+    int32_t span = 8;
+    int32_t shell = 1;
+};
+constexpr int32_t kNnSpanMax = 64;
+constexpr int32_t kNnShellMax = 4;
+
 struct Loc {
     int32_t c[3];
     double t[3];     // exact local coordinate in [0, 1]
@@ -276,6 +287,8 @@ struct gp_ctx_s {
     DevBuf<float> g_raw;          // [n_slots] unscaled query contributions of a fused pass (kept zero between passes)
     bool have_forward = false;
 
+    gp::NnParams nn_params;       // set by gp_set_nn_params or gp_autotune_nn
+
     // optional per-kernel timing with events on the context's stream
     struct TimedLaunch {
         const char* name;
@@ -329,6 +342,8 @@ gp_status gp_build_band_impl(gp_ctx ctx, const gp_shape* shapes, int32_t n_shape
                              const float* px, const float* py, const float* pz,
                              int32_t m1, int32_t m2);
 gp_status gp_nn_impl(gp_ctx ctx, const float* qx, const float* qy, const float* qz, int32_t* nn);
+gp_status gp_autotune_nn_impl(gp_ctx ctx, const float* qx, const float* qy, const float* qz, int32_t* nn,
+                              int32_t reps, gp::NnParams* best_out, float* best_ms_out);
 gp_status gp_sample_impl(gp_ctx ctx, uint64_t seed, int32_t iteration, const float* sigma,
                          float sigma_const, float* qx, float* qy, float* qz, int32_t* src);
 gp_status gp_step_consts_impl(gp_ctx ctx, int32_t t, float lr0, float decay, int32_t decay_every, float beta1,

@@ -39,9 +39,7 @@
 namespace gp {
 namespace {
 
-constexpr int kNnFirstShell = 1;  // growth of the group's box scanned in lockstep
 constexpr int kNnMaxGrow = 8;     // growth beyond which a group with no point in its box goes to the ring search
-constexpr int kNnGroupCap = 8;     // a group's query cells span fewer than this many cells per axis
 
 struct Best {
     double d2;
@@ -478,7 +476,7 @@ __device__ inline uint32_t compact3(uint32_t v)
 constexpr int kWaves = kQueryBlock / 64;
 constexpr int kWaveSpan = kQueryTile / kWaves;   // sorted positions grouped and scanned by one wave
 
-__global__ __launch_bounds__(kQueryBlock, 4) void k_nn(Band B, Global G, const float* __restrict__ qx,
+__global__ __launch_bounds__(kQueryBlock, 4) void k_nn(Band B, Global G, NnParams P, const float* __restrict__ qx,
                                                     const float* __restrict__ qy, const float* __restrict__ qz,
                                                     int32_t* __restrict__ nn)
 {
@@ -544,7 +542,7 @@ __global__ __launch_bounds__(kQueryBlock, 4) void k_nn(Band B, Global G, const f
     __syncthreads();
 
     // ---- greedy groups along this wave's part of the sorted order: at most
-    // 64 queries whose cells span fewer than kNnGroupCap cells per axis.  From
+    // 64 queries whose cells span fewer than P.span cells per axis.  From
     // each group's first position the next 64 cells are loaded one per lane;
     // prefix minima and maxima over the lanes give the span of every prefix,
     // and the group ends before the first lane whose prefix does not fit.
@@ -568,8 +566,7 @@ __global__ __launch_bounds__(kQueryBlock, 4) void k_nn(Band B, Global G, const f
                     }
                 }
             }
-            const bool fits = in && hi[0] - lo[0] < kNnGroupCap && hi[1] - lo[1] < kNnGroupCap &&
-                              hi[2] - lo[2] < kNnGroupCap;
+            const bool fits = in && hi[0] - lo[0] < P.span && hi[1] - lo[1] < P.span && hi[2] - lo[2] < P.span;
             const uint64_t bad = __ballot(!fits);
             const int32_t len = bad ? max((int32_t)__builtin_ctzll(bad), 1) : 64;
             if (lane == 0) s_group[wave][ng] = (int16_t)g;
@@ -606,12 +603,12 @@ __global__ __launch_bounds__(kQueryBlock, 4) void k_nn(Band B, Global G, const f
             }
         wave_minmax6(wb);
         if (__any(q.open)) {
-            // ---- lockstep pass over the group's box grown by kNnFirstShell
-            // cells, grown further one cell at a time while it holds no point
+            // ---- lockstep pass over the group's box grown by P.shell cells,
+            // grown further one cell at a time while it holds no point
             int32_t lo[3], hi[3];
             {
                 int32_t olo[3] = {0, 0, 0}, ohi[3] = {-1, -1, -1};
-                for (int e = kNnFirstShell;; ++e) {
+                for (int e = P.shell;; ++e) {
                     for (int a = 0; a < 3; ++a) {
                         lo[a] = max(wb[a] - e, 0);
                         hi[a] = min(wb[3 + a] + e, s.R[a] - 1);
@@ -710,7 +707,74 @@ gp_status gp_nn_impl(gp_ctx ctx, const float* qx, const float* qy, const float* 
     if (ctx->n_tiles == 0) return GP_OK;
     Global G{ctx->cell_start.p, ctx->spts.p};
     GP_TIMED(ctx, "k_nn");
-    k_nn<<<(unsigned)ctx->n_tiles, kQueryBlock, 0, ctx->stream>>>(ctx->band(), G, qx, qy, qz, nn);
+    k_nn<<<(unsigned)ctx->n_tiles, kQueryBlock, 0, ctx->stream>>>(ctx->band(), G, ctx->nn_params, qx, qy, qz, nn);
     GP_HIP(ctx, hipGetLastError());
+    return GP_OK;
+}
+
+// Times k_nn for every (span, shell) pair of a small grid on the caller's
+// queries (the results are the same for all of them) and keeps the fastest in
+// the context.  Each candidate runs once untimed, then `reps` times between
+// events; its time is the smallest of those.  The context's current setting
+// is timed first and is only replaced by one at least 2% faster, so timing
+// noise does not move a setting that is already as good.
+gp_status gp_autotune_nn_impl(gp_ctx ctx, const float* qx, const float* qy, const float* qz, int32_t* nn,
+                              int32_t reps, NnParams* best_out, float* best_ms_out)
+{
+    static const int32_t spans[] = {4, 6, 8, 12, 16, 24, 32};
+    static const int32_t shells[] = {0, 1, 2};
+    constexpr int kCandidates = 1 + 7 * 3;
+    NnParams cand[kCandidates];
+    cand[0] = ctx->nn_params;
+    int nc = 1;
+    for (int32_t sp : spans)
+        for (int32_t sh : shells) {
+            if (sp == cand[0].span && sh == cand[0].shell) continue;
+            cand[nc].span = sp;
+            cand[nc].shell = sh;
+            ++nc;
+        }
+    NnParams best = ctx->nn_params;
+    float best_ms = -1.f;
+    if (ctx->n_tiles > 0) {
+        Global G{ctx->cell_start.p, ctx->spts.p};
+        hipEvent_t ev[2];
+        GP_HIP(ctx, hipEventCreate(&ev[0]));
+        if (hipEventCreate(&ev[1]) != hipSuccess) {
+            (void)hipEventDestroy(ev[0]);
+            ctx->err = "hipEventCreate failed";
+            return GP_ERR_DEVICE;
+        }
+        hipError_t e = hipSuccess;
+        for (int c = 0; c < nc && e == hipSuccess; ++c) {
+            const NnParams P = cand[c];
+            float t_min = -1.f;
+            for (int32_t r = 0; r <= reps && e == hipSuccess; ++r) {
+                if (r > 0) e = hipEventRecord(ev[0], ctx->stream);
+                k_nn<<<(unsigned)ctx->n_tiles, kQueryBlock, 0, ctx->stream>>>(ctx->band(), G, P, qx, qy, qz, nn);
+                if (e == hipSuccess) e = hipGetLastError();
+                if (r > 0 && e == hipSuccess) e = hipEventRecord(ev[1], ctx->stream);
+                if (r > 0 && e == hipSuccess) e = hipEventSynchronize(ev[1]);
+                float ms = 0.f;
+                if (r > 0 && e == hipSuccess) e = hipEventElapsedTime(&ms, ev[0], ev[1]);
+                if (r > 0 && e == hipSuccess && (t_min < 0.f || ms < t_min)) t_min = ms;
+            }
+            if (e != hipSuccess) break;
+            const float need = c == 0 || !(best.span == cand[0].span && best.shell == cand[0].shell) ? 1.f : 0.98f;
+            if (t_min >= 0.f && (best_ms < 0.f || t_min < best_ms * need)) {
+                best_ms = t_min;
+                best = P;
+            }
+        }
+        (void)hipEventDestroy(ev[0]);
+        (void)hipEventDestroy(ev[1]);
+        GP_HIP(ctx, e);
+        // leave nn holding the chosen configuration's (identical) result
+        k_nn<<<(unsigned)ctx->n_tiles, kQueryBlock, 0, ctx->stream>>>(ctx->band(), G, best, qx, qy, qz, nn);
+        GP_HIP(ctx, hipGetLastError());
+    }
+    ctx->nn_params = best;
+    if (best_out) *best_out = best;
+    if (best_ms_out) *best_ms_out = best_ms;
     return GP_OK;
 }

@@ -570,15 +570,48 @@ __global__ __launch_bounds__(kFinalizeBlock) void k_finalize(Band B, const doubl
     const double2* qp = reinterpret_cast<const double2*>(q_part);
     const int64_t pb = s.tile_begin * parts * 2, pe = s.tile_end * parts * 2;
     const int hi = threadIdx.x & 1;   // (kFinalizeBlock is even: a thread's pairs are all low or all high)
-    double a0 = 0.0, a1 = 0.0;
-    for (int64_t m = pb + threadIdx.x; m < pe; m += blockDim.x) {
-        const double2 d = qp[m];
-        a0 += d.x;
-        a1 += d.y;
+    // four independent accumulators so that four loads are in flight per thread
+    double a0[4] = {0.0, 0.0, 0.0, 0.0}, a1[4] = {0.0, 0.0, 0.0, 0.0};
+    int64_t m = pb + threadIdx.x;
+    for (; m + 3 * (int64_t)blockDim.x < pe; m += 4 * (int64_t)blockDim.x) {
+        double2 d[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) d[u] = qp[m + u * (int64_t)blockDim.x];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            a0[u] += d[u].x;
+            a1[u] += d[u].y;
+        }
     }
-    v[2 * hi] = a0;
-    v[2 * hi + 1] = a1;
-    for (int64_t b = s.brick_begin + threadIdx.x; b < s.brick_end; b += blockDim.x) v[4] += tv_part[b];
+#pragma unroll
+    for (int u = 0; u < 3; ++u) {   // at most three left
+        if (m < pe) {
+            const double2 d = qp[m];
+            a0[u] += d.x;
+            a1[u] += d.y;
+        }
+        m += blockDim.x;
+    }
+    const double s0 = (a0[0] + a0[1]) + (a0[2] + a0[3]), s1 = (a1[0] + a1[1]) + (a1[2] + a1[3]);
+    v[0] = hi ? 0.0 : s0;
+    v[1] = hi ? 0.0 : s1;
+    v[2] = hi ? s0 : 0.0;
+    v[3] = hi ? s1 : 0.0;
+    double t4[4] = {0.0, 0.0, 0.0, 0.0};
+    int64_t b = s.brick_begin + threadIdx.x;
+    for (; b + 3 * (int64_t)blockDim.x < s.brick_end; b += 4 * (int64_t)blockDim.x) {
+        double d[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) d[u] = tv_part[b + u * (int64_t)blockDim.x];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) t4[u] += d[u];
+    }
+#pragma unroll
+    for (int u = 0; u < 3; ++u) {
+        if (b < s.brick_end) t4[u] += tv_part[b];
+        b += blockDim.x;
+    }
+    v[4] = (t4[0] + t4[1]) + (t4[2] + t4[3]);
 #pragma unroll
     for (int i = 0; i < 5; ++i)
         for (int o = 32; o > 0; o >>= 1) v[i] += __shfl_xor(v[i], o, 64);
@@ -586,12 +619,15 @@ __global__ __launch_bounds__(kFinalizeBlock) void k_finalize(Band B, const doubl
     if (lane == 0)
         for (int i = 0; i < 5; ++i) lds[wave * 5 + i] = v[i];
     __syncthreads();
-    if (threadIdx.x == 0) {
-        for (int i = 0; i < 5; ++i) {
-            double a = 0.0;
-            for (int wv = 0; wv < kFinalizeBlock / 64; ++wv) a += lds[wv * 5 + i];
-            v[i] = a;
-        }
+    if (wave != 0) return;
+    constexpr int kFinalizeWaves = kFinalizeBlock / 64;
+    static_assert((kFinalizeWaves & (kFinalizeWaves - 1)) == 0 && kFinalizeWaves <= 64, "power-of-two waves");
+#pragma unroll
+    for (int i = 0; i < 5; ++i) {
+        v[i] = lane < kFinalizeWaves ? lds[lane * 5 + i] : 0.0;
+        for (int o = kFinalizeWaves / 2; o > 0; o >>= 1) v[i] += __shfl_xor(v[i], o, 64);
+    }
+    if (lane == 0) {
         const double nq = v[3];
         const double iq = nq > 0.0 ? 1.0 / nq : 0.0;
         const double pull = v[0] * iq, surf = v[1] * iq, grad = v[2] * iq;

@@ -10,7 +10,7 @@ from __future__ import annotations
 
 import ctypes
 import os
-from typing import Optional, Sequence
+from typing import Optional, Sequence, Tuple
 
 import torch
 
@@ -23,7 +23,7 @@ STATUS = {0: "GP_OK", 1: "GP_ERR_ARG", 2: "GP_ERR_DOMAIN", 3: "GP_ERR_CAPACITY",
           5: "GP_ERR_DEVICE", 6: "GP_ERR_STATE", 7: "GP_ERR_NUMERIC"}
 
 EXPORTS = ("gp_create", "gp_destroy", "gp_last_error", "gp_set_stream", "gp_sync", "gp_build_band",
-           "gp_nn_query", "gp_sample_queries", "gp_pull_forward", "gp_pull_backward", "gp_pull_forward_backward", "gp_step",
+           "gp_nn_query", "gp_set_nn_params", "gp_get_nn_params", "gp_autotune_nn", "gp_sample_queries", "gp_pull_forward", "gp_pull_backward", "gp_pull_forward_backward", "gp_step",
            "gp_shape_slots", "gp_export_layout", "gp_export_active_cells", "gp_gather_vertices", "gp_scatter_vertices",
            "gp_init_sphere", "gp_timing_enable", "gp_timing_report")
 
@@ -66,6 +66,10 @@ def load_library(path: str = LIB_PATH):
         "gp_build_band": (st, [P, ctypes.POINTER(gp_shape), i32, P, P, P, i32, i32, i32,
                                ctypes.POINTER(i64), ctypes.POINTER(i64)]),
         "gp_nn_query": (st, [P, P, P, P, i64, P]),
+        "gp_set_nn_params": (st, [P, i32, i32]),
+        "gp_get_nn_params": (st, [P, ctypes.POINTER(i32), ctypes.POINTER(i32)]),
+        "gp_autotune_nn": (st, [P, P, P, P, i64, P, i32, ctypes.POINTER(i32), ctypes.POINTER(i32),
+                                ctypes.POINTER(f32)]),
         "gp_sample_queries": (st, [P, u64, i32, P, f32, P, P, P, P]),
         "gp_pull_forward": (st, [P, P, P, P, P, i64, P, gp_weights, P, P]),
         "gp_pull_backward": (st, [P, P, P, P, P, i64, P, gp_weights, P, P]),
@@ -170,6 +174,27 @@ def gp_nn_query(ctx, qx, qy, qz, nn_out) -> None:
     _stream(ctx)
     _check(ctx, load_library().gp_nn_query(ctx, _ptr(qx, torch.float32), _ptr(qy, torch.float32),
                                            _ptr(qz, torch.float32), qx.numel(), _ptr(nn_out, torch.int32)))
+
+
+def gp_set_nn_params(ctx, group_span: int, first_shell: int) -> None:
+    _check(ctx, load_library().gp_set_nn_params(ctx, int(group_span), int(first_shell)))
+
+
+def gp_get_nn_params(ctx) -> Tuple[int, int]:
+    span, shell = ctypes.c_int32(0), ctypes.c_int32(0)
+    _check(ctx, load_library().gp_get_nn_params(ctx, ctypes.byref(span), ctypes.byref(shell)))
+    return span.value, shell.value
+
+
+def gp_autotune_nn(ctx, qx, qy, qz, nn_out, reps: int = 2) -> Tuple[int, int, float]:
+    """Time the NN search shapes on these queries and keep the fastest: (group_span, first_shell, ms)."""
+    _stream(ctx)
+    span, shell, ms = ctypes.c_int32(0), ctypes.c_int32(0), ctypes.c_float(0.0)
+    _check(ctx, load_library().gp_autotune_nn(ctx, _ptr(qx, torch.float32), _ptr(qy, torch.float32),
+                                              _ptr(qz, torch.float32), qx.numel(), _ptr(nn_out, torch.int32),
+                                              int(reps), ctypes.byref(span), ctypes.byref(shell),
+                                              ctypes.byref(ms)))
+    return span.value, shell.value, ms.value
 
 
 def gp_sample_queries(ctx, seed: int, iteration: int, sigma, sigma_const: float, qx, qy, qz, src_out=None) -> None:

@@ -182,6 +182,11 @@ class Problem:
         gp.gp_nn_query(self.ctx, self.qx[: self.n_queries], self.qy[: self.n_queries],
                        self.qz[: self.n_queries], self.nn)
 
+    def autotune(self, reps: int = 2):
+        """Pick the NN search shape by timing it on the current queries (leaves nn filled)."""
+        return gp.gp_autotune_nn(self.ctx, self.qx[: self.n_queries], self.qy[: self.n_queries],
+                                 self.qz[: self.n_queries], self.nn, reps)
+
     def forward(self, field: Optional[torch.Tensor] = None):
         f = self.field if field is None else field
         gp.gp_pull_forward(self.ctx, self.qx[: self.n_queries], self.qy[: self.n_queries],

@@ -253,12 +253,7 @@ def test_fused_forward_backward(m1, m2):
     prob.close()
 
 
-def test_nn_exact_ties_and_distant_queries():
-    """Points on a lattice in shuffled index order, queries at lattice cube
-    centres and edge midpoints (8-way and 4-way exact ties: the lowest index
-    must win), queries on lattice points, and queries many cells away from
-    every point (the box grows to its limit, then the ring search)."""
-    log("case: exact ties and distant queries")
+def _tie_case():
     dom = synth.Domain((40, 40, 40), (-1.0, -1.0, -1.0), (1.0, 1.0, 1.0))
     g = np.arange(-4, 5, dtype=np.float32) * np.float32(0.0625)      # lattice step 1/16, exact in float
     lat = np.stack(np.meshgrid(g, g, g, indexing="ij"), -1).reshape(-1, 3)
@@ -271,6 +266,16 @@ def test_nn_exact_ties_and_distant_queries():
     q = np.concatenate([centres, edges, lat[:50], far]).astype(np.float32)
     q = q[rng.permutation(len(q))]
     D = synth.sphere_sdf_field(dom, 0.3, noise=0.02, seed=4)
+    return dom, pts, q, D
+
+
+def test_nn_exact_ties_and_distant_queries():
+    """Points on a lattice in shuffled index order, queries at lattice cube
+    centres and edge midpoints (8-way and 4-way exact ties: the lowest index
+    must win), queries on lattice points, and queries many cells away from
+    every point (the box grows to its limit, then the ring search)."""
+    log("case: exact ties and distant queries")
+    dom, pts, q, D = _tie_case()
     prob = _run_gpu(dom, pts, q, D, 3, 3)
     cf, vf, nn, ref = _oracle(dom, pts, q, D, 3, 3)
     got_nn = prob.nn[: len(q)].cpu().numpy()
@@ -318,3 +323,45 @@ def test_batch_with_a_shape_without_queries_and_a_one_point_shape():
         else:
             assert np.abs(bg[i]).max() == 0.0
     batch.close()
+
+
+def test_nn_search_shapes_and_autotuner():
+    """Every NN search shape (group span, first shell), including the
+    extremes, and the autotuner's choice give the oracle's indices exactly, on
+    the exact-tie lattice and on a sparse sphere (few points per cell, so most
+    queries leave the lockstep box open)."""
+    from paper_2308_13175_amd import gridpull as gp
+    sparse = synth.cube_domain(64), synth.sphere_points(1500, 0.5, seed=7)
+    cases = [("ties",) + _tie_case()[:3],
+             ("sparse sphere", sparse[0], sparse[1], synth.host_queries(sparse[1], 30_000, 0.04, seed=8))]
+    for name, dom, pts, q in cases:
+        nn = oracle.nn_bruteforce(q, pts)
+        prob = make_problem([spec(pts, dom, len(q), 0.0)])
+        prob.set_queries(q)
+        assert gp.gp_get_nn_params(prob.ctx) == (8, 1)
+        for span, shell in [(1, 0), (2, 0), (3, 2), (8, 1), (16, 0), (64, 4)]:
+            log("case: %s, group span %d, first shell %d" % (name, span, shell))
+            gp.gp_set_nn_params(prob.ctx, span, shell)
+            prob.nn.fill_(-7)
+            prob.nearest()
+            prob.sync()
+            got = prob.nn[: len(q)].cpu().numpy()
+            bad = np.nonzero(got != nn)[0]
+            assert len(bad) == 0, "%s span %d shell %d: %d differ" % (name, span, shell, len(bad))
+        log("case: %s, autotuner" % name)
+        gp.gp_set_nn_params(prob.ctx, 8, 1)   # the tuner starts from the current setting
+        prob.nn.fill_(-7)
+        span, shell, ms = prob.autotune(reps=1)
+        prob.sync()
+        assert span in (4, 6, 8, 12, 16, 24, 32) and shell in (0, 1, 2) and ms > 0
+        assert gp.gp_get_nn_params(prob.ctx) == (span, shell)
+        assert np.array_equal(prob.nn[: len(q)].cpu().numpy(), nn)
+        prob.nearest()
+        prob.sync()
+        assert np.array_equal(prob.nn[: len(q)].cpu().numpy(), nn)
+        for bad_args in [(0, 1), (65, 1), (8, -1), (8, 5)]:
+            with pytest.raises(gp.GridPullError) as ei:
+                gp.gp_set_nn_params(prob.ctx, *bad_args)
+            assert ei.value.status == 1
+        assert gp.gp_get_nn_params(prob.ctx) == (span, shell)
+        prob.close()
