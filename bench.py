@@ -304,6 +304,66 @@ def build_problem(config: int):
     return wl, prob, setup_ms
 
 
+def schedule_sweep(kind: str, iters: int = 1600, n_points: int = 200_000, n_queries: int = 50_000):
+    """Whole optimisation runs on the paper's default schedule, one JSON line per setting.
+
+    Sec. 4's defaults: 50 000 queries per iteration, 1600 iterations, Adam with
+    lr 1 (one cell here) times 0.3 every 400 iterations, a small-sphere initial
+    field, M1 = 3 and M2 = 14.  One quantity varies per sweep, as in the
+    ablations: the grid resolution R (Tab. 14), the TV band M2 (Tab. 17) or
+    the pull band M1 (3 against all cells).  Input: the 200K-point torus,
+    sigma = 2 cells.  Iteration 1 runs eagerly with t = 1, the other
+    iterations replay one captured graph.
+    """
+    import torch
+
+    from paper_2308_13175_amd import synth
+    from paper_2308_13175_amd.problem import AdamConfig, GraphedIteration, Problem, ShapeSpec
+
+    pts = synth.torus_points(n_points, seed=1)
+    if kind == "res":
+        settings = [(r, 3, 14) for r in (32, 64, 128, 256, 512)]
+    elif kind == "m2":
+        settings = [(256, 3, m2) for m2 in (2, 14, 30, 50, 256)]
+    elif kind == "m1":
+        settings = [(256, m1, 14) for m1 in (3, 256)]
+    else:
+        raise SystemExit("unknown sweep %r (res, m2, m1)" % kind)
+    for res, m1, m2 in settings:
+        dom = synth.cube_domain(res)
+        h = dom.h[0]
+        spec = ShapeSpec(pts, dom.dims, dom.lo, dom.hi, n_queries, 2.0 * h)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        prob = Problem([spec], m1=m1, m2=m2, adam=AdamConfig(lr0=h, eps=1e-8))
+        torch.cuda.synchronize()
+        setup_s = time.perf_counter() - t0
+        prob.iteration(1)
+        nn_search = prob.autotune(reps=2)[:3]   # before the capture: the graph keeps the search shape
+        graph = GraphedIteration(prob)
+        prob.init_sphere()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        prob.iteration(1)
+        for _ in range(iters - 1):
+            graph.replay()
+        torch.cuda.synchronize()
+        run_s = time.perf_counter() - t0
+        prob.sync()
+        loss = prob.loss.cpu().numpy()[0]
+        _, flags = prob.layout()
+        print(json.dumps({
+            "sweep": kind, "workload": "torus-200k", "res": res, "m1": m1, "m2": m2, "iterations": iters,
+            "queries_per_iteration": n_queries, "run_s": run_s, "ms_per_iteration": run_s * 1e3 / iters,
+            "setup_s": setup_s, "slots": prob.n_slots, "optimised_vertices": prob.n_active,
+            "tv_vertices": int(((flags & 2) > 0).sum()), "final_loss": [float(x) for x in loss],
+            "final_valid": int(prob.n_valid.sum()), "nn_search": list(nn_search)}), flush=True)
+        del graph
+        prob.close()
+        del prob
+        torch.cuda.empty_cache()
+
+
 def cpu_baseline(wl, budget_s: float = 16.0):
     """The FP64 oracle on one host thread, on a bounded sample of the workload."""
     import numpy as np
@@ -387,6 +447,8 @@ def main():
                     help="workload: 1 sphere-10k, 2 torus-200k (default), 3 union24-2M, 4 batched64, 5 room-20M")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--sweep", choices=["res", "m2", "m1"],
+                    help="instead of the benchmark: whole runs on the paper's schedule, one JSON line per setting")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default NN search shape instead of timing the candidates first")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -403,6 +465,9 @@ def main():
     from paper_2308_13175_amd.problem import GraphedIteration
 
     torch.cuda.set_device(0)
+    if args.sweep:
+        schedule_sweep(args.sweep)
+        return
     wl, prob, setup_ms = build_problem(args.config)
     Q, J = prob.n_queries, prob.n_points
     n_tv = None
@@ -412,10 +477,10 @@ def main():
         prob.iteration(None)
     tuned_ms = None
     if not args.no_autotune:
-        _, _, tuned_ms = prob.autotune(reps=3)
-    nn_span, nn_shell = gp.gp_get_nn_params(prob.ctx)
-    log("NN search shape: group span %d, first shell %d%s" % (
-        nn_span, nn_shell, " (autotuned, %.3f ms)" % tuned_ms if tuned_ms is not None else ""))
+        _, _, _, tuned_ms = prob.autotune(reps=3)
+    nn_span, nn_shell, nn_parts = gp.gp_get_nn_params(prob.ctx)
+    log("NN search shape: group span %d, first shell %d, %d blocks per tile%s" % (
+        nn_span, nn_shell, nn_parts, " (autotuned, %.3f ms)" % tuned_ms if tuned_ms is not None else ""))
     torch.cuda.synchronize()
     gp.gp_timing_enable(prob.ctx, True)
     gp.gp_timing_report(prob.ctx)          # start a clean period
@@ -507,7 +572,8 @@ def main():
                    "slots": prob.n_slots, "optimised_vertices": V, "tv_vertices": V2,
                    "step": "sample+nn+forward+backward+adam"},
         "roofline": roof,
-        "nn_search": {"group_span": nn_span, "first_shell": nn_shell, "autotuned": tuned_ms is not None,
+        "nn_search": {"group_span": nn_span, "first_shell": nn_shell, "tile_parts": nn_parts,
+                      "autotuned": tuned_ms is not None,
                       "autotune_best_ms": tuned_ms},
         "fwd_bwd": {"queries_per_s": Q / (fb_ms * 1e-3), "ms": fb_ms, "median_ms": fb_median,
                     "algorithmic_GBps": fb_bytes / (fb_ms * 1e-3) / 1e9,

@@ -120,7 +120,8 @@ gp_status gp_sync(gp_ctx ctx);
  *           later passed and must not overlap between shapes.
  * px,py,pz: device float32 points of all shapes; the context keeps a sorted
  *           copy, so the arrays may be freed afterwards.
- * m1, m2:   band half-widths in cells, 0 <= m <= 64.
+ * m1, m2:   band half-widths in cells, 0 <= m <= 1024; a width of at least
+ *           the largest dims - 1 covers the whole grid ("all grids").
  * brick:    brick edge in vertices; only 8 is supported (else GP_ERR_ARG).
  * n_slots_out, n_active_vertices_out: host; the field length and the number
  *           of optimised vertices over all shapes.
@@ -154,31 +155,36 @@ gp_status gp_nn_query(gp_ctx ctx, const float* qx, const float* qy, const float*
  * sorted along a Morton curve of their cells and cut into groups of at most
  * 64 whose cells span fewer than group_span cells on every axis; a group's
  * lanes scan the group's cell box grown by first_shell cells together, and
- * the queries that box does not settle continue alone.
- * group_span in [1, 64], first_shell in [0, 4]; defaults 8 and 1.  The
- * setting belongs to the context and survives gp_build_band.
+ * the queries that box does not settle continue alone.  tile_parts blocks
+ * share a tile (each sorts it and takes 1/tile_parts of the groups), which
+ * gives small batches more blocks.
+ * group_span in [1, 64], first_shell in [0, 4], tile_parts in {1, 2, 4};
+ * defaults 8, 1 and 1.  The setting belongs to the context and survives
+ * gp_build_band.
  * Errors: GP_ERR_ARG (out of range or null outputs).
  */
-gp_status gp_set_nn_params(gp_ctx ctx, int32_t group_span, int32_t first_shell);
-gp_status gp_get_nn_params(gp_ctx ctx, int32_t* group_span, int32_t* first_shell);
+gp_status gp_set_nn_params(gp_ctx ctx, int32_t group_span, int32_t first_shell, int32_t tile_parts);
+gp_status gp_get_nn_params(gp_ctx ctx, int32_t* group_span, int32_t* first_shell, int32_t* tile_parts);
 
 /*
  * Autotuner of the search shape above: runs gp_nn_query's kernel on the given
  * queries for group_span in {4, 6, 8, 12, 16, 24, 32} x first_shell in
- * {0, 1, 2}, each once untimed and then reps times between HIP events on the
- * context's stream (its time: the smallest of those), keeps the pair with the
- * smallest time in the context and leaves nn_out holding the nearest
- * neighbours (as gp_nn_query).  The context's current setting is timed first
- * and stays unless another is at least 2% faster.
+ * {0, 1, 2} at the current tile_parts, then tile_parts in {1, 2, 4} at the
+ * best of those, each once untimed and then reps times between HIP events on
+ * the context's stream (its time: the smallest of those); keeps the fastest
+ * in the context and leaves nn_out holding the nearest neighbours (as
+ * gp_nn_query).  The context's current setting is timed first and stays
+ * unless another is at least 2% faster.
  * Arguments as gp_nn_query; reps in [1, 100]; group_span_out,
- * first_shell_out (host, may be NULL) receive the choice and best_ms_out
- * (host, may be NULL) its time in ms (-1 with no queries).
+ * first_shell_out, tile_parts_out (host, may be NULL) receive the choice and
+ * best_ms_out (host, may be NULL) its time in ms (-1 with no queries).
  * Synchronises; not for use under stream capture.
  * Errors: as gp_nn_query, GP_ERR_ARG for reps, GP_ERR_DEVICE.
  */
 gp_status gp_autotune_nn(gp_ctx ctx, const float* qx, const float* qy, const float* qz,
                          int64_t n_queries, int32_t* nn_out, int32_t reps,
-                         int32_t* group_span_out, int32_t* first_shell_out, float* best_ms_out);
+                         int32_t* group_span_out, int32_t* first_shell_out, int32_t* tile_parts_out,
+                         float* best_ms_out);
 
 /*
  * Draw one iteration's queries (Sec. 3: Gaussian around randomly chosen

@@ -334,10 +334,14 @@ gp_status gp_build_band_impl(gp_ctx ctx, const gp_shape* shapes, int32_t n_shape
         if (bad != ~0ull)
             return gp_fail(ctx, GP_ERR_DOMAIN, "shape " + std::to_string(s) + ": point " + std::to_string(bad) +
                                                    " lies outside the domain");
-        // separable Chebyshev dilation x -> y -> z
-        k_dilate<<<blocks_for(nc), kThreads, 0, st>>>(c0.p, c1.p, d.R[0], d.R[1], d.R[2], 0, m1, m2, 1, 1);
-        k_dilate<<<blocks_for(nc), kThreads, 0, st>>>(c1.p, c0.p, d.R[0], d.R[1], d.R[2], 1, m1, m2, 2, 4);
-        k_dilate<<<blocks_for(nc), kThreads, 0, st>>>(c0.p, c1.p, d.R[0], d.R[1], d.R[2], 2, m1, m2, 2, 4);
+        // separable Chebyshev dilation x -> y -> z; a width of the largest
+        // extent minus one already reaches every cell, so wider ones are cut
+        // to it (same sets, bounded work)
+        const int32_t rmax = std::max(d.R[0], std::max(d.R[1], d.R[2]));
+        const int32_t e1 = std::min(m1, rmax - 1), e2 = std::min(m2, rmax - 1);
+        k_dilate<<<blocks_for(nc), kThreads, 0, st>>>(c0.p, c1.p, d.R[0], d.R[1], d.R[2], 0, e1, e2, 1, 1);
+        k_dilate<<<blocks_for(nc), kThreads, 0, st>>>(c1.p, c0.p, d.R[0], d.R[1], d.R[2], 1, e1, e2, 2, 4);
+        k_dilate<<<blocks_for(nc), kThreads, 0, st>>>(c0.p, c1.p, d.R[0], d.R[1], d.R[2], 2, e1, e2, 2, 4);
         k_vertex_flags<<<blocks_for(nv), kThreads, 0, st>>>(c1.p, vf.p, d.R[0], d.R[1], d.R[2]);
         k_brick_active<<<blocks_for(nbt), kThreads, 0, st>>>(vf.p, d, active.p);
         size_t need = 0;

@@ -142,7 +142,8 @@ gp_status gp_build_band(gp_ctx ctx, const gp_shape* shapes, int32_t n_shapes, co
     if (!ctx) return GP_ERR_ARG;
     ctx->err.clear();
     if (!shapes || n_shapes < 1) return gp_fail(ctx, GP_ERR_ARG, "need at least one shape");
-    if (m1 < 0 || m2 < 0 || m1 > 64 || m2 > 64) return gp_fail(ctx, GP_ERR_ARG, "m1 and m2 must lie in [0, 64]");
+    if (m1 < 0 || m2 < 0 || m1 > 1024 || m2 > 1024)
+        return gp_fail(ctx, GP_ERR_ARG, "m1 and m2 must lie in [0, 1024]");
     if (brick != 8) return gp_fail(ctx, GP_ERR_ARG, "only 8^3 bricks are supported");
     bool any_points = false;
     for (int32_t s = 0; s < n_shapes; ++s) {
@@ -189,30 +190,34 @@ gp_status gp_nn_query(gp_ctx ctx, const float* qx, const float* qy, const float*
     return gp_nn_impl(ctx, qx, qy, qz, nn_out);
 }
 
-gp_status gp_set_nn_params(gp_ctx ctx, int32_t group_span, int32_t first_shell)
+gp_status gp_set_nn_params(gp_ctx ctx, int32_t group_span, int32_t first_shell, int32_t tile_parts)
 {
     if (!ctx) return GP_ERR_ARG;
     if (group_span < 1 || group_span > gp::kNnSpanMax)
         return gp_fail(ctx, GP_ERR_ARG, "group_span must be in [1, 64]");
     if (first_shell < 0 || first_shell > gp::kNnShellMax)
         return gp_fail(ctx, GP_ERR_ARG, "first_shell must be in [0, 4]");
+    if (tile_parts != 1 && tile_parts != 2 && tile_parts != 4)
+        return gp_fail(ctx, GP_ERR_ARG, "tile_parts must be 1, 2 or 4");
     ctx->nn_params.span = group_span;
     ctx->nn_params.shell = first_shell;
+    ctx->nn_params.parts = tile_parts;
     return GP_OK;
 }
 
-gp_status gp_get_nn_params(gp_ctx ctx, int32_t* group_span, int32_t* first_shell)
+gp_status gp_get_nn_params(gp_ctx ctx, int32_t* group_span, int32_t* first_shell, int32_t* tile_parts)
 {
     if (!ctx) return GP_ERR_ARG;
-    if (!group_span || !first_shell) return gp_fail(ctx, GP_ERR_ARG, "null output");
+    if (!group_span || !first_shell || !tile_parts) return gp_fail(ctx, GP_ERR_ARG, "null output");
     *group_span = ctx->nn_params.span;
     *first_shell = ctx->nn_params.shell;
+    *tile_parts = ctx->nn_params.parts;
     return GP_OK;
 }
 
 gp_status gp_autotune_nn(gp_ctx ctx, const float* qx, const float* qy, const float* qz, int64_t n_queries,
                          int32_t* nn_out, int32_t reps, int32_t* group_span_out, int32_t* first_shell_out,
-                         float* best_ms_out)
+                         int32_t* tile_parts_out, float* best_ms_out)
 {
     gp_status st = ready(ctx);
     if (st != GP_OK) return st;
@@ -224,6 +229,7 @@ gp_status gp_autotune_nn(gp_ctx ctx, const float* qx, const float* qy, const flo
     if ((st = gp_autotune_nn_impl(ctx, qx, qy, qz, nn_out, reps, &best, &ms)) != GP_OK) return st;
     if (group_span_out) *group_span_out = best.span;
     if (first_shell_out) *first_shell_out = best.shell;
+    if (tile_parts_out) *tile_parts_out = best.parts;
     if (best_ms_out) *best_ms_out = ms;
     return GP_OK;
 }

@@ -63,12 +63,14 @@ struct Band {
 };
 
 // Nearest-neighbour search shape: a group of queries is cut where its cells
-// would span `span` or more cells on an axis, and its lockstep box is the
-// group's cell box grown by `shell` cells.  Any values give the same exact
-// result; they only move work between the lockstep and per-query passes.
+// would span `span` or more cells on an axis, its lockstep box is the group's
+// cell box grown by `shell` cells, and `parts` blocks (1, 2 or 4) share each
+// query tile.  Any values give the same exact result; they only move work
+// between the lockstep and per-query passes and between blocks.
 struct NnParams {
     int32_t span = 8;
     int32_t shell = 1;
+    int32_t parts = 1;
 };
 constexpr int32_t kNnSpanMax = 64;
 constexpr int32_t kNnShellMax = 4;

@@ -490,7 +490,10 @@ __global__ __launch_bounds__(kQueryBlock, 4) void k_nn(Band B, Global G, NnParam
     __shared__ int32_t s_ngroups[kWaves];
     __shared__ float4 s_tq[kWaves][kTail];
 
-    const int64_t tile = blockIdx.x;
+    // P.parts blocks share a tile: each sorts all of it and scans its own
+    // contiguous share of the sorted positions (more blocks for small batches)
+    const int64_t tile = blockIdx.x / P.parts;
+    const int32_t part = (int32_t)(blockIdx.x % P.parts);
     const int32_t shape = B.tile_shape[tile];
     const ShapeDesc& s = B.shapes[shape];
     const int64_t q0 = B.tile_start[tile];
@@ -546,8 +549,9 @@ __global__ __launch_bounds__(kQueryBlock, 4) void k_nn(Band B, Global G, NnParam
     // each group's first position the next 64 cells are loaded one per lane;
     // prefix minima and maxima over the lanes give the span of every prefix,
     // and the group ends before the first lane whose prefix does not fit.
-    const int32_t wb0 = __builtin_amdgcn_readfirstlane(min(wave * kWaveSpan, nq));
-    const int32_t we0 = __builtin_amdgcn_readfirstlane(min(wb0 + kWaveSpan, nq));
+    const int32_t wspan = kWaveSpan / P.parts;
+    const int32_t wb0 = __builtin_amdgcn_readfirstlane(min((part * kWaves + wave) * wspan, nq));
+    const int32_t we0 = __builtin_amdgcn_readfirstlane(min(wb0 + wspan, nq));
     {
         int32_t ng = 0;
         for (int32_t g = wb0; g < we0; ++ng) {
@@ -707,34 +711,27 @@ gp_status gp_nn_impl(gp_ctx ctx, const float* qx, const float* qy, const float* 
     if (ctx->n_tiles == 0) return GP_OK;
     Global G{ctx->cell_start.p, ctx->spts.p};
     GP_TIMED(ctx, "k_nn");
-    k_nn<<<(unsigned)ctx->n_tiles, kQueryBlock, 0, ctx->stream>>>(ctx->band(), G, ctx->nn_params, qx, qy, qz, nn);
+    k_nn<<<(unsigned)(ctx->n_tiles * ctx->nn_params.parts), kQueryBlock, 0, ctx->stream>>>(ctx->band(), G,
+                                                                                          ctx->nn_params, qx, qy, qz, nn);
     GP_HIP(ctx, hipGetLastError());
     return GP_OK;
 }
 
 // Times k_nn for every (span, shell) pair of a small grid on the caller's
-// queries (the results are the same for all of them) and keeps the fastest in
-// the context.  Each candidate runs once untimed, then `reps` times between
-// events; its time is the smallest of those.  The context's current setting
-// is timed first and is only replaced by one at least 2% faster, so timing
-// noise does not move a setting that is already as good.
+// queries (the results are the same for all of them), then the number of
+// blocks per tile for the best pair, and keeps the fastest in the context.
+// Each candidate runs once untimed, then `reps` times between events; its
+// time is the smallest of those.  The context's current setting is timed
+// first and is only replaced by one at least 2% faster, so timing noise does
+// not move a setting that is already as good.
 gp_status gp_autotune_nn_impl(gp_ctx ctx, const float* qx, const float* qy, const float* qz, int32_t* nn,
                               int32_t reps, NnParams* best_out, float* best_ms_out)
 {
     static const int32_t spans[] = {4, 6, 8, 12, 16, 24, 32};
     static const int32_t shells[] = {0, 1, 2};
-    constexpr int kCandidates = 1 + 7 * 3;
-    NnParams cand[kCandidates];
-    cand[0] = ctx->nn_params;
-    int nc = 1;
-    for (int32_t sp : spans)
-        for (int32_t sh : shells) {
-            if (sp == cand[0].span && sh == cand[0].shell) continue;
-            cand[nc].span = sp;
-            cand[nc].shell = sh;
-            ++nc;
-        }
-    NnParams best = ctx->nn_params;
+    static const int32_t parts[] = {1, 2, 4};
+    const NnParams current = ctx->nn_params;
+    NnParams best = current;
     float best_ms = -1.f;
     if (ctx->n_tiles > 0) {
         Global G{ctx->cell_start.p, ctx->spts.p};
@@ -746,12 +743,12 @@ gp_status gp_autotune_nn_impl(gp_ctx ctx, const float* qx, const float* qy, cons
             return GP_ERR_DEVICE;
         }
         hipError_t e = hipSuccess;
-        for (int c = 0; c < nc && e == hipSuccess; ++c) {
-            const NnParams P = cand[c];
+        auto time_one = [&](const NnParams& P) -> float {
             float t_min = -1.f;
             for (int32_t r = 0; r <= reps && e == hipSuccess; ++r) {
                 if (r > 0) e = hipEventRecord(ev[0], ctx->stream);
-                k_nn<<<(unsigned)ctx->n_tiles, kQueryBlock, 0, ctx->stream>>>(ctx->band(), G, P, qx, qy, qz, nn);
+                k_nn<<<(unsigned)(ctx->n_tiles * P.parts), kQueryBlock, 0, ctx->stream>>>(ctx->band(), G, P, qx, qy,
+                                                                                            qz, nn);
                 if (e == hipSuccess) e = hipGetLastError();
                 if (r > 0 && e == hipSuccess) e = hipEventRecord(ev[1], ctx->stream);
                 if (r > 0 && e == hipSuccess) e = hipEventSynchronize(ev[1]);
@@ -759,18 +756,39 @@ gp_status gp_autotune_nn_impl(gp_ctx ctx, const float* qx, const float* qy, cons
                 if (r > 0 && e == hipSuccess) e = hipEventElapsedTime(&ms, ev[0], ev[1]);
                 if (r > 0 && e == hipSuccess && (t_min < 0.f || ms < t_min)) t_min = ms;
             }
-            if (e != hipSuccess) break;
-            const float need = c == 0 || !(best.span == cand[0].span && best.shell == cand[0].shell) ? 1.f : 0.98f;
-            if (t_min >= 0.f && (best_ms < 0.f || t_min < best_ms * need)) {
-                best_ms = t_min;
+            return t_min;
+        };
+        // a challenger must beat the current setting by 2%, anything else plainly
+        auto offer = [&](const NnParams& P) {
+            const float t = time_one(P);
+            if (e != hipSuccess || t < 0.f) return;
+            const bool holding = best.span == current.span && best.shell == current.shell &&
+                                 best.parts == current.parts;
+            if (best_ms < 0.f || t < best_ms * (holding ? 0.98f : 1.f)) {
+                best_ms = t;
                 best = P;
             }
+        };
+        offer(current);
+        for (int32_t sp : spans)
+            for (int32_t sh : shells) {
+                NnParams P = current;
+                P.span = sp;
+                P.shell = sh;
+                if (sp != current.span || sh != current.shell) offer(P);
+            }
+        const NnParams shaped = best;
+        for (int32_t pa : parts) {
+            NnParams P = shaped;
+            P.parts = pa;
+            if (pa != shaped.parts) offer(P);
         }
         (void)hipEventDestroy(ev[0]);
         (void)hipEventDestroy(ev[1]);
         GP_HIP(ctx, e);
         // leave nn holding the chosen configuration's (identical) result
-        k_nn<<<(unsigned)ctx->n_tiles, kQueryBlock, 0, ctx->stream>>>(ctx->band(), G, best, qx, qy, qz, nn);
+        k_nn<<<(unsigned)(ctx->n_tiles * best.parts), kQueryBlock, 0, ctx->stream>>>(ctx->band(), G, best, qx, qy, qz,
+                                                                                       nn);
         GP_HIP(ctx, hipGetLastError());
     }
     ctx->nn_params = best;

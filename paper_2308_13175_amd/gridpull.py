@@ -66,10 +66,10 @@ def load_library(path: str = LIB_PATH):
         "gp_build_band": (st, [P, ctypes.POINTER(gp_shape), i32, P, P, P, i32, i32, i32,
                                ctypes.POINTER(i64), ctypes.POINTER(i64)]),
         "gp_nn_query": (st, [P, P, P, P, i64, P]),
-        "gp_set_nn_params": (st, [P, i32, i32]),
-        "gp_get_nn_params": (st, [P, ctypes.POINTER(i32), ctypes.POINTER(i32)]),
+        "gp_set_nn_params": (st, [P, i32, i32, i32]),
+        "gp_get_nn_params": (st, [P, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32)]),
         "gp_autotune_nn": (st, [P, P, P, P, i64, P, i32, ctypes.POINTER(i32), ctypes.POINTER(i32),
-                                ctypes.POINTER(f32)]),
+                                ctypes.POINTER(i32), ctypes.POINTER(f32)]),
         "gp_sample_queries": (st, [P, u64, i32, P, f32, P, P, P, P]),
         "gp_pull_forward": (st, [P, P, P, P, P, i64, P, gp_weights, P, P]),
         "gp_pull_backward": (st, [P, P, P, P, P, i64, P, gp_weights, P, P]),
@@ -176,25 +176,26 @@ def gp_nn_query(ctx, qx, qy, qz, nn_out) -> None:
                                            _ptr(qz, torch.float32), qx.numel(), _ptr(nn_out, torch.int32)))
 
 
-def gp_set_nn_params(ctx, group_span: int, first_shell: int) -> None:
-    _check(ctx, load_library().gp_set_nn_params(ctx, int(group_span), int(first_shell)))
+def gp_set_nn_params(ctx, group_span: int, first_shell: int, tile_parts: int = 1) -> None:
+    _check(ctx, load_library().gp_set_nn_params(ctx, int(group_span), int(first_shell), int(tile_parts)))
 
 
-def gp_get_nn_params(ctx) -> Tuple[int, int]:
-    span, shell = ctypes.c_int32(0), ctypes.c_int32(0)
-    _check(ctx, load_library().gp_get_nn_params(ctx, ctypes.byref(span), ctypes.byref(shell)))
-    return span.value, shell.value
+def gp_get_nn_params(ctx) -> Tuple[int, int, int]:
+    span, shell, parts = ctypes.c_int32(0), ctypes.c_int32(0), ctypes.c_int32(0)
+    _check(ctx, load_library().gp_get_nn_params(ctx, ctypes.byref(span), ctypes.byref(shell), ctypes.byref(parts)))
+    return span.value, shell.value, parts.value
 
 
-def gp_autotune_nn(ctx, qx, qy, qz, nn_out, reps: int = 2) -> Tuple[int, int, float]:
-    """Time the NN search shapes on these queries and keep the fastest: (group_span, first_shell, ms)."""
+def gp_autotune_nn(ctx, qx, qy, qz, nn_out, reps: int = 2) -> Tuple[int, int, int, float]:
+    """Time the NN search shapes on these queries and keep the fastest:
+    (group_span, first_shell, tile_parts, ms)."""
     _stream(ctx)
-    span, shell, ms = ctypes.c_int32(0), ctypes.c_int32(0), ctypes.c_float(0.0)
+    span, shell, parts, ms = ctypes.c_int32(0), ctypes.c_int32(0), ctypes.c_int32(0), ctypes.c_float(0.0)
     _check(ctx, load_library().gp_autotune_nn(ctx, _ptr(qx, torch.float32), _ptr(qy, torch.float32),
                                               _ptr(qz, torch.float32), qx.numel(), _ptr(nn_out, torch.int32),
                                               int(reps), ctypes.byref(span), ctypes.byref(shell),
-                                              ctypes.byref(ms)))
-    return span.value, shell.value, ms.value
+                                              ctypes.byref(parts), ctypes.byref(ms)))
+    return span.value, shell.value, parts.value, ms.value
 
 
 def gp_sample_queries(ctx, seed: int, iteration: int, sigma, sigma_const: float, qx, qy, qz, src_out=None) -> None:

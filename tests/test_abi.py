@@ -87,6 +87,10 @@ def test_state_and_argument_errors():
         with pytest.raises(gp.GridPullError) as e:
             gp.gp_build_band(ctx, [gp.make_shape(dom.dims, dom.lo, dom.hi, 0, 2, 0, 4)] * 2, px, py, pz, 3, 3)
         assert e.value.status == 1            # overlapping slices
+        for m1, m2 in [(-1, 3), (3, 1025)]:
+            with pytest.raises(gp.GridPullError) as e:
+                gp.gp_build_band(ctx, [good], px, py, pz, m1, m2)
+            assert e.value.status == 1        # band width out of range
         bad = torch.tensor([[0.1, 0.2, 0.3], [1.5, 0.0, 0.0]], device="cuda")
         with pytest.raises(gp.GridPullError) as e:
             gp.gp_build_band(ctx, [good], *[bad[:, a].contiguous() for a in range(3)], 3, 3)

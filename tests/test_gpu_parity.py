@@ -43,7 +43,7 @@ def _oracle(dom, pts, q, D, m1=3, m2=3, weights=(1.0, 1.0, 0.005)):
     return cf, vf, nn, ref
 
 
-@pytest.mark.parametrize("m1,m2", [(3, 3), (1, 4), (4, 2)])
+@pytest.mark.parametrize("m1,m2", [(3, 3), (1, 4), (4, 2), (3, 14)])
 def test_sphere_64_parity(m1, m2):
     log("case: sphere 64^3 J=10k Q=50k m1=%d m2=%d" % (m1, m2))
     dom, pts, q, D = _sphere_case()
@@ -90,15 +90,16 @@ def test_anisotropic_grid_and_edge_cases():
     prob.close()
 
 
-def test_dense_band_when_m_covers_the_grid():
-    log("case: M >= R (every cell optimised)")
+@pytest.mark.parametrize("m1,m2", [(12, 12), (100, 3), (3, 1024), (11, 11)])
+def test_dense_band_when_m_covers_the_grid(m1, m2):
+    log("case: M >= R - 1 (every cell in the band), m1=%d m2=%d" % (m1, m2))
     dom = synth.cube_domain(12)
     pts = synth.sphere_points(500, 0.5, seed=9)
     q = synth.host_queries(pts, 3000, 0.2, seed=10)
     D = synth.sphere_sdf_field(dom, 0.5, noise=0.05, seed=1)
-    prob = _run_gpu(dom, pts, q, D, 12, 12)
-    cf, vf, nn, ref = _oracle(dom, pts, q, D, 12, 12)
-    assert np.all(cf & 2) and np.all(vf & 1)
+    prob = _run_gpu(dom, pts, q, D, m1, m2)
+    cf, vf, nn, ref = _oracle(dom, pts, q, D, m1, m2)
+    assert np.all(cf & (2 if m1 >= 11 else 4)) and np.all(vf & 1)
     compare_band(prob, 0, dom, cf, vf)
     got, nv = loss_terms(prob)
     assert int(nv[0]) == ref["n_valid"]
@@ -326,10 +327,10 @@ def test_batch_with_a_shape_without_queries_and_a_one_point_shape():
 
 
 def test_nn_search_shapes_and_autotuner():
-    """Every NN search shape (group span, first shell), including the
-    extremes, and the autotuner's choice give the oracle's indices exactly, on
-    the exact-tie lattice and on a sparse sphere (few points per cell, so most
-    queries leave the lockstep box open)."""
+    """Every NN search shape (group span, first shell, blocks per tile),
+    including the extremes, and the autotuner's choice give the oracle's
+    indices exactly, on the exact-tie lattice and on a sparse sphere (few
+    points per cell, so most queries leave the lockstep box open)."""
     from paper_2308_13175_amd import gridpull as gp
     sparse = synth.cube_domain(64), synth.sphere_points(1500, 0.5, seed=7)
     cases = [("ties",) + _tie_case()[:3],
@@ -338,30 +339,30 @@ def test_nn_search_shapes_and_autotuner():
         nn = oracle.nn_bruteforce(q, pts)
         prob = make_problem([spec(pts, dom, len(q), 0.0)])
         prob.set_queries(q)
-        assert gp.gp_get_nn_params(prob.ctx) == (8, 1)
-        for span, shell in [(1, 0), (2, 0), (3, 2), (8, 1), (16, 0), (64, 4)]:
-            log("case: %s, group span %d, first shell %d" % (name, span, shell))
-            gp.gp_set_nn_params(prob.ctx, span, shell)
+        assert gp.gp_get_nn_params(prob.ctx) == (8, 1, 1)
+        for span, shell, parts in [(1, 0, 1), (2, 0, 4), (3, 2, 2), (8, 1, 4), (16, 0, 2), (64, 4, 1), (64, 4, 4)]:
+            log("case: %s, group span %d, first shell %d, %d blocks per tile" % (name, span, shell, parts))
+            gp.gp_set_nn_params(prob.ctx, span, shell, parts)
             prob.nn.fill_(-7)
             prob.nearest()
             prob.sync()
             got = prob.nn[: len(q)].cpu().numpy()
             bad = np.nonzero(got != nn)[0]
-            assert len(bad) == 0, "%s span %d shell %d: %d differ" % (name, span, shell, len(bad))
+            assert len(bad) == 0, "%s span %d shell %d parts %d: %d differ" % (name, span, shell, parts, len(bad))
         log("case: %s, autotuner" % name)
-        gp.gp_set_nn_params(prob.ctx, 8, 1)   # the tuner starts from the current setting
+        gp.gp_set_nn_params(prob.ctx, 8, 1, 1)   # the tuner starts from the current setting
         prob.nn.fill_(-7)
-        span, shell, ms = prob.autotune(reps=1)
+        span, shell, parts, ms = prob.autotune(reps=1)
         prob.sync()
-        assert span in (4, 6, 8, 12, 16, 24, 32) and shell in (0, 1, 2) and ms > 0
-        assert gp.gp_get_nn_params(prob.ctx) == (span, shell)
+        assert span in (4, 6, 8, 12, 16, 24, 32) and shell in (0, 1, 2) and parts in (1, 2, 4) and ms > 0
+        assert gp.gp_get_nn_params(prob.ctx) == (span, shell, parts)
         assert np.array_equal(prob.nn[: len(q)].cpu().numpy(), nn)
         prob.nearest()
         prob.sync()
         assert np.array_equal(prob.nn[: len(q)].cpu().numpy(), nn)
-        for bad_args in [(0, 1), (65, 1), (8, -1), (8, 5)]:
+        for bad_args in [(0, 1, 1), (65, 1, 1), (8, -1, 1), (8, 5, 1), (8, 1, 3), (8, 1, 0)]:
             with pytest.raises(gp.GridPullError) as ei:
                 gp.gp_set_nn_params(prob.ctx, *bad_args)
             assert ei.value.status == 1
-        assert gp.gp_get_nn_params(prob.ctx) == (span, shell)
+        assert gp.gp_get_nn_params(prob.ctx) == (span, shell, parts)
         prob.close()
