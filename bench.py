@@ -317,6 +317,7 @@ def schedule_sweep(kind: str, iters: int = 1600, n_points: int = 200_000, n_quer
     """
     import torch
 
+    from paper_2308_13175_amd import gridpull as gp
     from paper_2308_13175_amd import synth
     from paper_2308_13175_amd.problem import AdamConfig, GraphedIteration, Problem, ShapeSpec
 
@@ -351,13 +352,22 @@ def schedule_sweep(kind: str, iters: int = 1600, n_points: int = 200_000, n_quer
         run_s = time.perf_counter() - t0
         prob.sync()
         loss = prob.loss.cpu().numpy()[0]
+        # per-kernel event times over a few extra eager iterations
+        gp.gp_timing_enable(prob.ctx, True)
+        gp.gp_timing_report(prob.ctx)
+        for _ in range(10):
+            prob.iteration(None)
+        torch.cuda.synchronize()
+        kern = gp.gp_timing_report(prob.ctx)
+        gp.gp_timing_enable(prob.ctx, False)
         _, flags = prob.layout()
         print(json.dumps({
             "sweep": kind, "workload": "torus-200k", "res": res, "m1": m1, "m2": m2, "iterations": iters,
             "queries_per_iteration": n_queries, "run_s": run_s, "ms_per_iteration": run_s * 1e3 / iters,
             "setup_s": setup_s, "slots": prob.n_slots, "optimised_vertices": prob.n_active,
             "tv_vertices": int(((flags & 2) > 0).sum()), "final_loss": [float(x) for x in loss],
-            "final_valid": int(prob.n_valid.sum()), "nn_search": list(nn_search)}), flush=True)
+            "final_valid": int(prob.n_valid.sum()), "nn_search": list(nn_search),
+            "kernels_avg_ms": {k: round(ms / max(n, 1), 5) for k, (n, ms) in sorted(kern.items())}}), flush=True)
         del graph
         prob.close()
         del prob

@@ -476,6 +476,9 @@ __device__ inline uint32_t compact3(uint32_t v)
 constexpr int kWaves = kQueryBlock / 64;
 constexpr int kWaveSpan = kQueryTile / kWaves;   // sorted positions grouped and scanned by one wave
 
+// kTuning only names the instance: the autotuner launches k_nn<true>, so
+// kernel traces keep its trial launches apart from the search itself.
+template <bool kTuning>
 __global__ __launch_bounds__(kQueryBlock, 4) void k_nn(Band B, Global G, NnParams P, const float* __restrict__ qx,
                                                     const float* __restrict__ qy, const float* __restrict__ qz,
                                                     int32_t* __restrict__ nn)
@@ -711,7 +714,7 @@ gp_status gp_nn_impl(gp_ctx ctx, const float* qx, const float* qy, const float* 
     if (ctx->n_tiles == 0) return GP_OK;
     Global G{ctx->cell_start.p, ctx->spts.p};
     GP_TIMED(ctx, "k_nn");
-    k_nn<<<(unsigned)(ctx->n_tiles * ctx->nn_params.parts), kQueryBlock, 0, ctx->stream>>>(ctx->band(), G,
+    k_nn<false><<<(unsigned)(ctx->n_tiles * ctx->nn_params.parts), kQueryBlock, 0, ctx->stream>>>(ctx->band(), G,
                                                                                           ctx->nn_params, qx, qy, qz, nn);
     GP_HIP(ctx, hipGetLastError());
     return GP_OK;
@@ -747,7 +750,7 @@ gp_status gp_autotune_nn_impl(gp_ctx ctx, const float* qx, const float* qy, cons
             float t_min = -1.f;
             for (int32_t r = 0; r <= reps && e == hipSuccess; ++r) {
                 if (r > 0) e = hipEventRecord(ev[0], ctx->stream);
-                k_nn<<<(unsigned)(ctx->n_tiles * P.parts), kQueryBlock, 0, ctx->stream>>>(ctx->band(), G, P, qx, qy,
+                k_nn<true><<<(unsigned)(ctx->n_tiles * P.parts), kQueryBlock, 0, ctx->stream>>>(ctx->band(), G, P, qx, qy,
                                                                                             qz, nn);
                 if (e == hipSuccess) e = hipGetLastError();
                 if (r > 0 && e == hipSuccess) e = hipEventRecord(ev[1], ctx->stream);
@@ -787,7 +790,7 @@ gp_status gp_autotune_nn_impl(gp_ctx ctx, const float* qx, const float* qy, cons
         (void)hipEventDestroy(ev[1]);
         GP_HIP(ctx, e);
         // leave nn holding the chosen configuration's (identical) result
-        k_nn<<<(unsigned)(ctx->n_tiles * best.parts), kQueryBlock, 0, ctx->stream>>>(ctx->band(), G, best, qx, qy, qz,
+        k_nn<true><<<(unsigned)(ctx->n_tiles * best.parts), kQueryBlock, 0, ctx->stream>>>(ctx->band(), G, best, qx, qy, qz,
                                                                                        nn);
         GP_HIP(ctx, hipGetLastError());
     }
