@@ -245,7 +245,7 @@ __device__ inline void eval_chunk(const float4* __restrict__ buf, int32_t cnt, S
         const bool lt = d2f < b1;
         b2 = __builtin_amdgcn_fmed3f(b1, b2, d2f);
         id = lt ? __float_as_int(p.w) : id;
-        b1 = fminf(b1, d2f);
+        b1 = lt ? d2f : b1;   // a select on the same compare (no NaN canonicalisation of a min)
     }
     q.best1 = b1;
     q.best2 = b2;
@@ -329,7 +329,7 @@ struct Tail {
                 const bool lt = d < b1[k];
                 b2[k] = __builtin_amdgcn_fmed3f(b1[k], b2[k], d);
                 id[k] = lt ? __float_as_int(p.w) : id[k];
-                b1[k] = fminf(b1[k], d);
+                b1[k] = lt ? d : b1[k];
             }
         }
     }

@@ -169,6 +169,7 @@ constexpr int kGradBlock = kQueryTile / kGradParts;    // one query per thread
 constexpr int kOctVol = 64;                       // vertices per octant
 constexpr int kCacheOcts = 72;                    // LDS octant accumulators per block (72 x 512 B)
 constexpr int kCacheTable = 256;                  // open-addressing table: octant key -> LDS octant
+constexpr int kCacheProbes = 32;                  // longest probe sequence before a key is left uncached
 constexpr double kFixScale = 4294967296.0;        // 2^32
 constexpr float kFixLimit = 1048576.f;            // 2^20
 
@@ -199,11 +200,15 @@ __device__ inline int32_t table_home(int32_t key)
     return (int32_t)(((uint32_t)key * 2654435761u) >> 24);
 }
 
+// Both walk the same probe sequence and give up after kCacheProbes places, so
+// a key that found no free place within it is not cached (its contributions
+// go straight to memory) and a lookup stops as soon: a block whose queries
+// touch more octants than the table holds costs a bounded number of probes.
 __device__ inline void cache_insert(int32_t* keys, int32_t key)
 {
     int32_t h = table_home(key);
 #pragma unroll 1
-    for (int p = 0; p < kCacheTable; ++p) {
+    for (int p = 0; p < kCacheProbes; ++p) {
         const int32_t old = atomicCAS(&keys[h], -1, key);
         if (old == -1 || old == key) return;
         h = (h + 1) & (kCacheTable - 1);
@@ -214,7 +219,7 @@ __device__ inline int32_t cache_find(const int32_t* keys, const int32_t* idx, in
 {
     int32_t h = table_home(key);
 #pragma unroll 1
-    for (int p = 0; p < kCacheTable; ++p) {
+    for (int p = 0; p < kCacheProbes; ++p) {
         const int32_t k = keys[h];
         if (k == key) return idx[h];
         if (k == -1) return -1;
