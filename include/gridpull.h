@@ -128,7 +128,8 @@ gp_status gp_sync(gp_ctx ctx);
  * Synchronises.  May be called again to rebuild (previous state is dropped).
  * Errors: GP_ERR_ARG (null pointers, n_shapes < 1, dims < 1, hi <= lo,
  * m out of range), GP_ERR_DOMAIN (a point outside its shape's box),
- * GP_ERR_CAPACITY (more than 2^31 slots or points), GP_ERR_OOM.
+ * GP_ERR_CAPACITY (more than 2^30 slots or brick directory entries, or
+ * more than 2^31 points), GP_ERR_OOM.
  */
 gp_status gp_build_band(gp_ctx ctx, const gp_shape* shapes, int32_t n_shapes,
                         const float* px, const float* py, const float* pz,

@@ -300,6 +300,7 @@ gp_status gp_build_band_impl(gp_ctx ctx, const gp_shape* shapes, int32_t n_shape
     }
     if (sorted_total >= ((int64_t)1 << 31) || n_points >= ((int64_t)1 << 31))
         return gp_fail(ctx, GP_ERR_CAPACITY, "more than 2^31 points");
+    if (dir_total >= kMaxSlots) return gp_fail(ctx, GP_ERR_CAPACITY, "more than 2^30 brick directory entries");
 
     DevBuf<ShapeDesc> d_shape1;
     GP_HIP(ctx, d_shape1.alloc(1));
@@ -357,8 +358,8 @@ gp_status gp_build_band_impl(gp_ctx ctx, const gp_shape* shapes, int32_t n_shape
         GP_HIP(ctx, hipMemcpyAsync(&last_act, active.p + nbt - 1, 4, hipMemcpyDeviceToHost, st));
         GP_HIP(ctx, hipStreamSynchronize(st));
         const int64_t nb_s = (int64_t)last_idx + last_act;
-        if ((brick_base + nb_s) * kBrickVol >= ((int64_t)1 << 31))
-            return gp_fail(ctx, GP_ERR_CAPACITY, "more than 2^31 field slots");
+        if ((brick_base + nb_s) * kBrickVol >= kMaxSlots)
+            return gp_fail(ctx, GP_ERR_CAPACITY, "more than 2^30 field slots");
 
         auto part = std::make_unique<ShapeBricks>();
         part->n_dir = nbt;

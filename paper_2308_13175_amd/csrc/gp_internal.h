@@ -7,6 +7,7 @@
 #include <stdint.h>
 
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "gridpull.h"
@@ -19,6 +20,9 @@ constexpr int kMaskWords = kBrickVol / 32;
 constexpr int kQueryBlock = 256;          // threads per block of the query kernels
 constexpr int kQueriesPerThread = 4;
 constexpr int kQueryTile = kQueryBlock * kQueriesPerThread;
+// Field slots and brick directory entries stay below 2^30, so that 4-byte
+// elements are addressed with 32-bit byte offsets (see at32).
+constexpr int64_t kMaxSlots = (int64_t)1 << 30;
 constexpr double kEpsNorm = 1e-12;        // |grad f| below this: no normalised gradient
 
 // Per-shape constants as the kernels see them.
@@ -104,6 +108,17 @@ __device__ inline Loc locate(const ShapeDesc& s, float x, float y, float z)
     return L;
 }
 
+// Element i (< 2^30) of a 4-byte array through a 32-bit byte offset: with a
+// uniform base the load takes the scalar-base plus vector-offset form, with
+// no 64-bit address arithmetic per lane.
+template <class T>
+__device__ inline T* at32(T* base, uint32_t i)
+{
+    static_assert(sizeof(T) == 4, "4-byte elements");
+    using Byte = typename std::conditional<std::is_const<T>::value, const char, char>::type;
+    return reinterpret_cast<T*>(reinterpret_cast<Byte*>(base) + i * 4u);
+}
+
 __device__ inline int32_t brick_of(const Band& B, const ShapeDesc& s, int32_t bx, int32_t by, int32_t bz)
 {
     return B.dir[s.dir_off + ((int64_t)bx * s.nb[1] + by) * s.nb[2] + bz];
@@ -121,19 +136,25 @@ __device__ inline bool mask_bit(const uint32_t* m, int32_t brick, int32_t local)
 
 // Slots of the eight corners of cell c, corner (a,b,c) at index 4a+2b+c.
 // Every corner of an M1-band cell exists, so no -1 is returned for them.
+// The corner one step up an axis lies in the next brick only when the cell
+// sits on the brick's last layer of that axis, so the eight directory
+// entries are one base entry plus fixed strides.
 __device__ inline void corner_slots(const Band& B, const ShapeDesc& s, const int32_t c[3], int32_t slot[8])
 {
-    int32_t bx[2] = {c[0] >> 3, (c[0] + 1) >> 3};
-    int32_t by[2] = {c[1] >> 3, (c[1] + 1) >> 3};
-    int32_t bz[2] = {c[2] >> 3, (c[2] + 1) >> 3};
+    const uint32_t e0 = (uint32_t)s.dir_off + ((uint32_t)(c[0] >> 3) * s.nb[1] + (c[1] >> 3)) * s.nb[2] + (c[2] >> 3);
+    const uint32_t st[3] = {(c[0] & 7) == 7 ? (uint32_t)(s.nb[1] * s.nb[2]) : 0u, (c[1] & 7) == 7 ? (uint32_t)s.nb[2] : 0u,
+                            (c[2] & 7) == 7 ? 1u : 0u};
+    const int32_t lx[2] = {(c[0] & 7) << 6, ((c[0] + 1) & 7) << 6};
+    const int32_t ly[2] = {(c[1] & 7) << 3, ((c[1] + 1) & 7) << 3};
+    const int32_t lz[2] = {c[2] & 7, (c[2] + 1) & 7};
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
         for (int b = 0; b < 2; ++b)
 #pragma unroll
             for (int d = 0; d < 2; ++d) {
-                int32_t br = brick_of(B, s, bx[a], by[b], bz[d]);
-                slot[4 * a + 2 * b + d] = br * kBrickVol + local_index(c[0] + a, c[1] + b, c[2] + d);
+                const int32_t br = *at32(B.dir, e0 + a * st[0] + b * st[1] + d * st[2]);
+                slot[4 * a + 2 * b + d] = br * kBrickVol + lx[a] + ly[b] + lz[d];
             }
 }
 

@@ -41,7 +41,7 @@ __device__ inline void eval_side(const Band& B, const ShapeDesc& s, const float*
     corner_slots(B, s, L.c, out.slot);
     float v[8];
 #pragma unroll
-    for (int i = 0; i < 8; ++i) v[i] = D[out.slot[i]];
+    for (int i = 0; i < 8; ++i) v[i] = *at32(D, (uint32_t)out.slot[i]);
     out.t[0] = (float)L.t[0];
     out.t[1] = (float)L.t[1];
     out.t[2] = (float)L.t[2];
@@ -173,20 +173,9 @@ constexpr int kCacheProbes = 32;                  // longest probe sequence befo
 constexpr double kFixScale = 4294967296.0;        // 2^32
 constexpr float kFixLimit = 1048576.f;            // 2^20
 
-// Octant key of a slot, and the slot's place inside its octant.
-__device__ inline int32_t oct_key(int32_t slot)
-{
-    const int32_t l = slot & (kBrickVol - 1);
-    return ((slot >> 9) << 3) | ((l >> 6) & 4) | ((l >> 4) & 2) | ((l >> 2) & 1);
-}
-
-__device__ inline int32_t oct_index(int32_t slot)
-{
-    const int32_t l = slot & (kBrickVol - 1);
-    return ((l >> 2) & 48) | ((l >> 1) & 12) | (l & 3);
-}
-
-// Slot of place w of octant key.
+// A vertex with brick-local coordinates (x, y, z) in brick br lies in octant
+// key br * 8 + (x >> 2) * 4 + (y >> 2) * 2 + (z >> 2), at place
+// (x & 3) * 16 + (y & 3) * 4 + (z & 3) of it.  Slot of place w of octant key:
 __device__ inline int32_t oct_slot(int32_t key, int32_t w)
 {
     const int32_t o = key & 7;
@@ -264,35 +253,76 @@ __device__ inline void query_adjoint(const ShapeDesc& s, const QueryState& st, g
     trilinear_adjoint(st.s.t, s.inv_hf, dfs, dgsf, cs);
 }
 
-__device__ inline void insert_slot_octs(const int32_t slot[8], int32_t* keys)
+// Octant key and place of the corners of a cell whose lowest corner has
+// brick-local coordinates packed 3 bits per axis (x lowest): corner (a, b, d)
+// lies in octant (slot >> 9) * 8 + k[0][a] + k[1][b] + k[2][d] at place
+// i[0][a] + i[1][b] + i[2][d] (a corner in the next brick along an axis has
+// local coordinate 0 there, which (l + 1) & 7 gives).
+struct CornerOct {
+    int32_t k[3][2], i[3][2];
+};
+
+__device__ inline CornerOct corner_oct(int32_t packed)
 {
-    int32_t last = -1;
+    CornerOct o;
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
-        const int32_t key = oct_key(slot[i]);
-        if (key != last) cache_insert(keys, key);
-        last = key;
+    for (int ax = 0; ax < 3; ++ax) {
+        const int32_t l = (packed >> (3 * ax)) & 7;
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+            const int32_t x = (l + e) & 7;
+            o.k[ax][e] = (x >> 2) << (2 - ax);
+            o.i[ax][e] = (x & 3) << (4 - 2 * ax);
+        }
     }
+    return o;
 }
 
-__device__ inline void scatter_slots(const int32_t slot[8], const float cv[8], const int32_t* keys,
-                                     const int32_t* idx, unsigned long long* __restrict__ acc,
-                                     float* __restrict__ G, float scale)
+__device__ inline int32_t pack_local(const int32_t c[3])
 {
+    return (c[0] & 7) | ((c[1] & 7) << 3) | ((c[2] & 7) << 6);
+}
+
+__device__ inline void insert_cell_octs(const int32_t slot[8], int32_t packed, int32_t* keys)
+{
+    const CornerOct o = corner_oct(packed);
+    int32_t last = -1;
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int d = 0; d < 2; ++d) {
+                const int32_t key = ((slot[4 * a + 2 * b + d] >> 9) << 3) + o.k[0][a] + o.k[1][b] + o.k[2][d];
+                if (key != last) cache_insert(keys, key);
+                last = key;
+            }
+}
+
+__device__ inline void scatter_cell(const int32_t slot[8], int32_t packed, const float cv[8], const int32_t* keys,
+                                    const int32_t* idx, unsigned long long* __restrict__ acc,
+                                    float* __restrict__ G, float scale)
+{
+    const CornerOct o = corner_oct(packed);
     int32_t last_key = -1, last_li = -1;
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
-        const int32_t key = oct_key(slot[i]);
-        if (key != last_key) {
-            last_key = key;
-            last_li = cache_find(keys, idx, key);
-        }
-        if (last_li >= 0 && fabsf(cv[i]) < kFixLimit)
-            atomicAdd(&acc[last_li * kOctVol + oct_index(slot[i])],
-                      (unsigned long long)__double2ll_rn((double)cv[i] * kFixScale));
-        else
-            atomicAdd(&G[slot[i]], scale * cv[i]);
-    }
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int d = 0; d < 2; ++d) {
+                const int i = 4 * a + 2 * b + d;
+                const int32_t key = ((slot[i] >> 9) << 3) + o.k[0][a] + o.k[1][b] + o.k[2][d];
+                if (key != last_key) {
+                    last_key = key;
+                    last_li = cache_find(keys, idx, key);
+                }
+                if (last_li >= 0 && fabsf(cv[i]) < kFixLimit)
+                    atomicAdd(&acc[last_li * kOctVol + o.i[0][a] + o.i[1][b] + o.i[2][d]],
+                              (unsigned long long)__double2ll_rn((double)cv[i] * kFixScale));
+                else
+                    atomicAdd(at32(G, (uint32_t)slot[i]), scale * cv[i]);
+            }
 }
 
 // One thread per query of a quarter tile: evaluate, take the adjoint, keep the 16
@@ -336,7 +366,7 @@ __global__ __launch_bounds__(kGradBlock) void k_query_grad(Band B, const float* 
 
     const int64_t k = q0 + threadIdx.x;
     float cq[8], cs[8];
-    int32_t sq[8], ss[8];
+    int32_t sq[8], ss[8], lq = 0, ls = 0;
     bool valid = false;
     double part[4] = {0.0, 0.0, 0.0, 0.0};
     if (k < qe) {
@@ -357,8 +387,10 @@ __global__ __launch_bounds__(kGradBlock) void k_query_grad(Band B, const float* 
                 sq[i] = st.q.slot[i];
                 ss[i] = st.s.slot[i];
             }
-            insert_slot_octs(sq, s_keys);
-            insert_slot_octs(ss, s_keys);
+            lq = pack_local(st.q.c);
+            ls = pack_local(st.s.c);
+            insert_cell_octs(sq, lq, s_keys);
+            insert_cell_octs(ss, ls, s_keys);
         }
     }
     __syncthreads();
@@ -380,8 +412,8 @@ __global__ __launch_bounds__(kGradBlock) void k_query_grad(Band B, const float* 
     }
     __syncthreads();
     if (valid) {
-        scatter_slots(sq, cq, s_keys, s_idx, s_acc, G, scale);
-        scatter_slots(ss, cs, s_keys, s_idx, s_acc, G, scale);
+        scatter_cell(sq, lq, cq, s_keys, s_idx, s_acc, G, scale);
+        scatter_cell(ss, ls, cs, s_keys, s_idx, s_acc, G, scale);
     }
     __syncthreads();
     // flush: the cached octants, one atomic per vertex that received anything
