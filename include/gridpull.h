@@ -188,6 +188,16 @@ gp_status gp_autotune_nn(gp_ctx ctx, const float* qx, const float* qy, const flo
                          float* best_ms_out);
 
 /*
+ * Thread layout of the TV kernels (Eq. 5 and its gradient; the same
+ * arithmetic either way): 1 = one block per brick, one thread per vertex;
+ * 2 = one wave per brick, one lane per column of eight vertices; 0 (the
+ * default) = by band size: the forward uses 2 from 2048 bricks on, the
+ * backward from 16384.  The setting belongs to the context.
+ * Errors: GP_ERR_ARG (layout not 0, 1 or 2).
+ */
+gp_status gp_set_tv_layout(gp_ctx ctx, int32_t layout);
+
+/*
  * Draw one iteration's queries (Sec. 3: Gaussian around randomly chosen
  * surface points, resampled every iteration).  For shape s with J points and
  * Q queries, query k uses source point P[(floor(k*J/Q) + o) mod J] where P is

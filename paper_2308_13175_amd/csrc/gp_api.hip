@@ -215,6 +215,14 @@ gp_status gp_get_nn_params(gp_ctx ctx, int32_t* group_span, int32_t* first_shell
     return GP_OK;
 }
 
+gp_status gp_set_tv_layout(gp_ctx ctx, int32_t layout)
+{
+    if (!ctx) return GP_ERR_ARG;
+    if (layout < 0 || layout > 2) return gp_fail(ctx, GP_ERR_ARG, "layout must be 0, 1 or 2");
+    ctx->tv_layout = layout;
+    return GP_OK;
+}
+
 gp_status gp_autotune_nn(gp_ctx ctx, const float* qx, const float* qy, const float* qz, int64_t n_queries,
                          int32_t* nn_out, int32_t reps, int32_t* group_span_out, int32_t* first_shell_out,
                          int32_t* tile_parts_out, float* best_ms_out)

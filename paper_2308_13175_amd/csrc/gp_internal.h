@@ -302,7 +302,7 @@ struct gp_ctx_s {
     // per-iteration scratch
     DevBuf<double> q_part;        // [n_tiles][4] sum pull, surf, grad, count
     DevBuf<double> tv_part;       // [n_bricks] sum tau
-    DevBuf<float> tau;            // [n_slots]
+    DevBuf<float> tau;            // [n_slots] 1 / tau of the last forward (0 where tau = 0)
     DevBuf<double> inv_qv;        // [n_shapes] 1 / valid count (0 if none)
     DevBuf<int32_t> flag;         // device error flag
     DevBuf<int32_t> iter;         // device-resident iteration counter (last Adam t)
@@ -311,6 +311,7 @@ struct gp_ctx_s {
     bool have_forward = false;
 
     gp::NnParams nn_params;       // set by gp_set_nn_params or gp_autotune_nn
+    int32_t tv_layout = 0;        // 0 by band size, 1 block per brick, 2 wave per brick (gp_set_tv_layout)
 
     // optional per-kernel timing with events on the context's stream
     struct TimedLaunch {

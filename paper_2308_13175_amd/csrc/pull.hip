@@ -440,20 +440,30 @@ __global__ __launch_bounds__(kGradBlock) void k_query_grad(Band B, const float* 
     }
 }
 
-// ---- TV (Eq. 5): one block per brick, one thread per vertex.  The brick's
-// field values (and in the backward its tau) are staged in LDS with a halo of
-// one vertex across each face, together with a flag for TV vertices (vertices
-// of an absent brick or outside the grid are not TV vertices).
+// ---- TV (Eq. 5).  A vertex takes part only if it is a TV vertex (V2 mask),
+// and so does each of its six axis neighbours; a missing brick or a vertex
+// outside the grid is not a TV vertex.  The forward stores 1/tau (0 where
+// tau = 0) for the backward, which then divides nothing.  Two layouts of the
+// same arithmetic:
+// - one block per brick, one thread per vertex, the brick and a one-vertex
+//   halo staged in LDS: many waves for a band of few bricks;
+// - one wave per brick, lane (i, j) owning the column of vertices
+//   (i, j, 0..7), which are contiguous slots: the z neighbours are in its own
+//   column, the x and y neighbours in the columns of lanes i +- 1, j +- 1
+//   (shuffles), and what lies across a brick face is loaded from the
+//   neighbouring brick by the lanes on that face.  Five times as many bricks
+//   are in flight per CU, which large bands need.
 
 constexpr int kHalo = kBrick + 2;                        // staged vertices per axis
 constexpr int kHaloVol = kHalo * kHalo * kHalo;
+constexpr int kTvWaves = 4;                              // bricks per block in the wave layout
 
 __device__ inline int32_t halo_index(int32_t i, int32_t j, int32_t k)   // brick-local, -1..8
 {
     return ((i + 1) * kHalo + (j + 1)) * kHalo + (k + 1);
 }
 
-// Stage values of one or two slot arrays (a, b may be null) and the TV flags.
+// Stage values of one or two slot arrays (b may be null) and the TV flags.
 __device__ inline void stage_brick(const Band& B, const ShapeDesc& s, int32_t brick, const BrickInfo& bi,
                                    const float* __restrict__ a, const float* __restrict__ b, float* sa, float* sb,
                                    uint8_t* tv)
@@ -494,8 +504,8 @@ __device__ inline void stage_brick(const Band& B, const ShapeDesc& s, int32_t br
     }
 }
 
-__global__ __launch_bounds__(kBrickVol) void k_tv_forward(Band B, const float* __restrict__ D, float* __restrict__ tau,
-                                                          double* __restrict__ tv_part)
+__global__ __launch_bounds__(kBrickVol) void k_tv_forward_brick(Band B, const float* __restrict__ D,
+                                                                float* __restrict__ itau, double* __restrict__ tv_part)
 {
     __shared__ float s_d[kHaloVol];
     __shared__ uint8_t s_tv[kHaloVol];
@@ -520,7 +530,7 @@ __global__ __launch_bounds__(kBrickVol) void k_tv_forward(Band B, const float* _
             s2 = fmaf(d, d, s2);
         }
         tau_v = sqrtf(s2);
-        tau[brick * kBrickVol + t] = tau_v;
+        itau[brick * kBrickVol + t] = tau_v > 0.f ? 1.f / tau_v : 0.f;
     }
     double v = (double)tau_v;
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
@@ -533,14 +543,15 @@ __global__ __launch_bounds__(kBrickVol) void k_tv_forward(Band B, const float* _
     }
 }
 
-// Gather form of the TV gradient (each vertex writes its own slot).  With
-// raw != nullptr the query contributions accumulated unscaled in raw are
-// added too, times dloss / valid count of the shape, and raw is cleared.
-__global__ __launch_bounds__(kBrickVol) void k_tv_backward(Band B, const float* __restrict__ D,
-                                                           const float* __restrict__ tau, gp_weights w,
-                                                           const double* __restrict__ dloss,
-                                                           const double* __restrict__ inv_qv,
-                                                           float* __restrict__ raw, float* __restrict__ G)
+// Gradient of alpha * L_TV in gather form (every vertex sums over its own
+// neighbours and writes only its own slot), scaled by dloss.  With raw, also
+// adds dloss / valid count times the unscaled query contributions of the
+// fused pass and clears them.
+__global__ __launch_bounds__(kBrickVol) void k_tv_backward_brick(Band B, const float* __restrict__ D,
+                                                                 const float* __restrict__ itau, gp_weights w,
+                                                                 const double* __restrict__ dloss,
+                                                                 const double* __restrict__ inv_qv,
+                                                                 float* __restrict__ raw, float* __restrict__ G)
 {
     __shared__ float s_d[kHaloVol], s_t[kHaloVol];
     __shared__ uint8_t s_tv[kHaloVol];
@@ -548,7 +559,7 @@ __global__ __launch_bounds__(kBrickVol) void k_tv_backward(Band B, const float* 
     const BrickInfo bi = B.bricks[brick];
     const ShapeDesc& s = B.shapes[bi.shape];
     const bool tv_on = s.n_tv > 0;
-    if (tv_on) stage_brick(B, s, brick, bi, D, tau, s_d, s_t, s_tv);
+    if (tv_on) stage_brick(B, s, brick, bi, D, itau, s_d, s_t, s_tv);
     __syncthreads();
     const float scale = tv_on ? (float)((double)w.alpha * dloss[bi.shape] / (double)s.n_tv) : 0.f;
     const float rscale = raw ? (float)(dloss[bi.shape] * inv_qv[bi.shape]) : 0.f;
@@ -568,22 +579,200 @@ __global__ __launch_bounds__(kBrickVol) void k_tv_backward(Band B, const float* 
     const int32_t h = halo_index(li, lj, lk);
     if (tv_on && s_tv[h]) {
         const float dv = s_d[h];
-        const float tv = s_t[h];
-        const float inv_tv = tv > 0.f ? 1.f / tv : 0.f;
+        const float inv_tv = s_t[h];
         const int32_t nbh[6] = {h + kHalo * kHalo, h - kHalo * kHalo, h + kHalo, h - kHalo, h + 1, h - 1};
         float acc = 0.f;
 #pragma unroll
         for (int o = 0; o < 6; ++o) {
             if (!s_tv[nbh[o]]) continue;
-            const float d = dv - s_d[nbh[o]];
-            const float tj = s_t[nbh[o]];
-            const float inv_tj = tj > 0.f ? 1.f / tj : 0.f;
-            acc = fmaf(d, inv_tv + inv_tj, acc);
+            acc = fmaf(dv - s_d[nbh[o]], inv_tv + s_t[nbh[o]], acc);
         }
         add = fmaf(scale, acc, add);
         touch = true;
     }
     if (touch) G[slot] += add;
+}
+
+// The 8 mask bits of column col (0..63) of a brick: vertices col * 8 + k.
+__device__ inline uint32_t col_mask(const uint32_t* m, int32_t brick, int32_t col)
+{
+    const uint32_t w = m[(int64_t)brick * kMaskWords + (col >> 2)];
+    return (w >> ((col & 3) * 8)) & 0xffu;
+}
+
+__device__ inline void load_col(const float* __restrict__ a, int32_t slot0, float v[8])
+{
+#pragma unroll
+    for (int k = 0; k < 8; ++k) v[k] = *at32(a, (uint32_t)(slot0 + k));
+}
+
+// Directory entry of the brick at offset (dx, dy, dz) from bi, or -1.
+__device__ inline int32_t nbr_brick(const Band& B, const ShapeDesc& s, const BrickInfo& bi, int dx, int dy, int dz)
+{
+    const int32_t x = bi.bx + dx, y = bi.by + dy, z = bi.bz + dz;
+    if (x < 0 || y < 0 || z < 0 || x >= s.nb[0] || y >= s.nb[1] || z >= s.nb[2]) return -1;
+    return brick_of(B, s, x, y, z);
+}
+
+// The neighbour column of this lane's column in direction (di, dj) of the
+// i-j plane: from lane (i + di, j + dj), or across the brick face.  Values of
+// up to two arrays (b may be null) and the neighbours' V2 bits.
+__device__ inline uint32_t side_col(const Band& B, const ShapeDesc& s, const BrickInfo& bi, int lane, int di, int dj,
+                                    const float va[8], const float vb[8], uint32_t m, const float* __restrict__ a,
+                                    const float* __restrict__ b, float na[8], float nb[8])
+{
+    const int32_t i = lane >> 3, j = lane & 7, ii = i + di, jj = j + dj;
+    const int src = (lane + di * 8 + dj) & 63;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        na[k] = __shfl(va[k], src, 64);
+        if (b) nb[k] = __shfl(vb[k], src, 64);
+    }
+    uint32_t nm = (uint32_t)__shfl((int)m, src, 64);
+    if (ii < 0 || ii > 7 || jj < 0 || jj > 7) {
+        const int32_t br = nbr_brick(B, s, bi, (ii > 7) - (ii < 0), (jj > 7) - (jj < 0), 0);
+        const int32_t ncol = ((ii & 7) << 3) | (jj & 7);
+        nm = 0u;
+        if (br >= 0) {
+            load_col(a, br * kBrickVol + ncol * 8, na);
+            if (b) load_col(b, br * kBrickVol + ncol * 8, nb);
+            nm = col_mask(B.m_v2, br, ncol);
+        }
+    }
+    return nm;
+}
+
+__global__ __launch_bounds__(kTvWaves * 64) void k_tv_forward_wave(Band B, const float* __restrict__ D,
+                                                                   float* __restrict__ itau,
+                                                                   double* __restrict__ tv_part, int32_t n_bricks)
+{
+    const int lane = threadIdx.x & 63;
+    const int32_t brick = (int32_t)blockIdx.x * kTvWaves + (int32_t)(threadIdx.x >> 6);
+    if (brick >= n_bricks) return;
+    const BrickInfo bi = B.bricks[brick];
+    const ShapeDesc& s = B.shapes[bi.shape];
+    const int32_t slot0 = brick * kBrickVol + lane * 8;
+    float v[8], s2[8];
+    load_col(D, slot0, v);
+    const uint32_t m = col_mask(B.m_v2, brick, lane);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) s2[k] = 0.f;
+    // z neighbours: inside the column, then across the two z faces
+#pragma unroll
+    for (int k = 0; k < 7; ++k)
+        if ((m >> k) & (m >> (k + 1)) & 1u) {
+            const float d = v[k] - v[k + 1];
+            s2[k] = fmaf(d, d, s2[k]);
+            s2[k + 1] = fmaf(d, d, s2[k + 1]);
+        }
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+        const int32_t br = nbr_brick(B, s, bi, 0, 0, e ? 1 : -1);
+        const int k = e ? 7 : 0, kn = e ? 0 : 7;
+        if (br >= 0 && ((m >> k) & 1u) && ((col_mask(B.m_v2, br, lane) >> kn) & 1u)) {
+            const float d = v[k] - *at32(D, (uint32_t)(br * kBrickVol + lane * 8 + kn));
+            s2[k] = fmaf(d, d, s2[k]);
+        }
+    }
+    // x and y neighbours
+#pragma unroll 1
+    for (int dir = 0; dir < 4; ++dir) {
+        const int di = dir == 0 ? 1 : (dir == 1 ? -1 : 0), dj = dir == 2 ? 1 : (dir == 3 ? -1 : 0);
+        float n[8];
+        const uint32_t nm = side_col(B, s, bi, lane, di, dj, v, nullptr, m, D, nullptr, n, nullptr);
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+            if ((m & nm) >> k & 1u) {
+                const float d = v[k] - n[k];
+                s2[k] = fmaf(d, d, s2[k]);
+            }
+    }
+    double sum = 0.0;
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+        if ((m >> k) & 1u) {
+            const float t = sqrtf(s2[k]);
+            *at32(itau, (uint32_t)(slot0 + k)) = t > 0.f ? 1.f / t : 0.f;
+            sum += (double)t;
+        }
+    for (int o = 32; o > 0; o >>= 1) sum += __shfl_xor(sum, o, 64);
+    if (lane == 0) tv_part[brick] = sum;
+}
+
+__global__ __launch_bounds__(kTvWaves * 64, 5) void k_tv_backward_wave(Band B, const float* __restrict__ D,
+                                                                    const float* __restrict__ itau, gp_weights w,
+                                                                    const double* __restrict__ dloss,
+                                                                    const double* __restrict__ inv_qv,
+                                                                    float* __restrict__ raw, float* __restrict__ G,
+                                                                    int32_t n_bricks)
+{
+    const int lane = threadIdx.x & 63;
+    const int32_t brick = (int32_t)blockIdx.x * kTvWaves + (int32_t)(threadIdx.x >> 6);
+    if (brick >= n_bricks) return;
+    const BrickInfo bi = B.bricks[brick];
+    const ShapeDesc& s = B.shapes[bi.shape];
+    const bool tv_on = s.n_tv > 0;
+    const float scale = tv_on ? (float)((double)w.alpha * dloss[bi.shape] / (double)s.n_tv) : 0.f;
+    const float rscale = raw ? (float)(dloss[bi.shape] * inv_qv[bi.shape]) : 0.f;
+    const int32_t slot0 = brick * kBrickVol + lane * 8;
+    float add[8];
+    uint32_t touched = 0u;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) add[k] = 0.f;
+    if (raw) {
+        float r[8];
+        load_col(raw, slot0, r);
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+            if (r[k] != 0.f) {
+                add[k] = rscale * r[k];
+                touched |= 1u << k;
+            }
+        if (touched)
+#pragma unroll
+            for (int k = 0; k < 8; ++k) *at32(raw, (uint32_t)(slot0 + k)) = 0.f;
+    }
+    const uint32_t m = tv_on ? col_mask(B.m_v2, brick, lane) : 0u;
+    if (__ballot(m != 0u)) {
+        float v[8], it[8], acc[8];
+        load_col(D, slot0, v);
+        load_col(itau, slot0, it);
+#pragma unroll
+        for (int k = 0; k < 8; ++k) acc[k] = 0.f;
+#pragma unroll
+        for (int k = 0; k < 7; ++k)
+            if ((m >> k) & (m >> (k + 1)) & 1u) {
+                const float d = v[k] - v[k + 1], c = it[k] + it[k + 1];
+                acc[k] = fmaf(d, c, acc[k]);
+                acc[k + 1] = fmaf(-d, c, acc[k + 1]);
+            }
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+            const int32_t br = nbr_brick(B, s, bi, 0, 0, e ? 1 : -1);
+            const int k = e ? 7 : 0, kn = e ? 0 : 7;
+            if (br >= 0 && ((m >> k) & 1u) && ((col_mask(B.m_v2, br, lane) >> kn) & 1u)) {
+                const uint32_t ns = (uint32_t)(br * kBrickVol + lane * 8 + kn);
+                acc[k] = fmaf(v[k] - *at32(D, ns), it[k] + *at32(itau, ns), acc[k]);
+            }
+        }
+#pragma unroll 1
+        for (int dir = 0; dir < 4; ++dir) {
+            const int di = dir == 0 ? 1 : (dir == 1 ? -1 : 0), dj = dir == 2 ? 1 : (dir == 3 ? -1 : 0);
+            float n[8], nt[8];
+            const uint32_t nm = side_col(B, s, bi, lane, di, dj, v, it, m, D, itau, n, nt);
+#pragma unroll
+            for (int k = 0; k < 8; ++k)
+                if ((m & nm) >> k & 1u) acc[k] = fmaf(v[k] - n[k], it[k] + nt[k], acc[k]);
+        }
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+            if ((m >> k) & 1u) add[k] = fmaf(scale, acc[k], add[k]);
+        touched |= m;
+    }
+    if (touched)
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+            if ((touched >> k) & 1u) *at32(G, (uint32_t)(slot0 + k)) += add[k];
 }
 
 // One block per shape: deterministic sums of the tile and brick partials.
@@ -686,6 +875,40 @@ __global__ __launch_bounds__(kFinalizeBlock) void k_finalize(Band B, const doubl
 
 using namespace gp;
 
+// TV layout for this context, unless gp_set_tv_layout fixed one: block per
+// brick for a small band (more waves), wave per brick for a large one (more
+// bricks in flight).  Measured crossovers: the forward gains from about 2000
+// bricks (0.44 -> 0.26 ms at 137k bricks, 24 -> 19 us at 6k), the backward,
+// which moves two arrays and keeps more registers, only far above 6k bricks
+// (0.71 -> 0.54 ms at 137k, 32 -> 34 us at 6k).
+constexpr int64_t kTvWaveMinBricksFwd = 2048;
+constexpr int64_t kTvWaveMinBricksBwd = 16384;
+
+static bool tv_wave_layout(gp_ctx ctx, int64_t min_bricks)
+{
+    return ctx->tv_layout == 2 || (ctx->tv_layout == 0 && ctx->n_bricks >= min_bricks);
+}
+
+static void launch_tv_forward(gp_ctx ctx, const Band& B, const float* field, hipStream_t st)
+{
+    if (tv_wave_layout(ctx, kTvWaveMinBricksFwd))
+        k_tv_forward_wave<<<(unsigned)((ctx->n_bricks + kTvWaves - 1) / kTvWaves), kTvWaves * 64, 0, st>>>(
+            B, field, ctx->tau.p, ctx->tv_part.p, (int32_t)ctx->n_bricks);
+    else
+        k_tv_forward_brick<<<(unsigned)ctx->n_bricks, kBrickVol, 0, st>>>(B, field, ctx->tau.p, ctx->tv_part.p);
+}
+
+static void launch_tv_backward(gp_ctx ctx, const Band& B, const float* field, gp_weights w, const double* dloss,
+                               float* raw, float* grad, hipStream_t st)
+{
+    if (tv_wave_layout(ctx, kTvWaveMinBricksBwd))
+        k_tv_backward_wave<<<(unsigned)((ctx->n_bricks + kTvWaves - 1) / kTvWaves), kTvWaves * 64, 0, st>>>(
+            B, field, ctx->tau.p, w, dloss, ctx->inv_qv.p, raw, grad, (int32_t)ctx->n_bricks);
+    else
+        k_tv_backward_brick<<<(unsigned)ctx->n_bricks, kBrickVol, 0, st>>>(B, field, ctx->tau.p, w, dloss,
+                                                                        ctx->inv_qv.p, raw, grad);
+}
+
 gp_status gp_forward_impl(gp_ctx ctx, const float* qx, const float* qy, const float* qz, const int32_t* nn,
                           const float* field, gp_weights w, double* loss_out, int64_t* n_valid_out)
 {
@@ -698,7 +921,7 @@ gp_status gp_forward_impl(gp_ctx ctx, const float* qx, const float* qy, const fl
     }
     if (ctx->n_bricks > 0) {
         GP_TIMED(ctx, "k_tv_forward");
-        k_tv_forward<<<(unsigned)ctx->n_bricks, kBrickVol, 0, st>>>(B, field, ctx->tau.p, ctx->tv_part.p);
+        launch_tv_forward(ctx, B, field, st);
     }
     GP_TIMED(ctx, "k_finalize");
     k_finalize<<<(unsigned)ctx->n_shapes, kFinalizeBlock, 0, st>>>(B, ctx->q_part.p, ctx->tv_part.p, w, loss_out, n_valid_out,
@@ -721,8 +944,7 @@ gp_status gp_backward_impl(gp_ctx ctx, const float* qx, const float* qy, const f
     }
     if (ctx->n_bricks > 0) {
         GP_TIMED(ctx, "k_tv_backward");
-        k_tv_backward<<<(unsigned)ctx->n_bricks, kBrickVol, 0, st>>>(B, field, ctx->tau.p, w, dloss, ctx->inv_qv.p,
-                                                               nullptr, grad);
+        launch_tv_backward(ctx, B, field, w, dloss, nullptr, grad, st);
     }
     GP_HIP(ctx, hipGetLastError());
     return GP_OK;
@@ -742,7 +964,7 @@ gp_status gp_forward_backward_impl(gp_ctx ctx, const float* qx, const float* qy,
     }
     if (ctx->n_bricks > 0) {
         GP_TIMED(ctx, "k_tv_forward");
-        k_tv_forward<<<(unsigned)ctx->n_bricks, kBrickVol, 0, st>>>(B, field, ctx->tau.p, ctx->tv_part.p);
+        launch_tv_forward(ctx, B, field, st);
     }
     {
         GP_TIMED(ctx, "k_finalize");
@@ -751,8 +973,7 @@ gp_status gp_forward_backward_impl(gp_ctx ctx, const float* qx, const float* qy,
     }
     if (ctx->n_bricks > 0) {
         GP_TIMED(ctx, "k_tv_backward");
-        k_tv_backward<<<(unsigned)ctx->n_bricks, kBrickVol, 0, st>>>(B, field, ctx->tau.p, w, dloss, ctx->inv_qv.p,
-                                                               ctx->g_raw.p, grad);
+        launch_tv_backward(ctx, B, field, w, dloss, ctx->g_raw.p, grad, st);
     }
     GP_HIP(ctx, hipGetLastError());
     ctx->have_forward = true;

@@ -23,7 +23,7 @@ STATUS = {0: "GP_OK", 1: "GP_ERR_ARG", 2: "GP_ERR_DOMAIN", 3: "GP_ERR_CAPACITY",
           5: "GP_ERR_DEVICE", 6: "GP_ERR_STATE", 7: "GP_ERR_NUMERIC"}
 
 EXPORTS = ("gp_create", "gp_destroy", "gp_last_error", "gp_set_stream", "gp_sync", "gp_build_band",
-           "gp_nn_query", "gp_set_nn_params", "gp_get_nn_params", "gp_autotune_nn", "gp_sample_queries", "gp_pull_forward", "gp_pull_backward", "gp_pull_forward_backward", "gp_step",
+           "gp_nn_query", "gp_set_nn_params", "gp_get_nn_params", "gp_autotune_nn", "gp_set_tv_layout", "gp_sample_queries", "gp_pull_forward", "gp_pull_backward", "gp_pull_forward_backward", "gp_step",
            "gp_shape_slots", "gp_export_layout", "gp_export_active_cells", "gp_gather_vertices", "gp_scatter_vertices",
            "gp_init_sphere", "gp_timing_enable", "gp_timing_report")
 
@@ -67,6 +67,7 @@ def load_library(path: str = LIB_PATH):
                                ctypes.POINTER(i64), ctypes.POINTER(i64)]),
         "gp_nn_query": (st, [P, P, P, P, i64, P]),
         "gp_set_nn_params": (st, [P, i32, i32, i32]),
+        "gp_set_tv_layout": (st, [P, i32]),
         "gp_get_nn_params": (st, [P, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32)]),
         "gp_autotune_nn": (st, [P, P, P, P, i64, P, i32, ctypes.POINTER(i32), ctypes.POINTER(i32),
                                 ctypes.POINTER(i32), ctypes.POINTER(f32)]),
@@ -178,6 +179,11 @@ def gp_nn_query(ctx, qx, qy, qz, nn_out) -> None:
 
 def gp_set_nn_params(ctx, group_span: int, first_shell: int, tile_parts: int = 1) -> None:
     _check(ctx, load_library().gp_set_nn_params(ctx, int(group_span), int(first_shell), int(tile_parts)))
+
+
+def gp_set_tv_layout(ctx, layout: int) -> None:
+    """0: by band size, 1: one block per brick, 2: one wave per brick."""
+    _check(ctx, load_library().gp_set_tv_layout(ctx, int(layout)))
 
 
 def gp_get_nn_params(ctx) -> Tuple[int, int, int]:

@@ -366,3 +366,48 @@ def test_nn_search_shapes_and_autotuner():
             assert ei.value.status == 1
         assert gp.gp_get_nn_params(prob.ctx) == (span, shell, parts)
         prob.close()
+
+
+@pytest.mark.parametrize("layout", [1, 2])
+def test_tv_layouts(layout):
+    """Both thread layouts of the TV kernels (block per brick, wave per brick)
+    give the oracle's loss terms and gradient, through the separate and the
+    fused calls: the sphere with a wide TV band (many brick faces inside the
+    band) and the anisotropic grid with random values (bricks cut by the grid
+    boundary, neighbours outside the grid)."""
+    from paper_2308_13175_amd import gridpull as gp
+
+    dom, pts, q, D = _sphere_case()
+    rng = np.random.default_rng(5)
+    adom = synth.Domain((24, 17, 31), (-1.125, -0.625, -0.875), (0.875, 0.8125, 1.0625))
+    apts = (synth.sphere_points(3000, 0.45, seed=3) + np.float32(0.05)).astype(np.float32)
+    aq = synth.host_queries(apts, 9000, 0.05, seed=7)
+    aD = rng.normal(size=adom.n_vertices).astype(np.float32) * 0.2
+    for name, (dm, p_, q_, D_, m1, m2) in [("sphere m2=14", (dom, pts, q, D, 3, 14)),
+                                           ("anisotropic", (adom, apts, aq, aD, 2, 3))]:
+        log("case: TV layout %d, %s" % (layout, name))
+        prob = make_problem([spec(p_, dm, len(q_), 0.0)], m1=m1, m2=m2)
+        gp.gp_set_tv_layout(prob.ctx, layout)
+        prob.set_dense_field([D_])
+        prob.set_queries(q_)
+        prob.nearest()
+        cf, vf, nn, ref = _oracle(dm, p_, q_, D_, m1, m2)
+        prob.forward()
+        prob.grad.zero_()
+        prob.backward()
+        prob.sync()
+        got, nv = loss_terms(prob)
+        assert int(nv[0]) == ref["n_valid"]
+        assert_terms_close(got[0], ref)
+        assert_grad_close(prob.dense_grad()[0], ref["dD"])
+        for rep in range(2):
+            prob.grad.zero_()
+            prob.forward_backward()
+            prob.sync()
+            got, nv = loss_terms(prob)
+            assert_terms_close(got[0], ref)
+            assert_grad_close(prob.dense_grad()[0], ref["dD"])
+        with pytest.raises(gp.GridPullError) as ei:
+            gp.gp_set_tv_layout(prob.ctx, 3)
+        assert ei.value.status == 1
+        prob.close()
