@@ -340,7 +340,7 @@ def schedule_sweep(kind: str, iters: int = 1600, n_points: int = 200_000, n_quer
         torch.cuda.synchronize()
         setup_s = time.perf_counter() - t0
         prob.iteration(1)
-        nn_search = prob.autotune(reps=2)[:3]   # before the capture: the graph keeps the search shape
+        nn_search = prob.autotune(reps=2)[0]   # before the capture: the graph keeps the search shape
         graph = GraphedIteration(prob)
         prob.init_sphere()
         torch.cuda.synchronize()
@@ -487,10 +487,10 @@ def main():
         prob.iteration(None)
     tuned_ms = None
     if not args.no_autotune:
-        _, _, _, tuned_ms = prob.autotune(reps=3)
-    nn_span, nn_shell, nn_parts = gp.gp_get_nn_params(prob.ctx)
-    log("NN search shape: group span %d, first shell %d, %d blocks per tile%s" % (
-        nn_span, nn_shell, nn_parts, " (autotuned, %.3f ms)" % tuned_ms if tuned_ms is not None else ""))
+        _, tuned_ms = prob.autotune(reps=3)
+    nn_span, nn_shell, nn_parts, nn_skip = gp.gp_get_nn_params(prob.ctx)
+    log("NN search shape: group span %d, first shell %d, %d blocks per tile, skip empty %d%s" % (
+        nn_span, nn_shell, nn_parts, nn_skip, " (autotuned, %.3f ms)" % tuned_ms if tuned_ms is not None else ""))
     torch.cuda.synchronize()
     gp.gp_timing_enable(prob.ctx, True)
     gp.gp_timing_report(prob.ctx)          # start a clean period
@@ -582,7 +582,7 @@ def main():
                    "slots": prob.n_slots, "optimised_vertices": V, "tv_vertices": V2,
                    "step": "sample+nn+forward+backward+adam"},
         "roofline": roof,
-        "nn_search": {"group_span": nn_span, "first_shell": nn_shell, "tile_parts": nn_parts,
+        "nn_search": {"group_span": nn_span, "first_shell": nn_shell, "tile_parts": nn_parts, "skip_empty": nn_skip,
                       "autotuned": tuned_ms is not None,
                       "autotune_best_ms": tuned_ms},
         "fwd_bwd": {"queries_per_s": Q / (fb_ms * 1e-3), "ms": fb_ms, "median_ms": fb_median,

@@ -158,34 +158,43 @@ gp_status gp_nn_query(gp_ctx ctx, const float* qx, const float* qy, const float*
  * lanes scan the group's cell box grown by first_shell cells together, and
  * the queries that box does not settle continue alone.  tile_parts blocks
  * share a tile (each sorts it and takes 1/tile_parts of the groups), which
- * gives small batches more blocks.
- * group_span in [1, 64], first_shell in [0, 4], tile_parts in {1, 2, 4};
- * defaults 8, 1 and 1.  The setting belongs to the context and survives
- * gp_build_band.
- * Errors: GP_ERR_ARG (out of range or null outputs).
+ * gives small batches more blocks.  With skip_empty, every column of cells
+ * to be scanned is first cut to its first and last cell holding a point (a
+ * bitmap of one bit per cell), which saves range lookups where points are
+ * sparse.
  */
-gp_status gp_set_nn_params(gp_ctx ctx, int32_t group_span, int32_t first_shell, int32_t tile_parts);
-gp_status gp_get_nn_params(gp_ctx ctx, int32_t* group_span, int32_t* first_shell, int32_t* tile_parts);
+typedef struct {
+    int32_t group_span;    /* [1, 64], default 8 */
+    int32_t first_shell;   /* [0, 4], default 1 */
+    int32_t tile_parts;    /* 1, 2 or 4, default 1 */
+    int32_t skip_empty;    /* 0 or 1, default 0 */
+} gp_nn_params;
 
 /*
- * Autotuner of the search shape above: runs gp_nn_query's kernel on the given
+ * Set / read the context's search shape (host struct; it survives
+ * gp_build_band).  Errors: GP_ERR_ARG (null pointer, a field out of range).
+ */
+gp_status gp_set_nn_params(gp_ctx ctx, const gp_nn_params* params);
+gp_status gp_get_nn_params(gp_ctx ctx, gp_nn_params* params);
+
+/*
+ * Autotuner of the search shape: runs gp_nn_query's kernel on the given
  * queries for group_span in {4, 6, 8, 12, 16, 24, 32} x first_shell in
- * {0, 1, 2} at the current tile_parts, then tile_parts in {1, 2, 4} at the
- * best of those, each once untimed and then reps times between HIP events on
- * the context's stream (its time: the smallest of those); keeps the fastest
- * in the context and leaves nn_out holding the nearest neighbours (as
+ * {0, 1, 2} at the current tile_parts and skip_empty, then tile_parts in
+ * {1, 2, 4} at the best of those, then the other skip_empty setting; each
+ * candidate once untimed and then reps times between HIP events on the
+ * context's stream (its time: the smallest of those).  Keeps the fastest in
+ * the context and leaves nn_out holding the nearest neighbours (as
  * gp_nn_query).  The context's current setting is timed first and stays
  * unless another is at least 2% faster.
- * Arguments as gp_nn_query; reps in [1, 100]; group_span_out,
- * first_shell_out, tile_parts_out (host, may be NULL) receive the choice and
- * best_ms_out (host, may be NULL) its time in ms (-1 with no queries).
- * Synchronises; not for use under stream capture.
+ * Arguments as gp_nn_query; reps in [1, 100]; chosen_out (host, may be NULL)
+ * receives the choice and best_ms_out (host, may be NULL) its time in ms
+ * (-1 with no queries).  Synchronises; not for use under stream capture.
  * Errors: as gp_nn_query, GP_ERR_ARG for reps, GP_ERR_DEVICE.
  */
 gp_status gp_autotune_nn(gp_ctx ctx, const float* qx, const float* qy, const float* qz,
                          int64_t n_queries, int32_t* nn_out, int32_t reps,
-                         int32_t* group_span_out, int32_t* first_shell_out, int32_t* tile_parts_out,
-                         float* best_ms_out);
+                         gp_nn_params* chosen_out, float* best_ms_out);
 
 /*
  * Thread layout of the TV kernels (Eq. 5 and its gradient; the same

@@ -245,6 +245,19 @@ __global__ void k_gather_sorted(const float* __restrict__ px, const float* __res
     }
 }
 
+// One word of the occupancy bitmap: bit b of word w is cell 32 w + b (bit 1
+// of the cell flags: the cell holds a point).
+__global__ void k_pack_occ(const uint8_t* __restrict__ cells, int64_t n_cells, uint32_t* __restrict__ occ)
+{
+    GRID_STRIDE(w, (n_cells + 31) / 32)
+    {
+        uint32_t v = 0;
+        const int64_t c0 = w * 32;
+        for (int b = 0; b < 32 && c0 + b < n_cells; ++b) v |= (uint32_t)(cells[c0 + b] & 1) << b;
+        occ[w] = v;
+    }
+}
+
 struct ShapeBricks {
     DevBuf<int32_t> dir;
     DevBuf<BrickInfo> bricks;
@@ -267,7 +280,7 @@ gp_status gp_build_band_impl(gp_ctx ctx, const gp_shape* shapes, int32_t n_shape
 
     // ---- host-side descriptors ------------------------------------------
     std::vector<ShapeDesc> hs(n_shapes);
-    int64_t dir_total = 0, dense_total = 0, sorted_total = 0, tiles_total = 0;
+    int64_t dir_total = 0, dense_total = 0, sorted_total = 0, tiles_total = 0, occ_total = 0;
     int64_t n_points = 0, n_queries = 0;
     for (int32_t s = 0; s < n_shapes; ++s) {
         const gp_shape& in = shapes[s];
@@ -297,11 +310,15 @@ gp_status gp_build_band_impl(gp_ctx ctx, const gp_shape* shapes, int32_t n_shape
         n_queries = std::max(n_queries, in.query_off + in.query_cnt);
         d.n_tv = 0;
         d.brick_begin = d.brick_end = 0;
+        d.occ_off = occ_total;
+        occ_total += ((int64_t)d.R[0] * d.R[1] * d.R[2] + 31) / 32;
     }
     if (sorted_total >= ((int64_t)1 << 31) || n_points >= ((int64_t)1 << 31))
         return gp_fail(ctx, GP_ERR_CAPACITY, "more than 2^31 points");
     if (dir_total >= kMaxSlots) return gp_fail(ctx, GP_ERR_CAPACITY, "more than 2^30 brick directory entries");
 
+    if (ctx->occ.alloc((size_t)std::max<int64_t>(occ_total, 1)) != hipSuccess)
+        return gp_fail(ctx, GP_ERR_OOM, "out of device memory for the occupancy bitmap");
     DevBuf<ShapeDesc> d_shape1;
     GP_HIP(ctx, d_shape1.alloc(1));
     DevBuf<unsigned long long> d_bad;
@@ -335,6 +352,7 @@ gp_status gp_build_band_impl(gp_ctx ctx, const gp_shape* shapes, int32_t n_shape
         if (bad != ~0ull)
             return gp_fail(ctx, GP_ERR_DOMAIN, "shape " + std::to_string(s) + ": point " + std::to_string(bad) +
                                                    " lies outside the domain");
+        k_pack_occ<<<blocks_for((nc + 31) / 32), kThreads, 0, st>>>(c0.p, nc, ctx->occ.p + d.occ_off);
         // separable Chebyshev dilation x -> y -> z; a width of the largest
         // extent minus one already reaches every cell, so wider ones are cut
         // to it (same sets, bounded work)

@@ -190,28 +190,37 @@ gp_status gp_nn_query(gp_ctx ctx, const float* qx, const float* qy, const float*
     return gp_nn_impl(ctx, qx, qy, qz, nn_out);
 }
 
-gp_status gp_set_nn_params(gp_ctx ctx, int32_t group_span, int32_t first_shell, int32_t tile_parts)
+gp_status gp_set_nn_params(gp_ctx ctx, const gp_nn_params* params)
 {
     if (!ctx) return GP_ERR_ARG;
-    if (group_span < 1 || group_span > gp::kNnSpanMax)
+    if (!params) return gp_fail(ctx, GP_ERR_ARG, "null params");
+    if (params->group_span < 1 || params->group_span > gp::kNnSpanMax)
         return gp_fail(ctx, GP_ERR_ARG, "group_span must be in [1, 64]");
-    if (first_shell < 0 || first_shell > gp::kNnShellMax)
+    if (params->first_shell < 0 || params->first_shell > gp::kNnShellMax)
         return gp_fail(ctx, GP_ERR_ARG, "first_shell must be in [0, 4]");
-    if (tile_parts != 1 && tile_parts != 2 && tile_parts != 4)
+    if (params->tile_parts != 1 && params->tile_parts != 2 && params->tile_parts != 4)
         return gp_fail(ctx, GP_ERR_ARG, "tile_parts must be 1, 2 or 4");
-    ctx->nn_params.span = group_span;
-    ctx->nn_params.shell = first_shell;
-    ctx->nn_params.parts = tile_parts;
+    if (params->skip_empty != 0 && params->skip_empty != 1) return gp_fail(ctx, GP_ERR_ARG, "skip_empty must be 0 or 1");
+    ctx->nn_params.span = params->group_span;
+    ctx->nn_params.shell = params->first_shell;
+    ctx->nn_params.parts = params->tile_parts;
+    ctx->nn_params.skip_empty = params->skip_empty;
     return GP_OK;
 }
 
-gp_status gp_get_nn_params(gp_ctx ctx, int32_t* group_span, int32_t* first_shell, int32_t* tile_parts)
+static void nn_params_out(const gp::NnParams& p, gp_nn_params* out)
+{
+    out->group_span = p.span;
+    out->first_shell = p.shell;
+    out->tile_parts = p.parts;
+    out->skip_empty = p.skip_empty;
+}
+
+gp_status gp_get_nn_params(gp_ctx ctx, gp_nn_params* params)
 {
     if (!ctx) return GP_ERR_ARG;
-    if (!group_span || !first_shell || !tile_parts) return gp_fail(ctx, GP_ERR_ARG, "null output");
-    *group_span = ctx->nn_params.span;
-    *first_shell = ctx->nn_params.shell;
-    *tile_parts = ctx->nn_params.parts;
+    if (!params) return gp_fail(ctx, GP_ERR_ARG, "null output");
+    nn_params_out(ctx->nn_params, params);
     return GP_OK;
 }
 
@@ -224,8 +233,7 @@ gp_status gp_set_tv_layout(gp_ctx ctx, int32_t layout)
 }
 
 gp_status gp_autotune_nn(gp_ctx ctx, const float* qx, const float* qy, const float* qz, int64_t n_queries,
-                         int32_t* nn_out, int32_t reps, int32_t* group_span_out, int32_t* first_shell_out,
-                         int32_t* tile_parts_out, float* best_ms_out)
+                         int32_t* nn_out, int32_t reps, gp_nn_params* chosen_out, float* best_ms_out)
 {
     gp_status st = ready(ctx);
     if (st != GP_OK) return st;
@@ -235,9 +243,7 @@ gp_status gp_autotune_nn(gp_ctx ctx, const float* qx, const float* qy, const flo
     gp::NnParams best;
     float ms = -1.f;
     if ((st = gp_autotune_nn_impl(ctx, qx, qy, qz, nn_out, reps, &best, &ms)) != GP_OK) return st;
-    if (group_span_out) *group_span_out = best.span;
-    if (first_shell_out) *first_shell_out = best.shell;
-    if (tile_parts_out) *tile_parts_out = best.parts;
+    if (chosen_out) nn_params_out(best, chosen_out);
     if (best_ms_out) *best_ms_out = ms;
     return GP_OK;
 }

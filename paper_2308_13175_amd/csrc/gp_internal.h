@@ -45,6 +45,7 @@ struct ShapeDesc {
     int64_t dense_off;     // offset of the shape's (R+1)^3 dense vertex array
     int64_t sorted_off;    // first entry of the shape's points in the sorted copy
     int64_t n_tv;          // number of TV vertices
+    int64_t occ_off;       // first word of the shape's cell occupancy bitmap
 };
 
 // Brick metadata: owning shape and brick coordinates.
@@ -64,17 +65,21 @@ struct Band {
     const uint32_t* m_v2;        // [n_bricks][16] TV vertex
     const int64_t* tile_start;   // [n_tiles] first query of each tile
     const int32_t* tile_shape;   // [n_tiles]
+    const uint32_t* occ;         // per shape, 1 bit per cell (x-major id): the cell holds a point
 };
 
 // Nearest-neighbour search shape: a group of queries is cut where its cells
 // would span `span` or more cells on an axis, its lockstep box is the group's
-// cell box grown by `shell` cells, and `parts` blocks (1, 2 or 4) share each
-// query tile.  Any values give the same exact result; they only move work
-// between the lockstep and per-query passes and between blocks.
+// cell box grown by `shell` cells, `parts` blocks (1, 2 or 4) share each
+// query tile, and with skip_empty every column of cells is first trimmed to
+// its first and last occupied cell (occupancy bitmap).  Any values give the
+// same exact result; they only move work between the lockstep and per-query
+// passes, between blocks, and between loads of bitmap words and of ranges.
 struct NnParams {
     int32_t span = 8;
     int32_t shell = 1;
     int32_t parts = 1;
+    int32_t skip_empty = 0;   // trim each scanned column to its occupied cells first
 };
 constexpr int32_t kNnSpanMax = 64;
 constexpr int32_t kNnShellMax = 4;
@@ -293,6 +298,7 @@ struct gp_ctx_s {
     DevBuf<uint32_t> m_a1, m_a2, m_base, m_v, m_v2;
     DevBuf<int64_t> tile_start;
     DevBuf<int32_t> tile_shape;
+    DevBuf<uint32_t> occ;         // cell occupancy bitmaps of all shapes
 
     // nearest-neighbour buckets: points sorted by cell slot
     DevBuf<int32_t> cell_start;   // [n_slots + 1]
@@ -334,6 +340,7 @@ struct gp_ctx_s {
         b.m_v2 = m_v2.p;
         b.tile_start = tile_start.p;
         b.tile_shape = tile_shape.p;
+        b.occ = occ.p;
         return b;
     }
 };

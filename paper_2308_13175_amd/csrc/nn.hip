@@ -379,12 +379,49 @@ __device__ inline int32_t flush_runs(const Band& B, const ShapeDesc& s, const Gl
     return rest;
 }
 
+// The first and last cell of column (x, y) in [za, zb] that hold a point,
+// from the occupancy bitmap (za > zb afterwards: none).
+__device__ inline void trim_column(const Band& B, const ShapeDesc& s, int32_t x, int32_t y, int32_t& za, int32_t& zb)
+{
+    if (za > zb) return;
+    const int64_t base = s.occ_off * 32 + ((int64_t)x * s.R[1] + y) * s.R[2];   // bit of cell (x, y, 0)
+    const int64_t i0 = base + za, i1 = base + zb;
+    const int64_t w0 = i0 >> 5, w1 = i1 >> 5;
+    const uint32_t m0 = ~0u << (i0 & 31), m1 = ~0u >> (31 - (i1 & 31));
+    int64_t first = -1, last = -1;
+#pragma unroll 1
+    for (int64_t w = w0; w <= w1; ++w) {
+        uint32_t v = B.occ[w] & (w == w0 ? m0 : ~0u) & (w == w1 ? m1 : ~0u);
+        if (v) {
+            first = w * 32 + __builtin_ctz(v);
+            break;
+        }
+    }
+    if (first < 0) {
+        za = 1;
+        zb = 0;
+        return;
+    }
+#pragma unroll 1
+    for (int64_t w = w1; w >= (first >> 5); --w) {
+        uint32_t v = B.occ[w] & (w == w0 ? m0 : ~0u) & (w == w1 ? m1 : ~0u);
+        if (v) {
+            last = w * 32 + 31 - __builtin_clz(v);
+            break;
+        }
+    }
+    za = (int32_t)(first - base);
+    zb = (int32_t)(last - base);
+}
+
 // Stage the brick-aligned pieces of this lane's z range [za, zb] on row
 // (x, y) (an empty range adds nothing), flushing whenever 64 are staged.
+// With trim, the range is first cut to its occupied cells.
 template <class Ev>
 __device__ inline void stage_range(const Band& B, const ShapeDesc& s, const Global& G, int4* __restrict__ runs,
-                                   int32_t& n, Ev& ev, int32_t x, int32_t y, int32_t za, int32_t zb)
+                                   int32_t& n, Ev& ev, int32_t x, int32_t y, int32_t za, int32_t zb, bool trim)
 {
+    if (trim) trim_column(B, s, x, y, za, zb);
     int32_t z0 = za;
     for (;;) {
         const bool has = z0 <= zb;
@@ -409,7 +446,7 @@ __device__ inline void stage_range(const Band& B, const ShapeDesc& s, const Glob
 template <class Ev>
 __device__ inline void scan_box(const Band& B, const ShapeDesc& s, const Global& G, int4* __restrict__ runs, Ev& ev,
                                 const int32_t lo[3], const int32_t hi[3], const int32_t olo[3], const int32_t ohi[3],
-                                const float4* balls = nullptr, int32_t nb = 0)
+                                bool trim, const float4* balls = nullptr, int32_t nb = 0)
 {
     const int lane = threadIdx.x & 63;
     if (lo[0] > hi[0] || lo[1] > hi[1] || lo[2] > hi[2]) return;
@@ -452,8 +489,8 @@ __device__ inline void scan_box(const Band& B, const ShapeDesc& s, const Global&
             zd = zb;
             zb = min(zb, olo[2] - 1);
         }
-        stage_range(B, s, G, runs, n, ev, x, y, za, zb);
-        stage_range(B, s, G, runs, n, ev, x, y, zc, zd);
+        stage_range(B, s, G, runs, n, ev, x, y, za, zb, trim);
+        stage_range(B, s, G, runs, n, ev, x, y, zc, zd, trim);
     }
     if (n > 0) {
         wave_sync();
@@ -621,7 +658,7 @@ __global__ __launch_bounds__(kQueryBlock, 4) void k_nn(Band B, Global G, NnParam
                         hi[a] = min(wb[3 + a] + e, s.R[a] - 1);
                     }
                     Lockstep ev{&q, wbuf};
-                    scan_box(B, s, G, runs, ev, lo, hi, olo, ohi);
+                    scan_box(B, s, G, runs, ev, lo, hi, olo, ohi, P.skip_empty != 0);
                     if (__any(q.id1 >= 0) || e >= kNnMaxGrow) break;
                     for (int a = 0; a < 3; ++a) {
                         olo[a] = lo[a];
@@ -677,7 +714,7 @@ __global__ __launch_bounds__(kQueryBlock, 4) void k_nn(Band B, Global G, NnParam
                     ev.b1[t] = ev.b2[t] = __builtin_inff();
                     ev.id[t] = -1;
                 }
-                scan_box(B, s, G, runs, ev, reg, reg + 3, lo, hi, tq, ev.ns);
+                scan_box(B, s, G, runs, ev, reg, reg + 3, lo, hi, P.skip_empty != 0, tq, ev.ns);
                 // reduce every slot over the wave and merge it into its lane
                 uint64_t own = batch;
 #pragma unroll
@@ -722,7 +759,8 @@ gp_status gp_nn_impl(gp_ctx ctx, const float* qx, const float* qy, const float* 
 
 // Times k_nn for every (span, shell) pair of a small grid on the caller's
 // queries (the results are the same for all of them), then the number of
-// blocks per tile for the best pair, and keeps the fastest in the context.
+// blocks per tile for the best pair, then the other skip_empty setting, and
+// keeps the fastest in the context.
 // Each candidate runs once untimed, then `reps` times between events; its
 // time is the smallest of those.  The context's current setting is timed
 // first and is only replaced by one at least 2% faster, so timing noise does
@@ -766,7 +804,7 @@ gp_status gp_autotune_nn_impl(gp_ctx ctx, const float* qx, const float* qy, cons
             const float t = time_one(P);
             if (e != hipSuccess || t < 0.f) return;
             const bool holding = best.span == current.span && best.shell == current.shell &&
-                                 best.parts == current.parts;
+                                 best.parts == current.parts && best.skip_empty == current.skip_empty;
             if (best_ms < 0.f || t < best_ms * (holding ? 0.98f : 1.f)) {
                 best_ms = t;
                 best = P;
@@ -785,6 +823,11 @@ gp_status gp_autotune_nn_impl(gp_ctx ctx, const float* qx, const float* qy, cons
             NnParams P = shaped;
             P.parts = pa;
             if (pa != shaped.parts) offer(P);
+        }
+        {
+            NnParams P = best;
+            P.skip_empty = !best.skip_empty;
+            offer(P);
         }
         (void)hipEventDestroy(ev[0]);
         (void)hipEventDestroy(ev[1]);

@@ -44,6 +44,14 @@ class gp_weights(ctypes.Structure):
     _fields_ = [("alpha", ctypes.c_float), ("beta", ctypes.c_float), ("gamma", ctypes.c_float)]
 
 
+class gp_nn_params(ctypes.Structure):
+    _fields_ = [("group_span", ctypes.c_int32), ("first_shell", ctypes.c_int32), ("tile_parts", ctypes.c_int32),
+                ("skip_empty", ctypes.c_int32)]
+
+    def as_tuple(self) -> Tuple[int, int, int, int]:
+        return (self.group_span, self.first_shell, self.tile_parts, self.skip_empty)
+
+
 _lib = None
 
 
@@ -66,11 +74,10 @@ def load_library(path: str = LIB_PATH):
         "gp_build_band": (st, [P, ctypes.POINTER(gp_shape), i32, P, P, P, i32, i32, i32,
                                ctypes.POINTER(i64), ctypes.POINTER(i64)]),
         "gp_nn_query": (st, [P, P, P, P, i64, P]),
-        "gp_set_nn_params": (st, [P, i32, i32, i32]),
+        "gp_set_nn_params": (st, [P, ctypes.POINTER(gp_nn_params)]),
         "gp_set_tv_layout": (st, [P, i32]),
-        "gp_get_nn_params": (st, [P, ctypes.POINTER(i32), ctypes.POINTER(i32), ctypes.POINTER(i32)]),
-        "gp_autotune_nn": (st, [P, P, P, P, i64, P, i32, ctypes.POINTER(i32), ctypes.POINTER(i32),
-                                ctypes.POINTER(i32), ctypes.POINTER(f32)]),
+        "gp_get_nn_params": (st, [P, ctypes.POINTER(gp_nn_params)]),
+        "gp_autotune_nn": (st, [P, P, P, P, i64, P, i32, ctypes.POINTER(gp_nn_params), ctypes.POINTER(f32)]),
         "gp_sample_queries": (st, [P, u64, i32, P, f32, P, P, P, P]),
         "gp_pull_forward": (st, [P, P, P, P, P, i64, P, gp_weights, P, P]),
         "gp_pull_backward": (st, [P, P, P, P, P, i64, P, gp_weights, P, P]),
@@ -177,8 +184,9 @@ def gp_nn_query(ctx, qx, qy, qz, nn_out) -> None:
                                            _ptr(qz, torch.float32), qx.numel(), _ptr(nn_out, torch.int32)))
 
 
-def gp_set_nn_params(ctx, group_span: int, first_shell: int, tile_parts: int = 1) -> None:
-    _check(ctx, load_library().gp_set_nn_params(ctx, int(group_span), int(first_shell), int(tile_parts)))
+def gp_set_nn_params(ctx, group_span: int, first_shell: int, tile_parts: int = 1, skip_empty: int = 0) -> None:
+    p = gp_nn_params(int(group_span), int(first_shell), int(tile_parts), int(skip_empty))
+    _check(ctx, load_library().gp_set_nn_params(ctx, ctypes.byref(p)))
 
 
 def gp_set_tv_layout(ctx, layout: int) -> None:
@@ -186,22 +194,22 @@ def gp_set_tv_layout(ctx, layout: int) -> None:
     _check(ctx, load_library().gp_set_tv_layout(ctx, int(layout)))
 
 
-def gp_get_nn_params(ctx) -> Tuple[int, int, int]:
-    span, shell, parts = ctypes.c_int32(0), ctypes.c_int32(0), ctypes.c_int32(0)
-    _check(ctx, load_library().gp_get_nn_params(ctx, ctypes.byref(span), ctypes.byref(shell), ctypes.byref(parts)))
-    return span.value, shell.value, parts.value
+def gp_get_nn_params(ctx) -> Tuple[int, int, int, int]:
+    """(group_span, first_shell, tile_parts, skip_empty)."""
+    p = gp_nn_params()
+    _check(ctx, load_library().gp_get_nn_params(ctx, ctypes.byref(p)))
+    return p.as_tuple()
 
 
-def gp_autotune_nn(ctx, qx, qy, qz, nn_out, reps: int = 2) -> Tuple[int, int, int, float]:
+def gp_autotune_nn(ctx, qx, qy, qz, nn_out, reps: int = 2) -> Tuple[Tuple[int, int, int, int], float]:
     """Time the NN search shapes on these queries and keep the fastest:
-    (group_span, first_shell, tile_parts, ms)."""
+    ((group_span, first_shell, tile_parts, skip_empty), ms)."""
     _stream(ctx)
-    span, shell, parts, ms = ctypes.c_int32(0), ctypes.c_int32(0), ctypes.c_int32(0), ctypes.c_float(0.0)
+    p, ms = gp_nn_params(), ctypes.c_float(0.0)
     _check(ctx, load_library().gp_autotune_nn(ctx, _ptr(qx, torch.float32), _ptr(qy, torch.float32),
                                               _ptr(qz, torch.float32), qx.numel(), _ptr(nn_out, torch.int32),
-                                              int(reps), ctypes.byref(span), ctypes.byref(shell),
-                                              ctypes.byref(parts), ctypes.byref(ms)))
-    return span.value, shell.value, parts.value, ms.value
+                                              int(reps), ctypes.byref(p), ctypes.byref(ms)))
+    return p.as_tuple(), ms.value
 
 
 def gp_sample_queries(ctx, seed: int, iteration: int, sigma, sigma_const: float, qx, qy, qz, src_out=None) -> None:

@@ -327,10 +327,11 @@ def test_batch_with_a_shape_without_queries_and_a_one_point_shape():
 
 
 def test_nn_search_shapes_and_autotuner():
-    """Every NN search shape (group span, first shell, blocks per tile),
-    including the extremes, and the autotuner's choice give the oracle's
-    indices exactly, on the exact-tie lattice and on a sparse sphere (few
-    points per cell, so most queries leave the lockstep box open)."""
+    """Every NN search shape (group span, first shell, blocks per tile, empty
+    cells skipped or not), including the extremes, and the autotuner's choice
+    give the oracle's indices exactly, on the exact-tie lattice and on a
+    sparse sphere (few points per cell, so most queries leave the lockstep box
+    open and most scanned cells are empty)."""
     from paper_2308_13175_amd import gridpull as gp
     sparse = synth.cube_domain(64), synth.sphere_points(1500, 0.5, seed=7)
     cases = [("ties",) + _tie_case()[:3],
@@ -339,32 +340,36 @@ def test_nn_search_shapes_and_autotuner():
         nn = oracle.nn_bruteforce(q, pts)
         prob = make_problem([spec(pts, dom, len(q), 0.0)])
         prob.set_queries(q)
-        assert gp.gp_get_nn_params(prob.ctx) == (8, 1, 1)
-        for span, shell, parts in [(1, 0, 1), (2, 0, 4), (3, 2, 2), (8, 1, 4), (16, 0, 2), (64, 4, 1), (64, 4, 4)]:
-            log("case: %s, group span %d, first shell %d, %d blocks per tile" % (name, span, shell, parts))
-            gp.gp_set_nn_params(prob.ctx, span, shell, parts)
+        assert gp.gp_get_nn_params(prob.ctx) == (8, 1, 1, 0)
+        for shape in [(1, 0, 1, 0), (2, 0, 4, 1), (3, 2, 2, 0), (8, 1, 4, 1), (8, 1, 1, 1), (16, 0, 2, 1),
+                      (64, 4, 1, 0), (64, 4, 4, 1)]:
+            log("case: %s, search shape %s" % (name, shape))
+            gp.gp_set_nn_params(prob.ctx, *shape)
             prob.nn.fill_(-7)
             prob.nearest()
             prob.sync()
             got = prob.nn[: len(q)].cpu().numpy()
             bad = np.nonzero(got != nn)[0]
-            assert len(bad) == 0, "%s span %d shell %d parts %d: %d differ" % (name, span, shell, parts, len(bad))
+            assert len(bad) == 0, "%s shape %s: %d differ" % (name, shape, len(bad))
         log("case: %s, autotuner" % name)
-        gp.gp_set_nn_params(prob.ctx, 8, 1, 1)   # the tuner starts from the current setting
+        gp.gp_set_nn_params(prob.ctx, 8, 1, 1, 0)   # the tuner starts from the current setting
         prob.nn.fill_(-7)
-        span, shell, parts, ms = prob.autotune(reps=1)
+        chosen, ms = prob.autotune(reps=1)
         prob.sync()
-        assert span in (4, 6, 8, 12, 16, 24, 32) and shell in (0, 1, 2) and parts in (1, 2, 4) and ms > 0
-        assert gp.gp_get_nn_params(prob.ctx) == (span, shell, parts)
+        span, shell, parts, skip = chosen
+        assert span in (4, 6, 8, 12, 16, 24, 32) and shell in (0, 1, 2) and parts in (1, 2, 4) and skip in (0, 1)
+        assert ms > 0
+        assert gp.gp_get_nn_params(prob.ctx) == chosen
         assert np.array_equal(prob.nn[: len(q)].cpu().numpy(), nn)
         prob.nearest()
         prob.sync()
         assert np.array_equal(prob.nn[: len(q)].cpu().numpy(), nn)
-        for bad_args in [(0, 1, 1), (65, 1, 1), (8, -1, 1), (8, 5, 1), (8, 1, 3), (8, 1, 0)]:
+        for bad_args in [(0, 1, 1, 0), (65, 1, 1, 0), (8, -1, 1, 0), (8, 5, 1, 0), (8, 1, 3, 0), (8, 1, 0, 0),
+                         (8, 1, 1, 2)]:
             with pytest.raises(gp.GridPullError) as ei:
                 gp.gp_set_nn_params(prob.ctx, *bad_args)
             assert ei.value.status == 1
-        assert gp.gp_get_nn_params(prob.ctx) == (span, shell, parts)
+        assert gp.gp_get_nn_params(prob.ctx) == chosen
         prob.close()
 
 
