@@ -526,10 +526,12 @@ gp_status gp_build_band_impl(gp_ctx ctx, const gp_shape* shapes, int32_t n_shape
         ctx->tv_part.alloc((size_t)std::max<int64_t>(n_bricks, 1)) != hipSuccess ||
         ctx->tau.alloc((size_t)std::max<int64_t>(n_slots, 1)) != hipSuccess ||
         ctx->inv_qv.alloc(n_shapes) != hipSuccess || ctx->flag.alloc(1) != hipSuccess ||
+        ctx->fin_part.alloc((size_t)n_shapes * 32 * 5) != hipSuccess || ctx->fin_count.alloc(n_shapes) != hipSuccess ||
         ctx->iter.alloc(1) != hipSuccess || ctx->step_c.alloc(2) != hipSuccess ||
         ctx->g_raw.alloc((size_t)std::max<int64_t>(n_slots, 1)) != hipSuccess)
         return gp_fail(ctx, GP_ERR_OOM, "out of device memory for the iteration scratch");
     GP_HIP(ctx, hipMemsetAsync(ctx->flag.p, 0, 4, st));
+    GP_HIP(ctx, hipMemsetAsync(ctx->fin_count.p, 0, 4 * (size_t)n_shapes, st));
     GP_HIP(ctx, hipMemsetAsync(ctx->iter.p, 0, 4, st));
     GP_HIP(ctx, hipMemsetAsync(ctx->tau.p, 0, std::max<int64_t>(n_slots, 1) * 4, st));
     GP_HIP(ctx, hipMemsetAsync(ctx->g_raw.p, 0, std::max<int64_t>(n_slots, 1) * 4, st));

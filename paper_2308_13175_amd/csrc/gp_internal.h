@@ -310,6 +310,8 @@ struct gp_ctx_s {
     DevBuf<double> tv_part;       // [n_bricks] sum tau
     DevBuf<float> tau;            // [n_slots] 1 / tau of the last forward (0 where tau = 0)
     DevBuf<double> inv_qv;        // [n_shapes] 1 / valid count (0 if none)
+    DevBuf<double> fin_part;      // [n_shapes][32][5] chunk sums of the loss reduction
+    DevBuf<int32_t> fin_count;    // [n_shapes] chunks finished (back to 0 after each reduction)
     DevBuf<int32_t> flag;         // device error flag
     DevBuf<int32_t> iter;         // device-resident iteration counter (last Adam t)
     DevBuf<float> step_c;         // [2] lr_t / (1 - beta1^t), 1 / sqrt(1 - beta2^t)

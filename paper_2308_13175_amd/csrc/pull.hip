@@ -11,6 +11,8 @@
 // Vertex side, one block per brick: tau_i over the six axis neighbours that
 //   are TV vertices (Eq. 5) in the forward; in the backward the gradient is
 //   gathered per vertex (each vertex writes only its own slot).
+#include <algorithm>
+
 #include "gp_internal.h"
 
 namespace gp {
@@ -775,27 +777,36 @@ __global__ __launch_bounds__(kTvWaves * 64, 5) void k_tv_backward_wave(Band B, c
             if ((touched >> k) & 1u) *at32(G, (uint32_t)(slot0 + k)) += add[k];
 }
 
-// One block per shape: deterministic sums of the tile and brick partials.
-// The tile partials of a shape are contiguous (4 doubles per entry); each
-// thread reads pairs of them with a fixed stride, so it always adds to the
-// same two of the four sums.
-constexpr int kFinalizeBlock = 1024;
+// Per-shape loss from the tile and brick partials, deterministically:
+// kFinChunks blocks per shape (fewer were measured slower, even for small
+// shapes) each sum a fixed contiguous chunk of them and write their five sums
+// to fin_part; the last block of the shape to finish (a per-shape counter,
+// reset by that block for the next call) adds the chunks in order.  The tile
+// partials are pairs of doubles, (pull, surface) then (gradient term, count);
+// a chunk starts on an even pair and the block stride is even, so a thread
+// always adds to the same two of the four sums.
+constexpr int kFinalizeBlock = 256;
+constexpr int kFinChunks = 32;
 
 __global__ __launch_bounds__(kFinalizeBlock) void k_finalize(Band B, const double* __restrict__ q_part,
                                                              const double* __restrict__ tv_part, gp_weights w,
                                                              double* __restrict__ loss_out,
                                                              int64_t* __restrict__ n_valid_out,
                                                              double* __restrict__ inv_qv, int32_t* __restrict__ flag,
-                                                             int32_t parts)
+                                                             int32_t parts, double* __restrict__ fin_part,
+                                                             int32_t* __restrict__ fin_count)
 {
     __shared__ double lds[kFinalizeBlock / 64 * 5];
-    const int32_t shape = blockIdx.x;
+    __shared__ int32_t s_last;
+    const int32_t chunk = blockIdx.x, nch = gridDim.x, shape = blockIdx.y;
     const ShapeDesc& s = B.shapes[shape];
     double v[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
     // q_part holds `parts` partial sums per tile, 4 doubles each
     const double2* qp = reinterpret_cast<const double2*>(q_part);
-    const int64_t pb = s.tile_begin * parts * 2, pe = s.tile_end * parts * 2;
-    const int hi = threadIdx.x & 1;   // (kFinalizeBlock is even: a thread's pairs are all low or all high)
+    const int64_t np = (s.tile_end - s.tile_begin) * parts;            // pairs of pairs
+    const int64_t pb = s.tile_begin * parts * 2 + 2 * (np * chunk / nch);
+    const int64_t pe = s.tile_begin * parts * 2 + 2 * (np * (chunk + 1) / nch);
+    const int hi = threadIdx.x & 1;
     // four independent accumulators so that four loads are in flight per thread
     double a0[4] = {0.0, 0.0, 0.0, 0.0}, a1[4] = {0.0, 0.0, 0.0, 0.0};
     int64_t m = pb + threadIdx.x;
@@ -823,21 +834,9 @@ __global__ __launch_bounds__(kFinalizeBlock) void k_finalize(Band B, const doubl
     v[1] = hi ? 0.0 : s1;
     v[2] = hi ? s0 : 0.0;
     v[3] = hi ? s1 : 0.0;
-    double t4[4] = {0.0, 0.0, 0.0, 0.0};
-    int64_t b = s.brick_begin + threadIdx.x;
-    for (; b + 3 * (int64_t)blockDim.x < s.brick_end; b += 4 * (int64_t)blockDim.x) {
-        double d[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) d[u] = tv_part[b + u * (int64_t)blockDim.x];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) t4[u] += d[u];
-    }
-#pragma unroll
-    for (int u = 0; u < 3; ++u) {
-        if (b < s.brick_end) t4[u] += tv_part[b];
-        b += blockDim.x;
-    }
-    v[4] = (t4[0] + t4[1]) + (t4[2] + t4[3]);
+    const int64_t nbk = s.brick_end - s.brick_begin;
+    const int64_t bb = s.brick_begin + nbk * chunk / nch, be = s.brick_begin + nbk * (chunk + 1) / nch;
+    for (int64_t b = bb + threadIdx.x; b < be; b += blockDim.x) v[4] += tv_part[b];
 #pragma unroll
     for (int i = 0; i < 5; ++i)
         for (int o = 32; o > 0; o >>= 1) v[i] += __shfl_xor(v[i], o, 64);
@@ -845,29 +844,47 @@ __global__ __launch_bounds__(kFinalizeBlock) void k_finalize(Band B, const doubl
     if (lane == 0)
         for (int i = 0; i < 5; ++i) lds[wave * 5 + i] = v[i];
     __syncthreads();
-    if (wave != 0) return;
-    constexpr int kFinalizeWaves = kFinalizeBlock / 64;
-    static_assert((kFinalizeWaves & (kFinalizeWaves - 1)) == 0 && kFinalizeWaves <= 64, "power-of-two waves");
+    if (threadIdx.x == 0) {
+        double* out = fin_part + ((int64_t)shape * kFinChunks + chunk) * 5;
+        for (int i = 0; i < 5; ++i) {
+            double a = 0.0;
+            for (int wv = 0; wv < kFinalizeBlock / 64; ++wv) a += lds[wv * 5 + i];
+            out[i] = a;
+        }
+        __threadfence();
+        s_last = atomicAdd(&fin_count[shape], 1) == nch - 1;
+    }
+    __syncthreads();
+    if (!s_last) return;
+    // the shape's last block: every chunk's sums are visible after the fence;
+    // one load per thread, then the chunks are added in order
+    static_assert(kFinChunks * 5 <= kFinalizeBlock, "one chunk sum per thread");
+    __shared__ double s_chunk[kFinChunks * 5];
+    __threadfence();
+    if (threadIdx.x < nch * 5)
+        s_chunk[threadIdx.x] = __hip_atomic_load(fin_part + (int64_t)shape * kFinChunks * 5 + threadIdx.x,
+                                                 __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    double t[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+#pragma unroll 1
+    for (int c = 0; c < nch; ++c)
 #pragma unroll
-    for (int i = 0; i < 5; ++i) {
-        v[i] = lane < kFinalizeWaves ? lds[lane * 5 + i] : 0.0;
-        for (int o = kFinalizeWaves / 2; o > 0; o >>= 1) v[i] += __shfl_xor(v[i], o, 64);
-    }
-    if (lane == 0) {
-        const double nq = v[3];
-        const double iq = nq > 0.0 ? 1.0 / nq : 0.0;
-        const double pull = v[0] * iq, surf = v[1] * iq, grad = v[2] * iq;
-        const double tv = s.n_tv > 0 ? v[4] / (double)s.n_tv : 0.0;
-        const double total = pull + (double)w.alpha * tv + (double)w.beta * surf + (double)w.gamma * grad;
-        loss_out[shape * 5 + 0] = total;
-        loss_out[shape * 5 + 1] = pull;
-        loss_out[shape * 5 + 2] = tv;
-        loss_out[shape * 5 + 3] = surf;
-        loss_out[shape * 5 + 4] = grad;
-        n_valid_out[shape] = (int64_t)nq;
-        inv_qv[shape] = iq;
-        if (!isfinite(total)) atomicOr(flag, 1);
-    }
+        for (int i = 0; i < 5; ++i) t[i] += s_chunk[c * 5 + i];
+    atomicExch(&fin_count[shape], 0);
+    const double nq = t[3];
+    const double iq = nq > 0.0 ? 1.0 / nq : 0.0;
+    const double pull = t[0] * iq, surf = t[1] * iq, grad = t[2] * iq;
+    const double tv = s.n_tv > 0 ? t[4] / (double)s.n_tv : 0.0;
+    const double total = pull + (double)w.alpha * tv + (double)w.beta * surf + (double)w.gamma * grad;
+    loss_out[shape * 5 + 0] = total;
+    loss_out[shape * 5 + 1] = pull;
+    loss_out[shape * 5 + 2] = tv;
+    loss_out[shape * 5 + 3] = surf;
+    loss_out[shape * 5 + 4] = grad;
+    n_valid_out[shape] = (int64_t)nq;
+    inv_qv[shape] = iq;
+    if (!isfinite(total)) atomicOr(flag, 1);
 }
 
 }  // namespace
@@ -924,8 +941,9 @@ gp_status gp_forward_impl(gp_ctx ctx, const float* qx, const float* qy, const fl
         launch_tv_forward(ctx, B, field, st);
     }
     GP_TIMED(ctx, "k_finalize");
-    k_finalize<<<(unsigned)ctx->n_shapes, kFinalizeBlock, 0, st>>>(B, ctx->q_part.p, ctx->tv_part.p, w, loss_out, n_valid_out,
-                                                        ctx->inv_qv.p, ctx->flag.p, 1);
+    k_finalize<<<dim3(kFinChunks, (unsigned)ctx->n_shapes), kFinalizeBlock, 0, st>>>(
+        B, ctx->q_part.p, ctx->tv_part.p, w, loss_out, n_valid_out, ctx->inv_qv.p, ctx->flag.p, 1, ctx->fin_part.p,
+        ctx->fin_count.p);
     GP_HIP(ctx, hipGetLastError());
     ctx->have_forward = true;
     return GP_OK;
@@ -968,8 +986,9 @@ gp_status gp_forward_backward_impl(gp_ctx ctx, const float* qx, const float* qy,
     }
     {
         GP_TIMED(ctx, "k_finalize");
-        k_finalize<<<(unsigned)ctx->n_shapes, kFinalizeBlock, 0, st>>>(B, ctx->q_part.p, ctx->tv_part.p, w, loss_out,
-                                                            n_valid_out, ctx->inv_qv.p, ctx->flag.p, kGradParts);
+        k_finalize<<<dim3(kFinChunks, (unsigned)ctx->n_shapes), kFinalizeBlock, 0, st>>>(
+            B, ctx->q_part.p, ctx->tv_part.p, w, loss_out, n_valid_out, ctx->inv_qv.p, ctx->flag.p, kGradParts,
+            ctx->fin_part.p, ctx->fin_count.p);
     }
     if (ctx->n_bricks > 0) {
         GP_TIMED(ctx, "k_tv_backward");
