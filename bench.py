@@ -187,7 +187,7 @@ def copy_calibration(mib=256, reps=3):
 
 
 def batched_vs_per_shape(wl, prob, steps, warmup, autotune=True):
-    """Config 4: one batched launch sequence against one context per shape.
+    """The 64-shape batch: one batched launch sequence against one context per shape.
 
     Times the same iteration (eager and as captured graphs) both ways, then
     puts both in the same state (geometric initial field, the batched
@@ -465,7 +465,7 @@ def main():
                     help="also run a plain 256 MiB device copy (scale for the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path (--gpus %d requested)" % args.gpus,
+        print("bench.py measures one GPU only: the library has no multi-GPU path (--gpus %d requested)" % args.gpus,
               file=sys.stderr)
         sys.exit(2)
 
