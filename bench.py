@@ -488,9 +488,10 @@ def main():
     tuned_ms = None
     if not args.no_autotune:
         _, tuned_ms = prob.autotune(reps=3)
-    nn_span, nn_shell, nn_parts, nn_skip = gp.gp_get_nn_params(prob.ctx)
-    log("NN search shape: group span %d, first shell %d, %d blocks per tile, skip empty %d%s" % (
-        nn_span, nn_shell, nn_parts, nn_skip, " (autotuned, %.3f ms)" % tuned_ms if tuned_ms is not None else ""))
+    nn_span, nn_shell, nn_parts, nn_skip, nn_sort = gp.gp_get_nn_params(prob.ctx)
+    log("NN search shape: group span %d, first shell %d, %d blocks per tile, skip empty %d, sort %d%s" % (
+        nn_span, nn_shell, nn_parts, nn_skip, nn_sort,
+        " (autotuned, %.3f ms)" % tuned_ms if tuned_ms is not None else ""))
     torch.cuda.synchronize()
     gp.gp_timing_enable(prob.ctx, True)
     gp.gp_timing_report(prob.ctx)          # start a clean period
@@ -583,6 +584,7 @@ def main():
                    "step": "sample+nn+forward+backward+adam"},
         "roofline": roof,
         "nn_search": {"group_span": nn_span, "first_shell": nn_shell, "tile_parts": nn_parts, "skip_empty": nn_skip,
+                      "morton_sort": nn_sort,
                       "autotuned": tuned_ms is not None,
                       "autotune_best_ms": tuned_ms},
         "fwd_bwd": {"queries_per_s": Q / (fb_ms * 1e-3), "ms": fb_ms, "median_ms": fb_median,

@@ -161,13 +161,15 @@ gp_status gp_nn_query(gp_ctx ctx, const float* qx, const float* qy, const float*
  * gives small batches more blocks.  With skip_empty, every column of cells
  * to be scanned is first cut to its first and last cell holding a point (a
  * bitmap of one bit per cell), which saves range lookups where points are
- * sparse.
+ * sparse.  Without morton_sort the groups are cut along the queries' own
+ * order (enough when the caller's order is already spatially coherent).
  */
 typedef struct {
     int32_t group_span;    /* [1, 64], default 8 */
     int32_t first_shell;   /* [0, 4], default 1 */
     int32_t tile_parts;    /* 1, 2 or 4, default 1 */
     int32_t skip_empty;    /* 0 or 1, default 0 */
+    int32_t morton_sort;   /* 0 or 1, default 1 */
 } gp_nn_params;
 
 /*
@@ -181,7 +183,8 @@ gp_status gp_get_nn_params(gp_ctx ctx, gp_nn_params* params);
  * Autotuner of the search shape: runs gp_nn_query's kernel on the given
  * queries for group_span in {4, 6, 8, 12, 16, 24, 32} x first_shell in
  * {0, 1, 2} at the current tile_parts and skip_empty, then tile_parts in
- * {1, 2, 4} at the best of those, then the other skip_empty setting; each
+ * {1, 2, 4} at the best of those, then the other skip_empty setting, then
+ * the other morton_sort setting; each
  * candidate once untimed and then reps times between HIP events on the
  * context's stream (its time: the smallest of those).  Keeps the fastest in
  * the context and leaves nn_out holding the nearest neighbours (as

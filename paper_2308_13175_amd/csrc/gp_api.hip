@@ -201,10 +201,13 @@ gp_status gp_set_nn_params(gp_ctx ctx, const gp_nn_params* params)
     if (params->tile_parts != 1 && params->tile_parts != 2 && params->tile_parts != 4)
         return gp_fail(ctx, GP_ERR_ARG, "tile_parts must be 1, 2 or 4");
     if (params->skip_empty != 0 && params->skip_empty != 1) return gp_fail(ctx, GP_ERR_ARG, "skip_empty must be 0 or 1");
+    if (params->morton_sort != 0 && params->morton_sort != 1)
+        return gp_fail(ctx, GP_ERR_ARG, "morton_sort must be 0 or 1");
     ctx->nn_params.span = params->group_span;
     ctx->nn_params.shell = params->first_shell;
     ctx->nn_params.parts = params->tile_parts;
     ctx->nn_params.skip_empty = params->skip_empty;
+    ctx->nn_params.sort = params->morton_sort;
     return GP_OK;
 }
 
@@ -214,6 +217,7 @@ static void nn_params_out(const gp::NnParams& p, gp_nn_params* out)
     out->first_shell = p.shell;
     out->tile_parts = p.parts;
     out->skip_empty = p.skip_empty;
+    out->morton_sort = p.sort;
 }
 
 gp_status gp_get_nn_params(gp_ctx ctx, gp_nn_params* params)

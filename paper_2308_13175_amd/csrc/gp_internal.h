@@ -71,8 +71,9 @@ struct Band {
 // Nearest-neighbour search shape: a group of queries is cut where its cells
 // would span `span` or more cells on an axis, its lockstep box is the group's
 // cell box grown by `shell` cells, `parts` blocks (1, 2 or 4) share each
-// query tile, and with skip_empty every column of cells is first trimmed to
-// its first and last occupied cell (occupancy bitmap).  Any values give the
+// query tile, with skip_empty every column of cells is first trimmed to its
+// first and last occupied cell (occupancy bitmap), and without sort the
+// groups are cut along the input order.  Any values give the
 // same exact result; they only move work between the lockstep and per-query
 // passes, between blocks, and between loads of bitmap words and of ranges.
 struct NnParams {
@@ -80,6 +81,7 @@ struct NnParams {
     int32_t shell = 1;
     int32_t parts = 1;
     int32_t skip_empty = 0;   // trim each scanned column to its occupied cells first
+    int32_t sort = 1;         // Morton-sort each tile before grouping (else the input order)
 };
 constexpr int32_t kNnSpanMax = 64;
 constexpr int32_t kNnShellMax = 4;

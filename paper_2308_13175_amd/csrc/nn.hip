@@ -575,7 +575,7 @@ __global__ __launch_bounds__(kQueryBlock, 4) void k_nn(Band B, Global G, NnParam
     int32_t span = 1;
     for (int a = 0; a < 3; ++a) span = max(span, box[3 + a] - box[a] + 1);
     const int32_t bits = min(3 * (32 - __builtin_clz((uint32_t)span - 1u | 1u)), 30);
-    BlockSort(sort_tmp).Sort(key, val, 0, bits);
+    if (P.sort) BlockSort(sort_tmp).Sort(key, val, 0, bits);   // (uniform: every thread or none)
 #pragma unroll
     for (int j = 0; j < kQueriesPerThread; ++j) {
         const int32_t pos = threadIdx.x * kQueriesPerThread + j;
@@ -759,8 +759,8 @@ gp_status gp_nn_impl(gp_ctx ctx, const float* qx, const float* qy, const float* 
 
 // Times k_nn for every (span, shell) pair of a small grid on the caller's
 // queries (the results are the same for all of them), then the number of
-// blocks per tile for the best pair, then the other skip_empty setting, and
-// keeps the fastest in the context.
+// blocks per tile for the best pair, then the other skip_empty setting, then
+// the other sort setting, and keeps the fastest in the context.
 // Each candidate runs once untimed, then `reps` times between events; its
 // time is the smallest of those.  The context's current setting is timed
 // first and is only replaced by one at least 2% faster, so timing noise does
@@ -804,7 +804,8 @@ gp_status gp_autotune_nn_impl(gp_ctx ctx, const float* qx, const float* qy, cons
             const float t = time_one(P);
             if (e != hipSuccess || t < 0.f) return;
             const bool holding = best.span == current.span && best.shell == current.shell &&
-                                 best.parts == current.parts && best.skip_empty == current.skip_empty;
+                                 best.parts == current.parts && best.skip_empty == current.skip_empty &&
+                                 best.sort == current.sort;
             if (best_ms < 0.f || t < best_ms * (holding ? 0.98f : 1.f)) {
                 best_ms = t;
                 best = P;
@@ -827,6 +828,11 @@ gp_status gp_autotune_nn_impl(gp_ctx ctx, const float* qx, const float* qy, cons
         {
             NnParams P = best;
             P.skip_empty = !best.skip_empty;
+            offer(P);
+        }
+        {
+            NnParams P = best;
+            P.sort = !best.sort;
             offer(P);
         }
         (void)hipEventDestroy(ev[0]);

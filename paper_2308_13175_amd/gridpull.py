@@ -46,10 +46,10 @@ class gp_weights(ctypes.Structure):
 
 class gp_nn_params(ctypes.Structure):
     _fields_ = [("group_span", ctypes.c_int32), ("first_shell", ctypes.c_int32), ("tile_parts", ctypes.c_int32),
-                ("skip_empty", ctypes.c_int32)]
+                ("skip_empty", ctypes.c_int32), ("morton_sort", ctypes.c_int32)]
 
-    def as_tuple(self) -> Tuple[int, int, int, int]:
-        return (self.group_span, self.first_shell, self.tile_parts, self.skip_empty)
+    def as_tuple(self) -> Tuple[int, int, int, int, int]:
+        return (self.group_span, self.first_shell, self.tile_parts, self.skip_empty, self.morton_sort)
 
 
 _lib = None
@@ -184,8 +184,9 @@ def gp_nn_query(ctx, qx, qy, qz, nn_out) -> None:
                                            _ptr(qz, torch.float32), qx.numel(), _ptr(nn_out, torch.int32)))
 
 
-def gp_set_nn_params(ctx, group_span: int, first_shell: int, tile_parts: int = 1, skip_empty: int = 0) -> None:
-    p = gp_nn_params(int(group_span), int(first_shell), int(tile_parts), int(skip_empty))
+def gp_set_nn_params(ctx, group_span: int, first_shell: int, tile_parts: int = 1, skip_empty: int = 0,
+                     morton_sort: int = 1) -> None:
+    p = gp_nn_params(int(group_span), int(first_shell), int(tile_parts), int(skip_empty), int(morton_sort))
     _check(ctx, load_library().gp_set_nn_params(ctx, ctypes.byref(p)))
 
 
@@ -194,16 +195,16 @@ def gp_set_tv_layout(ctx, layout: int) -> None:
     _check(ctx, load_library().gp_set_tv_layout(ctx, int(layout)))
 
 
-def gp_get_nn_params(ctx) -> Tuple[int, int, int, int]:
-    """(group_span, first_shell, tile_parts, skip_empty)."""
+def gp_get_nn_params(ctx) -> Tuple[int, int, int, int, int]:
+    """(group_span, first_shell, tile_parts, skip_empty, morton_sort)."""
     p = gp_nn_params()
     _check(ctx, load_library().gp_get_nn_params(ctx, ctypes.byref(p)))
     return p.as_tuple()
 
 
-def gp_autotune_nn(ctx, qx, qy, qz, nn_out, reps: int = 2) -> Tuple[Tuple[int, int, int, int], float]:
+def gp_autotune_nn(ctx, qx, qy, qz, nn_out, reps: int = 2) -> Tuple[Tuple[int, int, int, int, int], float]:
     """Time the NN search shapes on these queries and keep the fastest:
-    ((group_span, first_shell, tile_parts, skip_empty), ms)."""
+    ((group_span, first_shell, tile_parts, skip_empty, morton_sort), ms)."""
     _stream(ctx)
     p, ms = gp_nn_params(), ctypes.c_float(0.0)
     _check(ctx, load_library().gp_autotune_nn(ctx, _ptr(qx, torch.float32), _ptr(qy, torch.float32),

@@ -185,7 +185,7 @@ class Problem:
     def autotune(self, reps: int = 2):
         """Pick the NN search shape by timing it on the current queries (leaves nn filled).
 
-        Returns ((group_span, first_shell, tile_parts, skip_empty), best ms)."""
+        Returns ((group_span, first_shell, tile_parts, skip_empty, morton_sort), best ms)."""
         return gp.gp_autotune_nn(self.ctx, self.qx[: self.n_queries], self.qy[: self.n_queries],
                                  self.qz[: self.n_queries], self.nn, reps)
 

@@ -340,9 +340,9 @@ def test_nn_search_shapes_and_autotuner():
         nn = oracle.nn_bruteforce(q, pts)
         prob = make_problem([spec(pts, dom, len(q), 0.0)])
         prob.set_queries(q)
-        assert gp.gp_get_nn_params(prob.ctx) == (8, 1, 1, 0)
-        for shape in [(1, 0, 1, 0), (2, 0, 4, 1), (3, 2, 2, 0), (8, 1, 4, 1), (8, 1, 1, 1), (16, 0, 2, 1),
-                      (64, 4, 1, 0), (64, 4, 4, 1)]:
+        assert gp.gp_get_nn_params(prob.ctx) == (8, 1, 1, 0, 1)
+        for shape in [(1, 0, 1, 0, 1), (2, 0, 4, 1, 0), (3, 2, 2, 0, 1), (8, 1, 4, 1, 1), (8, 1, 1, 1, 0),
+                      (16, 0, 2, 1, 1), (64, 4, 1, 0, 0), (64, 4, 4, 1, 1)]:
             log("case: %s, search shape %s" % (name, shape))
             gp.gp_set_nn_params(prob.ctx, *shape)
             prob.nn.fill_(-7)
@@ -352,20 +352,21 @@ def test_nn_search_shapes_and_autotuner():
             bad = np.nonzero(got != nn)[0]
             assert len(bad) == 0, "%s shape %s: %d differ" % (name, shape, len(bad))
         log("case: %s, autotuner" % name)
-        gp.gp_set_nn_params(prob.ctx, 8, 1, 1, 0)   # the tuner starts from the current setting
+        gp.gp_set_nn_params(prob.ctx, 8, 1, 1, 0, 1)   # the tuner starts from the current setting
         prob.nn.fill_(-7)
         chosen, ms = prob.autotune(reps=1)
         prob.sync()
-        span, shell, parts, skip = chosen
-        assert span in (4, 6, 8, 12, 16, 24, 32) and shell in (0, 1, 2) and parts in (1, 2, 4) and skip in (0, 1)
+        span, shell, parts, skip, sort = chosen
+        assert span in (4, 6, 8, 12, 16, 24, 32) and shell in (0, 1, 2) and parts in (1, 2, 4)
+        assert skip in (0, 1) and sort in (0, 1)
         assert ms > 0
         assert gp.gp_get_nn_params(prob.ctx) == chosen
         assert np.array_equal(prob.nn[: len(q)].cpu().numpy(), nn)
         prob.nearest()
         prob.sync()
         assert np.array_equal(prob.nn[: len(q)].cpu().numpy(), nn)
-        for bad_args in [(0, 1, 1, 0), (65, 1, 1, 0), (8, -1, 1, 0), (8, 5, 1, 0), (8, 1, 3, 0), (8, 1, 0, 0),
-                         (8, 1, 1, 2)]:
+        for bad_args in [(0, 1, 1, 0, 1), (65, 1, 1, 0, 1), (8, -1, 1, 0, 1), (8, 5, 1, 0, 1), (8, 1, 3, 0, 1),
+                         (8, 1, 0, 0, 1), (8, 1, 1, 2, 1), (8, 1, 1, 0, 2)]:
             with pytest.raises(gp.GridPullError) as ei:
                 gp.gp_set_nn_params(prob.ctx, *bad_args)
             assert ei.value.status == 1
