@@ -39,8 +39,8 @@ def _load():
     global _lib
     if _lib is not None:
         return _lib
-    if not os.path.exists(_LIB):
-        build(force=True)
+    if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        build(force=True)   # missing or older than its source
     lib = ctypes.CDLL(_LIB)
     P = ctypes.c_void_p
     i64, i32, u32, u64, f64 = ctypes.c_int64, ctypes.c_int32, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_double
@@ -59,6 +59,8 @@ def _load():
     lib.og_philox4x32_10.argtypes = [P, P, P]
     lib.og_query_offsets.restype = None
     lib.og_query_offsets.argtypes = [u64, u32, u32, i64, i64, P]
+    lib.og_extract_surface.restype = i64
+    lib.og_extract_surface.argtypes = [P, P, P, P, P, i64, P, P]
     _lib = lib
     return lib
 
@@ -225,3 +227,20 @@ def nn_exact(queries: np.ndarray, points: np.ndarray, k: int = 16, workers: int 
         sel = np.nonzero(unsafe)[0]
         out[sel] = nn_bruteforce(q[sel], p)
     return out
+
+
+def extract_surface(dims, lo, hi, D: np.ndarray, vert_flags: np.ndarray):
+    """Zero level set of the field over the cells whose eight corners are
+    optimised (the mesh step after the optimisation, Sec. 3/4), by marching
+    tetrahedra (six per cell along its main diagonal; the C file states the
+    reading).  Returns (keys int64 [n] = cell_id * 16 + tet * 2 + triangle,
+    triangles float64 [n, 3, 3]) in key order."""
+    lib = _load()
+    R, L, H = _grid(dims, lo, hi)
+    Dd = np.ascontiguousarray(D, dtype=np.float64)
+    vf = np.ascontiguousarray(vert_flags, dtype=np.uint8)
+    n = lib.og_extract_surface(_p(R), _p(L), _p(H), _p(Dd), _p(vf), 0, None, None)
+    keys = np.zeros(max(n, 1), dtype=np.int64)
+    xyz = np.zeros((max(n, 1), 3, 3), dtype=np.float64)
+    lib.og_extract_surface(_p(R), _p(L), _p(H), _p(Dd), _p(vf), n, _p(keys), _p(xyz))
+    return keys[:n], xyz[:n]

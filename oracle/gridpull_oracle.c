@@ -516,3 +516,106 @@ void og_query_offsets(uint64_t seed, uint32_t iteration, uint32_t stream, int64_
         z_out[3 * i + 2] = r1 * cos(two_pi * U[3]);
     }
 }
+
+/* ------------------------------------------------------------------------ */
+/* Surface extraction (the mesh step after the optimisation, Sec. 3/4: the    */
+/* zero level set of the field over the cells that were optimised).          */
+/* Reading taken here: marching tetrahedra instead of the marching-cubes      */
+/* case table.  Every cell whose eight corners are optimised vertices is cut  */
+/* into six tetrahedra along its main diagonal (corner (0,0,0) to (1,1,1),   */
+/* corner (a,b,c) at index 4a + 2b + c); the cut is the same on both sides of */
+/* every face, so the mesh has no cracks.  A vertex is inside where f < 0.   */
+/* A tetrahedron with one vertex on one side and three on the other gives    */
+/* one triangle, two and two give two; each triangle vertex sits on an edge  */
+/* (p, q), p inside, where the linear interpolant vanishes:                 */
+/* p + f_p / (f_p - f_q) (q - p).                                           */
+/* Triangles are listed by cell id, then tetrahedron, then triangle; the     */
+/* key of a triangle is cell_id * 16 + tet * 2 + triangle.                   */
+/* ------------------------------------------------------------------------ */
+
+/* the six tetrahedra: (0, A, B, 7) along the paths 0 -> A -> B -> 7 */
+static const int kTets[6][4] = {{0, 4, 6, 7}, {0, 4, 5, 7}, {0, 2, 6, 7},
+                                {0, 2, 3, 7}, {0, 1, 5, 7}, {0, 1, 3, 7}};
+
+static void edge_point(const double P[8][3], const double f[8], int a, int b, double out[3])
+{
+    double t = f[a] / (f[a] - f[b]);
+    for (int k = 0; k < 3; ++k) out[k] = P[a][k] + t * (P[b][k] - P[a][k]);
+}
+
+/* Triangles of one tetrahedron (corner indices v[4] into P, f): returns how
+ * many (0, 1 or 2) and writes their vertices to tri[2][3][3]. */
+static int tet_triangles(const double P[8][3], const double f[8], const int v[4], double tri[2][3][3])
+{
+    int in[4], out[4], ni = 0, no = 0;
+    for (int i = 0; i < 4; ++i) {
+        if (f[v[i]] < 0.0) in[ni++] = v[i];
+        else out[no++] = v[i];
+    }
+    if (ni == 0 || no == 0) return 0;
+    if (ni == 1 || no == 1) {
+        /* the lone vertex and the three edges leaving it; every edge point is
+         * taken from its inside end, so that a grid edge gives the same point
+         * in every tetrahedron that has it */
+        for (int k = 0; k < 3; ++k) {
+            if (ni == 1) edge_point(P, f, in[0], out[k], tri[0][k]);
+            else edge_point(P, f, in[k], out[0], tri[0][k]);
+        }
+        return 1;
+    }
+    /* two in (a, b), two out (c, d): the quad ac, ad, bd, bc as two triangles */
+    double ac[3], ad[3], bd[3], bc[3];
+    edge_point(P, f, in[0], out[0], ac);
+    edge_point(P, f, in[0], out[1], ad);
+    edge_point(P, f, in[1], out[1], bd);
+    edge_point(P, f, in[1], out[0], bc);
+    for (int k = 0; k < 3; ++k) {
+        tri[0][0][k] = ac[k]; tri[0][1][k] = ad[k]; tri[0][2][k] = bd[k];
+        tri[1][0][k] = ac[k]; tri[1][1][k] = bd[k]; tri[1][2][k] = bc[k];
+    }
+    return 2;
+}
+
+/* D: dense vertex values; vert_flags bit 1: optimised vertex.  Writes at most
+ * capacity triangles (keys and 9 coordinates each) and returns how many the
+ * field has in total. */
+int64_t og_extract_surface(const int32_t* R_in, const double* lo, const double* hi, const double* D,
+                           const uint8_t* vert_flags, int64_t capacity, int64_t* keys, double* xyz)
+{
+    grid_t g;
+    grid_init(&g, R_in, lo, hi);
+    int64_t n = 0;
+    for (int64_t cx = 0; cx < g.R[0]; ++cx)
+    for (int64_t cy = 0; cy < g.R[1]; ++cy)
+    for (int64_t cz = 0; cz < g.R[2]; ++cz) {
+        double P[8][3], f[8];
+        int all = 1;
+        for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b)
+        for (int c = 0; c < 2; ++c) {
+            int64_t vid = vertex_id(&g, cx + a, cy + b, cz + c);
+            int i = 4 * a + 2 * b + c;
+            if (!(vert_flags[vid] & 1)) all = 0;
+            f[i] = D[vid];
+            P[i][0] = g.lo[0] + (double)(cx + a) * g.h[0];
+            P[i][1] = g.lo[1] + (double)(cy + b) * g.h[1];
+            P[i][2] = g.lo[2] + (double)(cz + c) * g.h[2];
+        }
+        if (!all) continue;
+        int64_t c3[3] = {cx, cy, cz};
+        int64_t cid = cell_id(&g, c3);
+        for (int t = 0; t < 6; ++t) {
+            double tri[2][3][3];
+            int m = tet_triangles(P, f, kTets[t], tri);
+            for (int r = 0; r < m; ++r) {
+                if (n < capacity) {
+                    keys[n] = cid * 16 + t * 2 + r;
+                    for (int v = 0; v < 3; ++v)
+                        for (int k = 0; k < 3; ++k) xyz[9 * n + 3 * v + k] = tri[r][v][k];
+                }
+                ++n;
+            }
+        }
+    }
+    return n;
+}

@@ -1,0 +1,96 @@
+"""Pins of the oracle's surface extraction (marching tetrahedra over the
+optimised cells): hand-counted cases, a plane, and a closed sphere."""
+import numpy as np
+
+import oracle
+
+
+def _one_cell(values):
+    """A single cell (grid 1x1x1 over [0,1]^3) with the given corner values,
+    corner (a,b,c) at index 4a + 2b + c, every vertex optimised."""
+    dims, lo, hi = (1, 1, 1), (0.0, 0.0, 0.0), (1.0, 1.0, 1.0)
+    D = np.zeros(8)
+    for a in range(2):
+        for b in range(2):
+            for c in range(2):
+                D[(a * 2 + b) * 2 + c] = values[4 * a + 2 * b + c]
+    return oracle.extract_surface(dims, lo, hi, D, np.ones(8, np.uint8))
+
+
+def test_single_negative_corner_counts():
+    # corner 0 and corner 7 lie in all six tetrahedra, corner 4 (x) in two,
+    # so one negative corner gives 6, 6 and 2 triangles
+    for corner, expect in [(0, 6), (7, 6), (4, 2), (2, 2), (1, 2), (6, 2), (5, 2), (3, 2)]:
+        v = np.ones(8)
+        v[corner] = -1.0
+        keys, tri = _one_cell(v)
+        assert len(keys) == expect, (corner, len(keys))
+        # every triangle vertex is the midpoint of an edge from that corner (values -1 / 1)
+        cx = np.array([corner >> 2 & 1, corner >> 1 & 1, corner & 1], float)
+        d = np.abs(tri.reshape(-1, 3) - cx).max(axis=1)
+        assert np.allclose(d, 0.5)
+
+
+def test_no_sign_change_and_all_inside():
+    assert len(_one_cell(np.ones(8))[0]) == 0
+    assert len(_one_cell(-np.ones(8))[0]) == 0
+
+
+def test_checkerboard_of_two_and_two():
+    # x < 0.5 inside: value = x - 0.5 at the corners: every tetrahedron has
+    # two corners each side or one and three; the cut is the plane x = 0.5
+    v = np.array([(a - 0.5) for a in (0, 0, 0, 0, 1, 1, 1, 1)], float)
+    keys, tri = _one_cell(v)
+    assert len(keys) > 0
+    assert np.allclose(tri[..., 0], 0.5)
+    # the triangles cover the unit square of the plane exactly once
+    e1 = tri[:, 1] - tri[:, 0]
+    e2 = tri[:, 2] - tri[:, 0]
+    area = 0.5 * np.linalg.norm(np.cross(e1, e2), axis=1).sum()
+    assert abs(area - 1.0) < 1e-12
+
+
+def test_plane_in_a_dense_band():
+    # D = z - c over a 6x5x7 grid, every cell optimised: all vertices on the
+    # plane and the area equals the domain's x-y extent
+    dims, lo, hi = (6, 5, 7), (-1.0, -0.5, -0.75), (0.5, 0.75, 1.0)
+    c = 0.1234
+    V = np.array(dims) + 1
+    z = lo[2] + np.arange(V[2]) * ((hi[2] - lo[2]) / dims[2])
+    D = np.broadcast_to(z - c, (V[0], V[1], V[2])).reshape(-1).astype(np.float64)
+    keys, tri = oracle.extract_surface(dims, lo, hi, D, np.ones(int(V.prod()), np.uint8))
+    assert np.abs(tri[..., 2] - c).max() < 1e-12
+    e1 = tri[:, 1] - tri[:, 0]
+    e2 = tri[:, 2] - tri[:, 0]
+    area = 0.5 * np.linalg.norm(np.cross(e1, e2), axis=1).sum()
+    assert abs(area - (hi[0] - lo[0]) * (hi[1] - lo[1])) < 1e-9
+    assert np.all(np.diff(keys) > 0)
+
+
+def test_sphere_is_closed_and_near():
+    # closed-form sphere SDF over a band around it: the mesh is watertight
+    # (every edge in exactly two triangles) and its vertices lie within the
+    # linear-interpolation error of the sphere along a cell's longest edge
+    R, r = 24, 0.55
+    dims, lo, hi = (R, R, R), (-1.0, -1.0, -1.0), (1.0, 1.0, 1.0)
+    h = 2.0 / R
+    g = lo[0] + np.arange(R + 1) * h
+    X, Y, Z = np.meshgrid(g, g, g, indexing="ij")
+    D = (np.sqrt(X * X + Y * Y + Z * Z) - r).reshape(-1)
+    vf = (np.abs(D) < 3 * h).astype(np.uint8)
+    keys, tri = oracle.extract_surface(dims, lo, hi, D, vf)
+    v = tri.reshape(-1, 3)
+    err = np.abs(np.linalg.norm(v, axis=1) - r)
+    # chord error of |x| along an edge of length L at distance >= r - L: L^2 / (8 (r - L))
+    L = np.sqrt(3) * h
+    assert err.max() <= L * L / (8 * (r - L)) + 1e-12
+    # watertight: canonical edges (vertex coordinates are computed identically
+    # in every tetrahedron sharing a grid edge)
+    edges = {}
+    for t in tri:
+        pts = [tuple(p) for p in t]
+        for a, b in ((0, 1), (1, 2), (2, 0)):
+            e = (min(pts[a], pts[b]), max(pts[a], pts[b]))
+            edges[e] = edges.get(e, 0) + 1
+    counts = np.array(list(edges.values()))
+    assert np.all(counts == 2), np.bincount(counts)
