@@ -329,6 +329,31 @@ gp_status gp_export_layout(gp_ctx ctx, int64_t* vertex_id_of_slot, uint8_t* slot
 gp_status gp_export_active_cells(gp_ctx ctx, int32_t shape, int64_t* cell_ids, int64_t capacity,
                                  int64_t* n_out);
 
+/*
+ * Mesh of the zero level set of `field` over the cells of one shape whose
+ * eight corners are optimised vertices (the surface extracted after the
+ * optimisation, Sec. 3/4).  Marching tetrahedra: each such cell is cut into
+ * six tetrahedra along its main diagonal, (0, A, B, 7) for the corner paths
+ * 0 -> A -> B -> 7 (corner (a, b, c) at index 4a + 2b + c), which neighbouring
+ * cells cut alike, so the mesh has no cracks.  A corner is inside where
+ * f < 0; a tetrahedron with one corner on one side gives one triangle, two
+ * and two give two; each triangle corner is p + f_p / (f_p - f_q) (q - p) on
+ * an edge from its inside end p to its outside end q, in double (vertex
+ * positions lo + i * (hi - lo) / R), rounded to float at the end.
+ * field:   device float [n_slots] (the slot layout of gp_build_band).
+ * tri_xyz: device float [capacity][3][3], the corners' x, y, z.
+ * tri_key: device int64 [capacity], cell_id * 16 + tetrahedron * 2 +
+ *          triangle (cell_id x-major), ascending; the triangles follow it.
+ * n_out:   host; the number of triangles.  With capacity 0 (outputs may be
+ *          NULL) only the count is returned.
+ * Synchronises; allocates temporary device memory (about 40 bytes per
+ * triangle plus 8 per slot of the shape).
+ * Errors: GP_ERR_STATE before gp_build_band, GP_ERR_ARG, GP_ERR_CAPACITY
+ * (capacity below the count; n_out is set), GP_ERR_OOM.
+ */
+gp_status gp_extract_surface(gp_ctx ctx, int32_t shape, const float* field, float* tri_xyz, int64_t* tri_key,
+                             int64_t capacity, int64_t* n_out);
+
 /* field[slot] = dense[dense_off(s) + vertex id] for every slot (0 where the
  * slot has no vertex), where dense is the concatenation, in shape order, of
  * each shape's (R+1)^3 vertex values in x-major order.  Device arrays. */

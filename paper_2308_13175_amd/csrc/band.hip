@@ -290,6 +290,7 @@ gp_status gp_build_band_impl(gp_ctx ctx, const gp_shape* shapes, int32_t n_shape
             d.inv_h[a] = (double)in.dims[a] / (in.hi[a] - in.lo[a]);
             d.inv_hf[a] = (float)d.inv_h[a];
             d.h[a] = (float)((in.hi[a] - in.lo[a]) / (double)in.dims[a]);
+            d.hd[a] = (in.hi[a] - in.lo[a]) / (double)in.dims[a];
             d.R[a] = in.dims[a];
             d.nb[a] = (in.dims[a] + 1 + kBrick - 1) / kBrick;
         }

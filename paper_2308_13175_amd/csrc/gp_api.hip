@@ -1,5 +1,6 @@
 // The C ABI: argument validation, status codes, stream handling.  The
-// numerical work lives in band.hip, nn.hip, sample.hip, pull.hip and step.hip.
+// numerical work lives in band.hip, nn.hip, sample.hip, pull.hip, step.hip and
+// surface.hip.
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -375,6 +376,17 @@ gp_status gp_export_active_cells(gp_ctx ctx, int32_t shape, int64_t* cell_ids, i
     if (!n_out || shape < 0 || shape >= ctx->n_shapes || capacity < 0 || (capacity > 0 && !cell_ids))
         return gp_fail(ctx, GP_ERR_ARG, "need a shape index in range, n_out, and cell_ids when capacity > 0");
     return gp_active_cells_impl(ctx, shape, cell_ids, capacity, n_out);
+}
+
+gp_status gp_extract_surface(gp_ctx ctx, int32_t shape, const float* field, float* tri_xyz, int64_t* tri_key,
+                             int64_t capacity, int64_t* n_out)
+{
+    gp_status st = ready(ctx);
+    if (st != GP_OK) return st;
+    if (!n_out || !field || shape < 0 || shape >= ctx->n_shapes || capacity < 0 ||
+        (capacity > 0 && (!tri_xyz || !tri_key)))
+        return gp_fail(ctx, GP_ERR_ARG, "need a shape index in range, field, n_out, and outputs when capacity > 0");
+    return gp_extract_surface_impl(ctx, shape, field, tri_xyz, tri_key, capacity, n_out);
 }
 
 gp_status gp_gather_vertices(gp_ctx ctx, const float* dense, float* field)

@@ -31,6 +31,7 @@ struct ShapeDesc {
     double inv_h[3];       // R_a / (hi_a - lo_a)
     float inv_hf[3];       // the same in float (gradient factors)
     float h[3];
+    double hd[3];          // (hi_a - lo_a) / R_a in double (vertex positions)
     int32_t R[3];          // cells per axis
     int32_t nb[3];         // bricks per axis = ceil((R+1)/8)
     int64_t dir_off;       // first directory entry of this shape
@@ -396,5 +397,7 @@ gp_status gp_step_impl(gp_ctx ctx, float* field, float* grad, float* m, float* v
                        float eps);
 gp_status gp_layout_impl(gp_ctx ctx, int64_t* vid, uint8_t* flags);
 gp_status gp_active_cells_impl(gp_ctx ctx, int32_t shape, int64_t* cell_ids, int64_t capacity, int64_t* n_out);
+gp_status gp_extract_surface_impl(gp_ctx ctx, int32_t shape, const float* field, float* tri_xyz, int64_t* tri_key,
+                                  int64_t capacity, int64_t* n_out);
 gp_status gp_gather_impl(gp_ctx ctx, const float* dense, float* field, bool to_field);
 gp_status gp_init_sphere_impl(gp_ctx ctx, const double* centre, const double* radius, float* field);

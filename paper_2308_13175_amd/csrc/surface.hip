@@ -1,0 +1,226 @@
+// The mesh of the field's zero level set over the optimised cells (the
+// surface the paper extracts once the optimisation ends, Sec. 3/4).
+//
+// Marching tetrahedra rather than the marching-cubes case table: each cell
+// whose eight corners are optimised vertices is cut into six tetrahedra along
+// its main diagonal, (0, A, B, 7) for the paths 0 -> A -> B -> 7 through the
+// corners (corner (a, b, c) at index 4a + 2b + c).  Neighbouring cells cut a
+// shared face along the same diagonal, so the mesh has no cracks and needs no
+// ambiguity rules.  A corner is inside where f < 0.  A tetrahedron with one
+// corner on one side gives one triangle, two and two give two; a triangle
+// corner is the zero of the linear interpolant on an edge, taken from the
+// edge's inside end p towards its outside end q: p + f_p / (f_p - f_q) (q - p),
+// in double with no fused multiply-add, so a grid edge gives the same point in
+// every tetrahedron and every cell that has it.
+//
+// One thread per (brick, cell whose lowest corner is in the brick): a count
+// pass, a scan, an emit pass, then a sort by key = cell id * 16 + tet * 2 +
+// triangle (cell id x-major), so the output order does not depend on the
+// brick layout.
+#include <hipcub/hipcub.hpp>
+
+#include "gp_internal.h"
+
+namespace gp {
+namespace {
+
+constexpr int kThreads = 256;
+
+inline unsigned blocks_for(int64_t n)
+{
+    int64_t b = (n + kThreads - 1) / kThreads;
+    return (unsigned)std::max<int64_t>(1, std::min<int64_t>(b, (int64_t)1 << 30));
+}
+
+__constant__ int kTet[6][4] = {{0, 4, 6, 7}, {0, 4, 5, 7}, {0, 2, 6, 7}, {0, 2, 3, 7}, {0, 1, 5, 7}, {0, 1, 3, 7}};
+
+// Corners of the cell with lowest corner at local cell l of brick `brick`:
+// global cell c, and whether all eight corners are optimised (then slot[] and
+// the values f[] are filled).
+__device__ inline bool optimised_cell(const Band& B, const ShapeDesc& s, int32_t brick, int32_t l, int32_t c[3],
+                                      const float* __restrict__ field, float f[8])
+{
+    const BrickInfo bi = B.bricks[brick];
+    c[0] = bi.bx * kBrick + (l >> 6);
+    c[1] = bi.by * kBrick + ((l >> 3) & 7);
+    c[2] = bi.bz * kBrick + (l & 7);
+    if (c[0] >= s.R[0] || c[1] >= s.R[1] || c[2] >= s.R[2]) return false;
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int d = 0; d < 2; ++d) {
+                const int32_t i = c[0] + a, j = c[1] + b, k = c[2] + d;
+                const int32_t br = brick_of(B, s, i >> 3, j >> 3, k >> 3);
+                if (br < 0) return false;
+                const int32_t loc = local_index(i, j, k);
+                if (!mask_bit(B.m_v, br, loc)) return false;
+                f[4 * a + 2 * b + d] = field[(int64_t)br * kBrickVol + loc];
+            }
+    return true;
+}
+
+__device__ inline int tet_count(const float f[8], int t)
+{
+    int ni = 0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) ni += f[kTet[t][i]] < 0.f;
+    return ni == 0 || ni == 4 ? 0 : (ni == 2 ? 2 : 1);
+}
+
+__global__ void k_surf_count(Band B, int32_t shape, const float* __restrict__ field, int32_t* __restrict__ count)
+{
+    const ShapeDesc& s = B.shapes[shape];
+    const int64_t n = (s.brick_end - s.brick_begin) * kBrickVol;
+    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < n; g += (int64_t)gridDim.x * blockDim.x) {
+        int32_t c[3];
+        float f[8];
+        int32_t m = 0;
+        if (optimised_cell(B, s, (int32_t)(s.brick_begin + g / kBrickVol), (int32_t)(g % kBrickVol), c, field, f))
+            for (int t = 0; t < 6; ++t) m += tet_count(f, t);
+        count[g] = m;
+    }
+}
+
+__device__ inline void edge_point(const double P[8][3], const double fd[8], int a, int b, float* out)
+{
+#pragma clang fp contract(off)
+    const double t = fd[a] / (fd[a] - fd[b]);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const double d = P[b][k] - P[a][k];
+        const double v = P[a][k] + t * d;
+        out[k] = (float)v;
+    }
+}
+
+__global__ void k_surf_emit(Band B, int32_t shape, const float* __restrict__ field, const int32_t* __restrict__ offset,
+                            float* __restrict__ xyz, int64_t* __restrict__ key, int32_t* __restrict__ idx)
+{
+#pragma clang fp contract(off)
+    const ShapeDesc& s = B.shapes[shape];
+    const int64_t n = (s.brick_end - s.brick_begin) * kBrickVol;
+    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < n; g += (int64_t)gridDim.x * blockDim.x) {
+        if (offset[g + 1] == offset[g]) continue;
+        int32_t c[3];
+        float f[8];
+        if (!optimised_cell(B, s, (int32_t)(s.brick_begin + g / kBrickVol), (int32_t)(g % kBrickVol), c, field, f))
+            continue;
+        double P[8][3], fd[8];
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int b = 0; b < 2; ++b)
+#pragma unroll
+                for (int d = 0; d < 2; ++d) {
+                    const int i = 4 * a + 2 * b + d;
+                    P[i][0] = s.lo[0] + (double)(c[0] + a) * s.hd[0];
+                    P[i][1] = s.lo[1] + (double)(c[1] + b) * s.hd[1];
+                    P[i][2] = s.lo[2] + (double)(c[2] + d) * s.hd[2];
+                    fd[i] = (double)f[i];
+                }
+        const int64_t cid = ((int64_t)c[0] * s.R[1] + c[1]) * s.R[2] + c[2];
+        int32_t o = offset[g];
+        for (int t = 0; t < 6; ++t) {
+            int in[4], out[4], ni = 0, no = 0;
+            for (int i = 0; i < 4; ++i) {
+                const int v = kTet[t][i];
+                if (f[v] < 0.f) in[ni++] = v;
+                else out[no++] = v;
+            }
+            if (ni == 0 || no == 0) continue;
+            float* tri = xyz + (int64_t)o * 9;
+            if (ni == 1 || no == 1) {
+                for (int k = 0; k < 3; ++k) {
+                    if (ni == 1) edge_point(P, fd, in[0], out[k], tri + 3 * k);
+                    else edge_point(P, fd, in[k], out[0], tri + 3 * k);
+                }
+                key[o] = cid * 16 + t * 2;
+                idx[o] = o;
+                ++o;
+            } else {
+                float ac[3], ad[3], bd[3], bc[3];
+                edge_point(P, fd, in[0], out[0], ac);
+                edge_point(P, fd, in[0], out[1], ad);
+                edge_point(P, fd, in[1], out[1], bd);
+                edge_point(P, fd, in[1], out[0], bc);
+                for (int k = 0; k < 3; ++k) {
+                    tri[k] = ac[k];
+                    tri[3 + k] = ad[k];
+                    tri[6 + k] = bd[k];
+                    tri[9 + k] = ac[k];
+                    tri[12 + k] = bd[k];
+                    tri[15 + k] = bc[k];
+                }
+                key[o] = cid * 16 + t * 2;
+                key[o + 1] = cid * 16 + t * 2 + 1;
+                idx[o] = o;
+                idx[o + 1] = o + 1;
+                o += 2;
+            }
+        }
+    }
+}
+
+__global__ void k_surf_gather(const float* __restrict__ xyz, const int32_t* __restrict__ order, int64_t n,
+                              float* __restrict__ out)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n * 9; i += (int64_t)gridDim.x * blockDim.x)
+        out[i] = xyz[(int64_t)order[i / 9] * 9 + i % 9];
+}
+
+}  // namespace
+}  // namespace gp
+
+using namespace gp;
+
+gp_status gp_extract_surface_impl(gp_ctx ctx, int32_t shape, const float* field, float* tri_xyz, int64_t* tri_key,
+                                  int64_t capacity, int64_t* n_out)
+{
+    *n_out = 0;
+    const ShapeDesc& d = ctx->h_shapes[shape];
+    const int64_t n = (d.brick_end - d.brick_begin) * kBrickVol;
+    if (n == 0) return GP_OK;
+    if (n >= ((int64_t)1 << 31)) return gp_fail(ctx, GP_ERR_CAPACITY, "too many cells for the surface pass");
+    hipStream_t st = ctx->stream;
+    const Band B = ctx->band();
+    DevBuf<int32_t> count, offset;
+    if (count.alloc(n + 1) != hipSuccess || offset.alloc(n + 1) != hipSuccess)
+        return gp_fail(ctx, GP_ERR_OOM, "out of device memory for the surface pass");
+    GP_HIP(ctx, hipMemsetAsync(count.p + n, 0, sizeof(int32_t), st));
+    k_surf_count<<<blocks_for(n), kThreads, 0, st>>>(B, shape, field, count.p);
+    GP_HIP(ctx, hipGetLastError());
+    size_t need = 0;
+    GP_HIP(ctx, hipcub::DeviceScan::ExclusiveSum(nullptr, need, count.p, offset.p, (int)(n + 1), st));
+    DevBuf<uint8_t> tmp;
+    if (tmp.alloc(std::max<size_t>(need, 1)) != hipSuccess)
+        return gp_fail(ctx, GP_ERR_OOM, "out of device memory for the surface pass");
+    GP_HIP(ctx, hipcub::DeviceScan::ExclusiveSum(tmp.p, need, count.p, offset.p, (int)(n + 1), st));
+    int32_t total = 0;
+    GP_HIP(ctx, hipMemcpyAsync(&total, offset.p + n, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    GP_HIP(ctx, hipStreamSynchronize(st));
+    *n_out = total;
+    if (total > capacity)
+        return gp_fail(ctx, GP_ERR_CAPACITY, "the outputs hold " + std::to_string(capacity) + " triangles, " +
+                                                 std::to_string(total) + " needed");
+    if (total == 0) return GP_OK;
+    DevBuf<float> xyz;
+    DevBuf<int64_t> key;
+    DevBuf<int32_t> idx, order;
+    if (xyz.alloc((size_t)total * 9) != hipSuccess || key.alloc(total) != hipSuccess ||
+        idx.alloc(total) != hipSuccess || order.alloc(total) != hipSuccess)
+        return gp_fail(ctx, GP_ERR_OOM, "out of device memory for the surface pass");
+    k_surf_emit<<<blocks_for(n), kThreads, 0, st>>>(B, shape, field, offset.p, xyz.p, key.p, idx.p);
+    GP_HIP(ctx, hipGetLastError());
+    size_t need2 = 0;
+    GP_HIP(ctx, hipcub::DeviceRadixSort::SortPairs(nullptr, need2, key.p, tri_key, idx.p, order.p, total, 0, 64, st));
+    DevBuf<uint8_t> tmp2;
+    if (tmp2.alloc(std::max<size_t>(need2, 1)) != hipSuccess)
+        return gp_fail(ctx, GP_ERR_OOM, "out of device memory for the surface pass");
+    GP_HIP(ctx, hipcub::DeviceRadixSort::SortPairs(tmp2.p, need2, key.p, tri_key, idx.p, order.p, total, 0, 64, st));
+    k_surf_gather<<<blocks_for((int64_t)total * 9), kThreads, 0, st>>>(xyz.p, order.p, total, tri_xyz);
+    GP_HIP(ctx, hipGetLastError());
+    GP_HIP(ctx, hipStreamSynchronize(st));
+    return GP_OK;
+}

@@ -24,7 +24,7 @@ STATUS = {0: "GP_OK", 1: "GP_ERR_ARG", 2: "GP_ERR_DOMAIN", 3: "GP_ERR_CAPACITY",
 
 EXPORTS = ("gp_create", "gp_destroy", "gp_last_error", "gp_set_stream", "gp_sync", "gp_build_band",
            "gp_nn_query", "gp_set_nn_params", "gp_get_nn_params", "gp_autotune_nn", "gp_set_tv_layout", "gp_sample_queries", "gp_pull_forward", "gp_pull_backward", "gp_pull_forward_backward", "gp_step",
-           "gp_shape_slots", "gp_export_layout", "gp_export_active_cells", "gp_gather_vertices", "gp_scatter_vertices",
+           "gp_shape_slots", "gp_export_layout", "gp_export_active_cells", "gp_extract_surface", "gp_gather_vertices", "gp_scatter_vertices",
            "gp_init_sphere", "gp_timing_enable", "gp_timing_report")
 
 
@@ -86,6 +86,7 @@ def load_library(path: str = LIB_PATH):
         "gp_shape_slots": (st, [P, P]),
         "gp_export_layout": (st, [P, P, P]),
         "gp_export_active_cells": (st, [P, i32, P, i64, ctypes.POINTER(i64)]),
+        "gp_extract_surface": (st, [P, i32, P, P, P, i64, ctypes.POINTER(i64)]),
         "gp_gather_vertices": (st, [P, P, P]),
         "gp_scatter_vertices": (st, [P, P, P]),
         "gp_init_sphere": (st, [P, P, P, P]),
@@ -283,6 +284,23 @@ def gp_export_active_cells(ctx, shape: int, device=None) -> torch.Tensor:
     if n.value > 0:
         _check(ctx, lib.gp_export_active_cells(ctx, int(shape), _ptr(out, torch.int64), n.value, ctypes.byref(n)))
     return out[: n.value]
+
+
+def gp_extract_surface(ctx, shape: int, field, device=None):
+    """Zero-level-set triangles of one shape: (tri float32 [n, 3, 3], key int64 [n]), key ascending."""
+    _stream(ctx)
+    lib = load_library()
+    n = ctypes.c_int64(0)
+    st = lib.gp_extract_surface(ctx, int(shape), _ptr(field, torch.float32), None, None, 0, ctypes.byref(n))
+    if st not in (GP_OK, GP_ERR_CAPACITY):
+        _check(ctx, st)
+    dev = device or field.device
+    tri = torch.empty((max(n.value, 1), 3, 3), dtype=torch.float32, device=dev)
+    key = torch.empty(max(n.value, 1), dtype=torch.int64, device=dev)
+    if n.value > 0:
+        _check(ctx, lib.gp_extract_surface(ctx, int(shape), _ptr(field, torch.float32), _ptr(tri, torch.float32),
+                                           _ptr(key, torch.int64), n.value, ctypes.byref(n)))
+    return tri[: n.value], key[: n.value]
 
 
 def gp_gather_vertices(ctx, dense, field) -> None:
