@@ -374,6 +374,64 @@ def schedule_sweep(kind: str, iters: int = 1600, n_points: int = 200_000, n_quer
         torch.cuda.empty_cache()
 
 
+def surface_runs(iters: int = 1600, n_queries: int = 50_000):
+    """Whole runs on the paper's schedule, then the mesh and its quality.
+
+    Each setting optimises from the small-sphere initial field (M1 = 3,
+    M2 = 14, 50 000 queries per iteration, sigma = 2 cells, 1600 iterations
+    with lr 1 cell x 0.3 every 400), extracts the zero level set with
+    gp_extract_surface and measures it against the closed-form surface the
+    points were drawn from: CD-L1, normal consistency and F-score at
+    tau = 0.005 (the shapes span about 1.3 units).  One JSON line each.
+    """
+    import numpy as np
+    import torch
+
+    from paper_2308_13175_amd import gridpull as gp
+    from paper_2308_13175_amd import metrics, synth
+    from paper_2308_13175_amd.problem import AdamConfig, GraphedIteration, Problem, ShapeSpec
+
+    torus = synth.torus_points(200_000, seed=1)
+    torus_ref = synth.torus_points(100_000, jitter=0.0, seed=17)
+    sphere = synth.sphere_points(10_000, 0.5, seed=0)
+    sphere_ref = synth.sphere_points(100_000, 0.5, seed=18)
+    settings = [("torus-200k", torus, torus_ref, metrics.torus_sdf(0.5, 0.15), 128),
+                ("torus-200k", torus, torus_ref, metrics.torus_sdf(0.5, 0.15), 256),
+                ("sphere-10k", sphere, sphere_ref, metrics.sphere_sdf(0.5), 64)]
+    for name, pts, ref, (sdf, grad), res in settings:
+        dom = synth.cube_domain(res)
+        h = dom.h[0]
+        prob = Problem([ShapeSpec(pts, dom.dims, dom.lo, dom.hi, n_queries, 2.0 * h)], m1=3, m2=14,
+                       adam=AdamConfig(lr0=h, eps=1e-8))
+        prob.iteration(1)
+        prob.autotune(reps=2)
+        graph = GraphedIteration(prob)
+        prob.init_sphere()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        prob.iteration(1)
+        for _ in range(iters - 1):
+            graph.replay()
+        torch.cuda.synchronize()
+        run_s = time.perf_counter() - t0
+        prob.sync()
+        gp.gp_extract_surface(prob.ctx, 0, prob.field)      # warm
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        tri, key = gp.gp_extract_surface(prob.ctx, 0, prob.field)
+        torch.cuda.synchronize()
+        extract_ms = (time.perf_counter() - t0) * 1e3
+        tri = tri.cpu().numpy()
+        m = metrics.reconstruction_metrics(tri, ref, sdf, grad, tau=0.005)
+        print(json.dumps({"surface": name, "res": res, "m1": 3, "m2": 14, "iterations": iters,
+                          "queries_per_iteration": n_queries, "run_s": run_s, "triangles": int(len(tri)),
+                          "extract_ms": extract_ms, **m}), flush=True)
+        del graph
+        prob.close()
+        del prob
+        torch.cuda.empty_cache()
+
+
 def cpu_baseline(wl, budget_s: float = 16.0):
     """The FP64 oracle on one host thread, on a bounded sample of the workload."""
     import numpy as np
@@ -459,6 +517,9 @@ def main():
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--sweep", choices=["res", "m2", "m1"],
                     help="instead of the benchmark: whole runs on the paper's schedule, one JSON line per setting")
+    ap.add_argument("--surface", action="store_true",
+                    help="instead of the benchmark: whole runs, then the extracted mesh against the closed-form "
+                         "surface (CD, NC, F-score), one JSON line per shape and grid")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default NN search shape instead of timing the candidates first")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -477,6 +538,9 @@ def main():
     torch.cuda.set_device(0)
     if args.sweep:
         schedule_sweep(args.sweep)
+        return
+    if args.surface:
+        surface_runs()
         return
     wl, prob, setup_ms = build_problem(args.config)
     Q, J = prob.n_queries, prob.n_points

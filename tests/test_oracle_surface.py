@@ -94,3 +94,30 @@ def test_sphere_is_closed_and_near():
             edges[e] = edges.get(e, 0) + 1
     counts = np.array(list(edges.values()))
     assert np.all(counts == 2), np.bincount(counts)
+
+
+def test_metrics_on_the_exact_sphere_mesh():
+    """The measures of the extracted mesh of the exact sphere SDF: near zero
+    distance, normals consistent, F-score 1 at a threshold above the
+    interpolation error; a shifted sphere is measured as far."""
+    from paper_2308_13175_amd import metrics
+
+    R, r = 32, 0.5
+    h = 2.0 / R
+    g = -1.0 + np.arange(R + 1) * h
+    X, Y, Z = np.meshgrid(g, g, g, indexing="ij")
+    D = (np.sqrt(X * X + Y * Y + Z * Z) - r).reshape(-1)
+    vf = (np.abs(D) < 3 * h).astype(np.uint8)
+    _, tri = oracle.extract_surface((R, R, R), (-1.0,) * 3, (1.0,) * 3, D, vf)
+    rng = np.random.default_rng(3)
+    s = rng.normal(size=(20_000, 3))
+    surf = r * s / np.linalg.norm(s, axis=1, keepdims=True)
+    sdf, grad = metrics.sphere_sdf(r)
+    m = metrics.reconstruction_metrics(tri, surf, sdf, grad, tau=0.01, n_samples=50_000)
+    assert m["accuracy"] < 2e-3 and m["completeness"] < 5e-3
+    assert m["nc"] > 0.995
+    assert m["fscore"] > 0.99
+    sdf2, grad2 = metrics.sphere_sdf(r, centre=(0.05, 0.0, 0.0))
+    m2 = metrics.reconstruction_metrics(tri, surf + np.array([0.05, 0.0, 0.0]), sdf2, grad2, tau=0.01,
+                                        n_samples=50_000)
+    assert m2["cd_l1"] > 5 * m["cd_l1"] and m2["fscore"] < 0.5
