@@ -382,7 +382,9 @@ def surface_runs(iters: int = 1600, n_queries: int = 50_000):
     with lr 1 cell x 0.3 every 400), extracts the zero level set with
     gp_extract_surface and measures it against the closed-form surface the
     points were drawn from: CD-L1, normal consistency and F-score at
-    tau = 0.005 (the shapes span about 1.3 units).  One JSON line each.
+    tau = 0.005 (the shapes span about 1.3 units).  The same measures of the
+    mesh of the closed-form SDF sampled on the same band are reported beside
+    them.  One JSON line each.
     """
     import numpy as np
     import torch
@@ -415,6 +417,16 @@ def surface_runs(iters: int = 1600, n_queries: int = 50_000):
         torch.cuda.synchronize()
         run_s = time.perf_counter() - t0
         prob.sync()
+        # the mesh of the closed-form field on the same band: what extraction
+        # and measurement alone give (the field's own interpolation error)
+        g = np.asarray(dom.lo)[:, None] + np.arange(res + 1)[None, :] * h
+        X, Y, Z = np.meshgrid(g[0], g[1], g[2], indexing="ij")
+        dense = sdf(np.stack([X.ravel(), Y.ravel(), Z.ravel()], 1)).astype(np.float32)
+        keep = prob.field.clone()
+        prob.set_dense_field([dense])
+        etri, _ = gp.gp_extract_surface(prob.ctx, 0, prob.field)
+        m_exact = metrics.reconstruction_metrics(etri.cpu().numpy(), ref, sdf, grad, tau=0.005)
+        prob.field.copy_(keep)
         gp.gp_extract_surface(prob.ctx, 0, prob.field)      # warm
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -425,7 +437,10 @@ def surface_runs(iters: int = 1600, n_queries: int = 50_000):
         m = metrics.reconstruction_metrics(tri, ref, sdf, grad, tau=0.005)
         print(json.dumps({"surface": name, "res": res, "m1": 3, "m2": 14, "iterations": iters,
                           "queries_per_iteration": n_queries, "run_s": run_s, "triangles": int(len(tri)),
-                          "extract_ms": extract_ms, **m}), flush=True)
+                          "extract_ms": extract_ms, **m,
+                          "closed_form_field": {"triangles": int(len(etri)),
+                                                **{k: m_exact[k] for k in ("cd_l1", "nc", "fscore")}}}),
+              flush=True)
         del graph
         prob.close()
         del prob
