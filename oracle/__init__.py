@@ -61,6 +61,8 @@ def _load():
     lib.og_query_offsets.argtypes = [u64, u32, u32, i64, i64, P]
     lib.og_extract_surface.restype = i64
     lib.og_extract_surface.argtypes = [P, P, P, P, P, i64, P, P]
+    lib.og_normal_term.restype = i64
+    lib.og_normal_term.argtypes = [P, P, P, P, P, P, P, P, P, i64, P, P, P, P, P, P, f64, f64, P, P]
     _lib = lib
     return lib
 
@@ -244,3 +246,26 @@ def extract_surface(dims, lo, hi, D: np.ndarray, vert_flags: np.ndarray):
     xyz = np.zeros((max(n, 1), 3, 3), dtype=np.float64)
     lib.og_extract_surface(_p(R), _p(L), _p(H), _p(Dd), _p(vf), n, _p(keys), _p(xyz))
     return keys[:n], xyz[:n]
+
+
+def normal_term(dims, lo, hi, cell_flags, D, queries, nn, points, normals, weight: float = 1.0,
+                eps_n: float = 1e-12, with_grad: bool = True):
+    """Normal supervision (Sec. 4, normals paragraph; the C file states the
+    reading): L_N = mean over valid queries of 1 - gh_s . n_s at s = NN(q).
+    Returns (L_N, weight * dL_N/dD as a dense vertex array or None, Q_v)."""
+    lib = _load()
+    R, L, H = _grid(dims, lo, hi)
+    qx, qy, qz = _soa(queries)
+    px, py, pz = _soa(points)
+    nx, ny, nz = _soa(normals)
+    nn = np.ascontiguousarray(nn, dtype=np.int32)
+    Dd = np.ascontiguousarray(D, dtype=np.float64)
+    cf = np.ascontiguousarray(cell_flags, dtype=np.uint8)
+    grad = np.zeros(int(np.prod(R.astype(np.int64) + 1)), dtype=np.float64) if with_grad else None
+    term = np.zeros(1, dtype=np.float64)
+    nv = lib.og_normal_term(_p(R), _p(L), _p(H), _p(cf), _p(Dd), _p(qx), _p(qy), _p(qz), _p(nn), len(qx),
+                            _p(px), _p(py), _p(pz), _p(nx), _p(ny), _p(nz), float(weight), float(eps_n),
+                            _p(term), _p(grad) if grad is not None else None)
+    if nv < 0:
+        raise DomainError("a nearest point lies outside the grid")
+    return float(term[0]), grad, int(nv)

@@ -619,3 +619,64 @@ int64_t og_extract_surface(const int32_t* R_in, const double* lo, const double* 
     }
     return n;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Normal supervision (Sec. 4, normals paragraph: with ground-truth normals, */
+/* the gradient of the field at the surface points is supervised by them).  */
+/* Reading taken here: the same cosine form as the gradient-consistency term */
+/* with the given normal in place of the query's gradient,                  */
+/*   L_N = (1/Q_v) sum over valid queries of (1 - gh_s . n_s),               */
+/* s = NN(q), gh_s = grad f(s) / |grad f(s)| (below eps_n the term is 1 with */
+/* zero gradient), Q_v and validity as in og_loss_grad.  Writes L_N to       */
+/* term_out and adds weight * d L_N / d D to grad_out (nullable; not zeroed).*/
+/* Returns Q_v, or -1 if a nearest point lies outside the grid.              */
+/* ------------------------------------------------------------------------ */
+int64_t og_normal_term(const int32_t* R, const double* lo, const double* hi, const uint8_t* cell_flags,
+                       const double* D, const float* qx, const float* qy, const float* qz, const int32_t* nn,
+                       int64_t n_queries, const float* px, const float* py, const float* pz,
+                       const float* nx, const float* ny, const float* nz, double weight, double eps_n,
+                       double* term_out, double* grad_out)
+{
+    grid_t g;
+    grid_init(&g, R, lo, hi);
+    int64_t n_valid = 0;
+    for (int64_t k = 0; k < n_queries; ++k) {
+        double q[3] = {qx[k], qy[k], qz[k]};
+        int64_t c[3];
+        double t[3];
+        if (locate(&g, q, c, t) && (cell_flags[cell_id(&g, c)] & 2)) ++n_valid;
+    }
+    double inv_q = n_valid > 0 ? 1.0 / (double)n_valid : 0.0;
+    double sum = 0.0;
+    for (int64_t k = 0; k < n_queries; ++k) {
+        double q[3] = {qx[k], qy[k], qz[k]};
+        int64_t c[3];
+        double t[3];
+        if (!locate(&g, q, c, t) || !(cell_flags[cell_id(&g, c)] & 2)) continue;
+        int64_t j = nn[k];
+        double s[3] = {px[j], py[j], pz[j]};
+        int64_t cs[3];
+        double ts[3];
+        if (!locate(&g, s, cs, ts)) return -1;
+        interp_t is;
+        interpolate(&g, D, cs, ts, &is);
+        double nj[3] = {nx[j], ny[j], nz[j]};
+        if (is.n < eps_n) {
+            sum += 1.0;
+            continue;
+        }
+        double ghs[3], cosv = 0.0;
+        for (int a = 0; a < 3; ++a) {
+            ghs[a] = is.g[a] / is.n;
+            cosv += ghs[a] * nj[a];
+        }
+        sum += 1.0 - cosv;
+        if (!grad_out) continue;
+        /* d (1 - gh . n) / d grad f = -(n - (gh . n) gh) / |grad f| */
+        double dl_dg[3];
+        for (int a = 0; a < 3; ++a) dl_dg[a] = -(nj[a] - cosv * ghs[a]) / is.n;
+        scatter(grad_out, &is, weight * inv_q, 0.0, dl_dg);
+    }
+    *term_out = sum * inv_q;
+    return n_valid;
+}

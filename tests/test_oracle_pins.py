@@ -555,3 +555,55 @@ def test_adam_matches_torch_optimizer():
         sched.step()
         oracle.adam(D, G, m, v, vf, t=t, lr0=0.5, decay=0.3, decay_every=3)
         assert np.max(np.abs(D - p.detach().numpy())) < 1e-12
+
+
+# ---------------------------------------------------------------------------
+# Normal supervision (reading A28): closed forms and central differences
+# ---------------------------------------------------------------------------
+
+def test_normal_term_on_a_linear_field():
+    """A linear field has the exact gradient everywhere: with its own unit
+    direction as every point's normal the term is 0 and so is its gradient;
+    with the opposite normal it is 2, with a perpendicular one 1."""
+    dims, lo, hi, dom = _dom(10)
+    n0 = np.array([0.36, -0.48, 0.8])
+    V = np.array(dims) + 1
+    g = [lo[a] + np.arange(V[a]) * (hi[a] - lo[a]) / dims[a] for a in range(3)]
+    X, Y, Z = np.meshgrid(*g, indexing="ij")
+    D = (n0[0] * X + n0[1] * Y + n0[2] * Z + 0.05).reshape(-1)
+    pts = synth.sphere_points(80, 0.4, seed=4)
+    q = synth.host_queries(pts, 300, 0.05, seed=5)
+    cf, vf = oracle.build_band(dims, lo, hi, pts, 2, 2)
+    nn = oracle.nn_bruteforce(q, pts)
+    perp = np.array([0.8, 0.6, 0.0])
+    for normal, expect in [(n0, 0.0), (-n0, 2.0), (perp, 1.0)]:
+        nrm = np.tile(normal.astype(np.float32), (len(pts), 1))
+        term, grad, nv = oracle.normal_term(dims, lo, hi, cf, D, q, nn, pts, nrm)
+        assert nv > 0
+        assert abs(term - expect) < 1e-6, (normal, term)
+        if expect == 0.0:
+            assert np.abs(grad).max() < 1e-6
+
+
+def test_normal_term_gradient_matches_central_differences():
+    dims, lo, hi, dom, pts, q, cf, vf, D, nn = _fd_problem(seed=33)
+    rng = np.random.default_rng(2)
+    nrm = rng.normal(size=(len(pts), 3))
+    nrm /= np.linalg.norm(nrm, axis=1, keepdims=True)
+    w = 0.7
+    term, G, nv = oracle.normal_term(dims, lo, hi, cf, D, q, nn, pts, nrm, weight=w)
+    assert nv > 0 and 0.0 < term < 2.0
+    active = np.nonzero(vf & 1)[0]
+    pick = np.concatenate([active[np.argsort(-np.abs(G[active]))[:30]], rng.choice(active, 30)])
+    hstep = 1e-6
+    gmax = np.abs(G).max()
+    assert gmax > 0
+    for v in pick:
+        Dp = D.copy()
+        Dp[v] += hstep
+        Dm = D.copy()
+        Dm[v] -= hstep
+        tp = oracle.normal_term(dims, lo, hi, cf, Dp, q, nn, pts, nrm, with_grad=False)[0]
+        tm = oracle.normal_term(dims, lo, hi, cf, Dm, q, nn, pts, nrm, with_grad=False)[0]
+        fd = w * (tp - tm) / (2 * hstep)
+        assert abs(fd - G[v]) <= 1e-6 * gmax + 1e-9, (v, fd, G[v])
