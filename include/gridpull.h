@@ -279,6 +279,29 @@ gp_status gp_pull_forward_backward(gp_ctx ctx, const float* qx, const float* qy,
                                    int64_t* n_valid_out, float* grad);
 
 /*
+ * Normal supervision (Sec. 4, normals paragraph: with ground-truth normals,
+ * the gradient of the field at the surface points is supervised by them).
+ * Reading: L_N = (1/Q_v) sum over valid queries of (1 - gh_s . n_s), with
+ * s = NN(q), gh_s = grad f(s) / |grad f(s)| (below 1e-12 the term is 1 with
+ * zero gradient), Q_v and validity as for gp_pull_forward.  A separate term:
+ * the caller adds weight * L_N to the objective of gp_pull_forward.
+ * qx,qy,qz,nn,field: as gp_pull_backward.
+ * nx,ny,nz: device float unit normals, indexed like the points of
+ *          gp_build_band (global index point_off + j).
+ * weight:  the term's weight; dloss: device [n_shapes] upstream scale or NULL
+ *          (1).
+ * term_out: device double [n_shapes], L_N of each shape (unweighted).
+ * grad:    device float [n_slots] or NULL; receives += weight * dloss *
+ *          dL_N/dD (float atomics: the order of the additions varies).
+ * The first call on a context allocates its scratch.
+ * Errors: GP_ERR_STATE, GP_ERR_ARG.
+ */
+gp_status gp_pull_normals(gp_ctx ctx, const float* qx, const float* qy, const float* qz,
+                          const int32_t* nn, int64_t n_queries, const float* field,
+                          const float* nx, const float* ny, const float* nz, float weight,
+                          const double* dloss, double* term_out, float* grad);
+
+/*
  * One Adam step (Kingma and Ba, 2015) on the optimised vertices at iteration
  * t, learning rate lr0 * decay^floor((t-1)/decay_every) (Sec. 4: decay 0.3
  * every 400 iterations); then grad is set to 0 on every slot.  Slots that are

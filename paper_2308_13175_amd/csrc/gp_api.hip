@@ -1,6 +1,6 @@
 // The C ABI: argument validation, status codes, stream handling.  The
-// numerical work lives in band.hip, nn.hip, sample.hip, pull.hip, step.hip and
-// surface.hip.
+// numerical work lives in band.hip, nn.hip, sample.hip, pull.hip, step.hip,
+// normals.hip and surface.hip.
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -297,6 +297,19 @@ gp_status gp_pull_forward_backward(gp_ctx ctx, const float* qx, const float* qy,
     if ((n_queries > 0 && !nn) || !field || !dloss || !loss_out || !n_valid_out || !grad)
         return gp_fail(ctx, GP_ERR_ARG, "null argument");
     return gp_forward_backward_impl(ctx, qx, qy, qz, nn, field, w, dloss, loss_out, n_valid_out, grad);
+}
+
+gp_status gp_pull_normals(gp_ctx ctx, const float* qx, const float* qy, const float* qz, const int32_t* nn,
+                          int64_t n_queries, const float* field, const float* nx, const float* ny, const float* nz,
+                          float weight, const double* dloss, double* term_out, float* grad)
+{
+    gp_status st = ready(ctx);
+    if (st != GP_OK) return st;
+    if ((st = check_queries(ctx, qx, qy, qz, n_queries)) != GP_OK) return st;
+    if ((n_queries > 0 && !nn) || !field || !term_out) return gp_fail(ctx, GP_ERR_ARG, "null argument");
+    if (ctx->n_points > 0 && (!nx || !ny || !nz)) return gp_fail(ctx, GP_ERR_ARG, "null normal array");
+    if (!std::isfinite(weight)) return gp_fail(ctx, GP_ERR_ARG, "weight must be finite");
+    return gp_normals_impl(ctx, qx, qy, qz, nn, field, nx, ny, nz, weight, dloss, term_out, grad);
 }
 
 gp_status gp_step(gp_ctx ctx, float* field, float* grad, float* m, float* v, int32_t t, float lr0, float decay,

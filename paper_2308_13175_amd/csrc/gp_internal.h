@@ -315,6 +315,8 @@ struct gp_ctx_s {
     DevBuf<double> inv_qv;        // [n_shapes] 1 / valid count (0 if none)
     DevBuf<double> fin_part;      // [n_shapes][32][5] chunk sums of the loss reduction
     DevBuf<int32_t> fin_count;    // [n_shapes] chunks finished (back to 0 after each reduction)
+    DevBuf<double> nrm_part;      // normal supervision: per-block (term, count), allocated on first use
+    DevBuf<float> nrm_scale;      // normal supervision: per-shape gradient scale
     DevBuf<int32_t> flag;         // device error flag
     DevBuf<int32_t> iter;         // device-resident iteration counter (last Adam t)
     DevBuf<float> step_c;         // [2] lr_t / (1 - beta1^t), 1 / sqrt(1 - beta2^t)
@@ -397,6 +399,9 @@ gp_status gp_step_impl(gp_ctx ctx, float* field, float* grad, float* m, float* v
                        float eps);
 gp_status gp_layout_impl(gp_ctx ctx, int64_t* vid, uint8_t* flags);
 gp_status gp_active_cells_impl(gp_ctx ctx, int32_t shape, int64_t* cell_ids, int64_t capacity, int64_t* n_out);
+gp_status gp_normals_impl(gp_ctx ctx, const float* qx, const float* qy, const float* qz, const int32_t* nn,
+                          const float* field, const float* nx, const float* ny, const float* nz, float weight,
+                          const double* dloss, double* term_out, float* grad);
 gp_status gp_extract_surface_impl(gp_ctx ctx, int32_t shape, const float* field, float* tri_xyz, int64_t* tri_key,
                                   int64_t capacity, int64_t* n_out);
 gp_status gp_gather_impl(gp_ctx ctx, const float* dense, float* field, bool to_field);

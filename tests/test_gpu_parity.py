@@ -454,3 +454,45 @@ def test_surface_extraction():
                                                   ctypes.byref(n))
         assert st == gp.GP_ERR_CAPACITY and n.value == len(rkey)
         prob.close()
+
+
+def test_normal_supervision():
+    """gp_pull_normals against the oracle's normal term: the mean per shape
+    and weight * its gradient, with the points' true normals on the noisy
+    sphere and with random unit normals on a random anisotropic field."""
+    import torch
+
+    from paper_2308_13175_amd import gridpull as gp
+
+    dom, pts, q, D = _sphere_case()
+    rng = np.random.default_rng(13)
+    adom = synth.Domain((24, 17, 31), (-1.125, -0.625, -0.875), (0.875, 0.8125, 1.0625))
+    apts = (synth.sphere_points(3000, 0.45, seed=3) + np.float32(0.05)).astype(np.float32)
+    aq = synth.host_queries(apts, 9000, 0.05, seed=7)
+    aD = (rng.normal(size=adom.n_vertices) * 0.2).astype(np.float32)
+    rn = rng.normal(size=(len(apts), 3))
+    cases = [("sphere, true normals", dom, pts, q, D, pts / np.linalg.norm(pts, axis=1, keepdims=True)),
+             ("anisotropic, random normals", adom, apts, aq, aD, rn / np.linalg.norm(rn, axis=1, keepdims=True))]
+    for name, dm, p_, q_, D_, nrm in cases:
+        log("case: normal supervision, %s" % name)
+        nrm = nrm.astype(np.float32)
+        prob = make_problem([spec(p_, dm, len(q_), 0.0)])
+        prob.set_dense_field([D_])
+        prob.set_queries(q_)
+        prob.nearest()
+        dev = prob.device
+        nx, ny, nz = (torch.from_numpy(np.ascontiguousarray(nrm[:, a])).to(dev) for a in range(3))
+        term = torch.zeros(1, dtype=torch.float64, device=dev)
+        prob.grad.zero_()
+        n = prob.n_queries
+        gp.gp_pull_normals(prob.ctx, prob.qx[:n], prob.qy[:n], prob.qz[:n], prob.nn, prob.field, nx, ny, nz,
+                           0.7, None, term, prob.grad)
+        prob.sync()
+        cf, vf = oracle.build_band(dm.dims, dm.lo, dm.hi, p_, 3, 3)
+        nn = oracle.nn_bruteforce(q_, p_)
+        rterm, rgrad, nv = oracle.normal_term(dm.dims, dm.lo, dm.hi, cf, D_.astype(np.float64), q_, nn, p_, nrm,
+                                              weight=0.7)
+        got = float(term.cpu().numpy()[0])
+        assert abs(got - rterm) <= 1e-5 * abs(rterm), (got, rterm)
+        assert_grad_close(prob.dense_grad()[0], rgrad)
+        prob.close()
