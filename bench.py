@@ -400,16 +400,23 @@ def surface_runs(iters: int = 1600, n_queries: int = 50_000):
     # noisy torus: N(0, 0.01^2) on every point, fitted with alpha = 1 and with
     # the paper's alpha = 2 for noisy inputs (Sec. 4, noise paragraph)
     noisy = synth.torus_points(200_000, jitter=0.01, seed=1)
-    settings = [("torus-200k", torus, torus_ref, metrics.torus_sdf(0.5, 0.15), 128, 1.0),
-                ("torus-200k", torus, torus_ref, metrics.torus_sdf(0.5, 0.15), 256, 1.0),
-                ("sphere-10k", sphere, sphere_ref, metrics.sphere_sdf(0.5), 64, 1.0),
-                ("torus-200k-noise0.01", noisy, torus_ref, metrics.torus_sdf(0.5, 0.15), 128, 1.0),
-                ("torus-200k-noise0.01", noisy, torus_ref, metrics.torus_sdf(0.5, 0.15), 128, 2.0)]
-    for name, pts, ref, (sdf, grad), res, alpha in settings:
+    # with ground-truth normals (the closed form's gradient at each point),
+    # supervised with weight 1 (Sec. 4, normals paragraph)
+    tsdf = metrics.torus_sdf(0.5, 0.15)
+    tnormals = tsdf[1](torus.astype(np.float64))
+    settings = [("torus-200k", torus, torus_ref, tsdf, 128, 1.0, None),
+                ("torus-200k", torus, torus_ref, tsdf, 256, 1.0, None),
+                ("sphere-10k", sphere, sphere_ref, metrics.sphere_sdf(0.5), 64, 1.0, None),
+                ("torus-200k-noise0.01", noisy, torus_ref, tsdf, 128, 1.0, None),
+                ("torus-200k-noise0.01", noisy, torus_ref, tsdf, 128, 2.0, None),
+                ("torus-200k-normals", torus, torus_ref, tsdf, 128, 1.0, tnormals)]
+    for name, pts, ref, (sdf, grad), res, alpha, normals in settings:
         dom = synth.cube_domain(res)
         h = dom.h[0]
         prob = Problem([ShapeSpec(pts, dom.dims, dom.lo, dom.hi, n_queries, 2.0 * h)], m1=3, m2=14,
                        weights=(alpha, 1.0, 0.005), adam=AdamConfig(lr0=h, eps=1e-8))
+        if normals is not None:
+            prob.set_normals(normals, 1.0)
         prob.iteration(1)
         prob.autotune(reps=2)
         graph = GraphedIteration(prob)
@@ -440,7 +447,8 @@ def surface_runs(iters: int = 1600, n_queries: int = 50_000):
         extract_ms = (time.perf_counter() - t0) * 1e3
         tri = tri.cpu().numpy()
         m = metrics.reconstruction_metrics(tri, ref, sdf, grad, tau=0.005)
-        print(json.dumps({"surface": name, "res": res, "m1": 3, "m2": 14, "alpha": alpha, "iterations": iters,
+        print(json.dumps({"surface": name, "res": res, "m1": 3, "m2": 14, "alpha": alpha,
+                          "normal_weight": 1.0 if normals is not None else 0.0, "iterations": iters,
                           "queries_per_iteration": n_queries, "run_s": run_s, "triangles": int(len(tri)),
                           "extract_ms": extract_ms, **m,
                           "closed_form_field": {"triangles": int(len(etri)),

@@ -104,6 +104,8 @@ class Problem:
         self.loss = torch.zeros(self.n_shapes, 5, dtype=torch.float64, device=dev)
         self.n_valid = torch.zeros(self.n_shapes, dtype=torch.int64, device=dev)
         self.dloss = torch.ones(self.n_shapes, dtype=torch.float64, device=dev)
+        self.normals = None          # (nx, ny, nz, weight) once set_normals is called
+        self.normal_term = torch.zeros(self.n_shapes, dtype=torch.float64, device=dev)
 
     # -- lifetime ----------------------------------------------------------
     def close(self):
@@ -221,6 +223,14 @@ class Problem:
         gp.gp_step(self.ctx, self.field, self.grad, self.m, self.v, 0 if t is None else int(t),
                    a.lr0 if lr0 is None else lr0, a.decay, a.decay_every, a.beta1, a.beta2, a.eps)
 
+    def set_normals(self, normals: np.ndarray, weight: float):
+        """Ground-truth unit normals of the points (indexed like them): every
+        iteration then adds weight * the normal supervision term."""
+        n = np.asarray(normals, np.float32).reshape(-1, 3)
+        assert len(n) == self.n_points
+        self.normals = tuple(torch.from_numpy(np.ascontiguousarray(n[:, a])).to(self.device) for a in range(3)) + (
+            float(weight),)
+
     def iteration(self, t: Optional[int] = None, seed: int = 0):
         """One full optimisation iteration (sample, NN, forward, backward, Adam).
 
@@ -230,6 +240,11 @@ class Problem:
         self.sample(seed, -1 if t is None else int(t))
         self.nearest()
         self.forward_backward()
+        if self.normals is not None:
+            nx, ny, nz, w = self.normals
+            n = self.n_queries
+            gp.gp_pull_normals(self.ctx, self.qx[:n], self.qy[:n], self.qz[:n], self.nn, self.field, nx, ny, nz, w,
+                               self.dloss, self.normal_term, self.grad)
         self.step(t)
 
     def sync(self):
