@@ -43,6 +43,12 @@
  *     dx = (double)q_x - (double)s_x, no fused multiply-add, ties to the
  *     lowest point index.
  *
+ * Parity unpinned: nothing in the paper fixes whether these readings, the
+ * sampler, the marching-tetrahedra surface or the normal term are what the
+ * authors ran, nor the reconstruction quality of its tables (no datasets or
+ * trained fields here).  Each function is pinned against closed forms,
+ * invariants and brute force instead; the tests name the pins.
+ *
  * Linear ids are x-major: cell (cx*Ry + cy)*Rz + cz, vertex
  * (i*(Ry+1) + j)*(Rz+1) + k.
  *
