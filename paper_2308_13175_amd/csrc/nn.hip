@@ -174,15 +174,18 @@ __device__ inline int32_t search(const Band& B, const ShapeDesc& s, const Global
     return best.id;
 }
 
-// Wave-wide minimum of v[0..2] and maximum of v[3..5].
+// Wave-wide minimum of v[0..2] and maximum of v[3..5] (the same in every
+// lane afterwards, so kept in scalar registers).
 __device__ inline void wave_minmax6(int32_t v[6])
 {
 #pragma unroll
-    for (int i = 0; i < 6; ++i)
+    for (int i = 0; i < 6; ++i) {
         for (int o = 32; o > 0; o >>= 1) {
             int32_t w = __shfl_xor(v[i], o, 64);
             v[i] = i < 3 ? min(v[i], w) : max(v[i], w);
         }
+        v[i] = __builtin_amdgcn_readfirstlane(v[i]);
+    }
 }
 
 __device__ inline uint32_t spread3(uint32_t v)
@@ -287,7 +290,23 @@ __device__ inline void wave_best2(float& b1, float& b2, int32_t& id)
     b2 = second;
 }
 
+// Inclusive prefix maximum over the lanes of non-negative values: within
+// rows of 16 by DPP row shifts, then across rows from the rows' last lanes.
+__device__ inline int32_t wave_prefix_max(int32_t v)
+{
+    v = max(v, __builtin_amdgcn_update_dpp(0, v, 0x111, 0xf, 0xf, false));   // row_shr:1
+    v = max(v, __builtin_amdgcn_update_dpp(0, v, 0x112, 0xf, 0xf, false));   // row_shr:2
+    v = max(v, __builtin_amdgcn_update_dpp(0, v, 0x114, 0xf, 0xf, false));   // row_shr:4
+    v = max(v, __builtin_amdgcn_update_dpp(0, v, 0x118, 0xf, 0xf, false));   // row_shr:8
+    const int32_t r0 = __builtin_amdgcn_readlane(v, 15);
+    const int32_t r1 = max(r0, __builtin_amdgcn_readlane(v, 31));
+    const int32_t r2 = max(r1, __builtin_amdgcn_readlane(v, 47));
+    const int row = (threadIdx.x & 63) >> 4;
+    return max(v, row == 0 ? 0 : (row == 1 ? r0 : (row == 2 ? r1 : r2)));
+}
+
 constexpr int kRunCap = 128;   // runs staged per wave (a batch of 64 plus one append round)
+constexpr int kRunArea = kRunCap + 16;   // per wave: the runs, then 64 ints marking run starts in a chunk
 constexpr int kTail = 8;       // open queries served together by the point-parallel pass
 constexpr int kTailSpan = 24;  // larger balls (cells per axis) go to the ring search
 
@@ -351,23 +370,32 @@ __device__ inline int32_t flush_runs(const Band& B, const ShapeDesc& s, const Gl
     int32_t total;
     const int32_t off = wave_exclusive_sum(pe - pb, total);
     total = __builtin_amdgcn_readfirstlane(total);
-    // stream position p -> the last run whose offset is <= p
-    auto point_at = [&](int32_t p) -> float4 {
-        int32_t j = 0;
-        for (int step = 32; step > 0; step >>= 1) {
-            const int32_t c = j + step;
-            const int32_t o = __shfl(off, c < cnt ? c : cnt - 1, 64);
-            if (c < cnt && o <= p) j = c;
-        }
+    // Stream position c + lane -> the last non-empty run starting at or before
+    // it: every non-empty run starting inside the chunk marks its start (no
+    // two share one), a prefix maximum spreads the marks over the lanes, and
+    // the run covering the chunk's first position comes from the previous
+    // chunk's last lane.  Chunks are taken in order.
+    int32_t* starts = reinterpret_cast<int32_t*>(runs + kRunCap);
+    int32_t carry = 0;   // 1 + run covering the next chunk's first position
+    auto chunk_at = [&](int32_t c) -> float4 {
+        starts[lane] = 0;
+        wave_sync();
+        const int32_t h = off - c;
+        if (lane < cnt && pe > pb && h >= 0 && h < 64) starts[h] = lane + 1;
+        wave_sync();
+        const int32_t v = wave_prefix_max(max(starts[lane], carry));
+        carry = __builtin_amdgcn_readlane(v, 63);
+        const int32_t j = max(v - 1, 0);
+        const int32_t p = c + lane;
         const int32_t idx = __shfl(pb, j, 64) + (p - __shfl(off, j, 64));
-        const float4 v = G.pts[p < total ? idx : 0];   // a scan only happens for a shape with points
-        return p < total ? v : make_float4(0.f, 0.f, 0.f, 0.f);
+        const float4 x = G.pts[p < total ? idx : 0];   // a scan only happens for a shape with points
+        return p < total ? x : make_float4(0.f, 0.f, 0.f, 0.f);
     };
-    float4 nxt = total > 0 ? point_at(lane) : make_float4(0.f, 0.f, 0.f, 0.f);
+    float4 nxt = total > 0 ? chunk_at(0) : make_float4(0.f, 0.f, 0.f, 0.f);
     for (int32_t c = 0; c < total; c += 64) {
         const float4 cur = nxt;
         ev.stage(cur);
-        nxt = point_at(c + 64 + lane);    // the next chunk's loads fly during the evaluation
+        nxt = chunk_at(c + 64);    // the next chunk's loads fly during the evaluation
         ev.eval(cur, min(64, total - c));
     }
     const int32_t rest = n - cnt;
@@ -525,7 +553,7 @@ __global__ __launch_bounds__(kQueryBlock, 4) void k_nn(Band B, Global G, NnParam
     __shared__ uint32_t s_cell[kQueryTile];          // sorted position -> packed cell (10 bits per axis)
     __shared__ int32_t s_red[kWaves * 6];
     __shared__ float4 s_buf[kQueryBlock];
-    __shared__ int4 s_runs[kWaves][kRunCap];
+    __shared__ int4 s_runs[kWaves][kRunArea];
     __shared__ int16_t s_group[kWaves][kWaveSpan + 1];
     __shared__ int32_t s_ngroups[kWaves];
     __shared__ float4 s_tq[kWaves][kTail];
