@@ -31,6 +31,7 @@ struct Side {
     double g[3];       // grad f
     double n;          // |grad f|
     double gh[3];      // grad f / |grad f| (0 if |grad f| < eps)
+    double inv_n;      // 1 / |grad f| (0 if |grad f| < eps)
     bool ok;           // |grad f| >= eps
 };
 
@@ -55,6 +56,7 @@ __device__ inline void eval_side(const Band& B, const ShapeDesc& s, const float*
     out.n = sqrt(fma(it.g[0], it.g[0], fma(it.g[1], it.g[1], it.g[2] * it.g[2])));
     out.ok = out.n >= kEpsNorm;
     const double inv = out.ok ? 1.0 / out.n : 0.0;
+    out.inv_n = inv;
     out.gh[0] = it.g[0] * inv;
     out.gh[1] = it.g[1] * inv;
     out.gh[2] = it.g[2] * inv;
@@ -186,9 +188,13 @@ __device__ inline int32_t oct_slot(int32_t key, int32_t w)
     return (key >> 3) * kBrickVol + ((i * kBrick + j) * kBrick + k);
 }
 
+// Multiplicative (Fibonacci) hashing at 24 bits: keys are below 2^24 (brick
+// < 2^21), so a 24-bit multiply (full rate, where a 32-bit one is not) by
+// 0x9E3779 (2^24 over the golden ratio) gives key * 0x9E3779 mod 2^24, whose
+// top 8 bits spread neighbouring keys over the table.
 __device__ inline int32_t table_home(int32_t key)
 {
-    return (int32_t)(((uint32_t)key * 2654435761u) >> 24);
+    return (int32_t)((__umul24((uint32_t)key, 0x9E3779u) >> 16) & 255u);
 }
 
 // Both walk the same probe sequence and give up after kCacheProbes places, so
@@ -232,7 +238,7 @@ __device__ inline void query_adjoint(const ShapeDesc& s, const QueryState& st, g
     const double df = -(gh[0] * st.r[0] + gh[1] * st.r[1] + gh[2] * st.r[2]) * inv_lp;
     double dg[3] = {0.0, 0.0, 0.0}, dgs[3] = {0.0, 0.0, 0.0};
     if (st.q.ok) {
-        const double k = -st.q.f * inv_lp / st.q.n;
+        const double k = -st.q.f * inv_lp * st.q.inv_n;
         const double dd = gh[0] * st.d[0] + gh[1] * st.d[1] + gh[2] * st.d[2];
 #pragma unroll
         for (int a = 0; a < 3; ++a) dg[a] = k * fma(-dd, gh[a], st.d[a]);
@@ -240,7 +246,7 @@ __device__ inline void query_adjoint(const ShapeDesc& s, const QueryState& st, g
     // gradient-consistency term through both normalised gradients
     if (st.q.ok && st.s.ok) {
         const double c = gh[0] * ghs[0] + gh[1] * ghs[1] + gh[2] * ghs[2];
-        const double kq = (double)w.gamma / st.q.n, ks = (double)w.gamma / st.s.n;
+        const double kq = (double)w.gamma * st.q.inv_n, ks = (double)w.gamma * st.s.inv_n;
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
             dg[a] -= kq * fma(-c, gh[a], ghs[a]);
