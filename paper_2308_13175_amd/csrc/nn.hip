@@ -239,7 +239,7 @@ __device__ inline void eval_chunk(const float4* __restrict__ buf, int32_t cnt, S
 {
     float b1 = q.best1, b2 = q.best2;
     int32_t id = q.id1;
-#pragma unroll 4
+#pragma unroll 8
     for (int32_t t = 0; t < cnt; ++t) {
         const float4 p = buf[t];
         const float dx = q.x - p.x, dy = q.y - p.y, dz = q.z - p.z;
