@@ -333,73 +333,68 @@ __device__ inline void scatter_cell(const int32_t slot[8], int32_t packed, const
             }
 }
 
-// One thread per query of a quarter tile: evaluate, take the adjoint, keep the 16
-// corner contributions in registers while the block registers the bricks
-// they fall in, then accumulate them in LDS copies of those octants (at most
-// kCacheOcts, the rest straight to memory; fixed point) and add the octants to
-// G once.  kLoss: also the tile's loss partials, and the contributions
-// go out unscaled (the per-shape scale 1/valid count is applied when they are
-// folded into the gradient); otherwise they are scaled by dloss / valid count.
-template <bool kLoss>
-__global__ __launch_bounds__(kGradBlock) void k_query_grad(Band B, const float* __restrict__ qx,
-                                                           const float* __restrict__ qy,
-                                                           const float* __restrict__ qz,
-                                                           const int32_t* __restrict__ nn,
-                                                           const float* __restrict__ px,
-                                                           const float* __restrict__ py,
-                                                           const float* __restrict__ pz,
-                                                           const float* __restrict__ D, gp_weights w,
-                                                           const double* __restrict__ dloss,
-                                                           const double* __restrict__ inv_qv,
-                                                           float* __restrict__ G, double* __restrict__ q_part,
-                                                           int32_t* flag)
+// Dense window: when the cells of a block's queries and of their nearest
+// points fit in a box of at most kWinVol vertices, the block accumulates in
+// an LDS copy of that box (x-major, w1 x w2 vertices per x layer), indexed
+// directly: no table, no probing.  Same fixed point and the same bypass of
+// large contributions as the octant cache.
+constexpr int64_t kWinVol = (int64_t)kCacheOcts * kOctVol;
+
+__device__ inline void window_add(const int32_t c[3], const int32_t box[6], int32_t w1, int32_t w2,
+                                  const int32_t slot[8], const float cv[8], unsigned long long* __restrict__ acc,
+                                  float* __restrict__ G, float scale)
 {
-    __shared__ unsigned long long s_acc[kCacheOcts * kOctVol];
-    __shared__ int32_t s_keys[kCacheTable], s_idx[kCacheTable], s_oct[kCacheOcts];
-    __shared__ int32_t s_wcount[kGradBlock / 64];
-    __shared__ double s_red[kGradBlock / 64 * 4];
-    const int64_t tile = blockIdx.x / kGradParts;
-    const int32_t quarter = blockIdx.x % kGradParts;
-    const int32_t shape = B.tile_shape[tile];
-    const ShapeDesc& s = B.shapes[shape];
-    const int64_t q0 = B.tile_start[tile] + (int64_t)quarter * kGradBlock;
-    const int64_t qe = min(B.tile_start[tile] + (int64_t)kQueryTile, s.query_off + s.query_cnt);
-    const float scale = kLoss ? 1.f : (float)(dloss[shape] * inv_qv[shape]);
-
-    static_assert(kCacheTable == kGradBlock, "one table entry per thread");
-    s_keys[threadIdx.x] = -1;
-    for (int32_t i = threadIdx.x; i < kCacheOcts * kOctVol / 2; i += blockDim.x)
-        reinterpret_cast<ulonglong2*>(s_acc)[i] = make_ulonglong2(0ull, 0ull);
-    __syncthreads();
-
-    const int64_t k = q0 + threadIdx.x;
-    float cq[8], cs[8];
-    int32_t sq[8], ss[8], lq = 0, ls = 0;
-    bool valid = false;
-    double part[4] = {0.0, 0.0, 0.0, 0.0};
-    if (k < qe) {
-        QueryState st;
-        valid = eval_query(B, s, D, qx[k], qy[k], qz[k], nn[k], px, py, pz, flag, st);
-        if (valid) {
-            if (kLoss) {
-                part[0] = st.lp;
-                part[1] = fabs(st.s.f);
-                part[2] = (st.q.ok && st.s.ok) ? 1.0 - fma(st.q.gh[0], st.s.gh[0],
-                                                           fma(st.q.gh[1], st.s.gh[1], st.q.gh[2] * st.s.gh[2]))
-                                               : 1.0;
-                part[3] = 1.0;
-            }
-            query_adjoint(s, st, w, cq, cs);
+    const int32_t base = ((c[0] - box[0]) * w1 + (c[1] - box[1])) * w2 + (c[2] - box[2]);
+    const int32_t sx = w1 * w2;
 #pragma unroll
-            for (int i = 0; i < 8; ++i) {
-                sq[i] = st.q.slot[i];
-                ss[i] = st.s.slot[i];
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int d = 0; d < 2; ++d) {
+                const int i = 4 * a + 2 * b + d;
+                if (fabsf(cv[i]) < kFixLimit)
+                    atomicAdd(&acc[base + a * sx + b * w2 + d],
+                              (unsigned long long)__double2ll_rn((double)cv[i] * kFixScale));
+                else
+                    atomicAdd(at32(G, (uint32_t)slot[i]), scale * cv[i]);
             }
-            lq = pack_local(st.q.c);
-            ls = pack_local(st.s.c);
-            insert_cell_octs(sq, lq, s_keys);
-            insert_cell_octs(ss, ls, s_keys);
-        }
+}
+
+// Add the window's non-zero entries to the gradient, one atomic per vertex.
+// The entry of vertex (x, y, z) of the box is found from its index by float
+// reciprocals: the index is below 2^13, far inside float's exact range, and
+// (i + 1/2) / w stays at least 1/(2w) away from an integer.
+__device__ inline void window_flush(const Band& B, const ShapeDesc& s, const int32_t box[6], int32_t w1, int32_t w2,
+                                    int32_t vol, const unsigned long long* __restrict__ acc, float* __restrict__ G,
+                                    float scale)
+{
+    const int32_t w12 = w1 * w2;
+    const float inv12 = 1.f / (float)w12, inv2 = 1.f / (float)w2;
+    for (int32_t i = threadIdx.x; i < vol; i += blockDim.x) {
+        const long long a = (long long)acc[i];
+        if (a == 0) continue;
+        const int32_t x = (int32_t)(((float)i + 0.5f) * inv12);
+        const int32_t r = i - x * w12;
+        const int32_t y = (int32_t)(((float)r + 0.5f) * inv2);
+        const int32_t vx = box[0] + x, vy = box[1] + y, vz = box[2] + (r - y * w2);
+        const int32_t br = brick_of(B, s, vx >> 3, vy >> 3, vz >> 3);
+        atomicAdd(at32(G, (uint32_t)(br * kBrickVol + local_index(vx, vy, vz))),
+                  (float)((double)a * (1.0 / kFixScale) * (double)scale));
+    }
+}
+
+// The octant cache for a block whose box is too large for the window:
+// register the octants the block's contributions fall in, number the first
+// kCacheOcts of them in table order, accumulate, and add each octant to G.
+__device__ inline void octant_path(bool valid, const int32_t sq[8], const int32_t ss[8], int32_t lq, int32_t ls,
+                                   const float cq[8], const float cs[8], int32_t* s_keys, int32_t* s_idx,
+                                   int32_t* s_oct, int32_t* s_wcount, unsigned long long* __restrict__ s_acc,
+                                   float* __restrict__ G, float scale)
+{
+    if (valid) {
+        insert_cell_octs(sq, lq, s_keys);
+        insert_cell_octs(ss, ls, s_keys);
     }
     __syncthreads();
     // LDS octant numbers in table order (one table entry per thread)
@@ -430,6 +425,101 @@ __global__ __launch_bounds__(kGradBlock) void k_query_grad(Band B, const float* 
         const long long a = (long long)s_acc[i];
         if (a != 0) atomicAdd(&G[oct_slot(s_oct[i >> 6], i & (kOctVol - 1))],
                               (float)((double)a * (1.0 / kFixScale) * (double)scale));
+    }
+}
+
+// One thread per query of a quarter tile: evaluate, take the adjoint, keep the 16
+// corner contributions in registers, then accumulate them in LDS and add the
+// sums to G once per vertex: in the block's dense window when its box fits,
+// else in LDS copies of the octants they fall in (registered in a table
+// first; at most kCacheOcts, the rest straight to memory).  Fixed point
+// either way.  kLoss: also the tile's loss partials, and the contributions
+// go out unscaled (the per-shape scale 1/valid count is applied when they are
+// folded into the gradient); otherwise they are scaled by dloss / valid count.
+template <bool kLoss>
+__global__ __launch_bounds__(kGradBlock) void k_query_grad(Band B, const float* __restrict__ qx,
+                                                           const float* __restrict__ qy,
+                                                           const float* __restrict__ qz,
+                                                           const int32_t* __restrict__ nn,
+                                                           const float* __restrict__ px,
+                                                           const float* __restrict__ py,
+                                                           const float* __restrict__ pz,
+                                                           const float* __restrict__ D, gp_weights w,
+                                                           const double* __restrict__ dloss,
+                                                           const double* __restrict__ inv_qv,
+                                                           float* __restrict__ G, double* __restrict__ q_part,
+                                                           int32_t* flag)
+{
+    __shared__ unsigned long long s_acc[kCacheOcts * kOctVol];
+    __shared__ int32_t s_keys[kCacheTable], s_idx[kCacheTable], s_oct[kCacheOcts];
+    __shared__ int32_t s_wcount[kGradBlock / 64];
+    __shared__ double s_red[kGradBlock / 64 * 4];
+    __shared__ int32_t s_box[kGradBlock / 64 * 6];
+    const int64_t tile = blockIdx.x / kGradParts;
+    const int32_t quarter = blockIdx.x % kGradParts;
+    const int32_t shape = B.tile_shape[tile];
+    const ShapeDesc& s = B.shapes[shape];
+    const int64_t q0 = B.tile_start[tile] + (int64_t)quarter * kGradBlock;
+    const int64_t qe = min(B.tile_start[tile] + (int64_t)kQueryTile, s.query_off + s.query_cnt);
+    const float scale = kLoss ? 1.f : (float)(dloss[shape] * inv_qv[shape]);
+
+    static_assert(kCacheTable == kGradBlock, "one table entry per thread");
+    s_keys[threadIdx.x] = -1;
+    for (int32_t i = threadIdx.x; i < kCacheOcts * kOctVol / 2; i += blockDim.x)
+        reinterpret_cast<ulonglong2*>(s_acc)[i] = make_ulonglong2(0ull, 0ull);
+    __syncthreads();
+
+    const int64_t k = q0 + threadIdx.x;
+    float cq[8], cs[8];
+    int32_t sq[8], ss[8], ccq[3] = {0, 0, 0}, ccs[3] = {0, 0, 0};
+    bool valid = false;
+    double part[4] = {0.0, 0.0, 0.0, 0.0};
+    if (k < qe) {
+        QueryState st;
+        valid = eval_query(B, s, D, qx[k], qy[k], qz[k], nn[k], px, py, pz, flag, st);
+        if (valid) {
+            if (kLoss) {
+                part[0] = st.lp;
+                part[1] = fabs(st.s.f);
+                part[2] = (st.q.ok && st.s.ok) ? 1.0 - fma(st.q.gh[0], st.s.gh[0],
+                                                           fma(st.q.gh[1], st.s.gh[1], st.q.gh[2] * st.s.gh[2]))
+                                               : 1.0;
+                part[3] = 1.0;
+            }
+            query_adjoint(s, st, w, cq, cs);
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                sq[i] = st.q.slot[i];
+                ss[i] = st.s.slot[i];
+            }
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                ccq[a] = st.q.c[a];
+                ccs[a] = st.s.c[a];
+            }
+        }
+    }
+    // the box of the block's cells, in vertices w0 x w1 x w2
+    int32_t box[6];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        box[a] = valid ? min(ccq[a], ccs[a]) : 0x7fffffff;
+        box[3 + a] = valid ? max(ccq[a], ccs[a]) : -1;
+    }
+    block_minmax6(box, s_box);
+#pragma unroll
+    for (int a = 0; a < 6; ++a) box[a] = __builtin_amdgcn_readfirstlane(box[a]);
+    const int32_t w0 = box[3] - box[0] + 2, w1 = box[4] - box[1] + 2, w2 = box[5] - box[2] + 2;
+    if (box[3] >= 0 && (int64_t)w0 * w1 * w2 <= kWinVol) {
+        if (valid) {
+            window_add(ccq, box, w1, w2, sq, cq, s_acc, G, scale);
+            window_add(ccs, box, w1, w2, ss, cs, s_acc, G, scale);
+        }
+        __syncthreads();
+        window_flush(B, s, box, w1, w2, w0 * w1 * w2, s_acc, G, scale);
+    } else {
+        octant_path(valid, sq, ss, pack_local(ccq), pack_local(ccs), cq, cs, s_keys, s_idx, s_oct, s_wcount, s_acc,
+                    G, scale);
     }
     if (kLoss) {
         // tile partials in a fixed order: lanes, then waves
