@@ -62,6 +62,53 @@ def test_sphere_64_parity(m1, m2):
     prob.close()
 
 
+def _block_boxes(dom, pts, q, nn, cf, block=256):
+    """Vertex volume of the box of each block's query cells and nearest-point
+    cells, over the queries in the M1 band (the ones the gradient pass uses)."""
+    R = np.array(dom.dims)
+    cell = lambda x: np.clip(np.floor((x.astype(np.float64) - dom.lo) / dom.h), 0, R - 1).astype(np.int64)
+    cq, cs = cell(q), cell(pts[nn])
+    ok = (cf[(cq[:, 0] * R[1] + cq[:, 1]) * R[2] + cq[:, 2]] & 2) != 0
+    vols = []
+    for b in range(0, len(q), block):
+        m = ok[b:b + block]
+        if not m.any():
+            continue
+        c = np.concatenate([cq[b:b + block][m], cs[b:b + block][m]])
+        vols.append(int(np.prod(c.max(0) - c.min(0) + 2)))
+    return np.array(vols)
+
+
+@pytest.mark.parametrize("order", ["cell-sorted", "random"])
+def test_gradient_accumulation_paths(order):
+    """A block of the gradient pass sums its contributions in a dense LDS
+    window over its vertex box when the box holds at most 4608 vertices, and
+    in LDS copies of the octants they fall in otherwise.  Queries around
+    cell-sorted points with a small spread keep every block's box small (the
+    window); queries around points drawn at random spread every block over
+    the sphere (the octants).  Both against the oracle."""
+    log("case: gradient accumulation, %s sources" % order)
+    dom = synth.cube_domain(64)
+    pts = synth.sphere_points(10_000, 0.5, seed=21)
+    c = np.minimum(np.floor((pts.astype(np.float64) - dom.lo) / dom.h), 63).astype(np.int64)
+    pts = pts[np.argsort((c[:, 0] * 64 + c[:, 1]) * 64 + c[:, 2], kind="stable")]
+    q = synth.host_queries(pts, 40_000, 0.01, seed=22, stratified=(order == "cell-sorted"))
+    D = synth.sphere_sdf_field(dom, 0.5, noise=0.01, seed=23)
+    cf, vf, nn, ref = _oracle(dom, pts, q, D)
+    vols = _block_boxes(dom, pts, q, nn, cf)
+    if order == "cell-sorted":
+        assert vols.max() <= 4608
+    else:
+        assert vols.min() > 4608
+    prob = _run_gpu(dom, pts, q, D)
+    assert np.array_equal(prob.nn[: len(q)].cpu().numpy(), nn)
+    got, nv = loss_terms(prob)
+    assert int(nv[0]) == ref["n_valid"]
+    assert_terms_close(got[0], ref)
+    assert_grad_close(prob.dense_grad()[0], ref["dD"])
+    prob.close()
+
+
 def test_anisotropic_grid_and_edge_cases():
     """Anisotropic cells, a point on hi, queries outside the domain, duplicate points."""
     log("case: anisotropic 24x17x31 with edge cases")
