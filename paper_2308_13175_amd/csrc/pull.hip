@@ -334,50 +334,63 @@ __device__ inline void scatter_cell(const int32_t slot[8], int32_t packed, const
 }
 
 // Dense window: when the cells of a block's queries and of their nearest
-// points fit in a box of at most kWinVol vertices, the block accumulates in
-// an LDS copy of that box (x-major, w1 x w2 vertices per x layer), indexed
-// directly: no table, no probing.  Same fixed point and the same bypass of
-// large contributions as the octant cache.
+// points fit in a box of at most kWinPasses * kWinVol vertices, the block
+// accumulates in an LDS copy of that box (x-major, w1 x w2 vertices per x
+// layer), indexed directly: no table, no probing.  A box larger than the
+// window is taken in slabs of whole x layers, one pass each (every
+// contribution is added in the pass of its slab).  Same fixed point and the
+// same bypass of large contributions as the octant cache.
 constexpr int64_t kWinVol = (int64_t)kCacheOcts * kOctVol;
+constexpr int32_t kWinPasses = 4;
 
-__device__ inline void window_add(const int32_t c[3], const int32_t box[6], int32_t w1, int32_t w2,
-                                  const int32_t slot[8], const float cv[8], unsigned long long* __restrict__ acc,
-                                  float* __restrict__ G, float scale)
+// Contributions of one cell's corners whose box-relative x lies in [x0, x1).
+__device__ inline void window_add(const int32_t c[3], const int32_t box[6], int32_t x0, int32_t x1, int32_t w1,
+                                  int32_t w2, const int32_t slot[8], const float cv[8],
+                                  unsigned long long* __restrict__ acc, float* __restrict__ G, float scale)
 {
-    const int32_t base = ((c[0] - box[0]) * w1 + (c[1] - box[1])) * w2 + (c[2] - box[2]);
+    const int32_t rx = c[0] - box[0];
+    const int32_t base = ((rx - x0) * w1 + (c[1] - box[1])) * w2 + (c[2] - box[2]);
     const int32_t sx = w1 * w2;
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+    for (int a = 0; a < 2; ++a) {
+        if (rx + a < x0 || rx + a >= x1) continue;
 #pragma unroll
         for (int b = 0; b < 2; ++b)
 #pragma unroll
             for (int d = 0; d < 2; ++d) {
                 const int i = 4 * a + 2 * b + d;
-                if (fabsf(cv[i]) < kFixLimit)
-                    atomicAdd(&acc[base + a * sx + b * w2 + d],
-                              (unsigned long long)__double2ll_rn((double)cv[i] * kFixScale));
+                // (converted here, in its pass: kept opaque so that the
+                // conversions are not hoisted out of the pass loop and held
+                // as 16 64-bit values)
+                float v = cv[i];
+                asm volatile("" : "+v"(v));
+                if (fabsf(v) < kFixLimit)
+                    atomicAdd(&acc[base + a * sx + b * w2 + d], (unsigned long long)__double2ll_rn((double)v * kFixScale));
                 else
-                    atomicAdd(at32(G, (uint32_t)slot[i]), scale * cv[i]);
+                    atomicAdd(at32(G, (uint32_t)slot[i]), scale * v);
             }
+    }
 }
 
-// Add the window's non-zero entries to the gradient, one atomic per vertex.
-// The entry of vertex (x, y, z) of the box is found from its index by float
+// Add the non-zero entries of the slab starting at box-relative x layer x0
+// (vol entries) to the gradient, one atomic per vertex, and clear them for
+// the next slab.  The vertex of an entry is found from its index by float
 // reciprocals: the index is below 2^13, far inside float's exact range, and
 // (i + 1/2) / w stays at least 1/(2w) away from an integer.
-__device__ inline void window_flush(const Band& B, const ShapeDesc& s, const int32_t box[6], int32_t w1, int32_t w2,
-                                    int32_t vol, const unsigned long long* __restrict__ acc, float* __restrict__ G,
-                                    float scale)
+__device__ inline void window_flush(const Band& B, const ShapeDesc& s, const int32_t box[6], int32_t x0, int32_t w1,
+                                    int32_t w2, int32_t vol, unsigned long long* __restrict__ acc,
+                                    float* __restrict__ G, float scale)
 {
     const int32_t w12 = w1 * w2;
     const float inv12 = 1.f / (float)w12, inv2 = 1.f / (float)w2;
     for (int32_t i = threadIdx.x; i < vol; i += blockDim.x) {
         const long long a = (long long)acc[i];
         if (a == 0) continue;
+        acc[i] = 0ull;
         const int32_t x = (int32_t)(((float)i + 0.5f) * inv12);
         const int32_t r = i - x * w12;
         const int32_t y = (int32_t)(((float)r + 0.5f) * inv2);
-        const int32_t vx = box[0] + x, vy = box[1] + y, vz = box[2] + (r - y * w2);
+        const int32_t vx = box[0] + x0 + x, vy = box[1] + y, vz = box[2] + (r - y * w2);
         const int32_t br = brick_of(B, s, vx >> 3, vy >> 3, vz >> 3);
         atomicAdd(at32(G, (uint32_t)(br * kBrickVol + local_index(vx, vy, vz))),
                   (float)((double)a * (1.0 / kFixScale) * (double)scale));
@@ -510,13 +523,19 @@ __global__ __launch_bounds__(kGradBlock) void k_query_grad(Band B, const float* 
 #pragma unroll
     for (int a = 0; a < 6; ++a) box[a] = __builtin_amdgcn_readfirstlane(box[a]);
     const int32_t w0 = box[3] - box[0] + 2, w1 = box[4] - box[1] + 2, w2 = box[5] - box[2] + 2;
-    if (box[3] >= 0 && (int64_t)w0 * w1 * w2 <= kWinVol) {
-        if (valid) {
-            window_add(ccq, box, w1, w2, sq, cq, s_acc, G, scale);
-            window_add(ccs, box, w1, w2, ss, cs, s_acc, G, scale);
+    const int64_t w12 = (int64_t)w1 * w2;
+    const int32_t layers = box[3] >= 0 && w12 <= kWinVol ? (int32_t)(kWinVol / w12) : 0;   // x layers per slab
+    if (layers > 0 && w0 <= kWinPasses * layers) {
+        for (int32_t x0 = 0; x0 < w0; x0 += layers) {
+            const int32_t x1 = min(x0 + layers, w0);
+            if (valid) {
+                window_add(ccq, box, x0, x1, w1, w2, sq, cq, s_acc, G, scale);
+                window_add(ccs, box, x0, x1, w1, w2, ss, cs, s_acc, G, scale);
+            }
+            __syncthreads();
+            window_flush(B, s, box, x0, w1, w2, (x1 - x0) * (int32_t)w12, s_acc, G, scale);
+            __syncthreads();
         }
-        __syncthreads();
-        window_flush(B, s, box, w1, w2, w0 * w1 * w2, s_acc, G, scale);
     } else {
         octant_path(valid, sq, ss, pack_local(ccq), pack_local(ccs), cq, cs, s_keys, s_idx, s_oct, s_wcount, s_acc,
                     G, scale);

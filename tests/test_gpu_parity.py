@@ -62,44 +62,54 @@ def test_sphere_64_parity(m1, m2):
     prob.close()
 
 
-def _block_boxes(dom, pts, q, nn, cf, block=256):
-    """Vertex volume of the box of each block's query cells and nearest-point
-    cells, over the queries in the M1 band (the ones the gradient pass uses)."""
+def _window_passes(dom, pts, q, nn, cf, block=256, window=4608, max_passes=4):
+    """Per block of the gradient pass: how many x-slab passes of the dense LDS
+    window (`window` vertices) its vertex box takes, or 0 for the octant cache
+    (a box layer larger than the window, or more than max_passes slabs).  The
+    box covers the cells of the block's queries in the M1 band and of their
+    nearest points."""
     R = np.array(dom.dims)
     cell = lambda x: np.clip(np.floor((x.astype(np.float64) - dom.lo) / dom.h), 0, R - 1).astype(np.int64)
     cq, cs = cell(q), cell(pts[nn])
     ok = (cf[(cq[:, 0] * R[1] + cq[:, 1]) * R[2] + cq[:, 2]] & 2) != 0
-    vols = []
+    out = []
     for b in range(0, len(q), block):
         m = ok[b:b + block]
         if not m.any():
             continue
         c = np.concatenate([cq[b:b + block][m], cs[b:b + block][m]])
-        vols.append(int(np.prod(c.max(0) - c.min(0) + 2)))
-    return np.array(vols)
+        w = c.max(0) - c.min(0) + 2
+        layers = window // (w[1] * w[2])
+        passes = -(-w[0] // layers) if layers > 0 else 0
+        out.append(passes if passes <= max_passes else 0)
+    return np.array(out)
 
 
-@pytest.mark.parametrize("order", ["cell-sorted", "random"])
-def test_gradient_accumulation_paths(order):
+@pytest.mark.parametrize("case", ["one slab", "several slabs", "octants"])
+def test_gradient_accumulation_paths(case):
     """A block of the gradient pass sums its contributions in a dense LDS
-    window over its vertex box when the box holds at most 4608 vertices, and
-    in LDS copies of the octants they fall in otherwise.  Queries around
-    cell-sorted points with a small spread keep every block's box small (the
-    window); queries around points drawn at random spread every block over
-    the sphere (the octants).  Both against the oracle."""
-    log("case: gradient accumulation, %s sources" % order)
+    window over its vertex box, in one pass or in up to four x slabs, and in
+    LDS copies of the octants they fall in when the box is larger still.
+    Queries around cell-sorted points with a small spread keep every block's
+    box within one window; a larger spread needs several slabs; sources drawn
+    at random spread every block over the sphere (the octants).  The path of
+    every block is computed on the host; each case against the oracle."""
+    log("case: gradient accumulation, %s" % case)
     dom = synth.cube_domain(64)
     pts = synth.sphere_points(10_000, 0.5, seed=21)
     c = np.minimum(np.floor((pts.astype(np.float64) - dom.lo) / dom.h), 63).astype(np.int64)
     pts = pts[np.argsort((c[:, 0] * 64 + c[:, 1]) * 64 + c[:, 2], kind="stable")]
-    q = synth.host_queries(pts, 40_000, 0.01, seed=22, stratified=(order == "cell-sorted"))
+    n, sigma = (10_000, 0.04) if case == "several slabs" else (40_000, 0.01)
+    q = synth.host_queries(pts, n, sigma, seed=22, stratified=(case != "octants"))
     D = synth.sphere_sdf_field(dom, 0.5, noise=0.01, seed=23)
     cf, vf, nn, ref = _oracle(dom, pts, q, D)
-    vols = _block_boxes(dom, pts, q, nn, cf)
-    if order == "cell-sorted":
-        assert vols.max() <= 4608
+    passes = _window_passes(dom, pts, q, nn, cf)
+    if case == "one slab":
+        assert (passes == 1).all()
+    elif case == "several slabs":
+        assert (passes >= 1).all() and set(passes.tolist()) >= {2, 3, 4}
     else:
-        assert vols.min() > 4608
+        assert (passes == 0).all()
     prob = _run_gpu(dom, pts, q, D)
     assert np.array_equal(prob.nn[: len(q)].cpu().numpy(), nn)
     got, nv = loss_terms(prob)
