@@ -21,7 +21,7 @@
 // query's gap to the box, no other point can be as close and the query is
 // resolved.
 //
-// Point-parallel pass (lane = point) for the few queries left open: up to 8
+// Point-parallel pass (lane = point) for the few queries left open: up to 6
 // at a time, the cells meeting the bounding box of the ball of each one's
 // candidate distance, outside the box already scanned, are streamed once;
 // every lane tests its point against each of the queries, and the per-lane
@@ -307,7 +307,7 @@ __device__ inline int32_t wave_prefix_max(int32_t v)
 
 constexpr int kRunCap = 128;   // runs staged per wave (a batch of 64 plus one append round)
 constexpr int kRunArea = kRunCap + 16;   // per wave: the runs, then 64 ints marking run starts in a chunk
-constexpr int kTail = 8;       // open queries served together by the point-parallel pass
+constexpr int kTail = 6;       // open queries served together by the point-parallel pass
 constexpr int kTailSpan = 24;  // larger balls (cells per axis) go to the ring search
 
 // Lockstep evaluation: lane = query, each staged point broadcast from LDS.
