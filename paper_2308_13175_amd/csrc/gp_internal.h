@@ -166,6 +166,25 @@ __device__ inline void corner_slots(const Band& B, const ShapeDesc& s, const int
             }
 }
 
+// Work item of block b among n: the chip dispatches consecutive blocks to
+// its eight XCDs in turn, and each XCD has its own L2, so neighbouring work
+// items (which read the same points and field values) would land in
+// different L2s.  Renumbered, each run of 8 * kXcdChunk blocks gives every
+// XCD kXcdChunk consecutive items (neighbours share its L2), while the runs
+// still spread every region of the work over all eight XCDs (balance); the
+// last n mod (8 * kXcdChunk) blocks keep their numbers.  A bijection of
+// [0, n), so every item is done once whatever the mapping of blocks to XCDs
+// really is.
+constexpr int64_t kXcdChunk = 16;
+
+__device__ inline int64_t xcd_work_item(int64_t b, int64_t n)
+{
+    constexpr int64_t run = 8 * kXcdChunk;
+    if (b >= n / run * run) return b;
+    const int64_t r = b % run;
+    return b - r + (r & 7) * kXcdChunk + (r >> 3);
+}
+
 // Block-wide minimum of v[0..2] and maximum of v[3..5] (blockDim = 256).
 // Every thread receives the result.  scratch: shared int [4 * 6].
 __device__ inline void block_minmax6(int32_t v[6], int32_t* scratch)

@@ -560,8 +560,9 @@ __global__ __launch_bounds__(kQueryBlock, 4) void k_nn(Band B, Global G, NnParam
 
     // P.parts blocks share a tile: each sorts all of it and scans its own
     // contiguous share of the sorted positions (more blocks for small batches)
-    const int64_t tile = blockIdx.x / P.parts;
-    const int32_t part = (int32_t)(blockIdx.x % P.parts);
+    const int64_t item = xcd_work_item(blockIdx.x, gridDim.x);
+    const int64_t tile = item / P.parts;
+    const int32_t part = (int32_t)(item % P.parts);
     const int32_t shape = B.tile_shape[tile];
     const ShapeDesc& s = B.shapes[shape];
     const int64_t q0 = B.tile_start[tile];

@@ -134,7 +134,7 @@ __global__ __launch_bounds__(kQueryBlock) void k_forward_query(Band B, const flo
                                                                double* __restrict__ q_part, int32_t* flag)
 {
     __shared__ double lds[4 * 4];
-    const int64_t tile = blockIdx.x;
+    const int64_t tile = xcd_work_item(blockIdx.x, gridDim.x);
     const int32_t shape = B.tile_shape[tile];
     const ShapeDesc& s = B.shapes[shape];
     const int64_t q0 = B.tile_start[tile];
@@ -468,8 +468,9 @@ __global__ __launch_bounds__(kGradBlock) void k_query_grad(Band B, const float* 
     __shared__ int32_t s_wcount[kGradBlock / 64];
     __shared__ double s_red[kGradBlock / 64 * 4];
     __shared__ int32_t s_box[kGradBlock / 64 * 6];
-    const int64_t tile = blockIdx.x / kGradParts;
-    const int32_t quarter = blockIdx.x % kGradParts;
+    const int64_t item = xcd_work_item(blockIdx.x, gridDim.x);
+    const int64_t tile = item / kGradParts;
+    const int32_t quarter = (int32_t)(item % kGradParts);
     const int32_t shape = B.tile_shape[tile];
     const ShapeDesc& s = B.shapes[shape];
     const int64_t q0 = B.tile_start[tile] + (int64_t)quarter * kGradBlock;
@@ -552,7 +553,7 @@ __global__ __launch_bounds__(kGradBlock) void k_query_grad(Band B, const float* 
         if (threadIdx.x < 4) {
             double a = 0.0;
             for (int wv = 0; wv < kGradBlock / 64; ++wv) a += s_red[wv * 4 + threadIdx.x];
-            q_part[blockIdx.x * 4 + threadIdx.x] = a;
+            q_part[item * 4 + threadIdx.x] = a;
         }
     }
 }
