@@ -183,8 +183,9 @@ gp_status gp_get_nn_params(gp_ctx ctx, gp_nn_params* params);
  * Autotuner of the search shape: runs gp_nn_query's kernel on the given
  * queries for group_span in {4, 6, 8, 12, 16, 24, 32} x first_shell in
  * {0, 1, 2} at the current tile_parts and skip_empty, then tile_parts in
- * {1, 2, 4} at the best of those, then the other skip_empty setting, then
- * the other morton_sort setting; each
+ * {1, 2, 4} at the best of those (and, if that changes tile_parts, the
+ * span x shell grid again at the new tile_parts), then the other skip_empty
+ * setting, then the other morton_sort setting; each
  * candidate once untimed and then reps times between HIP events on the
  * context's stream (its time: the smallest of those).  Keeps the fastest in
  * the context and leaves nn_out holding the nearest neighbours (as

@@ -788,8 +788,9 @@ gp_status gp_nn_impl(gp_ctx ctx, const float* qx, const float* qy, const float* 
 
 // Times k_nn for every (span, shell) pair of a small grid on the caller's
 // queries (the results are the same for all of them), then the number of
-// blocks per tile for the best pair, then the other skip_empty setting, then
-// the other sort setting, and keeps the fastest in the context.
+// blocks per tile for the best pair (and, if that changed, every pair again
+// at the new number), then the other skip_empty setting, then the other sort
+// setting, and keeps the fastest in the context.
 // Each candidate runs once untimed, then `reps` times between events; its
 // time is the smallest of those.  The context's current setting is timed
 // first and is only replaced by one at least 2% faster, so timing noise does
@@ -853,6 +854,16 @@ gp_status gp_autotune_nn_impl(gp_ctx ctx, const float* qx, const float* qy, cons
             NnParams P = shaped;
             P.parts = pa;
             if (pa != shaped.parts) offer(P);
+        }
+        if (best.parts != shaped.parts) {   // the pairs again, at the new number of blocks per tile
+            const NnParams parted = best;
+            for (int32_t sp : spans)
+                for (int32_t sh : shells) {
+                    NnParams P = parted;
+                    P.span = sp;
+                    P.shell = sh;
+                    if (sp != parted.span || sh != parted.shell) offer(P);
+                }
         }
         {
             NnParams P = best;
