@@ -376,7 +376,8 @@ def schedule_sweep(kind: str, iters: int = 1600, n_points: int = 200_000, n_quer
         torch.cuda.synchronize()
         setup_s = time.perf_counter() - t0
         prob.iteration(1)
-        nn_search = prob.autotune(reps=2)[0]   # before the capture: the graph keeps the search shape
+        tune_nn(prob)   # before the capture: the graph keeps the search shape
+        nn_search = gp.gp_get_nn_params(prob.ctx)
         graph = GraphedIteration(prob)
         prob.init_sphere()
         torch.cuda.synchronize()
@@ -454,7 +455,7 @@ def surface_runs(iters: int = 1600, n_queries: int = 50_000):
         if normals is not None:
             prob.set_normals(normals, 1.0)
         prob.iteration(1)
-        prob.autotune(reps=2)
+        tune_nn(prob)
         graph = GraphedIteration(prob)
         prob.init_sphere()
         torch.cuda.synchronize()
