@@ -7,8 +7,9 @@
 //
 // A block takes a tile of 1024 queries and sorts them by the Morton code of
 // their cell; each wave cuts its quarter of the sorted list into groups of at
-// most 64 queries whose cells span at most 8 cells per axis and serves the
-// groups one at a time in two passes.
+// most 64 queries whose cells span fewer than group_span cells per axis
+// (default 8) and serves the groups one at a time in two passes.  Blocks take
+// their tiles in an XCD-aware order (xcd_work_item).
 //
 // Lockstep pass (lane = query): the box of the group's cells grown by one
 // cell.  Its rows (x, y) are laid out one per lane and cut into z-runs inside

@@ -6,11 +6,15 @@
 //   p = q - f grad f / |grad f|, the residual p - s to the query's nearest
 //   point s = NN(q) (Eq. 4), and at s: f(s) (Eq. 6) and grad f(s) for the
 //   cosine term (Eq. 7).  The forward writes per-tile sums (double); the
-//   backward recomputes the same quantities and scatters the adjoint into
-//   the 8 corners at q and the 8 corners at s with float atomics.
-// Vertex side, one block per brick: tau_i over the six axis neighbours that
-//   are TV vertices (Eq. 5) in the forward; in the backward the gradient is
-//   gathered per vertex (each vertex writes only its own slot).
+//   backward (fused with the forward in k_query_grad) takes the adjoint of
+//   the same quantities and adds it to the 8 corners at q and the 8 corners
+//   at s: summed per block in LDS (fixed point; a dense window over the
+//   block's vertex box, or LDS copies of the octants touched), then one
+//   float atomic per vertex.
+// Vertex side, per brick (a block, or a wave): tau_i over the six axis
+//   neighbours that are TV vertices (Eq. 5) in the forward; in the backward
+//   the gradient is gathered per vertex (each vertex writes only its own
+//   slot).
 #include <algorithm>
 
 #include "gp_internal.h"
