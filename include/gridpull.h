@@ -252,18 +252,32 @@ gp_status gp_pull_forward(gp_ctx ctx, const float* qx, const float* qy, const fl
                           gp_weights w, double* loss_out, int64_t* n_valid_out);
 
 /*
+ * Token of the last forward (gp_pull_forward or gp_pull_forward_backward) on
+ * this context, or 0 if there is none or it is no longer usable: a later call
+ * of this library that writes its query, nearest-point or field array
+ * (gp_sample_queries, gp_nn_query, gp_autotune_nn, gp_step, gp_init_sphere,
+ * gp_gather_vertices) or rebuilds the band makes it 0.  Take it right after
+ * the forward and hand it to the gp_pull_backward that differentiates it.
+ * Writes the caller makes itself (a copy into the field) are not seen.
+ */
+uint64_t gp_forward_token(gp_ctx ctx);
+
+/*
  * Backward pass: grad[slot] += sum_s dloss[s] * dL_s / dD[slot] for every
  * optimised vertex, with the L of gp_pull_forward, through trilinear
  * interpolation, the analytic gradient and its normalisation (derivative 0
  * where |grad f| < 1e-12 and where the residual p - s is 0; d|f_s| = sign f_s).
- * Must follow a gp_pull_forward on the same queries and field (it reuses
- * that call's valid counts and tau); else GP_ERR_STATE.
+ * It reuses the valid counts and tau of the forward it differentiates, so it
+ * must name that forward: forward_token is gp_forward_token() taken after
+ * it, and qx, qy, qz, nn, field are the arrays it read.  GP_ERR_STATE if the
+ * token is 0 or not the current one (another forward ran since, or one of
+ * those arrays was written by the library), or if the arrays differ.
  * dloss: device double [n_shapes] upstream scale (1 for plain optimisation).
  * grad:  device float32 [n_slots], accumulated into.
  */
 gp_status gp_pull_backward(gp_ctx ctx, const float* qx, const float* qy, const float* qz,
                            const int32_t* nn, int64_t n_queries, const float* field,
-                           gp_weights w, const double* dloss, float* grad);
+                           gp_weights w, const double* dloss, float* grad, uint64_t forward_token);
 
 /*
  * Forward and backward in one pass over the queries (Eq. 4-8 and their

@@ -276,7 +276,7 @@ gp_status gp_build_band_impl(gp_ctx ctx, const gp_shape* shapes, int32_t n_shape
 {
     hipStream_t st = ctx->stream;
     ctx->built = false;
-    ctx->have_forward = false;
+    ctx->fwd_token = 0;
 
     // ---- host-side descriptors ------------------------------------------
     std::vector<ShapeDesc> hs(n_shapes);

@@ -74,6 +74,23 @@ gp_status check_queries(gp_ctx ctx, const void* a, const void* b, const void* c,
     return GP_OK;
 }
 
+// The forward that just ran on these arrays becomes the one a backward may follow.
+void record_forward(gp_ctx ctx, const void* qx, const void* qy, const void* qz, const void* nn, const void* field)
+{
+    ctx->fwd_token = ++ctx->token_counter;
+    const void* a[5] = {qx, qy, qz, nn, field};
+    for (int i = 0; i < 5; ++i) ctx->fwd_arrays[i] = a[i];
+}
+
+// A call of the library is about to write array p: a forward that read it is
+// no longer the state a backward may use.
+void invalidate_forward(gp_ctx ctx, const void* p)
+{
+    if (!p) return;
+    for (int i = 0; i < 5; ++i)
+        if (ctx->fwd_arrays[i] == p) ctx->fwd_token = 0;
+}
+
 }  // namespace
 
 extern "C" {
@@ -171,6 +188,7 @@ gp_status gp_build_band(gp_ctx ctx, const gp_shape* shapes, int32_t n_shapes, co
     }
     if (any_points && (!px || !py || !pz)) return gp_fail(ctx, GP_ERR_ARG, "null point array");
     if (hipSetDevice(ctx->device) != hipSuccess) return gp_fail(ctx, GP_ERR_DEVICE, "hipSetDevice failed");
+    ctx->fwd_token = 0;
     gp_status st = gp_build_band_impl(ctx, shapes, n_shapes, px, py, pz, m1, m2);
     if (st != GP_OK) {
         (void)hipStreamSynchronize(ctx->stream);
@@ -188,6 +206,7 @@ gp_status gp_nn_query(gp_ctx ctx, const float* qx, const float* qy, const float*
     if (st != GP_OK) return st;
     if ((st = check_queries(ctx, qx, qy, qz, n_queries)) != GP_OK) return st;
     if (n_queries > 0 && !nn_out) return gp_fail(ctx, GP_ERR_ARG, "null nn_out");
+    invalidate_forward(ctx, nn_out);
     return gp_nn_impl(ctx, qx, qy, qz, nn_out);
 }
 
@@ -245,6 +264,7 @@ gp_status gp_autotune_nn(gp_ctx ctx, const float* qx, const float* qy, const flo
     if ((st = check_queries(ctx, qx, qy, qz, n_queries)) != GP_OK) return st;
     if (n_queries > 0 && !nn_out) return gp_fail(ctx, GP_ERR_ARG, "null nn_out");
     if (reps < 1 || reps > 100) return gp_fail(ctx, GP_ERR_ARG, "reps must be in [1, 100]");
+    invalidate_forward(ctx, nn_out);
     gp::NnParams best;
     float ms = -1.f;
     if ((st = gp_autotune_nn_impl(ctx, qx, qy, qz, nn_out, reps, &best, &ms)) != GP_OK) return st;
@@ -260,6 +280,9 @@ gp_status gp_sample_queries(gp_ctx ctx, uint64_t seed, int32_t iteration, const 
     if (st != GP_OK) return st;
     if (ctx->n_queries > 0 && (!qx || !qy || !qz)) return gp_fail(ctx, GP_ERR_ARG, "null query array");
     if (!sigma && !(sigma_const >= 0.f)) return gp_fail(ctx, GP_ERR_ARG, "sigma_const must be >= 0");
+    invalidate_forward(ctx, qx);
+    invalidate_forward(ctx, qy);
+    invalidate_forward(ctx, qz);
     return gp_sample_impl(ctx, seed, iteration, sigma, sigma_const, qx, qy, qz, src_out);
 }
 
@@ -272,16 +295,33 @@ gp_status gp_pull_forward(gp_ctx ctx, const float* qx, const float* qy, const fl
     if ((st = check_queries(ctx, qx, qy, qz, n_queries)) != GP_OK) return st;
     if ((n_queries > 0 && !nn) || !field || !loss_out || !n_valid_out)
         return gp_fail(ctx, GP_ERR_ARG, "null argument");
-    return gp_forward_impl(ctx, qx, qy, qz, nn, field, w, loss_out, n_valid_out);
+    if ((st = gp_forward_impl(ctx, qx, qy, qz, nn, field, w, loss_out, n_valid_out)) != GP_OK) return st;
+    record_forward(ctx, qx, qy, qz, nn, field);
+    return GP_OK;
+}
+
+uint64_t gp_forward_token(gp_ctx ctx)
+{
+    return ctx ? ctx->fwd_token : 0;
 }
 
 gp_status gp_pull_backward(gp_ctx ctx, const float* qx, const float* qy, const float* qz, const int32_t* nn,
-                           int64_t n_queries, const float* field, gp_weights w, const double* dloss, float* grad)
+                           int64_t n_queries, const float* field, gp_weights w, const double* dloss, float* grad,
+                           uint64_t forward_token)
 {
     gp_status st = ready(ctx);
     if (st != GP_OK) return st;
-    if (!ctx->have_forward)
-        return gp_fail(ctx, GP_ERR_STATE, "gp_pull_backward needs a preceding gp_pull_forward");
+    if (ctx->fwd_token == 0)
+        return gp_fail(ctx, GP_ERR_STATE, "gp_pull_backward needs a preceding gp_pull_forward whose queries, "
+                                          "nearest points and field have not been written since");
+    if (forward_token != ctx->fwd_token)
+        return gp_fail(ctx, GP_ERR_STATE, "forward_token names another forward than the last one");
+    {
+        const void* a[5] = {qx, qy, qz, nn, field};
+        for (int i = 0; i < 5; ++i)
+            if (a[i] != ctx->fwd_arrays[i])
+                return gp_fail(ctx, GP_ERR_STATE, "gp_pull_backward must see the arrays of its forward");
+    }
     if ((st = check_queries(ctx, qx, qy, qz, n_queries)) != GP_OK) return st;
     if ((n_queries > 0 && !nn) || !field || !dloss || !grad) return gp_fail(ctx, GP_ERR_ARG, "null argument");
     return gp_backward_impl(ctx, qx, qy, qz, nn, field, w, dloss, grad);
@@ -296,7 +336,10 @@ gp_status gp_pull_forward_backward(gp_ctx ctx, const float* qx, const float* qy,
     if ((st = check_queries(ctx, qx, qy, qz, n_queries)) != GP_OK) return st;
     if ((n_queries > 0 && !nn) || !field || !dloss || !loss_out || !n_valid_out || !grad)
         return gp_fail(ctx, GP_ERR_ARG, "null argument");
-    return gp_forward_backward_impl(ctx, qx, qy, qz, nn, field, w, dloss, loss_out, n_valid_out, grad);
+    if ((st = gp_forward_backward_impl(ctx, qx, qy, qz, nn, field, w, dloss, loss_out, n_valid_out, grad)) != GP_OK)
+        return st;
+    record_forward(ctx, qx, qy, qz, nn, field);
+    return GP_OK;
 }
 
 gp_status gp_pull_normals(gp_ctx ctx, const float* qx, const float* qy, const float* qz, const int32_t* nn,
@@ -321,6 +364,7 @@ gp_status gp_step(gp_ctx ctx, float* field, float* grad, float* m, float* v, int
     if (t < 0 || decay_every < 1) return gp_fail(ctx, GP_ERR_ARG, "need t >= 0 and decay_every >= 1");
     if (!(beta1 >= 0.f && beta1 < 1.f) || !(beta2 >= 0.f && beta2 < 1.f) || !(eps >= 0.f))
         return gp_fail(ctx, GP_ERR_ARG, "need 0 <= beta < 1 and eps >= 0");
+    invalidate_forward(ctx, field);
     if ((st = gp_step_consts_impl(ctx, t, lr0, decay, decay_every, beta1, beta2)) != GP_OK) return st;
     return gp_step_impl(ctx, field, grad, m, v, beta1, beta2, eps);
 }
@@ -407,6 +451,7 @@ gp_status gp_gather_vertices(gp_ctx ctx, const float* dense, float* field)
     gp_status st = ready(ctx);
     if (st != GP_OK) return st;
     if (!dense || !field) return gp_fail(ctx, GP_ERR_ARG, "null argument");
+    invalidate_forward(ctx, field);
     return gp_gather_impl(ctx, dense, field, true);
 }
 
@@ -423,6 +468,7 @@ gp_status gp_init_sphere(gp_ctx ctx, const double* centre, const double* radius,
     gp_status st = ready(ctx);
     if (st != GP_OK) return st;
     if (!centre || !radius || !field) return gp_fail(ctx, GP_ERR_ARG, "null argument");
+    invalidate_forward(ctx, field);
     return gp_init_sphere_impl(ctx, centre, radius, field);
 }
 

@@ -340,7 +340,13 @@ struct gp_ctx_s {
     DevBuf<int32_t> iter;         // device-resident iteration counter (last Adam t)
     DevBuf<float> step_c;         // [2] lr_t / (1 - beta1^t), 1 / sqrt(1 - beta2^t)
     DevBuf<float> g_raw;          // [n_slots] unscaled query contributions of a fused pass (kept zero between passes)
-    bool have_forward = false;
+    // The last forward (gp_pull_forward or gp_pull_forward_backward): its
+    // token (0 = none, or invalidated) and the arrays it read.  A backward
+    // must name that token and the same arrays; a later call of the library
+    // that writes one of those arrays, or rebuilds the band, invalidates it.
+    uint64_t token_counter = 0;
+    uint64_t fwd_token = 0;
+    const void* fwd_arrays[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};   // qx, qy, qz, nn, field
 
     gp::NnParams nn_params;       // set by gp_set_nn_params or gp_autotune_nn
     int32_t tv_layout = 0;        // 0 by band size, 1 block per brick, 2 wave per brick (gp_set_tv_layout)

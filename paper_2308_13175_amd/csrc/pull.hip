@@ -1065,7 +1065,6 @@ gp_status gp_forward_impl(gp_ctx ctx, const float* qx, const float* qy, const fl
         B, ctx->q_part.p, ctx->tv_part.p, w, loss_out, n_valid_out, ctx->inv_qv.p, ctx->flag.p, 1, ctx->fin_part.p,
         ctx->fin_count.p);
     GP_HIP(ctx, hipGetLastError());
-    ctx->have_forward = true;
     return GP_OK;
 }
 
@@ -1115,6 +1114,5 @@ gp_status gp_forward_backward_impl(gp_ctx ctx, const float* qx, const float* qy,
         launch_tv_backward(ctx, B, field, w, dloss, ctx->g_raw.p, grad, st);
     }
     GP_HIP(ctx, hipGetLastError());
-    ctx->have_forward = true;
     return GP_OK;
 }

@@ -197,13 +197,19 @@ class Problem:
                            self.qz[: self.n_queries], self.nn, f, self.weights, self.loss, self.n_valid)
         return self.loss
 
+    def forward_token(self) -> int:
+        """Token of the last forward on this context (0: none usable)."""
+        return gp.gp_forward_token(self.ctx)
+
     def backward(self, field: Optional[torch.Tensor] = None, grad: Optional[torch.Tensor] = None,
-                 dloss: Optional[torch.Tensor] = None):
+                 dloss: Optional[torch.Tensor] = None, token: Optional[int] = None):
+        """Adjoint of the forward named by token (default: the last one)."""
         f = self.field if field is None else field
         g = self.grad if grad is None else grad
         d = self.dloss if dloss is None else dloss
+        tok = self.forward_token() if token is None else token
         gp.gp_pull_backward(self.ctx, self.qx[: self.n_queries], self.qy[: self.n_queries],
-                            self.qz[: self.n_queries], self.nn, f, self.weights, d, g)
+                            self.qz[: self.n_queries], self.nn, f, self.weights, d, g, tok)
         return g
 
     def forward_backward(self, field: Optional[torch.Tensor] = None, grad: Optional[torch.Tensor] = None,
@@ -255,13 +261,18 @@ class PullLoss(torch.autograd.Function):
     """Per-shape total loss L (Eq. 8) as a differentiable function of the field.
 
     forward runs gp_pull_forward, backward runs the hand-written adjoint
-    gp_pull_backward with the incoming gradient as the per-shape scale.
+    gp_pull_backward with the incoming gradient as the per-shape scale.  The
+    forward's token goes with the graph node: if another forward on the same
+    problem, or a library call that rewrote its queries, nearest points or
+    field, came in between, the backward raises (GP_ERR_STATE) instead of
+    using that state.
     """
 
     @staticmethod
     def forward(ctx, field: torch.Tensor, problem: Problem):
         loss = problem.forward(field.detach())
         ctx.problem = problem
+        ctx.token = problem.forward_token()
         ctx.save_for_backward(field)
         return loss[:, 0].clone()
 
@@ -269,7 +280,7 @@ class PullLoss(torch.autograd.Function):
     def backward(ctx, grad_total: torch.Tensor):
         (field,) = ctx.saved_tensors
         g = torch.zeros_like(field)
-        ctx.problem.backward(field.detach(), g, grad_total.detach().to(torch.float64).contiguous())
+        ctx.problem.backward(field.detach(), g, grad_total.detach().to(torch.float64).contiguous(), ctx.token)
         return g, None
 
 

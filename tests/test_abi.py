@@ -13,7 +13,7 @@ LIB = os.path.join(ROOT, "paper_2308_13175_amd", "libgridpull.so")
 
 def _declared():
     text = open(HEADER).read()
-    return re.findall(r"^(?:gp_status|void|const char\*)\s+(gp_\w+)\(", text, re.M)
+    return re.findall(r"^(?:gp_status|void|const char\*|uint64_t)\s+(gp_\w+)\(", text, re.M)
 
 
 def test_header_declares_the_abi():
@@ -102,14 +102,35 @@ def test_state_and_argument_errors():
         nv = torch.zeros(1, dtype=torch.int64, device="cuda")
         dl = torch.ones(1, dtype=torch.float64, device="cuda")
         with pytest.raises(gp.GridPullError) as e:
-            gp.gp_pull_backward(ctx, q, q, q, nn, field, (1, 1, 0.005), dl, field)
+            gp.gp_pull_backward(ctx, q, q, q, nn, field, (1, 1, 0.005), dl, field, 0)
         assert e.value.status == 6            # backward before forward
+        assert gp.gp_forward_token(ctx) == 0
+        # the token: only the last forward, on the arrays it read, unwritten since
+        qq = torch.tensor([0.1, 0.5, 0.1, 0.5], device="cuda")
+        gp.gp_nn_query(ctx, qq, qq, qq, nn)
+        grad = torch.zeros_like(field)
+        gp.gp_pull_forward(ctx, qq, qq, qq, nn, field, (1, 1, 0.005), loss, nv)
+        t1 = gp.gp_forward_token(ctx)
+        assert t1 != 0
+        gp.gp_pull_backward(ctx, qq, qq, qq, nn, field, (1, 1, 0.005), dl, grad, t1)
+        gp.gp_pull_forward(ctx, qq, qq, qq, nn, field, (1, 1, 0.005), loss, nv)
+        t2 = gp.gp_forward_token(ctx)
+        assert t2 not in (0, t1)
+        for args, tok in (((qq, qq, qq, nn, field), t1),                 # an older forward
+                          ((qq, qq, qq, nn, field.clone()), t2)):        # another field array
+            with pytest.raises(gp.GridPullError) as e:
+                gp.gp_pull_backward(ctx, *args, (1, 1, 0.005), dl, grad, tok)
+            assert e.value.status == 6
+        gp.gp_nn_query(ctx, qq, qq, qq, nn)                               # rewrites the forward's nn
+        assert gp.gp_forward_token(ctx) == 0
+        with pytest.raises(gp.GridPullError) as e:
+            gp.gp_pull_backward(ctx, qq, qq, qq, nn, field, (1, 1, 0.005), dl, grad, t2)
+        assert e.value.status == 6
         q3 = torch.zeros(3, device="cuda")
         with pytest.raises(gp.GridPullError) as e:
             gp.gp_pull_forward(ctx, q3, q3, q3, nn, field, (1, 1, 0.005), loss, nv)
         assert e.value.status == 1            # wrong query count
         # an out-of-range nearest index is reported by the next sync
-        qq = torch.tensor([0.1, 0.5, 0.1, 0.5], device="cuda")
         bad_nn = torch.tensor([7, 0, 0, 1], dtype=torch.int32, device="cuda")
         gp.gp_pull_forward(ctx, qq, qq, qq, bad_nn, field, (1, 1, 0.005), loss, nv)
         with pytest.raises(gp.GridPullError) as e:

@@ -7,7 +7,7 @@ import pytest
 
 import oracle
 from paper_2308_13175_amd import synth
-from helpers import log, make_problem, spec
+from helpers import assert_grad_close, log, make_problem, spec
 
 pytestmark = pytest.mark.gpu
 
@@ -143,26 +143,56 @@ def test_free_running_trajectory():
     prob.close()
 
 
-def test_autograd_wrapper_matches_backward():
+def test_autograd_wrapper_matches_backward_and_oracle():
+    """The torch.autograd.Function's gradient against the oracle's dL/dD
+    (Eq. 4-8 differentiated) and against a direct backward; a backward whose
+    forward state was replaced raises instead of using it."""
     import torch
 
+    from paper_2308_13175_amd import gridpull as gp
     from paper_2308_13175_amd.problem import pull_loss
 
     log("case: autograd")
     dom = synth.cube_domain(32)
     pts = synth.sphere_points(3000, 0.5, seed=1)
     prob = make_problem([spec(pts, dom, 9000, 0.04)])
-    prob.set_dense_field([synth.sphere_sdf_field(dom, 0.5, noise=0.02, seed=1)])
+    D = synth.sphere_sdf_field(dom, 0.5, noise=0.02, seed=1)
+    prob.set_dense_field([D])
     prob.sample(seed=3, iteration=1)
     prob.nearest()
     field = prob.field.clone().requires_grad_(True)
     loss = pull_loss(field, prob)
     (2.5 * loss.sum()).backward()
+    # against the oracle, on the same queries and nearest points
+    q = prob.queries()
+    nn = prob.nn[: prob.n_queries].cpu().numpy()
+    assert np.array_equal(nn, oracle.nn_bruteforce(q, pts))
+    cf, vf = oracle.build_band(dom.dims, dom.lo, dom.hi, pts, 3, 3)
+    ref = oracle.loss_grad(dom.dims, dom.lo, dom.hi, cf, vf, D.astype(np.float64), q, nn, pts)
+    assert abs(float(loss[0].detach()) - ref["total"]) <= 1e-5 * abs(ref["total"])
+    dense = torch.zeros(dom.n_vertices, dtype=torch.float32, device="cuda")
+    gp.gp_scatter_vertices(prob.ctx, field.grad, dense)
+    assert_grad_close(dense.cpu().numpy(), 2.5 * ref["dD"])
+    # against a direct backward of the same forward
     prob.forward(field.detach())
     direct = torch.zeros_like(prob.field)
     prob.backward(field.detach(), direct, torch.full((1,), 2.5, dtype=torch.float64, device="cuda"))
     assert float((field.grad - direct).abs().max()) <= 1e-6 * float(direct.abs().max())
     assert abs(float(loss[0].detach()) - float(prob.loss[0, 0])) <= 1e-12 * abs(float(loss[0].detach()))
+    # stale state: another forward between the wrapper's forward and its backward
+    f2 = prob.field.clone().requires_grad_(True)
+    loss2 = pull_loss(f2, prob)
+    prob.forward(prob.field * 1.5)
+    with pytest.raises(gp.GridPullError) as e:
+        loss2.sum().backward()
+    assert e.value.status == 6
+    # ... or new queries sampled into the arrays the forward read
+    f3 = prob.field.clone().requires_grad_(True)
+    loss3 = pull_loss(f3, prob)
+    prob.sample(seed=3, iteration=2)
+    with pytest.raises(gp.GridPullError) as e:
+        loss3.sum().backward()
+    assert e.value.status == 6
     prob.close()
 
 

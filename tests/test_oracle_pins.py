@@ -607,3 +607,142 @@ def test_normal_term_gradient_matches_central_differences():
         tm = oracle.normal_term(dims, lo, hi, cf, Dm, q, nn, pts, nrm, with_grad=False)[0]
         fd = w * (tp - tm) / (2 * hstep)
         assert abs(fd - G[v]) <= 1e-6 * gmax + 1e-9, (v, fd, G[v])
+
+
+# ---------------------------------------------------------------------------
+# nn_exact (k-d tree candidates, exact re-rank, brute force where unsafe)
+# against the brute force on the cases its margin logic must get right
+# ---------------------------------------------------------------------------
+
+def _nn_cases():
+    rng = np.random.default_rng(41)
+    cases = {}
+    # J >> k: a random cloud, queries near and far from it
+    pts = rng.uniform(-1, 1, size=(4000, 3)).astype(np.float32)
+    q = np.concatenate([pts[rng.integers(0, 4000, 1500)] + rng.normal(0, 0.01, (1500, 3)),
+                        rng.uniform(-3, 3, (500, 3))]).astype(np.float32)
+    cases["random_J4000"] = (q, pts, 16)
+    # every point repeated 24 times (more copies than candidates): the
+    # lowest index of the copies must win, which lies beyond the k-th candidate
+    base = rng.uniform(-1, 1, size=(60, 3)).astype(np.float32)
+    dup = np.repeat(base, 24, axis=0)
+    perm = rng.permutation(len(dup))
+    cases["duplicates_beyond_k"] = (base[rng.integers(0, 60, 800)] + rng.normal(0, 0.02, (800, 3)).astype(np.float32),
+                                    dup[perm], 16)
+    # a lattice with queries at cell centres: 8 equidistant lattice points
+    g = np.arange(6, dtype=np.float32) * np.float32(0.25)
+    lat = np.stack(np.meshgrid(g, g, g, indexing="ij"), -1).reshape(-1, 3)
+    lat = lat[rng.permutation(len(lat))]
+    centres = (np.stack(np.meshgrid(g[:-1], g[:-1], g[:-1], indexing="ij"), -1).reshape(-1, 3)
+               + np.float32(0.125)).astype(np.float32)
+    cases["lattice_8way_ties"] = (centres, lat, 16)
+    # the best distance shared by 30 points around each query (the
+    # permutations and signs of (1, 2, 2) and (0, 0, 3) times 2^-6, all at
+    # distance 3 * 2^-6; query coordinates are multiples of 2^-10 and at
+    # least 0.25 apart, so every
+    # coordinate and distance is exact), so the 16th candidate ties the best
+    cells = rng.choice(64, size=40, replace=False)
+    qs = (np.stack([cells // 16, (cells // 4) % 4, cells % 4], 1) * 0.25 - 0.375 +
+          rng.integers(0, 64, size=(40, 3)) / 1024.0).astype(np.float32)   # 0.25 apart at least
+    offs = set()
+    for base in ((1, 2, 2), (0, 0, 3)):
+        for perm in ((0, 1, 2), (0, 2, 1), (1, 0, 2), (1, 2, 0), (2, 0, 1), (2, 1, 0)):
+            for sg in range(8):
+                v = tuple(base[perm[a]] * (-1 if (sg >> a) & 1 else 1) for a in range(3))
+                offs.add(v)
+    offs = np.array(sorted(offs), np.float64) / 64.0
+    assert len(offs) == 30
+    ring = (qs[:, None, :].astype(np.float64) + offs[None, :, :]).reshape(-1, 3).astype(np.float32)
+    far = rng.uniform(2, 3, size=(500, 3)).astype(np.float32)
+    cases["kth_candidate_ties_best"] = (qs, np.concatenate([far, ring[rng.permutation(len(ring))]]), 16)
+    # k = 1: the tree's single candidate is always re-checked
+    cases["k1"] = (q[:600], pts, 1)
+    return cases
+
+
+@pytest.mark.parametrize("name", list(_nn_cases().keys()))
+def test_nn_exact_matches_bruteforce(name):
+    q, pts, k = _nn_cases()[name]
+    ref = oracle.nn_bruteforce(q, pts)
+    got = oracle.nn_exact(q, pts, k=k, workers=1)
+    assert np.array_equal(got, ref), (name, np.nonzero(got != ref)[0][:10])
+    if name == "kth_candidate_ties_best":
+        # each query's answer is the lowest index among its 30 equidistant points
+        qd = q.astype(np.float64)
+        pd = pts.astype(np.float64)
+        for i in range(len(q)):
+            d2 = ((qd[i, 0] - pd[:, 0]) ** 2 + (qd[i, 1] - pd[:, 1]) ** 2) + (qd[i, 2] - pd[:, 2]) ** 2
+            tied = np.nonzero(d2 == d2.min())[0]
+            assert len(tied) == 30 and got[i] == tied.min()
+
+
+# ---------------------------------------------------------------------------
+# A linear field of slope 2: every normalisation by |grad f| shows
+# ---------------------------------------------------------------------------
+
+def test_slope_two_field_pull_gradient_and_normal_terms():
+    """D = 2 (n.x + c): f(q) = 2 dist(q), grad f = 2 n, and the normalised
+    gradient is n.  The pull (Eq. 4) moves q by f along the unit direction to
+    q - 2 dist n (not q - 4 dist n, as it would without the normalisation);
+    Eq. 7's cosine is 1 (not 4) so its term is 0; the normal term is 0, 2 and
+    1 for the normal n, -n and a perpendicular one (not 1 - 2 n.n_s)."""
+    dims, lo, hi, dom, n, c, D1, pts, q = _plane_setup(seed=12)
+    D = 2.0 * D1
+    cf, vf = oracle.build_band(dims, lo, hi, pts, 2, 2)
+    nn = oracle.nn_bruteforce(q, pts)
+    rng = np.random.default_rng(5)
+    for _ in range(20):
+        x = rng.uniform(-0.9, 0.9, 3)
+        f, g = oracle.eval_field(dims, lo, hi, D, x)
+        assert abs(f - 2.0 * (n @ x + c)) < 1e-12
+        assert np.max(np.abs(g - 2.0 * n)) < 1e-11
+    out = oracle.loss_grad(dims, lo, hi, cf, vf, D, q, nn, pts, want_grad=True, per_query=True)
+    pq = out["per_query"]
+    valid = pq[:, 3] > 0
+    assert valid.sum() > 1000
+    qd = q.astype(np.float64)[valid]
+    s = pts[nn].astype(np.float64)[valid]
+    dist = qd @ n + c
+    p = qd - 2.0 * dist[:, None] * n[None, :]
+    assert np.max(np.abs(pq[valid, 0] - np.linalg.norm(p - s, axis=1))) < 1e-9
+    assert np.max(np.abs(pq[valid, 1] - np.abs(2.0 * (s @ n + c)))) < 1e-12
+    assert np.max(np.abs(pq[valid, 2])) < 1e-12
+    # the loss is a mean of the per-query values over the valid queries
+    assert abs(out["pull"] - pq[valid, 0].mean()) < 1e-12
+    perp = np.cross(n, [0.0, 0.0, 1.0])
+    perp /= np.linalg.norm(perp)
+    for normal, expect in [(n, 0.0), (-n, 2.0), (perp, 1.0)]:
+        nrm = np.tile(normal.astype(np.float32), (len(pts), 1))
+        term, grad, nv = oracle.normal_term(dims, lo, hi, cf, D, q, nn, pts, nrm)
+        assert nv == valid.sum()
+        assert abs(term - expect) < 1e-6, (normal, term)
+        if expect == 0.0:
+            assert np.abs(grad).max() < 1e-6
+
+
+def test_slope_two_field_adjoint_matches_central_differences():
+    """The adjoint of the normalised pull on the slope-2 field: central
+    differences of the oracle's own loss at vertices of the band.  The points
+    sit 0.01 off the plane, so that |f(s)| has no kink within the step."""
+    dims, lo, hi, dom, n, c, D1, pts, q = _plane_setup(res=10, seed=13)
+    D = 2.0 * D1
+    pts = (pts.astype(np.float64) + 0.01 * n).astype(np.float32)
+    q = q[:400]
+    cf, vf = oracle.build_band(dims, lo, hi, pts, 2, 2)
+    nn = oracle.nn_bruteforce(q, pts)
+    out = oracle.loss_grad(dims, lo, hi, cf, vf, D, q, nn, pts)
+    G = out["dD"]
+    active = np.nonzero(vf & 1)[0]
+    rng = np.random.default_rng(3)
+    pick = np.concatenate([active[np.argsort(-np.abs(G[active]))[:25]], rng.choice(active, 25)])
+    hstep = 1e-6
+    gmax = np.abs(G).max()
+    for v in pick:
+        Dp = D.copy()
+        Dp[v] += hstep
+        Dm = D.copy()
+        Dm[v] -= hstep
+        lp = oracle.loss_grad(dims, lo, hi, cf, vf, Dp, q, nn, pts, want_grad=False)["total"]
+        lm = oracle.loss_grad(dims, lo, hi, cf, vf, Dm, q, nn, pts, want_grad=False)["total"]
+        fd = (lp - lm) / (2 * hstep)
+        assert abs(fd - G[v]) <= 2e-6 * gmax + 1e-9, (v, fd, G[v])
