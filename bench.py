@@ -1,21 +1,25 @@
 #!/usr/bin/env python
-"""Throughput of the GridPull optimisation iteration on one MI355X.
+"""Throughput of the GridPull pull step on one MI355X.
 
-One step = one full iteration of the hot path over one batch of synthetic
-queries: sample queries around the points, nearest surface point of every
-query, forward (pull, surface, gradient-consistency and TV terms), backward
-(hand-written adjoint scattered into the grid), Adam step.  The band and the
-point buckets are built once before timing (their build time is reported as
-setup_ms).
+The metric is pulled queries per second of the forward + backward pass (the
+pull, surface, gradient-consistency and TV terms of Eq. 4-8, their
+hand-written adjoint scattered into the grid, and the per-shape loss
+reduction), with the queries and their nearest surface points already
+resident in HBM: one step = one gp_pull_forward_backward over the whole batch
+of synthetic queries.  value = queries x steps / the timed region's wall
+time.  The roofline is that of the dominant kernel of the step (the fused
+query pass, k_query_grad), on its algorithmic bytes per launch: 16 B per query
+(q and its nearest-point index), 12 B per distinct nearest point, 12 B per
+optimised vertex (field read, gradient read and written), timed with HIP
+events on the library's stream during the timed region.
 
-value = queries pulled per second over whole iterations replayed as one
-captured hipGraph per iteration (the way a fixed-shape training loop runs;
-the iteration's device-resident counter advances the sampler and the Adam
-schedule on every replay).  The same iteration launched eagerly, with HIP
-events around every kernel (from which the roofline of the dominant kernel
-is computed), is reported next to it.  cpu_baseline times the FP64
-oracle (one thread) on a bounded sample of the same workload and scales it to
-the same unit.
+Beside it, the whole optimisation iteration (query sampling, nearest points,
+forward + backward, Adam), replayed as one captured hipGraph per iteration;
+per-kernel event times of that iteration; on the default workload, the 64
+uneven shapes of the batched workload in one launch sequence against one
+context per shape, at equal accuracy; and cpu_baseline, the FP64 oracle on one
+host thread on a bounded sample of the same workload, in the same unit.
+The band and the point buckets are built once before timing (setup_ms).
 """
 import argparse
 import json
@@ -225,8 +229,9 @@ def copy_calibration(mib=256, reps=3):
 def batched_vs_per_shape(wl, prob, steps, warmup, autotune=True):
     """The 64-shape batch: one batched launch sequence against one context per shape.
 
-    Times the same iteration (eager and as captured graphs) both ways, then
-    puts both in the same state (geometric initial field, the batched
+    Times the metric's step (forward + backward on resident queries and
+    nearest points) and the whole iteration (as captured graphs) both ways,
+    then puts both in the same state (geometric initial field, the batched
     queries) and compares nearest neighbours, loss terms and gradients.
     """
     import numpy as np
@@ -239,33 +244,47 @@ def batched_vs_per_shape(wl, prob, steps, warmup, autotune=True):
     for p in singles:
         p.init_sphere()
     torch.cuda.synchronize()
-
-    def run_eager(n):
-        for _ in range(n):
-            for p in singles:
-                p.iteration(None)
-
-    run_eager(warmup)
+    for _ in range(warmup):
+        for p in singles:
+            p.iteration(None)
     if autotune:
         for p in singles:
             p.autotune(reps=1)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    run_eager(steps)
-    torch.cuda.synchronize()
-    eager_s = (time.perf_counter() - t0) / steps
-    graphs = [GraphedIteration(p) for p in singles]
-    for _ in range(warmup):
-        for g in graphs:
-            g.replay()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        for g in graphs:
-            g.replay()
-    torch.cuda.synchronize()
-    graph_s = (time.perf_counter() - t0) / steps
-    del graphs
+    for p in singles:
+        p.iteration(None)
+    # the metric's step, both ways (each side on its own resident queries)
+    def time_fb(probs):
+        for _ in range(warmup):
+            for p in probs:
+                p.forward_backward()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            for p in probs:
+                p.forward_backward()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / steps
+
+    fb_single_s = time_fb(singles)
+    fb_batch_s = time_fb([prob])
+    # whole iterations as captured graphs, both ways
+    def time_graphs(probs):
+        graphs = [GraphedIteration(p) for p in probs]
+        for _ in range(warmup):
+            for g in graphs:
+                g.replay()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            for g in graphs:
+                g.replay()
+        torch.cuda.synchronize()
+        el = (time.perf_counter() - t0) / steps
+        del graphs
+        return el
+
+    it_single_s = time_graphs(singles)
+    it_batch_s = time_graphs([prob])
 
     # same state both ways: initial field, the batched problem's queries
     prob.init_sphere()
@@ -276,14 +295,13 @@ def batched_vs_per_shape(wl, prob, steps, warmup, autotune=True):
     prob.grad.zero_()
     prob.forward()
     prob.backward()
-    off = 0
     sizes = [int(np.prod(np.asarray(sp.dims, np.int64) + 1)) for sp in prob.specs]
     dense_b = torch.zeros(sum(sizes), dtype=torch.float32, device=prob.device)
     gp.gp_scatter_vertices(prob.ctx, prob.grad, dense_b)
     loss_b = prob.loss.cpu().numpy()
     nn_equal = True
     worst_loss, worst_grad = 0.0, 0.0
-    doff = 0
+    off = doff = 0
     for i, p in enumerate(singles):
         n = p.n_queries
         p.qx[:n].copy_(prob.qx[off:off + n])
@@ -306,10 +324,36 @@ def batched_vs_per_shape(wl, prob, steps, warmup, autotune=True):
         off += n
         doff += sizes[i]
         p.close()
-    return {"per_shape_queries_per_s": prob.n_queries / eager_s, "per_shape_ms_per_step": eager_s * 1e3,
-            "per_shape_graph_queries_per_s": prob.n_queries / graph_s, "per_shape_graph_ms_per_step": graph_s * 1e3,
-            "nn_identical": nn_equal, "max_rel_err_loss_terms": worst_loss,
-            "max_rel_err_grad": worst_grad, "shapes": len(singles)}
+    Q = prob.n_queries
+    return {"workload": wl.name, "shapes": len(singles), "queries_per_step": Q,
+            "fwd_bwd": {"batched_queries_per_s": Q / fb_batch_s, "per_shape_queries_per_s": Q / fb_single_s,
+                        "batched_ms": fb_batch_s * 1e3, "per_shape_ms": fb_single_s * 1e3,
+                        "speedup": fb_single_s / fb_batch_s},
+            "iteration_graph": {"batched_queries_per_s": Q / it_batch_s, "per_shape_queries_per_s": Q / it_single_s,
+                                "batched_ms": it_batch_s * 1e3, "per_shape_ms": it_single_s * 1e3,
+                                "speedup": it_single_s / it_batch_s},
+            "nn_identical": nn_equal, "max_rel_err_loss_terms": worst_loss, "max_rel_err_grad": worst_grad}
+
+
+def batched_record(args):
+    """Build the 64-shape batched workload and compare it against per-shape contexts."""
+    import torch
+
+    from paper_2308_13175_amd import gridpull as gp
+
+    wl, prob, setup_ms = build_problem(4)
+    for _ in range(args.warmup):
+        prob.iteration(None)
+    if not args.no_autotune:
+        tune_nn(prob)
+    prob.iteration(None)
+    rec = batched_vs_per_shape(wl, prob, max(3, args.steps // 5), 2, not args.no_autotune)
+    rec["setup_ms"] = setup_ms
+    rec["nn_search_shape"] = list(gp.gp_get_nn_params(prob.ctx))
+    prob.close()
+    del prob
+    torch.cuda.empty_cache()
+    return rec
 
 
 def build_problem(config: int):
@@ -497,57 +541,101 @@ def surface_runs(iters: int = 1600, n_queries: int = 50_000):
         torch.cuda.empty_cache()
 
 
-def cpu_baseline(wl, budget_s: float = 16.0):
-    """The FP64 oracle on one host thread, on a bounded sample of the workload."""
+def _window(dom, pts, cells: int):
+    """A sub-grid of cells^3 cells of dom (same cell size and vertex lattice)
+    around the densest region of the points, and the points inside it."""
+    import numpy as np
+
+    from paper_2308_13175_amd import synth
+
+    R = np.asarray(dom.dims, np.int64)
+    if np.all(R <= cells):
+        return dom, pts
+    lo = np.asarray(dom.lo, np.float64)
+    h = np.asarray(dom.h, np.float64)
+    w = np.minimum(R, cells)
+    c = np.clip(np.floor((pts.astype(np.float64) - lo) / h), 0, R - 1).astype(np.int64)
+    # the coarse block (of the window's size) holding the most points
+    blk = c // w
+    nb = (R + w - 1) // w
+    ids, cnt = np.unique((blk[:, 0] * nb[1] + blk[:, 1]) * nb[2] + blk[:, 2], return_counts=True)
+    b = ids[np.argmax(cnt)]
+    b3 = np.array([b // (nb[1] * nb[2]), (b // nb[2]) % nb[1], b % nb[2]])
+    c0 = np.minimum(b3 * w, R - w)
+    wlo = lo + c0 * h
+    whi = lo + (c0 + w) * h
+    sub = synth.Domain(tuple(int(x) for x in w), tuple(float(x) for x in wlo), tuple(float(x) for x in whi))
+    inside = np.all((pts >= wlo.astype(np.float32)) & (pts <= whi.astype(np.float32)), axis=1)
+    return sub, pts[inside]
+
+
+def cpu_baseline(wl, v2_total: int, budget_s: float = 16.0, window_cells: int = 160):
+    """The FP64 oracle on one host thread, on a bounded sample of the workload,
+    in the metric's unit (forward + backward queries/s).
+
+    Shape 0 of the workload; a grid larger than window_cells^3 cells is cut to
+    a window of that many cells (same cell size) around its densest points.
+    The oracle's loss and gradient are timed on as many of the window's
+    queries as fit the budget, and its query-independent part (TV over the
+    band, gradient clear) once; both are scaled to the full workload: queries
+    per step, and v2_total TV vertices (the workload's band, counted on the
+    library's band, which equals the oracle's).  Brute-force nearest points and Adam are timed
+    too and reported beside it.
+    """
     import numpy as np
 
     import oracle
     from paper_2308_13175_amd import synth
 
     s = wl.shapes[0]
+    sub, pts = _window(s.domain, s.points, window_cells)
+    Q = wl.n_queries
+    frac_q = len(pts) / max(len(s.points), 1)
+    n_q = max(1000, int(min(s.n_queries * frac_q, 2_000_000)))
+    q_all = synth.host_queries(pts, n_q, s.sigma if np.ndim(s.sigma) == 0 else float(np.median(s.sigma)), seed=99)
+    t0 = time.perf_counter()
+    cf, vf = oracle.build_band(sub.dims, sub.lo, sub.hi, pts, wl.m1, wl.m2)
+    t_band = time.perf_counter() - t0
+    v2_window = int(np.count_nonzero(vf & 2))
+    # small-sphere initial field at the full domain's centre (its cost is what matters)
     dom = s.domain
-    pts = s.points
-    Q = s.n_queries
-    J = len(pts)
-    q_all = synth.host_queries(pts, min(Q, 2_000_000), s.sigma, seed=99)
-    cf, vf = oracle.build_band(dom.dims, dom.lo, dom.hi, pts, wl.m1, wl.m2)
-    pos = None
-    D = np.zeros(dom.n_vertices)
     ctr = [0.5 * (dom.lo[a] + dom.hi[a]) for a in range(3)]
-    # small-sphere initial field (only its cost matters here)
-    vx, vy, vz = dom.vdims
-    xs = dom.lo[0] + np.arange(vx) * dom.h[0] - ctr[0]
-    ys = dom.lo[1] + np.arange(vy) * dom.h[1] - ctr[1]
-    zs = dom.lo[2] + np.arange(vz) * dom.h[2] - ctr[2]
+    vx, vy, vz = sub.vdims
+    xs = sub.lo[0] + np.arange(vx) * sub.h[0] - ctr[0]
+    ys = sub.lo[1] + np.arange(vy) * sub.h[1] - ctr[1]
+    zs = sub.lo[2] + np.arange(vz) * sub.h[2] - ctr[2]
     D = (np.sqrt(xs[:, None, None] ** 2 + ys[None, :, None] ** 2 + zs[None, None, :] ** 2)
-         - 2 * min(dom.h)).reshape(-1)
-    # nearest neighbours: brute force on a query sample, scaled linearly
-    n_nn = 64
-    t0 = time.perf_counter()
-    oracle.nn_bruteforce(q_all[:n_nn], pts)
-    t = time.perf_counter() - t0
-    n_nn = int(max(64, min(len(q_all), n_nn * (0.5 * budget_s) / max(t, 1e-6))))
-    t0 = time.perf_counter()
-    nn_s = oracle.nn_bruteforce(q_all[:n_nn], pts)
-    t_nn_q = (time.perf_counter() - t0) / n_nn
-    # per-query loss/gradient work: the fixed part (TV, gradient clear) measured with no queries
+         - 2 * min(sub.h)).reshape(-1)
+    # the query-independent part: no queries
     empty = np.zeros((0, 3), np.float32)
     t0 = time.perf_counter()
-    oracle.loss_grad(dom.dims, dom.lo, dom.hi, cf, vf, D, empty, np.zeros(0, np.int32), pts)
+    oracle.loss_grad(sub.dims, sub.lo, sub.hi, cf, vf, D, empty, np.zeros(0, np.int32), pts)
     t_fixed = time.perf_counter() - t0
-    nq = min(len(q_all), 200_000)
-    nn_l = oracle.nn_exact(q_all[:nq], pts)
+    nn_l = oracle.nn_exact(q_all, pts)
+    # per-query part: as many queries as fit about half the budget
+    n = 2000
+    while True:
+        t0 = time.perf_counter()
+        oracle.loss_grad(sub.dims, sub.lo, sub.hi, cf, vf, D, q_all[:n], nn_l[:n], pts)
+        t = time.perf_counter() - t0 - t_fixed
+        if t > 0.25 * budget_s or n >= len(q_all):
+            break
+        n = min(len(q_all), int(n * max(2.0, 0.5 * budget_s / max(t, 1e-3))))
+    t_q = max(t, 0.0) / n
+    t_fb = Q * t_q + t_fixed * (v2_total / max(v2_window, 1))
+    # nearest points by brute force over all of shape 0's points, a few queries
+    full_q = synth.host_queries(s.points, 64, s.sigma if np.ndim(s.sigma) == 0 else float(np.median(s.sigma)),
+                                seed=98)
+    k = 4
     t0 = time.perf_counter()
-    oracle.loss_grad(dom.dims, dom.lo, dom.hi, cf, vf, D, q_all[:nq], nn_l, pts)
-    t_q = max(time.perf_counter() - t0 - t_fixed, 0.0) / nq
-    G = np.zeros(dom.n_vertices)
-    m = np.zeros(dom.n_vertices)
-    v = np.zeros(dom.n_vertices)
+    oracle.nn_bruteforce(full_q[:k], s.points)
+    t_nn = (time.perf_counter() - t0) / k
+    G = np.zeros(len(D))
+    m = np.zeros(len(D))
+    v = np.zeros(len(D))
     t0 = time.perf_counter()
     oracle.adam(D, G, m, v, vf, 1, 0.01)
     t_adam = time.perf_counter() - t0
-    t_iter = Q * (t_nn_q + t_q) + t_fixed + t_adam
-    Qtot = wl.n_queries
     model = ""
     try:
         with open("/proc/cpuinfo") as f:
@@ -558,17 +646,80 @@ def cpu_baseline(wl, budget_s: float = 16.0):
     except OSError:
         pass
     return {
-        "value": Qtot / (t_iter * Qtot / Q) if Q else 0.0,
+        "value": Q / t_fb if t_fb > 0 else 0.0,
         "unit": "queries/s",
         "cores": 1,
         "host_cpu": model,
         "host_threads": os.cpu_count(),
         "kind": "oracle",
-        "sample": ("FP64 oracle, 1 thread, shape 0 of %s: brute-force NN on %d queries + loss/gradient on %d "
-                   "queries, scaled linearly to %d queries per iteration, plus the band-wide TV/gradient clear "
-                   "and Adam over the full grid, measured once (NN %.3g s/query, loss %.3g s/query, fixed %.3g s, "
-                   "Adam %.3g s)" % (wl.name, n_nn, nq, Q, t_nn_q, t_q, t_fixed, t_adam)),
+        "sample": ("FP64 oracle, 1 thread, shape 0 of %s cut to a %s-cell window (%d points, band built in %.1f s): "
+                   "loss and gradient on %d queries (%.3g s/query) plus the query-independent TV and gradient "
+                   "clear over the window's %d TV vertices (%.3g s), scaled to %d queries per step and %.3g TV "
+                   "vertices" % (wl.name, "x".join(str(x) for x in sub.dims), len(pts), t_band, n, t_q,
+                                 v2_window, t_fixed, Q, float(v2_total))),
+        "nn_bruteforce_s_per_query": t_nn,
+        "nn_bruteforce_points": len(s.points),
+        "adam_s_per_vertex": t_adam / max(len(D), 1),
     }
+
+
+def timed_fwd_bwd(prob, steps: int):
+    """steps fused forward + backward passes on the resident queries and
+    nearest points, bracketed by device synchronisations; per-kernel HIP
+    events (on the library's stream) over the same region.  Returns (wall
+    seconds, {kernel: (launches, total ms)})."""
+    import torch
+
+    from paper_2308_13175_amd import gridpull as gp
+
+    gp.gp_timing_enable(prob.ctx, True)
+    gp.gp_timing_report(prob.ctx)          # a clean period
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        prob.forward_backward()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    kern = gp.gp_timing_report(prob.ctx)
+    gp.gp_timing_enable(prob.ctx, False)
+    return elapsed, kern
+
+
+def iteration_rate(prob, steps: int, warmup: int, graph: bool = True):
+    """Whole iterations (sample, NN, forward + backward, Adam): as captured
+    graph replays (or eager launches), then eager with per-kernel events."""
+    import torch
+
+    from paper_2308_13175_amd import gridpull as gp
+    from paper_2308_13175_amd.problem import GraphedIteration
+
+    out = {}
+    if graph:
+        g = GraphedIteration(prob)
+        for _ in range(warmup):
+            g.replay()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            g.replay()
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        prob.sync()
+        del g
+        out["graph"] = {"queries_per_s": prob.n_queries * steps / el, "ms_per_step": el * 1e3 / steps}
+    gp.gp_timing_enable(prob.ctx, True)
+    gp.gp_timing_report(prob.ctx)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        prob.iteration(None)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    kern = gp.gp_timing_report(prob.ctx)
+    gp.gp_timing_enable(prob.ctx, False)
+    out["eager"] = {"queries_per_s": prob.n_queries * steps / el, "ms_per_step": el * 1e3 / steps}
+    out["kernels_avg_ms"] = {k: round(ms / max(n, 1), 5) for k, (n, ms) in sorted(kern.items())}
+    return out
 
 
 def main():
@@ -576,10 +727,12 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--config", type=int, default=2, choices=[1, 2, 3, 4, 5],
-                    help="workload: 1 sphere-10k, 2 torus-200k (default), 3 union24-2M, 4 batched64, 5 room-20M")
+    ap.add_argument("--config", type=int, default=5, choices=[1, 2, 3, 4, 5],
+                    help="workload: 1 sphere-10k, 2 torus-200k, 3 union24-2M, 4 batched64, 5 room-20M (default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--no-batched", action="store_true",
+                    help="skip the 64-shape batched-vs-per-shape record on the room workload")
     ap.add_argument("--sweep", choices=["res", "m2", "m1"],
                     help="instead of the benchmark: whole runs on the paper's schedule, one JSON line per setting")
     ap.add_argument("--surface", action="store_true",
@@ -598,7 +751,6 @@ def main():
     import torch
 
     from paper_2308_13175_amd import gridpull as gp
-    from paper_2308_13175_amd.problem import GraphedIteration
 
     torch.cuda.set_device(0)
     if args.sweep:
@@ -609,7 +761,6 @@ def main():
         return
     wl, prob, setup_ms = build_problem(args.config)
     Q, J = prob.n_queries, prob.n_points
-    n_tv = None
     log("band: %d slots, %d optimised vertices, setup %.1f ms" % (prob.n_slots, prob.n_active, setup_ms))
 
     for _ in range(args.warmup):
@@ -617,91 +768,49 @@ def main():
     tuned_ms = None
     if not args.no_autotune:
         tuned_ms = tune_nn(prob)
-    nn_span, nn_shell, nn_parts, nn_skip, nn_sort = gp.gp_get_nn_params(prob.ctx)
-    log("NN search shape: group span %d, first shell %d, %d blocks per tile, skip empty %d, sort %d%s" % (
-        nn_span, nn_shell, nn_parts, nn_skip, nn_sort,
-        " (autotuned, %.3f ms)" % tuned_ms if tuned_ms is not None else ""))
-    torch.cuda.synchronize()
-    gp.gp_timing_enable(prob.ctx, True)
-    gp.gp_timing_report(prob.ctx)          # start a clean period
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        prob.iteration(None)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    kern = gp.gp_timing_report(prob.ctx)
-    gp.gp_timing_enable(prob.ctx, False)
+    nn_params = gp.gp_get_nn_params(prob.ctx)
+    log("NN search shape: %s%s" % (nn_params, " (autotuned, %.3f ms)" % tuned_ms if tuned_ms is not None else ""))
+    it = iteration_rate(prob, max(5, args.steps // 2), args.warmup, graph=not args.no_graph)
     prob.sync()
     loss = prob.loss.cpu().numpy()
-    n_valid = int(prob.n_valid.sum())
-    log("loss after %d iterations: %s, valid %d" % (args.warmup + args.steps, loss[0].tolist(), n_valid))
+    log("loss: %s, valid %d" % (loss[0].tolist(), int(prob.n_valid.sum())))
 
-    graph = None
-    if not args.no_graph:
-        graph = GraphedIteration(prob)
-        for _ in range(args.warmup):
-            graph.replay()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(args.steps):
-            graph.replay()
-        torch.cuda.synchronize()
-        g_elapsed = time.perf_counter() - t0
-        prob.sync()
-
+    # the metric's step: forward + backward over the resident queries and nearest points
+    for _ in range(args.warmup):
+        prob.forward_backward()
+    elapsed, kern = timed_fwd_bwd(prob, args.steps)
+    prob.sync()
     fb_median = fwd_bwd_median_ms(prob)
     copy_gbps = copy_bandwidth()
-    # TV vertex count for the byte model
     _, flags = prob.layout()
     V2 = int(((flags & 2) > 0).sum())
     V = prob.n_active
-    per_point_sigma = prob.sigma is not None
     avg = {k: (n, ms / max(n, 1)) for k, (n, ms) in kern.items()}
-    dom_k = max((k for k in avg if kernel_bytes(k, Q, J, V, V2, prob.n_slots, per_point_sigma) is not None),
-                key=lambda k: kern[k][1])
-    fb_ms = sum(avg[k][1] for k in ("k_forward_query", "k_query_grad", "k_tv_forward", "k_finalize",
-                                     "k_backward_query", "k_tv_backward") if k in avg)
-    fb_bytes = 16 * Q + 12 * min(Q, J) + 12 * V
     ms_step = elapsed * 1e3 / args.steps
-    if dom_k == "k_nn":
-        # ALU bound: distance tests an exact cell-bucket search must make
-        qs = prob.queries()
-        pairs, n_s = [], 0
-        off = 0
-        for sh in wl.shapes:
-            pr, n = nn_required_pairs(sh.points, sh.domain, qs[off:off + sh.n_queries],
-                                      n_sample=max(200, int(10000 * sh.n_queries / max(Q, 1))))
-            pairs.append(pr * sh.n_queries)
-            off += sh.n_queries
-        per_launch = NN_FLOPS_PER_PAIR * sum(pairs)
-        ach = per_launch / (avg[dom_k][1] * 1e-3) / 1e12
-        roof = {"bound": "alu", "kernel": dom_k, "achieved": ach, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": ach / FP32_PEAK_TFLOPS, "traffic": measured_traffic(dom_k, args.config),
-                "flops_per_launch": per_launch, "required_pairs_per_query": sum(pairs) / max(Q, 1),
-                "avg_launch_ms": avg[dom_k][1]}
-    else:
-        by = kernel_bytes(dom_k, Q, J, V, V2, prob.n_slots, per_point_sigma)
-        ach = by / (avg[dom_k][1] * 1e-3) / 1e9
-        roof = {"bound": "hbm", "kernel": dom_k, "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": ach / HBM_PEAK_GBS, "traffic": measured_traffic(dom_k, args.config),
-                "bytes_per_launch": by, "avg_launch_ms": avg[dom_k][1]}
+    fb_bytes = 16 * Q + 12 * min(Q, J) + 12 * V
+    dom_k = "k_query_grad"
+    by = kernel_bytes(dom_k, Q, J, V, V2, prob.n_slots, prob.sigma is not None)
+    ach = by / (avg[dom_k][1] * 1e-3) / 1e9
+    roof = {"bound": "hbm", "kernel": dom_k, "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": ach / HBM_PEAK_GBS, "traffic": measured_traffic(dom_k, args.config),
+            "bytes_per_launch": by, "bytes_model": "16 Q + 12 min(Q, J) + 12 V",
+            "avg_launch_ms": avg[dom_k][1]}
     kernels_hbm = {}
     for k in avg:
-        by = kernel_bytes(k, Q, J, V, V2, prob.n_slots, per_point_sigma)
-        if by is not None:
-            kernels_hbm[k] = {"bytes": by, "GBps": by / (avg[k][1] * 1e-3) / 1e9,
-                              "frac": by / (avg[k][1] * 1e-3) / 1e9 / HBM_PEAK_GBS}
-    eager_qps = Q * args.steps / elapsed
-    graph_qps = Q * args.steps / g_elapsed if graph is not None else None
+        b = kernel_bytes(k, Q, J, V, V2, prob.n_slots, prob.sigma is not None)
+        if b is not None:
+            kernels_hbm[k] = {"bytes": b, "GBps": b / (avg[k][1] * 1e-3) / 1e9,
+                              "frac": b / (avg[k][1] * 1e-3) / 1e9 / HBM_PEAK_GBS}
+    nn_ms = it["kernels_avg_ms"].get("k_nn")
+    value = Q * args.steps / elapsed
     out = {
         "metric": METRIC,
-        "value": graph_qps if graph_qps is not None else eager_qps,
+        "value": value,
         "unit": "queries/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": (g_elapsed * 1e3 / args.steps) if graph is not None else ms_step,
+        "ms_per_step": ms_step,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -710,38 +819,30 @@ def main():
         "config": {"workload": wl.name, "shapes": len(wl.shapes), "points": J, "queries_per_step": Q,
                    "grid": [list(s.domain.dims) for s in wl.shapes][:4], "m1": wl.m1, "m2": wl.m2,
                    "slots": prob.n_slots, "optimised_vertices": V, "tv_vertices": V2,
-                   "step": "sample+nn+forward+backward+adam"},
+                   "step": "forward+backward (gp_pull_forward_backward) on resident queries and nearest points"},
         "roofline": roof,
-        "nn_search": {"group_span": nn_span, "first_shell": nn_shell, "tile_parts": nn_parts, "skip_empty": nn_skip,
-                      "morton_sort": nn_sort,
-                      "autotuned": tuned_ms is not None,
-                      "autotune_best_ms": tuned_ms},
-        "fwd_bwd": {"queries_per_s": Q / (fb_ms * 1e-3), "ms": fb_ms, "median_ms": fb_median,
-                    "algorithmic_GBps": fb_bytes / (fb_ms * 1e-3) / 1e9,
-                    "hbm_frac": fb_bytes / (fb_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
-                    "copy_frac": fb_bytes / (fb_ms * 1e-3) / 1e9 / copy_gbps},
+        "fwd_bwd": {"queries_per_s": value, "ms": ms_step, "median_ms": fb_median,
+                    "kernels_ms": {k: round(v[1], 5) for k, v in sorted(avg.items())},
+                    "algorithmic_bytes": fb_bytes,
+                    "algorithmic_GBps": fb_bytes / (ms_step * 1e-3) / 1e9,
+                    "hbm_frac": fb_bytes / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                    "copy_frac": fb_bytes / (ms_step * 1e-3) / 1e9 / copy_gbps},
+        "iteration": {"step": "sample+nn+forward+backward+adam", **it},
+        "nn": {"queries_per_s": Q / (nn_ms * 1e-3) if nn_ms else None, "ms": nn_ms,
+               "search_shape": list(nn_params), "autotuned": tuned_ms is not None, "autotune_best_ms": tuned_ms},
         "copy_GBps": copy_gbps,
-        "kernels_avg_ms": {k: round(v[1], 5) for k, v in sorted(avg.items())},
         "kernels_hbm": kernels_hbm,
         "setup_ms": setup_ms,
     }
-    out["timed"] = "graph replay" if graph is not None else "eager launches"
-    out["eager"] = {"queries_per_s": eager_qps, "ms_per_step": ms_step}
-    if graph is not None:
-        out["graph"] = {"queries_per_s": graph_qps, "ms_per_step": g_elapsed * 1e3 / args.steps}
-    if args.config == 4:
-        cmp = batched_vs_per_shape(wl, prob, max(3, args.steps // 5), 2, not args.no_autotune)
-        cmp["batched_queries_per_s"] = eager_qps
-        if graph is not None:
-            cmp["batched_graph_queries_per_s"] = graph_qps
-            cmp["speedup_graph"] = graph_qps / cmp["per_shape_graph_queries_per_s"]
-        cmp["speedup_eager"] = eager_qps / cmp["per_shape_queries_per_s"]
-        out["batched_vs_per_shape"] = cmp
+    prob.close()
+    del prob
+    torch.cuda.empty_cache()
+    if args.config == 4 or (args.config == 5 and not args.no_batched):
+        out["batched_vs_per_shape"] = batched_record(args)
     if not args.no_cpu_baseline:
         t0 = time.perf_counter()
-        out["cpu_baseline"] = cpu_baseline(wl)
+        out["cpu_baseline"] = cpu_baseline(wl, V2)
         log("cpu baseline took %.1f s" % (time.perf_counter() - t0))
-    prob.close()
     if args.copy_calibration:
         copy_calibration()
     print(json.dumps(out), flush=True)

@@ -140,6 +140,49 @@ __global__ void k_brick_active(const uint8_t* __restrict__ verts, ShapeDesc s, i
     }
 }
 
+// Bricks are numbered along a Morton curve of their coordinates, so that
+// bricks with neighbouring numbers are neighbours in space.  Everything that
+// runs over bricks, or over points and queries in brick order (the points are
+// sorted by slot, the sampler's sources follow that order), then moves
+// through the grid region by region: a block of queries drawn from
+// consecutive points stays in a compact box even where its points cross from
+// one brick into the next.  Key of directory entry b: the interleaved bits of
+// (bx, by, bz), or all ones for a brick without an optimised vertex.
+__device__ inline uint64_t spread3_64(uint32_t v)
+{
+    uint64_t x = v & 0x1fffffull;   // 21 bits
+    x = (x | (x << 32)) & 0x1f00000000ffffull;
+    x = (x | (x << 16)) & 0x1f0000ff0000ffull;
+    x = (x | (x << 8)) & 0x100f00f00f00f00full;
+    x = (x | (x << 4)) & 0x10c30c30c30c30c3ull;
+    x = (x | (x << 2)) & 0x1249249249249249ull;
+    return x;
+}
+
+__global__ void k_brick_keys(const int32_t* __restrict__ active, ShapeDesc s, uint64_t* __restrict__ keys,
+                             int32_t* __restrict__ ids)
+{
+    const int64_t nbt = (int64_t)s.nb[0] * s.nb[1] * s.nb[2];
+    GRID_STRIDE(b, nbt)
+    {
+        const uint32_t bz = (uint32_t)(b % s.nb[2]);
+        const uint32_t by = (uint32_t)((b / s.nb[2]) % s.nb[1]);
+        const uint32_t bx = (uint32_t)(b / ((int64_t)s.nb[2] * s.nb[1]));
+        keys[b] = active[b] ? (spread3_64(bx) << 2) | (spread3_64(by) << 1) | spread3_64(bz) : ~0ull;
+        ids[b] = (int32_t)b;
+    }
+}
+
+// index[b] = the Morton rank of active directory entry b (the active entries
+// sort first: their keys are below all ones).
+__global__ void k_brick_rank(const int32_t* __restrict__ sorted_ids, int64_t n_active, int32_t* __restrict__ index)
+{
+    GRID_STRIDE(r, n_active)
+    {
+        index[sorted_ids[r]] = (int32_t)r;
+    }
+}
+
 __global__ void k_fill_dir(const int32_t* __restrict__ active, const int32_t* __restrict__ index, ShapeDesc s,
                            int32_t shape, int64_t brick_base, int32_t* __restrict__ dir,
                            BrickInfo* __restrict__ bricks)
@@ -379,6 +422,32 @@ gp_status gp_build_band_impl(gp_ctx ctx, const gp_shape* shapes, int32_t n_shape
         const int64_t nb_s = (int64_t)last_idx + last_act;
         if ((brick_base + nb_s) * kBrickVol >= kMaxSlots)
             return gp_fail(ctx, GP_ERR_CAPACITY, "more than 2^30 field slots");
+        {
+            // brick numbers along the Morton curve (index[] of the active entries)
+            DevBuf<uint64_t> kin, kout;
+            DevBuf<int32_t> iin, iout;
+            if (kin.alloc(nbt) != hipSuccess || kout.alloc(nbt) != hipSuccess || iin.alloc(nbt) != hipSuccess ||
+                iout.alloc(nbt) != hipSuccess)
+                return gp_fail(ctx, GP_ERR_OOM, "out of device memory for the brick order of shape " +
+                                                    std::to_string(s));
+            k_brick_keys<<<blocks_for(nbt), kThreads, 0, st>>>(active.p, d, kin.p, iin.p);
+            int32_t bits = 1;
+            while ((int64_t(1) << bits) < std::max(d.nb[0], std::max(d.nb[1], d.nb[2]))) ++bits;
+            const int end_bit = 3 * bits + 1;   // the top bit set only in the keys of inactive entries
+            size_t need3 = 0;
+            GP_HIP(ctx, hipcub::DeviceRadixSort::SortPairs(nullptr, need3, kin.p, kout.p, iin.p, iout.p, (int)nbt, 0,
+                                                          end_bit, st));
+            if (need3 > cub_bytes) {
+                GP_HIP(ctx, cub_buf.alloc(need3));
+                cub_tmp = cub_buf.p;
+                cub_bytes = need3;
+            }
+            GP_HIP(ctx, hipcub::DeviceRadixSort::SortPairs(cub_tmp, need3, kin.p, kout.p, iin.p, iout.p, (int)nbt, 0,
+                                                          end_bit, st));
+            if (nb_s > 0) k_brick_rank<<<blocks_for(nb_s), kThreads, 0, st>>>(iout.p, nb_s, index.p);
+            GP_HIP(ctx, hipGetLastError());
+            GP_HIP(ctx, hipStreamSynchronize(st));
+        }
 
         auto part = std::make_unique<ShapeBricks>();
         part->n_dir = nbt;
@@ -529,13 +598,15 @@ gp_status gp_build_band_impl(gp_ctx ctx, const gp_shape* shapes, int32_t n_shape
         ctx->inv_qv.alloc(n_shapes) != hipSuccess || ctx->flag.alloc(1) != hipSuccess ||
         ctx->fin_part.alloc((size_t)n_shapes * 32 * 5) != hipSuccess || ctx->fin_count.alloc(n_shapes) != hipSuccess ||
         ctx->iter.alloc(1) != hipSuccess || ctx->step_c.alloc(2) != hipSuccess ||
-        ctx->g_raw.alloc((size_t)std::max<int64_t>(n_slots, 1)) != hipSuccess)
+        ctx->g_raw.alloc((size_t)std::max<int64_t>(n_slots, 1)) != hipSuccess ||
+        ctx->nn_pos.alloc((size_t)std::max<int64_t>(n_queries, 1)) != hipSuccess)
         return gp_fail(ctx, GP_ERR_OOM, "out of device memory for the iteration scratch");
     GP_HIP(ctx, hipMemsetAsync(ctx->flag.p, 0, 4, st));
     GP_HIP(ctx, hipMemsetAsync(ctx->fin_count.p, 0, 4 * (size_t)n_shapes, st));
     GP_HIP(ctx, hipMemsetAsync(ctx->iter.p, 0, 4, st));
     GP_HIP(ctx, hipMemsetAsync(ctx->tau.p, 0, std::max<int64_t>(n_slots, 1) * 4, st));
     GP_HIP(ctx, hipMemsetAsync(ctx->g_raw.p, 0, std::max<int64_t>(n_slots, 1) * 4, st));
+    GP_HIP(ctx, hipMemsetAsync(ctx->nn_pos.p, 0, std::max<int64_t>(n_queries, 1) * 4, st));
 
     ctx->h_shapes = hs;
     ctx->h_slot_begin.resize(n_shapes + 1);

@@ -185,6 +185,40 @@ __device__ inline int64_t xcd_work_item(int64_t b, int64_t n)
     return b - r + (r & 7) * kXcdChunk + (r >> 3);
 }
 
+// Coordinates of a query's nearest point nn (an index among its shape's
+// points, valid: 0 <= nn < point_cnt).  The NN search records, per query, the
+// position of its result in the cell-sorted copy; when that position still
+// holds point nn (the sorted copy keeps each point's original index), the
+// point is read there, 16 contiguous bytes next to the points of the
+// neighbouring queries.  Otherwise (nearest points that did not come from the
+// search, or a stale position) it is read from the original order.  Either
+// way the same coordinates.
+struct PointView {
+    const float4* spts;     // cell-sorted copy: x, y, z, original index within the shape (bits)
+    const int32_t* pos;     // [n_queries] position in spts of each query's last NN result
+    const float* ox;        // original order, at sorted_off + index
+    const float* oy;
+    const float* oz;
+};
+
+__device__ inline void nearest_point(const ShapeDesc& s, const PointView& P, int64_t k, int32_t nn, float& sx,
+                                     float& sy, float& sz)
+{
+    int32_t p = P.pos[k];
+    p = (p >= 0 && p < s.point_cnt) ? p : 0;
+    const float4 v = P.spts[s.sorted_off + p];
+    if (__float_as_int(v.w) == nn) {
+        sx = v.x;
+        sy = v.y;
+        sz = v.z;
+    } else {
+        const int64_t g = s.sorted_off + nn;
+        sx = P.ox[g];
+        sy = P.oy[g];
+        sz = P.oz[g];
+    }
+}
+
 // Block-wide minimum of v[0..2] and maximum of v[3..5] (blockDim = 256).
 // Every thread receives the result.  scratch: shared int [4 * 6].
 __device__ inline void block_minmax6(int32_t v[6], int32_t* scratch)
@@ -326,6 +360,7 @@ struct gp_ctx_s {
     DevBuf<int32_t> cell_start;   // [n_slots + 1]
     DevBuf<float4> spts;          // sorted points: x, y, z, original index within the shape (bits)
     DevBuf<float> ox, oy, oz;     // points in their original order, at sorted_off + index
+    DevBuf<int32_t> nn_pos;       // [n_queries] position in spts (within the shape) of the last NN result
 
     // per-iteration scratch
     DevBuf<double> q_part;        // [n_tiles][4] sum pull, surf, grad, count
@@ -359,6 +394,11 @@ struct gp_ctx_s {
     bool timing = false;
     std::vector<TimedLaunch> timed;
     std::vector<hipEvent_t> event_pool;
+
+    gp::PointView points() const
+    {
+        return gp::PointView{spts.p, nn_pos.p, ox.p, oy.p, oz.p};
+    }
 
     gp::Band band() const
     {

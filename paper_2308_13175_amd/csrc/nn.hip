@@ -44,7 +44,8 @@ constexpr int kNnMaxGrow = 8;     // growth beyond which a group with no point i
 
 struct Best {
     double d2;
-    int32_t id;
+    int32_t id;     // original index within the shape (the tie rule)
+    int32_t pos;    // global position in the cell-sorted copy
 };
 
 __device__ inline double exact_d2(float qx, float qy, float qz, float sx, float sy, float sz)
@@ -60,11 +61,12 @@ __device__ inline double exact_d2(float qx, float qy, float qz, float sx, float 
     return s + zz;
 }
 
-__device__ inline void consider(double d2, int32_t id, Best& best)
+__device__ inline void consider(double d2, int32_t id, int32_t pos, Best& best)
 {
     if (d2 < best.d2 || (d2 == best.d2 && id < best.id)) {
         best.d2 = d2;
         best.id = id;
+        best.pos = pos;
     }
 }
 
@@ -81,6 +83,10 @@ struct Global {
     const int32_t* cell_start;
     const float4* pts;    // x, y, z, original index (bits)
 };
+
+// The search passes carry, in .w of each staged point, its position in the
+// cell-sorted copy instead of its original index (float pass ties are not
+// decided there: they go to the exact search, which uses the original index).
 
 // Global range of the points of cells (x, y, za..zb) (one brick): empty if none.
 __device__ inline void run_range(const Band& B, const ShapeDesc& s, const Global& G, int32_t x, int32_t y,
@@ -109,6 +115,7 @@ __device__ inline void query_cell(const ShapeDesc& s, float x, float y, float z,
 // Exact ring search: cells in rings of growing Chebyshev radius around the
 // query's cell, each opened only if its box can hold a point at least as close
 // as the best so far; stops once every unopened cell is provably farther.
+// Returns the winner's position in the sorted copy (-1 for a shape without points).
 __device__ inline int32_t search(const Band& B, const ShapeDesc& s, const Global& G, float x, float y, float z)
 {
     if (s.point_cnt <= 0) return -1;
@@ -118,7 +125,7 @@ __device__ inline int32_t search(const Band& B, const ShapeDesc& s, const Global
 #pragma unroll
     for (int a = 0; a < 3; ++a) margin[a] = 1e-4f * (1.f + fabsf(du[a]));
     const float h2[3] = {s.h[0] * s.h[0], s.h[1] * s.h[1], s.h[2] * s.h[2]};
-    Best best{__builtin_inf(), 0x7fffffff};
+    Best best{__builtin_inf(), 0x7fffffff, -1};
     for (int32_t r = 0;; ++r) {
         const int32_t xl = max(c0[0] - r, 0), xh = min(c0[0] + r, s.R[0] - 1);
         const int32_t yl = max(c0[1] - r, 0), yh = min(c0[1] + r, s.R[1] - 1);
@@ -148,7 +155,7 @@ __device__ inline int32_t search(const Band& B, const ShapeDesc& s, const Global
                     run_range(B, s, G, cx, cy, cz, cz, b, e);
                     for (int32_t i = b; i < e; ++i) {
                         const float4 p = G.pts[i];
-                        consider(exact_d2(x, y, z, p.x, p.y, p.z), __float_as_int(p.w), best);
+                        consider(exact_d2(x, y, z, p.x, p.y, p.z), __float_as_int(p.w), i, best);
                     }
                 }
             }
@@ -172,7 +179,7 @@ __device__ inline int32_t search(const Band& B, const ShapeDesc& s, const Global
         if (!more) break;
         if (best.d2 < (double)(bound * (1.f - 1e-6f))) break;
     }
-    return best.id;
+    return best.pos;
 }
 
 // Wave-wide minimum of v[0..2] and maximum of v[3..5] (the same in every
@@ -390,7 +397,7 @@ __device__ inline int32_t flush_runs(const Band& B, const ShapeDesc& s, const Gl
         const int32_t p = c + lane;
         const int32_t idx = __shfl(pb, j, 64) + (p - __shfl(off, j, 64));
         const float4 x = G.pts[p < total ? idx : 0];   // a scan only happens for a shape with points
-        return p < total ? x : make_float4(0.f, 0.f, 0.f, 0.f);
+        return p < total ? make_float4(x.x, x.y, x.z, __int_as_float(idx)) : make_float4(0.f, 0.f, 0.f, 0.f);
     };
     float4 nxt = total > 0 ? chunk_at(0) : make_float4(0.f, 0.f, 0.f, 0.f);
     for (int32_t c = 0; c < total; c += 64) {
@@ -547,7 +554,7 @@ constexpr int kWaveSpan = kQueryTile / kWaves;   // sorted positions grouped and
 template <bool kTuning>
 __global__ __launch_bounds__(kQueryBlock, 4) void k_nn(Band B, Global G, NnParams P, const float* __restrict__ qx,
                                                     const float* __restrict__ qy, const float* __restrict__ qz,
-                                                    int32_t* __restrict__ nn)
+                                                    int32_t* __restrict__ nn, int32_t* __restrict__ nn_pos)
 {
     __shared__ typename BlockSort::TempStorage sort_tmp;
     __shared__ int16_t s_order[kQueryTile];
@@ -767,7 +774,11 @@ __global__ __launch_bounds__(kQueryBlock, 4) void k_nn(Band B, Global G, NnParam
             if (tail && q.best2 > q.best1 * (1.f + 1e-6f)) q.open = false;
         }
         if (!live) continue;
-        nn[k] = (s.point_cnt > 0 && !q.open) ? q.id1 : search(B, s, G, q.x, q.y, q.z);
+        // the winner's position in the sorted copy; its original index is
+        // stored there too (a load from the same small region as the scan)
+        const int32_t at = (s.point_cnt > 0 && !q.open) ? q.id1 : search(B, s, G, q.x, q.y, q.z);
+        nn[k] = at >= 0 ? __float_as_int(G.pts[at].w) : -1;
+        nn_pos[k] = at >= 0 ? (int32_t)(at - s.sorted_off) : 0;
     }
 }
 
@@ -781,8 +792,8 @@ gp_status gp_nn_impl(gp_ctx ctx, const float* qx, const float* qy, const float* 
     if (ctx->n_tiles == 0) return GP_OK;
     Global G{ctx->cell_start.p, ctx->spts.p};
     GP_TIMED(ctx, "k_nn");
-    k_nn<false><<<(unsigned)(ctx->n_tiles * ctx->nn_params.parts), kQueryBlock, 0, ctx->stream>>>(ctx->band(), G,
-                                                                                          ctx->nn_params, qx, qy, qz, nn);
+    k_nn<false><<<(unsigned)(ctx->n_tiles * ctx->nn_params.parts), kQueryBlock, 0, ctx->stream>>>(
+        ctx->band(), G, ctx->nn_params, qx, qy, qz, nn, ctx->nn_pos.p);
     GP_HIP(ctx, hipGetLastError());
     return GP_OK;
 }
@@ -820,7 +831,7 @@ gp_status gp_autotune_nn_impl(gp_ctx ctx, const float* qx, const float* qy, cons
             for (int32_t r = 0; r <= reps && e == hipSuccess; ++r) {
                 if (r > 0) e = hipEventRecord(ev[0], ctx->stream);
                 k_nn<true><<<(unsigned)(ctx->n_tiles * P.parts), kQueryBlock, 0, ctx->stream>>>(ctx->band(), G, P, qx, qy,
-                                                                                            qz, nn);
+                                                                                            qz, nn, ctx->nn_pos.p);
                 if (e == hipSuccess) e = hipGetLastError();
                 if (r > 0 && e == hipSuccess) e = hipEventRecord(ev[1], ctx->stream);
                 if (r > 0 && e == hipSuccess) e = hipEventSynchronize(ev[1]);
@@ -881,7 +892,7 @@ gp_status gp_autotune_nn_impl(gp_ctx ctx, const float* qx, const float* qy, cons
         GP_HIP(ctx, e);
         // leave nn holding the chosen configuration's (identical) result
         k_nn<true><<<(unsigned)(ctx->n_tiles * best.parts), kQueryBlock, 0, ctx->stream>>>(ctx->band(), G, best, qx, qy, qz,
-                                                                                       nn);
+                                                                                       nn, ctx->nn_pos.p);
         GP_HIP(ctx, hipGetLastError());
     }
     ctx->nn_params = best;

@@ -75,19 +75,13 @@ struct QueryState {
 };
 
 __device__ inline bool eval_query(const Band& B, const ShapeDesc& s, const float* __restrict__ D, float x, float y,
-                                  float z, int32_t nn, const float* __restrict__ px, const float* __restrict__ py,
-                                  const float* __restrict__ pz, int32_t* bad_nn, QueryState& st)
+                                  float z, int64_t k, int32_t nn, const PointView& P, int32_t* bad_nn, QueryState& st)
 {
     // the loads of both sides are issued before any of them is tested
     const Loc L = locate(s, x, y, z);
     const bool nn_ok = nn >= 0 && nn < s.point_cnt;
-    const int64_t g = s.sorted_off + (nn_ok ? nn : 0);
     float sx = 0.f, sy = 0.f, sz = 0.f;
-    if (s.point_cnt > 0) {
-        sx = px[g];
-        sy = py[g];
-        sz = pz[g];
-    }
+    if (s.point_cnt > 0) nearest_point(s, P, k, nn_ok ? nn : 0, sx, sy, sz);
     const int32_t br = L.inside ? brick_of(B, s, L.c[0] >> 3, L.c[1] >> 3, L.c[2] >> 3) : -1;
     if (br < 0 || !mask_bit(B.m_a1, br, local_index(L.c[0], L.c[1], L.c[2]))) return false;
     if (!nn_ok) {
@@ -130,10 +124,7 @@ __device__ inline void block_sum(double (&v)[N], double* lds /* [4 waves][N] */)
 __global__ __launch_bounds__(kQueryBlock) void k_forward_query(Band B, const float* __restrict__ qx,
                                                                const float* __restrict__ qy,
                                                                const float* __restrict__ qz,
-                                                               const int32_t* __restrict__ nn,
-                                                               const float* __restrict__ px,
-                                                               const float* __restrict__ py,
-                                                               const float* __restrict__ pz,
+                                                               const int32_t* __restrict__ nn, PointView P,
                                                                const float* __restrict__ D,
                                                                double* __restrict__ q_part, int32_t* flag)
 {
@@ -147,7 +138,7 @@ __global__ __launch_bounds__(kQueryBlock) void k_forward_query(Band B, const flo
     int cnt = 0;
     for (int64_t k = q0 + threadIdx.x; k < qe; k += blockDim.x) {
         QueryState st;
-        if (!eval_query(B, s, D, qx[k], qy[k], qz[k], nn[k], px, py, pz, flag, st)) continue;
+        if (!eval_query(B, s, D, qx[k], qy[k], qz[k], k, nn[k], P, flag, st)) continue;
         const double lg = (st.q.ok && st.s.ok)
                               ? 1.0 - fma(st.q.gh[0], st.s.gh[0], fma(st.q.gh[1], st.s.gh[1], st.q.gh[2] * st.s.gh[2]))
                               : 1.0;
@@ -164,70 +155,6 @@ __global__ __launch_bounds__(kQueryBlock) void k_forward_query(Band B, const flo
 
 constexpr int kGradParts = 4;                          // blocks per query tile in the gradient pass
 constexpr int kGradBlock = kQueryTile / kGradParts;    // one query per thread
-// The contributions of a block land in few places (its queries come from
-// neighbouring points).  They are accumulated in LDS copies of the 4^3-vertex
-// octants of the bricks they touch ("cells" of the cache, keyed by brick * 8 +
-// octant) and flushed once, octant by octant, so that the lanes of a wave add
-// to nearby addresses.  The accumulators hold fixed point with 32 fraction
-// bits in 64-bit integers: integer LDS atomics run at full rate where float
-// ones do not, and the sums inside a block become exact.  A contribution of
-// 2^20 or more in magnitude bypasses them (a float atomic on the gradient),
-// so no sum can leave the range of the fixed point; so do the contributions
-// of octants beyond the cache's capacity.
-constexpr int kOctVol = 64;                       // vertices per octant
-constexpr int kCacheOcts = 72;                    // LDS octant accumulators per block (72 x 512 B)
-constexpr int kCacheTable = 256;                  // open-addressing table: octant key -> LDS octant
-constexpr int kCacheProbes = 32;                  // longest probe sequence before a key is left uncached
-constexpr double kFixScale = 4294967296.0;        // 2^32
-constexpr float kFixLimit = 1048576.f;            // 2^20
-
-// A vertex with brick-local coordinates (x, y, z) in brick br lies in octant
-// key br * 8 + (x >> 2) * 4 + (y >> 2) * 2 + (z >> 2), at place
-// (x & 3) * 16 + (y & 3) * 4 + (z & 3) of it.  Slot of place w of octant key:
-__device__ inline int32_t oct_slot(int32_t key, int32_t w)
-{
-    const int32_t o = key & 7;
-    const int32_t i = ((o >> 2) << 2) | (w >> 4), j = (((o >> 1) & 1) << 2) | ((w >> 2) & 3),
-                  k = ((o & 1) << 2) | (w & 3);
-    return (key >> 3) * kBrickVol + ((i * kBrick + j) * kBrick + k);
-}
-
-// Multiplicative (Fibonacci) hashing at 24 bits: keys are below 2^24 (brick
-// < 2^21), so a 24-bit multiply (full rate, where a 32-bit one is not) by
-// 0x9E3779 (2^24 over the golden ratio) gives key * 0x9E3779 mod 2^24, whose
-// top 8 bits spread neighbouring keys over the table.
-__device__ inline int32_t table_home(int32_t key)
-{
-    return (int32_t)((__umul24((uint32_t)key, 0x9E3779u) >> 16) & 255u);
-}
-
-// Both walk the same probe sequence and give up after kCacheProbes places, so
-// a key that found no free place within it is not cached (its contributions
-// go straight to memory) and a lookup stops as soon: a block whose queries
-// touch more octants than the table holds costs a bounded number of probes.
-__device__ inline void cache_insert(int32_t* keys, int32_t key)
-{
-    int32_t h = table_home(key);
-#pragma unroll 1
-    for (int p = 0; p < kCacheProbes; ++p) {
-        const int32_t old = atomicCAS(&keys[h], -1, key);
-        if (old == -1 || old == key) return;
-        h = (h + 1) & (kCacheTable - 1);
-    }
-}
-
-__device__ inline int32_t cache_find(const int32_t* keys, const int32_t* idx, int32_t key)
-{
-    int32_t h = table_home(key);
-#pragma unroll 1
-    for (int p = 0; p < kCacheProbes; ++p) {
-        const int32_t k = keys[h];
-        if (k == key) return idx[h];
-        if (k == -1) return -1;
-        h = (h + 1) & (kCacheTable - 1);
-    }
-    return -1;
-}
 
 // Adjoint of one valid query (Eq. 4, 6, 7 differentiated): the contributions
 // to the 8 corners of q's cell and the 8 corners of s's cell.
@@ -265,213 +192,191 @@ __device__ inline void query_adjoint(const ShapeDesc& s, const QueryState& st, g
     trilinear_adjoint(st.s.t, s.inv_hf, dfs, dgsf, cs);
 }
 
-// Octant key and place of the corners of a cell whose lowest corner has
-// brick-local coordinates packed 3 bits per axis (x lowest): corner (a, b, d)
-// lies in octant (slot >> 9) * 8 + k[0][a] + k[1][b] + k[2][d] at place
-// i[0][a] + i[1][b] + i[2][d] (a corner in the next brick along an axis has
-// local coordinate 0 there, which (l + 1) & 7 gives).
-struct CornerOct {
-    int32_t k[3][2], i[3][2];
+// Accumulation of the contributions of a block.  Its queries come from
+// neighbouring points (and bricks are numbered along a Morton curve, so
+// neighbouring points stay neighbours across brick boundaries), so their 16
+// corner contributions each fall in a small box of the grid, the box of the
+// block's query and nearest-point cells.  The block sums them in an LDS
+// window, a dense copy of that box, and adds each non-zero window entry to
+// the gradient once.  A box larger than the window is taken in slabs of
+// whole layers along x or y (whichever makes the smaller cross-section), one
+// pass each: a contribution is added in the pass of its slab.  A box that
+// would take more than kWinMaxPasses passes sends its contributions straight
+// to the gradient (global float atomics).
+// The flush walks the window in index order (z fastest), so that the lanes
+// of a wave add to runs of consecutive slots (a z-run is contiguous inside a
+// brick) and clear what they read; the slot of an entry comes from an LDS
+// copy of the directory entries of the slab's bricks.
+// The entries hold fixed point with 32 fraction bits in 64-bit integers:
+// integer LDS atomics run at full rate where float ones do not (measured:
+// a float window made the pass several times slower), and the sums inside a
+// block are exact.  A contribution of 2^20 or more in magnitude bypasses the
+// window, so no sum leaves the range of the fixed point (a vertex receives
+// at most 2 contributions from each of the 256 queries).
+constexpr int kWinCap = 4608;      // window vertices (36 KB)
+constexpr int kWinMaxPasses = 16;
+constexpr int kWinBricks = 768;    // directory entries of a slab's bricks (at most 578 for kWinCap vertices)
+constexpr double kFixScale = 4294967296.0;   // 2^32
+constexpr float kFixLimit = 1048576.f;       // 2^20
+
+// The box of a block (vertices lo .. lo + w - 1), its slab axis ax (0 or 1;
+// o = 1 - ax is the other of x and y), the layers of ax per pass and the
+// number of passes (0: no window).
+struct Window {
+    int32_t lo[3];
+    int32_t w[3];
+    int32_t ax;
+    int32_t layers;
+    int32_t passes;
 };
 
-__device__ inline CornerOct corner_oct(int32_t packed)
+__device__ inline Window choose_window(const int32_t box[6])
 {
-    CornerOct o;
-#pragma unroll
-    for (int ax = 0; ax < 3; ++ax) {
-        const int32_t l = (packed >> (3 * ax)) & 7;
-#pragma unroll
-        for (int e = 0; e < 2; ++e) {
-            const int32_t x = (l + e) & 7;
-            o.k[ax][e] = (x >> 2) << (2 - ax);
-            o.i[ax][e] = (x & 3) << (4 - 2 * ax);
-        }
+    Window W;
+    W.passes = 0;
+    W.ax = 0;
+    W.layers = 0;
+    for (int a = 0; a < 3; ++a) {
+        W.lo[a] = box[a];
+        W.w[a] = box[3 + a] - box[a] + 2;
     }
-    return o;
+    if (box[3] < 0) return W;   // no valid query
+    W.ax = W.w[1] > W.w[0] ? 1 : 0;
+    const int64_t cross = (int64_t)W.w[1 - W.ax] * W.w[2];
+    if (cross > kWinCap) return W;
+    W.layers = (int32_t)min((int64_t)W.w[W.ax], kWinCap / cross);
+    const int32_t passes = (W.w[W.ax] + W.layers - 1) / W.layers;
+    if (passes <= kWinMaxPasses) W.passes = passes;
+    return W;
 }
 
-__device__ inline int32_t pack_local(const int32_t c[3])
+// Index strides of the x and y corners in the window layout ((a * w_o + o) * w_z + z).
+__device__ inline void window_strides(const Window& W, int32_t& sx, int32_t& sy)
 {
-    return (c[0] & 7) | ((c[1] & 7) << 3) | ((c[2] & 7) << 6);
+    const int32_t s_ax = W.w[1 - W.ax] * W.w[2], s_o = W.w[2];
+    sx = W.ax == 0 ? s_ax : s_o;
+    sy = W.ax == 1 ? s_ax : s_o;
 }
 
-__device__ inline void insert_cell_octs(const int32_t slot[8], int32_t packed, int32_t* keys)
+// Window index (in the slab of pass layers [a0, a1) along ax) of every
+// corner of cell c, or -1 outside the slab.
+__device__ inline void window_corners(const Window& W, int32_t a0, int32_t a1, const int32_t c[3], int32_t idx[8])
 {
-    const CornerOct o = corner_oct(packed);
-    int32_t last = -1;
+    int32_t sx, sy;
+    window_strides(W, sx, sy);
+    const int32_t r[3] = {c[0] - W.lo[0], c[1] - W.lo[1], c[2] - W.lo[2]};
+    const int32_t ra = r[W.ax] - a0;   // along the slab axis, relative to the slab
+    const int32_t rx = W.ax == 0 ? ra : r[0], ry = W.ax == 1 ? ra : r[1];
+    const int32_t na = a1 - a0;
+    const int32_t base = rx * sx + ry * sy + r[2];
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
-#pragma unroll
-        for (int b = 0; b < 2; ++b)
-#pragma unroll
-            for (int d = 0; d < 2; ++d) {
-                const int32_t key = ((slot[4 * a + 2 * b + d] >> 9) << 3) + o.k[0][a] + o.k[1][b] + o.k[2][d];
-                if (key != last) cache_insert(keys, key);
-                last = key;
-            }
-}
-
-__device__ inline void scatter_cell(const int32_t slot[8], int32_t packed, const float cv[8], const int32_t* keys,
-                                    const int32_t* idx, unsigned long long* __restrict__ acc,
-                                    float* __restrict__ G, float scale)
-{
-    const CornerOct o = corner_oct(packed);
-    int32_t last_key = -1, last_li = -1;
-#pragma unroll
-    for (int a = 0; a < 2; ++a)
-#pragma unroll
-        for (int b = 0; b < 2; ++b)
-#pragma unroll
-            for (int d = 0; d < 2; ++d) {
-                const int i = 4 * a + 2 * b + d;
-                const int32_t key = ((slot[i] >> 9) << 3) + o.k[0][a] + o.k[1][b] + o.k[2][d];
-                if (key != last_key) {
-                    last_key = key;
-                    last_li = cache_find(keys, idx, key);
-                }
-                if (last_li >= 0 && fabsf(cv[i]) < kFixLimit)
-                    atomicAdd(&acc[last_li * kOctVol + o.i[0][a] + o.i[1][b] + o.i[2][d]],
-                              (unsigned long long)__double2ll_rn((double)cv[i] * kFixScale));
-                else
-                    atomicAdd(at32(G, (uint32_t)slot[i]), scale * cv[i]);
-            }
-}
-
-// Dense window: when the cells of a block's queries and of their nearest
-// points fit in a box of at most kWinPasses * kWinVol vertices, the block
-// accumulates in an LDS copy of that box (x-major, w1 x w2 vertices per x
-// layer), indexed directly: no table, no probing.  A box larger than the
-// window is taken in slabs of whole x layers, one pass each (every
-// contribution is added in the pass of its slab).  Same fixed point and the
-// same bypass of large contributions as the octant cache.
-constexpr int64_t kWinVol = (int64_t)kCacheOcts * kOctVol;
-constexpr int32_t kWinPasses = 4;
-
-// Contributions of one cell's corners whose box-relative x lies in [x0, x1).
-__device__ inline void window_add(const int32_t c[3], const int32_t box[6], int32_t x0, int32_t x1, int32_t w1,
-                                  int32_t w2, const int32_t slot[8], const float cv[8],
-                                  unsigned long long* __restrict__ acc, float* __restrict__ G, float scale)
-{
-    const int32_t rx = c[0] - box[0];
-    const int32_t base = ((rx - x0) * w1 + (c[1] - box[1])) * w2 + (c[2] - box[2]);
-    const int32_t sx = w1 * w2;
-#pragma unroll
-    for (int a = 0; a < 2; ++a) {
-        if (rx + a < x0 || rx + a >= x1) continue;
-#pragma unroll
-        for (int b = 0; b < 2; ++b)
-#pragma unroll
-            for (int d = 0; d < 2; ++d) {
-                const int i = 4 * a + 2 * b + d;
-                // (converted here, in its pass: kept opaque so that the
-                // conversions are not hoisted out of the pass loop and held
-                // as 16 64-bit values)
-                float v = cv[i];
-                asm volatile("" : "+v"(v));
-                if (fabsf(v) < kFixLimit)
-                    atomicAdd(&acc[base + a * sx + b * w2 + d], (unsigned long long)__double2ll_rn((double)v * kFixScale));
-                else
-                    atomicAdd(at32(G, (uint32_t)slot[i]), scale * v);
-            }
+    for (int i = 0; i < 8; ++i) {
+        const int32_t da = W.ax == 0 ? (i >> 2) : ((i >> 1) & 1);
+        const bool in = ra + da >= 0 && ra + da < na;   // the other axes lie inside the box
+        idx[i] = in ? base + (i >> 2) * sx + ((i >> 1) & 1) * sy + (i & 1) : -1;
     }
 }
 
-// Add the non-zero entries of the slab starting at box-relative x layer x0
-// (vol entries) to the gradient, one atomic per vertex, and clear them for
-// the next slab.  The vertex of an entry is found from its index by float
-// reciprocals: the index is below 2^13, far inside float's exact range, and
-// (i + 1/2) / w stays at least 1/(2w) away from an integer.
-__device__ inline void window_flush(const Band& B, const ShapeDesc& s, const int32_t box[6], int32_t x0, int32_t w1,
-                                    int32_t w2, int32_t vol, unsigned long long* __restrict__ acc,
-                                    float* __restrict__ G, float scale)
+// The contributions of one cell: into the window where the corner lies in
+// the current slab (index >= 0); contributions too large for the fixed
+// point go straight to the gradient in pass 0 (bypass).
+__device__ inline void window_add(const int32_t idx[8], const int32_t slot[8], const float v[8], bool first,
+                                  unsigned long long* acc, float* __restrict__ G, float scale)
 {
-    const int32_t w12 = w1 * w2;
-    const float inv12 = 1.f / (float)w12, inv2 = 1.f / (float)w2;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        // (converted here, in its pass: kept opaque so that the conversions
+        // are not hoisted out of the pass loop and held as 16 64-bit values)
+        float x = v[i];
+        asm volatile("" : "+v"(x));
+        const bool big = !(fabsf(x) < kFixLimit);
+        if (idx[i] >= 0 && !big)
+            atomicAdd(&acc[idx[i]], (unsigned long long)__double2ll_rn((double)x * kFixScale));
+        else if (first && big)
+            atomicAdd(at32(G, (uint32_t)slot[i]), scale * x);
+    }
+}
+
+// Directory entries of the bricks of the slab [a0, a1) in LDS (-1: none).
+struct WinBricks {
+    int32_t b0[3];     // first brick per axis
+    int32_t nb[3];     // bricks per axis
+};
+
+__device__ inline WinBricks slab_bricks(const Band& B, const ShapeDesc& s, const Window& W, int32_t a0, int32_t a1,
+                                        int32_t* wdir)
+{
+    WinBricks T;
+    int32_t n = 1;
+    for (int a = 0; a < 3; ++a) {
+        const int32_t lo = W.lo[a] + (a == W.ax ? a0 : 0);
+        const int32_t w = a == W.ax ? a1 - a0 : W.w[a];
+        T.b0[a] = lo >> 3;
+        T.nb[a] = ((lo + w - 1) >> 3) - T.b0[a] + 1;
+        n *= T.nb[a];
+    }
+    const int32_t nyz = T.nb[1] * T.nb[2];
+    for (int32_t i = threadIdx.x; i < n; i += blockDim.x) {
+        const int32_t bx = T.b0[0] + i / nyz, r = i % nyz;
+        const int32_t by = T.b0[1] + r / T.nb[2], bz = T.b0[2] + r % T.nb[2];
+        wdir[i] = (bx < s.nb[0] && by < s.nb[1] && bz < s.nb[2]) ? brick_of(B, s, bx, by, bz) : -1;
+    }
+    return T;
+}
+
+// Add every non-zero entry of the slab [a0, a1) to the gradient, in index
+// order, and clear it.  The vertex of an entry is found from its index by
+// float reciprocals: the index is below 2^13, far inside float's exact
+// range, and (i + 1/2) / w stays at least 1/(2w) away from an integer.
+__device__ inline void window_flush(const Window& W, int32_t a0, int32_t a1, const WinBricks& T, const int32_t* wdir,
+                                    unsigned long long* acc, float* __restrict__ G, float scale)
+{
+    const int32_t wo = W.w[1 - W.ax], wz = W.w[2];
+    const int32_t w12 = wo * wz, vol = (a1 - a0) * w12;
+    const float inv12 = 1.f / (float)w12, inv2 = 1.f / (float)wz;
     for (int32_t i = threadIdx.x; i < vol; i += blockDim.x) {
-        const long long a = (long long)acc[i];
-        if (a == 0) continue;
+        const long long v = (long long)acc[i];
+        if (v == 0) continue;
         acc[i] = 0ull;
-        const int32_t x = (int32_t)(((float)i + 0.5f) * inv12);
-        const int32_t r = i - x * w12;
-        const int32_t y = (int32_t)(((float)r + 0.5f) * inv2);
-        const int32_t vx = box[0] + x0 + x, vy = box[1] + y, vz = box[2] + (r - y * w2);
-        const int32_t br = brick_of(B, s, vx >> 3, vy >> 3, vz >> 3);
+        const int32_t ia = (int32_t)(((float)i + 0.5f) * inv12);
+        const int32_t r = i - ia * w12;
+        const int32_t io = (int32_t)(((float)r + 0.5f) * inv2);
+        const int32_t va = W.lo[W.ax] + a0 + ia, vo = W.lo[1 - W.ax] + io;
+        const int32_t vx = W.ax == 0 ? va : vo, vy = W.ax == 0 ? vo : va, vz = W.lo[2] + (r - io * wz);
+        const int32_t br = wdir[(((vx >> 3) - T.b0[0]) * T.nb[1] + ((vy >> 3) - T.b0[1])) * T.nb[2] + ((vz >> 3) - T.b0[2])];
         atomicAdd(at32(G, (uint32_t)(br * kBrickVol + local_index(vx, vy, vz))),
-                  (float)((double)a * (1.0 / kFixScale) * (double)scale));
+                  (float)((double)v * (1.0 / kFixScale) * (double)scale));
     }
 }
 
-// The octant cache for a block whose box is too large for the window:
-// register the octants the block's contributions fall in, number the first
-// kCacheOcts of them in table order, accumulate, and add each octant to G.
-__device__ inline void octant_path(bool valid, const int32_t sq[8], const int32_t ss[8], int32_t lq, int32_t ls,
-                                   const float cq[8], const float cs[8], int32_t* s_keys, int32_t* s_idx,
-                                   int32_t* s_oct, int32_t* s_wcount, unsigned long long* __restrict__ s_acc,
-                                   float* __restrict__ G, float scale)
+// Every contribution of one cell straight to the gradient (no window).
+__device__ inline void direct_add(const int32_t slot[8], const float v[8], float* __restrict__ G, float scale)
 {
-    if (valid) {
-        insert_cell_octs(sq, lq, s_keys);
-        insert_cell_octs(ss, ls, s_keys);
-    }
-    __syncthreads();
-    // LDS octant numbers in table order (one table entry per thread)
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const bool used_e = s_keys[threadIdx.x] != -1;
-    const uint64_t um = __ballot(used_e);
-    if (lane == 0) s_wcount[wave] = __popcll(um);
-    __syncthreads();
-    int32_t before = __popcll(um & ((1ull << lane) - 1ull)), n_used = 0;
-    for (int wv = 0; wv < kGradBlock / 64; ++wv) {
-        before += wv < wave ? s_wcount[wv] : 0;
-        n_used += s_wcount[wv];
-    }
-    {
-        const int32_t li = used_e && before < kCacheOcts ? before : -1;
-        s_idx[threadIdx.x] = li;
-        if (li >= 0) s_oct[li] = s_keys[threadIdx.x];
-    }
-    __syncthreads();
-    if (valid) {
-        scatter_cell(sq, lq, cq, s_keys, s_idx, s_acc, G, scale);
-        scatter_cell(ss, ls, cs, s_keys, s_idx, s_acc, G, scale);
-    }
-    __syncthreads();
-    // flush: the cached octants, one atomic per vertex that received anything
-    const int32_t used = min(n_used, kCacheOcts);
-    for (int32_t i = threadIdx.x; i < used * kOctVol; i += blockDim.x) {
-        const long long a = (long long)s_acc[i];
-        if (a != 0) atomicAdd(&G[oct_slot(s_oct[i >> 6], i & (kOctVol - 1))],
-                              (float)((double)a * (1.0 / kFixScale) * (double)scale));
-    }
+#pragma unroll
+    for (int i = 0; i < 8; ++i) atomicAdd(at32(G, (uint32_t)slot[i]), scale * v[i]);
 }
 
-// One thread per query of a quarter tile: evaluate, take the adjoint, keep the 16
-// corner contributions in registers, then accumulate them in LDS and add the
-// sums to G once per vertex: in the block's dense window when its box fits,
-// else in LDS copies of the octants they fall in (registered in a table
-// first; at most kCacheOcts, the rest straight to memory).  Fixed point
-// either way.  kLoss: also the tile's loss partials, and the contributions
-// go out unscaled (the per-shape scale 1/valid count is applied when they are
-// folded into the gradient); otherwise they are scaled by dloss / valid count.
+// One thread per query of a quarter tile: evaluate, take the adjoint, add
+// the 16 corner contributions to the block's window (or straight to the
+// gradient outside it), then flush the window.  kLoss: also the tile's loss
+// partials, and the contributions go out unscaled (the per-shape scale
+// 1/valid count is applied when they are folded into the gradient);
+// otherwise they are scaled by dloss / valid count.
 template <bool kLoss>
 __global__ __launch_bounds__(kGradBlock) void k_query_grad(Band B, const float* __restrict__ qx,
                                                            const float* __restrict__ qy,
                                                            const float* __restrict__ qz,
-                                                           const int32_t* __restrict__ nn,
-                                                           const float* __restrict__ px,
-                                                           const float* __restrict__ py,
-                                                           const float* __restrict__ pz,
+                                                           const int32_t* __restrict__ nn, PointView P,
                                                            const float* __restrict__ D, gp_weights w,
                                                            const double* __restrict__ dloss,
                                                            const double* __restrict__ inv_qv,
                                                            float* __restrict__ G, double* __restrict__ q_part,
                                                            int32_t* flag)
 {
-    __shared__ unsigned long long s_acc[kCacheOcts * kOctVol];
-    __shared__ int32_t s_keys[kCacheTable], s_idx[kCacheTable], s_oct[kCacheOcts];
-    __shared__ int32_t s_wcount[kGradBlock / 64];
+    __shared__ unsigned long long s_acc[kWinCap];
     __shared__ double s_red[kGradBlock / 64 * 4];
     __shared__ int32_t s_box[kGradBlock / 64 * 6];
+    __shared__ int32_t s_wdir[kWinBricks];
     const int64_t item = xcd_work_item(blockIdx.x, gridDim.x);
     const int64_t tile = item / kGradParts;
     const int32_t quarter = (int32_t)(item % kGradParts);
@@ -481,11 +386,8 @@ __global__ __launch_bounds__(kGradBlock) void k_query_grad(Band B, const float* 
     const int64_t qe = min(B.tile_start[tile] + (int64_t)kQueryTile, s.query_off + s.query_cnt);
     const float scale = kLoss ? 1.f : (float)(dloss[shape] * inv_qv[shape]);
 
-    static_assert(kCacheTable == kGradBlock, "one table entry per thread");
-    s_keys[threadIdx.x] = -1;
-    for (int32_t i = threadIdx.x; i < kCacheOcts * kOctVol / 2; i += blockDim.x)
+    for (int32_t i = threadIdx.x; i < kWinCap / 2; i += blockDim.x)
         reinterpret_cast<ulonglong2*>(s_acc)[i] = make_ulonglong2(0ull, 0ull);
-    __syncthreads();
 
     const int64_t k = q0 + threadIdx.x;
     float cq[8], cs[8];
@@ -494,7 +396,7 @@ __global__ __launch_bounds__(kGradBlock) void k_query_grad(Band B, const float* 
     double part[4] = {0.0, 0.0, 0.0, 0.0};
     if (k < qe) {
         QueryState st;
-        valid = eval_query(B, s, D, qx[k], qy[k], qz[k], nn[k], px, py, pz, flag, st);
+        valid = eval_query(B, s, D, qx[k], qy[k], qz[k], k, nn[k], P, flag, st);
         if (valid) {
             if (kLoss) {
                 part[0] = st.lp;
@@ -517,33 +419,37 @@ __global__ __launch_bounds__(kGradBlock) void k_query_grad(Band B, const float* 
             }
         }
     }
-    // the box of the block's cells, in vertices w0 x w1 x w2
+    // the box of the block's query and nearest-point cells
     int32_t box[6];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         box[a] = valid ? min(ccq[a], ccs[a]) : 0x7fffffff;
         box[3 + a] = valid ? max(ccq[a], ccs[a]) : -1;
     }
-    block_minmax6(box, s_box);
+    block_minmax6(box, s_box);   // (its barriers also order the window clear)
 #pragma unroll
     for (int a = 0; a < 6; ++a) box[a] = __builtin_amdgcn_readfirstlane(box[a]);
-    const int32_t w0 = box[3] - box[0] + 2, w1 = box[4] - box[1] + 2, w2 = box[5] - box[2] + 2;
-    const int64_t w12 = (int64_t)w1 * w2;
-    const int32_t layers = box[3] >= 0 && w12 <= kWinVol ? (int32_t)(kWinVol / w12) : 0;   // x layers per slab
-    if (layers > 0 && w0 <= kWinPasses * layers) {
-        for (int32_t x0 = 0; x0 < w0; x0 += layers) {
-            const int32_t x1 = min(x0 + layers, w0);
-            if (valid) {
-                window_add(ccq, box, x0, x1, w1, w2, sq, cq, s_acc, G, scale);
-                window_add(ccs, box, x0, x1, w1, w2, ss, cs, s_acc, G, scale);
-            }
-            __syncthreads();
-            window_flush(B, s, box, x0, w1, w2, (x1 - x0) * (int32_t)w12, s_acc, G, scale);
-            __syncthreads();
+    const Window W = choose_window(box);
+    if (W.passes == 0) {
+        if (valid) {
+            direct_add(sq, cq, G, scale);
+            direct_add(ss, cs, G, scale);
         }
     } else {
-        octant_path(valid, sq, ss, pack_local(ccq), pack_local(ccs), cq, cs, s_keys, s_idx, s_oct, s_wcount, s_acc,
-                    G, scale);
+        for (int32_t p = 0; p < W.passes; ++p) {
+            const int32_t a0 = p * W.layers, a1 = min(a0 + W.layers, W.w[W.ax]);
+            const WinBricks T = slab_bricks(B, s, W, a0, a1, s_wdir);
+            if (valid) {
+                int32_t iq[8], is[8];
+                window_corners(W, a0, a1, ccq, iq);
+                window_corners(W, a0, a1, ccs, is);
+                window_add(iq, sq, cq, p == 0, s_acc, G, scale);
+                window_add(is, ss, cs, p == 0, s_acc, G, scale);
+            }
+            __syncthreads();
+            window_flush(W, a0, a1, T, s_wdir, s_acc, G, scale);
+            __syncthreads();
+        }
     }
     if (kLoss) {
         // tile partials in a fixed order: lanes, then waves
@@ -1053,8 +959,7 @@ gp_status gp_forward_impl(gp_ctx ctx, const float* qx, const float* qy, const fl
     Band B = ctx->band();
     if (ctx->n_tiles > 0) {
         GP_TIMED(ctx, "k_forward_query");
-        k_forward_query<<<(unsigned)ctx->n_tiles, kQueryBlock, 0, st>>>(B, qx, qy, qz, nn, ctx->ox.p, ctx->oy.p,
-                                                                        ctx->oz.p, field, ctx->q_part.p, ctx->flag.p);
+        k_forward_query<<<(unsigned)ctx->n_tiles, kQueryBlock, 0, st>>>(B, qx, qy, qz, nn, ctx->points(), field, ctx->q_part.p, ctx->flag.p);
     }
     if (ctx->n_bricks > 0) {
         GP_TIMED(ctx, "k_tv_forward");
@@ -1076,7 +981,7 @@ gp_status gp_backward_impl(gp_ctx ctx, const float* qx, const float* qy, const f
     if (ctx->n_tiles > 0) {
         GP_TIMED(ctx, "k_backward_query");
         k_query_grad<false><<<(unsigned)(ctx->n_tiles * kGradParts), kGradBlock, 0, st>>>(
-            B, qx, qy, qz, nn, ctx->ox.p, ctx->oy.p, ctx->oz.p, field, w, dloss, ctx->inv_qv.p, grad, nullptr,
+            B, qx, qy, qz, nn, ctx->points(), field, w, dloss, ctx->inv_qv.p, grad, nullptr,
             ctx->flag.p);
     }
     if (ctx->n_bricks > 0) {
@@ -1096,7 +1001,7 @@ gp_status gp_forward_backward_impl(gp_ctx ctx, const float* qx, const float* qy,
     if (ctx->n_tiles > 0) {
         GP_TIMED(ctx, "k_query_grad");
         k_query_grad<true><<<(unsigned)(ctx->n_tiles * kGradParts), kGradBlock, 0, st>>>(
-            B, qx, qy, qz, nn, ctx->ox.p, ctx->oy.p, ctx->oz.p, field, w, dloss, ctx->inv_qv.p, ctx->g_raw.p,
+            B, qx, qy, qz, nn, ctx->points(), field, w, dloss, ctx->inv_qv.p, ctx->g_raw.p,
             ctx->q_part.p, ctx->flag.p);
     }
     if (ctx->n_bricks > 0) {

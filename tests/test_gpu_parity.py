@@ -62,12 +62,12 @@ def test_sphere_64_parity(m1, m2):
     prob.close()
 
 
-def _window_passes(dom, pts, q, nn, cf, block=256, window=4608, max_passes=4):
-    """Per block of the gradient pass: how many x-slab passes of the dense LDS
-    window (`window` vertices) its vertex box takes, or 0 for the octant cache
-    (a box layer larger than the window, or more than max_passes slabs).  The
-    box covers the cells of the block's queries in the M1 band and of their
-    nearest points."""
+def _window_passes(dom, pts, q, nn, cf, block=256, cap=4608, max_passes=16):
+    """Per block of the gradient pass, how many slab passes of the LDS window
+    (cap vertices) its vertex box takes, or 0 when it takes none (its
+    contributions go straight to the gradient).  The box covers the cells of
+    the block's queries in the M1 band and of their nearest points, plus one
+    vertex; slabs are whole layers along x or y, whichever is longer."""
     R = np.array(dom.dims)
     cell = lambda x: np.clip(np.floor((x.astype(np.float64) - dom.lo) / dom.h), 0, R - 1).astype(np.int64)
     cq, cs = cell(q), cell(pts[nn])
@@ -79,37 +79,45 @@ def _window_passes(dom, pts, q, nn, cf, block=256, window=4608, max_passes=4):
             continue
         c = np.concatenate([cq[b:b + block][m], cs[b:b + block][m]])
         w = c.max(0) - c.min(0) + 2
-        layers = window // (w[1] * w[2])
-        passes = -(-w[0] // layers) if layers > 0 else 0
+        ax = 1 if w[1] > w[0] else 0
+        cross = w[1 - ax] * w[2]
+        if cross > cap:
+            out.append(0)
+            continue
+        layers = min(w[ax], cap // cross)
+        passes = -(-w[ax] // layers)
         out.append(passes if passes <= max_passes else 0)
     return np.array(out)
 
 
-@pytest.mark.parametrize("case", ["one slab", "several slabs", "octants"])
+@pytest.mark.parametrize("case", ["one pass", "several passes", "no window"])
 def test_gradient_accumulation_paths(case):
-    """A block of the gradient pass sums its contributions in a dense LDS
-    window over its vertex box, in one pass or in up to four x slabs, and in
-    LDS copies of the octants they fall in when the box is larger still.
-    Queries around cell-sorted points with a small spread keep every block's
-    box within one window; a larger spread needs several slabs; sources drawn
-    at random spread every block over the sphere (the octants).  The path of
-    every block is computed on the host; each case against the oracle."""
+    """A block of the gradient pass sums its contributions in an LDS window
+    over the box of its cells, in one pass or in slabs of that box, and
+    sends them straight to the gradient when the box would take too many
+    slabs.  Queries around cell-sorted points with a small spread keep every
+    box within one window; a larger spread needs several slabs; sources
+    drawn at random on a finer grid spread every block over the sphere.
+    The path of every block is computed on the host; each case against the
+    oracle."""
     log("case: gradient accumulation, %s" % case)
-    dom = synth.cube_domain(64)
+    res, n, sigma, strat = {"one pass": (64, 40_000, 0.01, True), "several passes": (64, 80_000, 0.06, True),
+                            "no window": (128, 40_000, 0.01, False)}[case]
+    dom = synth.cube_domain(res)
     pts = synth.sphere_points(10_000, 0.5, seed=21)
-    c = np.minimum(np.floor((pts.astype(np.float64) - dom.lo) / dom.h), 63).astype(np.int64)
-    pts = pts[np.argsort((c[:, 0] * 64 + c[:, 1]) * 64 + c[:, 2], kind="stable")]
-    n, sigma = (10_000, 0.04) if case == "several slabs" else (40_000, 0.01)
-    q = synth.host_queries(pts, n, sigma, seed=22, stratified=(case != "octants"))
+    c = np.minimum(np.floor((pts.astype(np.float64) - dom.lo) / dom.h), res - 1).astype(np.int64)
+    pts = pts[np.argsort((c[:, 0] * res + c[:, 1]) * res + c[:, 2], kind="stable")]
+    q = synth.host_queries(pts, n, sigma, seed=22, stratified=strat)
     D = synth.sphere_sdf_field(dom, 0.5, noise=0.01, seed=23)
     cf, vf, nn, ref = _oracle(dom, pts, q, D)
     passes = _window_passes(dom, pts, q, nn, cf)
-    if case == "one slab":
+    log("  passes per block: %s" % np.bincount(passes).tolist())
+    if case == "one pass":
         assert (passes == 1).all()
-    elif case == "several slabs":
-        assert (passes >= 1).all() and set(passes.tolist()) >= {2, 3, 4}
+    elif case == "several passes":
+        assert (passes >= 1).all() and (passes >= 2).mean() > 0.3
     else:
-        assert (passes == 0).all()
+        assert (passes == 0).mean() > 0.9
     prob = _run_gpu(dom, pts, q, D)
     assert np.array_equal(prob.nn[: len(q)].cpu().numpy(), nn)
     got, nv = loss_terms(prob)
