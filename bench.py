@@ -366,8 +366,7 @@ def build_problem(config: int):
     wl = synth.WORKLOADS[config]()
     log("inputs: %s, %d points, %d queries/step (%.1f s)" % (wl.name, wl.n_points, wl.n_queries,
                                                               time.perf_counter() - t0))
-    hmin = min(min(s.domain.h) for s in wl.shapes)
-    adam = AdamConfig(lr0=wl.lr0_cells * hmin, eps=1e-8 * (5e4 / max(wl.n_queries, 1)))
+    adam = AdamConfig(lr0=wl.lr0(), eps=1e-8 * (5e4 / max(wl.n_queries, 1)))
     specs = [spec_from_synth(s) for s in wl.shapes]
     import torch
 
@@ -388,7 +387,7 @@ def schedule_sweep(kind: str, iters: int = 1600, n_points: int = 200_000, n_quer
     """Whole optimisation runs on the paper's default schedule, one JSON line per setting.
 
     Sec. 4's defaults: 50 000 queries per iteration, 1600 iterations, Adam with
-    lr 1 (one cell here) times 0.3 every 400 iterations, a small-sphere initial
+    lr 1.0 (the domain is [-1, 1]^3) times 0.3 every 400 iterations, a small-sphere initial
     field, M1 = 3 and M2 = 14.  One quantity varies per sweep, as in the
     ablations: the grid resolution R (Tab. 14), the TV band M2 (Tab. 17) or
     the pull band M1 (3 against all cells).  Input: the 200K-point torus,
@@ -416,7 +415,7 @@ def schedule_sweep(kind: str, iters: int = 1600, n_points: int = 200_000, n_quer
         spec = ShapeSpec(pts, dom.dims, dom.lo, dom.hi, n_queries, 2.0 * h)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        prob = Problem([spec], m1=m1, m2=m2, adam=AdamConfig(lr0=h, eps=1e-8))
+        prob = Problem([spec], m1=m1, m2=m2, adam=AdamConfig(lr0=1.0, eps=1e-8))
         torch.cuda.synchronize()
         setup_s = time.perf_counter() - t0
         prob.iteration(1)
@@ -460,7 +459,7 @@ def surface_runs(iters: int = 1600, n_queries: int = 50_000):
 
     Each setting optimises from the small-sphere initial field (M1 = 3,
     M2 = 14, 50 000 queries per iteration, sigma = 2 cells, 1600 iterations
-    with lr 1 cell x 0.3 every 400), extracts the zero level set with
+    with lr 1.0 x 0.3 every 400), extracts the zero level set with
     gp_extract_surface and measures it against the closed-form surface the
     points were drawn from: CD-L1, normal consistency and F-score at
     tau = 0.005 (the shapes span about 1.3 units).  The same measures of the
@@ -495,7 +494,7 @@ def surface_runs(iters: int = 1600, n_queries: int = 50_000):
         dom = synth.cube_domain(res)
         h = dom.h[0]
         prob = Problem([ShapeSpec(pts, dom.dims, dom.lo, dom.hi, n_queries, 2.0 * h)], m1=3, m2=14,
-                       weights=(alpha, 1.0, 0.005), adam=AdamConfig(lr0=h, eps=1e-8))
+                       weights=(alpha, 1.0, 0.005), adam=AdamConfig(lr0=1.0, eps=1e-8))
         if normals is not None:
             prob.set_normals(normals, 1.0)
         prob.iteration(1)

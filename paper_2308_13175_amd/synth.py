@@ -375,7 +375,17 @@ class Workload:
     m1: int = 3
     m2: int = 3
     iters: int = 20
-    lr0_cells: float = 1.0        # learning rate in units of the smallest cell size
+    # Adam's initial learning rate in world units: lr0_cells cells of the
+    # smallest cell size when given (the sphere workload starts at the
+    # closed-form field), else 1.0 in the units of the domain scaled to
+    # [-1, 1] on its longest side (half that side)
+    lr0_cells: Optional[float] = None
+
+    def lr0(self) -> float:
+        d = self.shapes[0].domain
+        if self.lr0_cells is not None:
+            return self.lr0_cells * min(min(s.domain.h) for s in self.shapes)
+        return 0.5 * max(d.hi[a] - d.lo[a] for a in range(3))
 
     @property
     def n_points(self) -> int:

@@ -58,7 +58,7 @@ def _sphere_setup():
     wl = synth.sphere_workload()
     s = wl.shapes[0]
     dom = s.domain
-    lr0 = wl.lr0_cells * dom.h[0]
+    lr0 = wl.lr0()
     D0 = synth.sphere_sdf_field(dom, 0.5, noise=0.01, seed=0)
     prob = make_problem([spec(s.points, dom, s.n_queries, s.sigma)], adam=AdamConfig(lr0=lr0))
     prob.set_dense_field([D0])
