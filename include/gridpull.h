@@ -252,6 +252,24 @@ gp_status gp_pull_forward(gp_ctx ctx, const float* qx, const float* qy, const fl
                           gp_weights w, double* loss_out, int64_t* n_valid_out);
 
 /*
+ * For callers that cannot allocate (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): the loss of
+ * gp_pull_forward, same arguments and same loss_out / n_valid_out, with no
+ * allocation at all.  It neither allocates nor uses the context's scratch:
+ * its partial sums live in a static device array of 8 MiB per GPU, held
+ * until the process ends, and it leaves the context's forward state (what a
+ * gp_pull_backward reuses, and gp_forward_token) as it was.  It stores no
+ * per-vertex tau, so no backward follows it.  Calls that overlap on one GPU
+ * (several contexts or threads on one device) share that array and race.
+ * Errors: as gp_pull_forward, and GP_ERR_CAPACITY when the band needs more
+ * scratch than 8 MiB (8 * (4 * tiles + bricks + 161 * shapes) + 4 * shapes
+ * bytes, with tiles = ceil(queries / 1024) per shape).
+ */
+gp_status gp_pull_forward_static(gp_ctx ctx, const float* qx, const float* qy, const float* qz,
+                                 const int32_t* nn, int64_t n_queries, const float* field,
+                                 gp_weights w, double* loss_out, int64_t* n_valid_out);
+
+/*
  * Token of the last forward (gp_pull_forward or gp_pull_forward_backward) on
  * this context, or 0 if there is none or it is no longer usable: a later call
  * of this library that writes its query, nearest-point or field array

@@ -300,6 +300,18 @@ gp_status gp_pull_forward(gp_ctx ctx, const float* qx, const float* qy, const fl
     return GP_OK;
 }
 
+gp_status gp_pull_forward_static(gp_ctx ctx, const float* qx, const float* qy, const float* qz, const int32_t* nn,
+                                 int64_t n_queries, const float* field, gp_weights w, double* loss_out,
+                                 int64_t* n_valid_out)
+{
+    gp_status st = ready(ctx);
+    if (st != GP_OK) return st;
+    if ((st = check_queries(ctx, qx, qy, qz, n_queries)) != GP_OK) return st;
+    if ((n_queries > 0 && !nn) || !field || !loss_out || !n_valid_out)
+        return gp_fail(ctx, GP_ERR_ARG, "null argument");
+    return gp_forward_static_impl(ctx, qx, qy, qz, nn, field, w, loss_out, n_valid_out);
+}
+
 uint64_t gp_forward_token(gp_ctx ctx)
 {
     return ctx ? ctx->fwd_token : 0;

@@ -454,6 +454,8 @@ gp_status gp_step_consts_impl(gp_ctx ctx, int32_t t, float lr0, float decay, int
 gp_status gp_forward_impl(gp_ctx ctx, const float* qx, const float* qy, const float* qz,
                           const int32_t* nn, const float* field, gp_weights w,
                           double* loss_out, int64_t* n_valid_out);
+gp_status gp_forward_static_impl(gp_ctx ctx, const float* qx, const float* qy, const float* qz, const int32_t* nn,
+                                 const float* field, gp_weights w, double* loss_out, int64_t* n_valid_out);
 gp_status gp_backward_impl(gp_ctx ctx, const float* qx, const float* qy, const float* qz,
                            const int32_t* nn, const float* field, gp_weights w,
                            const double* dloss, float* grad);

@@ -16,6 +16,7 @@
 //   the gradient is gathered per vertex (each vertex writes only its own
 //   slot).
 #include <algorithm>
+#include <mutex>
 
 #include "gp_internal.h"
 
@@ -471,7 +472,8 @@ __global__ __launch_bounds__(kGradBlock) void k_query_grad(Band B, const float* 
 // ---- TV (Eq. 5).  A vertex takes part only if it is a TV vertex (V2 mask),
 // and so does each of its six axis neighbours; a missing brick or a vertex
 // outside the grid is not a TV vertex.  The forward stores 1/tau (0 where
-// tau = 0) for the backward, which then divides nothing.  Two layouts of the
+// tau = 0) for the backward, which then divides nothing (unless it is given
+// no array for it: the loss alone).  Two layouts of the
 // same arithmetic:
 // - one block per brick, one thread per vertex, the brick and a one-vertex
 //   halo staged in LDS: many waves for a band of few bricks;
@@ -558,7 +560,7 @@ __global__ __launch_bounds__(kBrickVol) void k_tv_forward_brick(Band B, const fl
             s2 = fmaf(d, d, s2);
         }
         tau_v = sqrtf(s2);
-        itau[brick * kBrickVol + t] = tau_v > 0.f ? 1.f / tau_v : 0.f;
+        if (itau) itau[brick * kBrickVol + t] = tau_v > 0.f ? 1.f / tau_v : 0.f;
     }
     double v = (double)tau_v;
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
@@ -720,7 +722,7 @@ __global__ __launch_bounds__(kTvWaves * 64) void k_tv_forward_wave(Band B, const
     for (int k = 0; k < 8; ++k)
         if ((m >> k) & 1u) {
             const float t = sqrtf(s2[k]);
-            *at32(itau, (uint32_t)(slot0 + k)) = t > 0.f ? 1.f / t : 0.f;
+            if (itau) *at32(itau, (uint32_t)(slot0 + k)) = t > 0.f ? 1.f / t : 0.f;
             sum += (double)t;
         }
     for (int o = 32; o > 0; o >>= 1) sum += __shfl_xor(sum, o, 64);
@@ -932,13 +934,15 @@ static bool tv_wave_layout(gp_ctx ctx, int64_t min_bricks)
     return ctx->tv_layout == 2 || (ctx->tv_layout == 0 && ctx->n_bricks >= min_bricks);
 }
 
-static void launch_tv_forward(gp_ctx ctx, const Band& B, const float* field, hipStream_t st)
+// itau may be null (the loss alone); tv_part receives the per-brick sums.
+static void launch_tv_forward(gp_ctx ctx, const Band& B, const float* field, float* itau, double* tv_part,
+                              hipStream_t st)
 {
     if (tv_wave_layout(ctx, kTvWaveMinBricksFwd))
         k_tv_forward_wave<<<(unsigned)((ctx->n_bricks + kTvWaves - 1) / kTvWaves), kTvWaves * 64, 0, st>>>(
-            B, field, ctx->tau.p, ctx->tv_part.p, (int32_t)ctx->n_bricks);
+            B, field, itau, tv_part, (int32_t)ctx->n_bricks);
     else
-        k_tv_forward_brick<<<(unsigned)ctx->n_bricks, kBrickVol, 0, st>>>(B, field, ctx->tau.p, ctx->tv_part.p);
+        k_tv_forward_brick<<<(unsigned)ctx->n_bricks, kBrickVol, 0, st>>>(B, field, itau, tv_part);
 }
 
 static void launch_tv_backward(gp_ctx ctx, const Band& B, const float* field, gp_weights w, const double* dloss,
@@ -963,7 +967,7 @@ gp_status gp_forward_impl(gp_ctx ctx, const float* qx, const float* qy, const fl
     }
     if (ctx->n_bricks > 0) {
         GP_TIMED(ctx, "k_tv_forward");
-        launch_tv_forward(ctx, B, field, st);
+        launch_tv_forward(ctx, B, field, ctx->tau.p, ctx->tv_part.p, st);
     }
     GP_TIMED(ctx, "k_finalize");
     k_finalize<<<dim3(kFinChunks, (unsigned)ctx->n_shapes), kFinalizeBlock, 0, st>>>(
@@ -1006,7 +1010,7 @@ gp_status gp_forward_backward_impl(gp_ctx ctx, const float* qx, const float* qy,
     }
     if (ctx->n_bricks > 0) {
         GP_TIMED(ctx, "k_tv_forward");
-        launch_tv_forward(ctx, B, field, st);
+        launch_tv_forward(ctx, B, field, ctx->tau.p, ctx->tv_part.p, st);
     }
     {
         GP_TIMED(ctx, "k_finalize");
@@ -1018,6 +1022,89 @@ gp_status gp_forward_backward_impl(gp_ctx ctx, const float* qx, const float* qy,
         GP_TIMED(ctx, "k_tv_backward");
         launch_tv_backward(ctx, B, field, w, dloss, ctx->g_raw.p, grad, st);
     }
+    GP_HIP(ctx, hipGetLastError());
+    return GP_OK;
+}
+
+// ---------------------------------------------------------------------------
+// gp_pull_forward_static: the loss of gp_pull_forward with no allocation and
+// no context scratch.  Its scratch (the per-tile and per-brick partial sums,
+// the chunk sums and counter of the reduction, the reciprocal valid counts)
+// lives in the file-scope device array `scratch`; every GPU holds its own copy
+// until the process ends, and host code reaches it only through the address
+// hipGetSymbolAddress gives for that device (the array's name is no device
+// address on the host).  The copy keeps the last call's contents, so the
+// reduction counter is cleared (by a small kernel, never a memset node) at
+// the start of every call; calls that overlap on one GPU share the array and
+// race.
+constexpr size_t kStaticScratchBytes = (size_t)8 << 20;
+constexpr int kStaticMaxDevices = 64;
+
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+static std::mutex g_scratch_mutex;
+static void* g_scratch_ptr[kStaticMaxDevices] = {};
+
+// The device address of `scratch` on the context's device (current), found
+// once per device.
+static gp_status static_scratch(gp_ctx ctx, unsigned char** out)
+{
+    if (ctx->device < 0 || ctx->device >= kStaticMaxDevices)
+        return gp_fail(ctx, GP_ERR_DEVICE, "device index beyond the static scratch table");
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (!g_scratch_ptr[ctx->device]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) return gp_hip_fail(ctx, e == hipSuccess ? hipErrorInvalidSymbol : e,
+                                                      "hipGetSymbolAddress(scratch)");
+        g_scratch_ptr[ctx->device] = p;
+    }
+    *out = static_cast<unsigned char*>(g_scratch_ptr[ctx->device]);
+    return GP_OK;
+}
+
+namespace gp {
+namespace {
+
+__global__ void k_zero_i32(int32_t* __restrict__ p, int32_t n)
+{
+    const int32_t i = (int32_t)(blockIdx.x * blockDim.x + threadIdx.x);
+    if (i < n) p[i] = 0;
+}
+
+}  // namespace
+}  // namespace gp
+
+gp_status gp_forward_static_impl(gp_ctx ctx, const float* qx, const float* qy, const float* qz, const int32_t* nn,
+                                 const float* field, gp_weights w, double* loss_out, int64_t* n_valid_out)
+{
+    // layout (in doubles): tile partials [n_tiles * 4], brick partials
+    // [n_bricks], chunk sums [n_shapes * kFinChunks * 5], reciprocal valid
+    // counts [n_shapes], then the chunk counters [n_shapes] (int32)
+    const int64_t n_q = std::max<int64_t>(ctx->n_tiles, 1) * 4, n_t = std::max<int64_t>(ctx->n_bricks, 1);
+    const int64_t n_f = (int64_t)ctx->n_shapes * kFinChunks * 5, n_i = ctx->n_shapes;
+    const int64_t need = (n_q + n_t + n_f + n_i) * 8 + (int64_t)ctx->n_shapes * 4;
+    if (need > (int64_t)kStaticScratchBytes)
+        return gp_fail(ctx, GP_ERR_CAPACITY, "gp_pull_forward_static needs " + std::to_string(need) +
+                                                 " bytes of scratch for this band, beyond its " +
+                                                 std::to_string(kStaticScratchBytes));
+    unsigned char* base = nullptr;
+    gp_status stt = static_scratch(ctx, &base);
+    if (stt != GP_OK) return stt;
+    double* q_part = reinterpret_cast<double*>(base);
+    double* tv_part = q_part + n_q;
+    double* fin_part = tv_part + n_t;
+    double* inv_qv = fin_part + n_f;
+    int32_t* fin_count = reinterpret_cast<int32_t*>(inv_qv + n_i);
+    hipStream_t st = ctx->stream;
+    Band B = ctx->band();
+    k_zero_i32<<<(unsigned)((ctx->n_shapes + 255) / 256), 256, 0, st>>>(fin_count, ctx->n_shapes);
+    if (ctx->n_tiles > 0)
+        k_forward_query<<<(unsigned)ctx->n_tiles, kQueryBlock, 0, st>>>(B, qx, qy, qz, nn, ctx->points(), field,
+                                                                        q_part, ctx->flag.p);
+    if (ctx->n_bricks > 0) launch_tv_forward(ctx, B, field, nullptr, tv_part, st);
+    k_finalize<<<dim3(kFinChunks, (unsigned)ctx->n_shapes), kFinalizeBlock, 0, st>>>(
+        B, q_part, tv_part, w, loss_out, n_valid_out, inv_qv, ctx->flag.p, 1, fin_part, fin_count);
     GP_HIP(ctx, hipGetLastError());
     return GP_OK;
 }

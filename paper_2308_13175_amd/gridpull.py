@@ -23,7 +23,7 @@ STATUS = {0: "GP_OK", 1: "GP_ERR_ARG", 2: "GP_ERR_DOMAIN", 3: "GP_ERR_CAPACITY",
           5: "GP_ERR_DEVICE", 6: "GP_ERR_STATE", 7: "GP_ERR_NUMERIC"}
 
 EXPORTS = ("gp_create", "gp_destroy", "gp_last_error", "gp_set_stream", "gp_sync", "gp_build_band",
-           "gp_nn_query", "gp_set_nn_params", "gp_get_nn_params", "gp_autotune_nn", "gp_set_tv_layout", "gp_sample_queries", "gp_pull_forward", "gp_forward_token", "gp_pull_backward", "gp_pull_forward_backward", "gp_pull_normals", "gp_step",
+           "gp_nn_query", "gp_set_nn_params", "gp_get_nn_params", "gp_autotune_nn", "gp_set_tv_layout", "gp_sample_queries", "gp_pull_forward", "gp_pull_forward_static", "gp_forward_token", "gp_pull_backward", "gp_pull_forward_backward", "gp_pull_normals", "gp_step",
            "gp_shape_slots", "gp_export_layout", "gp_export_active_cells", "gp_extract_surface", "gp_gather_vertices", "gp_scatter_vertices",
            "gp_init_sphere", "gp_timing_enable", "gp_timing_report")
 
@@ -82,6 +82,7 @@ def load_library(path: str = LIB_PATH):
         "gp_pull_forward": (st, [P, P, P, P, P, i64, P, gp_weights, P, P]),
         "gp_pull_backward": (st, [P, P, P, P, P, i64, P, gp_weights, P, P, u64]),
         "gp_forward_token": (u64, [P]),
+        "gp_pull_forward_static": (st, [P, P, P, P, P, i64, P, gp_weights, P, P]),
         "gp_pull_forward_backward": (st, [P, P, P, P, P, i64, P, gp_weights, P, P, P, P]),
         "gp_pull_normals": (st, [P, P, P, P, P, i64, P, P, P, P, f32, P, P, P]),
         "gp_step": (st, [P, P, P, P, P, i32, f32, f32, i32, f32, f32, f32]),
@@ -233,6 +234,14 @@ def _weights(alpha, beta, gamma):
 def gp_pull_forward(ctx, qx, qy, qz, nn, field, weights, loss_out, n_valid_out) -> None:
     _stream(ctx)
     _check(ctx, load_library().gp_pull_forward(
+        ctx, _ptr(qx, torch.float32), _ptr(qy, torch.float32), _ptr(qz, torch.float32), _ptr(nn, torch.int32),
+        qx.numel(), _ptr(field, torch.float32), _weights(*weights), _ptr(loss_out, torch.float64),
+        _ptr(n_valid_out, torch.int64)))
+
+
+def gp_pull_forward_static(ctx, qx, qy, qz, nn, field, weights, loss_out, n_valid_out) -> None:
+    _stream(ctx)
+    _check(ctx, load_library().gp_pull_forward_static(
         ctx, _ptr(qx, torch.float32), _ptr(qy, torch.float32), _ptr(qz, torch.float32), _ptr(nn, torch.int32),
         qx.numel(), _ptr(field, torch.float32), _weights(*weights), _ptr(loss_out, torch.float64),
         _ptr(n_valid_out, torch.int64)))
