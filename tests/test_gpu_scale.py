@@ -60,42 +60,50 @@ def test_union24_2M_256_full_size():
     _full_parity(s.points, s.domain, q, D, sigma=s.sigma)
 
 
-def test_room_20M_full_grid():
-    log("case: room, 20M points, 1024x820x308, 2M sampled queries")
+def test_room_20M_full_grid_sampler_stream():
+    """The room at its full grid: a 2M-query slice of the GPU sampler's own
+    stream for the workload's 32M queries (stratified sources over the
+    cell-sorted points, sigma = 2h), block-aligned, so that the gradient
+    pass's blocks see the windows and slabs of the real run at full-grid
+    coordinates."""
+    log("case: room, 20M points, 1024x820x308, 2M queries of the sampler's 32M stream")
     wl = synth.room_workload()
     s = wl.shapes[0]
-    q = synth.host_queries(s.points, 2_000_000, s.sigma, seed=7, stratified=False)
+    stream = make_problem([spec(s.points, s.domain, s.n_queries, s.sigma)])
+    stream.sample(seed=11, iteration=3)
+    k0, n = 10 * 1024 * 1024, 2_000_000
+    q = stream.queries()[k0:k0 + n].copy()
+    stream.close()
+    log("  sampled")
     ctr = [0.5 * (s.domain.lo[a] + s.domain.hi[a]) for a in range(3)]
     D = synth.sphere_sdf_field(s.domain, 2.0, noise=0.002, seed=4, centre=ctr)
     _full_parity(s.points, s.domain, q, D, sigma=s.sigma)
 
 
 def test_batched_64_shapes_vs_single_and_oracle():
-    """64 uneven shapes in one context: each shape equals its own single-shape
+    """64 uneven shapes in one context, Q_i = 10 J_i queries each from the GPU
+    sampler's stream (sigma = 2 h_i): each shape equals its own single-shape
     run (1e-5 relative) and the oracle."""
-    log("case: 64 shapes batched (queries = points per shape)")
+    log("case: 64 shapes batched, queries = 10 x points per shape")
     wl = synth.batched_workload()
-    specs = []
-    qs = []
-    Ds = []
-    for i, s in enumerate(wl.shapes):
-        q = synth.host_queries(s.points, len(s.points), s.sigma, seed=100 + i)
-        specs.append(spec(s.points, s.domain, len(q), s.sigma))
-        qs.append(q)
-        Ds.append(synth.sphere_sdf_field(s.domain, 0.4, noise=0.01, seed=i))
+    specs = [spec(s.points, s.domain, s.n_queries, s.sigma) for s in wl.shapes]
+    Ds = [synth.sphere_sdf_field(s.domain, 0.4, noise=0.01, seed=i) for i, s in enumerate(wl.shapes)]
     batch = make_problem(specs)
     batch.set_dense_field(Ds)
-    batch.set_queries(np.concatenate(qs))
+    batch.sample(seed=21, iteration=2)
     batch.nearest()
     batch.forward()
     batch.backward()
     batch.sync()
+    qall = batch.queries()
     bl, bn = loss_terms(batch)
     bg = batch.dense_grad()
     bnn = batch.nn[: batch.n_queries].cpu().numpy()
+    batch.close()
+    log("  batch done: %d queries" % len(qall))
     off = 0
     for i, s in enumerate(wl.shapes):
-        q = qs[i]
+        q = qall[off:off + s.n_queries]
         single = make_problem([specs[i]])
         single.set_dense_field([Ds[i]])
         single.set_queries(q)
@@ -110,15 +118,13 @@ def test_batched_64_shapes_vs_single_and_oracle():
         sg = single.dense_grad()[0]
         assert np.max(np.abs(bg[i] - sg)) <= 1e-5 * np.abs(sg).max()
         single.close()
-        if i % 8 == 0:      # oracle on every eighth shape (all sizes are represented)
-            dom = s.domain
-            cf, vf = oracle.build_band(dom.dims, dom.lo, dom.hi, s.points, 3, 3)
-            nn_ref = oracle.nn_exact(q, s.points)
-            assert np.array_equal(bnn[off:off + len(q)], nn_ref)
-            ref = oracle.loss_grad(dom.dims, dom.lo, dom.hi, cf, vf, Ds[i].astype(np.float64), q, nn_ref,
-                                   s.points)
-            assert_terms_close(bl[i], ref)
-            assert_grad_close(bg[i], ref["dD"])
-            log("  shape %d (J=%d, R=%d) ok" % (i, len(s.points), dom.dims[0]))
+        dom = s.domain
+        cf, vf = oracle.build_band(dom.dims, dom.lo, dom.hi, s.points, 3, 3)
+        nn_ref = oracle.nn_exact(q, s.points)
+        assert np.array_equal(bnn[off:off + len(q)], nn_ref)
+        ref = oracle.loss_grad(dom.dims, dom.lo, dom.hi, cf, vf, Ds[i].astype(np.float64), q, nn_ref, s.points)
+        assert int(bn[i]) == ref["n_valid"]
+        assert_terms_close(bl[i], ref)
+        assert_grad_close(bg[i], ref["dD"])
+        log("  shape %d (J=%d, Q=%d, R=%d) ok" % (i, len(s.points), len(q), dom.dims[0]))
         off += len(q)
-    batch.close()
