@@ -460,7 +460,8 @@ def surface_runs(iters: int = 1600, n_queries: int = 50_000):
     Each setting optimises from the small-sphere initial field (M1 = 3,
     M2 = 14, 50 000 queries per iteration, sigma = 2 cells, 1600 iterations
     with lr 1.0 x 0.3 every 400), extracts the zero level set with
-    gp_extract_surface and measures it against the closed-form surface the
+    gp_extract_surface (marching cubes; the tetrahedra mesh is measured
+    beside it) and measures it against the closed-form surface the
     points were drawn from: CD-L1, normal consistency and F-score at
     tau = 0.005 (the shapes span about 1.3 units).  The same measures of the
     mesh of the closed-form SDF sampled on the same band are reported beside
@@ -527,12 +528,16 @@ def surface_runs(iters: int = 1600, n_queries: int = 50_000):
         extract_ms = (time.perf_counter() - t0) * 1e3
         tri = tri.cpu().numpy()
         m = metrics.reconstruction_metrics(tri, ref, sdf, grad, tau=0.005)
+        ttri, _ = gp.gp_extract_surface(prob.ctx, 0, prob.field, method=1)
+        m_tet = metrics.reconstruction_metrics(ttri.cpu().numpy(), ref, sdf, grad, tau=0.005)
         print(json.dumps({"surface": name, "res": res, "m1": 3, "m2": 14, "alpha": alpha,
                           "normal_weight": 1.0 if normals is not None else 0.0, "iterations": iters,
                           "queries_per_iteration": n_queries, "run_s": run_s, "triangles": int(len(tri)),
                           "extract_ms": extract_ms, **m,
                           "closed_form_field": {"triangles": int(len(etri)),
-                                                **{k: m_exact[k] for k in ("cd_l1", "nc", "fscore")}}}),
+                                                **{k: m_exact[k] for k in ("cd_l1", "nc", "fscore")}},
+                          "marching_tetrahedra": {"triangles": int(len(ttri)),
+                                                  **{k: m_tet[k] for k in ("cd_l1", "nc", "fscore")}}}),
               flush=True)
         del graph
         prob.close()

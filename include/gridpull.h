@@ -388,27 +388,39 @@ gp_status gp_export_active_cells(gp_ctx ctx, int32_t shape, int64_t* cell_ids, i
 /*
  * Mesh of the zero level set of `field` over the cells of one shape whose
  * eight corners are optimised vertices (the surface extracted after the
- * optimisation, Sec. 3/4).  Marching tetrahedra: each such cell is cut into
- * six tetrahedra along its main diagonal, (0, A, B, 7) for the corner paths
- * 0 -> A -> B -> 7 (corner (a, b, c) at index 4a + 2b + c), which neighbouring
- * cells cut alike, so the mesh has no cracks.  A corner is inside where
- * f < 0; a tetrahedron with one corner on one side gives one triangle, two
- * and two give two; each triangle corner is p + f_p / (f_p - f_q) (q - p) on
- * an edge from its inside end p to its outside end q, in double (vertex
- * positions lo + i * (hi - lo) / R), rounded to float at the end.
+ * optimisation: Sec. 3, last paragraph, cells not optimised are skipped;
+ * Sec. 4 "Details", marching cubes).  A corner is inside where f < 0.
+ * method 0, marching cubes: a cell's triangles follow from which of its
+ * corners are inside (corner (a, b, c) at index 4a + 2b + c), by one rule:
+ * on each face, walked counter-clockwise from outside, every run of inside
+ * corners is cut off by a segment from the edge where the walk leaves it to
+ * the edge where it entered (diagonal inside corners of a face are cut off
+ * separately, the same from both cells of the face: no cracks); the
+ * segments close into loops from the lowest crossed edge (edges along axis
+ * d numbered 4d + 2u + v by the other two coordinates), each loop fanned
+ * from its first edge.  At most 5 triangles per cell.
+ * method 1, marching tetrahedra: each cell is cut into six tetrahedra along
+ * its main diagonal, (0, A, B, 7) for the corner paths 0 -> A -> B -> 7,
+ * which neighbouring cells cut alike; one corner against three gives one
+ * triangle, two and two give two.
+ * Either way each triangle corner is p + f_p / (f_p - f_q) (q - p) on an edge
+ * from its inside end p to its outside end q, in double (vertex positions
+ * lo + i * (hi - lo) / R), rounded to float at the end.
  * field:   device float [n_slots] (the slot layout of gp_build_band).
  * tri_xyz: device float [capacity][3][3], the corners' x, y, z.
- * tri_key: device int64 [capacity], cell_id * 16 + tetrahedron * 2 +
- *          triangle (cell_id x-major), ascending; the triangles follow it.
+ * tri_key: device int64 [capacity], cell_id * 16 + the triangle's number in
+ *          its cell (method 1: tetrahedron * 2 + triangle; cell_id x-major),
+ *          ascending; the triangles follow it.
  * n_out:   host; the number of triangles.  With capacity 0 (outputs may be
  *          NULL) only the count is returned.
  * Synchronises; allocates temporary device memory (about 40 bytes per
  * triangle plus 8 per slot of the shape).
- * Errors: GP_ERR_STATE before gp_build_band, GP_ERR_ARG, GP_ERR_CAPACITY
- * (capacity below the count; n_out is set), GP_ERR_OOM.
+ * Errors: GP_ERR_STATE before gp_build_band, GP_ERR_ARG (also a method
+ * other than 0 or 1), GP_ERR_CAPACITY (capacity below the count; n_out is
+ * set), GP_ERR_OOM.
  */
 gp_status gp_extract_surface(gp_ctx ctx, int32_t shape, const float* field, float* tri_xyz, int64_t* tri_key,
-                             int64_t capacity, int64_t* n_out);
+                             int64_t capacity, int64_t* n_out, int32_t method);
 
 /* field[slot] = dense[dense_off(s) + vertex id] for every slot (0 where the
  * slot has no vertex), where dense is the concatenation, in shape order, of

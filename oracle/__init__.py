@@ -61,6 +61,10 @@ def _load():
     lib.og_query_offsets.argtypes = [u64, u32, u32, i64, i64, P]
     lib.og_extract_surface.restype = i64
     lib.og_extract_surface.argtypes = [P, P, P, P, P, i64, P, P]
+    lib.og_marching_cubes.restype = i64
+    lib.og_marching_cubes.argtypes = [P, P, P, P, P, i64, P, P]
+    lib.og_mc_counts.restype = None
+    lib.og_mc_counts.argtypes = [P]
     lib.og_normal_term.restype = i64
     lib.og_normal_term.argtypes = [P, P, P, P, P, P, P, P, P, i64, P, P, P, P, P, P, f64, f64, P, P]
     _lib = lib
@@ -246,6 +250,33 @@ def extract_surface(dims, lo, hi, D: np.ndarray, vert_flags: np.ndarray):
     xyz = np.zeros((max(n, 1), 3, 3), dtype=np.float64)
     lib.og_extract_surface(_p(R), _p(L), _p(H), _p(Dd), _p(vf), n, _p(keys), _p(xyz))
     return keys[:n], xyz[:n]
+
+
+def marching_cubes(dims, lo, hi, D: np.ndarray, vert_flags: np.ndarray):
+    """Zero level set of the field over the cells whose eight corners are
+    optimised, by marching cubes (Sec. 3, last paragraph; Sec. 4 "Details");
+    the C file states the face rule that resolves ambiguous faces.  Returns
+    (keys int64 [n] = cell_id * 16 + triangle number in the cell, triangles
+    float64 [n, 3, 3]) in key order."""
+    lib = _load()
+    R, L, H = _grid(dims, lo, hi)
+    Dd = np.ascontiguousarray(D, dtype=np.float64)
+    vf = np.ascontiguousarray(vert_flags, dtype=np.uint8)
+    n = lib.og_marching_cubes(_p(R), _p(L), _p(H), _p(Dd), _p(vf), 0, None, None)
+    if n < 0:
+        raise RuntimeError("marching cubes: a configuration's face segments do not close")
+    keys = np.zeros(max(n, 1), dtype=np.int64)
+    xyz = np.zeros((max(n, 1), 3, 3), dtype=np.float64)
+    lib.og_marching_cubes(_p(R), _p(L), _p(H), _p(Dd), _p(vf), n, _p(keys), _p(xyz))
+    return keys[:n], xyz[:n]
+
+
+def marching_cubes_counts() -> np.ndarray:
+    """Triangles per corner configuration (bit i: corner i = 4a + 2b + c inside)."""
+    lib = _load()
+    out = np.zeros(256, dtype=np.int32)
+    lib.og_mc_counts(_p(out))
+    return out
 
 
 def normal_term(dims, lo, hi, cell_flags, D, queries, nn, points, normals, weight: float = 1.0,

@@ -44,7 +44,7 @@
  *     lowest point index.
  *
  * Parity unpinned: nothing in the paper fixes whether these readings, the
- * sampler, the marching-tetrahedra surface or the normal term are what the
+ * sampler, the marching cubes face rule or the normal term are what the
  * authors ran, nor the reconstruction quality of its tables (no datasets or
  * trained fields here).  Each function is pinned against closed forms,
  * invariants and brute force instead; the tests name the pins.
@@ -624,6 +624,137 @@ int64_t og_extract_surface(const int32_t* R_in, const double* lo, const double* 
         }
     }
     return n;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Marching cubes (Lorensen and Cline, SIGGRAPH 1987): the mesh the paper     */
+/* extracts over the optimised cells (Sec. 3, last paragraph; Sec. 4        */
+/* "Details").  The triangles of a cell depend only on which of its eight     */
+/* corners are inside (f < 0), one of 256 configurations.  They are derived  */
+/* here from one rule rather than taken from a printed case table:          */
+/*  - each face is walked through its corners counter-clockwise as seen from */
+/*    outside the cube; an edge whose ends differ is crossed;                */
+/*  - on each face, every maximal run of inside corners along the walk gets  */
+/*    a segment from the crossed edge where the walk leaves it to the one    */
+/*    where it entered (on a face with two diagonal inside corners the two    */
+/*    are cut off separately: the ambiguity is resolved by the face alone,  */
+/*    the same way in both cells that share it, so the mesh has no cracks);   */
+/*  - a crossed edge ends a segment on one of its faces and starts one on the */
+/*    other, so the segments close into loops; loops are taken from the      */
+/*    smallest unused crossed edge (edge numbers below), and each loop        */
+/*    v0, v1, ..., v_k-1 becomes the fan (v0, v_i, v_i+1), i = 1 .. k-2.     */
+/* Corner (a,b,c) has index 4a + 2b + c.  Edges: along x, 2b + c; along y,   */
+/* 4 + 2a + c; along z, 8 + 2a + b.  A triangle vertex is the zero of the    */
+/* linear interpolant on its edge, from the inside end p: as edge_point.     */
+/* Keys: cell_id * 16 + the triangle's number in its cell.                    */
+/* ------------------------------------------------------------------------ */
+
+/* the faces, counter-clockwise from outside: x = 0, x = 1, y = 0, y = 1, z = 0, z = 1 */
+static const int mc_faces[6][4] = {{0, 1, 3, 2}, {4, 6, 7, 5}, {0, 4, 5, 1},
+                                   {2, 3, 7, 6}, {0, 2, 6, 4}, {1, 5, 7, 3}};
+
+static int mc_edge(int p, int q)
+{
+    int lo = p < q ? p : q, a = (lo >> 2) & 1, b = (lo >> 1) & 1, c = lo & 1;
+    switch (p ^ q) {
+    case 4: return 2 * b + c;          /* along x */
+    case 2: return 4 + 2 * a + c;      /* along y */
+    default: return 8 + 2 * a + b;     /* along z */
+    }
+}
+
+static void mc_edge_ends(int e, int* p, int* q)
+{
+    if (e < 4) { *p = e; *q = 4 + e; }                                      /* (0,b,c)-(1,b,c) */
+    else if (e < 8) { int a = (e - 4) >> 1, c = (e - 4) & 1; *p = 4 * a + c; *q = 4 * a + 2 + c; }
+    else { int a = (e - 8) >> 1, b = (e - 8) & 1; *p = 4 * a + 2 * b; *q = *p + 1; }
+}
+
+/* Triangles (as edge triples) of configuration cfg (bit i: corner i inside);
+ * returns how many, or -1 if the segments do not close into loops. */
+static int mc_triangles(int cfg, int tri[16][3])
+{
+    int next[12], used[12], n = 0;
+    for (int e = 0; e < 12; ++e) { next[e] = -1; used[e] = 0; }
+    for (int F = 0; F < 6; ++F) {
+        const int* c = mc_faces[F];
+        for (int j = 0; j < 4; ++j) {
+            int in_j = (cfg >> c[j]) & 1, in_n = (cfg >> c[(j + 1) % 4]) & 1;
+            if (!(in_j && !in_n)) continue;          /* not where the walk leaves a run */
+            int k = j;
+            while ((cfg >> c[k]) & 1) k = (k + 3) % 4; /* back to the corner before the run */
+            next[mc_edge(c[j], c[(j + 1) % 4])] = mc_edge(c[k], c[(k + 1) % 4]);
+        }
+    }
+    for (int e = 0; e < 12; ++e) {
+        if (next[e] < 0 || used[e]) continue;
+        int loop[12], m = 0, v = e;
+        do {
+            if (v < 0 || m == 12) return -1;         /* segments that do not close: no valid rule */
+            loop[m++] = v;
+            used[v] = 1;
+            v = next[v];
+        } while (v != e);
+        for (int i = 1; i + 1 < m; ++i) {
+            tri[n][0] = loop[0]; tri[n][1] = loop[i]; tri[n][2] = loop[i + 1];
+            ++n;
+        }
+    }
+    return n;
+}
+
+/* The same inputs and outputs as og_extract_surface, by marching cubes
+ * (-1 if the rule fails to close a configuration's segments). */
+int64_t og_marching_cubes(const int32_t* R_in, const double* lo, const double* hi, const double* D,
+                          const uint8_t* vert_flags, int64_t capacity, int64_t* keys, double* xyz)
+{
+    grid_t g;
+    grid_init(&g, R_in, lo, hi);
+    int64_t n = 0;
+    for (int64_t cx = 0; cx < g.R[0]; ++cx)
+    for (int64_t cy = 0; cy < g.R[1]; ++cy)
+    for (int64_t cz = 0; cz < g.R[2]; ++cz) {
+        double P[8][3], f[8];
+        int all = 1, cfg = 0;
+        for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b)
+        for (int c = 0; c < 2; ++c) {
+            int64_t vid = vertex_id(&g, cx + a, cy + b, cz + c);
+            int i = 4 * a + 2 * b + c;
+            if (!(vert_flags[vid] & 1)) all = 0;
+            f[i] = D[vid];
+            if (f[i] < 0.0) cfg |= 1 << i;
+            P[i][0] = g.lo[0] + (double)(cx + a) * g.h[0];
+            P[i][1] = g.lo[1] + (double)(cy + b) * g.h[1];
+            P[i][2] = g.lo[2] + (double)(cz + c) * g.h[2];
+        }
+        if (!all || cfg == 0 || cfg == 255) continue;
+        int64_t c3[3] = {cx, cy, cz};
+        int64_t cid = cell_id(&g, c3);
+        int tri[16][3];
+        int m = mc_triangles(cfg, tri);
+        if (m < 0) return -1;
+        for (int r = 0; r < m; ++r) {
+            if (n < capacity) {
+                keys[n] = cid * 16 + r;
+                for (int v = 0; v < 3; ++v) {
+                    int p, q;
+                    mc_edge_ends(tri[r][v], &p, &q);
+                    if (!(f[p] < 0.0)) { int t = p; p = q; q = t; }   /* p: the inside end */
+                    edge_point(P, f, p, q, xyz + 9 * n + 3 * v);
+                }
+            }
+            ++n;
+        }
+    }
+    return n;
+}
+
+/* The triangle count of every configuration (for the pins). */
+void og_mc_counts(int32_t* out)
+{
+    int tri[16][3];
+    for (int cfg = 0; cfg < 256; ++cfg) out[cfg] = mc_triangles(cfg, tri);
 }
 
 /* ------------------------------------------------------------------------ */

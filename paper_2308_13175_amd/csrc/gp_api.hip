@@ -448,14 +448,15 @@ gp_status gp_export_active_cells(gp_ctx ctx, int32_t shape, int64_t* cell_ids, i
 }
 
 gp_status gp_extract_surface(gp_ctx ctx, int32_t shape, const float* field, float* tri_xyz, int64_t* tri_key,
-                             int64_t capacity, int64_t* n_out)
+                             int64_t capacity, int64_t* n_out, int32_t method)
 {
     gp_status st = ready(ctx);
     if (st != GP_OK) return st;
     if (!n_out || !field || shape < 0 || shape >= ctx->n_shapes || capacity < 0 ||
         (capacity > 0 && (!tri_xyz || !tri_key)))
         return gp_fail(ctx, GP_ERR_ARG, "need a shape index in range, field, n_out, and outputs when capacity > 0");
-    return gp_extract_surface_impl(ctx, shape, field, tri_xyz, tri_key, capacity, n_out);
+    if (method != 0 && method != 1) return gp_fail(ctx, GP_ERR_ARG, "method must be 0 (marching cubes) or 1 (tetrahedra)");
+    return gp_extract_surface_impl(ctx, shape, field, tri_xyz, tri_key, capacity, n_out, method);
 }
 
 gp_status gp_gather_vertices(gp_ctx ctx, const float* dense, float* field)

@@ -470,6 +470,6 @@ gp_status gp_normals_impl(gp_ctx ctx, const float* qx, const float* qy, const fl
                           const float* field, const float* nx, const float* ny, const float* nz, float weight,
                           const double* dloss, double* term_out, float* grad);
 gp_status gp_extract_surface_impl(gp_ctx ctx, int32_t shape, const float* field, float* tri_xyz, int64_t* tri_key,
-                                  int64_t capacity, int64_t* n_out);
+                                  int64_t capacity, int64_t* n_out, int32_t method);
 gp_status gp_gather_impl(gp_ctx ctx, const float* dense, float* field, bool to_field);
 gp_status gp_init_sphere_impl(gp_ctx ctx, const double* centre, const double* radius, float* field);

@@ -89,7 +89,7 @@ def load_library(path: str = LIB_PATH):
         "gp_shape_slots": (st, [P, P]),
         "gp_export_layout": (st, [P, P, P]),
         "gp_export_active_cells": (st, [P, i32, P, i64, ctypes.POINTER(i64)]),
-        "gp_extract_surface": (st, [P, i32, P, P, P, i64, ctypes.POINTER(i64)]),
+        "gp_extract_surface": (st, [P, i32, P, P, P, i64, ctypes.POINTER(i64), i32]),
         "gp_gather_vertices": (st, [P, P, P]),
         "gp_scatter_vertices": (st, [P, P, P]),
         "gp_init_sphere": (st, [P, P, P, P]),
@@ -311,12 +311,14 @@ def gp_pull_normals(ctx, qx, qy, qz, nn, field, nx, ny, nz, weight: float, dloss
                                                _ptr(grad, torch.float32)))
 
 
-def gp_extract_surface(ctx, shape: int, field, device=None):
-    """Zero-level-set triangles of one shape: (tri float32 [n, 3, 3], key int64 [n]), key ascending."""
+def gp_extract_surface(ctx, shape: int, field, device=None, method: int = 0):
+    """Zero-level-set triangles of one shape: (tri float32 [n, 3, 3], key int64 [n]), key ascending.
+    method 0: marching cubes, 1: marching tetrahedra."""
     _stream(ctx)
     lib = load_library()
     n = ctypes.c_int64(0)
-    st = lib.gp_extract_surface(ctx, int(shape), _ptr(field, torch.float32), None, None, 0, ctypes.byref(n))
+    st = lib.gp_extract_surface(ctx, int(shape), _ptr(field, torch.float32), None, None, 0, ctypes.byref(n),
+                                int(method))
     if st not in (GP_OK, GP_ERR_CAPACITY):
         _check(ctx, st)
     dev = device or field.device
@@ -324,7 +326,7 @@ def gp_extract_surface(ctx, shape: int, field, device=None):
     key = torch.empty(max(n.value, 1), dtype=torch.int64, device=dev)
     if n.value > 0:
         _check(ctx, lib.gp_extract_surface(ctx, int(shape), _ptr(field, torch.float32), _ptr(tri, torch.float32),
-                                           _ptr(key, torch.int64), n.value, ctypes.byref(n)))
+                                           _ptr(key, torch.int64), n.value, ctypes.byref(n), int(method)))
     return tri[: n.value], key[: n.value]
 
 

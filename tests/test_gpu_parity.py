@@ -509,12 +509,15 @@ def test_tv_layouts(layout):
         prob.close()
 
 
-def test_surface_extraction():
-    """The zero-level-set mesh over the optimised cells equals the oracle's:
-    the same triangle keys (cell, tetrahedron, triangle) and the same corner
-    coordinates (both computed in double with the same operations, rounded
-    to float), on the noisy sphere and on a random field over an anisotropic
-    grid (many sign changes, cells cut by the band's edge)."""
+@pytest.mark.parametrize("method", [0, 1], ids=["marching cubes", "marching tetrahedra"])
+def test_surface_extraction(method):
+    """The zero-level-set mesh over the optimised cells equals the oracle's,
+    by marching cubes (the paper's mesh step) and by marching tetrahedra:
+    the same triangle keys (cell and the triangle's number in it) and the
+    same corner coordinates (both computed in double with the same
+    operations, rounded to float), on the noisy sphere and on a random field
+    over an anisotropic grid (many sign changes and ambiguous faces, cells
+    cut by the band's edge)."""
     import ctypes
 
     from paper_2308_13175_amd import gridpull as gp
@@ -524,14 +527,15 @@ def test_surface_extraction():
     adom = synth.Domain((24, 17, 31), (-1.125, -0.625, -0.875), (0.875, 0.8125, 1.0625))
     apts = (synth.sphere_points(3000, 0.45, seed=3) + np.float32(0.05)).astype(np.float32)
     aD = (rng.normal(size=adom.n_vertices) * 0.2).astype(np.float32)
+    ref_fn = oracle.marching_cubes if method == 0 else oracle.extract_surface
     for name, (dm, p_, D_, m1, m2) in [("sphere", (dom, pts, D, 3, 3)), ("anisotropic random", (adom, apts, aD, 2, 4))]:
-        log("case: surface extraction, %s" % name)
+        log("case: surface extraction (method %d), %s" % (method, name))
         prob = make_problem([spec(p_, dm, 0, 0.0)], m1=m1, m2=m2)
         prob.set_dense_field([D_])
-        tri, key = gp.gp_extract_surface(prob.ctx, 0, prob.field)
+        tri, key = gp.gp_extract_surface(prob.ctx, 0, prob.field, method=method)
         tri, key = tri.cpu().numpy(), key.cpu().numpy()
         cf, vf = oracle.build_band(dm.dims, dm.lo, dm.hi, p_, m1, m2)
-        rkey, rtri = oracle.extract_surface(dm.dims, dm.lo, dm.hi, D_.astype(np.float64), vf)
+        rkey, rtri = ref_fn(dm.dims, dm.lo, dm.hi, D_.astype(np.float64), vf)
         assert len(rkey) > 100
         assert np.array_equal(key, rkey), "%d vs %d triangles" % (len(key), len(rkey))
         diff = np.abs(tri.astype(np.float64) - rtri.astype(np.float32).astype(np.float64))
@@ -541,8 +545,11 @@ def test_surface_extraction():
         t1 = prob.field.new_empty((1, 3, 3))
         k1 = prob.field.new_empty((1,), dtype=prob.field.dtype).to(dtype=__import__("torch").int64)
         st = gp.load_library().gp_extract_surface(prob.ctx, 0, gp._ptr(prob.field), gp._ptr(t1), gp._ptr(k1), 1,
-                                                  ctypes.byref(n))
+                                                  ctypes.byref(n), method)
         assert st == gp.GP_ERR_CAPACITY and n.value == len(rkey)
+        with pytest.raises(gp.GridPullError) as e:
+            gp.gp_extract_surface(prob.ctx, 0, prob.field, method=2)
+        assert e.value.status == 1
         prob.close()
 
 

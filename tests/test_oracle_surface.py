@@ -121,3 +121,119 @@ def test_metrics_on_the_exact_sphere_mesh():
     m2 = metrics.reconstruction_metrics(tri, surf + np.array([0.05, 0.0, 0.0]), sdf2, grad2, tau=0.01,
                                         n_samples=50_000)
     assert m2["cd_l1"] > 5 * m["cd_l1"] and m2["fscore"] < 0.5
+
+
+# ---------------------------------------------------------------------------
+# Marching cubes (the paper's mesh step)
+# ---------------------------------------------------------------------------
+
+def _mc_one_cell(inside):
+    """One cell over [0,1]^3, corner (a,b,c) at index 4a + 2b + c, value -1
+    at the inside corners and +1 elsewhere."""
+    v = np.ones(8)
+    for i in inside:
+        v[i] = -1.0
+    D = np.zeros(8)
+    for a in range(2):
+        for b in range(2):
+            for c in range(2):
+                D[(a * 2 + b) * 2 + c] = v[4 * a + 2 * b + c]
+    return oracle.marching_cubes((1, 1, 1), (0.0, 0.0, 0.0), (1.0, 1.0, 1.0), D, np.ones(8, np.uint8))
+
+
+def _area(tri):
+    e1 = tri[:, 1] - tri[:, 0]
+    e2 = tri[:, 2] - tri[:, 0]
+    return 0.5 * np.linalg.norm(np.cross(e1, e2), axis=1).sum()
+
+
+def _edge_uses(tri):
+    """Directed and undirected uses of every triangle edge (by exact vertex coordinates)."""
+    directed, undirected = {}, {}
+    for t in tri:
+        pts = [tuple(p) for p in t]
+        for a, b in ((0, 1), (1, 2), (2, 0)):
+            directed[(pts[a], pts[b])] = directed.get((pts[a], pts[b]), 0) + 1
+            e = (min(pts[a], pts[b]), max(pts[a], pts[b]))
+            undirected[e] = undirected.get(e, 0) + 1
+    return directed, undirected
+
+
+def test_mc_hand_counted_cells():
+    """Counted by hand: a corner cut off is one triangle; two corners sharing
+    an edge, or a whole face, a quad (two); a corner with its three edge
+    neighbours, a hexagon (four); two diagonal corners of a face, or two
+    opposite corners of the cube, are cut off separately (two); complements
+    of a single corner, one."""
+    cases = [((), 0), ((0,), 1), ((7,), 1), ((0, 4), 2), ((0, 1, 2, 3), 2), ((0, 1, 2, 4), 4),
+             ((0, 3), 2), ((0, 6), 2), ((0, 7), 2), (tuple(range(1, 8)), 1), (tuple(range(8)), 0)]
+    for inside, expect in cases:
+        keys, tri = _mc_one_cell(inside)
+        assert len(keys) == expect, (inside, len(keys))
+    # values -1 / +1: every vertex is an edge midpoint; corner 0 alone gives the
+    # triangle of the three midpoints next to it
+    keys, tri = _mc_one_cell((0,))
+    assert {tuple(p) for p in tri[0]} == {(0.5, 0.0, 0.0), (0.0, 0.5, 0.0), (0.0, 0.0, 0.5)}
+    counts = oracle.marching_cubes_counts()
+    assert counts.max() == 5 and counts[0] == 0 and counts[255] == 0
+
+
+def test_mc_plane_area_exact():
+    """A tilted plane z = 0.3 + 0.2 x through a dense band over [-1, 1]^3:
+    linear interpolation of a linear field is exact, so every vertex lies on
+    the plane and the mesh covers exactly the plane inside the box,
+    4 sqrt(1 + 0.2^2)."""
+    R = 14
+    dims, lo, hi = (R, R, R), (-1.0,) * 3, (1.0,) * 3
+    g = -1.0 + np.arange(R + 1) * (2.0 / R)
+    X, Y, Z = np.meshgrid(g, g, g, indexing="ij")
+    D = (Z - (0.3 + 0.2 * X)).reshape(-1)
+    keys, tri = oracle.marching_cubes(dims, lo, hi, D, np.ones(D.size, np.uint8))
+    v = tri.reshape(-1, 3)
+    assert np.abs(v[:, 2] - (0.3 + 0.2 * v[:, 0])).max() < 1e-14
+    assert abs(_area(tri) - 4 * np.sqrt(1.04)) < 1e-12
+    assert np.all(np.diff(keys) > 0)
+
+
+def test_mc_sphere_closed_oriented_genus_zero():
+    """The closed-form sphere SDF over a band: the mesh is watertight (every
+    edge in exactly two triangles), consistently oriented (each edge once
+    each way), has the Euler characteristic of a sphere, and its vertices
+    lie within the interpolation error; its area is within that error of
+    4 pi r^2."""
+    R, r = 24, 0.55
+    dims, lo, hi = (R, R, R), (-1.0,) * 3, (1.0,) * 3
+    h = 2.0 / R
+    g = -1.0 + np.arange(R + 1) * h
+    X, Y, Z = np.meshgrid(g, g, g, indexing="ij")
+    D = (np.sqrt(X * X + Y * Y + Z * Z) - r).reshape(-1)
+    vf = (np.abs(D) < 3 * h).astype(np.uint8)
+    keys, tri = oracle.marching_cubes(dims, lo, hi, D, vf)
+    L = h
+    err = np.abs(np.linalg.norm(tri.reshape(-1, 3), axis=1) - r)
+    assert err.max() <= L * L / (8 * (r - L)) + 1e-12
+    directed, undirected = _edge_uses(tri)
+    assert set(undirected.values()) == {2}
+    assert set(directed.values()) == {1}
+    V = len({tuple(p) for p in tri.reshape(-1, 3)})
+    assert V - len(undirected) + len(tri) == 2
+    assert abs(_area(tri) / (4 * np.pi * r * r) - 1) < 0.02
+
+
+def test_mc_random_field_has_no_cracks():
+    """A random field (many ambiguous faces) over a dense band: every mesh
+    edge not on the domain's boundary is shared by exactly two triangles,
+    once each way; the face rule is the same from both cells of a face."""
+    rng = np.random.default_rng(11)
+    R = 9
+    dims, lo, hi = (R, R, R), (0.0,) * 3, (1.0,) * 3
+    D = rng.normal(size=(R + 1) ** 3)
+    keys, tri = oracle.marching_cubes(dims, lo, hi, D, np.ones(D.size, np.uint8))
+    assert len(tri) > 500
+    directed, undirected = _edge_uses(tri)
+    on_boundary = lambda p: any(abs(x) < 1e-15 or abs(x - 1.0) < 1e-15 for x in p)
+    for (a, b), n in undirected.items():
+        if on_boundary(a) and on_boundary(b):
+            assert n in (1, 2)
+        else:
+            assert n == 2 and directed.get((a, b)) == 1 and directed.get((b, a)) == 1, (a, b, n)
