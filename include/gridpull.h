@@ -163,6 +163,14 @@ gp_status gp_nn_query(gp_ctx ctx, const float* qx, const float* qy, const float*
  * bitmap of one bit per cell), which saves range lookups where points are
  * sparse.  Without morton_sort the groups are cut along the queries' own
  * order (enough when the caller's order is already spatially coherent).
+ *
+ * The search runs on a grid of its own per shape (the index that replaces
+ * the paper's KD-tree): the shape's box in cells 2^k band cells wide, k in
+ * [0, 3] the integer nearest to log2(cell_points / m) / 2, m the mean number
+ * of points per band cell holding a point (points on a surface fill a cell
+ * twice as wide four times as densely), so that sparse points do not leave
+ * most scanned cells empty at a fine band resolution.  "Cells" above are
+ * cells of this grid.
  */
 typedef struct {
     int32_t group_span;    /* [1, 64], default 8 */
@@ -170,31 +178,47 @@ typedef struct {
     int32_t tile_parts;    /* 1, 2 or 4, default 1 */
     int32_t skip_empty;    /* 0 or 1, default 0 */
     int32_t morton_sort;   /* 0 or 1, default 1 */
+    int32_t cell_points;   /* [1, 65536], default 8 */
 } gp_nn_params;
 
 /*
  * Set / read the context's search shape (host struct; it survives
- * gp_build_band).  Errors: GP_ERR_ARG (null pointer, a field out of range).
+ * gp_build_band).  A new cell_points rebuilds the search grids of a built
+ * context (synchronises).  Errors: GP_ERR_ARG (null pointer, a field out of
+ * range), GP_ERR_OOM.
  */
 gp_status gp_set_nn_params(gp_ctx ctx, const gp_nn_params* params);
 gp_status gp_get_nn_params(gp_ctx ctx, gp_nn_params* params);
 
 /*
- * Autotuner of the search shape: runs gp_nn_query's kernel on the given
- * queries for group_span in {4, 6, 8, 12, 16, 24, 32} x first_shell in
- * {0, 1, 2} at the current tile_parts and skip_empty, then tile_parts in
- * {1, 2, 4} at the best of those (and, if that changes tile_parts, the
- * span x shell grid again at the new tile_parts), then the other skip_empty
- * setting, then the other morton_sort setting; each
- * candidate once untimed and then reps times between HIP events on the
- * context's stream (its time: the smallest of those).  Keeps the fastest in
- * the context and leaves nn_out holding the nearest neighbours (as
- * gp_nn_query).  The context's current setting is timed first and stays
- * unless another is at least 2% faster.
+ * The search grid of shape `shape`: dims_out (host [3]) its cells per axis,
+ * level_out (host, may be NULL) its k (cells 2^k band cells wide).
+ * Errors: GP_ERR_STATE before gp_build_band, GP_ERR_ARG (shape out of range,
+ * null dims_out).
+ */
+gp_status gp_get_nn_grid(gp_ctx ctx, int32_t shape, int32_t* dims_out, int32_t* level_out);
+
+/*
+ * Autotuner of the search grid and shape, timing gp_nn_query's kernel on the
+ * given queries at the current setting, then:
+ *  1. the search grids of cell_points 4, 16, 64, ... times the current value
+ *     (each factor of 4 moves every shape's k by one) while each is the
+ *     fastest so far, else 1/4, 1/16, ... of it likewise (each grid rebuilt;
+ *     a value that gives grids already timed ends its direction);
+ *  2. on the fastest grid, group_span in {4, 6, 8, 12, 16, 24, 32} x
+ *     first_shell in {0, 1, 2}, then tile_parts in {1, 2, 4} at the best of
+ *     those (and, if that changes tile_parts, the span x shell grid again);
+ *  3. the other skip_empty setting, then the other morton_sort setting.
+ * Each candidate runs once and then reps times between HIP events on the
+ * context's stream (its time: the smallest of the repeats; one whose first
+ * run takes 4 times the best so far is not repeated).  Keeps the fastest in
+ * the context (with its search grids) and leaves nn_out holding the nearest
+ * neighbours (as gp_nn_query).  The current setting stays unless another is
+ * at least 2% faster.
  * Arguments as gp_nn_query; reps in [1, 100]; chosen_out (host, may be NULL)
  * receives the choice and best_ms_out (host, may be NULL) its time in ms
  * (-1 with no queries).  Synchronises; not for use under stream capture.
- * Errors: as gp_nn_query, GP_ERR_ARG for reps, GP_ERR_DEVICE.
+ * Errors: as gp_nn_query, GP_ERR_ARG for reps, GP_ERR_DEVICE, GP_ERR_OOM.
  */
 gp_status gp_autotune_nn(gp_ctx ctx, const float* qx, const float* qy, const float* qz,
                          int64_t n_queries, int32_t* nn_out, int32_t reps,

@@ -5,12 +5,19 @@
 // vertices of those cells are the optimised parameters.  Here the band is
 // built on the device with dense per-shape scratch flags (one byte per cell
 // and per vertex), separable Chebyshev dilation, then compacted into 8^3
-// vertex bricks addressed through a dense brick directory.  The point cloud is
-// bucketed by cell (a counting layout over the same brick slots) for the
-// nearest-neighbour search that stands in for the paper's KD-tree.
+// vertex bricks addressed through a dense brick directory.  The points are
+// kept sorted by band cell (the sampler's source order).
+//
+// The nearest-neighbour search that stands in for the paper's KD-tree runs on
+// a grid of its own per shape: the same box, cells 2^k times the band's (k >=
+// 0, chosen from the point density: where the points are sparse in the band's
+// cells, coarser cells hold about cell_points points each), its own Morton
+// ordered brick directory, a one-bit-per-cell occupancy bitmap and the points
+// bucketed by its cells (a counting layout over its brick slots).
 #include <hipcub/hipcub.hpp>
 
 #include <algorithm>
+#include <cmath>
 #include <memory>
 
 #include "gp_internal.h"
@@ -257,11 +264,11 @@ __global__ void k_count_masks(const BrickInfo* __restrict__ bricks, int64_t n_br
     }
 }
 
-// Point bucket keys: the slot of the point's cell (the slot of its lowest corner).
+// Sort keys of the points: the slot of the point's band cell (the slot of its
+// lowest corner).
 __global__ void k_point_keys(const float* __restrict__ px, const float* __restrict__ py,
                              const float* __restrict__ pz, Band B, int32_t shape,
-                             uint32_t* __restrict__ keys, int32_t* __restrict__ vals,
-                             unsigned* __restrict__ counts)
+                             uint32_t* __restrict__ keys, int32_t* __restrict__ vals)
 {
     const ShapeDesc& s = B.shapes[shape];
     GRID_STRIDE(j, s.point_cnt)
@@ -272,7 +279,6 @@ __global__ void k_point_keys(const float* __restrict__ px, const float* __restri
         uint32_t slot = (uint32_t)br * kBrickVol + (uint32_t)local_index(L.c[0], L.c[1], L.c[2]);
         keys[s.sorted_off + j] = slot;
         vals[s.sorted_off + j] = (int32_t)g;
-        atomicAdd(&counts[slot], 1u);
     }
 }
 
@@ -288,16 +294,68 @@ __global__ void k_gather_sorted(const float* __restrict__ px, const float* __res
     }
 }
 
-// One word of the occupancy bitmap: bit b of word w is cell 32 w + b (bit 1
-// of the cell flags: the cell holds a point).
-__global__ void k_pack_occ(const uint8_t* __restrict__ cells, int64_t n_cells, uint32_t* __restrict__ occ)
+// Number of cells holding a point (bit 1 of the cell flags), added to *count.
+__global__ void k_count_point_cells(const uint8_t* __restrict__ cells, int64_t n_cells,
+                                    unsigned long long* __restrict__ count)
 {
-    GRID_STRIDE(w, (n_cells + 31) / 32)
+    unsigned long long c = 0;
+    GRID_STRIDE(i, n_cells) c += cells[i] & 1;
+    for (int o = 32; o > 0; o >>= 1) c += __shfl_down(c, o);
+    if ((threadIdx.x & 63) == 0 && c) atomicAdd(count, c);
+}
+
+// ---- search grid ------------------------------------------------------------
+
+// Marks the search-grid bricks that hold a point of shape n (points read from
+// the original-order copy at sorted_off).
+__global__ void k_nn_mark(const float* __restrict__ ox, const float* __restrict__ oy, const float* __restrict__ oz,
+                          ShapeDesc n, int32_t* __restrict__ active)
+{
+    GRID_STRIDE(j, n.point_cnt)
     {
-        uint32_t v = 0;
-        const int64_t c0 = w * 32;
-        for (int b = 0; b < 32 && c0 + b < n_cells; ++b) v |= (uint32_t)(cells[c0 + b] & 1) << b;
-        occ[w] = v;
+        const int64_t g = n.sorted_off + j;
+        const Loc L = locate(n, ox[g], oy[g], oz[g]);
+        const int64_t b = ((int64_t)(L.c[0] >> 3) * n.nb[1] + (L.c[1] >> 3)) * n.nb[2] + (L.c[2] >> 3);
+        active[b] = 1;
+    }
+}
+
+__global__ void k_nn_fill_dir(const int32_t* __restrict__ active, const int32_t* __restrict__ index, int64_t nbt,
+                              int64_t brick_base, int32_t* __restrict__ dir)
+{
+    GRID_STRIDE(b, nbt) dir[b] = active[b] ? (int32_t)(brick_base + index[b]) : -1;
+}
+
+// Bucket keys of shape `shape`'s points in its search grid (the slot of the
+// point's cell), the per-slot counts and the occupancy bits.
+__global__ void k_nn_point_keys(const float* __restrict__ ox, const float* __restrict__ oy,
+                                const float* __restrict__ oz, Band N, int32_t shape, uint32_t* __restrict__ keys,
+                                int32_t* __restrict__ vals, unsigned* __restrict__ counts, uint32_t* __restrict__ occ)
+{
+    const ShapeDesc& n = N.shapes[shape];
+    GRID_STRIDE(j, n.point_cnt)
+    {
+        const int64_t g = n.sorted_off + j;
+        const Loc L = locate(n, ox[g], oy[g], oz[g]);
+        const int32_t br = brick_of(N, n, L.c[0] >> 3, L.c[1] >> 3, L.c[2] >> 3);
+        const uint32_t slot = (uint32_t)br * kBrickVol + (uint32_t)local_index(L.c[0], L.c[1], L.c[2]);
+        keys[g] = slot;
+        vals[g] = (int32_t)j;
+        atomicAdd(&counts[slot], 1u);
+        const int64_t bit = n.occ_off * 32 + ((int64_t)L.c[0] * n.R[1] + L.c[1]) * n.R[2] + L.c[2];
+        atomicOr(&occ[bit >> 5], 1u << (bit & 31));
+    }
+}
+
+__global__ void k_nn_gather(const float* __restrict__ ox, const float* __restrict__ oy, const float* __restrict__ oz,
+                            const int32_t* __restrict__ vals, int64_t begin, int64_t count,
+                            float4* __restrict__ spts)
+{
+    GRID_STRIDE(i, count)
+    {
+        const int32_t j = vals[begin + i];
+        const int64_t g = begin + j;
+        spts[begin + i] = make_float4(ox[g], oy[g], oz[g], __int_as_float(j));
     }
 }
 
@@ -323,7 +381,7 @@ gp_status gp_build_band_impl(gp_ctx ctx, const gp_shape* shapes, int32_t n_shape
 
     // ---- host-side descriptors ------------------------------------------
     std::vector<ShapeDesc> hs(n_shapes);
-    int64_t dir_total = 0, dense_total = 0, sorted_total = 0, tiles_total = 0, occ_total = 0;
+    int64_t dir_total = 0, dense_total = 0, sorted_total = 0, tiles_total = 0;
     int64_t n_points = 0, n_queries = 0;
     for (int32_t s = 0; s < n_shapes; ++s) {
         const gp_shape& in = shapes[s];
@@ -354,19 +412,16 @@ gp_status gp_build_band_impl(gp_ctx ctx, const gp_shape* shapes, int32_t n_shape
         n_queries = std::max(n_queries, in.query_off + in.query_cnt);
         d.n_tv = 0;
         d.brick_begin = d.brick_end = 0;
-        d.occ_off = occ_total;
-        occ_total += ((int64_t)d.R[0] * d.R[1] * d.R[2] + 31) / 32;
+        d.occ_off = 0;
     }
     if (sorted_total >= ((int64_t)1 << 31) || n_points >= ((int64_t)1 << 31))
         return gp_fail(ctx, GP_ERR_CAPACITY, "more than 2^31 points");
     if (dir_total >= kMaxSlots) return gp_fail(ctx, GP_ERR_CAPACITY, "more than 2^30 brick directory entries");
 
-    if (ctx->occ.alloc((size_t)std::max<int64_t>(occ_total, 1)) != hipSuccess)
-        return gp_fail(ctx, GP_ERR_OOM, "out of device memory for the occupancy bitmap");
-    DevBuf<ShapeDesc> d_shape1;
-    GP_HIP(ctx, d_shape1.alloc(1));
-    DevBuf<unsigned long long> d_bad;
+    DevBuf<unsigned long long> d_bad, d_occupied;
     GP_HIP(ctx, d_bad.alloc(1));
+    GP_HIP(ctx, d_occupied.alloc(n_shapes));
+    GP_HIP(ctx, hipMemsetAsync(d_occupied.p, 0, sizeof(unsigned long long) * n_shapes, st));
 
     std::vector<std::unique_ptr<ShapeBricks>> parts;
     int64_t brick_base = 0;
@@ -396,7 +451,7 @@ gp_status gp_build_band_impl(gp_ctx ctx, const gp_shape* shapes, int32_t n_shape
         if (bad != ~0ull)
             return gp_fail(ctx, GP_ERR_DOMAIN, "shape " + std::to_string(s) + ": point " + std::to_string(bad) +
                                                    " lies outside the domain");
-        k_pack_occ<<<blocks_for((nc + 31) / 32), kThreads, 0, st>>>(c0.p, nc, ctx->occ.p + d.occ_off);
+        k_count_point_cells<<<std::min(blocks_for(nc), 4096u), kThreads, 0, st>>>(c0.p, nc, d_occupied.p + s);
         // separable Chebyshev dilation x -> y -> z; a width of the largest
         // extent minus one already reaches every cell, so wider ones are cut
         // to it (same sets, bounded work)
@@ -523,6 +578,14 @@ gp_status gp_build_band_impl(gp_ctx ctx, const gp_shape* shapes, int32_t n_shape
     }
     ctx->n_active = n_active;
     GP_HIP(ctx, hipMemcpyAsync(ctx->shapes.p, hs.data(), n_shapes * sizeof(ShapeDesc), hipMemcpyHostToDevice, st));
+    ctx->h_occupied.assign(n_shapes, 0);
+    {
+        std::vector<unsigned long long> ho(n_shapes);
+        GP_HIP(ctx, hipMemcpyAsync(ho.data(), d_occupied.p, n_shapes * sizeof(unsigned long long),
+                                   hipMemcpyDeviceToHost, st));
+        GP_HIP(ctx, hipStreamSynchronize(st));
+        for (int32_t s = 0; s < n_shapes; ++s) ctx->h_occupied[s] = (int64_t)ho[s];
+    }
 
     // ---- query tiles -------------------------------------------------------
     std::vector<int64_t> ts(tiles_total > 0 ? tiles_total : 1);
@@ -537,18 +600,15 @@ gp_status gp_build_band_impl(gp_ctx ctx, const gp_shape* shapes, int32_t n_shape
     GP_HIP(ctx, hipMemcpyAsync(ctx->tile_start.p, ts.data(), ts.size() * 8, hipMemcpyHostToDevice, st));
     GP_HIP(ctx, hipMemcpyAsync(ctx->tile_shape.p, tsh.data(), tsh.size() * 4, hipMemcpyHostToDevice, st));
 
-    // ---- point buckets (sorted by cell slot) ------------------------------
+    // ---- points sorted by band cell slot ----------------------------------
     const int64_t np = sorted_total;
     {
         DevBuf<uint32_t> k_in, k_out;
         DevBuf<int32_t> v_in;
-        DevBuf<unsigned> counts;
         if (k_in.alloc(np) != hipSuccess || k_out.alloc(np) != hipSuccess || v_in.alloc(np) != hipSuccess ||
-            counts.alloc(n_slots + 1) != hipSuccess || ctx->cell_start.alloc(n_slots + 1) != hipSuccess ||
             ctx->spts.alloc(np) != hipSuccess || ctx->ox.alloc(np) != hipSuccess || ctx->oy.alloc(np) != hipSuccess ||
             ctx->oz.alloc(np) != hipSuccess)
-            return gp_fail(ctx, GP_ERR_OOM, "out of device memory for the point buckets");
-        GP_HIP(ctx, hipMemsetAsync(counts.p, 0, (n_slots + 1) * sizeof(unsigned), st));
+            return gp_fail(ctx, GP_ERR_OOM, "out of device memory for the sorted points");
         for (int32_t s = 0; s < n_shapes; ++s) {
             if (hs[s].point_cnt == 0) continue;
             const size_t nb = (size_t)hs[s].point_cnt * sizeof(float);
@@ -559,13 +619,9 @@ gp_status gp_build_band_impl(gp_ctx ctx, const gp_shape* shapes, int32_t n_shape
         Band B = ctx->band();
         for (int32_t s = 0; s < n_shapes; ++s)
             if (hs[s].point_cnt > 0)
-                k_point_keys<<<blocks_for(hs[s].point_cnt), kThreads, 0, st>>>(px, py, pz, B, s, k_in.p, v_in.p,
-                                                                               counts.p);
+                k_point_keys<<<blocks_for(hs[s].point_cnt), kThreads, 0, st>>>(px, py, pz, B, s, k_in.p, v_in.p);
         GP_HIP(ctx, hipGetLastError());
-        // cell_start = exclusive prefix sum of the per-slot counts
         size_t need = 0;
-        GP_HIP(ctx, hipcub::DeviceScan::ExclusiveSum(nullptr, need, counts.p, (unsigned*)ctx->cell_start.p,
-                                                     (int)(n_slots + 1), st));
         int end_bit = 1;
         while (((int64_t)1 << end_bit) < n_slots + 1 && end_bit < 32) ++end_bit;
         size_t need2 = 0;
@@ -580,8 +636,6 @@ gp_status gp_build_band_impl(gp_ctx ctx, const gp_shape* shapes, int32_t n_shape
             cub_tmp = cub_buf.p;
             cub_bytes = need;
         }
-        GP_HIP(ctx, hipcub::DeviceScan::ExclusiveSum(cub_tmp, need, counts.p, (unsigned*)ctx->cell_start.p,
-                                                     (int)(n_slots + 1), st));
         if (np > 0) {
             GP_HIP(ctx, hipcub::DeviceRadixSort::SortPairs(cub_tmp, need, k_in.p, k_out.p, v_in.p, v_out.p, (int)np, 0,
                                                           end_bit, st));
@@ -613,6 +667,191 @@ gp_status gp_build_band_impl(gp_ctx ctx, const gp_shape* shapes, int32_t n_shape
     for (int32_t s = 0; s < n_shapes; ++s) ctx->h_slot_begin[s] = hs[s].brick_begin * kBrickVol;
     ctx->h_slot_begin[n_shapes] = n_slots;
     GP_HIP(ctx, hipStreamSynchronize(st));
+    const gp_status ns = gp_build_nn_index(ctx, ctx->nn_params.cell_points);
+    if (ns != GP_OK) return ns;
     ctx->built = true;
+    return GP_OK;
+}
+
+// Level k of a shape's search grid (cells 2^k band cells wide per axis): the
+// one that brings the mean number of points per occupied cell closest to
+// cell_points on a log scale.  Points on a surface fill cells in two
+// dimensions, so doubling the cell edge multiplies that mean by about 4:
+// k = round(log2(cell_points / mean) / 2), within [0, 3].  The grid is never
+// finer than the band: queries lie about two band cells from the surface
+// (the sampler's spread), and a search for a query many cells away from every
+// point costs more than dense cells do.
+static int32_t nn_level(int64_t points, int64_t occupied, int32_t cell_points)
+{
+    if (points <= 0 || occupied <= 0) return 0;
+    const double mean = (double)points / (double)occupied;
+    const double k = std::nearbyint(0.5 * std::log2((double)cell_points / mean));
+    return (int32_t)std::min(3.0, std::max(0.0, k));
+}
+
+// Descriptor of a search grid at level k: the band's box, 2^k times its cell
+// edge (exact: a power of two), enough cells to cover the box.
+static ShapeDesc nn_desc(const ShapeDesc& d, int32_t k)
+{
+    ShapeDesc n = d;
+    const double f = std::ldexp(1.0, k);
+    for (int a = 0; a < 3; ++a) {
+        n.R[a] = (int32_t)((d.R[a] + ((int64_t)1 << k) - 1) >> k);
+        n.inv_h[a] = d.inv_h[a] / f;
+        n.inv_hf[a] = (float)n.inv_h[a];
+        n.h[a] = (float)(d.hd[a] * f);
+        n.hd[a] = d.hd[a] * f;
+        n.nb[a] = (n.R[a] + kBrick - 1) / kBrick;
+    }
+    return n;
+}
+
+std::vector<int32_t> gp_nn_levels(gp_ctx ctx, int32_t cell_points)
+{
+    std::vector<int32_t> k(ctx->n_shapes);
+    for (int32_t s = 0; s < ctx->n_shapes; ++s)
+        k[s] = nn_level(ctx->h_shapes[s].point_cnt, ctx->h_occupied[s], cell_points);
+    return k;
+}
+
+gp_status gp_build_nn_index(gp_ctx ctx, int32_t cell_points)
+{
+    hipStream_t st = ctx->stream;
+    const int32_t n_shapes = ctx->n_shapes;
+    const std::vector<ShapeDesc>& hs = ctx->h_shapes;
+    std::vector<ShapeDesc> ns(n_shapes);
+    std::vector<DevBuf<int32_t>> dirs(n_shapes);
+    std::vector<int32_t> levels(n_shapes, 0);
+    int64_t dir_total = 0, occ_total = 0, brick_base = 0;
+    void* cub_tmp = nullptr;
+    size_t cub_bytes = 0;
+    DevBuf<uint8_t> cub_buf;
+    auto cub_room = [&](size_t need) -> hipError_t {
+        if (need <= cub_bytes) return hipSuccess;
+        hipError_t e = cub_buf.alloc(need);
+        cub_tmp = cub_buf.p;
+        cub_bytes = e == hipSuccess ? need : 0;
+        return e;
+    };
+    ctx->nn_cell_points = 0;
+    for (int32_t s = 0; s < n_shapes; ++s) {
+        const ShapeDesc& d = hs[s];
+        const int32_t k = nn_level(d.point_cnt, ctx->h_occupied[s], cell_points);
+        {
+            ShapeDesc n = nn_desc(d, k);
+            const int64_t nbt = (int64_t)n.nb[0] * n.nb[1] * n.nb[2];
+            DevBuf<int32_t> active, index;
+            if (active.alloc(nbt) != hipSuccess || index.alloc(nbt) != hipSuccess)
+                return gp_fail(ctx, GP_ERR_OOM, "out of device memory for the search grid of shape " + std::to_string(s));
+            GP_HIP(ctx, hipMemsetAsync(active.p, 0, nbt * sizeof(int32_t), st));
+            if (n.point_cnt > 0)
+                k_nn_mark<<<blocks_for(n.point_cnt), kThreads, 0, st>>>(ctx->ox.p, ctx->oy.p, ctx->oz.p, n, active.p);
+            GP_HIP(ctx, hipGetLastError());
+            size_t need = 0;
+            GP_HIP(ctx, hipcub::DeviceScan::ExclusiveSum(nullptr, need, active.p, index.p, (int)nbt, st));
+            GP_HIP(ctx, cub_room(need));
+            GP_HIP(ctx, hipcub::DeviceScan::ExclusiveSum(cub_tmp, need, active.p, index.p, (int)nbt, st));
+            int32_t last_idx = 0, last_act = 0;
+            GP_HIP(ctx, hipMemcpyAsync(&last_idx, index.p + nbt - 1, 4, hipMemcpyDeviceToHost, st));
+            GP_HIP(ctx, hipMemcpyAsync(&last_act, active.p + nbt - 1, 4, hipMemcpyDeviceToHost, st));
+            GP_HIP(ctx, hipStreamSynchronize(st));
+            const int64_t nb_s = (int64_t)last_idx + last_act;
+            if ((brick_base + nb_s) * kBrickVol >= kMaxSlots)
+                return gp_fail(ctx, GP_ERR_CAPACITY, "more than 2^30 search grid slots");
+            {
+                // bricks numbered along the Morton curve
+                DevBuf<uint64_t> kin, kout;
+                DevBuf<int32_t> iin, iout;
+                if (kin.alloc(nbt) != hipSuccess || kout.alloc(nbt) != hipSuccess || iin.alloc(nbt) != hipSuccess ||
+                    iout.alloc(nbt) != hipSuccess)
+                    return gp_fail(ctx, GP_ERR_OOM, "out of device memory for the search grid of shape " +
+                                                        std::to_string(s));
+                k_brick_keys<<<blocks_for(nbt), kThreads, 0, st>>>(active.p, n, kin.p, iin.p);
+                int32_t bits = 1;
+                while ((int64_t(1) << bits) < std::max(n.nb[0], std::max(n.nb[1], n.nb[2]))) ++bits;
+                const int end_bit = 3 * bits + 1;
+                size_t need3 = 0;
+                GP_HIP(ctx, hipcub::DeviceRadixSort::SortPairs(nullptr, need3, kin.p, kout.p, iin.p, iout.p, (int)nbt,
+                                                              0, end_bit, st));
+                GP_HIP(ctx, cub_room(need3));
+                GP_HIP(ctx, hipcub::DeviceRadixSort::SortPairs(cub_tmp, need3, kin.p, kout.p, iin.p, iout.p, (int)nbt,
+                                                              0, end_bit, st));
+                if (nb_s > 0) k_brick_rank<<<blocks_for(nb_s), kThreads, 0, st>>>(iout.p, nb_s, index.p);
+                if (dirs[s].alloc(nbt) != hipSuccess)
+                    return gp_fail(ctx, GP_ERR_OOM, "out of device memory for the search grid of shape " +
+                                                        std::to_string(s));
+                k_nn_fill_dir<<<blocks_for(nbt), kThreads, 0, st>>>(active.p, index.p, nbt, brick_base, dirs[s].p);
+                GP_HIP(ctx, hipGetLastError());
+                GP_HIP(ctx, hipStreamSynchronize(st));   // scratch buffers are freed at scope end
+            }
+            n.dir_off = dir_total;
+            dir_total += nbt;
+            n.occ_off = occ_total;
+            occ_total += ((int64_t)n.R[0] * n.R[1] * n.R[2] + 31) / 32;
+            n.brick_begin = brick_base;
+            n.brick_end = brick_base + nb_s;
+            brick_base += nb_s;
+            ns[s] = n;
+            levels[s] = k;
+        }
+    }
+    if (dir_total >= kMaxSlots) return gp_fail(ctx, GP_ERR_CAPACITY, "more than 2^30 search grid directory entries");
+
+    const int64_t n_slots = brick_base * kBrickVol;
+    const int64_t np = n_shapes > 0 ? hs[n_shapes - 1].sorted_off + hs[n_shapes - 1].point_cnt : 0;
+    if (ctx->nn_shapes.alloc(n_shapes) != hipSuccess || ctx->nn_dir.alloc(dir_total) != hipSuccess ||
+        ctx->occ.alloc((size_t)std::max<int64_t>(occ_total, 1)) != hipSuccess ||
+        ctx->cell_start.alloc(n_slots + 1) != hipSuccess || ctx->nn_spts.alloc(np) != hipSuccess)
+        return gp_fail(ctx, GP_ERR_OOM, "out of device memory for the search grids");
+    GP_HIP(ctx, hipMemcpyAsync(ctx->nn_shapes.p, ns.data(), n_shapes * sizeof(ShapeDesc), hipMemcpyHostToDevice, st));
+    for (int32_t s = 0; s < n_shapes; ++s) {
+        const int64_t nbt = (int64_t)ns[s].nb[0] * ns[s].nb[1] * ns[s].nb[2];
+        GP_HIP(ctx, hipMemcpyAsync(ctx->nn_dir.p + ns[s].dir_off, dirs[s].p, nbt * sizeof(int32_t),
+                                   hipMemcpyDeviceToDevice, st));
+    }
+    GP_HIP(ctx, hipMemsetAsync(ctx->occ.p, 0, std::max<int64_t>(occ_total, 1) * sizeof(uint32_t), st));
+    {
+        DevBuf<uint32_t> k_in, k_out;
+        DevBuf<int32_t> v_in, v_out;
+        DevBuf<unsigned> counts;
+        if (k_in.alloc(np) != hipSuccess || k_out.alloc(np) != hipSuccess || v_in.alloc(np) != hipSuccess ||
+            v_out.alloc(np) != hipSuccess || counts.alloc(n_slots + 1) != hipSuccess)
+            return gp_fail(ctx, GP_ERR_OOM, "out of device memory for the search grids");
+        GP_HIP(ctx, hipMemsetAsync(counts.p, 0, (n_slots + 1) * sizeof(unsigned), st));
+        Band N = ctx->nn_band();
+        for (int32_t s = 0; s < n_shapes; ++s)
+            if (ns[s].point_cnt > 0)
+                k_nn_point_keys<<<blocks_for(ns[s].point_cnt), kThreads, 0, st>>>(
+                    ctx->ox.p, ctx->oy.p, ctx->oz.p, N, s, k_in.p, v_in.p, counts.p, ctx->occ.p);
+        GP_HIP(ctx, hipGetLastError());
+        // cell_start = exclusive prefix sum of the per-slot counts
+        size_t need = 0, need2 = 0;
+        GP_HIP(ctx, hipcub::DeviceScan::ExclusiveSum(nullptr, need, counts.p, (unsigned*)ctx->cell_start.p,
+                                                     (int)(n_slots + 1), st));
+        int end_bit = 1;
+        while (((int64_t)1 << end_bit) < n_slots + 1 && end_bit < 32) ++end_bit;
+        if (np > 0)
+            GP_HIP(ctx, hipcub::DeviceRadixSort::SortPairs(nullptr, need2, k_in.p, k_out.p, v_in.p, v_out.p, (int)np,
+                                                          0, end_bit, st));
+        GP_HIP(ctx, cub_room(std::max(need, need2)));
+        need = cub_bytes;
+        GP_HIP(ctx, hipcub::DeviceScan::ExclusiveSum(cub_tmp, need, counts.p, (unsigned*)ctx->cell_start.p,
+                                                     (int)(n_slots + 1), st));
+        if (np > 0) {
+            // a stable sort: within a cell the points keep their original order
+            GP_HIP(ctx, hipcub::DeviceRadixSort::SortPairs(cub_tmp, need, k_in.p, k_out.p, v_in.p, v_out.p, (int)np, 0,
+                                                          end_bit, st));
+            for (int32_t s = 0; s < n_shapes; ++s)
+                if (ns[s].point_cnt > 0)
+                    k_nn_gather<<<blocks_for(ns[s].point_cnt), kThreads, 0, st>>>(
+                        ctx->ox.p, ctx->oy.p, ctx->oz.p, v_out.p, ns[s].sorted_off, ns[s].point_cnt, ctx->nn_spts.p);
+        }
+        GP_HIP(ctx, hipGetLastError());
+        GP_HIP(ctx, hipStreamSynchronize(st));
+    }
+    ctx->h_nn_shapes = ns;
+    ctx->h_nn_levels = levels;
+    ctx->nn_slots = n_slots;
+    ctx->nn_cell_points = cell_points;
     return GP_OK;
 }

@@ -223,6 +223,17 @@ gp_status gp_set_nn_params(gp_ctx ctx, const gp_nn_params* params)
     if (params->skip_empty != 0 && params->skip_empty != 1) return gp_fail(ctx, GP_ERR_ARG, "skip_empty must be 0 or 1");
     if (params->morton_sort != 0 && params->morton_sort != 1)
         return gp_fail(ctx, GP_ERR_ARG, "morton_sort must be 0 or 1");
+    if (params->cell_points < 1 || params->cell_points > gp::kNnCellPointsMax)
+        return gp_fail(ctx, GP_ERR_ARG, "cell_points must be in [1, 65536]");
+    if (ctx->built && params->cell_points != ctx->nn_cell_points) {
+        if (hipSetDevice(ctx->device) != hipSuccess) return gp_fail(ctx, GP_ERR_DEVICE, "hipSetDevice failed");
+        const gp_status st = gp_build_nn_index(ctx, params->cell_points);
+        if (st != GP_OK) {
+            ctx->built = false;   // the search grids are gone
+            return st;
+        }
+    }
+    ctx->nn_params.cell_points = params->cell_points;
     ctx->nn_params.span = params->group_span;
     ctx->nn_params.shell = params->first_shell;
     ctx->nn_params.parts = params->tile_parts;
@@ -238,6 +249,7 @@ static void nn_params_out(const gp::NnParams& p, gp_nn_params* out)
     out->tile_parts = p.parts;
     out->skip_empty = p.skip_empty;
     out->morton_sort = p.sort;
+    out->cell_points = p.cell_points;
 }
 
 gp_status gp_get_nn_params(gp_ctx ctx, gp_nn_params* params)
@@ -245,6 +257,17 @@ gp_status gp_get_nn_params(gp_ctx ctx, gp_nn_params* params)
     if (!ctx) return GP_ERR_ARG;
     if (!params) return gp_fail(ctx, GP_ERR_ARG, "null output");
     nn_params_out(ctx->nn_params, params);
+    return GP_OK;
+}
+
+gp_status gp_get_nn_grid(gp_ctx ctx, int32_t shape, int32_t* dims_out, int32_t* level_out)
+{
+    gp_status st = ready(ctx);
+    if (st != GP_OK) return st;
+    if (shape < 0 || shape >= ctx->n_shapes) return gp_fail(ctx, GP_ERR_ARG, "shape out of range");
+    if (!dims_out) return gp_fail(ctx, GP_ERR_ARG, "null dims_out");
+    for (int a = 0; a < 3; ++a) dims_out[a] = ctx->h_nn_shapes[shape].R[a];
+    if (level_out) *level_out = ctx->h_nn_levels[shape];
     return GP_OK;
 }
 

@@ -46,7 +46,7 @@ struct ShapeDesc {
     int64_t dense_off;     // offset of the shape's (R+1)^3 dense vertex array
     int64_t sorted_off;    // first entry of the shape's points in the sorted copy
     int64_t n_tv;          // number of TV vertices
-    int64_t occ_off;       // first word of the shape's cell occupancy bitmap
+    int64_t occ_off;       // search grids only: first word of the shape's cell occupancy bitmap
 };
 
 // Brick metadata: owning shape and brick coordinates.
@@ -66,7 +66,7 @@ struct Band {
     const uint32_t* m_v2;        // [n_bricks][16] TV vertex
     const int64_t* tile_start;   // [n_tiles] first query of each tile
     const int32_t* tile_shape;   // [n_tiles]
-    const uint32_t* occ;         // per shape, 1 bit per cell (x-major id): the cell holds a point
+    const uint32_t* occ;         // search grids only: per shape, 1 bit per cell (x-major id), set if the cell holds a point
 };
 
 // Nearest-neighbour search shape: a group of queries is cut where its cells
@@ -83,9 +83,11 @@ struct NnParams {
     int32_t parts = 1;
     int32_t skip_empty = 0;   // trim each scanned column to its occupied cells first
     int32_t sort = 1;         // Morton-sort each tile before grouping (else the input order)
+    int32_t cell_points = 8;  // target points per occupied cell of the search grid (host side only)
 };
 constexpr int32_t kNnSpanMax = 64;
 constexpr int32_t kNnShellMax = 4;
+constexpr int32_t kNnCellPointsMax = 65536;
 
 struct Loc {
     int32_t c[3];
@@ -187,14 +189,14 @@ __device__ inline int64_t xcd_work_item(int64_t b, int64_t n)
 
 // Coordinates of a query's nearest point nn (an index among its shape's
 // points, valid: 0 <= nn < point_cnt).  The NN search records, per query, the
-// position of its result in the cell-sorted copy; when that position still
+// position of its result in the search grid's sorted copy; when that position still
 // holds point nn (the sorted copy keeps each point's original index), the
 // point is read there, 16 contiguous bytes next to the points of the
 // neighbouring queries.  Otherwise (nearest points that did not come from the
 // search, or a stale position) it is read from the original order.  Either
 // way the same coordinates.
 struct PointView {
-    const float4* spts;     // cell-sorted copy: x, y, z, original index within the shape (bits)
+    const float4* spts;     // the search grid's sorted copy: x, y, z, original index within the shape (bits)
     const int32_t* pos;     // [n_queries] position in spts of each query's last NN result
     const float* ox;        // original order, at sorted_off + index
     const float* oy;
@@ -354,13 +356,25 @@ struct gp_ctx_s {
     DevBuf<uint32_t> m_a1, m_a2, m_base, m_v, m_v2;
     DevBuf<int64_t> tile_start;
     DevBuf<int32_t> tile_shape;
-    DevBuf<uint32_t> occ;         // cell occupancy bitmaps of all shapes
+    std::vector<int64_t> h_occupied;   // [n_shapes] band cells holding a point
 
-    // nearest-neighbour buckets: points sorted by cell slot
-    DevBuf<int32_t> cell_start;   // [n_slots + 1]
-    DevBuf<float4> spts;          // sorted points: x, y, z, original index within the shape (bits)
+    DevBuf<float4> spts;          // points sorted by band cell slot (the sampler's source order): x, y, z,
+                                  // original index within the shape (bits)
     DevBuf<float> ox, oy, oz;     // points in their original order, at sorted_off + index
-    DevBuf<int32_t> nn_pos;       // [n_queries] position in spts (within the shape) of the last NN result
+
+    // nearest-neighbour search grid: per shape a grid over the same box with
+    // cells 2^k times the band's, its own brick directory, occupancy bitmap
+    // and points bucketed by its cells
+    std::vector<gp::ShapeDesc> h_nn_shapes;
+    std::vector<int32_t> h_nn_levels;   // [n_shapes] k: search cells are 2^k band cells wide
+    int32_t nn_cell_points = 0;   // the target the current search grids were built for (0: none)
+    int64_t nn_slots = 0;
+    DevBuf<gp::ShapeDesc> nn_shapes;
+    DevBuf<int32_t> nn_dir;
+    DevBuf<uint32_t> occ;         // occupancy bitmaps of all search grids
+    DevBuf<int32_t> cell_start;   // [nn_slots + 1]
+    DevBuf<float4> nn_spts;       // points sorted by search-grid slot: x, y, z, original index (bits)
+    DevBuf<int32_t> nn_pos;       // [n_queries] position in nn_spts (within the shape) of the last NN result
 
     // per-iteration scratch
     DevBuf<double> q_part;        // [n_tiles][4] sum pull, surf, grad, count
@@ -397,7 +411,19 @@ struct gp_ctx_s {
 
     gp::PointView points() const
     {
-        return gp::PointView{spts.p, nn_pos.p, ox.p, oy.p, oz.p};
+        return gp::PointView{nn_spts.p, nn_pos.p, ox.p, oy.p, oz.p};
+    }
+
+    // The band view with the search grids' descriptors, directory and
+    // occupancy in place of the band's (for the nearest-neighbour search).
+    gp::Band nn_band() const
+    {
+        gp::Band b = band();
+        b.shapes = nn_shapes.p;
+        b.dir = nn_dir.p;
+        b.bricks = nullptr;
+        b.occ = occ.p;
+        return b;
     }
 
     gp::Band band() const
@@ -412,7 +438,7 @@ struct gp_ctx_s {
         b.m_v2 = m_v2.p;
         b.tile_start = tile_start.p;
         b.tile_shape = tile_shape.p;
-        b.occ = occ.p;
+        b.occ = nullptr;
         return b;
     }
 };
@@ -444,6 +470,8 @@ gp_status gp_hip_fail(gp_ctx ctx, hipError_t e, const char* what);
 gp_status gp_build_band_impl(gp_ctx ctx, const gp_shape* shapes, int32_t n_shapes,
                              const float* px, const float* py, const float* pz,
                              int32_t m1, int32_t m2);
+gp_status gp_build_nn_index(gp_ctx ctx, int32_t cell_points);
+std::vector<int32_t> gp_nn_levels(gp_ctx ctx, int32_t cell_points);   // per shape, before the size limits
 gp_status gp_nn_impl(gp_ctx ctx, const float* qx, const float* qy, const float* qz, int32_t* nn);
 gp_status gp_autotune_nn_impl(gp_ctx ctx, const float* qx, const float* qy, const float* qz, int32_t* nn,
                               int32_t reps, gp::NnParams* best_out, float* best_ms_out);

@@ -1,9 +1,12 @@
 // Nearest surface point NN(q) of every query (Eq. 4).
 //
 // The paper organises the points in a KD-tree.  Here the points are bucketed
-// by grid cell (sorted by the slot of their cell, built once in band.hip); a
-// cell's points are contiguous, and so are the points of a run of cells along
-// z inside one brick.
+// by the cells of a search grid per shape (built in band.hip: the shape's box
+// in cells 2^k times the band's, k chosen from the point density so that an
+// occupied cell holds a few points whatever the band resolution), sorted by
+// the slot of their cell; a cell's points are contiguous, and so are the
+// points of a run of cells along z inside one brick.  Every "cell" below is a
+// search-grid cell.
 //
 // A block takes a tile of 1024 queries and sorts them by the Morton code of
 // their cell; each wave cuts its quarter of the sorted list into groups of at
@@ -34,6 +37,8 @@
 // the lowest point index, so every result equals a brute-force search bit
 // for bit.
 #include <hipcub/hipcub.hpp>
+
+#include <algorithm>
 
 #include "gp_internal.h"
 
@@ -790,21 +795,25 @@ using namespace gp;
 gp_status gp_nn_impl(gp_ctx ctx, const float* qx, const float* qy, const float* qz, int32_t* nn)
 {
     if (ctx->n_tiles == 0) return GP_OK;
-    Global G{ctx->cell_start.p, ctx->spts.p};
+    Global G{ctx->cell_start.p, ctx->nn_spts.p};
     GP_TIMED(ctx, "k_nn");
     k_nn<false><<<(unsigned)(ctx->n_tiles * ctx->nn_params.parts), kQueryBlock, 0, ctx->stream>>>(
-        ctx->band(), G, ctx->nn_params, qx, qy, qz, nn, ctx->nn_pos.p);
+        ctx->nn_band(), G, ctx->nn_params, qx, qy, qz, nn, ctx->nn_pos.p);
     GP_HIP(ctx, hipGetLastError());
     return GP_OK;
 }
 
-// Times k_nn for every (span, shell) pair of a small grid on the caller's
-// queries (the results are the same for all of them), then the number of
+// Times k_nn on the caller's queries (the results are the same for every
+// setting): first on the search grids of 4, 16, ... times the current target
+// density while each is faster than the last (a factor of 4 moves each
+// shape's grid by one level), else of 1/4, 1/16, ... of it; then, on the
+// fastest grid, every (span, shell) pair of a small grid, then the number of
 // blocks per tile for the best pair (and, if that changed, every pair again
 // at the new number), then the other skip_empty setting, then the other sort
 // setting, and keeps the fastest in the context.
-// Each candidate runs once untimed, then `reps` times between events; its
-// time is the smallest of those.  The context's current setting is timed
+// Each candidate runs once, then `reps` times, between events; its time is
+// the smallest of the repeats (a candidate whose first run takes 4 times the
+// best time so far is not repeated).  The context's current setting is timed
 // first and is only replaced by one at least 2% faster, so timing noise does
 // not move a setting that is already as good.
 gp_status gp_autotune_nn_impl(gp_ctx ctx, const float* qx, const float* qy, const float* qz, int32_t* nn,
@@ -817,7 +826,10 @@ gp_status gp_autotune_nn_impl(gp_ctx ctx, const float* qx, const float* qy, cons
     NnParams best = current;
     float best_ms = -1.f;
     if (ctx->n_tiles > 0) {
-        Global G{ctx->cell_start.p, ctx->spts.p};
+        if (ctx->nn_cell_points != current.cell_points) {
+            const gp_status rs = gp_build_nn_index(ctx, current.cell_points);
+            if (rs != GP_OK) return rs;
+        }
         hipEvent_t ev[2];
         GP_HIP(ctx, hipEventCreate(&ev[0]));
         if (hipEventCreate(&ev[1]) != hipSuccess) {
@@ -826,40 +838,77 @@ gp_status gp_autotune_nn_impl(gp_ctx ctx, const float* qx, const float* qy, cons
             return GP_ERR_DEVICE;
         }
         hipError_t e = hipSuccess;
+        gp_status rebuilt = GP_OK;
         auto time_one = [&](const NnParams& P) -> float {
+            const Global G{ctx->cell_start.p, ctx->nn_spts.p};
             float t_min = -1.f;
             for (int32_t r = 0; r <= reps && e == hipSuccess; ++r) {
-                if (r > 0) e = hipEventRecord(ev[0], ctx->stream);
-                k_nn<true><<<(unsigned)(ctx->n_tiles * P.parts), kQueryBlock, 0, ctx->stream>>>(ctx->band(), G, P, qx, qy,
-                                                                                            qz, nn, ctx->nn_pos.p);
+                e = hipEventRecord(ev[0], ctx->stream);
+                k_nn<true><<<(unsigned)(ctx->n_tiles * P.parts), kQueryBlock, 0, ctx->stream>>>(ctx->nn_band(), G, P,
+                                                                                            qx, qy, qz, nn, ctx->nn_pos.p);
                 if (e == hipSuccess) e = hipGetLastError();
-                if (r > 0 && e == hipSuccess) e = hipEventRecord(ev[1], ctx->stream);
-                if (r > 0 && e == hipSuccess) e = hipEventSynchronize(ev[1]);
+                if (e == hipSuccess) e = hipEventRecord(ev[1], ctx->stream);
+                if (e == hipSuccess) e = hipEventSynchronize(ev[1]);
                 float ms = 0.f;
-                if (r > 0 && e == hipSuccess) e = hipEventElapsedTime(&ms, ev[0], ev[1]);
-                if (r > 0 && e == hipSuccess && (t_min < 0.f || ms < t_min)) t_min = ms;
+                if (e == hipSuccess) e = hipEventElapsedTime(&ms, ev[0], ev[1]);
+                if (e != hipSuccess) break;
+                if (r == 0) {
+                    if (best_ms > 0.f && ms > 4.f * best_ms) return ms;   // far off: not worth the repeats
+                    continue;
+                }
+                if (t_min < 0.f || ms < t_min) t_min = ms;
             }
             return t_min;
+        };
+        auto same = [](const NnParams& a, const NnParams& b) {
+            return a.span == b.span && a.shell == b.shell && a.parts == b.parts && a.skip_empty == b.skip_empty &&
+                   a.sort == b.sort && a.cell_points == b.cell_points;
         };
         // a challenger must beat the current setting by 2%, anything else plainly
         auto offer = [&](const NnParams& P) {
             const float t = time_one(P);
             if (e != hipSuccess || t < 0.f) return;
-            const bool holding = best.span == current.span && best.shell == current.shell &&
-                                 best.parts == current.parts && best.skip_empty == current.skip_empty &&
-                                 best.sort == current.sort;
-            if (best_ms < 0.f || t < best_ms * (holding ? 0.98f : 1.f)) {
+            if (best_ms < 0.f || t < best_ms * (same(best, current) ? 0.98f : 1.f)) {
                 best_ms = t;
                 best = P;
             }
         };
         offer(current);
+        // the search grids of other targets, one level at a time; a target
+        // that gives grids already timed ends its direction (all levels at
+        // their limit)
+        std::vector<std::vector<int32_t>> tried{gp_nn_levels(ctx, current.cell_points)};
+        auto try_grid = [&](int32_t cp) -> bool {   // true if it is the fastest so far
+            if (e != hipSuccess || rebuilt != GP_OK) return false;
+            const std::vector<int32_t> lv = gp_nn_levels(ctx, cp);
+            if (std::find(tried.begin(), tried.end(), lv) != tried.end()) return false;
+            tried.push_back(lv);
+            rebuilt = gp_build_nn_index(ctx, cp);
+            if (rebuilt != GP_OK) return false;
+            NnParams P = current;
+            P.cell_points = cp;
+            offer(P);
+            return same(best, P);
+        };
+        for (int64_t cp = (int64_t)current.cell_points * 4; cp <= kNnCellPointsMax && try_grid((int32_t)cp); cp *= 4) {
+        }
+        if (best.cell_points == current.cell_points)
+            for (int32_t cp = current.cell_points / 4; cp >= 1 && try_grid(cp); cp /= 4) {
+            }
+        if (rebuilt == GP_OK && e == hipSuccess && ctx->nn_cell_points != best.cell_points)
+            rebuilt = gp_build_nn_index(ctx, best.cell_points);
+        if (rebuilt != GP_OK) {
+            (void)hipEventDestroy(ev[0]);
+            (void)hipEventDestroy(ev[1]);
+            return rebuilt;
+        }
+        const NnParams gridded = best;
         for (int32_t sp : spans)
             for (int32_t sh : shells) {
-                NnParams P = current;
+                NnParams P = gridded;
                 P.span = sp;
                 P.shell = sh;
-                if (sp != current.span || sh != current.shell) offer(P);
+                if (sp != gridded.span || sh != gridded.shell) offer(P);
             }
         const NnParams shaped = best;
         for (int32_t pa : parts) {
@@ -891,8 +940,9 @@ gp_status gp_autotune_nn_impl(gp_ctx ctx, const float* qx, const float* qy, cons
         (void)hipEventDestroy(ev[1]);
         GP_HIP(ctx, e);
         // leave nn holding the chosen configuration's (identical) result
-        k_nn<true><<<(unsigned)(ctx->n_tiles * best.parts), kQueryBlock, 0, ctx->stream>>>(ctx->band(), G, best, qx, qy, qz,
-                                                                                       nn, ctx->nn_pos.p);
+        const Global G{ctx->cell_start.p, ctx->nn_spts.p};
+        k_nn<true><<<(unsigned)(ctx->n_tiles * best.parts), kQueryBlock, 0, ctx->stream>>>(ctx->nn_band(), G, best, qx,
+                                                                                       qy, qz, nn, ctx->nn_pos.p);
         GP_HIP(ctx, hipGetLastError());
     }
     ctx->nn_params = best;

@@ -23,7 +23,7 @@ STATUS = {0: "GP_OK", 1: "GP_ERR_ARG", 2: "GP_ERR_DOMAIN", 3: "GP_ERR_CAPACITY",
           5: "GP_ERR_DEVICE", 6: "GP_ERR_STATE", 7: "GP_ERR_NUMERIC"}
 
 EXPORTS = ("gp_create", "gp_destroy", "gp_last_error", "gp_set_stream", "gp_sync", "gp_build_band",
-           "gp_nn_query", "gp_set_nn_params", "gp_get_nn_params", "gp_autotune_nn", "gp_set_tv_layout", "gp_sample_queries", "gp_pull_forward", "gp_pull_forward_static", "gp_forward_token", "gp_pull_backward", "gp_pull_forward_backward", "gp_pull_normals", "gp_step",
+           "gp_nn_query", "gp_set_nn_params", "gp_get_nn_params", "gp_get_nn_grid", "gp_autotune_nn", "gp_set_tv_layout", "gp_sample_queries", "gp_pull_forward", "gp_pull_forward_static", "gp_forward_token", "gp_pull_backward", "gp_pull_forward_backward", "gp_pull_normals", "gp_step",
            "gp_shape_slots", "gp_export_layout", "gp_export_active_cells", "gp_extract_surface", "gp_gather_vertices", "gp_scatter_vertices",
            "gp_init_sphere", "gp_timing_enable", "gp_timing_report")
 
@@ -46,10 +46,11 @@ class gp_weights(ctypes.Structure):
 
 class gp_nn_params(ctypes.Structure):
     _fields_ = [("group_span", ctypes.c_int32), ("first_shell", ctypes.c_int32), ("tile_parts", ctypes.c_int32),
-                ("skip_empty", ctypes.c_int32), ("morton_sort", ctypes.c_int32)]
+                ("skip_empty", ctypes.c_int32), ("morton_sort", ctypes.c_int32), ("cell_points", ctypes.c_int32)]
 
-    def as_tuple(self) -> Tuple[int, int, int, int, int]:
-        return (self.group_span, self.first_shell, self.tile_parts, self.skip_empty, self.morton_sort)
+    def as_tuple(self) -> Tuple[int, int, int, int, int, int]:
+        return (self.group_span, self.first_shell, self.tile_parts, self.skip_empty, self.morton_sort,
+                self.cell_points)
 
 
 _lib = None
@@ -77,6 +78,7 @@ def load_library(path: str = LIB_PATH):
         "gp_set_nn_params": (st, [P, ctypes.POINTER(gp_nn_params)]),
         "gp_set_tv_layout": (st, [P, i32]),
         "gp_get_nn_params": (st, [P, ctypes.POINTER(gp_nn_params)]),
+        "gp_get_nn_grid": (st, [P, i32, P, P]),
         "gp_autotune_nn": (st, [P, P, P, P, i64, P, i32, ctypes.POINTER(gp_nn_params), ctypes.POINTER(f32)]),
         "gp_sample_queries": (st, [P, u64, i32, P, f32, P, P, P, P]),
         "gp_pull_forward": (st, [P, P, P, P, P, i64, P, gp_weights, P, P]),
@@ -189,9 +191,18 @@ def gp_nn_query(ctx, qx, qy, qz, nn_out) -> None:
 
 
 def gp_set_nn_params(ctx, group_span: int, first_shell: int, tile_parts: int = 1, skip_empty: int = 0,
-                     morton_sort: int = 1) -> None:
-    p = gp_nn_params(int(group_span), int(first_shell), int(tile_parts), int(skip_empty), int(morton_sort))
+                     morton_sort: int = 1, cell_points: int = 8) -> None:
+    """A new cell_points rebuilds the search grids of a built context."""
+    p = gp_nn_params(int(group_span), int(first_shell), int(tile_parts), int(skip_empty), int(morton_sort),
+                     int(cell_points))
     _check(ctx, load_library().gp_set_nn_params(ctx, ctypes.byref(p)))
+
+
+def gp_get_nn_grid(ctx, shape: int) -> Tuple[Tuple[int, int, int], int]:
+    """((cells per axis of the shape's search grid), k): its cells are 2^k band cells wide."""
+    dims, level = (ctypes.c_int32 * 3)(), ctypes.c_int32(0)
+    _check(ctx, load_library().gp_get_nn_grid(ctx, int(shape), dims, ctypes.byref(level)))
+    return (dims[0], dims[1], dims[2]), level.value
 
 
 def gp_set_tv_layout(ctx, layout: int) -> None:
@@ -199,16 +210,16 @@ def gp_set_tv_layout(ctx, layout: int) -> None:
     _check(ctx, load_library().gp_set_tv_layout(ctx, int(layout)))
 
 
-def gp_get_nn_params(ctx) -> Tuple[int, int, int, int, int]:
-    """(group_span, first_shell, tile_parts, skip_empty, morton_sort)."""
+def gp_get_nn_params(ctx) -> Tuple[int, int, int, int, int, int]:
+    """(group_span, first_shell, tile_parts, skip_empty, morton_sort, cell_points)."""
     p = gp_nn_params()
     _check(ctx, load_library().gp_get_nn_params(ctx, ctypes.byref(p)))
     return p.as_tuple()
 
 
-def gp_autotune_nn(ctx, qx, qy, qz, nn_out, reps: int = 2) -> Tuple[Tuple[int, int, int, int, int], float]:
-    """Time the NN search shapes on these queries and keep the fastest:
-    ((group_span, first_shell, tile_parts, skip_empty, morton_sort), ms)."""
+def gp_autotune_nn(ctx, qx, qy, qz, nn_out, reps: int = 2) -> Tuple[Tuple[int, int, int, int, int, int], float]:
+    """Time the search grids and NN search shapes on these queries and keep the fastest:
+    ((group_span, first_shell, tile_parts, skip_empty, morton_sort, cell_points), ms)."""
     _stream(ctx)
     p, ms = gp_nn_params(), ctypes.c_float(0.0)
     _check(ctx, load_library().gp_autotune_nn(ctx, _ptr(qx, torch.float32), _ptr(qy, torch.float32),

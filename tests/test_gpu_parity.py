@@ -418,10 +418,11 @@ def test_batch_with_a_shape_without_queries_and_a_one_point_shape():
 
 def test_nn_search_shapes_and_autotuner():
     """Every NN search shape (group span, first shell, blocks per tile, empty
-    cells skipped or not), including the extremes, and the autotuner's choice
-    give the oracle's indices exactly, on the exact-tie lattice and on a
-    sparse sphere (few points per cell, so most queries leave the lockstep box
-    open and most scanned cells are empty)."""
+    cells skipped or not, search grids finer and coarser than the band),
+    including the extremes, and the autotuner's choice give the oracle's
+    indices exactly, on the exact-tie lattice and on a sparse sphere (few
+    points per cell, so most queries leave the lockstep box open and most
+    scanned cells are empty)."""
     from paper_2308_13175_amd import gridpull as gp
     sparse = synth.cube_domain(64), synth.sphere_points(1500, 0.5, seed=7)
     cases = [("ties",) + _tie_case()[:3],
@@ -430,9 +431,10 @@ def test_nn_search_shapes_and_autotuner():
         nn = oracle.nn_bruteforce(q, pts)
         prob = make_problem([spec(pts, dom, len(q), 0.0)])
         prob.set_queries(q)
-        assert gp.gp_get_nn_params(prob.ctx) == (8, 1, 1, 0, 1)
+        assert gp.gp_get_nn_params(prob.ctx) == (8, 1, 1, 0, 1, 8)
         for shape in [(1, 0, 1, 0, 1), (2, 0, 4, 1, 0), (3, 2, 2, 0, 1), (8, 1, 4, 1, 1), (8, 1, 1, 1, 0),
-                      (16, 0, 2, 1, 1), (64, 4, 1, 0, 0), (64, 4, 4, 1, 1)]:
+                      (16, 0, 2, 1, 1), (64, 4, 1, 0, 0), (64, 4, 4, 1, 1), (8, 1, 1, 0, 1, 1),
+                      (8, 1, 2, 1, 1, 256), (4, 0, 1, 1, 1, 4096), (8, 1, 1, 0, 1, 8)]:
             log("case: %s, search shape %s" % (name, shape))
             gp.gp_set_nn_params(prob.ctx, *shape)
             prob.nn.fill_(-7)
@@ -446,9 +448,9 @@ def test_nn_search_shapes_and_autotuner():
         prob.nn.fill_(-7)
         chosen, ms = prob.autotune(reps=1)
         prob.sync()
-        span, shell, parts, skip, sort = chosen
+        span, shell, parts, skip, sort, cell_points = chosen
         assert span in (4, 6, 8, 12, 16, 24, 32) and shell in (0, 1, 2) and parts in (1, 2, 4)
-        assert skip in (0, 1) and sort in (0, 1)
+        assert skip in (0, 1) and sort in (0, 1) and 1 <= cell_points <= 65536
         assert ms > 0
         assert gp.gp_get_nn_params(prob.ctx) == chosen
         assert np.array_equal(prob.nn[: len(q)].cpu().numpy(), nn)
@@ -456,12 +458,54 @@ def test_nn_search_shapes_and_autotuner():
         prob.sync()
         assert np.array_equal(prob.nn[: len(q)].cpu().numpy(), nn)
         for bad_args in [(0, 1, 1, 0, 1), (65, 1, 1, 0, 1), (8, -1, 1, 0, 1), (8, 5, 1, 0, 1), (8, 1, 3, 0, 1),
-                         (8, 1, 0, 0, 1), (8, 1, 1, 2, 1), (8, 1, 1, 0, 2)]:
+                         (8, 1, 0, 0, 1), (8, 1, 1, 2, 1), (8, 1, 1, 0, 2), (8, 1, 1, 0, 1, 0),
+                         (8, 1, 1, 0, 1, 65537)]:
             with pytest.raises(gp.GridPullError) as ei:
                 gp.gp_set_nn_params(prob.ctx, *bad_args)
             assert ei.value.status == 1
         assert gp.gp_get_nn_params(prob.ctx) == chosen
         prob.close()
+
+
+def _search_level(dom, pts, cell_points):
+    """The search grid's level from its definition: k nearest to
+    log2(cell_points / m) / 2 within [0, 3], m the mean number of points per
+    band cell holding a point (cells by the library's location rule)."""
+    lo, hi, R = np.asarray(dom.lo, np.float64), np.asarray(dom.hi, np.float64), np.asarray(dom.dims, np.int64)
+    u = (pts.astype(np.float64) - lo) * (R / (hi - lo))
+    c = np.clip(np.floor(u), 0, R - 1).astype(np.int64)
+    occupied = len(np.unique((c[:, 0] * R[1] + c[:, 1]) * R[2] + c[:, 2]))
+    return int(min(3, max(0, round(0.5 * math.log2(cell_points / (len(pts) / occupied))))))
+
+
+@pytest.mark.parametrize("res", [16, 32, 64, 128, 256])
+def test_nn_search_grid_across_band_resolutions(res):
+    """The same torus at band resolutions 16 to 256: the search grid takes the
+    level its definition gives (the band's cells where the points are dense,
+    up to 8 band cells wide where they are sparse), covers the box, and the
+    nearest points equal brute force bit for bit at each resolution and at
+    three other density targets."""
+    from paper_2308_13175_amd import gridpull as gp
+    dom = synth.cube_domain(res)
+    pts = synth.torus_points(20_000, seed=1)
+    q = synth.host_queries(pts, 20_000, 0.03, seed=2)
+    ref = oracle.nn_bruteforce(q, pts)
+    prob = make_problem([spec(pts, dom, len(q), 0.0)])
+    prob.set_queries(q)
+    for cell_points in (8, 1, 64, 4096):
+        log("case: torus R=%d, cell_points %d" % (res, cell_points))
+        gp.gp_set_nn_params(prob.ctx, 8, 1, 1, 0, 1, cell_points)
+        dims, level = gp.gp_get_nn_grid(prob.ctx, 0)
+        assert level == _search_level(dom, pts, cell_points)
+        f = 2.0 ** level
+        assert dims == tuple(int(math.ceil(r / f)) for r in dom.dims)
+        prob.nn.fill_(-7)
+        prob.nearest()
+        prob.sync()
+        got = prob.nn[: len(q)].cpu().numpy()
+        bad = np.nonzero(got != ref)[0]
+        assert len(bad) == 0, "R=%d cell_points %d: %d differ" % (res, cell_points, len(bad))
+    prob.close()
 
 
 @pytest.mark.parametrize("layout", [1, 2])
