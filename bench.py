@@ -160,42 +160,6 @@ def copy_bandwidth(mib=1024, reps=10):
     return gbps
 
 
-def tune_nn(prob, samples=3, reps=3):
-    """The NN autotuner on the queries of several iterations (the query sample
-    moves the best search shape), then every shape it chose timed on all of
-    those samples; the best mean is kept.  Returns its mean ms."""
-    import torch
-
-    from paper_2308_13175_amd import gridpull as gp
-
-    chosen = []
-    for it in range(1, samples + 1):
-        prob.sample(0, it)
-        shape, _ = prob.autotune(reps=reps)
-        if shape not in chosen:
-            chosen.append(shape)
-    best, best_ms = None, None
-    for shape in chosen:
-        gp.gp_set_nn_params(prob.ctx, *shape)
-        total = 0.0
-        for it in range(1, samples + 1):
-            prob.sample(0, it)
-            prob.nearest()
-            ms = []
-            for _ in range(2):
-                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-                e0.record()
-                prob.nearest()
-                e1.record()
-                torch.cuda.synchronize()
-                ms.append(e0.elapsed_time(e1))
-            total += min(ms)
-        if best_ms is None or total / samples < best_ms:
-            best, best_ms = shape, total / samples
-    gp.gp_set_nn_params(prob.ctx, *best)
-    return best_ms
-
-
 def fwd_bwd_median_ms(prob, n=50):
     """Median duration of one fused forward + backward (query pass, TV, loss) by events."""
     import torch
@@ -340,12 +304,13 @@ def batched_record(args):
     import torch
 
     from paper_2308_13175_amd import gridpull as gp
+    from paper_2308_13175_amd import tuning
 
     wl, prob, setup_ms = build_problem(4)
     for _ in range(args.warmup):
         prob.iteration(None)
     if not args.no_autotune:
-        tune_nn(prob)
+        tuning.tune_nn(prob)
     prob.iteration(None)
     rec = batched_vs_per_shape(wl, prob, max(3, args.steps // 5), 2, not args.no_autotune)
     rec["setup_ms"] = setup_ms
@@ -397,6 +362,7 @@ def schedule_sweep(kind: str, iters: int = 1600, n_points: int = 200_000, n_quer
     import torch
 
     from paper_2308_13175_amd import gridpull as gp
+    from paper_2308_13175_amd import tuning
     from paper_2308_13175_amd import synth
     from paper_2308_13175_amd.problem import AdamConfig, GraphedIteration, Problem, ShapeSpec
 
@@ -419,7 +385,7 @@ def schedule_sweep(kind: str, iters: int = 1600, n_points: int = 200_000, n_quer
         torch.cuda.synchronize()
         setup_s = time.perf_counter() - t0
         prob.iteration(1)
-        tune_nn(prob)   # before the capture: the graph keeps the search shape
+        tuning.tune_nn(prob)   # before the capture: the graph keeps the search shape
         nn_search = gp.gp_get_nn_params(prob.ctx)
         graph = GraphedIteration(prob)
         prob.init_sphere()
@@ -471,6 +437,7 @@ def surface_runs(iters: int = 1600, n_queries: int = 50_000):
     import torch
 
     from paper_2308_13175_amd import gridpull as gp
+    from paper_2308_13175_amd import tuning
     from paper_2308_13175_amd import metrics, synth
     from paper_2308_13175_amd.problem import AdamConfig, GraphedIteration, Problem, ShapeSpec
 
@@ -499,7 +466,7 @@ def surface_runs(iters: int = 1600, n_queries: int = 50_000):
         if normals is not None:
             prob.set_normals(normals, 1.0)
         prob.iteration(1)
-        tune_nn(prob)
+        tuning.tune_nn(prob)
         graph = GraphedIteration(prob)
         prob.init_sphere()
         torch.cuda.synchronize()
@@ -743,7 +710,10 @@ def main():
                     help="instead of the benchmark: whole runs, then the extracted mesh against the closed-form "
                          "surface (CD, NC, F-score), one JSON line per shape and grid")
     ap.add_argument("--no-autotune", action="store_true",
-                    help="keep the default NN search shape instead of timing the candidates first")
+                    help="keep the default search and gradient-pass settings instead of tuning them first")
+    ap.add_argument("--tuning-cache", default=None,
+                    help="JSON cache of tuned settings per GPU architecture and size class (default: "
+                         "~/.cache/gridpull/tuning.json); 'none' always tunes afresh and stores nothing")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 256 MiB device copy (scale for the HBM byte counters)")
     args = ap.parse_args()
@@ -755,6 +725,7 @@ def main():
     import torch
 
     from paper_2308_13175_amd import gridpull as gp
+    from paper_2308_13175_amd import tuning
 
     torch.cuda.set_device(0)
     if args.sweep:
@@ -769,11 +740,16 @@ def main():
 
     for _ in range(args.warmup):
         prob.iteration(None)
-    tuned_ms = None
+    tuned = None
     if not args.no_autotune:
-        tuned_ms = tune_nn(prob)
+        cache = tuning.DEFAULT_CACHE if args.tuning_cache is None else (
+            None if args.tuning_cache == "none" else args.tuning_cache)
+        tuned = tuning.tune(prob, cache)
+        log("tuning (%s, %s): %s" % (tuned["key"], tuned["source"], tuned))
     nn_params = gp.gp_get_nn_params(prob.ctx)
-    log("NN search shape: %s%s" % (nn_params, " (autotuned, %.3f ms)" % tuned_ms if tuned_ms is not None else ""))
+    grad_params = gp.gp_get_grad_params(prob.ctx)
+    nn_grids = sorted({gp.gp_get_nn_grid(prob.ctx, s)[1] for s in range(len(wl.shapes))})
+    log("NN search shape: %s, search grid levels %s; gradient pass: %s" % (nn_params, nn_grids, grad_params))
     it = iteration_rate(prob, max(5, args.steps // 2), args.warmup, graph=not args.no_graph)
     prob.sync()
     loss = prob.loss.cpu().numpy()
@@ -833,7 +809,11 @@ def main():
                     "copy_frac": fb_bytes / (ms_step * 1e-3) / 1e9 / copy_gbps},
         "iteration": {"step": "sample+nn+forward+backward+adam", **it},
         "nn": {"queries_per_s": Q / (nn_ms * 1e-3) if nn_ms else None, "ms": nn_ms,
-               "search_shape": list(nn_params), "autotuned": tuned_ms is not None, "autotune_best_ms": tuned_ms},
+               "search_shape": list(nn_params), "search_grid_levels": nn_grids},
+        "tuning": {"nn": list(nn_params), "grad": list(grad_params),
+                   "key": tuned["key"] if tuned else None, "source": tuned["source"] if tuned else "defaults",
+                   "nn_ms": tuned.get("nn_ms") if tuned else None,
+                   "grad_ms": tuned.get("grad_ms") if tuned else None},
         "copy_GBps": copy_gbps,
         "kernels_hbm": kernels_hbm,
         "setup_ms": setup_ms,

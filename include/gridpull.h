@@ -229,10 +229,63 @@ gp_status gp_autotune_nn(gp_ctx ctx, const float* qx, const float* qy, const flo
  * arithmetic either way): 1 = one block per brick, one thread per vertex;
  * 2 = one wave per brick, one lane per column of eight vertices; 0 (the
  * default) = by band size: the forward uses 2 from 2048 bricks on, the
- * backward from 16384.  The setting belongs to the context.
+ * backward from 16384.  Sets the two thresholds of gp_grad_params (1: both
+ * INT64_MAX, 2: both 0, 0: the defaults).  The setting belongs to the context.
  * Errors: GP_ERR_ARG (layout not 0, 1 or 2).
  */
 gp_status gp_set_tv_layout(gp_ctx ctx, int32_t layout);
+
+/*
+ * Settings of the gradient pass (derivative of Eq. 4-7 scattered to the
+ * field) and of the TV kernels (Eq. 5); every value gives the same
+ * arithmetic, only the speed changes (and, through the order of float
+ * atomics between blocks, the last bits of the gradient).
+ *   window_cap:         LDS window of a query block, in vertices: 2304, 4608
+ *                       (default) or 6912 (8 bytes each: 18, 36 or 54 KB of
+ *                       LDS per 256-query block, so fewer blocks per CU);
+ *   window_max_passes:  [1, 64], default 16: a block whose box of query and
+ *                       nearest-point cells needs more slab passes through
+ *                       the window adds its contributions straight to the
+ *                       gradient with global atomics;
+ *   tv_forward_wave_from, tv_backward_wave_from: >= 0; from this many
+ *                       bricks on, the TV forward (backward) takes one wave
+ *                       per brick, below it one block (defaults 2048, 16384).
+ * The settings belong to the context and survive gp_build_band.
+ * Errors: GP_ERR_ARG (null pointer, a field out of range).
+ */
+typedef struct {
+    int32_t window_cap;
+    int32_t window_max_passes;
+    int64_t tv_forward_wave_from;
+    int64_t tv_backward_wave_from;
+} gp_grad_params;
+
+gp_status gp_set_grad_params(gp_ctx ctx, const gp_grad_params* params);
+gp_status gp_get_grad_params(gp_ctx ctx, gp_grad_params* params);
+
+/*
+ * Autotuner of gp_grad_params on the caller's queries, nearest points and
+ * field (arguments as gp_pull_forward_backward): times the fused query pass
+ * for window_cap in {2304, 4608, 6912} x window_max_passes in {4, 16, 64},
+ * then the TV forward and the TV backward in each layout at the band's size
+ * (the faster one moves its threshold to the band's brick count, so that
+ * bands at least as large take the wave layout, or just above it).  Each
+ * candidate runs once and then reps times between HIP events on the
+ * context's stream (its time: the smallest of the repeats).  The current
+ * setting stays unless another is at least 2% faster.  Leaves the gradient
+ * and loss arrays of the caller untouched (it runs on the context's
+ * scratch), and invalidates the context's last forward (gp_forward_token).
+ * reps in [1, 100]; chosen_out (host, may be NULL) receives the settings,
+ * best_ms_out (host [3], may be NULL) the chosen query pass, TV forward and
+ * TV backward times in ms (-1 for a part with nothing to time).
+ * Synchronises; not for use under stream capture.
+ * Errors: GP_ERR_STATE before gp_build_band, GP_ERR_ARG (null pointers,
+ * n_queries not the end of the last shape's query slice, reps),
+ * GP_ERR_DEVICE.
+ */
+gp_status gp_autotune_grad(gp_ctx ctx, const float* qx, const float* qy, const float* qz, const int32_t* nn,
+                           int64_t n_queries, const float* field, gp_weights w, int32_t reps,
+                           gp_grad_params* chosen_out, float* best_ms_out);
 
 /*
  * Draw one iteration's queries (Sec. 3: Gaussian around randomly chosen

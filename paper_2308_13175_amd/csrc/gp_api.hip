@@ -275,7 +275,62 @@ gp_status gp_set_tv_layout(gp_ctx ctx, int32_t layout)
 {
     if (!ctx) return GP_ERR_ARG;
     if (layout < 0 || layout > 2) return gp_fail(ctx, GP_ERR_ARG, "layout must be 0, 1 or 2");
-    ctx->tv_layout = layout;
+    const gp::GradParams d;
+    gp::GradParams& g = ctx->grad_params;
+    g.tv_fwd_wave_from = layout == 0 ? d.tv_fwd_wave_from : (layout == 1 ? INT64_MAX : 0);
+    g.tv_bwd_wave_from = layout == 0 ? d.tv_bwd_wave_from : (layout == 1 ? INT64_MAX : 0);
+    return GP_OK;
+}
+
+gp_status gp_set_grad_params(gp_ctx ctx, const gp_grad_params* params)
+{
+    if (!ctx) return GP_ERR_ARG;
+    if (!params) return gp_fail(ctx, GP_ERR_ARG, "null params");
+    bool cap_ok = false;
+    for (int32_t c : gp::kWinCaps) cap_ok = cap_ok || params->window_cap == c;
+    if (!cap_ok) return gp_fail(ctx, GP_ERR_ARG, "window_cap must be 2304, 4608 or 6912");
+    if (params->window_max_passes < 1 || params->window_max_passes > gp::kWinPassesMax)
+        return gp_fail(ctx, GP_ERR_ARG, "window_max_passes must be in [1, 64]");
+    if (params->tv_forward_wave_from < 0 || params->tv_backward_wave_from < 0)
+        return gp_fail(ctx, GP_ERR_ARG, "the TV thresholds must be >= 0");
+    gp::GradParams& g = ctx->grad_params;
+    g.win_cap = params->window_cap;
+    g.win_max_passes = params->window_max_passes;
+    g.tv_fwd_wave_from = params->tv_forward_wave_from;
+    g.tv_bwd_wave_from = params->tv_backward_wave_from;
+    return GP_OK;
+}
+
+static void grad_params_out(const gp::GradParams& g, gp_grad_params* out)
+{
+    out->window_cap = g.win_cap;
+    out->window_max_passes = g.win_max_passes;
+    out->tv_forward_wave_from = g.tv_fwd_wave_from;
+    out->tv_backward_wave_from = g.tv_bwd_wave_from;
+}
+
+gp_status gp_get_grad_params(gp_ctx ctx, gp_grad_params* params)
+{
+    if (!ctx) return GP_ERR_ARG;
+    if (!params) return gp_fail(ctx, GP_ERR_ARG, "null output");
+    grad_params_out(ctx->grad_params, params);
+    return GP_OK;
+}
+
+gp_status gp_autotune_grad(gp_ctx ctx, const float* qx, const float* qy, const float* qz, const int32_t* nn,
+                           int64_t n_queries, const float* field, gp_weights w, int32_t reps,
+                           gp_grad_params* chosen_out, float* best_ms_out)
+{
+    gp_status st = ready(ctx);
+    if (st != GP_OK) return st;
+    if ((st = check_queries(ctx, qx, qy, qz, n_queries)) != GP_OK) return st;
+    if ((n_queries > 0 && !nn) || !field) return gp_fail(ctx, GP_ERR_ARG, "null nn or field");
+    if (reps < 1 || reps > 100) return gp_fail(ctx, GP_ERR_ARG, "reps must be in [1, 100]");
+    ctx->fwd_token = 0;
+    gp::GradParams best;
+    st = gp_autotune_grad_impl(ctx, qx, qy, qz, nn, field, w, reps, &best, best_ms_out);
+    if (st != GP_OK) return st;
+    if (chosen_out) grad_params_out(best, chosen_out);
     return GP_OK;
 }
 

@@ -89,6 +89,22 @@ constexpr int32_t kNnSpanMax = 64;
 constexpr int32_t kNnShellMax = 4;
 constexpr int32_t kNnCellPointsMax = 65536;
 
+// Settings of the gradient pass and the TV kernels (any values give the same
+// arithmetic; only the speed changes): the LDS window of the query pass in
+// vertices (kWinCaps; 8 bytes each, allocated at launch), the most slab
+// passes a block takes before its contributions go straight to the gradient,
+// and the band sizes (bricks) from which the TV forward and backward take one
+// wave per brick instead of one block.
+constexpr int32_t kWinCaps[3] = {2304, 4608, 6912};
+constexpr int32_t kWinCapMax = 6912;
+constexpr int32_t kWinPassesMax = 64;
+struct GradParams {
+    int32_t win_cap = 4608;
+    int32_t win_max_passes = 16;
+    int64_t tv_fwd_wave_from = 2048;
+    int64_t tv_bwd_wave_from = 16384;
+};
+
 struct Loc {
     int32_t c[3];
     double t[3];     // exact local coordinate in [0, 1]
@@ -398,7 +414,7 @@ struct gp_ctx_s {
     const void* fwd_arrays[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};   // qx, qy, qz, nn, field
 
     gp::NnParams nn_params;       // set by gp_set_nn_params or gp_autotune_nn
-    int32_t tv_layout = 0;        // 0 by band size, 1 block per brick, 2 wave per brick (gp_set_tv_layout)
+    gp::GradParams grad_params;   // set by gp_set_grad_params, gp_set_tv_layout or gp_autotune_grad
 
     // optional per-kernel timing with events on the context's stream
     struct TimedLaunch {
@@ -479,6 +495,9 @@ gp_status gp_sample_impl(gp_ctx ctx, uint64_t seed, int32_t iteration, const flo
                          float sigma_const, float* qx, float* qy, float* qz, int32_t* src);
 gp_status gp_step_consts_impl(gp_ctx ctx, int32_t t, float lr0, float decay, int32_t decay_every, float beta1,
                               float beta2);
+gp_status gp_autotune_grad_impl(gp_ctx ctx, const float* qx, const float* qy, const float* qz, const int32_t* nn,
+                                const float* field, gp_weights w, int32_t reps, gp::GradParams* best_out,
+                                float* best_ms_out);
 gp_status gp_forward_impl(gp_ctx ctx, const float* qx, const float* qy, const float* qz,
                           const int32_t* nn, const float* field, gp_weights w,
                           double* loss_out, int64_t* n_valid_out);

@@ -202,8 +202,10 @@ __device__ inline void query_adjoint(const ShapeDesc& s, const QueryState& st, g
 // the gradient once.  A box larger than the window is taken in slabs of
 // whole layers along x or y (whichever makes the smaller cross-section), one
 // pass each: a contribution is added in the pass of its slab.  A box that
-// would take more than kWinMaxPasses passes sends its contributions straight
-// to the gradient (global float atomics).
+// would take more than the context's maximum number of passes sends its
+// contributions straight to the gradient (global float atomics).  The
+// window's size (in LDS allocated at launch) and that maximum are settings of
+// the context (gp_set_grad_params).
 // The flush walks the window in index order (z fastest), so that the lanes
 // of a wave add to runs of consecutive slots (a z-run is contiguous inside a
 // brick) and clear what they read; the slot of an entry comes from an LDS
@@ -214,9 +216,22 @@ __device__ inline void query_adjoint(const ShapeDesc& s, const QueryState& st, g
 // block are exact.  A contribution of 2^20 or more in magnitude bypasses the
 // window, so no sum leaves the range of the fixed point (a vertex receives
 // at most 2 contributions from each of the 256 queries).
-constexpr int kWinCap = 4608;      // window vertices (36 KB)
-constexpr int kWinMaxPasses = 16;
-constexpr int kWinBricks = 768;    // directory entries of a slab's bricks (at most 578 for kWinCap vertices)
+// Directory entries of a slab's bricks, at most: a slab of d0 x d1 x d2 <= cap
+// vertices meets at most prod(floor((d_i + 6) / 8) + 1) bricks, largest for
+// 2 x 2 x cap/4 (two bricks on each short axis).
+__host__ __device__ constexpr int32_t win_bricks_bound(int32_t cap)
+{
+    return 4 * ((cap / 4 + 6) / 8 + 1);
+}
+
+// LDS of a query block: the window (cap 64-bit entries), then the slab's
+// brick directory entries.
+__host__ __device__ constexpr int32_t win_lds_bytes(int32_t cap)
+{
+    return cap * 8 + win_bricks_bound(cap) * 4;
+}
+static_assert(win_bricks_bound(4608) == 580 && win_bricks_bound(6912) == 868, "slab brick bound");
+static_assert(win_lds_bytes(kWinCapMax) <= 64 * 1024 - 512, "window LDS within one workgroup's 64 KB");
 constexpr double kFixScale = 4294967296.0;   // 2^32
 constexpr float kFixLimit = 1048576.f;       // 2^20
 
@@ -231,7 +246,7 @@ struct Window {
     int32_t passes;
 };
 
-__device__ inline Window choose_window(const int32_t box[6])
+__device__ inline Window choose_window(const int32_t box[6], int32_t cap, int32_t max_passes)
 {
     Window W;
     W.passes = 0;
@@ -244,10 +259,10 @@ __device__ inline Window choose_window(const int32_t box[6])
     if (box[3] < 0) return W;   // no valid query
     W.ax = W.w[1] > W.w[0] ? 1 : 0;
     const int64_t cross = (int64_t)W.w[1 - W.ax] * W.w[2];
-    if (cross > kWinCap) return W;
-    W.layers = (int32_t)min((int64_t)W.w[W.ax], kWinCap / cross);
+    if (cross > cap) return W;
+    W.layers = (int32_t)min((int64_t)W.w[W.ax], cap / cross);
     const int32_t passes = (W.w[W.ax] + W.layers - 1) / W.layers;
-    if (passes <= kWinMaxPasses) W.passes = passes;
+    if (passes <= max_passes) W.passes = passes;
     return W;
 }
 
@@ -372,12 +387,12 @@ __global__ __launch_bounds__(kGradBlock) void k_query_grad(Band B, const float* 
                                                            const double* __restrict__ dloss,
                                                            const double* __restrict__ inv_qv,
                                                            float* __restrict__ G, double* __restrict__ q_part,
-                                                           int32_t* flag)
+                                                           int32_t* flag, int32_t cap, int32_t max_passes)
 {
-    __shared__ unsigned long long s_acc[kWinCap];
+    extern __shared__ __align__(16) unsigned long long s_acc[];   // [cap], then the slab's directory entries
     __shared__ double s_red[kGradBlock / 64 * 4];
     __shared__ int32_t s_box[kGradBlock / 64 * 6];
-    __shared__ int32_t s_wdir[kWinBricks];
+    int32_t* const s_wdir = reinterpret_cast<int32_t*>(s_acc + cap);
     const int64_t item = xcd_work_item(blockIdx.x, gridDim.x);
     const int64_t tile = item / kGradParts;
     const int32_t quarter = (int32_t)(item % kGradParts);
@@ -387,7 +402,7 @@ __global__ __launch_bounds__(kGradBlock) void k_query_grad(Band B, const float* 
     const int64_t qe = min(B.tile_start[tile] + (int64_t)kQueryTile, s.query_off + s.query_cnt);
     const float scale = kLoss ? 1.f : (float)(dloss[shape] * inv_qv[shape]);
 
-    for (int32_t i = threadIdx.x; i < kWinCap / 2; i += blockDim.x)
+    for (int32_t i = threadIdx.x; i < cap / 2; i += blockDim.x)
         reinterpret_cast<ulonglong2*>(s_acc)[i] = make_ulonglong2(0ull, 0ull);
 
     const int64_t k = q0 + threadIdx.x;
@@ -430,7 +445,7 @@ __global__ __launch_bounds__(kGradBlock) void k_query_grad(Band B, const float* 
     block_minmax6(box, s_box);   // (its barriers also order the window clear)
 #pragma unroll
     for (int a = 0; a < 6; ++a) box[a] = __builtin_amdgcn_readfirstlane(box[a]);
-    const Window W = choose_window(box);
+    const Window W = choose_window(box, cap, max_passes);
     if (W.passes == 0) {
         if (valid) {
             direct_add(sq, cq, G, scale);
@@ -886,7 +901,7 @@ __global__ __launch_bounds__(kFinalizeBlock) void k_finalize(Band B, const doubl
     if (!s_last) return;
     // the shape's last block: every chunk's sums are visible after the fence;
     // one load per thread, then the chunks are added in order
-    static_assert(kFinChunks * 5 <= kFinalizeBlock, "one chunk sum per thread");
+static_assert(kFinChunks * 5 <= kFinalizeBlock, "one chunk sum per thread");
     __shared__ double s_chunk[kFinChunks * 5];
     __threadfence();
     if (threadIdx.x < nch * 5)
@@ -920,25 +935,22 @@ __global__ __launch_bounds__(kFinalizeBlock) void k_finalize(Band B, const doubl
 
 using namespace gp;
 
-// TV layout for this context, unless gp_set_tv_layout fixed one: block per
-// brick for a small band (more waves), wave per brick for a large one (more
-// bricks in flight).  Measured crossovers: the forward gains from about 2000
-// bricks (0.44 -> 0.26 ms at 137k bricks, 24 -> 19 us at 6k), the backward,
-// which moves two arrays and keeps more registers, only far above 6k bricks
-// (0.71 -> 0.54 ms at 137k, 32 -> 34 us at 6k).
-constexpr int64_t kTvWaveMinBricksFwd = 2048;
-constexpr int64_t kTvWaveMinBricksBwd = 16384;
-
-static bool tv_wave_layout(gp_ctx ctx, int64_t min_bricks)
+// TV layout: block per brick for a small band (more waves), wave per brick
+// for a large one (more bricks in flight), from the context's thresholds
+// (defaults from measured crossovers: the forward gains from about 2000
+// bricks, 0.44 -> 0.26 ms at 137k bricks and 24 -> 19 us at 6k; the
+// backward, which moves two arrays and keeps more registers, only far above
+// 6k bricks, 0.71 -> 0.54 ms at 137k and 32 -> 34 us at 6k).
+static bool tv_wave_layout(gp_ctx ctx, int64_t wave_from)
 {
-    return ctx->tv_layout == 2 || (ctx->tv_layout == 0 && ctx->n_bricks >= min_bricks);
+    return ctx->n_bricks >= wave_from;
 }
 
 // itau may be null (the loss alone); tv_part receives the per-brick sums.
 static void launch_tv_forward(gp_ctx ctx, const Band& B, const float* field, float* itau, double* tv_part,
                               hipStream_t st)
 {
-    if (tv_wave_layout(ctx, kTvWaveMinBricksFwd))
+    if (tv_wave_layout(ctx, ctx->grad_params.tv_fwd_wave_from))
         k_tv_forward_wave<<<(unsigned)((ctx->n_bricks + kTvWaves - 1) / kTvWaves), kTvWaves * 64, 0, st>>>(
             B, field, itau, tv_part, (int32_t)ctx->n_bricks);
     else
@@ -948,7 +960,7 @@ static void launch_tv_forward(gp_ctx ctx, const Band& B, const float* field, flo
 static void launch_tv_backward(gp_ctx ctx, const Band& B, const float* field, gp_weights w, const double* dloss,
                                float* raw, float* grad, hipStream_t st)
 {
-    if (tv_wave_layout(ctx, kTvWaveMinBricksBwd))
+    if (tv_wave_layout(ctx, ctx->grad_params.tv_bwd_wave_from))
         k_tv_backward_wave<<<(unsigned)((ctx->n_bricks + kTvWaves - 1) / kTvWaves), kTvWaves * 64, 0, st>>>(
             B, field, ctx->tau.p, w, dloss, ctx->inv_qv.p, raw, grad, (int32_t)ctx->n_bricks);
     else
@@ -984,9 +996,10 @@ gp_status gp_backward_impl(gp_ctx ctx, const float* qx, const float* qy, const f
     Band B = ctx->band();
     if (ctx->n_tiles > 0) {
         GP_TIMED(ctx, "k_backward_query");
-        k_query_grad<false><<<(unsigned)(ctx->n_tiles * kGradParts), kGradBlock, 0, st>>>(
+        const GradParams& gpar = ctx->grad_params;
+        k_query_grad<false><<<(unsigned)(ctx->n_tiles * kGradParts), kGradBlock, win_lds_bytes(gpar.win_cap), st>>>(
             B, qx, qy, qz, nn, ctx->points(), field, w, dloss, ctx->inv_qv.p, grad, nullptr,
-            ctx->flag.p);
+            ctx->flag.p, gpar.win_cap, gpar.win_max_passes);
     }
     if (ctx->n_bricks > 0) {
         GP_TIMED(ctx, "k_tv_backward");
@@ -1004,9 +1017,10 @@ gp_status gp_forward_backward_impl(gp_ctx ctx, const float* qx, const float* qy,
     Band B = ctx->band();
     if (ctx->n_tiles > 0) {
         GP_TIMED(ctx, "k_query_grad");
-        k_query_grad<true><<<(unsigned)(ctx->n_tiles * kGradParts), kGradBlock, 0, st>>>(
+        const GradParams& gpar = ctx->grad_params;
+        k_query_grad<true><<<(unsigned)(ctx->n_tiles * kGradParts), kGradBlock, win_lds_bytes(gpar.win_cap), st>>>(
             B, qx, qy, qz, nn, ctx->points(), field, w, dloss, ctx->inv_qv.p, ctx->g_raw.p,
-            ctx->q_part.p, ctx->flag.p);
+            ctx->q_part.p, ctx->flag.p, gpar.win_cap, gpar.win_max_passes);
     }
     if (ctx->n_bricks > 0) {
         GP_TIMED(ctx, "k_tv_forward");
@@ -1106,5 +1120,116 @@ gp_status gp_forward_static_impl(gp_ctx ctx, const float* qx, const float* qy, c
     k_finalize<<<dim3(kFinChunks, (unsigned)ctx->n_shapes), kFinalizeBlock, 0, st>>>(
         B, q_part, tv_part, w, loss_out, n_valid_out, inv_qv, ctx->flag.p, 1, fin_part, fin_count);
     GP_HIP(ctx, hipGetLastError());
+    return GP_OK;
+}
+
+// ---------------------------------------------------------------------------
+// gp_autotune_grad: the window settings of the fused query pass, then the TV
+// layouts at this band's size, each timed between events on the context's
+// stream (one untimed run, then the smallest of reps runs).  The query pass
+// accumulates into the context's own accumulator, cleared afterwards; the TV
+// backward writes a scratch gradient.
+gp_status gp_autotune_grad_impl(gp_ctx ctx, const float* qx, const float* qy, const float* qz, const int32_t* nn,
+                                const float* field, gp_weights w, int32_t reps, GradParams* best_out,
+                                float* best_ms_out)
+{
+    static const int32_t kPasses[] = {4, 16, 64};
+    hipStream_t st = ctx->stream;
+    const Band B = ctx->band();
+    const GradParams current = ctx->grad_params;
+    GradParams best = current;
+    float ms[3] = {-1.f, -1.f, -1.f};
+    hipEvent_t ev[2];
+    GP_HIP(ctx, hipEventCreate(&ev[0]));
+    if (hipEventCreate(&ev[1]) != hipSuccess) {
+        (void)hipEventDestroy(ev[0]);
+        return gp_fail(ctx, GP_ERR_DEVICE, "hipEventCreate failed");
+    }
+    hipError_t e = hipSuccess;
+    auto time_it = [&](auto&& launch) -> float {
+        float t_min = -1.f;
+        for (int32_t r = 0; r <= reps && e == hipSuccess; ++r) {
+            if (r > 0) e = hipEventRecord(ev[0], st);
+            if (e == hipSuccess) launch();
+            if (e == hipSuccess) e = hipGetLastError();
+            if (r > 0 && e == hipSuccess) e = hipEventRecord(ev[1], st);
+            if (r > 0 && e == hipSuccess) e = hipEventSynchronize(ev[1]);
+            float t = 0.f;
+            if (r > 0 && e == hipSuccess) e = hipEventElapsedTime(&t, ev[0], ev[1]);
+            if (r > 0 && e == hipSuccess && (t_min < 0.f || t < t_min)) t_min = t;
+        }
+        return t_min;
+    };
+    DevBuf<float> grad;
+    DevBuf<double> dloss;
+    if (ctx->n_tiles > 0) {
+        auto query_pass = [&](int32_t cap, int32_t passes) {
+            return time_it([&] {
+                k_query_grad<true><<<(unsigned)(ctx->n_tiles * kGradParts), kGradBlock, win_lds_bytes(cap), st>>>(
+                    B, qx, qy, qz, nn, ctx->points(), field, w, nullptr, nullptr, ctx->g_raw.p, ctx->q_part.p,
+                    ctx->flag.p, cap, passes);
+            });
+        };
+        float best_t = query_pass(current.win_cap, current.win_max_passes);
+        for (int32_t cap : kWinCaps)
+            for (int32_t passes : kPasses) {
+                if (cap == current.win_cap && passes == current.win_max_passes) continue;
+                const float t = query_pass(cap, passes);
+                if (e != hipSuccess || t < 0.f) continue;
+                const bool holding = best.win_cap == current.win_cap && best.win_max_passes == current.win_max_passes;
+                if (t < best_t * (holding ? 0.98f : 1.f)) {
+                    best_t = t;
+                    best.win_cap = cap;
+                    best.win_max_passes = passes;
+                }
+            }
+        ms[0] = best_t;
+        if (e == hipSuccess) e = hipMemsetAsync(ctx->g_raw.p, 0, (size_t)std::max<int64_t>(ctx->n_slots, 1) * 4, st);
+    }
+    if (ctx->n_bricks > 0 && e == hipSuccess) {
+        const int64_t nb = ctx->n_bricks;
+        const unsigned waves_grid = (unsigned)((nb + kTvWaves - 1) / kTvWaves);
+        // forward: writes the context's 1/tau and per-brick partials (scratch until the next forward)
+        const float t_wave = time_it([&] {
+            k_tv_forward_wave<<<waves_grid, kTvWaves * 64, 0, st>>>(B, field, ctx->tau.p, ctx->tv_part.p, (int32_t)nb);
+        });
+        const float t_brick = time_it([&] {
+            k_tv_forward_brick<<<(unsigned)nb, kBrickVol, 0, st>>>(B, field, ctx->tau.p, ctx->tv_part.p);
+        });
+        const bool wave_now = nb >= current.tv_fwd_wave_from;
+        const float t_now = wave_now ? t_wave : t_brick, t_other = wave_now ? t_brick : t_wave;
+        if (e == hipSuccess && t_other >= 0.f && t_other < 0.98f * t_now)
+            best.tv_fwd_wave_from = wave_now ? nb + 1 : std::min(current.tv_fwd_wave_from, nb);
+        ms[1] = (t_other >= 0.f && t_other < 0.98f * t_now) ? t_other : t_now;
+        // backward (the TV gradient alone, into a scratch gradient)
+        if (e == hipSuccess) e = grad.alloc((size_t)std::max<int64_t>(ctx->n_slots, 1));
+        if (e == hipSuccess) e = dloss.alloc((size_t)ctx->n_shapes);
+        if (e == hipSuccess) {
+            std::vector<double> ones((size_t)ctx->n_shapes, 1.0);
+            e = hipMemcpyAsync(dloss.p, ones.data(), ones.size() * sizeof(double), hipMemcpyHostToDevice, st);
+            if (e == hipSuccess) e = hipStreamSynchronize(st);
+        }
+        const float b_wave = time_it([&] {
+            k_tv_backward_wave<<<waves_grid, kTvWaves * 64, 0, st>>>(B, field, ctx->tau.p, w, dloss.p, ctx->inv_qv.p,
+                                                                    nullptr, grad.p, (int32_t)nb);
+        });
+        const float b_brick = time_it([&] {
+            k_tv_backward_brick<<<(unsigned)nb, kBrickVol, 0, st>>>(B, field, ctx->tau.p, w, dloss.p, ctx->inv_qv.p,
+                                                                 nullptr, grad.p);
+        });
+        const bool bwave_now = nb >= current.tv_bwd_wave_from;
+        const float b_now = bwave_now ? b_wave : b_brick, b_other = bwave_now ? b_brick : b_wave;
+        if (e == hipSuccess && b_other >= 0.f && b_other < 0.98f * b_now)
+            best.tv_bwd_wave_from = bwave_now ? nb + 1 : std::min(current.tv_bwd_wave_from, nb);
+        ms[2] = (b_other >= 0.f && b_other < 0.98f * b_now) ? b_other : b_now;
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    (void)hipEventDestroy(ev[0]);
+    (void)hipEventDestroy(ev[1]);
+    GP_HIP(ctx, e);
+    ctx->grad_params = best;
+    if (best_out) *best_out = best;
+    if (best_ms_out)
+        for (int i = 0; i < 3; ++i) best_ms_out[i] = ms[i];
     return GP_OK;
 }

@@ -23,7 +23,7 @@ STATUS = {0: "GP_OK", 1: "GP_ERR_ARG", 2: "GP_ERR_DOMAIN", 3: "GP_ERR_CAPACITY",
           5: "GP_ERR_DEVICE", 6: "GP_ERR_STATE", 7: "GP_ERR_NUMERIC"}
 
 EXPORTS = ("gp_create", "gp_destroy", "gp_last_error", "gp_set_stream", "gp_sync", "gp_build_band",
-           "gp_nn_query", "gp_set_nn_params", "gp_get_nn_params", "gp_get_nn_grid", "gp_autotune_nn", "gp_set_tv_layout", "gp_sample_queries", "gp_pull_forward", "gp_pull_forward_static", "gp_forward_token", "gp_pull_backward", "gp_pull_forward_backward", "gp_pull_normals", "gp_step",
+           "gp_nn_query", "gp_set_nn_params", "gp_get_nn_params", "gp_get_nn_grid", "gp_autotune_nn", "gp_set_tv_layout", "gp_set_grad_params", "gp_get_grad_params", "gp_autotune_grad", "gp_sample_queries", "gp_pull_forward", "gp_pull_forward_static", "gp_forward_token", "gp_pull_backward", "gp_pull_forward_backward", "gp_pull_normals", "gp_step",
            "gp_shape_slots", "gp_export_layout", "gp_export_active_cells", "gp_extract_surface", "gp_gather_vertices", "gp_scatter_vertices",
            "gp_init_sphere", "gp_timing_enable", "gp_timing_report")
 
@@ -53,6 +53,14 @@ class gp_nn_params(ctypes.Structure):
                 self.cell_points)
 
 
+class gp_grad_params(ctypes.Structure):
+    _fields_ = [("window_cap", ctypes.c_int32), ("window_max_passes", ctypes.c_int32),
+                ("tv_forward_wave_from", ctypes.c_int64), ("tv_backward_wave_from", ctypes.c_int64)]
+
+    def as_tuple(self) -> Tuple[int, int, int, int]:
+        return (self.window_cap, self.window_max_passes, self.tv_forward_wave_from, self.tv_backward_wave_from)
+
+
 _lib = None
 
 
@@ -77,6 +85,9 @@ def load_library(path: str = LIB_PATH):
         "gp_nn_query": (st, [P, P, P, P, i64, P]),
         "gp_set_nn_params": (st, [P, ctypes.POINTER(gp_nn_params)]),
         "gp_set_tv_layout": (st, [P, i32]),
+        "gp_set_grad_params": (st, [P, ctypes.POINTER(gp_grad_params)]),
+        "gp_get_grad_params": (st, [P, ctypes.POINTER(gp_grad_params)]),
+        "gp_autotune_grad": (st, [P, P, P, P, P, i64, P, gp_weights, i32, ctypes.POINTER(gp_grad_params), P]),
         "gp_get_nn_params": (st, [P, ctypes.POINTER(gp_nn_params)]),
         "gp_get_nn_grid": (st, [P, i32, P, P]),
         "gp_autotune_nn": (st, [P, P, P, P, i64, P, i32, ctypes.POINTER(gp_nn_params), ctypes.POINTER(f32)]),
@@ -208,6 +219,33 @@ def gp_get_nn_grid(ctx, shape: int) -> Tuple[Tuple[int, int, int], int]:
 def gp_set_tv_layout(ctx, layout: int) -> None:
     """0: by band size, 1: one block per brick, 2: one wave per brick."""
     _check(ctx, load_library().gp_set_tv_layout(ctx, int(layout)))
+
+
+def gp_set_grad_params(ctx, window_cap: int = 4608, window_max_passes: int = 16,
+                       tv_forward_wave_from: int = 2048, tv_backward_wave_from: int = 16384) -> None:
+    p = gp_grad_params(int(window_cap), int(window_max_passes), int(tv_forward_wave_from),
+                       int(tv_backward_wave_from))
+    _check(ctx, load_library().gp_set_grad_params(ctx, ctypes.byref(p)))
+
+
+def gp_get_grad_params(ctx) -> Tuple[int, int, int, int]:
+    """(window_cap, window_max_passes, tv_forward_wave_from, tv_backward_wave_from)."""
+    p = gp_grad_params()
+    _check(ctx, load_library().gp_get_grad_params(ctx, ctypes.byref(p)))
+    return p.as_tuple()
+
+
+def gp_autotune_grad(ctx, qx, qy, qz, nn, field, weights, reps: int = 2):
+    """Time the gradient-pass and TV settings on these inputs and keep the fastest:
+    ((window_cap, window_max_passes, tv_forward_wave_from, tv_backward_wave_from),
+     (query pass ms, TV forward ms, TV backward ms))."""
+    _stream(ctx)
+    p, ms = gp_grad_params(), (ctypes.c_float * 3)()
+    _check(ctx, load_library().gp_autotune_grad(ctx, _ptr(qx, torch.float32), _ptr(qy, torch.float32),
+                                                _ptr(qz, torch.float32), _ptr(nn, torch.int32), qx.numel(),
+                                                _ptr(field, torch.float32), _weights(*weights), int(reps),
+                                                ctypes.byref(p), ms))
+    return p.as_tuple(), (ms[0], ms[1], ms[2])
 
 
 def gp_get_nn_params(ctx) -> Tuple[int, int, int, int, int, int]:

@@ -185,11 +185,20 @@ class Problem:
                        self.qz[: self.n_queries], self.nn)
 
     def autotune(self, reps: int = 2):
-        """Pick the NN search shape by timing it on the current queries (leaves nn filled).
+        """Pick the NN search grid and shape by timing them on the current queries (leaves nn filled).
 
-        Returns ((group_span, first_shell, tile_parts, skip_empty, morton_sort), best ms)."""
+        Returns ((group_span, first_shell, tile_parts, skip_empty, morton_sort, cell_points), best ms)."""
         return gp.gp_autotune_nn(self.ctx, self.qx[: self.n_queries], self.qy[: self.n_queries],
                                  self.qz[: self.n_queries], self.nn, reps)
+
+    def autotune_grad(self, reps: int = 2):
+        """Pick the gradient-pass and TV settings by timing them on the current
+        queries, nearest points and field.
+
+        Returns ((window_cap, window_max_passes, tv_forward_wave_from,
+        tv_backward_wave_from), (query pass, TV forward, TV backward ms))."""
+        return gp.gp_autotune_grad(self.ctx, self.qx[: self.n_queries], self.qy[: self.n_queries],
+                                   self.qz[: self.n_queries], self.nn, self.field, self.weights, reps)
 
     def forward(self, field: Optional[torch.Tensor] = None):
         f = self.field if field is None else field

@@ -127,6 +127,67 @@ def test_gradient_accumulation_paths(case):
     prob.close()
 
 
+@pytest.mark.parametrize("cap,max_passes", [(2304, 16), (6912, 64), (4608, 1)])
+def test_window_settings_and_autotuner(cap, max_passes):
+    """The gradient pass at other window sizes and pass limits (a smaller
+    window takes more slabs, a larger one fewer, a limit of one pass sends
+    every box wider than the window straight to the gradient) gives the
+    oracle's loss terms and gradient; so does the setting the autotuner picks,
+    and out-of-range settings are refused."""
+    from paper_2308_13175_amd import gridpull as gp
+
+    log("case: window %d vertices, at most %d passes" % (cap, max_passes))
+    dom = synth.cube_domain(64)
+    pts = synth.sphere_points(10_000, 0.5, seed=21)
+    c = np.minimum(np.floor((pts.astype(np.float64) - dom.lo) / dom.h), 63).astype(np.int64)
+    pts = pts[np.argsort((c[:, 0] * 64 + c[:, 1]) * 64 + c[:, 2], kind="stable")]
+    q = synth.host_queries(pts, 80_000, 0.06, seed=22)
+    D = synth.sphere_sdf_field(dom, 0.5, noise=0.01, seed=23)
+    cf, vf, nn, ref = _oracle(dom, pts, q, D)
+    passes = _window_passes(dom, pts, q, nn, cf, cap=cap, max_passes=max_passes)
+    log("  passes per block: %s" % np.bincount(passes).tolist())
+    assert (passes == 0).any() if max_passes == 1 else (passes >= 1).all()
+    prob = make_problem([spec(pts, dom, len(q), 0.0)])
+    gp.gp_set_grad_params(prob.ctx, cap, max_passes, 2048, 16384)
+    assert gp.gp_get_grad_params(prob.ctx) == (cap, max_passes, 2048, 16384)
+    prob.set_dense_field([D])
+    prob.set_queries(q)
+    prob.nearest()
+
+    def check():
+        prob.forward()
+        prob.grad.zero_()
+        prob.backward()
+        prob.sync()
+        got, nv = loss_terms(prob)
+        assert int(nv[0]) == ref["n_valid"]
+        assert_terms_close(got[0], ref)
+        assert_grad_close(prob.dense_grad()[0], ref["dD"])
+        prob.grad.zero_()
+        prob.forward_backward()
+        prob.sync()
+        got, nv = loss_terms(prob)
+        assert_terms_close(got[0], ref)
+        assert_grad_close(prob.dense_grad()[0], ref["dD"])
+
+    check()
+    log("  autotuner")
+    prob.grad.fill_(3.0)
+    chosen, ms = prob.autotune_grad(reps=1)
+    prob.sync()
+    assert chosen[0] in (2304, 4608, 6912) and 1 <= chosen[1] <= 64 and chosen[2] >= 0 and chosen[3] >= 0
+    assert ms[0] > 0 and ms[1] > 0 and ms[2] > 0
+    assert gp.gp_get_grad_params(prob.ctx) == chosen
+    assert bool((prob.grad == 3.0).all())   # the caller's gradient is left alone
+    check()
+    for bad in [(4000, 16, 0, 0), (4608, 0, 0, 0), (4608, 65, 0, 0), (4608, 16, -1, 0), (4608, 16, 0, -1)]:
+        with pytest.raises(gp.GridPullError) as ei:
+            gp.gp_set_grad_params(prob.ctx, *bad)
+        assert ei.value.status == 1
+    assert gp.gp_get_grad_params(prob.ctx) == chosen
+    prob.close()
+
+
 def test_anisotropic_grid_and_edge_cases():
     """Anisotropic cells, a point on hi, queries outside the domain, duplicate points."""
     log("case: anisotropic 24x17x31 with edge cases")
