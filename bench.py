@@ -703,7 +703,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-batched", action="store_true",
-                    help="skip the 64-shape batched-vs-per-shape record on the room workload")
+                    help="skip the batched-vs-per-shape record (configs 4 and 5)")
     ap.add_argument("--sweep", choices=["res", "m2", "m1"],
                     help="instead of the benchmark: whole runs on the paper's schedule, one JSON line per setting")
     ap.add_argument("--surface", action="store_true",
@@ -821,7 +821,7 @@ def main():
     prob.close()
     del prob
     torch.cuda.empty_cache()
-    if args.config == 4 or (args.config == 5 and not args.no_batched):
+    if args.config in (4, 5) and not args.no_batched:
         out["batched_vs_per_shape"] = batched_record(args)
     if not args.no_cpu_baseline:
         t0 = time.perf_counter()

@@ -250,17 +250,35 @@ __global__ void k_fill_masks(const BrickInfo* __restrict__ bricks, int64_t n_bri
     }
 }
 
-// Count TV vertices and optimised vertices per shape.
+// Count TV vertices and optimised vertices per shape.  A wave whose words
+// all belong to one shape adds its sums with one atomic per counter (one
+// address per shape: per-word atomics serialise there).
 __global__ void k_count_masks(const BrickInfo* __restrict__ bricks, int64_t n_bricks,
                               const uint32_t* __restrict__ m_v, const uint32_t* __restrict__ m_v2,
                               unsigned long long* __restrict__ n_v, unsigned long long* __restrict__ n_v2)
 {
-    GRID_STRIDE(w, n_bricks * kMaskWords)
-    {
-        int32_t s = bricks[w / kMaskWords].shape;
-        uint32_t a = m_v[w], b = m_v2[w];
-        if (a) atomicAdd(&n_v[s], (unsigned long long)__popc(a));
-        if (b) atomicAdd(&n_v2[s], (unsigned long long)__popc(b));
+    const int64_t n = n_bricks * kMaskWords;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    // every lane of a wave runs the same number of rounds (the bound is rounded up to whole strides)
+    for (int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; w - (threadIdx.x & 63) < n; w += stride) {
+        const bool in = w < n;
+        const int32_t s = in ? bricks[w / kMaskWords].shape : -1;
+        unsigned long long a = in ? (unsigned long long)__popc(m_v[w]) : 0ull;
+        unsigned long long b = in ? (unsigned long long)__popc(m_v2[w]) : 0ull;
+        const int32_t s0 = __shfl(s, 0, 64);
+        if (__all(!in || s == s0)) {
+            for (int o = 32; o > 0; o >>= 1) {
+                a += __shfl_down(a, o, 64);
+                b += __shfl_down(b, o, 64);
+            }
+            if ((threadIdx.x & 63) == 0 && s0 >= 0) {
+                if (a) atomicAdd(&n_v[s0], a);
+                if (b) atomicAdd(&n_v2[s0], b);
+            }
+        } else if (in) {
+            if (a) atomicAdd(&n_v[s], a);
+            if (b) atomicAdd(&n_v2[s], b);
+        }
     }
 }
 
