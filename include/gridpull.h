@@ -184,8 +184,9 @@ typedef struct {
 /*
  * Set / read the context's search shape (host struct; it survives
  * gp_build_band).  A new cell_points rebuilds the search grids of a built
- * context (synchronises).  Errors: GP_ERR_ARG (null pointer, a field out of
- * range), GP_ERR_OOM.
+ * context (synchronises); if that rebuild fails, the context needs
+ * gp_build_band again (other calls report GP_ERR_STATE).  Errors: GP_ERR_ARG
+ * (null pointer, a field out of range), GP_ERR_OOM, GP_ERR_CAPACITY.
  */
 gp_status gp_set_nn_params(gp_ctx ctx, const gp_nn_params* params);
 gp_status gp_get_nn_params(gp_ctx ctx, gp_nn_params* params);

@@ -732,7 +732,7 @@ std::vector<int32_t> gp_nn_levels(gp_ctx ctx, int32_t cell_points)
     return k;
 }
 
-gp_status gp_build_nn_index(gp_ctx ctx, int32_t cell_points)
+static gp_status build_nn_index(gp_ctx ctx, int32_t cell_points)
 {
     hipStream_t st = ctx->stream;
     const int32_t n_shapes = ctx->n_shapes;
@@ -872,4 +872,13 @@ gp_status gp_build_nn_index(gp_ctx ctx, int32_t cell_points)
     ctx->nn_slots = n_slots;
     ctx->nn_cell_points = cell_points;
     return GP_OK;
+}
+
+// A failed rebuild leaves the search grids half replaced: the context is
+// then unusable until the next gp_build_band.
+gp_status gp_build_nn_index(gp_ctx ctx, int32_t cell_points)
+{
+    const gp_status st = build_nn_index(ctx, cell_points);
+    if (st != GP_OK) ctx->built = false;
+    return st;
 }

@@ -228,10 +228,7 @@ gp_status gp_set_nn_params(gp_ctx ctx, const gp_nn_params* params)
     if (ctx->built && params->cell_points != ctx->nn_cell_points) {
         if (hipSetDevice(ctx->device) != hipSuccess) return gp_fail(ctx, GP_ERR_DEVICE, "hipSetDevice failed");
         const gp_status st = gp_build_nn_index(ctx, params->cell_points);
-        if (st != GP_OK) {
-            ctx->built = false;   // the search grids are gone
-            return st;
-        }
+        if (st != GP_OK) return st;
     }
     ctx->nn_params.cell_points = params->cell_points;
     ctx->nn_params.span = params->group_span;

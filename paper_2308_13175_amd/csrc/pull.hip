@@ -213,9 +213,13 @@ __device__ inline void query_adjoint(const ShapeDesc& s, const QueryState& st, g
 // The entries hold fixed point with 32 fraction bits in 64-bit integers:
 // integer LDS atomics run at full rate where float ones do not (measured:
 // a float window made the pass several times slower), and the sums inside a
-// block are exact.  A contribution of 2^20 or more in magnitude bypasses the
+// block are exact.  A contribution of 2^19 or more in magnitude bypasses the
 // window, so no sum leaves the range of the fixed point (a vertex receives
-// at most 2 contributions from each of the 256 queries).
+// at most 2 contributions from each of the 256 queries).  The conversion
+// adds 1.5 * 2^52 to the scaled value in double: for |v| < 2^51 the sum lies
+// in [2^52, 2^53), where the double's ulp is 1, so the addition rounds v to
+// the nearest integer (ties to even, as a rounding conversion would) and the
+// sum's bits minus those of 1.5 * 2^52 are that integer in two's complement.
 // Directory entries of a slab's bricks, at most: a slab of d0 x d1 x d2 <= cap
 // vertices meets at most prod(floor((d_i + 6) / 8) + 1) bricks, largest for
 // 2 x 2 x cap/4 (two bricks on each short axis).
@@ -233,7 +237,8 @@ __host__ __device__ constexpr int32_t win_lds_bytes(int32_t cap)
 static_assert(win_bricks_bound(4608) == 580 && win_bricks_bound(6912) == 868, "slab brick bound");
 static_assert(win_lds_bytes(kWinCapMax) <= 64 * 1024 - 512, "window LDS within one workgroup's 64 KB");
 constexpr double kFixScale = 4294967296.0;   // 2^32
-constexpr float kFixLimit = 1048576.f;       // 2^20
+constexpr float kFixLimit = 524288.f;        // 2^19
+constexpr double kFixMagic = 6755399441055744.0;   // 1.5 * 2^52
 
 // The box of a block (vertices lo .. lo + w - 1), its slab axis ax (0 or 1;
 // o = 1 - ax is the other of x and y), the layers of ax per pass and the
@@ -307,7 +312,8 @@ __device__ inline void window_add(const int32_t idx[8], const int32_t slot[8], c
         asm volatile("" : "+v"(x));
         const bool big = !(fabsf(x) < kFixLimit);
         if (idx[i] >= 0 && !big)
-            atomicAdd(&acc[idx[i]], (unsigned long long)__double2ll_rn((double)x * kFixScale));
+            atomicAdd(&acc[idx[i]], (unsigned long long)(__double_as_longlong(fma((double)x, kFixScale, kFixMagic)) -
+                                                         __double_as_longlong(kFixMagic)));
         else if (first && big)
             atomicAdd(at32(G, (uint32_t)slot[i]), scale * x);
     }
