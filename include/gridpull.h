@@ -192,8 +192,9 @@ gp_status gp_set_nn_params(gp_ctx ctx, const gp_nn_params* params);
 gp_status gp_get_nn_params(gp_ctx ctx, gp_nn_params* params);
 
 /*
- * The search grid of shape `shape`: dims_out (host [3]) its cells per axis,
- * level_out (host, may be NULL) its k (cells 2^k band cells wide).
+ * The search grid of shape `shape` (the index that stands in for the KD-tree
+ * of Sec. 3, query sampling paragraph): dims_out (host [3]) its cells per
+ * axis, level_out (host, may be NULL) its k (cells 2^k band cells wide).
  * Errors: GP_ERR_STATE before gp_build_band, GP_ERR_ARG (shape out of range,
  * null dims_out).
  */
@@ -265,8 +266,9 @@ gp_status gp_set_grad_params(gp_ctx ctx, const gp_grad_params* params);
 gp_status gp_get_grad_params(gp_ctx ctx, gp_grad_params* params);
 
 /*
- * Autotuner of gp_grad_params on the caller's queries, nearest points and
- * field (arguments as gp_pull_forward_backward): times the fused query pass
+ * Autotuner of gp_grad_params (the passes that evaluate Eq. 4-8 and scatter
+ * their derivative) on the caller's queries, nearest points and field
+ * (arguments as gp_pull_forward_backward): times the fused query pass
  * for window_cap in {2304, 4608, 6912} x window_max_passes in {4, 16, 64},
  * then the TV forward and the TV backward in each layout at the band's size
  * (the faster one moves its threshold to the band's brick count, so that
