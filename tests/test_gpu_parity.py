@@ -589,6 +589,8 @@ def test_tv_layouts(layout):
         log("case: TV layout %d, %s" % (layout, name))
         prob = make_problem([spec(p_, dm, len(q_), 0.0)], m1=m1, m2=m2)
         gp.gp_set_tv_layout(prob.ctx, layout)
+        big = 2 ** 63 - 1
+        assert gp.gp_get_grad_params(prob.ctx)[2:] == ((big, big) if layout == 1 else (0, 0))
         prob.set_dense_field([D_])
         prob.set_queries(q_)
         prob.nearest()
@@ -611,6 +613,8 @@ def test_tv_layouts(layout):
         with pytest.raises(gp.GridPullError) as ei:
             gp.gp_set_tv_layout(prob.ctx, 3)
         assert ei.value.status == 1
+        gp.gp_set_tv_layout(prob.ctx, 0)
+        assert gp.gp_get_grad_params(prob.ctx)[2:] == (2048, 16384)
         prob.close()
 
 
