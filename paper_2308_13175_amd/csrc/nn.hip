@@ -50,7 +50,7 @@ constexpr int kNnMaxGrow = 8;     // growth beyond which a group with no point i
 struct Best {
     double d2;
     int32_t id;     // original index within the shape (the tie rule)
-    int32_t pos;    // global position in the cell-sorted copy
+    int32_t pos;    // global position in the search grid's sorted copy
 };
 
 __device__ inline double exact_d2(float qx, float qy, float qz, float sx, float sy, float sz)
@@ -90,7 +90,7 @@ struct Global {
 };
 
 // The search passes carry, in .w of each staged point, its position in the
-// cell-sorted copy instead of its original index (float pass ties are not
+// search grid's sorted copy instead of its original index (float pass ties are not
 // decided there: they go to the exact search, which uses the original index).
 
 // Global range of the points of cells (x, y, za..zb) (one brick): empty if none.
