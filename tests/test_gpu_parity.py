@@ -569,6 +569,36 @@ def test_nn_search_grid_across_band_resolutions(res):
     prob.close()
 
 
+def test_nn_points_on_search_cell_faces():
+    """Points on the faces of coarse search cells (a lattice of band vertices,
+    so at levels 1 to 3 every point lies on search-cell faces), queries at the
+    lattice's cell centres (8-way ties), on the points themselves and at random:
+    the search's cell assignment at a face and its gap bounds still give brute
+    force's indices bit for bit at every level."""
+    from paper_2308_13175_amd import gridpull as gp
+    dom = synth.Domain((32, 32, 32), (-1.0, -1.0, -1.0), (1.0, 1.0, 1.0))
+    g = (np.arange(4, 29, 4, dtype=np.float32) * np.float32(0.0625) - np.float32(1.0))   # every 4th vertex
+    lat = np.stack(np.meshgrid(g, g, g, indexing="ij"), -1).reshape(-1, 3).astype(np.float32)
+    rng = np.random.default_rng(11)
+    pts = lat[rng.permutation(len(lat))]
+    centres = (lat[(lat < g[-1]).all(1)] + np.float32(0.125)).astype(np.float32)
+    q = np.concatenate([centres, lat[:100], rng.uniform(-1, 1, (4000, 3)).astype(np.float32)]).astype(np.float32)
+    ref = oracle.nn_bruteforce(q, pts)
+    prob = make_problem([spec(pts, dom, len(q), 0.0)])
+    prob.set_queries(q)
+    for cell_points in (1, 4, 16, 64):
+        gp.gp_set_nn_params(prob.ctx, 8, 1, 1, 0, 1, cell_points)
+        level = gp.gp_get_nn_grid(prob.ctx, 0)[1]
+        log("case: lattice on search-cell faces, level %d" % level)
+        prob.nn.fill_(-7)
+        prob.nearest()
+        prob.sync()
+        got = prob.nn[: len(q)].cpu().numpy()
+        bad = np.nonzero(got != ref)[0]
+        assert len(bad) == 0, "level %d: %d differ" % (level, len(bad))
+    prob.close()
+
+
 @pytest.mark.parametrize("layout", [1, 2])
 def test_tv_layouts(layout):
     """Both thread layouts of the TV kernels (block per brick, wave per brick)
