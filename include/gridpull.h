@@ -46,8 +46,10 @@
  *    all shapes.  A single shape is n_shapes = 1.
  *
  * Field layout ("slots"): values of the optimised vertices are stored in
- * bricks of 8x8x8 vertices; the brick holding vertex (i,j,k) is
- * (i>>3, j>>3, k>>3) and the vertex's slot is brick*512 + ((i&7)*8+(j&7))*8+(k&7).
+ * bricks of B x B x B vertices (B = gp_build_band's brick: 4, 8 or 16); the
+ * brick holding vertex (i,j,k) is (i/B, j/B, k/B) and the vertex's slot is
+ * brick*B^3 + ((i%B)*B + j%B)*B + k%B (for B = 8: brick*512 +
+ * ((i&7)*8+(j&7))*8+(k&7)).
  * Only bricks that hold an optimised vertex exist.  Slots of different
  * shapes are disjoint, in shape order.  The field, its gradient and the Adam
  * moments are caller-owned float32 device arrays of n_slots entries in this
@@ -122,7 +124,12 @@ gp_status gp_sync(gp_ctx ctx);
  *           copy, so the arrays may be freed afterwards.
  * m1, m2:   band half-widths in cells, 0 <= m <= 1024; a width of at least
  *           the largest dims - 1 covers the whole grid ("all grids").
- * brick:    brick edge in vertices; only 8 is supported (else GP_ERR_ARG).
+ * brick:    brick edge in vertices: 4, 8 or 16 (else GP_ERR_ARG).  The field
+ *           layout is brick-major: slot = brick * brick^3 + local vertex, the
+ *           local vertex x-major inside the brick.  Smaller bricks pad a thin
+ *           band less, larger ones put more of a cell's corners in one brick;
+ *           the TV kernels' wave layout exists for 8 only (other sizes take
+ *           the block layout whatever gp_set_tv_layout asks).
  * n_slots_out, n_active_vertices_out: host; the field length and the number
  *           of optimised vertices over all shapes.
  * Synchronises.  May be called again to rebuild (previous state is dropped).
@@ -280,7 +287,9 @@ gp_status gp_get_grad_params(gp_ctx ctx, gp_grad_params* params);
  * scratch), and invalidates the context's last forward (gp_forward_token).
  * reps in [1, 100]; chosen_out (host, may be NULL) receives the settings,
  * best_ms_out (host [3], may be NULL) the chosen query pass, TV forward and
- * TV backward times in ms (-1 for a part with nothing to time).
+ * TV backward times in ms (-1 for a part with nothing to time; the TV layouts
+ * are timed for 8^3 bricks only, the other sizes having the block layout
+ * alone).
  * Synchronises; not for use under stream capture.
  * Errors: GP_ERR_STATE before gp_build_band, GP_ERR_ARG (null pointers,
  * n_queries not the end of the last shape's query slice, reps),

@@ -119,6 +119,7 @@ __global__ void k_vertex_flags(const uint8_t* __restrict__ cells, uint8_t* __res
 }
 
 // A brick exists iff it holds an optimised vertex.
+template <int kB>
 __global__ void k_brick_active(const uint8_t* __restrict__ verts, ShapeDesc s, int32_t* __restrict__ active)
 {
     const int64_t nbt = (int64_t)s.nb[0] * s.nb[1] * s.nb[2];
@@ -129,15 +130,15 @@ __global__ void k_brick_active(const uint8_t* __restrict__ verts, ShapeDesc s, i
         int32_t by = (int32_t)((b / s.nb[2]) % s.nb[1]);
         int32_t bx = (int32_t)(b / ((int64_t)s.nb[2] * s.nb[1]));
         int32_t any = 0;
-        for (int32_t lx = 0; lx < kBrick && !any; ++lx) {
-            int32_t i = bx * kBrick + lx;
+        for (int32_t lx = 0; lx < kB && !any; ++lx) {
+            int32_t i = bx * kB + lx;
             if (i >= V0) break;
-            for (int32_t ly = 0; ly < kBrick && !any; ++ly) {
-                int32_t j = by * kBrick + ly;
+            for (int32_t ly = 0; ly < kB && !any; ++ly) {
+                int32_t j = by * kB + ly;
                 if (j >= V1) break;
                 const uint8_t* row = verts + ((int64_t)i * V1 + j) * V2;
-                for (int32_t lz = 0; lz < kBrick; ++lz) {
-                    int32_t k = bz * kBrick + lz;
+                for (int32_t lz = 0; lz < kB; ++lz) {
+                    int32_t k = bz * kB + lz;
                     if (k >= V2) break;
                     if (row[k] & 1) { any = 1; break; }
                 }
@@ -213,6 +214,7 @@ __global__ void k_fill_dir(const int32_t* __restrict__ active, const int32_t* __
 }
 
 // Per (brick, 32-bit word): pack the vertex and cell flags of 32 slots.
+template <int kB>
 __global__ void k_fill_masks(const BrickInfo* __restrict__ bricks, int64_t n_bricks, ShapeDesc s,
                              const uint8_t* __restrict__ cells, const uint8_t* __restrict__ verts,
                              uint32_t* __restrict__ m_base, uint32_t* __restrict__ m_a1,
@@ -220,17 +222,18 @@ __global__ void k_fill_masks(const BrickInfo* __restrict__ bricks, int64_t n_bri
                              uint32_t* __restrict__ m_v2)
 {
     const int32_t V1 = s.R[1] + 1, V2 = s.R[2] + 1;
-    GRID_STRIDE(w, n_bricks * kMaskWords)
+    using G = Geo<kB>;
+    GRID_STRIDE(w, n_bricks * G::W)
     {
-        int64_t b = w / kMaskWords;
-        int32_t word = (int32_t)(w % kMaskWords);
+        int64_t b = w / G::W;
+        int32_t word = (int32_t)(w % G::W);
         BrickInfo bi = bricks[b];
         uint32_t fb = 0, f1 = 0, f2 = 0, fv = 0, fv2 = 0;
         for (int bit = 0; bit < 32; ++bit) {
             int32_t local = word * 32 + bit;
-            int32_t i = bi.bx * kBrick + (local >> 6);
-            int32_t j = bi.by * kBrick + ((local >> 3) & 7);
-            int32_t k = bi.bz * kBrick + (local & 7);
+            int32_t i = bi.bx * kB + (local >> (2 * G::S));
+            int32_t j = bi.by * kB + ((local >> G::S) & G::M);
+            int32_t k = bi.bz * kB + (local & G::M);
             if (i > s.R[0] || j > s.R[1] || k > s.R[2]) continue;
             uint8_t vf = verts[((int64_t)i * V1 + j) * V2 + k];
             if (vf & 1) fv |= 1u << bit;
@@ -253,16 +256,17 @@ __global__ void k_fill_masks(const BrickInfo* __restrict__ bricks, int64_t n_bri
 // Count TV vertices and optimised vertices per shape.  A wave whose words
 // all belong to one shape adds its sums with one atomic per counter (one
 // address per shape: per-word atomics serialise there).
+template <int kB>
 __global__ void k_count_masks(const BrickInfo* __restrict__ bricks, int64_t n_bricks,
                               const uint32_t* __restrict__ m_v, const uint32_t* __restrict__ m_v2,
                               unsigned long long* __restrict__ n_v, unsigned long long* __restrict__ n_v2)
 {
-    const int64_t n = n_bricks * kMaskWords;
+    const int64_t n = n_bricks * Geo<kB>::W;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     // every lane of a wave runs the same number of rounds (the bound is rounded up to whole strides)
     for (int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; w - (threadIdx.x & 63) < n; w += stride) {
         const bool in = w < n;
-        const int32_t s = in ? bricks[w / kMaskWords].shape : -1;
+        const int32_t s = in ? bricks[w / Geo<kB>::W].shape : -1;
         unsigned long long a = in ? (unsigned long long)__popc(m_v[w]) : 0ull;
         unsigned long long b = in ? (unsigned long long)__popc(m_v2[w]) : 0ull;
         const int32_t s0 = __shfl(s, 0, 64);
@@ -284,22 +288,25 @@ __global__ void k_count_masks(const BrickInfo* __restrict__ bricks, int64_t n_br
 
 // Sort keys of the points: the slot of the point's band cell (the slot of its
 // lowest corner).
+template <int kB>
 __global__ void k_point_keys(const float* __restrict__ px, const float* __restrict__ py,
                              const float* __restrict__ pz, Band B, int32_t shape,
                              uint32_t* __restrict__ keys, int32_t* __restrict__ vals)
 {
+    using G = Geo<kB>;
     const ShapeDesc& s = B.shapes[shape];
     GRID_STRIDE(j, s.point_cnt)
     {
         int64_t g = s.point_off + j;
         Loc L = locate(s, px[g], py[g], pz[g]);
-        int32_t br = brick_of(B, s, L.c[0] >> 3, L.c[1] >> 3, L.c[2] >> 3);
-        uint32_t slot = (uint32_t)br * kBrickVol + (uint32_t)local_index(L.c[0], L.c[1], L.c[2]);
+        int32_t br = brick_of(B, s, L.c[0] >> G::S, L.c[1] >> G::S, L.c[2] >> G::S);
+        uint32_t slot = (uint32_t)br * G::V + (uint32_t)local_index_b<kB>(L.c[0], L.c[1], L.c[2]);
         keys[s.sorted_off + j] = slot;
         vals[s.sorted_off + j] = (int32_t)g;
     }
 }
 
+template <int kB>
 __global__ void k_gather_sorted(const float* __restrict__ px, const float* __restrict__ py,
                                 const float* __restrict__ pz, const uint32_t* __restrict__ keys,
                                 const int32_t* __restrict__ vals, Band B, int64_t n, float4* __restrict__ spts)
@@ -307,7 +314,7 @@ __global__ void k_gather_sorted(const float* __restrict__ px, const float* __res
     GRID_STRIDE(i, n)
     {
         int32_t g = vals[i];
-        int32_t shape = B.bricks[keys[i] / kBrickVol].shape;
+        int32_t shape = B.bricks[keys[i] / Geo<kB>::V].shape;
         spts[i] = make_float4(px[g], py[g], pz[g], __int_as_float((int32_t)(g - B.shapes[shape].point_off)));
     }
 }
@@ -390,9 +397,11 @@ struct ShapeBricks {
 
 using namespace gp;
 
-gp_status gp_build_band_impl(gp_ctx ctx, const gp_shape* shapes, int32_t n_shapes, const float* px,
-                             const float* py, const float* pz, int32_t m1, int32_t m2)
+template <int kB>
+static gp_status build_band(gp_ctx ctx, const gp_shape* shapes, int32_t n_shapes, const float* px, const float* py,
+                            const float* pz, int32_t m1, int32_t m2)
 {
+    using G = Geo<kB>;
     hipStream_t st = ctx->stream;
     ctx->built = false;
     ctx->fwd_token = 0;
@@ -411,7 +420,7 @@ gp_status gp_build_band_impl(gp_ctx ctx, const gp_shape* shapes, int32_t n_shape
             d.h[a] = (float)((in.hi[a] - in.lo[a]) / (double)in.dims[a]);
             d.hd[a] = (in.hi[a] - in.lo[a]) / (double)in.dims[a];
             d.R[a] = in.dims[a];
-            d.nb[a] = (in.dims[a] + 1 + kBrick - 1) / kBrick;
+            d.nb[a] = (in.dims[a] + 1 + kB - 1) / kB;
         }
         d.dir_off = dir_total;
         dir_total += (int64_t)d.nb[0] * d.nb[1] * d.nb[2];
@@ -479,7 +488,7 @@ gp_status gp_build_band_impl(gp_ctx ctx, const gp_shape* shapes, int32_t n_shape
         k_dilate<<<blocks_for(nc), kThreads, 0, st>>>(c1.p, c0.p, d.R[0], d.R[1], d.R[2], 1, e1, e2, 2, 4);
         k_dilate<<<blocks_for(nc), kThreads, 0, st>>>(c0.p, c1.p, d.R[0], d.R[1], d.R[2], 2, e1, e2, 2, 4);
         k_vertex_flags<<<blocks_for(nv), kThreads, 0, st>>>(c1.p, vf.p, d.R[0], d.R[1], d.R[2]);
-        k_brick_active<<<blocks_for(nbt), kThreads, 0, st>>>(vf.p, d, active.p);
+        k_brick_active<kB><<<blocks_for(nbt), kThreads, 0, st>>>(vf.p, d, active.p);
         size_t need = 0;
         GP_HIP(ctx, hipcub::DeviceScan::ExclusiveSum(nullptr, need, active.p, index.p, (int)nbt, st));
         if (need > cub_bytes) {
@@ -493,7 +502,7 @@ gp_status gp_build_band_impl(gp_ctx ctx, const gp_shape* shapes, int32_t n_shape
         GP_HIP(ctx, hipMemcpyAsync(&last_act, active.p + nbt - 1, 4, hipMemcpyDeviceToHost, st));
         GP_HIP(ctx, hipStreamSynchronize(st));
         const int64_t nb_s = (int64_t)last_idx + last_act;
-        if ((brick_base + nb_s) * kBrickVol >= kMaxSlots)
+        if ((brick_base + nb_s) * G::V >= kMaxSlots)
             return gp_fail(ctx, GP_ERR_CAPACITY, "more than 2^30 field slots");
         {
             // brick numbers along the Morton curve (index[] of the active entries)
@@ -526,14 +535,14 @@ gp_status gp_build_band_impl(gp_ctx ctx, const gp_shape* shapes, int32_t n_shape
         part->n_dir = nbt;
         part->n_bricks = nb_s;
         if (part->dir.alloc(nbt) != hipSuccess || part->bricks.alloc(nb_s) != hipSuccess ||
-            part->m_base.alloc(nb_s * kMaskWords) != hipSuccess || part->m_a1.alloc(nb_s * kMaskWords) != hipSuccess ||
-            part->m_a2.alloc(nb_s * kMaskWords) != hipSuccess || part->m_v.alloc(nb_s * kMaskWords) != hipSuccess ||
-            part->m_v2.alloc(nb_s * kMaskWords) != hipSuccess)
+            part->m_base.alloc(nb_s * G::W) != hipSuccess || part->m_a1.alloc(nb_s * G::W) != hipSuccess ||
+            part->m_a2.alloc(nb_s * G::W) != hipSuccess || part->m_v.alloc(nb_s * G::W) != hipSuccess ||
+            part->m_v2.alloc(nb_s * G::W) != hipSuccess)
             return gp_fail(ctx, GP_ERR_OOM, "out of device memory for the bricks of shape " + std::to_string(s));
         k_fill_dir<<<blocks_for(nbt), kThreads, 0, st>>>(active.p, index.p, d, s, brick_base, part->dir.p,
                                                           part->bricks.p);
         if (nb_s > 0)
-            k_fill_masks<<<blocks_for(nb_s * kMaskWords), kThreads, 0, st>>>(
+            k_fill_masks<kB><<<blocks_for(nb_s * G::W), kThreads, 0, st>>>(
                 part->bricks.p, nb_s, d, c1.p, vf.p, part->m_base.p, part->m_a1.p, part->m_a2.p, part->m_v.p,
                 part->m_v2.p);
         GP_HIP(ctx, hipGetLastError());
@@ -546,7 +555,7 @@ gp_status gp_build_band_impl(gp_ctx ctx, const gp_shape* shapes, int32_t n_shape
 
     // ---- assemble the global arrays --------------------------------------
     const int64_t n_bricks = brick_base;
-    const int64_t n_slots = n_bricks * kBrickVol;
+    const int64_t n_slots = n_bricks * G::V;
     ctx->n_shapes = n_shapes;
     ctx->n_bricks = n_bricks;
     ctx->n_slots = n_slots;
@@ -557,19 +566,19 @@ gp_status gp_build_band_impl(gp_ctx ctx, const gp_shape* shapes, int32_t n_shape
     ctx->m1 = m1;
     ctx->m2 = m2;
     if (ctx->dir.alloc(dir_total) != hipSuccess || ctx->bricks.alloc(n_bricks) != hipSuccess ||
-        ctx->m_base.alloc(n_bricks * kMaskWords) != hipSuccess ||
-        ctx->m_a1.alloc(n_bricks * kMaskWords) != hipSuccess ||
-        ctx->m_a2.alloc(n_bricks * kMaskWords) != hipSuccess ||
-        ctx->m_v.alloc(n_bricks * kMaskWords) != hipSuccess ||
-        ctx->m_v2.alloc(n_bricks * kMaskWords) != hipSuccess || ctx->shapes.alloc(n_shapes) != hipSuccess)
+        ctx->m_base.alloc(n_bricks * G::W) != hipSuccess ||
+        ctx->m_a1.alloc(n_bricks * G::W) != hipSuccess ||
+        ctx->m_a2.alloc(n_bricks * G::W) != hipSuccess ||
+        ctx->m_v.alloc(n_bricks * G::W) != hipSuccess ||
+        ctx->m_v2.alloc(n_bricks * G::W) != hipSuccess || ctx->shapes.alloc(n_shapes) != hipSuccess)
         return gp_fail(ctx, GP_ERR_OOM, "out of device memory for the band");
     for (int32_t s = 0; s < n_shapes; ++s) {
         ShapeBricks& p = *parts[s];
         const ShapeDesc& d = hs[s];
         GP_HIP(ctx, hipMemcpyAsync(ctx->dir.p + d.dir_off, p.dir.p, p.n_dir * 4, hipMemcpyDeviceToDevice, st));
         if (p.n_bricks == 0) continue;
-        const size_t mb = (size_t)p.n_bricks * kMaskWords * 4;
-        const int64_t mo = d.brick_begin * kMaskWords;
+        const size_t mb = (size_t)p.n_bricks * G::W * 4;
+        const int64_t mo = d.brick_begin * G::W;
         GP_HIP(ctx, hipMemcpyAsync(ctx->bricks.p + d.brick_begin, p.bricks.p, p.n_bricks * sizeof(BrickInfo),
                                    hipMemcpyDeviceToDevice, st));
         GP_HIP(ctx, hipMemcpyAsync(ctx->m_base.p + mo, p.m_base.p, mb, hipMemcpyDeviceToDevice, st));
@@ -584,7 +593,7 @@ gp_status gp_build_band_impl(gp_ctx ctx, const gp_shape* shapes, int32_t n_shape
     GP_HIP(ctx, cnt.alloc(2 * (size_t)n_shapes));
     GP_HIP(ctx, hipMemsetAsync(cnt.p, 0, 2 * sizeof(unsigned long long) * n_shapes, st));
     if (n_bricks > 0)
-        k_count_masks<<<blocks_for(n_bricks * kMaskWords), kThreads, 0, st>>>(ctx->bricks.p, n_bricks, ctx->m_v.p,
+        k_count_masks<kB><<<blocks_for(n_bricks * G::W), kThreads, 0, st>>>(ctx->bricks.p, n_bricks, ctx->m_v.p,
                                                                              ctx->m_v2.p, cnt.p, cnt.p + n_shapes);
     std::vector<unsigned long long> hcnt(2 * (size_t)n_shapes);
     GP_HIP(ctx, hipMemcpyAsync(hcnt.data(), cnt.p, hcnt.size() * 8, hipMemcpyDeviceToHost, st));
@@ -637,7 +646,7 @@ gp_status gp_build_band_impl(gp_ctx ctx, const gp_shape* shapes, int32_t n_shape
         Band B = ctx->band();
         for (int32_t s = 0; s < n_shapes; ++s)
             if (hs[s].point_cnt > 0)
-                k_point_keys<<<blocks_for(hs[s].point_cnt), kThreads, 0, st>>>(px, py, pz, B, s, k_in.p, v_in.p);
+                k_point_keys<kB><<<blocks_for(hs[s].point_cnt), kThreads, 0, st>>>(px, py, pz, B, s, k_in.p, v_in.p);
         GP_HIP(ctx, hipGetLastError());
         size_t need = 0;
         int end_bit = 1;
@@ -657,7 +666,7 @@ gp_status gp_build_band_impl(gp_ctx ctx, const gp_shape* shapes, int32_t n_shape
         if (np > 0) {
             GP_HIP(ctx, hipcub::DeviceRadixSort::SortPairs(cub_tmp, need, k_in.p, k_out.p, v_in.p, v_out.p, (int)np, 0,
                                                           end_bit, st));
-            k_gather_sorted<<<blocks_for(np), kThreads, 0, st>>>(px, py, pz, k_out.p, v_out.p, B, np, ctx->spts.p);
+            k_gather_sorted<kB><<<blocks_for(np), kThreads, 0, st>>>(px, py, pz, k_out.p, v_out.p, B, np, ctx->spts.p);
         }
         GP_HIP(ctx, hipGetLastError());
         GP_HIP(ctx, hipStreamSynchronize(st));
@@ -682,13 +691,22 @@ gp_status gp_build_band_impl(gp_ctx ctx, const gp_shape* shapes, int32_t n_shape
 
     ctx->h_shapes = hs;
     ctx->h_slot_begin.resize(n_shapes + 1);
-    for (int32_t s = 0; s < n_shapes; ++s) ctx->h_slot_begin[s] = hs[s].brick_begin * kBrickVol;
+    for (int32_t s = 0; s < n_shapes; ++s) ctx->h_slot_begin[s] = hs[s].brick_begin * G::V;
     ctx->h_slot_begin[n_shapes] = n_slots;
     GP_HIP(ctx, hipStreamSynchronize(st));
     const gp_status ns = gp_build_nn_index(ctx, ctx->nn_params.cell_points);
     if (ns != GP_OK) return ns;
     ctx->built = true;
     return GP_OK;
+}
+
+gp_status gp_build_band_impl(gp_ctx ctx, const gp_shape* shapes, int32_t n_shapes, const float* px,
+                             const float* py, const float* pz, int32_t m1, int32_t m2, int32_t brick)
+{
+    ctx->brick = brick;
+    return with_brick(brick, [&](auto tag) {
+        return build_band<decltype(tag)::value>(ctx, shapes, n_shapes, px, py, pz, m1, m2);
+    });
 }
 
 // Level k of a shape's search grid (cells 2^k band cells wide per axis): the

@@ -162,7 +162,7 @@ gp_status gp_build_band(gp_ctx ctx, const gp_shape* shapes, int32_t n_shapes, co
     if (!shapes || n_shapes < 1) return gp_fail(ctx, GP_ERR_ARG, "need at least one shape");
     if (m1 < 0 || m2 < 0 || m1 > 1024 || m2 > 1024)
         return gp_fail(ctx, GP_ERR_ARG, "m1 and m2 must lie in [0, 1024]");
-    if (brick != 8) return gp_fail(ctx, GP_ERR_ARG, "only 8^3 bricks are supported");
+    if (brick != 4 && brick != 8 && brick != 16) return gp_fail(ctx, GP_ERR_ARG, "brick must be 4, 8 or 16");
     bool any_points = false;
     for (int32_t s = 0; s < n_shapes; ++s) {
         const gp_shape& d = shapes[s];
@@ -189,7 +189,7 @@ gp_status gp_build_band(gp_ctx ctx, const gp_shape* shapes, int32_t n_shapes, co
     if (any_points && (!px || !py || !pz)) return gp_fail(ctx, GP_ERR_ARG, "null point array");
     if (hipSetDevice(ctx->device) != hipSuccess) return gp_fail(ctx, GP_ERR_DEVICE, "hipSetDevice failed");
     ctx->fwd_token = 0;
-    gp_status st = gp_build_band_impl(ctx, shapes, n_shapes, px, py, pz, m1, m2);
+    gp_status st = gp_build_band_impl(ctx, shapes, n_shapes, px, py, pz, m1, m2, brick);
     if (st != GP_OK) {
         (void)hipStreamSynchronize(ctx->stream);
         return st;

@@ -14,8 +14,26 @@
 
 namespace gp {
 
-constexpr int kBrick = 8;                 // vertices per brick edge
-constexpr int kBrickVol = 512;            // vertices per brick
+// Bricks of the band: kB^3 vertices, kB in {4, 8, 16} (gp_build_band's
+// brick argument); every kernel that walks the band is instantiated per size.
+// The search grid of the nearest-neighbour search always uses 8^3 bricks
+// (kBrick, kBrickVol and the untemplated helpers below).
+template <int kB>
+struct Geo {
+    static_assert(kB == 4 || kB == 8 || kB == 16, "brick edge 4, 8 or 16");
+    static constexpr int32_t B = kB;                           // vertices per edge
+    static constexpr int32_t S = kB == 4 ? 2 : (kB == 8 ? 3 : 4);   // log2 B
+    static constexpr int32_t M = kB - 1;
+    static constexpr int32_t V = kB * kB * kB;                 // vertices per brick
+    static constexpr int32_t W = V / 32;                       // 32-bit mask words per brick
+};
+template <int kB>
+struct BrickTag {
+    static constexpr int value = kB;
+};
+
+constexpr int kBrick = 8;                 // the search grid's brick edge (and the default band brick)
+constexpr int kBrickVol = 512;
 constexpr int kMaskWords = kBrickVol / 32;
 constexpr int kQueryBlock = 256;          // threads per block of the query kernels
 constexpr int kQueriesPerThread = 4;
@@ -150,14 +168,28 @@ __device__ inline int32_t brick_of(const Band& B, const ShapeDesc& s, int32_t bx
     return B.dir[s.dir_off + ((int64_t)bx * s.nb[1] + by) * s.nb[2] + bz];
 }
 
+// Index of vertex (i, j, k) inside its brick: x-major over the brick's edge.
+template <int kB>
+__device__ inline int32_t local_index_b(int32_t i, int32_t j, int32_t k)
+{
+    using G = Geo<kB>;
+    return (((i & G::M) << G::S | (j & G::M)) << G::S) | (k & G::M);
+}
+
 __device__ inline int32_t local_index(int32_t i, int32_t j, int32_t k)
 {
-    return ((i & 7) * 8 + (j & 7)) * 8 + (k & 7);
+    return local_index_b<kBrick>(i, j, k);
+}
+
+template <int kB>
+__device__ inline bool mask_bit_b(const uint32_t* m, int32_t brick, int32_t local)
+{
+    return (m[(int64_t)brick * Geo<kB>::W + (local >> 5)] >> (local & 31)) & 1u;
 }
 
 __device__ inline bool mask_bit(const uint32_t* m, int32_t brick, int32_t local)
 {
-    return (m[(int64_t)brick * kMaskWords + (local >> 5)] >> (local & 31)) & 1u;
+    return mask_bit_b<kBrick>(m, brick, local);
 }
 
 // Slots of the eight corners of cell c, corner (a,b,c) at index 4a+2b+c.
@@ -165,14 +197,17 @@ __device__ inline bool mask_bit(const uint32_t* m, int32_t brick, int32_t local)
 // The corner one step up an axis lies in the next brick only when the cell
 // sits on the brick's last layer of that axis, so the eight directory
 // entries are one base entry plus fixed strides.
+template <int kB>
 __device__ inline void corner_slots(const Band& B, const ShapeDesc& s, const int32_t c[3], int32_t slot[8])
 {
-    const uint32_t e0 = (uint32_t)s.dir_off + ((uint32_t)(c[0] >> 3) * s.nb[1] + (c[1] >> 3)) * s.nb[2] + (c[2] >> 3);
-    const uint32_t st[3] = {(c[0] & 7) == 7 ? (uint32_t)(s.nb[1] * s.nb[2]) : 0u, (c[1] & 7) == 7 ? (uint32_t)s.nb[2] : 0u,
-                            (c[2] & 7) == 7 ? 1u : 0u};
-    const int32_t lx[2] = {(c[0] & 7) << 6, ((c[0] + 1) & 7) << 6};
-    const int32_t ly[2] = {(c[1] & 7) << 3, ((c[1] + 1) & 7) << 3};
-    const int32_t lz[2] = {c[2] & 7, (c[2] + 1) & 7};
+    using G = Geo<kB>;
+    const uint32_t e0 =
+        (uint32_t)s.dir_off + ((uint32_t)(c[0] >> G::S) * s.nb[1] + (c[1] >> G::S)) * s.nb[2] + (c[2] >> G::S);
+    const uint32_t st[3] = {(c[0] & G::M) == G::M ? (uint32_t)(s.nb[1] * s.nb[2]) : 0u,
+                            (c[1] & G::M) == G::M ? (uint32_t)s.nb[2] : 0u, (c[2] & G::M) == G::M ? 1u : 0u};
+    const int32_t lx[2] = {(c[0] & G::M) << (2 * G::S), ((c[0] + 1) & G::M) << (2 * G::S)};
+    const int32_t ly[2] = {(c[1] & G::M) << G::S, ((c[1] + 1) & G::M) << G::S};
+    const int32_t lz[2] = {c[2] & G::M, (c[2] + 1) & G::M};
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
@@ -180,7 +215,7 @@ __device__ inline void corner_slots(const Band& B, const ShapeDesc& s, const int
 #pragma unroll
             for (int d = 0; d < 2; ++d) {
                 const int32_t br = *at32(B.dir, e0 + a * st[0] + b * st[1] + d * st[2]);
-                slot[4 * a + 2 * b + d] = br * kBrickVol + lx[a] + ly[b] + lz[d];
+                slot[4 * a + 2 * b + d] = br * G::V + lx[a] + ly[b] + lz[d];
             }
 }
 
@@ -354,6 +389,7 @@ struct gp_ctx_s {
 
     // band state
     bool built = false;
+    int32_t brick = 8;          // band brick edge (4, 8 or 16)
     int32_t n_shapes = 0;
     int32_t m1 = 0, m2 = 0;
     int64_t n_bricks = 0;
@@ -459,6 +495,18 @@ struct gp_ctx_s {
     }
 };
 
+// Calls f(BrickTag<kB>{}) for the band's brick edge kB (4, 8 or 16), so that
+// a launch site picks the kernel instance of the context's bricks.
+template <class F>
+inline auto with_brick(int32_t brick, F&& f) -> decltype(f(gp::BrickTag<8>{}))
+{
+    switch (brick) {
+    case 4: return f(gp::BrickTag<4>{});
+    case 16: return f(gp::BrickTag<16>{});
+    default: return f(gp::BrickTag<8>{});
+    }
+}
+
 // Brackets one kernel launch with events when timing is enabled.
 hipEvent_t gp_timer_begin(gp_ctx ctx);
 void gp_timer_end(gp_ctx ctx, const char* name, hipEvent_t begin);
@@ -485,7 +533,7 @@ gp_status gp_hip_fail(gp_ctx ctx, hipError_t e, const char* what);
 // kernel launch wrappers implemented in the other translation units
 gp_status gp_build_band_impl(gp_ctx ctx, const gp_shape* shapes, int32_t n_shapes,
                              const float* px, const float* py, const float* pz,
-                             int32_t m1, int32_t m2);
+                             int32_t m1, int32_t m2, int32_t brick);
 gp_status gp_build_nn_index(gp_ctx ctx, int32_t cell_points);
 std::vector<int32_t> gp_nn_levels(gp_ctx ctx, int32_t cell_points);   // per shape, before the size limits
 gp_status gp_nn_impl(gp_ctx ctx, const float* qx, const float* qy, const float* qz, int32_t* nn);

@@ -30,18 +30,20 @@ struct SurfEval {
 
 // Validity of query (x, y, z) and the field at its nearest point; false for
 // an invalid query or an index outside the shape's points.
+template <int kB>
 __device__ inline bool eval_nearest(const Band& B, const ShapeDesc& s, const float* __restrict__ D, float x, float y,
                                     float z, int64_t k, int32_t nn, const PointView& P, SurfEval& e)
 {
     const Loc L = locate(s, x, y, z);
     if (!L.inside) return false;
-    const int32_t br = brick_of(B, s, L.c[0] >> 3, L.c[1] >> 3, L.c[2] >> 3);
-    if (br < 0 || !mask_bit(B.m_a1, br, local_index(L.c[0], L.c[1], L.c[2]))) return false;
+    using G = Geo<kB>;
+    const int32_t br = brick_of(B, s, L.c[0] >> G::S, L.c[1] >> G::S, L.c[2] >> G::S);
+    if (br < 0 || !mask_bit_b<kB>(B.m_a1, br, local_index_b<kB>(L.c[0], L.c[1], L.c[2]))) return false;
     if (nn < 0 || nn >= s.point_cnt) return false;
     float sx, sy, sz;
     nearest_point(s, P, k, nn, sx, sy, sz);
     const Loc Ls = locate(s, sx, sy, sz);
-    corner_slots(B, s, Ls.c, e.slot);
+    corner_slots<kB>(B, s, Ls.c, e.slot);
     float v[8];
 #pragma unroll
     for (int i = 0; i < 8; ++i) v[i] = D[e.slot[i]];
@@ -68,6 +70,7 @@ __device__ inline double block_sum256(double v, double* lds)
     return r;
 }
 
+template <int kB>
 __global__ __launch_bounds__(kNrmBlock) void k_normal_terms(Band B, const float* __restrict__ qx,
                                                             const float* __restrict__ qy,
                                                             const float* __restrict__ qz,
@@ -86,7 +89,7 @@ __global__ __launch_bounds__(kNrmBlock) void k_normal_terms(Band B, const float*
     const int64_t qe = min(B.tile_start[tile] + (int64_t)kQueryTile, s.query_off + s.query_cnt);
     double term = 0.0, cnt = 0.0;
     SurfEval e;
-    if (k < qe && eval_nearest(B, s, D, qx[k], qy[k], qz[k], k, nn[k], P, e)) {
+    if (k < qe && eval_nearest<kB>(B, s, D, qx[k], qy[k], qz[k], k, nn[k], P, e)) {
         const double n[3] = {(double)nx[e.point], (double)ny[e.point], (double)nz[e.point]};
         term = e.ok ? 1.0 - fma(e.gh[0], n[0], fma(e.gh[1], n[1], e.gh[2] * n[2])) : 1.0;
         cnt = 1.0;
@@ -116,6 +119,7 @@ __global__ void k_normal_mean(Band B, int32_t n_shapes, const double* __restrict
     scale[shape] = c > 0.0 ? (float)((double)weight * (dloss ? dloss[shape] : 1.0) / c) : 0.f;
 }
 
+template <int kB>
 __global__ __launch_bounds__(kNrmBlock) void k_normal_scatter(Band B, const float* __restrict__ qx,
                                                               const float* __restrict__ qy,
                                                               const float* __restrict__ qz,
@@ -133,7 +137,7 @@ __global__ __launch_bounds__(kNrmBlock) void k_normal_scatter(Band B, const floa
     const int64_t k = B.tile_start[tile] + (int64_t)(blockIdx.x % 4) * kNrmBlock + threadIdx.x;
     const int64_t qe = min(B.tile_start[tile] + (int64_t)kQueryTile, s.query_off + s.query_cnt);
     SurfEval e;
-    if (k >= qe || !eval_nearest(B, s, D, qx[k], qy[k], qz[k], k, nn[k], P, e) || !e.ok) return;
+    if (k >= qe || !eval_nearest<kB>(B, s, D, qx[k], qy[k], qz[k], k, nn[k], P, e) || !e.ok) return;
     const double n[3] = {(double)nx[e.point], (double)ny[e.point], (double)nz[e.point]};
     const double c = fma(e.gh[0], n[0], fma(e.gh[1], n[1], e.gh[2] * n[2]));
     float dg[3];
@@ -162,15 +166,19 @@ gp_status gp_normals_impl(gp_ctx ctx, const float* qx, const float* qy, const fl
     if ((int64_t)ctx->nrm_scale.n < ctx->n_shapes) GP_HIP(ctx, ctx->nrm_scale.alloc(ctx->n_shapes));
     if (blocks > 0) {
         GP_TIMED(ctx, "k_normal_terms");
-        k_normal_terms<<<(unsigned)blocks, kNrmBlock, 0, st>>>(B, qx, qy, qz, nn, ctx->points(),
-                                                               field, nx, ny, nz, ctx->nrm_part.p);
+        with_brick(ctx->brick, [&](auto tag) {
+            k_normal_terms<decltype(tag)::value><<<(unsigned)blocks, kNrmBlock, 0, st>>>(
+                B, qx, qy, qz, nn, ctx->points(), field, nx, ny, nz, ctx->nrm_part.p);
+        });
     }
     k_normal_mean<<<(unsigned)((ctx->n_shapes + 63) / 64), 64, 0, st>>>(B, ctx->n_shapes, ctx->nrm_part.p, weight,
                                                                         dloss, term_out, ctx->nrm_scale.p);
     if (grad && blocks > 0) {
         GP_TIMED(ctx, "k_normal_scatter");
-        k_normal_scatter<<<(unsigned)blocks, kNrmBlock, 0, st>>>(B, qx, qy, qz, nn, ctx->points(),
-                                                                 field, nx, ny, nz, ctx->nrm_scale.p, grad);
+        with_brick(ctx->brick, [&](auto tag) {
+            k_normal_scatter<decltype(tag)::value><<<(unsigned)blocks, kNrmBlock, 0, st>>>(
+                B, qx, qy, qz, nn, ctx->points(), field, nx, ny, nz, ctx->nrm_scale.p, grad);
+        });
     }
     GP_HIP(ctx, hipGetLastError());
     return GP_OK;

@@ -41,13 +41,14 @@ struct Side {
     bool ok;           // |grad f| >= eps
 };
 
+template <int kB>
 __device__ inline void eval_side(const Band& B, const ShapeDesc& s, const float* __restrict__ D, const Loc& L,
                                  Side& out)
 {
     out.c[0] = L.c[0];
     out.c[1] = L.c[1];
     out.c[2] = L.c[2];
-    corner_slots(B, s, L.c, out.slot);
+    corner_slots<kB>(B, s, L.c, out.slot);
     float v[8];
 #pragma unroll
     for (int i = 0; i < 8; ++i) v[i] = *at32(D, (uint32_t)out.slot[i]);
@@ -76,6 +77,7 @@ struct QueryState {
     double lp;       // |p - s|
 };
 
+template <int kB>
 __device__ inline bool eval_query(const Band& B, const ShapeDesc& s, const float* __restrict__ D, float x, float y,
                                   float z, int64_t k, int32_t nn, const PointView& P, int32_t* bad_nn, QueryState& st)
 {
@@ -84,15 +86,16 @@ __device__ inline bool eval_query(const Band& B, const ShapeDesc& s, const float
     const bool nn_ok = nn >= 0 && nn < s.point_cnt;
     float sx = 0.f, sy = 0.f, sz = 0.f;
     if (s.point_cnt > 0) nearest_point(s, P, k, nn_ok ? nn : 0, sx, sy, sz);
-    const int32_t br = L.inside ? brick_of(B, s, L.c[0] >> 3, L.c[1] >> 3, L.c[2] >> 3) : -1;
-    if (br < 0 || !mask_bit(B.m_a1, br, local_index(L.c[0], L.c[1], L.c[2]))) return false;
+    using G = Geo<kB>;
+    const int32_t br = L.inside ? brick_of(B, s, L.c[0] >> G::S, L.c[1] >> G::S, L.c[2] >> G::S) : -1;
+    if (br < 0 || !mask_bit_b<kB>(B.m_a1, br, local_index_b<kB>(L.c[0], L.c[1], L.c[2]))) return false;
     if (!nn_ok) {
         atomicOr(bad_nn, 2);   // reported as an argument error by the next gp_sync
         return false;
     }
     const Loc Ls = locate(s, sx, sy, sz);
-    eval_side(B, s, D, L, st.q);
-    eval_side(B, s, D, Ls, st.s);
+    eval_side<kB>(B, s, D, L, st.q);
+    eval_side<kB>(B, s, D, Ls, st.s);
     st.d[0] = (double)x - (double)sx;
     st.d[1] = (double)y - (double)sy;
     st.d[2] = (double)z - (double)sz;
@@ -123,6 +126,7 @@ __device__ inline void block_sum(double (&v)[N], double* lds /* [4 waves][N] */)
     }
 }
 
+template <int kB>
 __global__ __launch_bounds__(kQueryBlock) void k_forward_query(Band B, const float* __restrict__ qx,
                                                                const float* __restrict__ qy,
                                                                const float* __restrict__ qz,
@@ -140,7 +144,7 @@ __global__ __launch_bounds__(kQueryBlock) void k_forward_query(Band B, const flo
     int cnt = 0;
     for (int64_t k = q0 + threadIdx.x; k < qe; k += blockDim.x) {
         QueryState st;
-        if (!eval_query(B, s, D, qx[k], qy[k], qz[k], k, nn[k], P, flag, st)) continue;
+        if (!eval_query<kB>(B, s, D, qx[k], qy[k], qz[k], k, nn[k], P, flag, st)) continue;
         const double lg = (st.q.ok && st.s.ok)
                               ? 1.0 - fma(st.q.gh[0], st.s.gh[0], fma(st.q.gh[1], st.s.gh[1], st.q.gh[2] * st.s.gh[2]))
                               : 1.0;
@@ -221,22 +225,24 @@ __device__ inline void query_adjoint(const ShapeDesc& s, const QueryState& st, g
 // in [2^52, 2^53), where the double's ulp is 1, so the addition rounds v to
 // the nearest integer (ties to even, as a rounding conversion would) and the
 // sum's bits minus those of 1.5 * 2^52 are that integer in two's complement.
-// Directory entries of a slab's bricks, at most: a slab of d0 x d1 x d2 <= cap
-// vertices meets at most prod(floor((d_i + 6) / 8) + 1) bricks, largest for
-// 2 x 2 x cap/4 (two bricks on each short axis).
+// Directory entries of a slab's bricks (edge kB), at most: a slab of
+// d0 x d1 x d2 <= cap vertices meets at most prod(floor((d_i + kB - 2) / kB) + 1)
+// bricks, largest for 2 x 2 x cap/4 (two bricks on each short axis).
+template <int kB>
 __host__ __device__ constexpr int32_t win_bricks_bound(int32_t cap)
 {
-    return 4 * ((cap / 4 + 6) / 8 + 1);
+    return 4 * ((cap / 4 + kB - 2) / kB + 1);
 }
 
 // LDS of a query block: the window (cap 64-bit entries), then the slab's
 // brick directory entries.
+template <int kB>
 __host__ __device__ constexpr int32_t win_lds_bytes(int32_t cap)
 {
-    return cap * 8 + win_bricks_bound(cap) * 4;
+    return cap * 8 + win_bricks_bound<kB>(cap) * 4;
 }
-static_assert(win_bricks_bound(4608) == 580 && win_bricks_bound(6912) == 868, "slab brick bound");
-static_assert(win_lds_bytes(kWinCapMax) <= 64 * 1024 - 512, "window LDS within one workgroup's 64 KB");
+static_assert(win_bricks_bound<8>(4608) == 580 && win_bricks_bound<8>(6912) == 868, "slab brick bound");
+static_assert(win_lds_bytes<4>(kWinCapMax) <= 64 * 1024 - 512, "window LDS within one workgroup's 64 KB");
 constexpr double kFixScale = 4294967296.0;   // 2^32
 constexpr float kFixLimit = 524288.f;        // 2^19
 constexpr double kFixMagic = 6755399441055744.0;   // 1.5 * 2^52
@@ -326,16 +332,18 @@ struct WinBricks {
     int32_t nb[3];     // bricks per axis
 };
 
+template <int kB>
 __device__ inline WinBricks slab_bricks(const Band& B, const ShapeDesc& s, const Window& W, int32_t a0, int32_t a1,
                                         int32_t* wdir)
 {
+    constexpr int32_t S = Geo<kB>::S;
     WinBricks T;
     int32_t n = 1;
     for (int a = 0; a < 3; ++a) {
         const int32_t lo = W.lo[a] + (a == W.ax ? a0 : 0);
         const int32_t w = a == W.ax ? a1 - a0 : W.w[a];
-        T.b0[a] = lo >> 3;
-        T.nb[a] = ((lo + w - 1) >> 3) - T.b0[a] + 1;
+        T.b0[a] = lo >> S;
+        T.nb[a] = ((lo + w - 1) >> S) - T.b0[a] + 1;
         n *= T.nb[a];
     }
     const int32_t nyz = T.nb[1] * T.nb[2];
@@ -351,9 +359,11 @@ __device__ inline WinBricks slab_bricks(const Band& B, const ShapeDesc& s, const
 // order, and clear it.  The vertex of an entry is found from its index by
 // float reciprocals: the index is below 2^13, far inside float's exact
 // range, and (i + 1/2) / w stays at least 1/(2w) away from an integer.
+template <int kB>
 __device__ inline void window_flush(const Window& W, int32_t a0, int32_t a1, const WinBricks& T, const int32_t* wdir,
                                     unsigned long long* acc, float* __restrict__ G, float scale)
 {
+    using Gm = Geo<kB>;
     const int32_t wo = W.w[1 - W.ax], wz = W.w[2];
     const int32_t w12 = wo * wz, vol = (a1 - a0) * w12;
     const float inv12 = 1.f / (float)w12, inv2 = 1.f / (float)wz;
@@ -366,8 +376,9 @@ __device__ inline void window_flush(const Window& W, int32_t a0, int32_t a1, con
         const int32_t io = (int32_t)(((float)r + 0.5f) * inv2);
         const int32_t va = W.lo[W.ax] + a0 + ia, vo = W.lo[1 - W.ax] + io;
         const int32_t vx = W.ax == 0 ? va : vo, vy = W.ax == 0 ? vo : va, vz = W.lo[2] + (r - io * wz);
-        const int32_t br = wdir[(((vx >> 3) - T.b0[0]) * T.nb[1] + ((vy >> 3) - T.b0[1])) * T.nb[2] + ((vz >> 3) - T.b0[2])];
-        atomicAdd(at32(G, (uint32_t)(br * kBrickVol + local_index(vx, vy, vz))),
+        const int32_t br = wdir[(((vx >> Gm::S) - T.b0[0]) * T.nb[1] + ((vy >> Gm::S) - T.b0[1])) * T.nb[2] +
+                                ((vz >> Gm::S) - T.b0[2])];
+        atomicAdd(at32(G, (uint32_t)(br * Gm::V + local_index_b<kB>(vx, vy, vz))),
                   (float)((double)v * (1.0 / kFixScale) * (double)scale));
     }
 }
@@ -385,7 +396,7 @@ __device__ inline void direct_add(const int32_t slot[8], const float v[8], float
 // partials, and the contributions go out unscaled (the per-shape scale
 // 1/valid count is applied when they are folded into the gradient);
 // otherwise they are scaled by dloss / valid count.
-template <bool kLoss>
+template <bool kLoss, int kB>
 __global__ __launch_bounds__(kGradBlock) void k_query_grad(Band B, const float* __restrict__ qx,
                                                            const float* __restrict__ qy,
                                                            const float* __restrict__ qz,
@@ -419,7 +430,7 @@ __global__ __launch_bounds__(kGradBlock) void k_query_grad(Band B, const float* 
     double part[4] = {0.0, 0.0, 0.0, 0.0};
     if (k < qe) {
         QueryState st;
-        valid = eval_query(B, s, D, qx[k], qy[k], qz[k], k, nn[k], P, flag, st);
+        valid = eval_query<kB>(B, s, D, qx[k], qy[k], qz[k], k, nn[k], P, flag, st);
         if (valid) {
             if (kLoss) {
                 part[0] = st.lp;
@@ -461,7 +472,7 @@ __global__ __launch_bounds__(kGradBlock) void k_query_grad(Band B, const float* 
     } else {
         for (int32_t p = 0; p < W.passes; ++p) {
             const int32_t a0 = p * W.layers, a1 = min(a0 + W.layers, W.w[W.ax]);
-            const WinBricks T = slab_bricks(B, s, W, a0, a1, s_wdir);
+            const WinBricks T = slab_bricks<kB>(B, s, W, a0, a1, s_wdir);
             if (valid) {
                 int32_t iq[8], is[8];
                 window_corners(W, a0, a1, ccq, iq);
@@ -470,7 +481,7 @@ __global__ __launch_bounds__(kGradBlock) void k_query_grad(Band B, const float* 
                 window_add(is, ss, cs, p == 0, s_acc, G, scale);
             }
             __syncthreads();
-            window_flush(W, a0, a1, T, s_wdir, s_acc, G, scale);
+            window_flush<kB>(W, a0, a1, T, s_wdir, s_acc, G, scale);
             __syncthreads();
         }
     }
@@ -506,48 +517,59 @@ __global__ __launch_bounds__(kGradBlock) void k_query_grad(Band B, const float* 
 //   neighbouring brick by the lanes on that face.  Five times as many bricks
 //   are in flight per CU, which large bands need.
 
-constexpr int kHalo = kBrick + 2;                        // staged vertices per axis
-constexpr int kHaloVol = kHalo * kHalo * kHalo;
 constexpr int kTvWaves = 4;                              // bricks per block in the wave layout
 
-__device__ inline int32_t halo_index(int32_t i, int32_t j, int32_t k)   // brick-local, -1..8
+// Block-per-brick layout for bricks of edge kB: up to 512 threads, each
+// taking V / threads of the brick's vertices; the brick and a one-vertex halo
+// staged in LDS.
+template <int kB>
+struct TvBrick {
+    static constexpr int H = kB + 2;                                  // staged vertices per axis
+    static constexpr int HV = H * H * H;
+    static constexpr int T = Geo<kB>::V < 512 ? Geo<kB>::V : 512;     // threads per block
+};
+
+template <int kB>
+__device__ inline int32_t halo_index(int32_t i, int32_t j, int32_t k)   // brick-local, -1..kB
 {
-    return ((i + 1) * kHalo + (j + 1)) * kHalo + (k + 1);
+    constexpr int H = kB + 2;
+    return ((i + 1) * H + (j + 1)) * H + (k + 1);
 }
 
 // Stage values of one or two slot arrays (b may be null) and the TV flags.
+template <int kB>
 __device__ inline void stage_brick(const Band& B, const ShapeDesc& s, int32_t brick, const BrickInfo& bi,
                                    const float* __restrict__ a, const float* __restrict__ b, float* sa, float* sb,
                                    uint8_t* tv)
 {
-    const int t = threadIdx.x;   // 0 .. 511: the brick's own vertex t
-    {
-        const int32_t li = t >> 6, lj = (t >> 3) & 7, lk = t & 7;
-        const int32_t h = halo_index(li, lj, lk);
-        const int32_t slot = brick * kBrickVol + t;
+    using G = Geo<kB>;
+    for (int t = threadIdx.x; t < G::V; t += blockDim.x) {   // the brick's own vertex t
+        const int32_t li = t >> (2 * G::S), lj = (t >> G::S) & G::M, lk = t & G::M;
+        const int32_t h = halo_index<kB>(li, lj, lk);
+        const int32_t slot = brick * G::V + t;
         sa[h] = a[slot];
         if (b) sb[h] = b[slot];
-        tv[h] = (uint8_t)mask_bit(B.m_v2, brick, t);
+        tv[h] = (uint8_t)mask_bit_b<kB>(B.m_v2, brick, t);
     }
-    if (t < 6 * 64) {
-        // face f: axis f / 2, side -1 (even f) or +1 (odd f); 64 vertices each
-        const int f = t >> 6, w = t & 63, axis = f >> 1, side = (f & 1) ? 1 : -1;
+    for (int t = threadIdx.x; t < 6 * kB * kB; t += blockDim.x) {
+        // face f: axis f / 2, side -1 (even f) or +1 (odd f); kB^2 vertices each
+        const int f = t >> (2 * G::S), w = t & (kB * kB - 1), axis = f >> 1, side = (f & 1) ? 1 : -1;
         int32_t l[3];
-        l[axis] = side > 0 ? kBrick : -1;
-        l[(axis + 1) % 3] = w >> 3;
-        l[(axis + 2) % 3] = w & 7;
-        const int32_t gi = bi.bx * kBrick + l[0], gj = bi.by * kBrick + l[1], gk = bi.bz * kBrick + l[2];
-        const int32_t h = halo_index(l[0], l[1], l[2]);
+        l[axis] = side > 0 ? kB : -1;
+        l[(axis + 1) % 3] = w >> G::S;
+        l[(axis + 2) % 3] = w & G::M;
+        const int32_t gi = bi.bx * kB + l[0], gj = bi.by * kB + l[1], gk = bi.bz * kB + l[2];
+        const int32_t h = halo_index<kB>(l[0], l[1], l[2]);
         float va = 0.f, vb = 0.f;
         uint8_t flag = 0;
         if (gi >= 0 && gj >= 0 && gk >= 0 && gi <= s.R[0] && gj <= s.R[1] && gk <= s.R[2]) {
-            const int32_t nb = brick_of(B, s, gi >> 3, gj >> 3, gk >> 3);
+            const int32_t nb = brick_of(B, s, gi >> G::S, gj >> G::S, gk >> G::S);
             if (nb >= 0) {
-                const int32_t loc = local_index(gi, gj, gk);
-                const int32_t slot = nb * kBrickVol + loc;
+                const int32_t loc = local_index_b<kB>(gi, gj, gk);
+                const int32_t slot = nb * G::V + loc;
                 va = a[slot];
                 if (b) vb = b[slot];
-                flag = (uint8_t)mask_bit(B.m_v2, nb, loc);
+                flag = (uint8_t)mask_bit_b<kB>(B.m_v2, nb, loc);
             }
         }
         sa[h] = va;
@@ -556,24 +578,28 @@ __device__ inline void stage_brick(const Band& B, const ShapeDesc& s, int32_t br
     }
 }
 
-__global__ __launch_bounds__(kBrickVol) void k_tv_forward_brick(Band B, const float* __restrict__ D,
-                                                                float* __restrict__ itau, double* __restrict__ tv_part)
+template <int kB>
+__global__ __launch_bounds__(TvBrick<kB>::T) void k_tv_forward_brick(Band B, const float* __restrict__ D,
+                                                                   float* __restrict__ itau,
+                                                                   double* __restrict__ tv_part)
 {
-    __shared__ float s_d[kHaloVol];
-    __shared__ uint8_t s_tv[kHaloVol];
-    __shared__ double lds[kBrickVol / 64];
+    using G = Geo<kB>;
+    constexpr int H = TvBrick<kB>::H;
+    __shared__ float s_d[TvBrick<kB>::HV];
+    __shared__ uint8_t s_tv[TvBrick<kB>::HV];
+    __shared__ double lds[TvBrick<kB>::T / 64 + 1];
     const int32_t brick = blockIdx.x;
     const BrickInfo bi = B.bricks[brick];
     const ShapeDesc& s = B.shapes[bi.shape];
-    stage_brick(B, s, brick, bi, D, nullptr, s_d, nullptr, s_tv);
+    stage_brick<kB>(B, s, brick, bi, D, nullptr, s_d, nullptr, s_tv);
     __syncthreads();
-    const int t = threadIdx.x;
-    const int32_t li = t >> 6, lj = (t >> 3) & 7, lk = t & 7;
-    const int32_t h = halo_index(li, lj, lk);
-    float tau_v = 0.f;
-    if (s_tv[h]) {
+    double v = 0.0;
+    for (int t = threadIdx.x; t < G::V; t += blockDim.x) {
+        const int32_t li = t >> (2 * G::S), lj = (t >> G::S) & G::M, lk = t & G::M;
+        const int32_t h = halo_index<kB>(li, lj, lk);
+        if (!s_tv[h]) continue;
         const float dv = s_d[h];
-        const int32_t nbh[6] = {h + kHalo * kHalo, h - kHalo * kHalo, h + kHalo, h - kHalo, h + 1, h - 1};
+        const int32_t nbh[6] = {h + H * H, h - H * H, h + H, h - H, h + 1, h - 1};
         float s2 = 0.f;
 #pragma unroll
         for (int o = 0; o < 6; ++o) {
@@ -581,16 +607,17 @@ __global__ __launch_bounds__(kBrickVol) void k_tv_forward_brick(Band B, const fl
             const float d = dv - s_d[nbh[o]];
             s2 = fmaf(d, d, s2);
         }
-        tau_v = sqrtf(s2);
-        if (itau) itau[brick * kBrickVol + t] = tau_v > 0.f ? 1.f / tau_v : 0.f;
+        const float tau_v = sqrtf(s2);
+        if (itau) itau[brick * G::V + t] = tau_v > 0.f ? 1.f / tau_v : 0.f;
+        v += (double)tau_v;
     }
-    double v = (double)tau_v;
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    const int t = threadIdx.x;
     if ((t & 63) == 0) lds[t >> 6] = v;
     __syncthreads();
     if (t == 0) {
         double a = 0.0;
-        for (int wv = 0; wv < kBrickVol / 64; ++wv) a += lds[wv];
+        for (int wv = 0; wv < (int)(blockDim.x >> 6); ++wv) a += lds[wv];
         tv_part[brick] = a;
     }
 }
@@ -599,50 +626,54 @@ __global__ __launch_bounds__(kBrickVol) void k_tv_forward_brick(Band B, const fl
 // neighbours and writes only its own slot), scaled by dloss.  With raw, also
 // adds dloss / valid count times the unscaled query contributions of the
 // fused pass and clears them.
-__global__ __launch_bounds__(kBrickVol) void k_tv_backward_brick(Band B, const float* __restrict__ D,
-                                                                 const float* __restrict__ itau, gp_weights w,
-                                                                 const double* __restrict__ dloss,
-                                                                 const double* __restrict__ inv_qv,
-                                                                 float* __restrict__ raw, float* __restrict__ G)
+template <int kB>
+__global__ __launch_bounds__(TvBrick<kB>::T) void k_tv_backward_brick(Band B, const float* __restrict__ D,
+                                                                    const float* __restrict__ itau, gp_weights w,
+                                                                    const double* __restrict__ dloss,
+                                                                    const double* __restrict__ inv_qv,
+                                                                    float* __restrict__ raw, float* __restrict__ G)
 {
-    __shared__ float s_d[kHaloVol], s_t[kHaloVol];
-    __shared__ uint8_t s_tv[kHaloVol];
+    using Gm = Geo<kB>;
+    constexpr int H = TvBrick<kB>::H;
+    __shared__ float s_d[TvBrick<kB>::HV], s_t[TvBrick<kB>::HV];
+    __shared__ uint8_t s_tv[TvBrick<kB>::HV];
     const int32_t brick = blockIdx.x;
     const BrickInfo bi = B.bricks[brick];
     const ShapeDesc& s = B.shapes[bi.shape];
     const bool tv_on = s.n_tv > 0;
-    if (tv_on) stage_brick(B, s, brick, bi, D, itau, s_d, s_t, s_tv);
+    if (tv_on) stage_brick<kB>(B, s, brick, bi, D, itau, s_d, s_t, s_tv);
     __syncthreads();
     const float scale = tv_on ? (float)((double)w.alpha * dloss[bi.shape] / (double)s.n_tv) : 0.f;
     const float rscale = raw ? (float)(dloss[bi.shape] * inv_qv[bi.shape]) : 0.f;
-    const int t = threadIdx.x;
-    const int32_t slot = brick * kBrickVol + t;
-    float add = 0.f;
-    bool touch = false;
-    if (raw) {
-        const float r = raw[slot];
-        if (r != 0.f) {
-            add = rscale * r;
-            raw[slot] = 0.f;
+    for (int t = threadIdx.x; t < Gm::V; t += blockDim.x) {
+        const int32_t slot = brick * Gm::V + t;
+        float add = 0.f;
+        bool touch = false;
+        if (raw) {
+            const float r = raw[slot];
+            if (r != 0.f) {
+                add = rscale * r;
+                raw[slot] = 0.f;
+                touch = true;
+            }
+        }
+        const int32_t li = t >> (2 * Gm::S), lj = (t >> Gm::S) & Gm::M, lk = t & Gm::M;
+        const int32_t h = halo_index<kB>(li, lj, lk);
+        if (tv_on && s_tv[h]) {
+            const float dv = s_d[h];
+            const float inv_tv = s_t[h];
+            const int32_t nbh[6] = {h + H * H, h - H * H, h + H, h - H, h + 1, h - 1};
+            float acc = 0.f;
+#pragma unroll
+            for (int o = 0; o < 6; ++o) {
+                if (!s_tv[nbh[o]]) continue;
+                acc = fmaf(dv - s_d[nbh[o]], inv_tv + s_t[nbh[o]], acc);
+            }
+            add = fmaf(scale, acc, add);
             touch = true;
         }
+        if (touch) G[slot] += add;
     }
-    const int32_t li = t >> 6, lj = (t >> 3) & 7, lk = t & 7;
-    const int32_t h = halo_index(li, lj, lk);
-    if (tv_on && s_tv[h]) {
-        const float dv = s_d[h];
-        const float inv_tv = s_t[h];
-        const int32_t nbh[6] = {h + kHalo * kHalo, h - kHalo * kHalo, h + kHalo, h - kHalo, h + 1, h - 1};
-        float acc = 0.f;
-#pragma unroll
-        for (int o = 0; o < 6; ++o) {
-            if (!s_tv[nbh[o]]) continue;
-            acc = fmaf(dv - s_d[nbh[o]], inv_tv + s_t[nbh[o]], acc);
-        }
-        add = fmaf(scale, acc, add);
-        touch = true;
-    }
-    if (touch) G[slot] += add;
 }
 
 // The 8 mask bits of column col (0..63) of a brick: vertices col * 8 + k.
@@ -950,7 +981,7 @@ using namespace gp;
 // 6k bricks, 0.71 -> 0.54 ms at 137k and 32 -> 34 us at 6k).
 static bool tv_wave_layout(gp_ctx ctx, int64_t wave_from)
 {
-    return ctx->n_bricks >= wave_from;
+    return ctx->brick == kBrick && ctx->n_bricks >= wave_from;   // the wave layout is written for 8^3 bricks
 }
 
 // itau may be null (the loss alone); tv_part receives the per-brick sums.
@@ -961,7 +992,10 @@ static void launch_tv_forward(gp_ctx ctx, const Band& B, const float* field, flo
         k_tv_forward_wave<<<(unsigned)((ctx->n_bricks + kTvWaves - 1) / kTvWaves), kTvWaves * 64, 0, st>>>(
             B, field, itau, tv_part, (int32_t)ctx->n_bricks);
     else
-        k_tv_forward_brick<<<(unsigned)ctx->n_bricks, kBrickVol, 0, st>>>(B, field, itau, tv_part);
+        with_brick(ctx->brick, [&](auto tag) {
+            constexpr int kB = decltype(tag)::value;
+            k_tv_forward_brick<kB><<<(unsigned)ctx->n_bricks, TvBrick<kB>::T, 0, st>>>(B, field, itau, tv_part);
+        });
 }
 
 static void launch_tv_backward(gp_ctx ctx, const Band& B, const float* field, gp_weights w, const double* dloss,
@@ -971,8 +1005,11 @@ static void launch_tv_backward(gp_ctx ctx, const Band& B, const float* field, gp
         k_tv_backward_wave<<<(unsigned)((ctx->n_bricks + kTvWaves - 1) / kTvWaves), kTvWaves * 64, 0, st>>>(
             B, field, ctx->tau.p, w, dloss, ctx->inv_qv.p, raw, grad, (int32_t)ctx->n_bricks);
     else
-        k_tv_backward_brick<<<(unsigned)ctx->n_bricks, kBrickVol, 0, st>>>(B, field, ctx->tau.p, w, dloss,
-                                                                        ctx->inv_qv.p, raw, grad);
+        with_brick(ctx->brick, [&](auto tag) {
+            constexpr int kB = decltype(tag)::value;
+            k_tv_backward_brick<kB><<<(unsigned)ctx->n_bricks, TvBrick<kB>::T, 0, st>>>(B, field, ctx->tau.p, w, dloss,
+                                                                                      ctx->inv_qv.p, raw, grad);
+        });
 }
 
 gp_status gp_forward_impl(gp_ctx ctx, const float* qx, const float* qy, const float* qz, const int32_t* nn,
@@ -982,7 +1019,10 @@ gp_status gp_forward_impl(gp_ctx ctx, const float* qx, const float* qy, const fl
     Band B = ctx->band();
     if (ctx->n_tiles > 0) {
         GP_TIMED(ctx, "k_forward_query");
-        k_forward_query<<<(unsigned)ctx->n_tiles, kQueryBlock, 0, st>>>(B, qx, qy, qz, nn, ctx->points(), field, ctx->q_part.p, ctx->flag.p);
+        with_brick(ctx->brick, [&](auto tag) {
+            k_forward_query<decltype(tag)::value><<<(unsigned)ctx->n_tiles, kQueryBlock, 0, st>>>(
+                B, qx, qy, qz, nn, ctx->points(), field, ctx->q_part.p, ctx->flag.p);
+        });
     }
     if (ctx->n_bricks > 0) {
         GP_TIMED(ctx, "k_tv_forward");
@@ -1004,9 +1044,12 @@ gp_status gp_backward_impl(gp_ctx ctx, const float* qx, const float* qy, const f
     if (ctx->n_tiles > 0) {
         GP_TIMED(ctx, "k_backward_query");
         const GradParams& gpar = ctx->grad_params;
-        k_query_grad<false><<<(unsigned)(ctx->n_tiles * kGradParts), kGradBlock, win_lds_bytes(gpar.win_cap), st>>>(
-            B, qx, qy, qz, nn, ctx->points(), field, w, dloss, ctx->inv_qv.p, grad, nullptr,
-            ctx->flag.p, gpar.win_cap, gpar.win_max_passes);
+        with_brick(ctx->brick, [&](auto tag) {
+            constexpr int kB = decltype(tag)::value;
+            k_query_grad<false, kB><<<(unsigned)(ctx->n_tiles * kGradParts), kGradBlock, win_lds_bytes<kB>(gpar.win_cap),
+                                      st>>>(B, qx, qy, qz, nn, ctx->points(), field, w, dloss, ctx->inv_qv.p, grad,
+                                            nullptr, ctx->flag.p, gpar.win_cap, gpar.win_max_passes);
+        });
     }
     if (ctx->n_bricks > 0) {
         GP_TIMED(ctx, "k_tv_backward");
@@ -1025,9 +1068,13 @@ gp_status gp_forward_backward_impl(gp_ctx ctx, const float* qx, const float* qy,
     if (ctx->n_tiles > 0) {
         GP_TIMED(ctx, "k_query_grad");
         const GradParams& gpar = ctx->grad_params;
-        k_query_grad<true><<<(unsigned)(ctx->n_tiles * kGradParts), kGradBlock, win_lds_bytes(gpar.win_cap), st>>>(
-            B, qx, qy, qz, nn, ctx->points(), field, w, dloss, ctx->inv_qv.p, ctx->g_raw.p,
-            ctx->q_part.p, ctx->flag.p, gpar.win_cap, gpar.win_max_passes);
+        with_brick(ctx->brick, [&](auto tag) {
+            constexpr int kB = decltype(tag)::value;
+            k_query_grad<true, kB><<<(unsigned)(ctx->n_tiles * kGradParts), kGradBlock, win_lds_bytes<kB>(gpar.win_cap),
+                                     st>>>(B, qx, qy, qz, nn, ctx->points(), field, w, dloss, ctx->inv_qv.p,
+                                           ctx->g_raw.p, ctx->q_part.p, ctx->flag.p, gpar.win_cap,
+                                           gpar.win_max_passes);
+        });
     }
     if (ctx->n_bricks > 0) {
         GP_TIMED(ctx, "k_tv_forward");
@@ -1121,8 +1168,10 @@ gp_status gp_forward_static_impl(gp_ctx ctx, const float* qx, const float* qy, c
     Band B = ctx->band();
     k_zero_i32<<<(unsigned)((ctx->n_shapes + 255) / 256), 256, 0, st>>>(fin_count, ctx->n_shapes);
     if (ctx->n_tiles > 0)
-        k_forward_query<<<(unsigned)ctx->n_tiles, kQueryBlock, 0, st>>>(B, qx, qy, qz, nn, ctx->points(), field,
-                                                                        q_part, ctx->flag.p);
+        with_brick(ctx->brick, [&](auto tag) {
+            k_forward_query<decltype(tag)::value><<<(unsigned)ctx->n_tiles, kQueryBlock, 0, st>>>(
+                B, qx, qy, qz, nn, ctx->points(), field, q_part, ctx->flag.p);
+        });
     if (ctx->n_bricks > 0) launch_tv_forward(ctx, B, field, nullptr, tv_part, st);
     k_finalize<<<dim3(kFinChunks, (unsigned)ctx->n_shapes), kFinalizeBlock, 0, st>>>(
         B, q_part, tv_part, w, loss_out, n_valid_out, inv_qv, ctx->flag.p, 1, fin_part, fin_count);
@@ -1136,9 +1185,10 @@ gp_status gp_forward_static_impl(gp_ctx ctx, const float* qx, const float* qy, c
 // stream (one untimed run, then the smallest of reps runs).  The query pass
 // accumulates into the context's own accumulator, cleared afterwards; the TV
 // backward writes a scratch gradient.
-gp_status gp_autotune_grad_impl(gp_ctx ctx, const float* qx, const float* qy, const float* qz, const int32_t* nn,
-                                const float* field, gp_weights w, int32_t reps, GradParams* best_out,
-                                float* best_ms_out)
+template <int kB>
+static gp_status autotune_grad(gp_ctx ctx, const float* qx, const float* qy, const float* qz, const int32_t* nn,
+                               const float* field, gp_weights w, int32_t reps, GradParams* best_out,
+                               float* best_ms_out)
 {
     static const int32_t kPasses[] = {4, 16, 64};
     hipStream_t st = ctx->stream;
@@ -1172,7 +1222,7 @@ gp_status gp_autotune_grad_impl(gp_ctx ctx, const float* qx, const float* qy, co
     if (ctx->n_tiles > 0) {
         auto query_pass = [&](int32_t cap, int32_t passes) {
             return time_it([&] {
-                k_query_grad<true><<<(unsigned)(ctx->n_tiles * kGradParts), kGradBlock, win_lds_bytes(cap), st>>>(
+                k_query_grad<true, kB><<<(unsigned)(ctx->n_tiles * kGradParts), kGradBlock, win_lds_bytes<kB>(cap), st>>>(
                     B, qx, qy, qz, nn, ctx->points(), field, w, nullptr, nullptr, ctx->g_raw.p, ctx->q_part.p,
                     ctx->flag.p, cap, passes);
             });
@@ -1193,7 +1243,7 @@ gp_status gp_autotune_grad_impl(gp_ctx ctx, const float* qx, const float* qy, co
         ms[0] = best_t;
         if (e == hipSuccess) e = hipMemsetAsync(ctx->g_raw.p, 0, (size_t)std::max<int64_t>(ctx->n_slots, 1) * 4, st);
     }
-    if (ctx->n_bricks > 0 && e == hipSuccess) {
+    if (kB == kBrick && ctx->n_bricks > 0 && e == hipSuccess) {   // (other bricks have the block layout only)
         const int64_t nb = ctx->n_bricks;
         const unsigned waves_grid = (unsigned)((nb + kTvWaves - 1) / kTvWaves);
         // forward: writes the context's 1/tau and per-brick partials (scratch until the next forward)
@@ -1201,7 +1251,7 @@ gp_status gp_autotune_grad_impl(gp_ctx ctx, const float* qx, const float* qy, co
             k_tv_forward_wave<<<waves_grid, kTvWaves * 64, 0, st>>>(B, field, ctx->tau.p, ctx->tv_part.p, (int32_t)nb);
         });
         const float t_brick = time_it([&] {
-            k_tv_forward_brick<<<(unsigned)nb, kBrickVol, 0, st>>>(B, field, ctx->tau.p, ctx->tv_part.p);
+            k_tv_forward_brick<kB><<<(unsigned)nb, TvBrick<kB>::T, 0, st>>>(B, field, ctx->tau.p, ctx->tv_part.p);
         });
         const bool wave_now = nb >= current.tv_fwd_wave_from;
         const float t_now = wave_now ? t_wave : t_brick, t_other = wave_now ? t_brick : t_wave;
@@ -1221,7 +1271,7 @@ gp_status gp_autotune_grad_impl(gp_ctx ctx, const float* qx, const float* qy, co
                                                                     nullptr, grad.p, (int32_t)nb);
         });
         const float b_brick = time_it([&] {
-            k_tv_backward_brick<<<(unsigned)nb, kBrickVol, 0, st>>>(B, field, ctx->tau.p, w, dloss.p, ctx->inv_qv.p,
+            k_tv_backward_brick<kB><<<(unsigned)nb, TvBrick<kB>::T, 0, st>>>(B, field, ctx->tau.p, w, dloss.p, ctx->inv_qv.p,
                                                                  nullptr, grad.p);
         });
         const bool bwave_now = nb >= current.tv_bwd_wave_from;
@@ -1239,4 +1289,13 @@ gp_status gp_autotune_grad_impl(gp_ctx ctx, const float* qx, const float* qy, co
     if (best_ms_out)
         for (int i = 0; i < 3; ++i) best_ms_out[i] = ms[i];
     return GP_OK;
+}
+
+gp_status gp_autotune_grad_impl(gp_ctx ctx, const float* qx, const float* qy, const float* qz, const int32_t* nn,
+                                const float* field, gp_weights w, int32_t reps, GradParams* best_out,
+                                float* best_ms_out)
+{
+    return with_brick(ctx->brick, [&](auto tag) {
+        return autotune_grad<decltype(tag)::value>(ctx, qx, qy, qz, nn, field, w, reps, best_out, best_ms_out);
+    });
 }

@@ -57,26 +57,29 @@ __global__ void k_adam(const uint32_t* __restrict__ m_v, int64_t n_slots, float*
     }
 }
 
+template <int kB>
 __device__ inline int64_t slot_vertex(const Band& B, int64_t slot, int32_t& shape, int32_t ijk[3])
 {
-    const BrickInfo bi = B.bricks[slot / kBrickVol];
-    const int32_t local = (int32_t)(slot % kBrickVol);
+    using G = Geo<kB>;
+    const BrickInfo bi = B.bricks[slot / G::V];
+    const int32_t local = (int32_t)(slot % G::V);
     const ShapeDesc& s = B.shapes[bi.shape];
     shape = bi.shape;
-    ijk[0] = bi.bx * kBrick + (local >> 6);
-    ijk[1] = bi.by * kBrick + ((local >> 3) & 7);
-    ijk[2] = bi.bz * kBrick + (local & 7);
+    ijk[0] = bi.bx * kB + (local >> (2 * G::S));
+    ijk[1] = bi.by * kB + ((local >> G::S) & G::M);
+    ijk[2] = bi.bz * kB + (local & G::M);
     if (ijk[0] > s.R[0] || ijk[1] > s.R[1] || ijk[2] > s.R[2]) return -1;
     return ((int64_t)ijk[0] * (s.R[1] + 1) + ijk[1]) * (s.R[2] + 1) + ijk[2];
 }
 
+template <int kB>
 __global__ void k_layout(Band B, const uint32_t* __restrict__ m_base, const uint32_t* __restrict__ m_a2,
                          int64_t n_slots, int64_t* __restrict__ vid, uint8_t* __restrict__ flags)
 {
     GRID_STRIDE(i, n_slots)
     {
         int32_t shape, ijk[3];
-        const int64_t v = slot_vertex(B, i, shape, ijk);
+        const int64_t v = slot_vertex<kB>(B, i, shape, ijk);
         if (vid) vid[i] = v;
         if (flags) {
             const int64_t w = i >> 5;
@@ -94,6 +97,7 @@ __global__ void k_layout(Band B, const uint32_t* __restrict__ m_base, const uint
 
 // Linear id of the M1-band cell whose lowest corner is each slot of one
 // shape's slot range, or -1.
+template <int kB>
 __global__ void k_active_cells(Band B, int64_t slot0, int64_t n, int64_t* __restrict__ ids)
 {
     GRID_STRIDE(i, n)
@@ -102,7 +106,7 @@ __global__ void k_active_cells(Band B, int64_t slot0, int64_t n, int64_t* __rest
         int32_t shape, ijk[3];
         int64_t id = -1;
         if ((B.m_a1[slot >> 5] >> (slot & 31)) & 1u) {
-            slot_vertex(B, slot, shape, ijk);
+            slot_vertex<kB>(B, slot, shape, ijk);
             const ShapeDesc& s = B.shapes[shape];
             id = ((int64_t)ijk[0] * s.R[1] + ijk[1]) * s.R[2] + ijk[2];
         }
@@ -114,13 +118,14 @@ struct NonNegative {
     __device__ bool operator()(const int64_t& v) const { return v >= 0; }
 };
 
+template <int kB>
 __global__ void k_gather(Band B, int64_t n_slots, const float* __restrict__ dense, float* __restrict__ field,
                          int to_field)
 {
     GRID_STRIDE(i, n_slots)
     {
         int32_t shape, ijk[3];
-        const int64_t v = slot_vertex(B, i, shape, ijk);
+        const int64_t v = slot_vertex<kB>(B, i, shape, ijk);
         const int64_t off = B.shapes[shape].dense_off;
         if (to_field) {
             field[i] = v >= 0 ? dense[off + v] : 0.f;
@@ -130,13 +135,14 @@ __global__ void k_gather(Band B, int64_t n_slots, const float* __restrict__ dens
     }
 }
 
+template <int kB>
 __global__ void k_init_sphere(Band B, int64_t n_slots, const double* __restrict__ centre,
                               const double* __restrict__ radius, float* __restrict__ field)
 {
     GRID_STRIDE(i, n_slots)
     {
         int32_t shape, ijk[3];
-        const int64_t v = slot_vertex(B, i, shape, ijk);
+        const int64_t v = slot_vertex<kB>(B, i, shape, ijk);
         if (v < 0) {
             field[i] = 0.f;
             continue;
@@ -178,8 +184,10 @@ gp_status gp_step_impl(gp_ctx ctx, float* field, float* grad, float* m, float* v
 gp_status gp_layout_impl(gp_ctx ctx, int64_t* vid, uint8_t* flags)
 {
     if (ctx->n_slots == 0) return GP_OK;
-    k_layout<<<blocks_for(ctx->n_slots), kThreads, 0, ctx->stream>>>(ctx->band(), ctx->m_base.p, ctx->m_a2.p,
-                                                                     ctx->n_slots, vid, flags);
+    with_brick(ctx->brick, [&](auto tag) {
+        k_layout<decltype(tag)::value><<<blocks_for(ctx->n_slots), kThreads, 0, ctx->stream>>>(
+            ctx->band(), ctx->m_base.p, ctx->m_a2.p, ctx->n_slots, vid, flags);
+    });
     GP_HIP(ctx, hipGetLastError());
     return GP_OK;
 }
@@ -187,8 +195,10 @@ gp_status gp_layout_impl(gp_ctx ctx, int64_t* vid, uint8_t* flags)
 gp_status gp_gather_impl(gp_ctx ctx, const float* dense, float* field, bool to_field)
 {
     if (ctx->n_slots == 0) return GP_OK;
-    k_gather<<<blocks_for(ctx->n_slots), kThreads, 0, ctx->stream>>>(ctx->band(), ctx->n_slots, dense, field,
-                                                                     to_field ? 1 : 0);
+    with_brick(ctx->brick, [&](auto tag) {
+        k_gather<decltype(tag)::value><<<blocks_for(ctx->n_slots), kThreads, 0, ctx->stream>>>(
+            ctx->band(), ctx->n_slots, dense, field, to_field ? 1 : 0);
+    });
     GP_HIP(ctx, hipGetLastError());
     return GP_OK;
 }
@@ -201,8 +211,10 @@ gp_status gp_init_sphere_impl(gp_ctx ctx, const double* centre, const double* ra
     GP_HIP(ctx, d.alloc(4 * (size_t)n));
     GP_HIP(ctx, hipMemcpyAsync(d.p, centre, 3 * sizeof(double) * n, hipMemcpyHostToDevice, ctx->stream));
     GP_HIP(ctx, hipMemcpyAsync(d.p + 3 * n, radius, sizeof(double) * n, hipMemcpyHostToDevice, ctx->stream));
-    k_init_sphere<<<blocks_for(ctx->n_slots), kThreads, 0, ctx->stream>>>(ctx->band(), ctx->n_slots, d.p, d.p + 3 * n,
-                                                                          field);
+    with_brick(ctx->brick, [&](auto tag) {
+        k_init_sphere<decltype(tag)::value><<<blocks_for(ctx->n_slots), kThreads, 0, ctx->stream>>>(
+            ctx->band(), ctx->n_slots, d.p, d.p + 3 * n, field);
+    });
     GP_HIP(ctx, hipGetLastError());
     GP_HIP(ctx, hipStreamSynchronize(ctx->stream));   // the scratch is freed on return
     return GP_OK;
@@ -218,7 +230,9 @@ gp_status gp_active_cells_impl(gp_ctx ctx, int32_t shape, int64_t* cell_ids, int
     DevBuf<int64_t> cnt;
     if (ids.alloc(n) != hipSuccess || sel.alloc(n) != hipSuccess || cnt.alloc(1) != hipSuccess)
         return gp_fail(ctx, GP_ERR_OOM, "out of device memory for the cell export");
-    k_active_cells<<<blocks_for(n), kThreads, 0, st>>>(ctx->band(), b, n, ids.p);
+    with_brick(ctx->brick, [&](auto tag) {
+        k_active_cells<decltype(tag)::value><<<blocks_for(n), kThreads, 0, st>>>(ctx->band(), b, n, ids.p);
+    });
     GP_HIP(ctx, hipGetLastError());
     size_t need = 0;
     GP_HIP(ctx, hipcub::DeviceSelect::If(nullptr, need, ids.p, sel.p, cnt.p, (int)n, NonNegative(), st));

@@ -143,13 +143,15 @@ __device__ inline void edge_corners(int e, int& p, int& q)
 // Corners of the cell with lowest corner at local cell l of brick `brick`:
 // global cell c, and whether all eight corners are optimised (then slot[] and
 // the values f[] are filled).
+template <int kB>
 __device__ inline bool optimised_cell(const Band& B, const ShapeDesc& s, int32_t brick, int32_t l, int32_t c[3],
                                       const float* __restrict__ field, float f[8])
 {
+    using G = Geo<kB>;
     const BrickInfo bi = B.bricks[brick];
-    c[0] = bi.bx * kBrick + (l >> 6);
-    c[1] = bi.by * kBrick + ((l >> 3) & 7);
-    c[2] = bi.bz * kBrick + (l & 7);
+    c[0] = bi.bx * kB + (l >> (2 * G::S));
+    c[1] = bi.by * kB + ((l >> G::S) & G::M);
+    c[2] = bi.bz * kB + (l & G::M);
     if (c[0] >= s.R[0] || c[1] >= s.R[1] || c[2] >= s.R[2]) return false;
 #pragma unroll
     for (int a = 0; a < 2; ++a)
@@ -158,11 +160,11 @@ __device__ inline bool optimised_cell(const Band& B, const ShapeDesc& s, int32_t
 #pragma unroll
             for (int d = 0; d < 2; ++d) {
                 const int32_t i = c[0] + a, j = c[1] + b, k = c[2] + d;
-                const int32_t br = brick_of(B, s, i >> 3, j >> 3, k >> 3);
+                const int32_t br = brick_of(B, s, i >> G::S, j >> G::S, k >> G::S);
                 if (br < 0) return false;
-                const int32_t loc = local_index(i, j, k);
-                if (!mask_bit(B.m_v, br, loc)) return false;
-                f[4 * a + 2 * b + d] = field[(int64_t)br * kBrickVol + loc];
+                const int32_t loc = local_index_b<kB>(i, j, k);
+                if (!mask_bit_b<kB>(B.m_v, br, loc)) return false;
+                f[4 * a + 2 * b + d] = field[(int64_t)br * G::V + loc];
             }
     return true;
 }
@@ -183,16 +185,18 @@ __device__ inline int32_t corner_class(const float f[8])
     return cls;
 }
 
+template <int kB>
 __global__ void k_surf_count(Band B, int32_t shape, const float* __restrict__ field, int32_t method,
                              int32_t* __restrict__ count)
 {
     const ShapeDesc& s = B.shapes[shape];
-    const int64_t n = (s.brick_end - s.brick_begin) * kBrickVol;
+    const int64_t n = (s.brick_end - s.brick_begin) * Geo<kB>::V;
     for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < n; g += (int64_t)gridDim.x * blockDim.x) {
         int32_t c[3];
         float f[8];
         int32_t m = 0;
-        if (optimised_cell(B, s, (int32_t)(s.brick_begin + g / kBrickVol), (int32_t)(g % kBrickVol), c, field, f)) {
+        if (optimised_cell<kB>(B, s, (int32_t)(s.brick_begin + g / Geo<kB>::V), (int32_t)(g % Geo<kB>::V), c, field,
+                               f)) {
             if (method == 0) m = kMc.n[corner_class(f)];
             else
                 for (int t = 0; t < 6; ++t) m += tet_count(f, t);
@@ -213,18 +217,20 @@ __device__ inline void edge_point(const double P[8][3], const double fd[8], int 
     }
 }
 
+template <int kB>
 __global__ void k_surf_emit(Band B, int32_t shape, const float* __restrict__ field, int32_t method,
                             const int32_t* __restrict__ offset, float* __restrict__ xyz, int64_t* __restrict__ key,
                             int32_t* __restrict__ idx)
 {
 #pragma clang fp contract(off)
     const ShapeDesc& s = B.shapes[shape];
-    const int64_t n = (s.brick_end - s.brick_begin) * kBrickVol;
+    const int64_t n = (s.brick_end - s.brick_begin) * Geo<kB>::V;
     for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < n; g += (int64_t)gridDim.x * blockDim.x) {
         if (offset[g + 1] == offset[g]) continue;
         int32_t c[3];
         float f[8];
-        if (!optimised_cell(B, s, (int32_t)(s.brick_begin + g / kBrickVol), (int32_t)(g % kBrickVol), c, field, f))
+        if (!optimised_cell<kB>(B, s, (int32_t)(s.brick_begin + g / Geo<kB>::V), (int32_t)(g % Geo<kB>::V), c, field,
+                                f))
             continue;
         double P[8][3], fd[8];
 #pragma unroll
@@ -319,7 +325,7 @@ gp_status gp_extract_surface_impl(gp_ctx ctx, int32_t shape, const float* field,
 {
     *n_out = 0;
     const ShapeDesc& d = ctx->h_shapes[shape];
-    const int64_t n = (d.brick_end - d.brick_begin) * kBrickVol;
+    const int64_t n = (d.brick_end - d.brick_begin) * ((int64_t)ctx->brick * ctx->brick * ctx->brick);
     if (n == 0) return GP_OK;
     if (n >= ((int64_t)1 << 31)) return gp_fail(ctx, GP_ERR_CAPACITY, "too many cells for the surface pass");
     hipStream_t st = ctx->stream;
@@ -328,7 +334,9 @@ gp_status gp_extract_surface_impl(gp_ctx ctx, int32_t shape, const float* field,
     if (count.alloc(n + 1) != hipSuccess || offset.alloc(n + 1) != hipSuccess)
         return gp_fail(ctx, GP_ERR_OOM, "out of device memory for the surface pass");
     GP_HIP(ctx, hipMemsetAsync(count.p + n, 0, sizeof(int32_t), st));
-    k_surf_count<<<blocks_for(n), kThreads, 0, st>>>(B, shape, field, method, count.p);
+    with_brick(ctx->brick, [&](auto tag) {
+        k_surf_count<decltype(tag)::value><<<blocks_for(n), kThreads, 0, st>>>(B, shape, field, method, count.p);
+    });
     GP_HIP(ctx, hipGetLastError());
     size_t need = 0;
     GP_HIP(ctx, hipcub::DeviceScan::ExclusiveSum(nullptr, need, count.p, offset.p, (int)(n + 1), st));
@@ -350,7 +358,10 @@ gp_status gp_extract_surface_impl(gp_ctx ctx, int32_t shape, const float* field,
     if (xyz.alloc((size_t)total * 9) != hipSuccess || key.alloc(total) != hipSuccess ||
         idx.alloc(total) != hipSuccess || order.alloc(total) != hipSuccess)
         return gp_fail(ctx, GP_ERR_OOM, "out of device memory for the surface pass");
-    k_surf_emit<<<blocks_for(n), kThreads, 0, st>>>(B, shape, field, method, offset.p, xyz.p, key.p, idx.p);
+    with_brick(ctx->brick, [&](auto tag) {
+        k_surf_emit<decltype(tag)::value><<<blocks_for(n), kThreads, 0, st>>>(B, shape, field, method, offset.p, xyz.p,
+                                                                            key.p, idx.p);
+    });
     GP_HIP(ctx, hipGetLastError());
     size_t need2 = 0;
     GP_HIP(ctx, hipcub::DeviceRadixSort::SortPairs(nullptr, need2, key.p, tri_key, idx.p, order.p, total, 0, 64, st));

@@ -46,8 +46,9 @@ class Problem:
     """All shapes of one batch in one context (n_shapes = 1 for a single shape)."""
 
     def __init__(self, shapes: Sequence[ShapeSpec], m1: int = 3, m2: int = 3,
-                 weights=(1.0, 1.0, 0.005), device: int = 0, adam: Optional[AdamConfig] = None):
+                 weights=(1.0, 1.0, 0.005), device: int = 0, adam: Optional[AdamConfig] = None, brick: int = 8):
         self.device = torch.device("cuda", device)
+        self.brick = int(brick)
         self.specs = list(shapes)
         self.weights = tuple(float(x) for x in weights)
         self.adam = adam or AdamConfig()
@@ -88,7 +89,8 @@ class Problem:
                 self.sigma_const = 0.0
         with torch.cuda.device(dev):
             self.ctx = gp.gp_create(device)
-            self.n_slots, self.n_active = gp.gp_build_band(self.ctx, shp, self.px, self.py, self.pz, m1, m2, 8)
+            self.n_slots, self.n_active = gp.gp_build_band(self.ctx, shp, self.px, self.py, self.pz, m1, m2,
+                                                           self.brick)
             self.slot_begin = gp.gp_shape_slots(self.ctx, self.n_shapes)
         n = max(self.n_slots, 1)
         self.field = torch.zeros(n, dtype=torch.float32, device=dev)

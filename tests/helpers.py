@@ -12,10 +12,10 @@ def log(*a):
     sys.stdout.flush()
 
 
-def make_problem(specs, m1=3, m2=3, weights=(1.0, 1.0, 0.005), adam=None):
+def make_problem(specs, m1=3, m2=3, weights=(1.0, 1.0, 0.005), adam=None, brick=8):
     from paper_2308_13175_amd.problem import Problem
 
-    return Problem(specs, m1=m1, m2=m2, weights=weights, adam=adam)
+    return Problem(specs, m1=m1, m2=m2, weights=weights, adam=adam, brick=brick)
 
 
 def spec(points, dom, n_queries, sigma):

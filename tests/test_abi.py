@@ -78,9 +78,10 @@ def test_state_and_argument_errors():
         pts = torch.tensor([[0.1, 0.2, 0.3], [0.5, -0.5, 0.25]], device="cuda")
         px, py, pz = [pts[:, a].contiguous() for a in range(3)]
         good = gp.make_shape(dom.dims, dom.lo, dom.hi, 0, 2, 0, 4)
-        with pytest.raises(gp.GridPullError) as e:
-            gp.gp_build_band(ctx, [good], px, py, pz, 3, 3, brick=4)
-        assert e.value.status == 1
+        for brick in (0, 2, 6, 32):
+            with pytest.raises(gp.GridPullError) as e:
+                gp.gp_build_band(ctx, [good], px, py, pz, 3, 3, brick=brick)
+            assert e.value.status == 1        # brick edge not 4, 8 or 16
         with pytest.raises(gp.GridPullError) as e:
             gp.gp_build_band(ctx, [gp.make_shape((0, 8, 8), dom.lo, dom.hi, 0, 2, 0, 4)], px, py, pz, 3, 3)
         assert e.value.status == 1
