@@ -321,23 +321,31 @@ def batched_record(args):
     return rec
 
 
-def build_problem(config: int):
-    import numpy as np
-
+def make_workload(config: int):
+    """The synthetic workload of a configuration, its shape specifications and Adam settings."""
     from paper_2308_13175_amd import synth
-    from paper_2308_13175_amd.problem import AdamConfig, Problem, spec_from_synth
+    from paper_2308_13175_amd.problem import AdamConfig, spec_from_synth
 
     t0 = time.perf_counter()
     wl = synth.WORKLOADS[config]()
     log("inputs: %s, %d points, %d queries/step (%.1f s)" % (wl.name, wl.n_points, wl.n_queries,
                                                               time.perf_counter() - t0))
     adam = AdamConfig(lr0=wl.lr0(), eps=1e-8 * (5e4 / max(wl.n_queries, 1)))
-    specs = [spec_from_synth(s) for s in wl.shapes]
+    return wl, [spec_from_synth(s) for s in wl.shapes], adam
+
+
+def build_problem(config: int, brick: int = 8, made=None):
+    """The configuration's problem with bricks of the given edge (made: the
+    result of make_workload, to build from the same inputs again)."""
+    from paper_2308_13175_amd import synth
+    from paper_2308_13175_amd.problem import Problem
+
+    wl, specs, adam = made if made is not None else make_workload(config)
     import torch
 
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    prob = Problem(specs, m1=wl.m1, m2=wl.m2, adam=adam)
+    prob = Problem(specs, m1=wl.m1, m2=wl.m2, adam=adam, brick=brick)
     torch.cuda.synchronize()
     setup_ms = (time.perf_counter() - t0) * 1e3
     if config == 1:
@@ -734,16 +742,24 @@ def main():
     if args.surface:
         surface_runs()
         return
-    wl, prob, setup_ms = build_problem(args.config)
+    made = make_workload(args.config)
+    brick_rec = None
+    brick = 8
+    if not args.no_autotune:
+        cache = tuning.DEFAULT_CACHE if args.tuning_cache is None else (
+            None if args.tuning_cache == "none" else args.tuning_cache)
+        brick_rec = tuning.choose_brick(made[1], made[0].m1, made[0].m2, made[2], cache_path=cache)
+        brick = brick_rec["brick"]
+        log("brick (%s): %s" % (brick_rec["source"], brick_rec))
+    wl, prob, setup_ms = build_problem(args.config, brick, made)
     Q, J = prob.n_queries, prob.n_points
-    log("band: %d slots, %d optimised vertices, setup %.1f ms" % (prob.n_slots, prob.n_active, setup_ms))
+    log("band: %d slots, %d optimised vertices, bricks of %d^3, setup %.1f ms" % (prob.n_slots, prob.n_active,
+                                                                                  brick, setup_ms))
 
     for _ in range(args.warmup):
         prob.iteration(None)
     tuned = None
     if not args.no_autotune:
-        cache = tuning.DEFAULT_CACHE if args.tuning_cache is None else (
-            None if args.tuning_cache == "none" else args.tuning_cache)
         tuned = tuning.tune(prob, cache)
         log("tuning (%s, %s): %s" % (tuned["key"], tuned["source"], tuned))
     nn_params = gp.gp_get_nn_params(prob.ctx)
@@ -796,7 +812,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": wl.name, "shapes": len(wl.shapes), "points": J, "queries_per_step": Q,
+        "config": {"workload": wl.name, "shapes": len(wl.shapes), "points": J, "queries_per_step": Q, "brick": brick,
                    "grid": [list(s.domain.dims) for s in wl.shapes][:4], "m1": wl.m1, "m2": wl.m2,
                    "slots": prob.n_slots, "optimised_vertices": V, "tv_vertices": V2,
                    "step": "forward+backward (gp_pull_forward_backward) on resident queries and nearest points"},
@@ -810,7 +826,9 @@ def main():
         "iteration": {"step": "sample+nn+forward+backward+adam", **it},
         "nn": {"queries_per_s": Q / (nn_ms * 1e-3) if nn_ms else None, "ms": nn_ms,
                "search_shape": list(nn_params), "search_grid_levels": nn_grids},
-        "tuning": {"nn": list(nn_params), "grad": list(grad_params),
+        "tuning": {"brick": brick, "brick_source": brick_rec["source"] if brick_rec else "default",
+                   "brick_ms": brick_rec.get("brick_ms") if brick_rec else None,
+                   "nn": list(nn_params), "grad": list(grad_params),
                    "key": tuned["key"] if tuned else None, "source": tuned["source"] if tuned else "defaults",
                    "nn_ms": tuned.get("nn_ms") if tuned else None,
                    "grad_ms": tuned.get("grad_ms") if tuned else None},

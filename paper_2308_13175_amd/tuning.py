@@ -1,17 +1,20 @@
 """Autotuning of a problem's launch settings, with a persistent cache.
 
-Two groups of settings change only the speed, never the result:
-- the nearest-neighbour search grid and search shape (gp_autotune_nn), and
+Three groups of settings change only the speed, never the result:
+- the band's brick size (4, 8 or 16 vertices per edge; it fixes the field
+  layout, so it is chosen before the problem is built: `choose_brick` builds
+  the problem with each size and times its forward + backward);
+- the nearest-neighbour search grid and search shape (gp_autotune_nn);
 - the gradient pass's LDS window and the TV kernels' layouts (gp_autotune_grad).
 
-`tune` times them on the problem's own inputs: the search on the query samples
-of a few iterations (the sample moves the best shape, so each shape the tuner
-picks on one sample is timed on all of them and the best mean kept), then the
-gradient pass on the last sample.  The choice is stored in a JSON file under a
-key made of the GPU architecture and the problem's size class (queries per
-iteration and bricks, each rounded to a power of two, and whether it is a
-batch), and a later problem of the same class takes it from there without
-timing anything.
+`tune` times the last two on the problem's own inputs: the search on the
+query samples of a few iterations (the sample moves the best shape, so each
+shape the tuner picks on one sample is timed on all of them and the best mean
+kept), then the gradient pass on the last sample.  The choices are stored in
+a JSON file under a key made of the GPU architecture and the problem's size
+class (queries per iteration and points, each rounded to a power of two, and
+whether it is a batch), and a later problem of the same class takes them from
+there without timing anything.
 """
 from __future__ import annotations
 
@@ -26,11 +29,19 @@ from . import gridpull as gp
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "gridpull", "tuning.json")
 
 
-def size_class(n_queries: int, n_bricks: int, n_shapes: int) -> str:
-    """Queries per iteration and bricks as the nearest powers of two, and single or batch."""
+def size_class(n_queries: int, n_points: int, n_shapes: int) -> str:
+    """Queries per iteration and points as the nearest powers of two, and single or batch
+    (all known before the band is built, and the same for every brick size)."""
     q = int(round(math.log2(max(int(n_queries), 1))))
-    b = int(round(math.log2(max(int(n_bricks), 1))))
-    return "q2^%d-b2^%d-%s" % (q, b, "batch" if n_shapes > 1 else "single")
+    p = int(round(math.log2(max(int(n_points), 1))))
+    return "q2^%d-p2^%d-%s" % (q, p, "batch" if n_shapes > 1 else "single")
+
+
+def class_key(specs, device: int = 0) -> str:
+    """The cache key of a batch of shape specifications."""
+    nq = sum(int(s.n_queries) for s in specs)
+    npts = sum(len(s.points) for s in specs)
+    return "%s|%s" % (arch_name(device), size_class(nq, npts, len(specs)))
 
 
 def arch_name(device: int = 0) -> str:
@@ -69,8 +80,60 @@ def save_cache(path: str, data: Dict[str, dict]) -> None:
 
 def apply(prob, entry: dict) -> None:
     """Put a cache entry's settings into the problem's context."""
-    gp.gp_set_nn_params(prob.ctx, *entry["nn"])
-    gp.gp_set_grad_params(prob.ctx, *entry["grad"])
+    if "nn" in entry:
+        gp.gp_set_nn_params(prob.ctx, *entry["nn"])
+    if "grad" in entry:
+        gp.gp_set_grad_params(prob.ctx, *entry["grad"])
+
+
+def _fwd_bwd_ms(prob, reps: int) -> float:
+    import torch
+
+    prob.forward_backward()
+    torch.cuda.synchronize()
+    best = None
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        prob.forward_backward()
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        best = ms if best is None else min(best, ms)
+    return best
+
+
+def choose_brick(specs, m1: int, m2: int, adam=None, weights=(1.0, 1.0, 0.005),
+                 cache_path: Optional[str] = DEFAULT_CACHE, candidates=(4, 8, 16), reps: int = 5) -> dict:
+    """The brick size for this batch: from the cache when its class is there,
+    else each candidate's problem is built (small-sphere field, the queries of
+    iteration 1 and their nearest points) and its forward + backward timed
+    (the smallest of reps); the fastest is stored.  Returns {"key", "brick",
+    "source", and when timed "brick_ms": {size: ms}}."""
+    import torch
+
+    from .problem import Problem
+
+    key = class_key(specs)
+    cache = load_cache(cache_path) if cache_path else {}
+    if key in cache and "brick" in cache[key]:
+        return {"key": key, "brick": int(cache[key]["brick"]), "source": "cache"}
+    times = {}
+    for b in candidates:
+        prob = Problem(specs, m1=m1, m2=m2, weights=weights, adam=adam, brick=b)
+        prob.init_sphere()
+        prob.sample(0, 1)
+        prob.nearest()
+        times[b] = _fwd_bwd_ms(prob, reps)
+        prob.close()
+        del prob
+        torch.cuda.empty_cache()
+    best = min(times, key=times.get)
+    if cache_path:
+        cache = load_cache(cache_path)
+        cache.setdefault(key, {})["brick"] = best
+        save_cache(cache_path, cache)
+    return {"key": key, "brick": best, "source": "tuned", "brick_ms": {str(b): t for b, t in times.items()}}
 
 
 def _nn_mean_ms(prob, samples: int) -> float:
@@ -120,11 +183,10 @@ def tune(prob, cache_path: Optional[str] = DEFAULT_CACHE, samples: int = 3, reps
 
     Returns {"key", "source" ("cache" or "tuned"), "nn", "grad", and, when
     timed, "nn_ms" and "grad_ms"}."""
-    key = "%s|%s" % (arch_name(prob.device.index or 0),
-                     size_class(prob.n_queries, prob.n_slots // 512, len(prob.specs)))
+    key = class_key(prob.specs, prob.device.index or 0)
     cache = load_cache(cache_path) if cache_path else {}
-    if key in cache:
-        entry = cache[key]
+    if key in cache and "nn" in cache[key] and "grad" in cache[key]:
+        entry = {k: cache[key][k] for k in ("nn", "grad")}
         apply(prob, entry)
         prob.sample(0, samples)
         prob.nearest()
@@ -136,6 +198,6 @@ def tune(prob, cache_path: Optional[str] = DEFAULT_CACHE, samples: int = 3, reps
     entry = {"nn": list(gp.gp_get_nn_params(prob.ctx)), "grad": list(grad)}
     if cache_path:
         cache = load_cache(cache_path)
-        cache[key] = entry
+        cache.setdefault(key, {}).update(entry)
         save_cache(cache_path, cache)
     return {"key": key, "source": "tuned", **entry, "nn_ms": nn_ms, "grad_ms": list(grad_ms)}

@@ -27,7 +27,7 @@ def test_tune_then_read_from_cache(tmp_path):
     log("case: tuning, first problem (tuned and stored)")
     prob, dom, pts = _problem()
     first = tuning.tune(prob, path, samples=2, reps=1)
-    assert first["source"] == "tuned" and first["key"].endswith("|q2^16-b2^7-single")
+    assert first["source"] == "tuned" and first["key"].endswith("|q2^16-p2^13-single")
     assert tuning.load_cache(path)[first["key"]] == {"nn": first["nn"], "grad": first["grad"]}
     assert list(gp.gp_get_nn_params(prob.ctx)) == first["nn"]
     assert list(gp.gp_get_grad_params(prob.ctx)) == first["grad"]
