@@ -520,9 +520,10 @@ def surface_runs(iters: int = 1600, n_queries: int = 50_000):
         torch.cuda.empty_cache()
 
 
-def _window(dom, pts, cells: int):
+def _window(dom, pts, cells: int, centre=None):
     """A sub-grid of cells^3 cells of dom (same cell size and vertex lattice)
-    around the densest region of the points, and the points inside it."""
+    around a point (centre; by default the densest region of the points), and
+    the points inside it."""
     import numpy as np
 
     from paper_2308_13175_amd import synth
@@ -533,33 +534,41 @@ def _window(dom, pts, cells: int):
     lo = np.asarray(dom.lo, np.float64)
     h = np.asarray(dom.h, np.float64)
     w = np.minimum(R, cells)
-    c = np.clip(np.floor((pts.astype(np.float64) - lo) / h), 0, R - 1).astype(np.int64)
-    # the coarse block (of the window's size) holding the most points
-    blk = c // w
-    nb = (R + w - 1) // w
-    ids, cnt = np.unique((blk[:, 0] * nb[1] + blk[:, 1]) * nb[2] + blk[:, 2], return_counts=True)
-    b = ids[np.argmax(cnt)]
-    b3 = np.array([b // (nb[1] * nb[2]), (b // nb[2]) % nb[1], b % nb[2]])
-    c0 = np.minimum(b3 * w, R - w)
+    if centre is None:
+        c = np.clip(np.floor((pts.astype(np.float64) - lo) / h), 0, R - 1).astype(np.int64)
+        # the coarse block (of the window's size) holding the most points
+        blk = c // w
+        nb = (R + w - 1) // w
+        ids, cnt = np.unique((blk[:, 0] * nb[1] + blk[:, 1]) * nb[2] + blk[:, 2], return_counts=True)
+        b = ids[np.argmax(cnt)]
+        b3 = np.array([b // (nb[1] * nb[2]), (b // nb[2]) % nb[1], b % nb[2]])
+        c0 = np.minimum(b3 * w, R - w)
+    else:
+        cc = np.clip(np.floor((np.asarray(centre, np.float64) - lo) / h), 0, R - 1).astype(np.int64)
+        c0 = np.clip(cc - w // 2, 0, R - w)
     wlo = lo + c0 * h
     whi = lo + (c0 + w) * h
     sub = synth.Domain(tuple(int(x) for x in w), tuple(float(x) for x in wlo), tuple(float(x) for x in whi))
-    inside = np.all((pts >= wlo.astype(np.float32)) & (pts <= whi.astype(np.float32)), axis=1)
+    # in the window's own cell units, with a margin against rounding at its faces
+    u = (pts.astype(np.float64) - wlo) / ((whi - wlo) / w)
+    inside = np.all((u >= 1e-7) & (u <= w - 1e-7), axis=1)
     return sub, pts[inside]
 
 
-def cpu_baseline(wl, v2_total: int, budget_s: float = 16.0, window_cells: int = 160):
+def cpu_baseline(wl, v2_total: int, n_windows: int = 8, window_cells: int = 160, max_queries: int = 1_000_000):
     """The FP64 oracle on one host thread, on a bounded sample of the workload,
     in the metric's unit (forward + backward queries/s).
 
-    Shape 0 of the workload; a grid larger than window_cells^3 cells is cut to
-    a window of that many cells (same cell size) around its densest points.
-    The oracle's loss and gradient are timed on as many of the window's
-    queries as fit the budget, and its query-independent part (TV over the
-    band, gradient clear) once; both are scaled to the full workload: queries
-    per step, and v2_total TV vertices (the workload's band, counted on the
-    library's band, which equals the oracle's).  Brute-force nearest points and Adam are timed
-    too and reported beside it.
+    Shape 0 of the workload, cut (when its grid is larger) to n_windows windows
+    of window_cells^3 cells (same cell size): one around its densest points,
+    the others around points drawn at random (seeded).  In each window the
+    oracle's loss and gradient are timed on the window's share of the
+    workload's queries (at most max_queries), and its query-independent part
+    (TV over the window's band, gradient clear) once.  The per-query time
+    (all windows' queries together) is scaled to the workload's queries per
+    step, and the query-independent time to its v2_total TV vertices (counted
+    on the library's band, which equals the oracle's).  Brute-force nearest
+    points and Adam are timed too and reported beside it.
     """
     import numpy as np
 
@@ -567,41 +576,45 @@ def cpu_baseline(wl, v2_total: int, budget_s: float = 16.0, window_cells: int = 
     from paper_2308_13175_amd import synth
 
     s = wl.shapes[0]
-    sub, pts = _window(s.domain, s.points, window_cells)
     Q = wl.n_queries
-    frac_q = len(pts) / max(len(s.points), 1)
-    n_q = max(1000, int(min(s.n_queries * frac_q, 2_000_000)))
-    q_all = synth.host_queries(pts, n_q, s.sigma if np.ndim(s.sigma) == 0 else float(np.median(s.sigma)), seed=99)
-    t0 = time.perf_counter()
-    cf, vf = oracle.build_band(sub.dims, sub.lo, sub.hi, pts, wl.m1, wl.m2)
-    t_band = time.perf_counter() - t0
-    v2_window = int(np.count_nonzero(vf & 2))
-    # small-sphere initial field at the full domain's centre (its cost is what matters)
-    dom = s.domain
-    ctr = [0.5 * (dom.lo[a] + dom.hi[a]) for a in range(3)]
-    vx, vy, vz = sub.vdims
-    xs = sub.lo[0] + np.arange(vx) * sub.h[0] - ctr[0]
-    ys = sub.lo[1] + np.arange(vy) * sub.h[1] - ctr[1]
-    zs = sub.lo[2] + np.arange(vz) * sub.h[2] - ctr[2]
-    D = (np.sqrt(xs[:, None, None] ** 2 + ys[None, :, None] ** 2 + zs[None, None, :] ** 2)
-         - 2 * min(sub.h)).reshape(-1)
-    # the query-independent part: no queries
-    empty = np.zeros((0, 3), np.float32)
-    t0 = time.perf_counter()
-    oracle.loss_grad(sub.dims, sub.lo, sub.hi, cf, vf, D, empty, np.zeros(0, np.int32), pts)
-    t_fixed = time.perf_counter() - t0
-    nn_l = oracle.nn_exact(q_all, pts)
-    # per-query part: as many queries as fit about half the budget
-    n = 2000
-    while True:
+    sigma = s.sigma if np.ndim(s.sigma) == 0 else float(np.median(s.sigma))
+    whole = bool(np.all(np.asarray(s.domain.dims) <= window_cells))
+    rng = np.random.default_rng(7)
+    centres = [None] if whole else [None] + [s.points[i] for i in
+                                             rng.choice(len(s.points), n_windows - 1, replace=False)]
+    t_q_sum = t_fixed_sum = t_band_sum = 0.0
+    n_q_sum = v2_sum = n_pts_sum = 0
+    for wi, centre in enumerate(centres):
+        sub, pts = _window(s.domain, s.points, window_cells, centre)
+        n_q = max(1000, int(min(s.n_queries * len(pts) / max(len(s.points), 1), max_queries)))
+        q = synth.host_queries(pts, n_q, sigma, seed=99 + wi)
         t0 = time.perf_counter()
-        oracle.loss_grad(sub.dims, sub.lo, sub.hi, cf, vf, D, q_all[:n], nn_l[:n], pts)
-        t = time.perf_counter() - t0 - t_fixed
-        if t > 0.25 * budget_s or n >= len(q_all):
-            break
-        n = min(len(q_all), int(n * max(2.0, 0.5 * budget_s / max(t, 1e-3))))
-    t_q = max(t, 0.0) / n
-    t_fb = Q * t_q + t_fixed * (v2_total / max(v2_window, 1))
+        cf, vf = oracle.build_band(sub.dims, sub.lo, sub.hi, pts, wl.m1, wl.m2)
+        t_band_sum += time.perf_counter() - t0
+        # small-sphere initial field at the full domain's centre (its cost is what matters)
+        dom = s.domain
+        ctr = [0.5 * (dom.lo[a] + dom.hi[a]) for a in range(3)]
+        vx, vy, vz = sub.vdims
+        xs = sub.lo[0] + np.arange(vx) * sub.h[0] - ctr[0]
+        ys = sub.lo[1] + np.arange(vy) * sub.h[1] - ctr[1]
+        zs = sub.lo[2] + np.arange(vz) * sub.h[2] - ctr[2]
+        D = (np.sqrt(xs[:, None, None] ** 2 + ys[None, :, None] ** 2 + zs[None, None, :] ** 2)
+             - 2 * min(sub.h)).reshape(-1)
+        # the query-independent part: no queries
+        empty = np.zeros((0, 3), np.float32)
+        t0 = time.perf_counter()
+        oracle.loss_grad(sub.dims, sub.lo, sub.hi, cf, vf, D, empty, np.zeros(0, np.int32), pts)
+        t_fixed = time.perf_counter() - t0
+        nn_l = oracle.nn_exact(q, pts)
+        t0 = time.perf_counter()
+        oracle.loss_grad(sub.dims, sub.lo, sub.hi, cf, vf, D, q, nn_l, pts)
+        t_q_sum += max(time.perf_counter() - t0 - t_fixed, 0.0)
+        t_fixed_sum += t_fixed
+        n_q_sum += n_q
+        v2_sum += int(np.count_nonzero(vf & 2))
+        n_pts_sum += len(pts)
+    t_q = t_q_sum / max(n_q_sum, 1)
+    t_fb = Q * t_q + t_fixed_sum * (v2_total / max(v2_sum, 1))
     # nearest points by brute force over all of shape 0's points, a few queries
     full_q = synth.host_queries(s.points, 64, s.sigma if np.ndim(s.sigma) == 0 else float(np.median(s.sigma)),
                                 seed=98)
@@ -631,11 +644,12 @@ def cpu_baseline(wl, v2_total: int, budget_s: float = 16.0, window_cells: int = 
         "host_cpu": model,
         "host_threads": os.cpu_count(),
         "kind": "oracle",
-        "sample": ("FP64 oracle, 1 thread, shape 0 of %s cut to a %s-cell window (%d points, band built in %.1f s): "
-                   "loss and gradient on %d queries (%.3g s/query) plus the query-independent TV and gradient "
-                   "clear over the window's %d TV vertices (%.3g s), scaled to %d queries per step and %.3g TV "
-                   "vertices" % (wl.name, "x".join(str(x) for x in sub.dims), len(pts), t_band, n, t_q,
-                                 v2_window, t_fixed, Q, float(v2_total))),
+        "sample": ("FP64 oracle, 1 thread, shape 0 of %s in %d window(s) of %s cells (one around the densest "
+                   "points, the others around random points; %d points in all, bands built in %.1f s): loss and "
+                   "gradient on %d queries (%.3g s/query) plus the query-independent TV and gradient clear over "
+                   "the windows' %d TV vertices (%.3g s), scaled to %d queries per step and %.3g TV vertices"
+                   % (wl.name, len(centres), "x".join(str(x) for x in sub.dims), n_pts_sum, t_band_sum, n_q_sum,
+                      t_q, v2_sum, t_fixed_sum, Q, float(v2_total))),
         "nn_bruteforce_s_per_query": t_nn,
         "nn_bruteforce_points": len(s.points),
         "adam_s_per_vertex": t_adam / max(len(D), 1),
