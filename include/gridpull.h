@@ -249,13 +249,16 @@ gp_status gp_set_tv_layout(gp_ctx ctx, int32_t layout);
  * field) and of the TV kernels (Eq. 5); every value gives the same
  * arithmetic, only the speed changes (and, through the order of float
  * atomics between blocks, the last bits of the gradient).
- *   window_cap:         LDS window of a query block, in vertices: 2304, 4608
- *                       (default) or 6912 (8 bytes each: 18, 36 or 54 KB of
- *                       LDS per 256-query block, so fewer blocks per CU);
+ *   window_cap:         LDS accumulators of a query block, in vertices:
+ *                       2048, 4096 (default) or 6144 (8 bytes each, in rows
+ *                       of 16 consecutive slots: 16, 32 or 48 KB, plus 4 KB
+ *                       of line map, per 256-query block; the largest leaves
+ *                       fewer blocks per CU).  A block touching more 16-slot
+ *                       lines than there are rows takes them in turns;
  *   window_max_passes:  [1, 64], default 16: a block whose box of query and
- *                       nearest-point cells needs more slab passes through
- *                       the window adds its contributions straight to the
- *                       gradient with global atomics;
+ *                       nearest-point cells needs more slabs (whole x layers
+ *                       of at most 2048 lines) adds its contributions
+ *                       straight to the gradient with global atomics;
  *   tv_forward_wave_from, tv_backward_wave_from: >= 0; from this many
  *                       bricks on, the TV forward (backward) takes one wave
  *                       per brick, below it one block (defaults 2048, 16384).
@@ -276,7 +279,7 @@ gp_status gp_get_grad_params(gp_ctx ctx, gp_grad_params* params);
  * Autotuner of gp_grad_params (the passes that evaluate Eq. 4-8 and scatter
  * their derivative) on the caller's queries, nearest points and field
  * (arguments as gp_pull_forward_backward): times the fused query pass
- * for window_cap in {2304, 4608, 6912} x window_max_passes in {4, 16, 64},
+ * for window_cap in {2048, 4096, 6144} x window_max_passes in {4, 16, 64},
  * then the TV forward and the TV backward in each layout at the band's size
  * (the faster one moves its threshold to the band's brick count, so that
  * bands at least as large take the wave layout, or just above it).  Each

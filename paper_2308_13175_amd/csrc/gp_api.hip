@@ -285,7 +285,7 @@ gp_status gp_set_grad_params(gp_ctx ctx, const gp_grad_params* params)
     if (!params) return gp_fail(ctx, GP_ERR_ARG, "null params");
     bool cap_ok = false;
     for (int32_t c : gp::kWinCaps) cap_ok = cap_ok || params->window_cap == c;
-    if (!cap_ok) return gp_fail(ctx, GP_ERR_ARG, "window_cap must be 2304, 4608 or 6912");
+    if (!cap_ok) return gp_fail(ctx, GP_ERR_ARG, "window_cap must be 2048, 4096 or 6144");
     if (params->window_max_passes < 1 || params->window_max_passes > gp::kWinPassesMax)
         return gp_fail(ctx, GP_ERR_ARG, "window_max_passes must be in [1, 64]");
     if (params->tv_forward_wave_from < 0 || params->tv_backward_wave_from < 0)

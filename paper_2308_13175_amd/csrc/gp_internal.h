@@ -108,16 +108,16 @@ constexpr int32_t kNnShellMax = 4;
 constexpr int32_t kNnCellPointsMax = 65536;
 
 // Settings of the gradient pass and the TV kernels (any values give the same
-// arithmetic; only the speed changes): the LDS window of the query pass in
-// vertices (kWinCaps; 8 bytes each, allocated at launch), the most slab
-// passes a block takes before its contributions go straight to the gradient,
-// and the band sizes (bricks) from which the TV forward and backward take one
-// wave per brick instead of one block.
-constexpr int32_t kWinCaps[3] = {2304, 4608, 6912};
-constexpr int32_t kWinCapMax = 6912;
+// arithmetic; only the speed changes): the LDS rows of the query pass in
+// vertices (kWinCaps; 8 bytes each, in rows of 16 consecutive slots,
+// allocated at launch), the most slabs a block takes before its contributions
+// go straight to the gradient, and the band sizes (bricks) from which the TV
+// forward and backward take one wave per brick instead of one block.
+constexpr int32_t kWinCaps[3] = {2048, 4096, 6144};
+constexpr int32_t kWinCapMax = 6144;
 constexpr int32_t kWinPassesMax = 64;
 struct GradParams {
-    int32_t win_cap = 4608;
+    int32_t win_cap = 4096;
     int32_t win_max_passes = 16;
     int64_t tv_fwd_wave_from = 2048;
     int64_t tv_bwd_wave_from = 16384;

@@ -199,191 +199,193 @@ __device__ inline void query_adjoint(const ShapeDesc& s, const QueryState& st, g
 }
 
 // Accumulation of the contributions of a block.  Its queries come from
-// neighbouring points (and bricks are numbered along a Morton curve, so
-// neighbouring points stay neighbours across brick boundaries), so their 16
-// corner contributions each fall in a small box of the grid, the box of the
-// block's query and nearest-point cells.  The block sums them in an LDS
-// window, a dense copy of that box, and adds each non-zero window entry to
-// the gradient once.  A box larger than the window is taken in slabs of
-// whole layers along x or y (whichever makes the smaller cross-section), one
-// pass each: a contribution is added in the pass of its slab.  A box that
-// would take more than the context's maximum number of passes sends its
-// contributions straight to the gradient (global float atomics).  The
-// window's size (in LDS allocated at launch) and that maximum are settings of
-// the context (gp_set_grad_params).
-// The flush walks the window in index order (z fastest), so that the lanes
-// of a wave add to runs of consecutive slots (a z-run is contiguous inside a
-// brick) and clear what they read; the slot of an entry comes from an LDS
-// copy of the directory entries of the slab's bricks.
+// neighbouring points (bricks are numbered along a Morton curve, so
+// neighbouring points stay neighbours across brick faces), so their 16 corner
+// contributions fall in a small box of the grid, the box of the block's query
+// and nearest-point cells, but fill only about a quarter of its vertices: the
+// queries lie in a shell around the surface.  The block therefore sums them
+// in LDS rows of 16 consecutive slots (one 64-byte line of the gradient: in a
+// brick of edge kB, 16 / kB neighbouring y columns of kB vertices each) for
+// the lines it touches only:
+// - a line map, one 16-bit entry per line of the box (ordered by x, then
+//   z-brick, then y line), is marked at every touched line;
+// - each wave numbers the marked entries of its share of the map in map order
+//   (one LDS counter per block, one atomic per wave and step), so the touched
+//   lines get rows 0, 1, ..., lines next to each other in memory mostly on
+//   consecutive rows;
+// - each contribution is added to its entry (slot mod 16) of its line's row,
+//   and the row records its line (slot / 16);
+// - the flush walks the rows in order, 16 lanes per row, so that a wave adds
+//   whole lines, mostly contiguous runs of them, to the gradient (one float
+//   atomic per non-zero entry) and clears what it reads.
+// A block touching more lines than there are rows takes the rows in turns
+// (each turn adds the contributions of its rows and flushes them).  A box with
+// more lines than the map takes slabs of whole x layers, each marked,
+// numbered and flushed on its own; a box that would take more than the
+// context's maximum number of slabs sends its contributions straight to the
+// gradient (global float atomics).  The rows' size (LDS allocated at launch)
+// and that maximum are settings of the context (gp_set_grad_params).
 // The entries hold fixed point with 32 fraction bits in 64-bit integers:
 // integer LDS atomics run at full rate where float ones do not (measured:
-// a float window made the pass several times slower), and the sums inside a
-// block are exact.  A contribution of 2^19 or more in magnitude bypasses the
-// window, so no sum leaves the range of the fixed point (a vertex receives
-// at most 2 contributions from each of the 256 queries).  The conversion
-// adds 1.5 * 2^52 to the scaled value in double: for |v| < 2^51 the sum lies
-// in [2^52, 2^53), where the double's ulp is 1, so the addition rounds v to
-// the nearest integer (ties to even, as a rounding conversion would) and the
+// float accumulators made the pass several times slower), and the sums inside
+// a block are exact and independent of the order of the adds.  A
+// contribution of 2^19 or more in magnitude bypasses the rows, so no sum
+// leaves the range of the fixed point (a vertex receives at most 2
+// contributions from each of the 256 queries).  The conversion adds
+// 1.5 * 2^52 to the scaled value in double: for |v| < 2^51 the sum lies in
+// [2^52, 2^53), where the double's ulp is 1, so the addition rounds v to the
+// nearest integer (ties to even, as a rounding conversion would) and the
 // sum's bits minus those of 1.5 * 2^52 are that integer in two's complement.
-// Directory entries of a slab's bricks (edge kB), at most: a slab of
-// d0 x d1 x d2 <= cap vertices meets at most prod(floor((d_i + kB - 2) / kB) + 1)
-// bricks, largest for 2 x 2 x cap/4 (two bricks on each short axis).
-template <int kB>
-__host__ __device__ constexpr int32_t win_bricks_bound(int32_t cap)
-{
-    return 4 * ((cap / 4 + kB - 2) / kB + 1);
-}
+constexpr int32_t kRowSlots = 16;   // slots per row (one 64-byte line of the gradient)
+constexpr int32_t kLineMap = 2048;  // line-map entries (16 bits each)
 
-// LDS of a query block: the window (cap 64-bit entries), then the slab's
-// brick directory entries.
-template <int kB>
+// LDS of a query block: the rows (cap 64-bit entries), each row's line, then the line map.
 __host__ __device__ constexpr int32_t win_lds_bytes(int32_t cap)
 {
-    return cap * 8 + win_bricks_bound<kB>(cap) * 4;
+    return cap * 8 + (cap / kRowSlots) * 4 + kLineMap * 2;
 }
-static_assert(win_bricks_bound<8>(4608) == 580 && win_bricks_bound<8>(6912) == 868, "slab brick bound");
-static_assert(win_lds_bytes<4>(kWinCapMax) <= 64 * 1024 - 512, "window LDS within one workgroup's 64 KB");
+static_assert(win_lds_bytes(4096) + 512 <= 160 * 1024 / 4, "default rows: four blocks per CU");
+static_assert(win_lds_bytes(kWinCapMax) <= 64 * 1024 - 512, "rows within one workgroup's 64 KB");
 constexpr double kFixScale = 4294967296.0;   // 2^32
 constexpr float kFixLimit = 524288.f;        // 2^19
 constexpr double kFixMagic = 6755399441055744.0;   // 1.5 * 2^52
 
-// The box of a block (vertices lo .. lo + w - 1), its slab axis ax (0 or 1;
-// o = 1 - ax is the other of x and y), the layers of ax per pass and the
-// number of passes (0: no window).
-struct Window {
-    int32_t lo[3];
-    int32_t w[3];
-    int32_t ax;
-    int32_t layers;
-    int32_t passes;
+// Lines of a brick of edge kB: 16 / kB = 2^L neighbouring y columns each.
+template <int kB>
+struct LineGeo {
+    static constexpr int32_t L = 4 - Geo<kB>::S;
 };
 
-__device__ inline Window choose_window(const int32_t box[6], int32_t cap, int32_t max_passes)
+// The box of a block in lines: x vertices lo .. lo + nx - 1, z-bricks
+// zb0 .. zb0 + nzb - 1, y lines yl0 .. yl0 + nyl - 1; the x layers per slab
+// and the number of slabs (0: no rows, the contributions go straight to the
+// gradient).
+struct LineBox {
+    int32_t lo;
+    int32_t nx;
+    int32_t zb0, nzb;
+    int32_t yl0, nyl;
+    int32_t layers;
+    int32_t slabs;
+};
+
+template <int kB>
+__device__ inline LineBox choose_linebox(const int32_t box[6], int32_t max_slabs)
 {
-    Window W;
-    W.passes = 0;
-    W.ax = 0;
-    W.layers = 0;
-    for (int a = 0; a < 3; ++a) {
-        W.lo[a] = box[a];
-        W.w[a] = box[3 + a] - box[a] + 2;
-    }
-    if (box[3] < 0) return W;   // no valid query
-    W.ax = W.w[1] > W.w[0] ? 1 : 0;
-    const int64_t cross = (int64_t)W.w[1 - W.ax] * W.w[2];
-    if (cross > cap) return W;
-    W.layers = (int32_t)min((int64_t)W.w[W.ax], cap / cross);
-    const int32_t passes = (W.w[W.ax] + W.layers - 1) / W.layers;
-    if (passes <= max_passes) W.passes = passes;
-    return W;
+    constexpr int32_t S = Geo<kB>::S, L = LineGeo<kB>::L;
+    LineBox C;
+    C.slabs = 0;
+    C.layers = 0;
+    C.lo = box[0];
+    C.nx = box[3] - box[0] + 2;
+    C.zb0 = box[2] >> S;
+    C.nzb = ((box[5] + 1) >> S) - C.zb0 + 1;
+    C.yl0 = box[1] >> L;
+    C.nyl = ((box[4] + 1) >> L) - C.yl0 + 1;
+    if (box[3] < 0) return C;   // no valid query
+    const int64_t cross = (int64_t)C.nzb * C.nyl;
+    if (cross > kLineMap) return C;
+    C.layers = (int32_t)min((int64_t)C.nx, kLineMap / cross);
+    const int32_t slabs = (C.nx + C.layers - 1) / C.layers;
+    if (slabs <= max_slabs) C.slabs = slabs;
+    return C;
 }
 
-// Index strides of the x and y corners in the window layout ((a * w_o + o) * w_z + z).
-__device__ inline void window_strides(const Window& W, int32_t& sx, int32_t& sy)
+// Line-map index (in the slab of x layers [a0, a1)) of every corner of cell
+// c, or -1 outside the slab.
+template <int kB>
+__device__ inline void line_corners(const LineBox& C, int32_t a0, int32_t a1, const int32_t c[3], int32_t idx[8])
 {
-    const int32_t s_ax = W.w[1 - W.ax] * W.w[2], s_o = W.w[2];
-    sx = W.ax == 0 ? s_ax : s_o;
-    sy = W.ax == 1 ? s_ax : s_o;
-}
-
-// Window index (in the slab of pass layers [a0, a1) along ax) of every
-// corner of cell c, or -1 outside the slab.
-__device__ inline void window_corners(const Window& W, int32_t a0, int32_t a1, const int32_t c[3], int32_t idx[8])
-{
-    int32_t sx, sy;
-    window_strides(W, sx, sy);
-    const int32_t r[3] = {c[0] - W.lo[0], c[1] - W.lo[1], c[2] - W.lo[2]};
-    const int32_t ra = r[W.ax] - a0;   // along the slab axis, relative to the slab
-    const int32_t rx = W.ax == 0 ? ra : r[0], ry = W.ax == 1 ? ra : r[1];
-    const int32_t na = a1 - a0;
-    const int32_t base = rx * sx + ry * sy + r[2];
+    constexpr int32_t S = Geo<kB>::S, L = LineGeo<kB>::L;
+    const int32_t rx = c[0] - C.lo - a0, na = a1 - a0;
+    const int32_t z0 = (c[2] >> S) - C.zb0, z1 = ((c[2] + 1) >> S) - C.zb0;
+    const int32_t y0 = (c[1] >> L) - C.yl0, y1 = ((c[1] + 1) >> L) - C.yl0;
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
-        const int32_t da = W.ax == 0 ? (i >> 2) : ((i >> 1) & 1);
-        const bool in = ra + da >= 0 && ra + da < na;   // the other axes lie inside the box
-        idx[i] = in ? base + (i >> 2) * sx + ((i >> 1) & 1) * sy + (i & 1) : -1;
+        const int32_t x = rx + (i >> 2);
+        const bool in = (uint32_t)x < (uint32_t)na;   // y and z lie inside the box
+        idx[i] = in ? (x * C.nzb + ((i & 1) ? z1 : z0)) * C.nyl + (((i >> 1) & 1) ? y1 : y0) : -1;
     }
 }
 
-// The contributions of one cell: into the window where the corner lies in
-// the current slab (index >= 0); contributions too large for the fixed
-// point go straight to the gradient in pass 0 (bypass).
-__device__ inline void window_add(const int32_t idx[8], const int32_t slot[8], const float v[8], bool first,
-                                  unsigned long long* acc, float* __restrict__ G, float scale)
+// Mark the lines of the corners of cell c that lie in the slab.
+template <int kB>
+__device__ inline void line_mark(const LineBox& C, int32_t a0, int32_t a1, const int32_t c[3], uint16_t* map)
 {
+    int32_t idx[8];
+    line_corners<kB>(C, a0, a1, c, idx);
+#pragma unroll
+    for (int i = 0; i < 8; ++i)
+        if (idx[i] >= 0 && ((i & 1) == 0 || idx[i] != idx[i - 1])) map[idx[i]] = 1;
+}
+
+// Number the marked entries of the map (first n entries): each becomes its
+// row + 1; *cnt ends as the number of rows.  Every thread of the block calls
+// it (a wave's lanes take the same steps).
+__device__ inline void line_number(uint16_t* map, int32_t n, int32_t* cnt)
+{
+    const uint32_t lane = threadIdx.x & 63;
+    for (int32_t i0 = 0; i0 < n; i0 += blockDim.x) {
+        const int32_t i = i0 + (int32_t)threadIdx.x;
+        const bool m = i < n && map[i] != 0;
+        const uint64_t mask = __ballot(m);
+        if (mask == 0) continue;
+        int32_t base = 0;
+        if (lane == 0) base = atomicAdd(cnt, (int32_t)__popcll(mask));
+        base = __builtin_amdgcn_readfirstlane(base);
+        const int32_t below = (int32_t)__builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                                                 __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+        if (m) map[i] = (uint16_t)(base + below + 1);
+    }
+}
+
+// The contributions of one cell whose lines have rows [row0, row0 + nrows)
+// (and lie in the slab): into entry (slot mod 16) of the row, which records
+// its line; contributions too large for the fixed point go straight to the
+// gradient in the block's first turn (bypass).
+template <int kB>
+__device__ inline void line_add(const LineBox& C, int32_t a0, int32_t a1, const int32_t c[3], const int32_t slot[8],
+                                const float v[8], int32_t row0, int32_t nrows, bool first, const uint16_t* map,
+                                unsigned long long* acc, int32_t* rowkey, float* __restrict__ G, float scale)
+{
+    int32_t idx[8];
+    line_corners<kB>(C, a0, a1, c, idx);
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
-        // (converted here, in its pass: kept opaque so that the conversions
-        // are not hoisted out of the pass loop and held as 16 64-bit values)
+        // (converted here, in its turn: kept opaque so that the conversions
+        // are not hoisted out of the loop and held as 16 64-bit values)
         float x = v[i];
         asm volatile("" : "+v"(x));
         const bool big = !(fabsf(x) < kFixLimit);
-        if (idx[i] >= 0 && !big)
-            atomicAdd(&acc[idx[i]], (unsigned long long)(__double_as_longlong(fma((double)x, kFixScale, kFixMagic)) -
-                                                         __double_as_longlong(kFixMagic)));
-        else if (first && big)
+        if (idx[i] >= 0 && !big) {
+            const int32_t row = (int32_t)map[idx[i]] - 1 - row0;
+            if ((uint32_t)row < (uint32_t)nrows) {
+                atomicAdd(&acc[row * kRowSlots + (slot[i] & (kRowSlots - 1))],
+                          (unsigned long long)(__double_as_longlong(fma((double)x, kFixScale, kFixMagic)) -
+                                               __double_as_longlong(kFixMagic)));
+                rowkey[row] = slot[i] >> 4;
+            }
+        } else if (first && big) {
             atomicAdd(at32(G, (uint32_t)slot[i]), scale * x);
+        }
     }
 }
 
-// Directory entries of the bricks of the slab [a0, a1) in LDS (-1: none).
-struct WinBricks {
-    int32_t b0[3];     // first brick per axis
-    int32_t nb[3];     // bricks per axis
-};
-
-template <int kB>
-__device__ inline WinBricks slab_bricks(const Band& B, const ShapeDesc& s, const Window& W, int32_t a0, int32_t a1,
-                                        int32_t* wdir)
+// Add every non-zero entry of the first nrows rows to the gradient, in row
+// order (16 consecutive slots per row), and clear it.  kf = scale / 2^32.
+__device__ inline void line_flush(int32_t nrows, unsigned long long* acc, const int32_t* rowkey,
+                                  float* __restrict__ G, double kf)
 {
-    constexpr int32_t S = Geo<kB>::S;
-    WinBricks T;
-    int32_t n = 1;
-    for (int a = 0; a < 3; ++a) {
-        const int32_t lo = W.lo[a] + (a == W.ax ? a0 : 0);
-        const int32_t w = a == W.ax ? a1 - a0 : W.w[a];
-        T.b0[a] = lo >> S;
-        T.nb[a] = ((lo + w - 1) >> S) - T.b0[a] + 1;
-        n *= T.nb[a];
-    }
-    const int32_t nyz = T.nb[1] * T.nb[2];
+    const int32_t n = nrows * kRowSlots;
     for (int32_t i = threadIdx.x; i < n; i += blockDim.x) {
-        const int32_t bx = T.b0[0] + i / nyz, r = i % nyz;
-        const int32_t by = T.b0[1] + r / T.nb[2], bz = T.b0[2] + r % T.nb[2];
-        wdir[i] = (bx < s.nb[0] && by < s.nb[1] && bz < s.nb[2]) ? brick_of(B, s, bx, by, bz) : -1;
-    }
-    return T;
-}
-
-// Add every non-zero entry of the slab [a0, a1) to the gradient, in index
-// order, and clear it.  The vertex of an entry is found from its index by
-// float reciprocals: the index is below 2^13, far inside float's exact
-// range, and (i + 1/2) / w stays at least 1/(2w) away from an integer.
-template <int kB>
-__device__ inline void window_flush(const Window& W, int32_t a0, int32_t a1, const WinBricks& T, const int32_t* wdir,
-                                    unsigned long long* acc, float* __restrict__ G, float scale)
-{
-    using Gm = Geo<kB>;
-    const int32_t wo = W.w[1 - W.ax], wz = W.w[2];
-    const int32_t w12 = wo * wz, vol = (a1 - a0) * w12;
-    const float inv12 = 1.f / (float)w12, inv2 = 1.f / (float)wz;
-    for (int32_t i = threadIdx.x; i < vol; i += blockDim.x) {
         const long long v = (long long)acc[i];
         if (v == 0) continue;
         acc[i] = 0ull;
-        const int32_t ia = (int32_t)(((float)i + 0.5f) * inv12);
-        const int32_t r = i - ia * w12;
-        const int32_t io = (int32_t)(((float)r + 0.5f) * inv2);
-        const int32_t va = W.lo[W.ax] + a0 + ia, vo = W.lo[1 - W.ax] + io;
-        const int32_t vx = W.ax == 0 ? va : vo, vy = W.ax == 0 ? vo : va, vz = W.lo[2] + (r - io * wz);
-        const int32_t br = wdir[(((vx >> Gm::S) - T.b0[0]) * T.nb[1] + ((vy >> Gm::S) - T.b0[1])) * T.nb[2] +
-                                ((vz >> Gm::S) - T.b0[2])];
-        atomicAdd(at32(G, (uint32_t)(br * Gm::V + local_index_b<kB>(vx, vy, vz))),
-                  (float)((double)v * (1.0 / kFixScale) * (double)scale));
+        atomicAdd(at32(G, (uint32_t)(rowkey[i >> 4] * kRowSlots + (i & (kRowSlots - 1)))), (float)((double)v * kf));
     }
 }
 
-// Every contribution of one cell straight to the gradient (no window).
+// Every contribution of one cell straight to the gradient (no rows).
 __device__ inline void direct_add(const int32_t slot[8], const float v[8], float* __restrict__ G, float scale)
 {
 #pragma unroll
@@ -391,13 +393,13 @@ __device__ inline void direct_add(const int32_t slot[8], const float v[8], float
 }
 
 // One thread per query of a quarter tile: evaluate, take the adjoint, add
-// the 16 corner contributions to the block's window (or straight to the
-// gradient outside it), then flush the window.  kLoss: also the tile's loss
-// partials, and the contributions go out unscaled (the per-shape scale
-// 1/valid count is applied when they are folded into the gradient);
-// otherwise they are scaled by dloss / valid count.
+// the 16 corner contributions to the block's rows (or straight to the
+// gradient), then flush the rows.  kLoss: also the tile's loss partials, and
+// the contributions go out unscaled (the per-shape scale 1/valid count is
+// applied when they are folded into the gradient); otherwise they are scaled
+// by dloss / valid count.
 template <bool kLoss, int kB>
-__global__ __launch_bounds__(kGradBlock) void k_query_grad(Band B, const float* __restrict__ qx,
+__global__ __launch_bounds__(kGradBlock, 4) void k_query_grad(Band B, const float* __restrict__ qx,
                                                            const float* __restrict__ qy,
                                                            const float* __restrict__ qz,
                                                            const int32_t* __restrict__ nn, PointView P,
@@ -405,12 +407,15 @@ __global__ __launch_bounds__(kGradBlock) void k_query_grad(Band B, const float* 
                                                            const double* __restrict__ dloss,
                                                            const double* __restrict__ inv_qv,
                                                            float* __restrict__ G, double* __restrict__ q_part,
-                                                           int32_t* flag, int32_t cap, int32_t max_passes)
+                                                           int32_t* flag, int32_t cap, int32_t max_slabs)
 {
-    extern __shared__ __align__(16) unsigned long long s_acc[];   // [cap], then the slab's directory entries
+    extern __shared__ __align__(16) unsigned long long s_acc[];   // [cap] rows, then row lines, then the map
     __shared__ double s_red[kGradBlock / 64 * 4];
     __shared__ int32_t s_box[kGradBlock / 64 * 6];
-    int32_t* const s_wdir = reinterpret_cast<int32_t*>(s_acc + cap);
+    __shared__ int32_t s_cnt;
+    const int32_t nrows_cap = cap / kRowSlots;
+    int32_t* const s_rowkey = reinterpret_cast<int32_t*>(s_acc + cap);
+    uint16_t* const s_map = reinterpret_cast<uint16_t*>(s_rowkey + nrows_cap);
     const int64_t item = xcd_work_item(blockIdx.x, gridDim.x);
     const int64_t tile = item / kGradParts;
     const int32_t quarter = (int32_t)(item % kGradParts);
@@ -453,38 +458,6 @@ __global__ __launch_bounds__(kGradBlock) void k_query_grad(Band B, const float* 
             }
         }
     }
-    // the box of the block's query and nearest-point cells
-    int32_t box[6];
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        box[a] = valid ? min(ccq[a], ccs[a]) : 0x7fffffff;
-        box[3 + a] = valid ? max(ccq[a], ccs[a]) : -1;
-    }
-    block_minmax6(box, s_box);   // (its barriers also order the window clear)
-#pragma unroll
-    for (int a = 0; a < 6; ++a) box[a] = __builtin_amdgcn_readfirstlane(box[a]);
-    const Window W = choose_window(box, cap, max_passes);
-    if (W.passes == 0) {
-        if (valid) {
-            direct_add(sq, cq, G, scale);
-            direct_add(ss, cs, G, scale);
-        }
-    } else {
-        for (int32_t p = 0; p < W.passes; ++p) {
-            const int32_t a0 = p * W.layers, a1 = min(a0 + W.layers, W.w[W.ax]);
-            const WinBricks T = slab_bricks<kB>(B, s, W, a0, a1, s_wdir);
-            if (valid) {
-                int32_t iq[8], is[8];
-                window_corners(W, a0, a1, ccq, iq);
-                window_corners(W, a0, a1, ccs, is);
-                window_add(iq, sq, cq, p == 0, s_acc, G, scale);
-                window_add(is, ss, cs, p == 0, s_acc, G, scale);
-            }
-            __syncthreads();
-            window_flush<kB>(W, a0, a1, T, s_wdir, s_acc, G, scale);
-            __syncthreads();
-        }
-    }
     if (kLoss) {
         // tile partials in a fixed order: lanes, then waves
 #pragma unroll
@@ -498,6 +471,56 @@ __global__ __launch_bounds__(kGradBlock) void k_query_grad(Band B, const float* 
             double a = 0.0;
             for (int wv = 0; wv < kGradBlock / 64; ++wv) a += s_red[wv * 4 + threadIdx.x];
             q_part[item * 4 + threadIdx.x] = a;
+        }
+    }
+
+    // the box of the block's query and nearest-point cells
+    int32_t box[6];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        box[a] = valid ? min(ccq[a], ccs[a]) : 0x7fffffff;
+        box[3 + a] = valid ? max(ccq[a], ccs[a]) : -1;
+    }
+    block_minmax6(box, s_box);   // (its barriers also order the row clear)
+#pragma unroll
+    for (int a = 0; a < 6; ++a) box[a] = __builtin_amdgcn_readfirstlane(box[a]);
+    const LineBox C = choose_linebox<kB>(box, max_slabs);
+    if (C.slabs == 0) {
+        if (valid) {
+            direct_add(sq, cq, G, scale);
+            direct_add(ss, cs, G, scale);
+        }
+    } else {
+        const double kf = (double)scale * (1.0 / kFixScale);
+        const int32_t cross = C.nzb * C.nyl;
+        for (int32_t p = 0; p < C.slabs; ++p) {
+            const int32_t a0 = p * C.layers, a1 = min(a0 + C.layers, C.nx);
+            const int32_t nmap = (a1 - a0) * cross;
+            for (int32_t i = threadIdx.x; i < (nmap + 1) / 2; i += blockDim.x)
+                reinterpret_cast<uint32_t*>(s_map)[i] = 0u;
+            if (threadIdx.x == 0) s_cnt = 0;
+            __syncthreads();
+            if (valid) {
+                line_mark<kB>(C, a0, a1, ccq, s_map);
+                line_mark<kB>(C, a0, a1, ccs, s_map);
+            }
+            __syncthreads();
+            line_number(s_map, nmap, &s_cnt);
+            __syncthreads();
+            const int32_t n_rows = __builtin_amdgcn_readfirstlane(s_cnt);
+            // (at least one turn, so that the bypass of the first slab runs)
+            for (int32_t r0 = 0; r0 == 0 || r0 < n_rows; r0 += nrows_cap) {
+                const int32_t nrows = min(nrows_cap, n_rows - r0);
+                if (valid) {
+                    line_add<kB>(C, a0, a1, ccq, sq, cq, r0, nrows, p == 0 && r0 == 0, s_map, s_acc, s_rowkey, G,
+                                 scale);
+                    line_add<kB>(C, a0, a1, ccs, ss, cs, r0, nrows, p == 0 && r0 == 0, s_map, s_acc, s_rowkey, G,
+                                 scale);
+                }
+                __syncthreads();
+                line_flush(max(nrows, 0), s_acc, s_rowkey, G, kf);
+                __syncthreads();
+            }
         }
     }
 }
@@ -1046,7 +1069,7 @@ gp_status gp_backward_impl(gp_ctx ctx, const float* qx, const float* qy, const f
         const GradParams& gpar = ctx->grad_params;
         with_brick(ctx->brick, [&](auto tag) {
             constexpr int kB = decltype(tag)::value;
-            k_query_grad<false, kB><<<(unsigned)(ctx->n_tiles * kGradParts), kGradBlock, win_lds_bytes<kB>(gpar.win_cap),
+            k_query_grad<false, kB><<<(unsigned)(ctx->n_tiles * kGradParts), kGradBlock, win_lds_bytes(gpar.win_cap),
                                       st>>>(B, qx, qy, qz, nn, ctx->points(), field, w, dloss, ctx->inv_qv.p, grad,
                                             nullptr, ctx->flag.p, gpar.win_cap, gpar.win_max_passes);
         });
@@ -1070,7 +1093,7 @@ gp_status gp_forward_backward_impl(gp_ctx ctx, const float* qx, const float* qy,
         const GradParams& gpar = ctx->grad_params;
         with_brick(ctx->brick, [&](auto tag) {
             constexpr int kB = decltype(tag)::value;
-            k_query_grad<true, kB><<<(unsigned)(ctx->n_tiles * kGradParts), kGradBlock, win_lds_bytes<kB>(gpar.win_cap),
+            k_query_grad<true, kB><<<(unsigned)(ctx->n_tiles * kGradParts), kGradBlock, win_lds_bytes(gpar.win_cap),
                                      st>>>(B, qx, qy, qz, nn, ctx->points(), field, w, dloss, ctx->inv_qv.p,
                                            ctx->g_raw.p, ctx->q_part.p, ctx->flag.p, gpar.win_cap,
                                            gpar.win_max_passes);
@@ -1222,7 +1245,7 @@ static gp_status autotune_grad(gp_ctx ctx, const float* qx, const float* qy, con
     if (ctx->n_tiles > 0) {
         auto query_pass = [&](int32_t cap, int32_t passes) {
             return time_it([&] {
-                k_query_grad<true, kB><<<(unsigned)(ctx->n_tiles * kGradParts), kGradBlock, win_lds_bytes<kB>(cap), st>>>(
+                k_query_grad<true, kB><<<(unsigned)(ctx->n_tiles * kGradParts), kGradBlock, win_lds_bytes(cap), st>>>(
                     B, qx, qy, qz, nn, ctx->points(), field, w, nullptr, nullptr, ctx->g_raw.p, ctx->q_part.p,
                     ctx->flag.p, cap, passes);
             });

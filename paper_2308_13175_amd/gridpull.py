@@ -221,7 +221,7 @@ def gp_set_tv_layout(ctx, layout: int) -> None:
     _check(ctx, load_library().gp_set_tv_layout(ctx, int(layout)))
 
 
-def gp_set_grad_params(ctx, window_cap: int = 4608, window_max_passes: int = 16,
+def gp_set_grad_params(ctx, window_cap: int = 4096, window_max_passes: int = 16,
                        tv_forward_wave_from: int = 2048, tv_backward_wave_from: int = 16384) -> None:
     p = gp_grad_params(int(window_cap), int(window_max_passes), int(tv_forward_wave_from),
                        int(tv_backward_wave_from))

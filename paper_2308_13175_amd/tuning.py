@@ -187,10 +187,16 @@ def tune(prob, cache_path: Optional[str] = DEFAULT_CACHE, samples: int = 3, reps
     cache = load_cache(cache_path) if cache_path else {}
     if key in cache and "nn" in cache[key] and "grad" in cache[key]:
         entry = {k: cache[key][k] for k in ("nn", "grad")}
-        apply(prob, entry)
-        prob.sample(0, samples)
-        prob.nearest()
-        return {"key": key, "source": "cache", **entry}
+        try:
+            apply(prob, entry)
+        except gp.GridPullError:
+            # settings this build of the library refuses (an older cache): tune again
+            gp.gp_set_nn_params(prob.ctx, 8, 1)
+            gp.gp_set_grad_params(prob.ctx)
+        else:
+            prob.sample(0, samples)
+            prob.nearest()
+            return {"key": key, "source": "cache", **entry}
     nn_ms = tune_nn(prob, samples, reps)
     prob.sample(0, samples)
     prob.nearest()

@@ -132,47 +132,72 @@ def test_brick_sizes_through_the_path(brick):
     prob.close()
 
 
-def _window_passes(dom, pts, q, nn, cf, block=256, cap=4608, max_passes=16):
-    """Per block of the gradient pass, how many slab passes of the LDS window
-    (cap vertices) its vertex box takes, or 0 when it takes none (its
-    contributions go straight to the gradient).  The box covers the cells of
+def _row_turns(dom, pts, q, nn, cf, block=256, cap=4096, max_slabs=16, brick=8, linemap=2048):
+    """Per block of the gradient pass, (slabs, turns): the slabs of its line
+    box and the turns of LDS rows they take in all (0, 0 when the block sends
+    its contributions straight to the gradient).  The box covers the cells of
     the block's queries in the M1 band and of their nearest points, plus one
-    vertex; slabs are whole layers along x or y, whichever is longer."""
+    vertex, in lines of 16 consecutive slots (x, y / (16 / brick), z-brick);
+    slabs are whole x layers of at most linemap lines; a slab takes one turn
+    per cap / 16 of its distinct corner lines (at least one)."""
     R = np.array(dom.dims)
+    S = {4: 2, 8: 3, 16: 4}[brick]
+    L = 4 - S
+    rows = cap // 16
     cell = lambda x: np.clip(np.floor((x.astype(np.float64) - dom.lo) / dom.h), 0, R - 1).astype(np.int64)
     cq, cs = cell(q), cell(pts[nn])
     ok = (cf[(cq[:, 0] * R[1] + cq[:, 1]) * R[2] + cq[:, 2]] & 2) != 0
+    offs = np.array([[i >> 2, (i >> 1) & 1, i & 1] for i in range(8)])
     out = []
     for b in range(0, len(q), block):
         m = ok[b:b + block]
         if not m.any():
             continue
         c = np.concatenate([cq[b:b + block][m], cs[b:b + block][m]])
-        w = c.max(0) - c.min(0) + 2
-        ax = 1 if w[1] > w[0] else 0
-        cross = w[1 - ax] * w[2]
-        if cross > cap:
-            out.append(0)
+        lo, hi = c.min(0), c.max(0)
+        nx = hi[0] - lo[0] + 2
+        nzb = ((hi[2] + 1) >> S) - (lo[2] >> S) + 1
+        nyl = ((hi[1] + 1) >> L) - (lo[1] >> L) + 1
+        cross = nzb * nyl
+        if cross > linemap:
+            out.append((0, 0))
             continue
-        layers = min(w[ax], cap // cross)
-        passes = -(-w[ax] // layers)
-        out.append(passes if passes <= max_passes else 0)
+        layers = min(nx, linemap // cross)
+        slabs = -(-nx // layers)
+        if slabs > max_slabs:
+            out.append((0, 0))
+            continue
+        v = (c[:, None, :] + offs[None]).reshape(-1, 3)
+        line = np.stack([v[:, 0], v[:, 1] >> L, v[:, 2] >> S], 1)
+        rx = line[:, 0] - lo[0]
+        turns = 0
+        for p in range(slabs):
+            sel = line[(rx >= p * layers) & (rx < (p + 1) * layers)]
+            n = len(np.unique((sel[:, 0] << 42) | (sel[:, 1] << 21) | sel[:, 2]))
+            turns += max(1, -(-n // rows))
+        out.append((slabs, turns))
     return np.array(out)
 
 
-@pytest.mark.parametrize("case", ["one pass", "several passes", "no window"])
+@pytest.mark.parametrize("case", ["one turn", "several turns", "several slabs", "no rows"])
 def test_gradient_accumulation_paths(case):
-    """A block of the gradient pass sums its contributions in an LDS window
-    over the box of its cells, in one pass or in slabs of that box, and
-    sends them straight to the gradient when the box would take too many
-    slabs.  Queries around cell-sorted points with a small spread keep every
-    box within one window; a larger spread needs several slabs; sources
-    drawn at random on a finer grid spread every block over the sphere.
-    The path of every block is computed on the host; each case against the
+    """A block of the gradient pass sums its contributions in LDS rows, one
+    per 16-slot line of the gradient it touches: in one turn, in several
+    turns when it touches more lines than there are rows, in slabs when its
+    box has more lines than the line map, and straight to the gradient when
+    it would take more slabs than the limit.  Queries around cell-sorted points with a
+    small spread keep every block in one turn; a larger spread with half the
+    rows needs two turns; sources drawn at random on a finer grid spread every
+    block over the sphere (many slabs, or none under a limit of four).  The
+    path of every block is computed on the host; each case against the
     oracle."""
+    from paper_2308_13175_amd import gridpull as gp
+
     log("case: gradient accumulation, %s" % case)
-    res, n, sigma, strat = {"one pass": (64, 40_000, 0.01, True), "several passes": (64, 80_000, 0.06, True),
-                            "no window": (128, 40_000, 0.01, False)}[case]
+    res, n, sigma, strat, cap, max_slabs = {"one turn": (64, 40_000, 0.01, True, 4096, 16),
+                                            "several turns": (64, 80_000, 0.06, True, 2048, 16),
+                                            "several slabs": (128, 40_000, 0.01, False, 4096, 16),
+                                            "no rows": (128, 40_000, 0.01, False, 4096, 4)}[case]
     dom = synth.cube_domain(res)
     pts = synth.sphere_points(10_000, 0.5, seed=21)
     c = np.minimum(np.floor((pts.astype(np.float64) - dom.lo) / dom.h), res - 1).astype(np.int64)
@@ -180,31 +205,47 @@ def test_gradient_accumulation_paths(case):
     q = synth.host_queries(pts, n, sigma, seed=22, stratified=strat)
     D = synth.sphere_sdf_field(dom, 0.5, noise=0.01, seed=23)
     cf, vf, nn, ref = _oracle(dom, pts, q, D)
-    passes = _window_passes(dom, pts, q, nn, cf)
-    log("  passes per block: %s" % np.bincount(passes).tolist())
-    if case == "one pass":
-        assert (passes == 1).all()
-    elif case == "several passes":
-        assert (passes >= 1).all() and (passes >= 2).mean() > 0.3
+    paths = _row_turns(dom, pts, q, nn, cf, cap=cap, max_slabs=max_slabs)
+    log("  slabs per block: %s, turns per block: %s" % (np.bincount(paths[:, 0]).tolist(),
+                                                        np.bincount(paths[:, 1]).tolist()))
+    if case == "one turn":
+        assert (paths[:, 1] == 1).all()
+    elif case == "several turns":
+        assert (paths[:, 0] == 1).all() and (paths[:, 1] >= 2).mean() > 0.3
+    elif case == "several slabs":
+        assert (paths[:, 0] >= 2).all()
     else:
-        assert (passes == 0).mean() > 0.9
-    prob = _run_gpu(dom, pts, q, D)
+        assert (paths[:, 0] == 0).mean() > 0.9
+    prob = make_problem([spec(pts, dom, len(q), 0.0)])
+    gp.gp_set_grad_params(prob.ctx, cap, max_slabs, 2048, 16384)
+    prob.set_dense_field([D])
+    prob.set_queries(q)
+    prob.nearest()
+    prob.forward()
+    prob.grad.zero_()
+    prob.backward()
+    prob.sync()
     assert np.array_equal(prob.nn[: len(q)].cpu().numpy(), nn)
     got, nv = loss_terms(prob)
     assert int(nv[0]) == ref["n_valid"]
     assert_terms_close(got[0], ref)
     assert_grad_close(prob.dense_grad()[0], ref["dD"])
+    prob.grad.zero_()
+    prob.forward_backward()
+    prob.sync()
+    got, nv = loss_terms(prob)
+    assert_terms_close(got[0], ref)
+    assert_grad_close(prob.dense_grad()[0], ref["dD"])
     prob.close()
 
 
-@pytest.mark.parametrize("cap,max_passes,brick", [(2304, 16, 8), (6912, 64, 8), (4608, 1, 8), (2304, 16, 4),
-                                                   (6912, 64, 16)])
+@pytest.mark.parametrize("cap,max_passes,brick", [(2048, 16, 8), (6144, 64, 8), (4096, 1, 8), (2048, 16, 4),
+                                                   (6144, 64, 16), (2048, 4, 16)])
 def test_window_settings_and_autotuner(cap, max_passes, brick):
-    """The gradient pass at other window sizes and pass limits (a smaller
-    window takes more slabs, a larger one fewer, a limit of one pass sends
-    every box wider than the window straight to the gradient) gives the
-    oracle's loss terms and gradient; so does the setting the autotuner picks,
-    and out-of-range settings are refused."""
+    """The gradient pass at other row counts, slab limits and brick sizes (a
+    block touching more lines than there are rows takes them in turns)
+    gives the oracle's loss terms and gradient; so does the setting the
+    autotuner picks, and out-of-range settings are refused."""
     from paper_2308_13175_amd import gridpull as gp
 
     log("case: window %d vertices, at most %d passes, brick %d" % (cap, max_passes, brick))
@@ -215,9 +256,11 @@ def test_window_settings_and_autotuner(cap, max_passes, brick):
     q = synth.host_queries(pts, 80_000, 0.06, seed=22)
     D = synth.sphere_sdf_field(dom, 0.5, noise=0.01, seed=23)
     cf, vf, nn, ref = _oracle(dom, pts, q, D)
-    passes = _window_passes(dom, pts, q, nn, cf, cap=cap, max_passes=max_passes)
-    log("  passes per block: %s" % np.bincount(passes).tolist())
-    assert (passes == 0).any() if max_passes == 1 else (passes >= 1).all()
+    paths = _row_turns(dom, pts, q, nn, cf, cap=cap, max_slabs=max_passes, brick=brick)
+    log("  turns per block: %s" % np.bincount(paths[:, 1]).tolist())
+    assert (paths[:, 0] == 1).all()
+    if cap == 2048:
+        assert (paths[:, 1] >= 2).any()
     prob = make_problem([spec(pts, dom, len(q), 0.0)], brick=brick)
     gp.gp_set_grad_params(prob.ctx, cap, max_passes, 2048, 16384)
     assert gp.gp_get_grad_params(prob.ctx) == (cap, max_passes, 2048, 16384)
@@ -246,13 +289,14 @@ def test_window_settings_and_autotuner(cap, max_passes, brick):
     prob.grad.fill_(3.0)
     chosen, ms = prob.autotune_grad(reps=1)
     prob.sync()
-    assert chosen[0] in (2304, 4608, 6912) and 1 <= chosen[1] <= 64 and chosen[2] >= 0 and chosen[3] >= 0
+    assert chosen[0] in (2048, 4096, 6144) and 1 <= chosen[1] <= 64 and chosen[2] >= 0 and chosen[3] >= 0
     assert ms[0] > 0
     assert (ms[1] > 0 and ms[2] > 0) if brick == 8 else (ms[1] == -1 and ms[2] == -1)   # one TV layout only
     assert gp.gp_get_grad_params(prob.ctx) == chosen
     assert bool((prob.grad == 3.0).all())   # the caller's gradient is left alone
     check()
-    for bad in [(4000, 16, 0, 0), (4608, 0, 0, 0), (4608, 65, 0, 0), (4608, 16, -1, 0), (4608, 16, 0, -1)]:
+    for bad in [(4000, 16, 0, 0), (3584, 16, 0, 0), (4096, 0, 0, 0), (4096, 65, 0, 0), (4096, 16, -1, 0),
+                (4096, 16, 0, -1)]:
         with pytest.raises(gp.GridPullError) as ei:
             gp.gp_set_grad_params(prob.ctx, *bad)
         assert ei.value.status == 1

@@ -20,11 +20,11 @@ def test_size_class_rounds_to_powers_of_two():
 def test_cache_round_trip_and_atomic_replace(tmp_path):
     path = str(tmp_path / "sub" / "tuning.json")
     assert tuning.load_cache(path) == {}
-    entry = {"nn": [8, 1, 1, 0, 1, 8], "grad": [4608, 16, 2048, 16384]}
+    entry = {"nn": [8, 1, 1, 0, 1, 8], "grad": [4096, 16, 2048, 16384]}
     tuning.save_cache(path, {"gfx950|q2^20-p2^18-single": entry})
     assert tuning.load_cache(path) == {"gfx950|q2^20-p2^18-single": entry}
     data = tuning.load_cache(path)
-    data["gfx950|q2^25-p2^24-single"] = {"nn": [6, 1, 2, 1, 1, 8], "grad": [2304, 4, 0, 0]}
+    data["gfx950|q2^25-p2^24-single"] = {"nn": [6, 1, 2, 1, 1, 8], "grad": [2048, 4, 0, 0]}
     tuning.save_cache(path, data)
     assert sorted(tuning.load_cache(path)) == ["gfx950|q2^20-p2^18-single", "gfx950|q2^25-p2^24-single"]
     assert [f for f in os.listdir(tmp_path / "sub") if f.startswith(".tuning-")] == []
