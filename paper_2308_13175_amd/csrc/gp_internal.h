@@ -272,16 +272,68 @@ __device__ inline void nearest_point(const ShapeDesc& s, const PointView& P, int
     }
 }
 
+// Wave-wide reductions: DPP steps inside each row of 16 lanes (pairs, quads,
+// half rows, rows), then the four row results read from lanes 0, 16, 32 and
+// 48.  Every lane of the wave must be active; the result is wave-uniform.
+// The sums are taken in that fixed order (each step adds two partial sums,
+// the same in both lanes), so they do not depend on timing.
+template <int Ctrl>
+__device__ inline int32_t dpp_i32(int32_t v)
+{
+    return __builtin_amdgcn_update_dpp(v, v, Ctrl, 0xf, 0xf, false);
+}
+
+template <int Ctrl>
+__device__ inline double dpp_f64(double v)
+{
+    const long long b = __double_as_longlong(v);
+    const int32_t lo = dpp_i32<Ctrl>((int32_t)b), hi = dpp_i32<Ctrl>((int32_t)(b >> 32));
+    return __longlong_as_double((long long)(((unsigned long long)(uint32_t)hi << 32) | (uint32_t)lo));
+}
+
+__device__ inline double readlane_f64(double v, int lane)
+{
+    const long long b = __double_as_longlong(v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int32_t)b, lane);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int32_t)(b >> 32), lane);
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+__device__ inline int32_t wave_min_i32(int32_t v)
+{
+    v = min(v, dpp_i32<0xB1>(v));    // quad_perm [1, 0, 3, 2]
+    v = min(v, dpp_i32<0x4E>(v));    // quad_perm [2, 3, 0, 1]
+    v = min(v, dpp_i32<0x141>(v));   // row_half_mirror
+    v = min(v, dpp_i32<0x140>(v));   // row_mirror
+    return min(min(__builtin_amdgcn_readlane(v, 0), __builtin_amdgcn_readlane(v, 16)),
+               min(__builtin_amdgcn_readlane(v, 32), __builtin_amdgcn_readlane(v, 48)));
+}
+
+__device__ inline int32_t wave_max_i32(int32_t v)
+{
+    v = max(v, dpp_i32<0xB1>(v));
+    v = max(v, dpp_i32<0x4E>(v));
+    v = max(v, dpp_i32<0x141>(v));
+    v = max(v, dpp_i32<0x140>(v));
+    return max(max(__builtin_amdgcn_readlane(v, 0), __builtin_amdgcn_readlane(v, 16)),
+               max(__builtin_amdgcn_readlane(v, 32), __builtin_amdgcn_readlane(v, 48)));
+}
+
+__device__ inline double wave_sum_f64(double v)
+{
+    v += dpp_f64<0xB1>(v);
+    v += dpp_f64<0x4E>(v);
+    v += dpp_f64<0x141>(v);
+    v += dpp_f64<0x140>(v);
+    return (readlane_f64(v, 0) + readlane_f64(v, 16)) + (readlane_f64(v, 32) + readlane_f64(v, 48));
+}
+
 // Block-wide minimum of v[0..2] and maximum of v[3..5] (blockDim = 256).
 // Every thread receives the result.  scratch: shared int [4 * 6].
 __device__ inline void block_minmax6(int32_t v[6], int32_t* scratch)
 {
 #pragma unroll
-    for (int i = 0; i < 6; ++i)
-        for (int o = 32; o > 0; o >>= 1) {
-            int32_t w = __shfl_xor(v[i], o, 64);
-            v[i] = i < 3 ? min(v[i], w) : max(v[i], w);
-        }
+    for (int i = 0; i < 6; ++i) v[i] = i < 3 ? wave_min_i32(v[i]) : wave_max_i32(v[i]);
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     if (lane == 0)
         for (int i = 0; i < 6; ++i) scratch[wave * 6 + i] = v[i];

@@ -110,8 +110,7 @@ template <int N>
 __device__ inline void block_sum(double (&v)[N], double* lds /* [4 waves][N] */)
 {
 #pragma unroll
-    for (int i = 0; i < N; ++i)
-        for (int o = 32; o > 0; o >>= 1) v[i] += __shfl_xor(v[i], o, 64);
+    for (int i = 0; i < N; ++i) v[i] = wave_sum_f64(v[i]);
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     if (lane == 0)
         for (int i = 0; i < N; ++i) lds[wave * N + i] = v[i];
@@ -461,8 +460,7 @@ __global__ __launch_bounds__(kGradBlock, 4) void k_query_grad(Band B, const floa
     if (kLoss) {
         // tile partials in a fixed order: lanes, then waves
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
-            for (int o = 32; o > 0; o >>= 1) part[i] += __shfl_xor(part[i], o, 64);
+        for (int i = 0; i < 4; ++i) part[i] = wave_sum_f64(part[i]);
         const int wave = threadIdx.x >> 6;
         if ((threadIdx.x & 63) == 0)
             for (int i = 0; i < 4; ++i) s_red[wave * 4 + i] = part[i];
