@@ -718,11 +718,25 @@ __device__ inline int32_t nbr_brick(const Band& B, const ShapeDesc& s, const Bri
     return brick_of(B, s, x, y, z);
 }
 
+// The directory entries of the six face neighbours of a brick, in the order
+// x+1, x-1, y+1, y-1, z-1, z+1 (-1: none); the same for every lane of the
+// wave, so they are looked up once, all together, before any is needed.
+__device__ inline void face_nbrs(const Band& B, const ShapeDesc& s, const BrickInfo& bi, int32_t nbr[6])
+{
+    nbr[0] = nbr_brick(B, s, bi, 1, 0, 0);
+    nbr[1] = nbr_brick(B, s, bi, -1, 0, 0);
+    nbr[2] = nbr_brick(B, s, bi, 0, 1, 0);
+    nbr[3] = nbr_brick(B, s, bi, 0, -1, 0);
+    nbr[4] = nbr_brick(B, s, bi, 0, 0, -1);
+    nbr[5] = nbr_brick(B, s, bi, 0, 0, 1);
+}
+
 // The neighbour column of this lane's column in direction (di, dj) of the
-// i-j plane: from lane (i + di, j + dj), or across the brick face.  Values of
-// up to two arrays (b may be null) and the neighbours' V2 bits.
-__device__ inline uint32_t side_col(const Band& B, const ShapeDesc& s, const BrickInfo& bi, int lane, int di, int dj,
-                                    const float va[8], const float vb[8], uint32_t m, const float* __restrict__ a,
+// i-j plane: from lane (i + di, j + dj), or across the brick face into brick
+// br (the face neighbour in that direction).  Values of up to two arrays (b
+// may be null) and the neighbours' V2 bits.
+__device__ inline uint32_t side_col(const Band& B, int32_t br, int lane, int di, int dj, const float va[8],
+                                    const float vb[8], uint32_t m, const float* __restrict__ a,
                                     const float* __restrict__ b, float na[8], float nb[8])
 {
     const int32_t i = lane >> 3, j = lane & 7, ii = i + di, jj = j + dj;
@@ -734,7 +748,6 @@ __device__ inline uint32_t side_col(const Band& B, const ShapeDesc& s, const Bri
     }
     uint32_t nm = (uint32_t)__shfl((int)m, src, 64);
     if (ii < 0 || ii > 7 || jj < 0 || jj > 7) {
-        const int32_t br = nbr_brick(B, s, bi, (ii > 7) - (ii < 0), (jj > 7) - (jj < 0), 0);
         const int32_t ncol = ((ii & 7) << 3) | (jj & 7);
         nm = 0u;
         if (br >= 0) {
@@ -756,6 +769,8 @@ __global__ __launch_bounds__(kTvWaves * 64) void k_tv_forward_wave(Band B, const
     const BrickInfo bi = B.bricks[brick];
     const ShapeDesc& s = B.shapes[bi.shape];
     const int32_t slot0 = brick * kBrickVol + lane * 8;
+    int32_t nbr[6];
+    face_nbrs(B, s, bi, nbr);
     float v[8], s2[8];
     load_col(D, slot0, v);
     const uint32_t m = col_mask(B.m_v2, brick, lane);
@@ -771,7 +786,7 @@ __global__ __launch_bounds__(kTvWaves * 64) void k_tv_forward_wave(Band B, const
         }
 #pragma unroll
     for (int e = 0; e < 2; ++e) {
-        const int32_t br = nbr_brick(B, s, bi, 0, 0, e ? 1 : -1);
+        const int32_t br = nbr[4 + e];
         const int k = e ? 7 : 0, kn = e ? 0 : 7;
         if (br >= 0 && ((m >> k) & 1u) && ((col_mask(B.m_v2, br, lane) >> kn) & 1u)) {
             const float d = v[k] - *at32(D, (uint32_t)(br * kBrickVol + lane * 8 + kn));
@@ -783,7 +798,7 @@ __global__ __launch_bounds__(kTvWaves * 64) void k_tv_forward_wave(Band B, const
     for (int dir = 0; dir < 4; ++dir) {
         const int di = dir == 0 ? 1 : (dir == 1 ? -1 : 0), dj = dir == 2 ? 1 : (dir == 3 ? -1 : 0);
         float n[8];
-        const uint32_t nm = side_col(B, s, bi, lane, di, dj, v, nullptr, m, D, nullptr, n, nullptr);
+        const uint32_t nm = side_col(B, nbr[dir], lane, di, dj, v, nullptr, m, D, nullptr, n, nullptr);
 #pragma unroll
         for (int k = 0; k < 8; ++k)
             if ((m & nm) >> k & 1u) {
@@ -838,6 +853,8 @@ __global__ __launch_bounds__(kTvWaves * 64, 5) void k_tv_backward_wave(Band B, c
     }
     const uint32_t m = tv_on ? col_mask(B.m_v2, brick, lane) : 0u;
     if (__ballot(m != 0u)) {
+        int32_t nbr[6];
+        face_nbrs(B, s, bi, nbr);
         float v[8], it[8], acc[8];
         load_col(D, slot0, v);
         load_col(itau, slot0, it);
@@ -852,7 +869,7 @@ __global__ __launch_bounds__(kTvWaves * 64, 5) void k_tv_backward_wave(Band B, c
             }
 #pragma unroll
         for (int e = 0; e < 2; ++e) {
-            const int32_t br = nbr_brick(B, s, bi, 0, 0, e ? 1 : -1);
+            const int32_t br = nbr[4 + e];
             const int k = e ? 7 : 0, kn = e ? 0 : 7;
             if (br >= 0 && ((m >> k) & 1u) && ((col_mask(B.m_v2, br, lane) >> kn) & 1u)) {
                 const uint32_t ns = (uint32_t)(br * kBrickVol + lane * 8 + kn);
@@ -863,7 +880,7 @@ __global__ __launch_bounds__(kTvWaves * 64, 5) void k_tv_backward_wave(Band B, c
         for (int dir = 0; dir < 4; ++dir) {
             const int di = dir == 0 ? 1 : (dir == 1 ? -1 : 0), dj = dir == 2 ? 1 : (dir == 3 ? -1 : 0);
             float n[8], nt[8];
-            const uint32_t nm = side_col(B, s, bi, lane, di, dj, v, it, m, D, itau, n, nt);
+            const uint32_t nm = side_col(B, nbr[dir], lane, di, dj, v, it, m, D, itau, n, nt);
 #pragma unroll
             for (int k = 0; k < 8; ++k)
                 if ((m & nm) >> k & 1u) acc[k] = fmaf(v[k] - n[k], it[k] + nt[k], acc[k]);
