@@ -239,6 +239,45 @@ def test_gradient_accumulation_paths(case):
     prob.close()
 
 
+def test_large_contributions_bypass_the_rows():
+    """Contributions of 2^19 or more go straight to the gradient (the fixed
+    point of the LDS rows would overflow), mixed with small ones that take
+    the rows.  A field scaled by 1e-7 has |grad f| near 1e-7, so the
+    gradient-consistency adjoint (weight 1) carries 1/|grad f| ~ 1e7 (Eq. 7
+    differentiated) while the pull and surface adjoints stay of order one.
+    The largest such contribution is bounded below on the host from the
+    oracle's per-query cosine term: gamma * sin(theta) / |grad f| * R / 2 per
+    unit corner weight, with |grad f| <= 2e-7 for this field."""
+    log("case: contributions beyond the fixed-point range")
+    dom = synth.cube_domain(32)
+    pts = synth.sphere_points(3000, 0.5, seed=31)
+    q = synth.host_queries(pts, 12_000, 0.04, seed=32)
+    D = (1e-7 * synth.sphere_sdf_field(dom, 0.5, noise=0.01, seed=33).astype(np.float64)).astype(np.float32)
+    weights = (1.0, 1.0, 1.0)
+    cf, vf = oracle.build_band(dom.dims, dom.lo, dom.hi, pts, 3, 3)
+    nn = oracle.nn_bruteforce(q, pts)
+    ref = oracle.loss_grad(dom.dims, dom.lo, dom.hi, cf, vf, D.astype(np.float64), q, nn, pts, *weights,
+                           per_query=True)
+    pq = ref["per_query"]
+    lg = pq[pq[:, 3] > 0, 2]
+    sin_max = float(np.sqrt(np.clip(lg * (2.0 - lg), 0.0, None)).max())
+    # (corner weights of at least 1/8 on some corner of the cell: a factor 8 of margin)
+    assert weights[2] * sin_max / 2e-7 * (dom.dims[0] / 2.0) / 8.0 >= 2.0 ** 19
+    prob = _run_gpu(dom, pts, q, D, weights=weights)
+    assert np.array_equal(prob.nn[: len(q)].cpu().numpy(), nn)
+    got, nv = loss_terms(prob)
+    assert int(nv[0]) == ref["n_valid"]
+    assert_terms_close(got[0], ref)
+    assert_grad_close(prob.dense_grad()[0], ref["dD"])
+    prob.grad.zero_()
+    prob.forward_backward()
+    prob.sync()
+    got, nv = loss_terms(prob)
+    assert_terms_close(got[0], ref)
+    assert_grad_close(prob.dense_grad()[0], ref["dD"])
+    prob.close()
+
+
 @pytest.mark.parametrize("cap,max_passes,brick", [(2048, 16, 8), (6144, 64, 8), (4096, 1, 8), (2048, 16, 4),
                                                    (6144, 64, 16), (2048, 4, 16)])
 def test_window_settings_and_autotuner(cap, max_passes, brick):
