@@ -297,13 +297,15 @@ __device__ inline void line_corners(const LineBox& C, int32_t a0, int32_t a1, co
 {
     constexpr int32_t S = Geo<kB>::S, L = LineGeo<kB>::L;
     const int32_t rx = c[0] - C.lo - a0, na = a1 - a0;
-    const int32_t z0 = (c[2] >> S) - C.zb0, z1 = ((c[2] + 1) >> S) - C.zb0;
-    const int32_t y0 = (c[1] >> L) - C.yl0, y1 = ((c[1] + 1) >> L) - C.yl0;
+    const int32_t z0 = (c[2] >> S) - C.zb0, y0 = (c[1] >> L) - C.yl0;
+    // corner (a, b, d) = base + a * sx + b * dy + d * dz
+    const int32_t base = (rx * C.nzb + z0) * C.nyl + y0, sx = C.nzb * C.nyl;
+    const int32_t dz = (((c[2] + 1) >> S) - (c[2] >> S)) * C.nyl, dy = ((c[1] + 1) >> L) - (c[1] >> L);
+    const bool in0 = (uint32_t)rx < (uint32_t)na, in1 = (uint32_t)(rx + 1) < (uint32_t)na;   // y, z inside the box
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
-        const int32_t x = rx + (i >> 2);
-        const bool in = (uint32_t)x < (uint32_t)na;   // y and z lie inside the box
-        idx[i] = in ? (x * C.nzb + ((i & 1) ? z1 : z0)) * C.nyl + (((i >> 1) & 1) ? y1 : y0) : -1;
+        const int32_t off = ((i >> 2) ? sx : 0) + (((i >> 1) & 1) ? dy : 0) + ((i & 1) ? dz : 0);
+        idx[i] = ((i >> 2) ? in1 : in0) ? base + off : -1;
     }
 }
 
@@ -362,7 +364,7 @@ __device__ inline void line_add(const LineBox& C, int32_t a0, int32_t a1, const 
                 atomicAdd(&acc[row * kRowSlots + (slot[i] & (kRowSlots - 1))],
                           (unsigned long long)(__double_as_longlong(fma((double)x, kFixScale, kFixMagic)) -
                                                __double_as_longlong(kFixMagic)));
-                rowkey[row] = slot[i] >> 4;
+                if ((i & 1) == 0 || idx[i] != idx[i - 1]) rowkey[row] = slot[i] >> 4;
             }
         } else if (first && big) {
             atomicAdd(at32(G, (uint32_t)slot[i]), scale * x);
@@ -442,7 +444,6 @@ __global__ __launch_bounds__(kGradBlock, 4) void k_query_grad(Band B, const floa
                 part[2] = (st.q.ok && st.s.ok) ? 1.0 - fma(st.q.gh[0], st.s.gh[0],
                                                            fma(st.q.gh[1], st.s.gh[1], st.q.gh[2] * st.s.gh[2]))
                                                : 1.0;
-                part[3] = 1.0;
             }
             query_adjoint(s, st, w, cq, cs);
 #pragma unroll
@@ -458,9 +459,10 @@ __global__ __launch_bounds__(kGradBlock, 4) void k_query_grad(Band B, const floa
         }
     }
     if (kLoss) {
-        // tile partials in a fixed order: lanes, then waves
+        // tile partials in a fixed order: lanes, then waves (the count exactly, from the valid lanes)
 #pragma unroll
-        for (int i = 0; i < 4; ++i) part[i] = wave_sum_f64(part[i]);
+        for (int i = 0; i < 3; ++i) part[i] = wave_sum_f64(part[i]);
+        part[3] = (double)__popcll(__ballot(valid));
         const int wave = threadIdx.x >> 6;
         if ((threadIdx.x & 63) == 0)
             for (int i = 0; i < 4; ++i) s_red[wave * 4 + i] = part[i];
