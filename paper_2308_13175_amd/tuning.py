@@ -5,7 +5,8 @@ Three groups of settings change only the speed, never the result:
   layout, so it is chosen before the problem is built: `choose_brick` builds
   the problem with each size and times its forward + backward);
 - the nearest-neighbour search grid and search shape (gp_autotune_nn);
-- the gradient pass's LDS window and the TV kernels' layouts (gp_autotune_grad).
+- the gradient pass's LDS rows and slab limit, and the TV kernels' layouts
+  (gp_autotune_grad).
 
 `tune` times the last two on the problem's own inputs: the search on the
 query samples of a few iterations (the sample moves the best shape, so each

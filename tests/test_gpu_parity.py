@@ -287,7 +287,7 @@ def test_window_settings_and_autotuner(cap, max_passes, brick):
     autotuner picks, and out-of-range settings are refused."""
     from paper_2308_13175_amd import gridpull as gp
 
-    log("case: window %d vertices, at most %d passes, brick %d" % (cap, max_passes, brick))
+    log("case: rows of %d vertices, at most %d slabs, brick %d" % (cap, max_passes, brick))
     dom = synth.cube_domain(64)
     pts = synth.sphere_points(10_000, 0.5, seed=21)
     c = np.minimum(np.floor((pts.astype(np.float64) - dom.lo) / dom.h), 63).astype(np.int64)
