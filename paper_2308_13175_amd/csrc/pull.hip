@@ -8,10 +8,10 @@
 //   cosine term (Eq. 7).  The forward writes per-tile sums (double); the
 //   backward (fused with the forward in k_query_grad) takes the adjoint of
 //   the same quantities and adds it to the 8 corners at q and the 8 corners
-//   at s: summed per block in LDS (fixed point; a dense window over the
-//   block's vertex box, taken in slabs when the box is larger), then one
-//   float atomic per vertex (or straight to the gradient when the box would
-//   take too many slabs).
+//   at s: summed per block in LDS (fixed point, in rows of the 64-byte
+//   gradient lines the block touches), then one float atomic per non-zero
+//   entry (or straight to the gradient when the block's box would take too
+//   many slabs).
 // Vertex side, per brick (a block, or a wave): tau_i over the six axis
 //   neighbours that are TV vertices (Eq. 5) in the forward; in the backward
 //   the gradient is gathered per vertex (each vertex writes only its own
