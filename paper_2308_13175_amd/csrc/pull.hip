@@ -1220,7 +1220,7 @@ gp_status gp_forward_static_impl(gp_ctx ctx, const float* qx, const float* qy, c
 }
 
 // ---------------------------------------------------------------------------
-// gp_autotune_grad: the window settings of the fused query pass, then the TV
+// gp_autotune_grad: the row and slab settings of the fused query pass, then the TV
 // layouts at this band's size, each timed between events on the context's
 // stream (one untimed run, then the smallest of reps runs).  The query pass
 // accumulates into the context's own accumulator, cleared afterwards; the TV
