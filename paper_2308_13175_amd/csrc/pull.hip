@@ -364,7 +364,8 @@ __device__ inline void line_add(const LineBox& C, int32_t a0, int32_t a1, const 
                 atomicAdd(&acc[row * kRowSlots + (slot[i] & (kRowSlots - 1))],
                           (unsigned long long)(__double_as_longlong(fma((double)x, kFixScale, kFixMagic)) -
                                                __double_as_longlong(kFixMagic)));
-                if ((i & 1) == 0 || idx[i] != idx[i - 1]) rowkey[row] = slot[i] >> 4;
+                rowkey[row] = slot[i] >> 4;   // (every add names its row's line: a corner of the same
+                                              // line may have bypassed the rows)
             }
         } else if (first && big) {
             atomicAdd(at32(G, (uint32_t)slot[i]), scale * x);
