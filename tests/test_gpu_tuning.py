@@ -54,3 +54,23 @@ def test_tune_then_read_from_cache(tmp_path):
     assert_terms_close(got[0], ref)
     assert_grad_close(prob.dense_grad()[0], ref["dD"])
     prob.close()
+
+
+def test_stale_cache_entry_is_tuned_again(tmp_path):
+    """A cache entry holding settings this library refuses (written by a build
+    with other window sizes) is not applied: the problem is tuned again and
+    the entry replaced."""
+    from paper_2308_13175_amd import gridpull as gp
+    from paper_2308_13175_amd import tuning
+
+    log("case: tuning, stale cache entry")
+    path = str(tmp_path / "tuning.json")
+    prob, dom, pts = _problem()
+    key = tuning.class_key(prob.specs)
+    tuning.save_cache(path, {key: {"nn": [8, 1, 1, 0, 1, 8], "grad": [4608, 16, 2048, 16384]}})
+    out = tuning.tune(prob, path, samples=2, reps=1)
+    assert out["source"] == "tuned" and out["key"] == key
+    assert out["grad"][0] in (2048, 4096, 6144)
+    assert tuning.load_cache(path)[key] == {"nn": out["nn"], "grad": out["grad"]}
+    assert list(gp.gp_get_grad_params(prob.ctx)) == out["grad"]
+    prob.close()
