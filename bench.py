@@ -109,20 +109,26 @@ def nn_required_pairs(points, dom, queries, n_sample=10000, seed=0, max_reach=12
 
 
 def _source_sha(kernel):
+    """sha256 of the kernel's source file followed by the header every kernel
+    inlines (gp_internal.h): a change to either changes the kernel."""
     import hashlib
 
     src = KERNEL_SOURCES.get(kernel)
     if src is None:
         return None
-    with open(os.path.join(ROOT, "paper_2308_13175_amd", "csrc", src), "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()
+    h = hashlib.sha256()
+    for name in (src, "gp_internal.h"):
+        with open(os.path.join(ROOT, "paper_2308_13175_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
 
 
 def measured_traffic(kernel, config):
     """HBM bytes per launch from the committed counter summary, or None.
 
-    The summary records the sha256 of the kernel's source file when the
-    counters were taken; a kernel changed since then gets None.
+    The summary records the sha256 of the kernel's sources (its file and the
+    shared header) when the counters were taken; a kernel changed since then
+    gets None.
     """
     path = os.path.join(PROFILES, "%s_%s_traffic.txt" % (kernel, WORKLOAD_KEYS.get(config, "")))
     if not os.path.exists(path):

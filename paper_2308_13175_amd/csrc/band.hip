@@ -680,14 +680,15 @@ static gp_status build_band(gp_ctx ctx, const gp_shape* shapes, int32_t n_shapes
         ctx->fin_part.alloc((size_t)n_shapes * 32 * 5) != hipSuccess || ctx->fin_count.alloc(n_shapes) != hipSuccess ||
         ctx->iter.alloc(1) != hipSuccess || ctx->step_c.alloc(2) != hipSuccess ||
         ctx->g_raw.alloc((size_t)std::max<int64_t>(n_slots, 1)) != hipSuccess ||
-        ctx->nn_pos.alloc((size_t)std::max<int64_t>(n_queries, 1)) != hipSuccess)
+        ctx->nn_pt.alloc((size_t)std::max<int64_t>(n_queries, 1)) != hipSuccess)
         return gp_fail(ctx, GP_ERR_OOM, "out of device memory for the iteration scratch");
     GP_HIP(ctx, hipMemsetAsync(ctx->flag.p, 0, 4, st));
     GP_HIP(ctx, hipMemsetAsync(ctx->fin_count.p, 0, 4 * (size_t)n_shapes, st));
     GP_HIP(ctx, hipMemsetAsync(ctx->iter.p, 0, 4, st));
     GP_HIP(ctx, hipMemsetAsync(ctx->tau.p, 0, std::max<int64_t>(n_slots, 1) * 4, st));
     GP_HIP(ctx, hipMemsetAsync(ctx->g_raw.p, 0, std::max<int64_t>(n_slots, 1) * 4, st));
-    GP_HIP(ctx, hipMemsetAsync(ctx->nn_pos.p, 0, std::max<int64_t>(n_queries, 1) * 4, st));
+    // (all bits set: index -1, which names no point, so no record is taken before a search)
+    GP_HIP(ctx, hipMemsetAsync(ctx->nn_pt.p, 0xff, std::max<int64_t>(n_queries, 1) * sizeof(float4), st));
 
     ctx->h_shapes = hs;
     ctx->h_slot_begin.resize(n_shapes + 1);

@@ -239,16 +239,14 @@ __device__ inline int64_t xcd_work_item(int64_t b, int64_t n)
 }
 
 // Coordinates of a query's nearest point nn (an index among its shape's
-// points, valid: 0 <= nn < point_cnt).  The NN search records, per query, the
-// position of its result in the search grid's sorted copy; when that position still
-// holds point nn (the sorted copy keeps each point's original index), the
-// point is read there, 16 contiguous bytes next to the points of the
-// neighbouring queries.  Otherwise (nearest points that did not come from the
-// search, or a stale position) it is read from the original order.  Either
-// way the same coordinates.
+// points, valid: 0 <= nn < point_cnt).  The NN search records, per query,
+// the coordinates of its result together with the result's index; when that
+// index is nn, the point is read there, 16 contiguous bytes of the query's
+// own record (no dependent load).  Otherwise (nearest points that did not
+// come from the search, or a record of an earlier search) it is read from
+// the original order.  Either way the same coordinates.
 struct PointView {
-    const float4* spts;     // the search grid's sorted copy: x, y, z, original index within the shape (bits)
-    const int32_t* pos;     // [n_queries] position in spts of each query's last NN result
+    const float4* pt;       // [n_queries] last NN result per query: x, y, z, its index within the shape (bits)
     const float* ox;        // original order, at sorted_off + index
     const float* oy;
     const float* oz;
@@ -257,9 +255,7 @@ struct PointView {
 __device__ inline void nearest_point(const ShapeDesc& s, const PointView& P, int64_t k, int32_t nn, float& sx,
                                      float& sy, float& sz)
 {
-    int32_t p = P.pos[k];
-    p = (p >= 0 && p < s.point_cnt) ? p : 0;
-    const float4 v = P.spts[s.sorted_off + p];
+    const float4 v = P.pt[k];
     if (__float_as_int(v.w) == nn) {
         sx = v.x;
         sy = v.y;
@@ -478,7 +474,7 @@ struct gp_ctx_s {
     DevBuf<uint32_t> occ;         // occupancy bitmaps of all search grids
     DevBuf<int32_t> cell_start;   // [nn_slots + 1]
     DevBuf<float4> nn_spts;       // points sorted by search-grid slot: x, y, z, original index (bits)
-    DevBuf<int32_t> nn_pos;       // [n_queries] position in nn_spts (within the shape) of the last NN result
+    DevBuf<float4> nn_pt;         // [n_queries] the last NN result per query: coordinates and index (bits)
 
     // per-iteration scratch
     DevBuf<double> q_part;        // [n_tiles][4] sum pull, surf, grad, count
@@ -515,7 +511,7 @@ struct gp_ctx_s {
 
     gp::PointView points() const
     {
-        return gp::PointView{nn_spts.p, nn_pos.p, ox.p, oy.p, oz.p};
+        return gp::PointView{nn_pt.p, ox.p, oy.p, oz.p};
     }
 
     // The band view with the search grids' descriptors, directory and

@@ -559,7 +559,7 @@ constexpr int kWaveSpan = kQueryTile / kWaves;   // sorted positions grouped and
 template <bool kTuning>
 __global__ __launch_bounds__(kQueryBlock, 4) void k_nn(Band B, Global G, NnParams P, const float* __restrict__ qx,
                                                     const float* __restrict__ qy, const float* __restrict__ qz,
-                                                    int32_t* __restrict__ nn, int32_t* __restrict__ nn_pos)
+                                                    int32_t* __restrict__ nn, float4* __restrict__ nn_pt)
 {
     __shared__ typename BlockSort::TempStorage sort_tmp;
     __shared__ int16_t s_order[kQueryTile];
@@ -782,8 +782,9 @@ __global__ __launch_bounds__(kQueryBlock, 4) void k_nn(Band B, Global G, NnParam
         // the winner's position in the sorted copy; its original index is
         // stored there too (a load from the same small region as the scan)
         const int32_t at = (s.point_cnt > 0 && !q.open) ? q.id1 : search(B, s, G, q.x, q.y, q.z);
-        nn[k] = at >= 0 ? __float_as_int(G.pts[at].w) : -1;
-        nn_pos[k] = at >= 0 ? (int32_t)(at - s.sorted_off) : 0;
+        const float4 w = at >= 0 ? G.pts[at] : make_float4(0.f, 0.f, 0.f, __int_as_float(-1));
+        nn[k] = __float_as_int(w.w);
+        nn_pt[k] = w;
     }
 }
 
@@ -798,7 +799,7 @@ gp_status gp_nn_impl(gp_ctx ctx, const float* qx, const float* qy, const float* 
     Global G{ctx->cell_start.p, ctx->nn_spts.p};
     GP_TIMED(ctx, "k_nn");
     k_nn<false><<<(unsigned)(ctx->n_tiles * ctx->nn_params.parts), kQueryBlock, 0, ctx->stream>>>(
-        ctx->nn_band(), G, ctx->nn_params, qx, qy, qz, nn, ctx->nn_pos.p);
+        ctx->nn_band(), G, ctx->nn_params, qx, qy, qz, nn, ctx->nn_pt.p);
     GP_HIP(ctx, hipGetLastError());
     return GP_OK;
 }
@@ -845,7 +846,7 @@ gp_status gp_autotune_nn_impl(gp_ctx ctx, const float* qx, const float* qy, cons
             for (int32_t r = 0; r <= reps && e == hipSuccess; ++r) {
                 e = hipEventRecord(ev[0], ctx->stream);
                 k_nn<true><<<(unsigned)(ctx->n_tiles * P.parts), kQueryBlock, 0, ctx->stream>>>(ctx->nn_band(), G, P,
-                                                                                            qx, qy, qz, nn, ctx->nn_pos.p);
+                                                                                            qx, qy, qz, nn, ctx->nn_pt.p);
                 if (e == hipSuccess) e = hipGetLastError();
                 if (e == hipSuccess) e = hipEventRecord(ev[1], ctx->stream);
                 if (e == hipSuccess) e = hipEventSynchronize(ev[1]);
@@ -942,7 +943,7 @@ gp_status gp_autotune_nn_impl(gp_ctx ctx, const float* qx, const float* qy, cons
         // leave nn holding the chosen configuration's (identical) result
         const Global G{ctx->cell_start.p, ctx->nn_spts.p};
         k_nn<true><<<(unsigned)(ctx->n_tiles * best.parts), kQueryBlock, 0, ctx->stream>>>(ctx->nn_band(), G, best, qx,
-                                                                                       qy, qz, nn, ctx->nn_pos.p);
+                                                                                       qy, qz, nn, ctx->nn_pt.p);
         GP_HIP(ctx, hipGetLastError());
     }
     ctx->nn_params = best;
