@@ -888,3 +888,48 @@ def test_normal_supervision(brick):
         assert abs(got - rterm) <= 1e-5 * abs(rterm), (got, rterm)
         assert_grad_close(prob.dense_grad()[0], rgrad)
         prob.close()
+
+
+def test_nearest_points_not_from_the_search():
+    """The loss passes read a query's nearest point from the search's record
+    when the record names the same point, else from the caller's points in
+    their original order.  Nearest indices given by the caller, before any
+    search and after one (half of them changed), give the oracle's loss and
+    gradient for those indices (Eq. 4, 6, 7 use s = the given point)."""
+    import torch
+
+    log("case: caller-given nearest points")
+    dom = synth.cube_domain(32)
+    pts = synth.sphere_points(3000, 0.5, seed=41)
+    q = synth.host_queries(pts, 12_000, 0.04, seed=42)
+    D = synth.sphere_sdf_field(dom, 0.5, noise=0.01, seed=43)
+    cf, vf = oracle.build_band(dom.dims, dom.lo, dom.hi, pts, 3, 3)
+    prob = make_problem([spec(pts, dom, len(q), 0.0)])
+    prob.set_dense_field([D])
+    prob.set_queries(q)
+    rng = np.random.default_rng(44)
+    true_nn = oracle.nn_bruteforce(q, pts)
+    given = {"before any search": rng.integers(0, len(pts), len(q)).astype(np.int32),
+             "after a search": np.where(rng.random(len(q)) < 0.5, true_nn, (true_nn + 1) % len(pts)).astype(np.int32)}
+    for case, nn in given.items():
+        log("  " + case)
+        if case == "after a search":
+            prob.nearest()
+            assert np.array_equal(prob.nn[: len(q)].cpu().numpy(), true_nn)
+        prob.nn[: len(q)].copy_(torch.from_numpy(nn).to(prob.nn.device))
+        ref = oracle.loss_grad(dom.dims, dom.lo, dom.hi, cf, vf, D.astype(np.float64), q, nn, pts)
+        prob.forward()
+        prob.grad.zero_()
+        prob.backward()
+        prob.sync()
+        got, nv = loss_terms(prob)
+        assert int(nv[0]) == ref["n_valid"]
+        assert_terms_close(got[0], ref)
+        assert_grad_close(prob.dense_grad()[0], ref["dD"])
+        prob.grad.zero_()
+        prob.forward_backward()
+        prob.sync()
+        got, nv = loss_terms(prob)
+        assert_terms_close(got[0], ref)
+        assert_grad_close(prob.dense_grad()[0], ref["dD"])
+    prob.close()
